@@ -1,0 +1,145 @@
+"""Benchmark of the entire lineal path function on one MI355X.
+
+Default workload: full LPF of one 512 x 512 periodic image (non-overlapping disks, radii
+U[5, 20] px, volume fraction 0.3, seed 1602), all vectors with |dx|, |dy| <= 128, both phases,
+bit-packed input already resident in device memory.  One step = one lpf_full call.
+
+Prints ONE JSON line.  `value` = path placements per second (|D_c| * W * H * phases / t).
+`roofline` reports the dominant kernel (k_lpf_full) against the integer-VALU peak, with its
+algorithmic op count (N/32)(3 M_c + 2 |D_c|): one funnel shift, one AND and one OR per segment
+pixel per 32 start pixels, and one popcount per vector per 32 start pixels per phase.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz (4 SIMD16 per CU, 1 op/lane/clk)
+P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def path_pixels(cx: int, cy: int) -> int:
+    """M_c = sum over the canonical half domain of (max(|dx|,|dy|) + 1)."""
+    tot = 0
+    for dy in range(cy + 1):
+        for dx in range(-cx, cx + 1):
+            if dy == 0 and dx < 0:
+                continue
+            tot += max(abs(dx), dy) + 1
+    return tot
+
+
+def ops_alg(W: int, H: int, cx: int, cy: int, nph: int) -> float:
+    nv = (cx + 1) * (cy + 1) + cx * cy
+    M = path_pixels(cx, cy)
+    per_word = (3 * M + 2 * nv) if nph == 2 else (2 * M + nv)
+    return W * H / 32.0 * per_word
+
+
+def cpu_baseline(img, cx, cy, stride=16):
+    """The CPU oracle on every `stride`-th vector of the same workload (all host threads)."""
+    import numpy as np
+    import oracle
+    v = oracle.vectors(cx, cy)[::stride]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.lpf_vectors(img, v, 3, nthreads=threads)
+    dt = time.perf_counter() - t0
+    H, W = img.shape
+    placements = len(v) * W * H * 2
+    return {"value": placements / dt / 1e9, "unit": "Gplacements/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(v)} of {len(oracle.vectors(cx, cy))} vectors (every {stride}th in "
+                      f"canonical order), both phases, {W}x{H}, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the multi-GPU split is a design note, not an implemented path)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import Context, LPF_OUT_HALF
+
+    W = H = 512
+    cx = cy = 128
+    nph = 2
+    img = wl.rsa_512()
+    dev = torch.device("cuda:0")
+    ctx = Context(0)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        bits = ctx.pack(torch.from_numpy(img).to(dev), stream=stream)
+        out = torch.empty((nph, (cx + 1) * (cy + 1) + cx * cy), dtype=torch.int32, device=dev)
+        for _ in range(max(1, args.warmup)):
+            ctx.full(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=out, stream=stream)
+        stream.synchronize()
+        # events on the launch stream, one pair per step
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            evs[i][0].record(stream)
+            ctx.full(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=out, stream=stream)
+            evs[i][1].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    ms = wall * 1e3 / args.steps
+    nv = (cx + 1) * (cy + 1) + cx * cy
+    placements = nv * W * H * nph
+    value = placements / (wall / args.steps) / 1e9
+    kern_s = float(np.mean(step_ms)) / 1e3
+    ops = ops_alg(W, H, cx, cy, nph)
+    achieved = ops / kern_s / 1e12
+    line = {
+        "metric": "LPF path-placements/s",
+        "value": round(value, 3),
+        "unit": "Gplacements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "full LPF, 512x512 RSA disks r~U[5,20] phi=0.3 seed 1602, "
+                               "|dx|,|dy|<=128 (33025 vectors), both phases, bit-packed input",
+                   "W": W, "H": H, "cx": cx, "cy": cy, "phases": nph},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(P_INT_TOPS, 3),
+                     "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4), "traffic": None,
+                     "kernel": "k_lpf_full (+k_ext inside the event window)",
+                     "event_ms_mean": round(kern_s * 1e3, 4),
+                     "ops_alg_per_launch": ops},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(img, cx, cy, args.cpu_stride)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,107 @@
+/*
+ * liblpf -- the entire lineal path function of periodic two-phase pixel images on AMD MI355X
+ * (gfx950), after Havelka, Kucerova & Sykora, "Compression and Reconstruction of Random
+ * Microstructures using Accelerated Lineal Path Function" (arXiv:1601.04359).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Image.  W x H pixels, periodic in both directions (Sec. 2.1 periodicity assumption, kept for
+ *   the lineal path in Sec. 2.2).  x is the column (0 <= x < W), y the row (0 <= y < H).
+ *   Phase index = pixel value: phase 0 and phase 1 (the paper's two phases "b"/"w").
+ * Bit-packed image ("bits").  uint64 words, row-major, row stride ceil(W/64) words; pixel (x,y)
+ *   is bit (x % 64) of word bits[y * ceil(W/64) + x / 64].  Bits beyond W in the last word of a
+ *   row are ignored on input and written as zero by lpf_pack.
+ * Segments.  For a vector v = (dx,dy) with n = max(|dx|,|dy|), the segment from (0,0) to v is
+ *   digitised into n + 1 pixels p_k (Sec. 2.2, Bresenham): along the major axis p_k moves by k,
+ *   and the minor coordinate is sgn(m) * floor((2k|m| + n) / (2n)) (ties rounded away from the
+ *   origin).  L_i(v) = #{x : I(x + p_k mod (W,H)) == i for all k} -- the count behind Alg.
+ *   "L2_eval"; the probability of Sec. 2.2 is L_i(v) / (W H), left to the caller.
+ * Domain.  Cutoff (cx,cy), 0 <= cx <= W-1, 0 <= cy <= H-1.  The canonical half domain D_c lists
+ *   [0,cx] x [0,cy] row by row (dy outer, dx inner), then [-cx,-1] x [1,cy] row by row; its size
+ *   is (cx+1)(cy+1) + cx*cy, and with cx = W-1, cy = H-1 it is the domain of eq. (segments),
+ *   2WH - W - H + 1 vectors.  L(-v) is defined as L(v) (eq. (symmetry)).
+ * Phases.  phase_mask bit 0 = phase 0, bit 1 = phase 1 (LPF_PHASE0 | LPF_PHASE1 = LPF_BOTH).
+ *   nph = number of bits set.  Output arrays hold the phases in increasing order.
+ * Output layouts.  LPF_OUT_HALF: uint32 counts[nph][|D_c|] in canonical order.
+ *   LPF_OUT_GRID: uint32 counts[nph][2cy+1][2cx+1], element [p][dy+cy][dx+cx], with both v and
+ *   -v filled (eq. (symmetry)).
+ * Memory.  Pointers are DEVICE pointers unless marked (host).  The caller owns every buffer; the
+ *   library only reads/writes them inside the work it enqueues.  lpf_ctx owns its own scratch
+ *   memory and cached tables (vector tables, launch plans, graphs).
+ * Streams.  Every compute call validates its arguments on the host, enqueues its kernels on
+ *   `stream` (a hipStream_t passed as void*; NULL = the default stream) and returns without
+ *   synchronising.  Results are valid once the stream has reached that point.  Scratch memory
+ *   is per context: use one context per stream (calls on one context must not overlap).
+ * Errors.  Arguments are checked before anything is enqueued; on a check failure nothing is
+ *   written, LPF_E_INVAL is returned and lpf_last_error() names the argument.  A failing HIP
+ *   call returns LPF_E_DEVICE (an asynchronous kernel fault may surface on a later call or on
+ *   stream synchronisation).  No C++ exception crosses this interface.
+ */
+#ifndef LPF_H
+#define LPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lpf_ctx_s *lpf_ctx;
+
+typedef enum {
+  LPF_OK = 0,
+  LPF_E_INVAL = -22,
+  LPF_E_NOMEM = -12,
+  LPF_E_DEVICE = -5,
+  LPF_E_UNSUPPORTED = -95
+} lpf_status;
+
+enum { LPF_PHASE0 = 1u, LPF_PHASE1 = 2u, LPF_BOTH = 3u };
+enum { LPF_OUT_HALF = 0, LPF_OUT_GRID = 1 };
+
+/* Create a context bound to HIP device `hip_device` (made current for the context's own
+ * allocations).  *out (host) receives the handle.  Errors: LPF_E_INVAL for a bad device or NULL
+ * out, LPF_E_NOMEM when host memory runs out. */
+lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out);
+
+/* Release the context's scratch memory and caches.  Waits for the device first.  NULL is a
+ * no-op. */
+void lpf_ctx_destroy(lpf_ctx ctx);
+
+/* Message of the last failing call on this host thread; never NULL ("" when none). */
+const char *lpf_last_error(void);
+
+/* |D_c| = (cx+1)(cy+1) + cx*cy for cx, cy >= 0 (eq. (segments) with a cutoff); -1 when negative. */
+int64_t lpf_num_vectors(int cx, int cy);
+
+/* Write the canonical half domain as int16 pairs dxdy[2i] = dx, dxdy[2i+1] = dy (host buffer of
+ * 2*|D_c| int16).  Errors: LPF_E_INVAL for negative or > 32767 cutoffs or NULL dxdy. */
+lpf_status lpf_vectors(int cx, int cy, int16_t *dxdy);
+
+/* Pack a uint8 image (row-major W*H bytes, nonzero = phase 1) into the bit layout above.
+ * bits: ceil(W/64) * H uint64, written in full (padding bits zero).  One kernel launch.
+ * Errors: LPF_E_INVAL for NULL pointers or W, H outside [1, 65535]. */
+lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bits, void *stream);
+
+/* Entire lineal path function of one image (Sec. 2.2 definition; Alg. "L2_eval" result) for every
+ * vector of D_c and every phase of phase_mask, exact uint32 counts in `out_layout`.
+ * bits: packed image as above (read only).  counts: see "Output layouts" (written in full).
+ * Requires 1 <= W, H <= 65535, 0 <= cx <= W-1, 0 <= cy <= H-1, phase_mask in {1,2,3}.
+ * Errors: LPF_E_INVAL (arguments), LPF_E_UNSUPPORTED (an image whose halo rows exceed the
+ * on-chip staging limit), LPF_E_NOMEM / LPF_E_DEVICE (HIP). */
+lpf_status lpf_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                    unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
+
+/* Tile-shape override for lpf_full (and the kernels that share its launch plans); used by the
+ * autotuner.  R = 32-pixel words per lane (1,2,4,8,16), S = lanes per image row (power of two,
+ * <= 64), waves_per_group (1..8), lds_bytes = staging budget per workgroup (<= 160 KiB).
+ * 0 in any field restores the automatic choice for that field.  This replaces the paper's
+ * occupancy rule for the block size, eq. (block).  Errors: LPF_E_INVAL for values out of range.
+ * A shape that cannot cover an image makes the later compute call fail with LPF_E_UNSUPPORTED. */
+lpf_status lpf_set_full_shape(lpf_ctx ctx, int R, int S, int waves_per_group, int lds_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPF_H */

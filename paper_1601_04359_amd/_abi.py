@@ -1,0 +1,139 @@
+"""ctypes binding of liblpf (include/lpf.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Tensors are PyTorch tensors
+used as device memory; the stream is torch's current stream unless one is given.  All compute
+runs in the HIP kernels of liblpf.so; when the library is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"liblpf.so not built at {LIB_PATH}; run `python -m paper_1601_04359_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LPF_OK = 0
+LPF_E_INVAL = -22
+LPF_E_NOMEM = -12
+LPF_E_DEVICE = -5
+LPF_E_UNSUPPORTED = -95
+LPF_PHASE0, LPF_PHASE1, LPF_BOTH = 1, 2, 3
+LPF_OUT_HALF, LPF_OUT_GRID = 0, 1
+
+_P = ctypes.c_void_p
+_i32, _i64, _u32, _u64 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_uint64
+
+
+class LpfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblpf status {status}: {msg}")
+        self.status = status
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("lpf_ctx_create", _i32, _i32, ctypes.POINTER(_P))
+_sig("lpf_ctx_destroy", None, _P)
+_sig("lpf_last_error", ctypes.c_char_p)
+_sig("lpf_num_vectors", _i64, _i32, _i32)
+_sig("lpf_vectors", _i32, _i32, _i32, _P)
+_sig("lpf_pack", _i32, _P, _P, _i32, _i32, _P, _P)
+_sig("lpf_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != LPF_OK:
+        raise LpfError(status, _lib.lpf_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.data_ptr() % 8:
+        raise ValueError(f"{name}: must be 8-byte aligned")
+    return t.data_ptr()
+
+
+def lpf_ctx_create(device: int = 0) -> int:
+    h = _P()
+    _check(_lib.lpf_ctx_create(device, ctypes.byref(h)))
+    return h.value
+
+
+def lpf_ctx_destroy(ctx: int) -> None:
+    _lib.lpf_ctx_destroy(ctx)
+
+
+def lpf_num_vectors(cx: int, cy: int) -> int:
+    return int(_lib.lpf_num_vectors(cx, cy))
+
+
+def lpf_vectors(cx: int, cy: int):
+    import numpy as np
+    n = lpf_num_vectors(cx, cy)
+    if n < 0:
+        raise LpfError(LPF_E_INVAL, "negative cutoff")
+    out = np.zeros((n, 2), np.int16)
+    _check(_lib.lpf_vectors(cx, cy, out.ctypes.data_as(_P)))
+    return out
+
+
+def lpf_pack(ctx: int, img: torch.Tensor, W: int, H: int, bits: torch.Tensor, stream=None) -> None:
+    if img.numel() != W * H or bits.numel() != ((W + 63) // 64) * H:
+        raise ValueError("lpf_pack: buffer sizes do not match W, H")
+    _check(_lib.lpf_pack(ctx, _dev(img, torch.uint8, "img"), W, H,
+                         _dev(bits, torch.int64, "bits"), _stream(stream)))
+
+
+def counts_shape(cx: int, cy: int, phase_mask: int, layout: int):
+    nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+    if layout == LPF_OUT_HALF:
+        return (nph, lpf_num_vectors(cx, cy))
+    return (nph, 2 * cy + 1, 2 * cx + 1)
+
+
+def lpf_full(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, phase_mask: int,
+             out_layout: int, counts: torch.Tensor, stream=None) -> None:
+    if bits.numel() != ((W + 63) // 64) * H:
+        raise ValueError("lpf_full: bits size does not match W, H")
+    shp = counts_shape(cx, cy, phase_mask, out_layout) if 0 <= cx and 0 <= cy else None
+    if shp is not None and counts.numel() != int(torch.Size(shp).numel()):
+        raise ValueError(f"lpf_full: counts must hold {shp} elements")
+    _check(_lib.lpf_full(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+                         out_layout, _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_set_full_shape(ctx: int, R: int = 0, S: int = 0, waves_per_group: int = 0,
+                       lds_bytes: int = 0) -> None:
+    _check(_lib.lpf_set_full_shape(ctx, R, S, waves_per_group, lds_bytes))

@@ -1,0 +1,72 @@
+"""C-ABI checks that need no GPU: the library loads, exports what include/*.h declares, and its
+host-side logic (vector enumeration, argument checks) behaves as documented."""
+from __future__ import annotations
+
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(lpf_\w+|anneal_\w+)\s*\(", src,
+                             flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_declared_symbols():
+    from paper_1601_04359_amd import _abi
+    names = _declared_symbols()
+    assert {"lpf_full", "lpf_pack", "lpf_ctx_create", "lpf_vectors"} <= names
+    lib = _abi.lib()
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+
+
+@pytest.mark.parametrize("cx,cy", [(0, 0), (16, 16), (5, 9), (128, 128), (40, 3)])
+def test_vectors_match_oracle_enumeration(cx, cy):
+    from paper_1601_04359_amd import _abi
+    assert _abi.lpf_num_vectors(cx, cy) == oracle.num_vectors(cx, cy)
+    assert np.array_equal(_abi.lpf_vectors(cx, cy), oracle.vectors(cx, cy))
+
+
+def test_num_vectors_negative():
+    from paper_1601_04359_amd import _abi
+    assert _abi.lpf_num_vectors(-1, 3) == -1
+
+
+def test_argument_errors_without_device():
+    from paper_1601_04359_amd import _abi
+    lib = _abi.lib()
+    # NULL context: rejected before any HIP call, message names the argument
+    st = lib.lpf_full(None, None, 8, 8, 1, 1, 3, 0, None, None)
+    assert st == _abi.LPF_E_INVAL
+    assert b"ctx" in lib.lpf_last_error()
+    assert lib.lpf_vectors(-1, 0, None) == _abi.LPF_E_INVAL
+    assert b"cutoff" in lib.lpf_last_error()
+    assert lib.lpf_set_full_shape(None, 8, 2, 8, 0) == _abi.LPF_E_INVAL
+    h = ctypes.c_void_p()
+    assert lib.lpf_ctx_create(-1, ctypes.byref(h)) == _abi.LPF_E_INVAL
+    assert lib.lpf_ctx_create(0, None) == _abi.LPF_E_INVAL
+
+
+def test_python_binding_checks():
+    import torch
+    from paper_1601_04359_amd import _abi
+    with pytest.raises(ValueError):
+        _abi._dev(torch.zeros(4, dtype=torch.int64), torch.int64, "bits")  # host tensor
+    with pytest.raises(ValueError):
+        _abi.lpf_full(0, torch.zeros(3, dtype=torch.int64), 8, 8, 1, 1, 3, 0,
+                      torch.zeros(1, dtype=torch.int32))

@@ -1,0 +1,171 @@
+"""GPU parity of lpf_pack / lpf_full against the CPU oracle (bit-exact integer counts)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_04359_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_counts(ctx, img, cx, cy, mask=3, layout=0):
+    import torch
+    H, W = img.shape
+    t = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    bits = ctx.pack(t)
+    out = ctx.full(bits, W, H, cx, cy, mask, layout)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.uint32)
+
+
+def _announce(name):
+    print(f"[gpu] {name}", flush=True)
+
+
+def test_pack_layout(ctx):
+    import torch
+    _announce("pack layout")
+    for (H, W) in [(1, 1), (3, 64), (5, 65), (7, 130), (64, 64), (9, 200)]:
+        img = wl.random_binary(W, H, 0.5, W * 31 + H)
+        bits = ctx.pack(torch.from_numpy(img).cuda()).cpu().numpy().view(np.uint64)
+        wpr = (W + 63) // 64
+        ref = np.zeros((H, wpr), np.uint64)
+        for y in range(H):
+            for x in range(W):
+                if img[y, x]:
+                    ref[y, x // 64] |= np.uint64(1) << np.uint64(x % 64)
+        assert np.array_equal(bits, ref), (H, W)
+
+
+def test_small_boolean_64_grid(ctx):
+    _announce("64x64 boolean, cutoff 16, grid layout")
+    img = wl.small_boolean_64()
+    got = _gpu_counts(ctx, img, 16, 16, 3, 1)
+    ref = oracle.lpf(img, 16, 16, 3, layout=1)
+    assert np.array_equal(got, ref)
+    got_h = _gpu_counts(ctx, img, 16, 16, 3, 0)
+    assert np.array_equal(got_h, oracle.lpf(img, 16, 16, 3, layout=0))
+
+
+@pytest.mark.parametrize("seed", range(1, 4))
+def test_small_boolean_64_more_seeds(ctx, seed):
+    img = wl.small_boolean_64(1601 + seed)
+    assert np.array_equal(_gpu_counts(ctx, img, 16, 16), oracle.lpf(img, 16, 16, 3))
+
+
+@pytest.mark.parametrize("H,W,cx,cy", [
+    (1, 1, 0, 0), (1, 7, 6, 0), (9, 1, 0, 8), (5, 7, 6, 4), (23, 37, 36, 22), (31, 33, 32, 30),
+    (50, 50, 49, 49), (64, 96, 95, 63), (70, 130, 40, 30), (40, 200, 199, 39), (100, 100, 99, 99),
+])
+def test_ragged_full_domain(ctx, H, W, cx, cy):
+    _announce(f"ragged {H}x{W} c=({cx},{cy})")
+    img = wl.random_binary(W, H, 0.62, 1000 * H + W)
+    got = _gpu_counts(ctx, img, cx, cy)
+    ref = oracle.lpf(img, cx, cy, 3)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mask", [1, 2])
+def test_single_phase(ctx, mask):
+    img = wl.boolean_disks(96, 80, 5.0, 0.4, 7)
+    assert np.array_equal(_gpu_counts(ctx, img, 30, 25, mask), oracle.lpf(img, 30, 25, mask))
+
+
+def test_brute_tiny(ctx):
+    # the independent brute force, directly against the GPU
+    for s in range(4):
+        img = wl.random_binary(8, 8, 0.3 + 0.1 * s, 500 + s)
+        assert np.array_equal(_gpu_counts(ctx, img, 7, 7), brute.lpf(img, 7, 7, 3))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 0, 0), (2, 1, 0, 0), (4, 2, 0, 0), (8, 4, 2, 8192),
+                                   (16, 1, 8, 16384), (2, 4, 4, 0)])
+def test_forced_tile_shapes(ctx, shape):
+    # every lane layout and the multi-tile path (small LDS budget) give the same counts
+    R, S, wpg, lds = shape
+    _announce(f"tile shape R={R} S={S} wpg={wpg} lds={lds}")
+    img = wl.boolean_disks(200, 150, 6.0, 0.45, 99)
+    ref = oracle.lpf(img, 40, 37, 3)
+    try:
+        ctx.set_full_shape(R, S, wpg, lds)
+        got = _gpu_counts(ctx, img, 40, 37)
+    finally:
+        ctx.set_full_shape(0, 0, 0, 0)
+    assert np.array_equal(got, ref)
+
+
+def test_multi_tile_grid(ctx):
+    img = wl.boolean_disks(160, 300, 4.0, 0.5, 5)
+    try:
+        ctx.set_full_shape(0, 0, 0, 8192)
+        got = _gpu_counts(ctx, img, 20, 60, 3, 1)
+    finally:
+        ctx.set_full_shape(0, 0, 0, 0)
+    assert np.array_equal(got, oracle.lpf(img, 20, 60, 3, layout=1))
+
+
+def test_deterministic(ctx):
+    img = wl.boolean_disks(128, 128, 5.0, 0.5, 3)
+    a = _gpu_counts(ctx, img, 32, 32)
+    b = _gpu_counts(ctx, img, 32, 32)
+    assert np.array_equal(a, b)
+
+
+def _property_checks(img, got, cx, cy):
+    H, W = img.shape
+    v = oracle.vectors(cx, cy)
+    unit = np.max(np.abs(v), axis=1) <= 1
+    for ph in (0, 1):
+        s2 = brute.s2_fft(img, ph)
+        ref = s2[v[:, 1] % H, v[:, 0] % W]
+        assert got[ph, 0] == int((img == ph).sum())           # eq. (l2zero)
+        assert np.array_equal(got[ph, unit], ref[unit])        # unit steps = N S2
+        assert np.all(got[ph].astype(np.int64) <= ref)         # L <= N S2
+
+
+def test_rsa_512_cutoff_128(ctx):
+    # the 512 x 512, cutoff 128 workload at full size, in the benchmark's launch configuration:
+    # sampled vectors against the oracle, properties on all vectors
+    _announce("512x512 rsa disks, cutoff 128")
+    img = wl.rsa_512()
+    got = _gpu_counts(ctx, img, 128, 128)
+    v = oracle.vectors(128, 128)
+    g = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([g.choice(len(v), 120, replace=False), [0, 1, 128, 129, len(v) - 1],
+                                    np.flatnonzero((np.abs(v[:, 0]) == 128) | (v[:, 1] == 128))[:20]]))
+    ref = oracle.lpf_vectors(img, v[idx], 3)
+    assert np.array_equal(got[:, idx], ref)
+    _property_checks(img, got, 128, 128)
+
+
+def test_tiled_large_image(ctx):
+    # a 1024 x 1024 image with cutoff 512 (several row tiles): tiling property + sampled oracle
+    _announce("1024x1024 cutoff 512 (row tiles)")
+    small = wl.boolean_disks(256, 256, 9.0, 0.4, 17)
+    img = np.tile(small, (4, 4))
+    got = _gpu_counts(ctx, img, 255, 255)
+    v = oracle.vectors(255, 255)
+    g = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([g.choice(len(v), 60, replace=False), [0, len(v) - 1]]))
+    sub = oracle.lpf_vectors(small, v[idx], 3).astype(np.int64)
+    assert np.array_equal(got[:, idx].astype(np.int64), 16 * sub)
+    big = wl.boolean_disks(1024, 1024, 7.0, 0.35, 23)
+    got = _gpu_counts(ctx, big, 512, 512)
+    v = oracle.vectors(512, 512)
+    idx = np.unique(np.concatenate([g.choice(len(v), 40, replace=False), [0, 1, len(v) - 1]]))
+    assert np.array_equal(got[:, idx], oracle.lpf_vectors(big, v[idx], 3))
+    _property_checks(big, got, 512, 512)
