@@ -67,7 +67,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (5 times) before the timed steps, "
+                         "as the reference kernel for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -84,6 +87,13 @@ def main() -> int:
     nph = 2
     img = wl.rsa_512()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 * 2**20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = Context(0)
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):

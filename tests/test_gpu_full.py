@@ -92,11 +92,11 @@ def test_brute_tiny(ctx):
         assert np.array_equal(_gpu_counts(ctx, img, 7, 7), brute.lpf(img, 7, 7, 3))
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 0, 0), (2, 1, 0, 0), (4, 2, 0, 0), (8, 4, 2, 8192),
-                                   (16, 1, 8, 16384), (2, 4, 4, 0)])
+@pytest.mark.parametrize("shape", [(1, 8, 0, 0), (2, 4, 0, 0), (4, 2, 2, 8192), (8, 1, 0, 0),
+                                   (16, 1, 8, 16384), (2, 0, 4, 0), (1, 0, 1, 0), (8, 4, 3, 0)])
 def test_forced_tile_shapes(ctx, shape):
     # every lane layout and the multi-tile path (small LDS budget) give the same counts
-    R, S, wpg, lds = shape
+    R, S, wpg, lds = shape  # the image is 200 px wide: 7 words per row
     _announce(f"tile shape R={R} S={S} wpg={wpg} lds={lds}")
     img = wl.boolean_disks(200, 150, 6.0, 0.45, 99)
     ref = oracle.lpf(img, 40, 37, 3)
@@ -106,6 +106,17 @@ def test_forced_tile_shapes(ctx, shape):
     finally:
         ctx.set_full_shape(0, 0, 0, 0)
     assert np.array_equal(got, ref)
+
+
+def test_forced_shape_too_narrow(ctx):
+    from paper_1601_04359_amd import LpfError
+    img = wl.boolean_disks(200, 150, 6.0, 0.45, 99)
+    try:
+        ctx.set_full_shape(1, 1, 0, 0)
+        with pytest.raises(LpfError):
+            _gpu_counts(ctx, img, 40, 37)
+    finally:
+        ctx.set_full_shape(0, 0, 0, 0)
 
 
 def test_multi_tile_grid(ctx):
