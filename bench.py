@@ -25,6 +25,19 @@ if ROOT not in sys.path:
 # MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz (4 SIMD16 per CU, 1 op/lane/clk)
 P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 
+# HBM bytes per k_lpf_full launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by the
+# same counters on a 256 MiB copy), profiles/k_lpf_full_512_c128.md.  Valid only for the kernel
+# source the counters were taken on; reported as null once that source changes.
+MEASURED_TRAFFIC = {"src_sha256_16": "00871149f810cf37", "bytes": 2198 * 1024}
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1601_04359_amd", "csrc", "k_full.hip")
+    with open(path, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC["bytes"] if sha == MEASURED_TRAFFIC["src_sha256_16"] else None
+
 
 def path_pixels(cx: int, cy: int) -> int:
     """M_c = sum over the canonical half domain of (max(|dx|,|dy|) + 1)."""
@@ -139,7 +152,8 @@ def main() -> int:
                                "|dx|,|dy|<=128 (33025 vectors), both phases, bit-packed input",
                    "W": W, "H": H, "cx": cx, "cy": cy, "phases": nph},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(P_INT_TOPS, 3),
-                     "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4), "traffic": None,
+                     "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": "k_lpf_full (+k_ext inside the event window)",
                      "event_ms_mean": round(kern_s * 1e3, 4),
                      "ops_alg_per_launch": ops},
