@@ -92,6 +92,71 @@ lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bit
 lpf_status lpf_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
 
+/* Exact change of the lineal path function under pixel interchanges (Sec. 4 modification
+ * operator: the values of pixels a and b are exchanged, which preserves the volume fractions).
+ * swaps: int32[n][2] linear pixel indices y*W + x (device).  delta: int32[n][nph][|D_c|] (device,
+ * written in full) with delta[s][p][i] = L_p(I')(v_i) - L_p(I)(v_i), canonical vector order.
+ * An interchange of two pixels of the same phase, a == b, or an index outside [0, W*H) gives an
+ * all-zero row (indices live on the device and are not checked on the host).  Only the
+ * translations whose segment covers a or b are recounted.  Same requirements on W, H, cx, cy,
+ * phase_mask as lpf_full; 0 <= n <= 2^24.  Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
+lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                          unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
+                          void *stream);
+
+/* ---- simulated annealing (Sec. 4, Alg. "annealing"; objective eq. (LSE)) ------------------ */
+
+typedef struct lpf_anneal_s *lpf_anneal;
+
+/* One step's record (device).  accepted_k = index of the applied candidate in draw order, or -1
+ * when none passed; a = the phase-1 pixel that became phase 0, b = the phase-0 pixel that became
+ * phase 1; delta_e = its energy change; e = energy after the step; step = the step's index. */
+typedef struct {
+  int32_t accepted_k, a, b, reserved;
+  double delta_e, e;
+  uint64_t step;
+} lpf_step_result;
+
+enum { LPF_PROP_UNIFORM = 0, LPF_PROP_INTERFACIAL = 1 };
+
+/* Create an annealing chain on a W x H image (the "cell").  The caller owns and keeps alive:
+ *   bits    packed image (device), updated in place by every accepted step;
+ *   counts  uint32[nph][|D_c|] (device), written here with L(bits) and kept equal to it;
+ *   target  uint32[nph][|D_c|] (device, read only): exact counts of the original image over Nt
+ *           pixels (Nt >= 1), e.g. from lpf_full on that image with the same cutoff and phases;
+ *   e       one double (device), written here with eq. (LSE), sum over the mask's phases and D_c
+ *           of (target/Nt - counts/(W*H))^2, and updated by every accepted step.
+ * pos: NULL, or int32[W*H] (device) holding the phase-1 pixel list (n1 entries) followed by the
+ *   phase-0 list (a chain exported by lpf_anneal_export); NULL builds both lists in ascending
+ *   pixel order.  n1 is read only when pos is given.  seed and step0 select the random stream:
+ *   candidate k of step s uses Philox-4x64-10 with counter {s, k, 0, 0} and key {seed, 0x6c7066}:
+ *   a = pos1[(r0>>32)*n1 >> 32], b = pos0[(r1>>32)*n0 >> 32], U = (r2>>11) * 2^-53.
+ * Requires an image with both phases present; same W, H, cx, cy, phase_mask rules as lpf_full.
+ * Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
+lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, uint32_t *counts, const uint32_t *target,
+                             int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
+                             int n1, double *e, lpf_anneal *out, void *stream);
+
+/* One step: draw n_candidates interchanges (a phase-1 pixel with a phase-0 pixel; with
+ * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),
+ * compute each one's exact energy change de against the current state, and apply the first, in
+ * draw order, with de <= 0 or U < exp(-de/T) (the Metropolis rule for a minimisation).  The
+ * step's record is written to *out (device).  Everything stays on the device.
+ * Errors: LPF_E_INVAL (n_candidates outside [1, 2^20], proposal, T <= 0), LPF_E_NOMEM,
+ * LPF_E_DEVICE. */
+lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
+                       lpf_step_result *out, void *stream);
+
+/* Copy the chain's pixel lists to pos (device, int32[W*H]: phase-1 list then phase-0 list) and
+ * return, after synchronising the stream, the number of phase-1 pixels and the next step index
+ * (host).  With the caller's bits, counts and e this is everything a resumed chain needs. */
+lpf_status lpf_anneal_export(lpf_anneal st, int32_t *pos, int *n1, uint64_t *next_step,
+                             void *stream);
+
+/* Release the chain's device state (waits for the device).  NULL is a no-op. */
+void lpf_anneal_destroy(lpf_anneal st);
+
 /* Tile-shape override for lpf_full (and the kernels that share its launch plans); used by the
  * autotuner.  R = 32-pixel words per lane (1,2,4,8,16), S = lanes per image row (power of two,
  * <= 64), waves_per_group (1..8), lds_bytes = staging budget per workgroup (<= 160 KiB).

@@ -9,8 +9,19 @@ from __future__ import annotations
 import torch
 
 from . import _abi
-from ._abi import (LPF_BOTH, LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1, LpfError,
-                   counts_shape, lpf_num_vectors, lpf_vectors)
+from ._abi import (LPF_BOTH, LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1,
+                   LPF_PROP_INTERFACIAL, LPF_PROP_UNIFORM, LpfError, counts_shape,
+                   lpf_num_vectors, lpf_vectors)
+
+import numpy as _np
+
+# host view of lpf_step_result records (an int64 tensor of shape (n, 5) on the device)
+STEP_DTYPE = _np.dtype([("k", _np.int32), ("a", _np.int32), ("b", _np.int32), ("pad", _np.int32),
+                        ("de", _np.float64), ("e", _np.float64), ("step", _np.uint64)])
+
+
+def step_records(t: torch.Tensor) -> _np.ndarray:
+    return t.detach().cpu().numpy().view(STEP_DTYPE).reshape(-1)
 
 
 def packed_words(W: int, H: int) -> int:
@@ -58,6 +69,68 @@ class Context:
         _abi.lpf_full(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
         return out
 
+    def delta_swap(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                   swaps: torch.Tensor, phase_mask: int = LPF_BOTH, out=None,
+                   stream=None) -> torch.Tensor:
+        """delta int32 (n, nph, |D_c|) = L(I') - L(I) for interchanges swaps (n, 2) int32."""
+        n = swaps.shape[0]
+        nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+        if out is None:
+            out = torch.empty((n, nph, lpf_num_vectors(cx, cy)), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_delta_swap(self.handle, bits, W, H, cx, cy, phase_mask, swaps.contiguous(), n,
+                            out, stream)
+        return out
+
     def set_full_shape(self, R: int = 0, S: int = 0, waves_per_group: int = 0,
                        lds_bytes: int = 0) -> None:
         _abi.lpf_set_full_shape(self.handle, R, S, waves_per_group, lds_bytes)
+
+
+class Anneal:
+    """A device-resident annealing chain (anneal_step); the tensors below are its state.
+
+    bits (packed cell, updated in place), counts (int32 [nph][|D_c|]), e (float64 [1]) are
+    allocated here and owned by this object; target (int32 [nph][|D_c|]) is the caller's."""
+
+    def __init__(self, ctx: Context, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                 phase_mask: int, target: torch.Tensor, Nt: int, seed: int, step0: int = 0,
+                 pos: torch.Tensor | None = None, n1: int = 0, stream=None):
+        self.ctx, self.W, self.H, self.cx, self.cy, self.phase_mask = ctx, W, H, cx, cy, phase_mask
+        dev = bits.device
+        self.bits = bits.clone().contiguous()
+        self.counts = torch.empty(counts_shape(cx, cy, phase_mask, LPF_OUT_HALF), dtype=torch.int32,
+                                  device=dev)
+        self.target = target.contiguous()
+        self.e = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.handle = _abi.lpf_anneal_create(ctx.handle, self.bits, W, H, cx, cy, phase_mask,
+                                             self.counts, self.target, Nt, seed, step0, pos, n1,
+                                             self.e, stream)
+
+    def step(self, n_candidates: int, T: float, out: torch.Tensor,
+             proposal: int = LPF_PROP_UNIFORM, stream=None) -> None:
+        """One step; its record goes to `out` (a device int64 tensor row of 5 elements)."""
+        _abi.anneal_step(self.handle, n_candidates, proposal, T, out, stream)
+
+    def run(self, n_candidates: int, Ts, proposal: int = LPF_PROP_UNIFORM,
+            stream=None) -> torch.Tensor:
+        recs = torch.empty((len(Ts), 5), dtype=torch.int64, device=self.bits.device)
+        for i, T in enumerate(Ts):
+            _abi.anneal_step(self.handle, n_candidates, proposal, float(T), recs[i], stream)
+        return recs
+
+    def export(self, stream=None):
+        pos = torch.empty(self.W * self.H, dtype=torch.int32, device=self.bits.device)
+        n1, nxt = _abi.lpf_anneal_export(self.handle, pos, stream)
+        return pos, n1, nxt
+
+    def close(self) -> None:
+        if getattr(self, "handle", 0):
+            _abi.lpf_anneal_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

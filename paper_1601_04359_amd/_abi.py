@@ -52,6 +52,15 @@ _sig("lpf_vectors", _i32, _i32, _i32, _P)
 _sig("lpf_pack", _i32, _P, _P, _i32, _i32, _P, _P)
 _sig("lpf_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
 _sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
+_sig("lpf_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
+_sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
+     _P, _i32, _P, ctypes.POINTER(_P), _P)
+_sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
+_sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
+_sig("lpf_anneal_destroy", None, _P)
+
+LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL = 0, 1
+STEP_RESULT_BYTES = 40  # lpf_step_result: int32 x4, double x2, uint64
 
 
 def lib() -> ctypes.CDLL:
@@ -132,6 +141,50 @@ def lpf_full(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, pha
         raise ValueError(f"lpf_full: counts must hold {shp} elements")
     _check(_lib.lpf_full(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
                          out_layout, _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                   phase_mask: int, swaps: torch.Tensor, n: int, delta: torch.Tensor,
+                   stream=None) -> None:
+    if swaps.numel() != 2 * n:
+        raise ValueError("lpf_delta_swap: swaps must hold n pairs")
+    nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+    if n and delta.numel() != n * nph * lpf_num_vectors(cx, cy):
+        raise ValueError("lpf_delta_swap: delta must hold n * nph * |D_c| elements")
+    _check(_lib.lpf_delta_swap(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+                               _dev(swaps, torch.int32, "swaps") if n else None, n,
+                               _dev(delta, torch.int32, "delta") if n else None, _stream(stream)))
+
+
+def lpf_anneal_create(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                      phase_mask: int, counts: torch.Tensor, target: torch.Tensor, Nt: int,
+                      seed: int, step0: int, pos, n1: int, e: torch.Tensor, stream=None) -> int:
+    h = _P()
+    _check(_lib.lpf_anneal_create(
+        ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+        _dev(counts, torch.int32, "counts"), _dev(target, torch.int32, "target"), Nt, seed, step0,
+        _dev(pos, torch.int32, "pos") if pos is not None else None, n1,
+        _dev(e, torch.float64, "e"), ctypes.byref(h), _stream(stream)))
+    return h.value
+
+
+def anneal_step(st: int, n_candidates: int, proposal: int, T: float, out: torch.Tensor,
+                stream=None) -> None:
+    if out.device.type != "cuda" or out.dtype != torch.int64 or out.numel() < 5:
+        raise ValueError("anneal_step: out must be a device int64 tensor of >= 5 elements")
+    _check(_lib.anneal_step(st, n_candidates, proposal, float(T), out.data_ptr(), _stream(stream)))
+
+
+def lpf_anneal_export(st: int, pos: torch.Tensor | None, stream=None):
+    n1 = _i32()
+    nxt = _u64()
+    _check(_lib.lpf_anneal_export(st, _dev(pos, torch.int32, "pos") if pos is not None else None,
+                                  ctypes.byref(n1), ctypes.byref(nxt), _stream(stream)))
+    return n1.value, nxt.value
+
+
+def lpf_anneal_destroy(st: int) -> None:
+    _lib.lpf_anneal_destroy(st)
 
 
 def lpf_set_full_shape(ctx: int, R: int = 0, S: int = 0, waves_per_group: int = 0,

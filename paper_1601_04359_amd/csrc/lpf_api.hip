@@ -75,6 +75,16 @@ struct FullPlan {
   int64_t nv = 0;
 };
 
+struct DeltaPlan {
+  DeltaGeo geo{};
+  DeltaVec *vecs = nullptr;     // device, chunk order
+  int32_t *chunk_off = nullptr;  // device, nchunks + 1
+  uint32_t *runs = nullptr;      // device run table
+  int nchunks = 0;
+  int64_t nv = 0;
+  bool use_lds = false;
+};
+
 // Canonical half domain (eq. (segments) with a cutoff, one of each {v, -v}).
 void canonical_vectors(int cx, int cy, std::vector<int16_t> &out) {
   out.clear();
@@ -122,10 +132,28 @@ constexpr int kMaxLds = 160 * 1024;
 struct lpf_ctx_s {
   int dev = 0;
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
-  DevBuf ext, part;
+  std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
+  DevBuf ext, part, ext3;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
+};
+
+
+struct lpf_anneal_s {
+  lpf_ctx ctx = nullptr;
+  int W = 0, H = 0, cx = 0, cy = 0;
+  unsigned mask = 0;
+  uint64_t *bits = nullptr;
+  uint32_t *counts = nullptr;
+  const uint32_t *target = nullptr;
+  double *e = nullptr;
+  int64_t Nt = 0;
+  uint64_t seed = 0;
+  AnnealDev *dev = nullptr;  // device struct
+  int32_t *pos = nullptr;    // device, W*H: phase-1 list then phase-0 list (reserved in place)
+  DevBuf E3, cand, U, slot, S_part, ksel;
+  int K_cap = 0;
 };
 
 namespace {
@@ -248,6 +276,130 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
 
 int nph_of(unsigned mask) { return (int)(mask & 1u) + (int)((mask >> 1) & 1u); }
 
+constexpr int kDeltaLdsMax = 64 * 1024;
+
+// Geometry of the three frames used by the delta kernel (image, transposed, anti-transposed).
+DeltaGeo delta_geometry(int W, int H, int cx, int cy) {
+  DeltaGeo g{};
+  g.hy = std::min(cx, cy);
+  const int dims[3][3] = {{W, H, cx}, {H, W, cy}, {H, W, cy}};  // width, height, max major extent
+  int off = 0;
+  for (int i = 0; i < 3; ++i) {
+    ImgGeo &im = g.g[i];
+    im.W = dims[i][0];
+    im.H = dims[i][1];
+    im.we = ((im.W - 1 + dims[i][2]) >> 5) + 3;
+    im.off = off;
+    uint64_t pat = 0;
+    for (int t = 0; t < 64; t += im.W) pat |= 1ull << t;
+    im.pat = pat;
+    off += (im.H + g.hy) * im.we;
+  }
+  g.total = off;
+  return g;
+}
+
+lpf_status get_delta_plan(lpf_ctx c, int W, int H, int cx, int cy, int nchunks_req,
+                          DeltaPlan *&plan) {
+  std::vector<int16_t> can;
+  canonical_vectors(cx, cy, can);
+  const int64_t nv = (int64_t)can.size() / 2;
+  const int nchunks = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks_req, nv));
+  auto key = std::make_tuple(W, H, cx, cy, nchunks);
+  auto it = c->delta_plans.find(key);
+  if (it != c->delta_plans.end()) {
+    plan = &it->second;
+    return LPF_OK;
+  }
+  // Flat form of every vector: frame, major extent n, minor extent m, mirrored in x or not.
+  std::vector<DeltaVec> dv(nv);
+  std::vector<uint32_t> runs;
+  std::vector<int64_t> cost(nv);
+  for (int64_t i = 0; i < nv; ++i) {
+    const int dx = can[2 * i], dy = can[2 * i + 1];
+    const int adx = std::abs(dx);
+    int img, n, m;
+    bool q2;
+    if (adx >= dy) {
+      img = 0; n = adx; m = dy; q2 = dx < 0;
+    } else if (dx >= 0) {
+      img = 1; n = dy; m = dx; q2 = false;
+    } else {
+      img = 2; n = dy; m = adx; q2 = true;
+    }
+    // runs of the digitised flat segment: row j holds x with floor((2xm + n) / (2n)) == j
+    std::vector<int> lo(m + 1, -1), hi(m + 1, -1);
+    for (int x = 0; x <= n; ++x) {
+      const int j = n ? (int)((2LL * x * m + n) / (2LL * n)) : 0;
+      if (lo[j] < 0) lo[j] = x;
+      hi[j] = x;
+    }
+    dv[i] = DeltaVec{m, (int32_t)i, img, (int32_t)runs.size()};
+    int64_t px_tot = 0;
+    for (int j = 0; j <= m; ++j) {
+      const int a = q2 ? n - hi[j] : lo[j];
+      const int b = q2 ? n - lo[j] : hi[j];
+      runs.push_back((uint32_t)a | ((uint32_t)b << 16));
+      px_tot += (b - a) / 32 + 1;
+    }
+    cost[i] = (int64_t)(m + 1) * (4 * (n + 1) + 15 * (m + 1) * 1 + 15 * px_tot) + 8;
+  }
+  // chunks: longest-processing-time-first
+  std::vector<int> order(nv);
+  for (int64_t i = 0; i < nv; ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  using Item = std::pair<int64_t, int>;
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  for (int b = 0; b < nchunks; ++b) heap.push({0, b});
+  std::vector<std::vector<int>> bins(nchunks);
+  for (int i : order) {
+    Item t = heap.top();
+    heap.pop();
+    bins[t.second].push_back(i);
+    heap.push({t.first + cost[i], t.second});
+  }
+  std::vector<DeltaVec> vs;
+  vs.reserve(nv);
+  std::vector<int32_t> off(nchunks + 1, 0);
+  for (int b = 0; b < nchunks; ++b) {
+    off[b] = (int32_t)vs.size();
+    for (int i : bins[b]) vs.push_back(dv[i]);
+  }
+  off[nchunks] = (int32_t)vs.size();
+  DeltaPlan p;
+  p.geo = delta_geometry(W, H, cx, cy);
+  p.nchunks = nchunks;
+  p.nv = nv;
+  p.use_lds = (int64_t)p.geo.total * 4 <= kDeltaLdsMax;
+  hipError_t e;
+  if ((e = hipMalloc(&p.vecs, sizeof(DeltaVec) * vs.size())) != hipSuccess ||
+      (e = hipMalloc(&p.chunk_off, sizeof(int32_t) * off.size())) != hipSuccess ||
+      (e = hipMalloc(&p.runs, sizeof(uint32_t) * runs.size())) != hipSuccess)
+    return hip_fail(e, "delta plan allocation");
+  if ((e = hipMemcpy(p.vecs, vs.data(), sizeof(DeltaVec) * vs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.chunk_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.runs, runs.data(), sizeof(uint32_t) * runs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "delta plan upload");
+  auto res = c->delta_plans.emplace(key, p);
+  plan = &res.first->second;
+  return LPF_OK;
+}
+
+// Number of vector chunks for K candidates: enough workgroups to fill the device.
+int delta_chunks(int K) {
+  const int groups = (K + 255) / 256;
+  return std::max(1, 2048 / groups);
+}
+
+lpf_status check_image_args(const char *fn, int W, int H, int cx, int cy, unsigned mask) {
+  if (W < 1 || H < 1 || W > 65535 || H > 65535)
+    return fail(LPF_E_INVAL, std::string(fn) + ": W/H out of range");
+  if (cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1)
+    return fail(LPF_E_INVAL, std::string(fn) + ": cutoff must satisfy 0 <= cx <= W-1, 0 <= cy <= H-1");
+  if (mask < 1 || mask > 3) return fail(LPF_E_INVAL, std::string(fn) + ": phase_mask must be 1, 2 or 3");
+  return LPF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,6 +431,7 @@ lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out) {
   c->dev = hip_device;
   DeviceGuard g(c->dev);
   hipError_t e = prepare_full_kernels(kMaxLds);
+  if (e == hipSuccess) e = prepare_delta_kernels(kDeltaLdsMax);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "lpf_ctx_create: kernel attributes");
@@ -297,8 +450,14 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.bin_off);
       (void)hipFree(kv.second.dxdy);
     }
+    for (auto &kv : c->delta_plans) {
+      (void)hipFree(kv.second.vecs);
+      (void)hipFree(kv.second.chunk_off);
+      (void)hipFree(kv.second.runs);
+    }
     c->ext.release();
     c->part.release();
+    c->ext3.release();
   }
   delete c;
 }
@@ -368,6 +527,246 @@ lpf_status lpf_set_full_shape(lpf_ctx c, int R, int S, int waves_per_group, int 
   c->force_wpg = waves_per_group;
   c->force_lds = lds_bytes;
   return LPF_OK;
+}
+
+lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                          unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
+                          void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_delta_swap: ctx is NULL");
+  lpf_status st = check_image_args("lpf_delta_swap", W, H, cx, cy, phase_mask);
+  if (st != LPF_OK) return st;
+  if (n < 0 || n > (1 << 24)) return fail(LPF_E_INVAL, "lpf_delta_swap: n outside [0, 2^24]");
+  if (n == 0) return LPF_OK;
+  if (!bits || !swaps || !delta) return fail(LPF_E_INVAL, "lpf_delta_swap: NULL buffer");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_delta_swap: cannot select the context's device");
+  DeltaPlan *plan = nullptr;
+  if ((st = get_delta_plan(c, W, H, cx, cy, delta_chunks(n), plan)) != LPF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = c->ext3.ensure((size_t)plan->geo.total * 4)) != hipSuccess)
+    return hip_fail(e, "lpf_delta_swap: scratch");
+  if ((e = launch_ext3(bits, W, H, plan->geo, (uint32_t *)c->ext3.p, s)) != hipSuccess)
+    return hip_fail(e, "lpf_delta_swap: ext3");
+  DeltaLaunch L{};
+  L.E = (const uint32_t *)c->ext3.p;
+  L.geo = plan->geo;
+  L.bits = bits;
+  L.W = W;
+  L.H = H;
+  L.cand = reinterpret_cast<const int2 *>(swaps);
+  L.K = n;
+  L.vecs = plan->vecs;
+  L.chunk_off = plan->chunk_off;
+  L.runs = plan->runs;
+  L.phase_mask = phase_mask;
+  L.nv = (int)plan->nv;
+  L.delta_out = delta;
+  L.nchunks = plan->nchunks;
+  L.use_lds = plan->use_lds;
+  if ((e = launch_delta(0, L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
+  return LPF_OK;
+}
+
+lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, uint32_t *counts, const uint32_t *target,
+                             int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
+                             int n1, double *e_dev, lpf_anneal *out, void *stream) {
+  if (!out) return fail(LPF_E_INVAL, "lpf_anneal_create: out is NULL");
+  *out = nullptr;
+  if (!c) return fail(LPF_E_INVAL, "lpf_anneal_create: ctx is NULL");
+  lpf_status st = check_image_args("lpf_anneal_create", W, H, cx, cy, phase_mask);
+  if (st != LPF_OK) return st;
+  if (!bits || !counts || !target || !e_dev) return fail(LPF_E_INVAL, "lpf_anneal_create: NULL buffer");
+  if (Nt < 1 || Nt > ((int64_t)1 << 40)) return fail(LPF_E_INVAL, "lpf_anneal_create: Nt");
+  const int64_t N = (int64_t)W * H;
+  if (N < 2 || N > ((int64_t)1 << 26)) return fail(LPF_E_INVAL, "lpf_anneal_create: W*H outside [2, 2^26]");
+  if (pos && (n1 < 1 || n1 > N - 1)) return fail(LPF_E_INVAL, "lpf_anneal_create: n1");
+  // full evaluation for the initial counts (also validates the tile shape)
+  st = lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
+  if (st != LPF_OK) return st;
+  lpf_anneal a = new (std::nothrow) lpf_anneal_s();
+  if (!a) return fail(LPF_E_NOMEM, "lpf_anneal_create: host memory");
+  a->ctx = c;
+  a->W = W; a->H = H; a->cx = cx; a->cy = cy; a->mask = phase_mask;
+  a->bits = bits; a->counts = counts; a->target = target; a->e = e_dev;
+  a->Nt = Nt; a->seed = seed;
+  DeviceGuard g(c->dev);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  AnnealDev host{};
+  host.step = step0;
+  if ((e = hipMalloc(&a->dev, sizeof(AnnealDev))) != hipSuccess ||
+      (e = hipMalloc(&a->pos, sizeof(int32_t) * (size_t)N)) != hipSuccess) {
+    lpf_anneal_destroy(a);
+    return hip_fail(e, "lpf_anneal_create: allocation");
+  }
+  host.pos1 = a->pos;
+  host.pos0 = a->pos;  // set below once n1 is known
+  if (pos) {
+    host.n1 = n1;
+    host.n0 = (int32_t)(N - n1);
+    host.pos0 = a->pos + n1;
+    if ((e = hipMemcpyAsync(a->pos, pos, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(a->dev, &host, sizeof(AnnealDev), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      lpf_anneal_destroy(a);
+      return hip_fail(e, "lpf_anneal_create: state upload");
+    }
+  } else {
+    // lists in ascending order: count ones first, then place phase-0 list after the ones
+    int32_t *tmp1 = nullptr;
+    if ((e = hipMalloc(&tmp1, sizeof(int32_t) * (size_t)N)) != hipSuccess) {
+      lpf_anneal_destroy(a);
+      return hip_fail(e, "lpf_anneal_create: allocation");
+    }
+    AnnealDev scratch = host;
+    scratch.pos1 = a->pos;
+    scratch.pos0 = tmp1;
+    int32_t n1h = 0;
+    if ((e = hipMemcpyAsync(a->dev, &scratch, sizeof(AnnealDev), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_init_lists(a->dev, bits, W, H, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&n1h, &a->dev->n1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      (void)hipFree(tmp1);
+      lpf_anneal_destroy(a);
+      return hip_fail(e, "lpf_anneal_create: pixel lists");
+    }
+    if (n1h < 1 || n1h > N - 1) {
+      (void)hipFree(tmp1);
+      lpf_anneal_destroy(a);
+      return fail(LPF_E_INVAL, "lpf_anneal_create: the image must contain both phases");
+    }
+    host.n1 = n1h;
+    host.n0 = (int32_t)(N - n1h);
+    host.pos0 = a->pos + n1h;
+    if ((e = hipMemcpyAsync(a->pos + n1h, tmp1, sizeof(int32_t) * (size_t)(N - n1h), hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(a->dev, &host, sizeof(AnnealDev), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      (void)hipFree(tmp1);
+      lpf_anneal_destroy(a);
+      return hip_fail(e, "lpf_anneal_create: pixel lists");
+    }
+    (void)hipFree(tmp1);
+  }
+  const int nph = nph_of(phase_mask);
+  const int64_t nv = lpf_num_vectors(cx, cy);
+  if ((e = launch_lse(counts, target, nph * nv, N, Nt, e_dev, s)) != hipSuccess) {
+    lpf_anneal_destroy(a);
+    return hip_fail(e, "lpf_anneal_create: energy");
+  }
+  *out = a;
+  return LPF_OK;
+}
+
+lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
+                       void *stream) {
+  if (!a) return fail(LPF_E_INVAL, "anneal_step: state is NULL");
+  if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, "anneal_step: n_candidates outside [1, 2^20]");
+  if (proposal != LPF_PROP_UNIFORM && proposal != LPF_PROP_INTERFACIAL)
+    return fail(LPF_E_INVAL, "anneal_step: proposal");
+  if (!(T > 0.0)) return fail(LPF_E_INVAL, "anneal_step: T must be > 0");
+  if (!out) return fail(LPF_E_INVAL, "anneal_step: out is NULL");
+  lpf_ctx c = a->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  DeltaPlan *plan = nullptr;
+  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, delta_chunks(K), plan);
+  if (st != LPF_OK) return st;
+  DeltaPlan *plan1 = nullptr;
+  if ((st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, delta_chunks(1), plan1)) != LPF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  const bool first = a->E3.p == nullptr;
+  if ((e = a->E3.ensure((size_t)plan->geo.total * 4)) != hipSuccess ||
+      (e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
+      (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
+      (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
+      (e = a->S_part.ensure(sizeof(int64_t) * (size_t)K * plan->nchunks)) != hipSuccess ||
+      (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess)
+    return hip_fail(e, "anneal_step: scratch");
+  uint32_t *E = (uint32_t *)a->E3.p;
+  int2 *cand = (int2 *)a->cand.p;
+  const int64_t N = (int64_t)a->W * a->H;
+  if (first && (e = launch_ext3(a->bits, a->W, a->H, plan->geo, E, s)) != hipSuccess)
+    return hip_fail(e, "anneal_step: ext3");
+  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cand,
+                          (double *)a->U.p, (int2 *)a->slot.p, s)) != hipSuccess)
+    return hip_fail(e, "anneal_step: propose");
+  DeltaLaunch L{};
+  L.E = E;
+  L.geo = plan->geo;
+  L.bits = a->bits;
+  L.W = a->W;
+  L.H = a->H;
+  L.cand = cand;
+  L.K = K;
+  L.vecs = plan->vecs;
+  L.chunk_off = plan->chunk_off;
+  L.runs = plan->runs;
+  L.phase_mask = a->mask;
+  L.nv = (int)plan->nv;
+  L.counts = a->counts;
+  L.target = a->target;
+  L.N = N;
+  L.Nt = a->Nt;
+  L.S_part = (int64_t *)a->S_part.p;
+  L.nchunks = plan->nchunks;
+  L.use_lds = plan->use_lds;
+  if ((e = launch_delta(1, L, s)) != hipSuccess) return hip_fail(e, "anneal_step: delta");
+  if ((e = launch_select(a->dev, (const int64_t *)a->S_part.p, plan->nchunks, K, cand,
+                         (const double *)a->U.p, T, N, a->Nt, a->e, (int32_t *)a->ksel.p,
+                         reinterpret_cast<StepResult *>(out), s)) != hipSuccess)
+    return hip_fail(e, "anneal_step: select");
+  DeltaLaunch L1 = L;
+  L1.vecs = plan1->vecs;
+  L1.chunk_off = plan1->chunk_off;
+  L1.runs = plan1->runs;
+  L1.nchunks = plan1->nchunks;
+  L1.counts_rw = a->counts;
+  L1.k_sel = (const int32_t *)a->ksel.p;
+  if ((e = launch_delta(2, L1, s)) != hipSuccess) return hip_fail(e, "anneal_step: apply counts");
+  if ((e = launch_apply_swap(a->dev, a->bits, a->W, (const int32_t *)a->ksel.p, cand,
+                             (const int2 *)a->slot.p, s)) != hipSuccess)
+    return hip_fail(e, "anneal_step: apply swap");
+  if ((e = launch_ext3(a->bits, a->W, a->H, plan->geo, E, s)) != hipSuccess)
+    return hip_fail(e, "anneal_step: ext3");
+  return LPF_OK;
+}
+
+lpf_status lpf_anneal_export(lpf_anneal a, int32_t *pos, int *n1, uint64_t *next_step,
+                             void *stream) {
+  if (!a) return fail(LPF_E_INVAL, "lpf_anneal_export: state is NULL");
+  DeviceGuard g(a->ctx->dev);
+  hipStream_t s = (hipStream_t)stream;
+  AnnealDev host{};
+  hipError_t e;
+  if ((e = hipMemcpyAsync(&host, a->dev, sizeof(AnnealDev), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (pos && (e = hipMemcpyAsync(pos, a->pos, sizeof(int32_t) * (size_t)a->W * a->H,
+                                  hipMemcpyDeviceToDevice, s)) != hipSuccess) ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "lpf_anneal_export");
+  if (n1) *n1 = host.n1;
+  if (next_step) *next_step = host.step;
+  return LPF_OK;
+}
+
+void lpf_anneal_destroy(lpf_anneal a) {
+  if (!a) return;
+  {
+    DeviceGuard g(a->ctx->dev);
+    (void)hipDeviceSynchronize();
+    if (a->dev) (void)hipFree(a->dev);
+    if (a->pos) (void)hipFree(a->pos);
+    a->E3.release();
+    a->cand.release();
+    a->U.release();
+    a->slot.release();
+    a->S_part.release();
+    a->ksel.release();
+  }
+  delete a;
 }
 
 }  // extern "C"

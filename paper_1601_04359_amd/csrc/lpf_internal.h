@@ -25,6 +25,77 @@ struct FullShape {
   int nbins;  // wave-level vector bins per tile
 };
 
+// Geometry of one extended image used by the delta kernel (see k_delta.hip): width, height,
+// dwords per row, dword offset in the concatenated buffer, and the 64-bit pattern of columns
+// 0, W, 2W, ... (1 when W >= 64).
+struct ImgGeo {
+  int W, H, we, off;
+  uint64_t pat;
+};
+struct DeltaGeo {
+  ImgGeo g[3];  // image, transposed image, anti-transposed image
+  int total;    // dwords of all three
+  int hy;       // halo rows below each image
+};
+// A vector of the delta plan: minor extent m of its flat form, canonical index, image frame,
+// offset of its m+1 runs (alpha | beta << 16, normalised columns) in the run table.
+struct DeltaVec {
+  int32_t m, idx, img, run_off;
+};
+struct DeltaLaunch {
+  const uint32_t *E;
+  DeltaGeo geo;
+  const uint64_t *bits;
+  int W, H;
+  const int2 *cand;
+  int K;
+  const DeltaVec *vecs;
+  const int32_t *chunk_off;
+  const uint32_t *runs;
+  unsigned phase_mask;
+  int nv;
+  int32_t *delta_out;        // mode 0
+  const uint32_t *counts;    // mode 1
+  const uint32_t *target;    // mode 1
+  int64_t N, Nt;             // mode 1
+  int64_t *S_part;           // mode 1: [nchunks][K]
+  uint32_t *counts_rw;       // mode 2
+  const int32_t *k_sel;      // mode 2
+  int nchunks;
+  bool use_lds;
+};
+
+hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
+                       hipStream_t stream);
+
+// Device-side annealing state (k_anneal.hip).
+struct AnnealDev {
+  uint64_t step;
+  int32_t n1, n0;
+  int32_t *pos1, *pos0;  // phase-1 / phase-0 pixel lists (n1 and n0 entries)
+};
+// Same layout as lpf_step_result in include/lpf.h.
+struct StepResult {
+  int32_t k, a, b, pad;
+  double de, e;
+  uint64_t step;
+};
+hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
+                          int K, int proposal, int2 *cand, double *U, int2 *slot,
+                          hipStream_t stream);
+hipError_t launch_select(AnnealDev *st, const int64_t *S_part, int nchunks, int K,
+                         const int2 *cand, const double *U, double T, int64_t N, int64_t Nt,
+                         double *e, int32_t *k_sel, StepResult *out, hipStream_t stream);
+hipError_t launch_apply_swap(AnnealDev *st, uint64_t *bits, int W, const int32_t *k_sel,
+                             const int2 *cand, const int2 *slot, hipStream_t stream);
+hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
+                             hipStream_t stream);
+hipError_t launch_set_counts(AnnealDev *st, int n1, int n0, uint64_t step, hipStream_t stream);
+hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,
+                      int64_t Nt, double *e, hipStream_t stream);
+hipError_t launch_delta(int mode, const DeltaLaunch &L, hipStream_t stream);
+hipError_t prepare_delta_kernels(int max_lds_bytes);
+
 // Kernel launchers (defined in k_full.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,

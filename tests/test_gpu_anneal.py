@@ -1,0 +1,132 @@
+"""GPU annealing chain (anneal_step) against the CPU oracle's chain."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_04359_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _problem(cell_side, tgt_side, cx, mask, seed, phi=0.4, r=3.0):
+    tgt = wl.boolean_disks(tgt_side, tgt_side, r, phi, seed)
+    target = oracle.lpf(tgt, cx, cx, mask)
+    cell = wl.random_cell(cell_side, cell_side, int(round(phi * cell_side * cell_side)), seed + 1)
+    return tgt, target, cell
+
+
+def _gpu_chain(ctx, cell, cx, mask, target, Nt, seed, step0=0, pos=None, n1=0):
+    import torch
+    from paper_1601_04359_amd import Anneal
+    H, W = cell.shape
+    bits = ctx.pack(torch.from_numpy(cell).cuda())
+    t = torch.from_numpy(target.astype(np.int32)).cuda()
+    return Anneal(ctx, bits, W, H, cx, cx, mask, t, Nt, seed, step0, pos, n1)
+
+
+def _unpack(bits, W, H):
+    b = bits.cpu().numpy().view(np.uint64).reshape(H, -1)
+    out = np.zeros((H, W), np.uint8)
+    for x in range(W):
+        out[:, x] = (b[:, x // 64] >> np.uint64(x % 64)) & np.uint64(1)
+    return out
+
+
+@pytest.mark.parametrize("proposal,mask", [(0, 3), (1, 3), (0, 2)])
+def test_chain_matches_oracle(ctx, proposal, mask):
+    import torch
+    from paper_1601_04359_amd import step_records
+    print(f"[gpu] anneal chain proposal={proposal} mask={mask}", flush=True)
+    tgt, target, cell = _problem(16, 48, 5, mask, 21)
+    seed, K, nsteps = 99, 64, 60
+    Ts = 3e-4 * 0.93 ** np.arange(nsteps)
+    ch = _gpu_chain(ctx, cell, 5, mask, target, tgt.size, seed)
+    recs = step_records(ch.run(K, Ts, proposal))
+    torch.cuda.synchronize()
+    ref = oracle.AnnealState(cell, 5, 5, mask, target, tgt.size, seed)
+    e0 = ref.e
+    rres = ref.run(nsteps, K, Ts, proposal)
+    got = [(int(r["k"]), int(r["a"]), int(r["b"])) for r in recs]
+    want = [(int(r["k"]), int(r["a"]), int(r["b"])) for r in rres]
+    assert got == want
+    assert np.array_equal(recs["step"], np.arange(nsteps))
+    assert np.array_equal(recs["de"], rres["de"]) and np.array_equal(recs["e"], rres["e"])
+    assert sum(k >= 0 for k, _, _ in got) > 5
+    assert np.array_equal(_unpack(ch.bits, 16, 16), ref.img)
+    assert np.array_equal(ch.counts.cpu().numpy().astype(np.uint32), ref.counts)
+    assert float(ch.e.cpu()[0]) == ref.e
+    assert ref.e < e0
+    ch.close()
+
+
+def test_resume_from_export(ctx):
+    import torch
+    from paper_1601_04359_amd import step_records
+    tgt, target, cell = _problem(16, 48, 4, 3, 31)
+    seed, K = 5, 32
+    Ts = np.full(40, 2e-4)
+    one = _gpu_chain(ctx, cell, 4, 3, target, tgt.size, seed)
+    r_all = step_records(one.run(K, Ts))
+    first = _gpu_chain(ctx, cell, 4, 3, target, tgt.size, seed)
+    r_a = step_records(first.run(K, Ts[:20]))
+    pos, n1, nxt = first.export()
+    assert nxt == 20
+    second = _gpu_chain(ctx, _unpack(first.bits, 16, 16), 4, 3, target, tgt.size, seed,
+                        step0=nxt, pos=pos, n1=n1)
+    second.e.copy_(first.e)
+    r_b = step_records(second.run(K, Ts[20:]))
+    torch.cuda.synchronize()
+    both = np.concatenate([r_a, r_b])
+    assert np.array_equal(both[["k", "a", "b"]], r_all[["k", "a", "b"]])
+    assert np.array_equal(second.bits.cpu(), one.bits.cpu())
+    assert np.array_equal(second.counts.cpu(), one.counts.cpu())
+    for c in (one, first, second):
+        c.close()
+
+
+def test_reconstruction_cell_128_c32(ctx):
+    # the reconstruction workload's shapes: 128 x 128 cell, phase-1 LPF with cutoff 32 of a
+    # 1024 x 1024 disk image (phi 0.35, r 6), 4096 candidates per step.  Drift guard: the
+    # incrementally updated counts equal a fresh lpf_full of the cell; the running energy equals
+    # eq. (LSE) recomputed by the oracle; the first step agrees with the oracle's chain.
+    import torch
+    from paper_1601_04359_amd import step_records
+    print("[gpu] anneal 128x128 c=32 K=4096", flush=True)
+    tgt = wl.anneal_target()
+    bt = torch.from_numpy(tgt).cuda()
+    target = ctx.full(ctx.pack(bt), 1024, 1024, 32, 32, 2)
+    cell = wl.random_cell(128, 128, int(round(0.35 * 128 * 128)), 1)
+    ch = _gpu_chain(ctx, cell, 32, 2, target.cpu().numpy(), 1024 * 1024, 1)
+    Ts = 1e-3 * (0.01 ** (1 / 20000)) ** np.arange(12)
+    recs = step_records(ch.run(4096, Ts))
+    torch.cuda.synchronize()
+    fresh = ctx.full(ch.bits, 128, 128, 32, 32, 2)
+    assert torch.equal(fresh, ch.counts)
+    img = _unpack(ch.bits, 128, 128)
+    assert int(img.sum()) == int(cell.sum())
+    e = oracle.lse(ch.counts.cpu().numpy(), target.cpu().numpy(), 128 * 128, 1024 * 1024)
+    assert abs(float(ch.e.cpu()[0]) - e) <= 1e-12 * e
+    assert (recs["k"] >= 0).sum() > 0
+    # first step against the oracle (its draws up to the accepted one)
+    ref = oracle.AnnealState(cell, 32, 32, 2, target.cpu().numpy(), 1024 * 1024, 1)
+    k0 = int(recs["k"][0])
+    kk = k0 + 1 if k0 >= 0 else 4096
+    if kk <= 256:
+        r = ref.run(1, kk, Ts[:1])
+        assert (int(r["k"][0]), int(r["a"][0]), int(r["b"][0])) == \
+            (k0, int(recs["a"][0]), int(recs["b"][0]))
+        assert r["de"][0] == recs["de"][0]
+    ch.close()
