@@ -104,6 +104,39 @@ lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int c
                           unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
                           void *stream);
 
+/* One image of a batch: its size, cutoff, the offset of its packed rows in bits_pool (uint64
+ * words) and of its counts in counts_pool (uint32 elements, sized for the batch's layout). */
+typedef struct {
+  int32_t W, H, cx, cy;
+  int64_t bits_off;
+  int64_t counts_off;
+} lpf_image_desc;
+
+/* lpf_full for many images of any sizes in ONE persistent launch: workgroups draw work items
+ * (image, group of vector bins) from a device counter, longest first, until the list is empty.
+ * descs (host): n_images (<= 65535) descriptors; every image follows lpf_full's rules.  The first call for
+ * a set of (buffers, descriptors, phases, layout) builds launch plans and captures the launch
+ * sequence in a hipGraph owned by the context; later calls replay it (the pools' contents may
+ * change between calls, their addresses may not).  Shapes tuned by lpf_autotune_full for an
+ * image size are used.  Errors: LPF_E_INVAL (a descriptor, naming its index), LPF_E_UNSUPPORTED,
+ * LPF_E_NOMEM, LPF_E_DEVICE. */
+lpf_status lpf_batch(lpf_ctx ctx, const uint64_t *bits_pool, const lpf_image_desc *descs,
+                     int n_images, unsigned phase_mask, int out_layout, uint32_t *counts_pool,
+                     void *stream);
+
+/* Autotuner for lpf_full: times the tile shapes R in {2,4,8,16}, waves per group in {4,8} and
+ * staging budgets {64 KiB, 160 KiB} on the given image (several runs each, stream-ordered and
+ * synchronised here) and records the fastest for images of this W, H, cx, cy in the context;
+ * lpf_full and lpf_batch then use it.  *best_ms (host, may be NULL) receives its time.  This
+ * replaces the paper's fixed occupancy rule, eq. (block).  Errors: as lpf_full. */
+lpf_status lpf_autotune_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, void *stream, double *best_ms);
+
+/* The shape recorded by lpf_autotune_full for W, H, cx, cy (host outputs, each may be NULL).
+ * Errors: LPF_E_INVAL when none was recorded. */
+lpf_status lpf_get_tuned_shape(lpf_ctx ctx, int W, int H, int cx, int cy, int *R,
+                               int *waves_per_group, int *lds_bytes);
+
 /* ---- simulated annealing (Sec. 4, Alg. "annealing"; objective eq. (LSE)) ------------------ */
 
 typedef struct lpf_anneal_s *lpf_anneal;

@@ -82,6 +82,32 @@ class Context:
                             out, stream)
         return out
 
+    def batch(self, images, phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF,
+              stream=None):
+        """images: list of (bits tensor, W, H, cx, cy).  Packs them into one pool, runs lpf_batch
+        and returns (counts_pool, offsets, pool, descs); counts of image i are
+        counts_pool[offsets[i] : offsets[i] + size_i] in the layout's order."""
+        descs = (_abi.lpf_image_desc * len(images))()
+        off_b, off_c, offs = 0, 0, []
+        for i, (bits, W, H, cx, cy) in enumerate(images):
+            descs[i].W, descs[i].H, descs[i].cx, descs[i].cy = W, H, cx, cy
+            descs[i].bits_off, descs[i].counts_off = off_b, off_c
+            offs.append(off_c)
+            off_b += bits.numel()
+            off_c += int(torch.Size(counts_shape(cx, cy, phase_mask, layout)).numel())
+        dev = images[0][0].device
+        pool = torch.cat([b.reshape(-1) for (b, *_r) in images]).contiguous()
+        counts = torch.empty(max(off_c, 1), dtype=torch.int32, device=dev)
+        _abi.lpf_batch(self.handle, pool, descs, phase_mask, layout, counts, stream)
+        return counts, offs, pool, descs
+
+    def autotune(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                 phase_mask: int = LPF_BOTH, stream=None) -> float:
+        return _abi.lpf_autotune_full(self.handle, bits, W, H, cx, cy, phase_mask, stream)
+
+    def tuned_shape(self, W: int, H: int, cx: int, cy: int):
+        return _abi.lpf_get_tuned_shape(self.handle, W, H, cx, cy)
+
     def set_full_shape(self, R: int = 0, S: int = 0, waves_per_group: int = 0,
                        lds_bytes: int = 0) -> None:
         _abi.lpf_set_full_shape(self.handle, R, S, waves_per_group, lds_bytes)

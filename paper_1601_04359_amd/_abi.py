@@ -59,7 +59,18 @@ _sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
 _sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
 _sig("lpf_anneal_destroy", None, _P)
 
+_sig("lpf_batch", _i32, _P, _P, _P, _i32, _u32, _i32, _P, _P)
+_sig("lpf_autotune_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P,
+     ctypes.POINTER(ctypes.c_double))
+_sig("lpf_get_tuned_shape", _i32, _P, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32),
+     ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+
 LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL = 0, 1
+
+
+class lpf_image_desc(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("H", ctypes.c_int32), ("cx", ctypes.c_int32),
+                ("cy", ctypes.c_int32), ("bits_off", ctypes.c_int64), ("counts_off", ctypes.c_int64)]
 STEP_RESULT_BYTES = 40  # lpf_step_result: int32 x4, double x2, uint64
 
 
@@ -185,6 +196,29 @@ def lpf_anneal_export(st: int, pos: torch.Tensor | None, stream=None):
 
 def lpf_anneal_destroy(st: int) -> None:
     _lib.lpf_anneal_destroy(st)
+
+
+def lpf_batch(ctx: int, bits_pool: torch.Tensor, descs, phase_mask: int, out_layout: int,
+              counts_pool: torch.Tensor, stream=None) -> None:
+    """descs: a ctypes array of lpf_image_desc (host)."""
+    _check(_lib.lpf_batch(ctx, _dev(bits_pool, torch.int64, "bits_pool"), ctypes.byref(descs),
+                          len(descs), phase_mask, out_layout,
+                          _dev(counts_pool, torch.int32, "counts_pool"), _stream(stream)))
+
+
+def lpf_autotune_full(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                      phase_mask: int, stream=None) -> float:
+    ms = ctypes.c_double()
+    _check(_lib.lpf_autotune_full(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+                                  _stream(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def lpf_get_tuned_shape(ctx: int, W: int, H: int, cx: int, cy: int):
+    R, wpg, lds = _i32(), _i32(), _i32()
+    _check(_lib.lpf_get_tuned_shape(ctx, W, H, cx, cy, ctypes.byref(R), ctypes.byref(wpg),
+                                    ctypes.byref(lds)))
+    return R.value, wpg.value, lds.value
 
 
 def lpf_set_full_shape(ctx: int, R: int = 0, S: int = 0, waves_per_group: int = 0,

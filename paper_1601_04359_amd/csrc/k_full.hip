@@ -112,147 +112,236 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-template <int R>
-__global__ void __launch_bounds__(512)
-k_lpf_full(const uint32_t *__restrict__ E, int W, int H, int we, int S, int tile, int lds_rows,
-           int rst, const VecDesc *__restrict__ vecs, const int32_t *__restrict__ bin_off,
-           int wpg, unsigned phase_mask, uint32_t *__restrict__ out, int nv) {
-  extern __shared__ uint32_t lds[];
-  const int t_id = blockIdx.y;
-  const int Y0 = t_id * tile;
-  const int rows_here = min(tile, H - Y0);
-
-  // Stage rows Y0 .. Y0 + lds_rows - 1 (mod H) of E.
-  for (int i = threadIdx.x; i < lds_rows * we; i += blockDim.x) {
-    const int r = i / we;
-    const int e = i - r * we;
-    const int y = (Y0 + r) % H;
-    lds[r * rst + e] = E[(size_t)y * we + e];
+// Count of vector `idx` = (dx, dy) for phase slot p, in the image's output layout (the GRID
+// layout also fills -v, eq. (symmetry)).
+__device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int dx, int dy,
+                                          uint32_t c) {
+  if (I.layout == 0) {
+    I.out[(size_t)p * I.nv + idx] = c;
+  } else {
+    const int gw = 2 * I.cx + 1;
+    const size_t g = (size_t)gw * (2 * I.cy + 1);
+    I.out[(size_t)p * g + (size_t)(dy + I.cy) * gw + (dx + I.cx)] = c;
+    I.out[(size_t)p * g + (size_t)(I.cy - dy) * gw + (I.cx - dx)] = c;
   }
-  __syncthreads();
+}
 
+// One work item: waves w = 0..wpg-1 of the workgroup take bins bin0 + w of image I and count
+// their vectors over every row tile of the image.  lds: staged rows; cnt: per-wave count slots
+// (used only when the image has several row tiles).  Each count is written once, by lane 0 of
+// the wave owning the vector.
+template <int R>
+__device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg,
+                                             unsigned phase_mask, uint32_t *__restrict__ lds,
+                                             uint32_t *__restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rpw = 64 / S;
+  const int rpw = 64 / I.S;
   const int strip = lane / rpw;
   const int r_in = lane - strip * rpw;
-  const int swd = (W + 31) >> 5;
-  const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
-  const int nbands = (rows_here + rpw - 1) / rpw;
-  const int nph = (phase_mask & 1) + ((phase_mask >> 1) & 1);
-
-  const int bin = blockIdx.x * wpg + wave;
-  const int vb = bin_off[bin], ve = bin_off[bin + 1];
-  for (int j = vb; j < ve; ++j) {
-    const VecDesc v = vecs[j];
-    const int dx = v.dx, dy = v.dy;
-    const int adx = dx < 0 ? -dx : dx;
-    const int n = adx > dy ? adx : dy;
-    const bool xm = adx >= dy;
-    const int m = xm ? dy : adx;
-    uint32_t c0 = 0, c1 = 0;
-    for (int band = 0; band < nbands; ++band) {
-      const int row = band * rpw + r_in;
-      const uint32_t *base = lds + row * rst + strip * R;
-      uint32_t A[R], O[R];
+  const int swd = (I.W + 31) >> 5;
+  const uint32_t lastmask = (I.W & 31) ? ((1u << (I.W & 31)) - 1u) : 0xffffffffu;
+  const int bin = bin0 + wave;
+  const int vb = bin < I.nbins ? I.bin_off[bin] : 0;
+  const int ve = bin < I.nbins ? I.bin_off[bin + 1] : 0;
+  const bool tiled = I.ntiles > 1;
+  for (int t_id = 0; t_id < I.ntiles; ++t_id) {
+    const int Y0 = t_id * I.tile;
+    const int rows_here = min(I.tile, I.H - Y0);
+    if (t_id) __syncthreads();  // every wave is done with the previous tile
+    // Stage rows Y0 .. Y0 + lds_rows - 1 (mod H) of E.
+    for (int i = threadIdx.x; i < I.lds_rows * I.we; i += blockDim.x) {
+      const int r = i / I.we;
+      const int e = i - r * I.we;
+      const int y = (Y0 + r) % I.H;
+      lds[r * I.rst + e] = I.E[(size_t)y * I.we + e];
+    }
+    __syncthreads();
+    const int nbands = (rows_here + rpw - 1) / rpw;
+    for (int j = vb; j < ve; ++j) {
+      const VecDesc v = I.vecs[j];
+      const int dx = v.dx, dy = v.dy;
+      const int adx = dx < 0 ? -dx : dx;
+      const int n = adx > dy ? adx : dy;
+      const bool xm = adx >= dy;
+      const int m = xm ? dy : adx;
+      uint32_t c0 = 0, c1 = 0;
+      for (int band = 0; band < nbands; ++band) {
+        const int row = band * rpw + r_in;
+        const uint32_t *base = lds + row * I.rst + strip * R;
+        uint32_t A[R], O[R];
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        A[i] = 0xffffffffu;
-        O[i] = 0u;
-      }
-      if (xm) {
-        if (dx < 0) path_product<R, true, true>(base, rst, adx, n, m, A, O);
-        else path_product<R, true, false>(base, rst, adx, n, m, A, O);
-      } else {
-        if (dx < 0) path_product<R, false, true>(base, rst, adx, n, m, A, O);
-        else path_product<R, false, false>(base, rst, adx, n, m, A, O);
-      }
-      const bool row_ok = row < rows_here;
+        for (int i = 0; i < R; ++i) {
+          A[i] = 0xffffffffu;
+          O[i] = 0u;
+        }
+        if (xm) {
+          if (dx < 0) path_product<R, true, true>(base, I.rst, adx, n, m, A, O);
+          else path_product<R, true, false>(base, I.rst, adx, n, m, A, O);
+        } else {
+          if (dx < 0) path_product<R, false, true>(base, I.rst, adx, n, m, A, O);
+          else path_product<R, false, false>(base, I.rst, adx, n, m, A, O);
+        }
+        const bool row_ok = row < rows_here;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int w = strip * R + i;
-        uint32_t mk = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
-        mk = row_ok ? mk : 0u;
-        c1 += __popc(A[i] & mk);
-        c0 += __popc(~O[i] & mk);
+        for (int i = 0; i < R; ++i) {
+          const int w = strip * R + i;
+          uint32_t mk = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
+          mk = row_ok ? mk : 0u;
+          c1 += __popc(A[i] & mk);
+          c0 += __popc(~O[i] & mk);
+        }
+      }
+      c0 = wave_sum(c0);
+      c1 = wave_sum(c1);
+      if (lane == 0) {
+        if (!tiled) {
+          int p = 0;
+          if (phase_mask & 1) put_count(I, p++, v.idx, dx, dy, c0);
+          if (phase_mask & 2) put_count(I, p, v.idx, dx, dy, c1);
+        } else {
+          uint32_t *slot = cnt + 2 * (wave * kMaxBin + (j - vb));
+          slot[0] = t_id ? slot[0] + c0 : c0;
+          slot[1] = t_id ? slot[1] + c1 : c1;
+        }
       }
     }
-    c0 = wave_sum(c0);
-    c1 = wave_sum(c1);
-    if (lane == 0) {
+  }
+  if (tiled && lane == 0) {
+    for (int j = vb; j < ve; ++j) {
+      const VecDesc v = I.vecs[j];
+      const uint32_t *slot = cnt + 2 * (wave * kMaxBin + (j - vb));
       int p = 0;
-      uint32_t *o = out + (size_t)t_id * nph * nv;
-      if (phase_mask & 1) o[(size_t)(p++) * nv + v.idx] = c0;
-      if (phase_mask & 2) o[(size_t)p * nv + v.idx] = c1;
+      if (phase_mask & 1) put_count(I, p++, v.idx, v.dx, v.dy, slot[0]);
+      if (phase_mask & 2) put_count(I, p, v.idx, v.dx, v.dy, slot[1]);
     }
   }
 }
 
+// One image, one workgroup per work item (item = blockIdx.x).
 template <int R>
-static hipError_t launch_full_r(const FullShape &sh, const uint32_t *ext, int W, int H,
-                                const VecDesc *vecs, const int32_t *bin_off, unsigned phase_mask,
-                                uint32_t *out, int nv, hipStream_t stream) {
-  const int nwg = (sh.nbins + sh.wpg - 1) / sh.wpg;
-  dim3 grid(nwg, sh.ntiles);
-  size_t lds = (size_t)sh.lds_rows * sh.rst * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_lpf_full<R>, grid, dim3(64 * sh.wpg), lds, stream, ext, W, H, sh.we, sh.S,
-                     sh.tile, sh.lds_rows, sh.rst, vecs, bin_off, sh.wpg, phase_mask, out, nv);
+__global__ void __launch_bounds__(512)
+k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
+  extern __shared__ uint32_t lds[];
+  process_item<R>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
+}
+
+// Many images, persistent workgroups drawing work items from a device counter in descending
+// cost order until the list is exhausted (every wave reaches the exit test).
+__global__ void __launch_bounds__(512)
+k_lpf_batch(const FullImg *__restrict__ imgs, const int2 *__restrict__ items, int n_items,
+            int *__restrict__ counter, int wpg, unsigned phase_mask, int cnt_off) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const FullImg I = imgs[w.x];
+    switch (I.R) {
+      case 1: process_item<1>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 2: process_item<2>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 4: process_item<4>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 8: process_item<8>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      default: process_item<16>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+    }
+    __syncthreads();  // the item's last tile is no longer read before the next staging
+  }
+}
+
+__global__ void k_reset_counter(int *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+size_t full_lds_bytes(const FullShape &sh, int wpg) {
+  size_t b = (size_t)sh.lds_rows * sh.rst * sizeof(uint32_t);
+  if (sh.ntiles > 1) b += (size_t)wpg * kMaxBin * 2 * sizeof(uint32_t);
+  return b;
+}
+
+template <int R>
+static hipError_t launch_full_r(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                                hipStream_t stream) {
+  const int nwg = sh.nbins / sh.wpg;
+  const size_t lds = full_lds_bytes(sh, sh.wpg);
+  const int cnt_off = sh.lds_rows * sh.rst;
+  hipLaunchKernelGGL(k_lpf_full<R>, dim3(nwg), dim3(64 * sh.wpg), lds, stream, I, sh.wpg,
+                     phase_mask, cnt_off);
   return hipGetLastError();
 }
 
-hipError_t launch_full(const FullShape &sh, const uint32_t *ext, int W, int H, int /*cy*/,
-                       const VecDesc *vecs, const int32_t *bin_off, unsigned phase_mask,
-                       uint32_t *out, int nv, hipStream_t stream) {
+hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                       hipStream_t stream) {
   switch (sh.R) {
-    case 1: return launch_full_r<1>(sh, ext, W, H, vecs, bin_off, phase_mask, out, nv, stream);
-    case 2: return launch_full_r<2>(sh, ext, W, H, vecs, bin_off, phase_mask, out, nv, stream);
-    case 4: return launch_full_r<4>(sh, ext, W, H, vecs, bin_off, phase_mask, out, nv, stream);
-    case 8: return launch_full_r<8>(sh, ext, W, H, vecs, bin_off, phase_mask, out, nv, stream);
-    case 16: return launch_full_r<16>(sh, ext, W, H, vecs, bin_off, phase_mask, out, nv, stream);
+    case 1: return launch_full_r<1>(I, sh, phase_mask, stream);
+    case 2: return launch_full_r<2>(I, sh, phase_mask, stream);
+    case 4: return launch_full_r<4>(I, sh, phase_mask, stream);
+    case 8: return launch_full_r<8>(I, sh, phase_mask, stream);
+    case 16: return launch_full_r<16>(I, sh, phase_mask, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
+                        int wpg, unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lpf_batch, dim3(n_wg), dim3(64 * wpg), lds_bytes, stream, imgs, items,
+                     n_items, counter, wpg, phase_mask, cnt_off);
+  return hipGetLastError();
+}
+
+// E for many images in one launch: image b's rows at ext_off[b], we[b] dwords per row.
+__global__ void k_ext_batch(const FullImg *__restrict__ imgs, const uint64_t *__restrict__ pool,
+                            const int64_t *__restrict__ bits_off, uint32_t *__restrict__ ext,
+                            const int64_t *__restrict__ ext_off) {
+  const int b = blockIdx.z;
+  const FullImg I = imgs[b];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (e >= I.we || y >= I.H) return;
+  const uint32_t *row = reinterpret_cast<const uint32_t *>(pool + bits_off[b]) +
+                        (size_t)y * 2 * ((I.W + 63) / 64);
+  const int W = I.W;
+  const int s = (int)(((int64_t)32 * e) % W);
+  uint32_t v;
+  if (s + 32 <= W) {
+    const int q = s >> 5, sh = s & 31;
+    v = __builtin_amdgcn_alignbit(sh ? row[q + 1] : 0u, row[q], sh);
+  } else {
+    v = 0;
+    int x = s;
+    for (int t = 0; t < 32; ++t) {
+      v |= ((row[x >> 5] >> (x & 31)) & 1u) << t;
+      x = (x + 1 == W) ? 0 : x + 1;
+    }
+  }
+  ext[ext_off[b] + (size_t)y * I.we + e] = v;
+}
+
+hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int max_h,
+                            const uint64_t *pool, const int64_t *bits_off, uint32_t *ext,
+                            const int64_t *ext_off, hipStream_t stream) {
+  dim3 grid((max_we + 63) / 64, max_h, n_images);
+  hipLaunchKernelGGL(k_ext_batch, grid, dim3(64), 0, stream, imgs, pool, bits_off, ext, ext_off);
+  return hipGetLastError();
 }
 
 hipError_t prepare_full_kernels(int max_lds_bytes) {
   hipError_t e = hipSuccess;
   const void *fns[] = {(const void *)k_lpf_full<1>, (const void *)k_lpf_full<2>,
                        (const void *)k_lpf_full<4>, (const void *)k_lpf_full<8>,
-                       (const void *)k_lpf_full<16>};
+                       (const void *)k_lpf_full<16>, (const void *)k_lpf_batch};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
     if (r != hipSuccess) e = r;
   }
   return e;
-}
-
-// ---------------------------------------------------------------------------- tile sum / layout
-__global__ void k_finish(const uint32_t *__restrict__ part, int ntiles, int nph, int nv,
-                         const int16_t *__restrict__ dxdy, int cx, int cy, int layout,
-                         uint32_t *__restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nph * nv) return;
-  const int p = (int)(i / nv);
-  const int v = (int)(i - (int64_t)p * nv);
-  uint32_t s = 0;
-  for (int t = 0; t < ntiles; ++t) s += part[((size_t)t * nph + p) * nv + v];
-  if (layout == 0) {
-    out[(size_t)p * nv + v] = s;
-  } else {
-    const int gw = 2 * cx + 1;
-    const size_t g = (size_t)gw * (2 * cy + 1);
-    const int dx = dxdy[2 * v], dy = dxdy[2 * v + 1];
-    out[(size_t)p * g + (size_t)(dy + cy) * gw + (dx + cx)] = s;
-    out[(size_t)p * g + (size_t)(cy - dy) * gw + (cx - dx)] = s;
-  }
-}
-
-hipError_t launch_finish(const uint32_t *part, int ntiles, int nph, int nv, const int16_t *dxdy,
-                         int cx, int cy, int layout, uint32_t *out, hipStream_t stream) {
-  const int64_t n = (int64_t)nph * nv;
-  dim3 grid((unsigned)((n + 255) / 256));
-  hipLaunchKernelGGL(k_finish, grid, dim3(256), 0, stream, part, ntiles, nph, nv, dxdy, cx, cy,
-                     layout, out);
-  return hipGetLastError();
 }
 
 }  // namespace lpf

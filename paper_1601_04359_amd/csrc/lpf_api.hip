@@ -71,8 +71,13 @@ struct FullPlan {
   FullShape sh{};
   VecDesc *vecs = nullptr;   // device, bin order
   int32_t *bin_off = nullptr;  // device, nbins + 1
-  int16_t *dxdy = nullptr;   // device, canonical order
   int64_t nv = 0;
+  std::vector<int64_t> bin_cost;  // host: cost of each bin (pixels + overhead per vector)
+};
+
+struct TunedShape {
+  int R = 0, wpg = 0, lds = 0;
+  double ms = 0.0;
 };
 
 struct DeltaPlan {
@@ -133,7 +138,9 @@ struct lpf_ctx_s {
   int dev = 0;
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
-  DevBuf ext, part, ext3;
+  std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
+  std::map<std::string, struct BatchGraph *> batch_graphs;
+  DevBuf ext, ext3;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -156,11 +163,44 @@ struct lpf_anneal_s {
   int K_cap = 0;
 };
 
+// A captured lpf_batch launch (extended images, counter reset, persistent kernel).
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  FullImg *imgs = nullptr;
+  int2 *items = nullptr;
+  int64_t *bits_off = nullptr, *ext_off = nullptr;
+  int *counter = nullptr;
+  uint32_t *ext = nullptr;
+  int n_items = 0, n_wg = 0;
+};
+
 namespace {
+
+void free_batch_graph(BatchGraph *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  (void)hipFree(b->imgs);
+  (void)hipFree(b->items);
+  (void)hipFree(b->bits_off);
+  (void)hipFree(b->ext_off);
+  (void)hipFree(b->counter);
+  (void)hipFree(b->ext);
+  delete b;
+}
+
+void release_batch_graphs(lpf_ctx c);
 
 bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::string &why) {
   const int swd = (W + 31) / 32;
-  int R = c->force_R ? c->force_R : std::min(8, next_pow2(swd));
+  const TunedShape *tuned = nullptr;
+  auto tk = c->tuned.find(std::make_tuple(W, H, cx, cy));
+  if (tk != c->tuned.end()) tuned = &tk->second;
+  int fR = c->force_R ? c->force_R : (tuned ? tuned->R : 0);
+  int fW = c->force_wpg ? c->force_wpg : (tuned ? tuned->wpg : 0);
+  int fL = c->force_lds ? c->force_lds : (tuned ? tuned->lds : 0);
+  int R = fR ? fR : std::min(8, next_pow2(swd));
   int S = c->force_S ? c->force_S : next_pow2((swd + R - 1) / R);
   if (S > 64) {
     why = "image too wide for the lane layout (W > 64*R*32)";
@@ -173,7 +213,7 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   const int rpw = 64 / S;
   sh.R = R;
   sh.S = S;
-  sh.wpg = c->force_wpg ? c->force_wpg : 8;
+  sh.wpg = fW ? fW : 8;
   sh.we = S * R + (cx >> 5) + 1;
   int best = sh.we, best_score = 1 << 30;
   for (int r = sh.we; r < sh.we + 64; ++r) {
@@ -184,14 +224,16 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
     }
   }
   sh.rst = best;
-  int budget = c->force_lds ? c->force_lds : 64 * 1024;
+  int budget = fL ? fL : 64 * 1024;
+  const int slots = sh.wpg * kMaxBin * 2 * 4;  // count slots when the image needs row tiles
   for (;;) {
-    const int rows_max = budget / (sh.rst * 4);
-    int tile = rows_max - cy - rpw;
-    if (tile >= H) {
+    int tile;
+    const int rows_all = budget / (sh.rst * 4);
+    if (rows_all - cy - rpw >= H) {
       tile = H;
     } else {
-      tile = (tile / rpw) * rpw;
+      const int rows_max = (budget - slots) / (sh.rst * 4);
+      tile = ((rows_max - cy - rpw) / rpw) * rpw;
     }
     if (tile >= 1) {
       sh.tile = tile;
@@ -223,9 +265,10 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
   const int64_t nv = (int64_t)can.size() / 2;
   if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_full: too many vectors");
 
-  // Wave-level bins, longest-processing-time-first on cost = pixels + per-band overhead.
-  const int64_t target = std::max<int64_t>(sh.wpg, 8192 / sh.ntiles);
-  int64_t nb = std::min<int64_t>(nv, target);
+  // Wave-level bins, longest-processing-time-first on cost = pixels + per-band overhead, at most
+  // kMaxBin vectors per bin.
+  int64_t nb = std::min<int64_t>(nv, 8192);
+  nb = std::max<int64_t>(nb, (2 * nv + kMaxBin - 1) / kMaxBin);
   nb = (nb + sh.wpg - 1) / sh.wpg * sh.wpg;
   sh.nbins = (int)nb;
   std::vector<int> order(nv);
@@ -244,7 +287,7 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
     Item t = heap.top();
     heap.pop();
     bins[t.second].push_back(i);
-    heap.push({t.first + cost[i], t.second});
+    if ((int)bins[t.second].size() < kMaxBin) heap.push({t.first + cost[i], t.second});
   }
   std::vector<VecDesc> vecs;
   vecs.reserve(nv);
@@ -263,18 +306,49 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
     return hip_fail(e, "lpf_full: plan allocation");
   if ((e = hipMalloc(&p.bin_off, sizeof(int32_t) * off.size())) != hipSuccess)
     return hip_fail(e, "lpf_full: plan allocation");
-  if ((e = hipMalloc(&p.dxdy, sizeof(int16_t) * std::max<size_t>(can.size(), 2))) != hipSuccess)
-    return hip_fail(e, "lpf_full: plan allocation");
   if ((e = hipMemcpy(p.vecs, vecs.data(), sizeof(VecDesc) * nv, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p.bin_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p.dxdy, can.data(), sizeof(int16_t) * can.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      (e = hipMemcpy(p.bin_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "lpf_full: plan upload");
+  for (int b = 0; b < sh.nbins; ++b) {
+    int64_t c = 0;
+    for (int i : bins[b]) c += cost[i];
+    p.bin_cost.push_back(c);
+  }
   auto res = c->full_plans.emplace(key, p);
   plan = &res.first->second;
   return LPF_OK;
 }
 
+void release_batch_graphs(lpf_ctx c) {
+  for (auto &kv : c->batch_graphs) free_batch_graph(kv.second);
+  c->batch_graphs.clear();
+}
+
 int nph_of(unsigned mask) { return (int)(mask & 1u) + (int)((mask >> 1) & 1u); }
+
+FullImg make_img(const FullPlan &p, const uint32_t *ext, uint32_t *out, int W, int H, int cx,
+                 int cy, int layout) {
+  FullImg I{};
+  I.E = ext;
+  I.out = out;
+  I.vecs = p.vecs;
+  I.bin_off = p.bin_off;
+  I.W = W;
+  I.H = H;
+  I.cx = cx;
+  I.cy = cy;
+  I.R = p.sh.R;
+  I.S = p.sh.S;
+  I.we = p.sh.we;
+  I.rst = p.sh.rst;
+  I.tile = p.sh.tile;
+  I.ntiles = p.sh.ntiles;
+  I.lds_rows = p.sh.lds_rows;
+  I.nv = (int)p.nv;
+  I.layout = layout;
+  I.nbins = p.sh.nbins;
+  return I;
+}
 
 constexpr int kDeltaLdsMax = 64 * 1024;
 
@@ -448,15 +522,14 @@ void lpf_ctx_destroy(lpf_ctx c) {
     for (auto &kv : c->full_plans) {
       (void)hipFree(kv.second.vecs);
       (void)hipFree(kv.second.bin_off);
-      (void)hipFree(kv.second.dxdy);
     }
+    release_batch_graphs(c);
     for (auto &kv : c->delta_plans) {
       (void)hipFree(kv.second.vecs);
       (void)hipFree(kv.second.chunk_off);
       (void)hipFree(kv.second.runs);
     }
     c->ext.release();
-    c->part.release();
     c->ext3.release();
   }
   delete c;
@@ -489,27 +562,14 @@ lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int c
   lpf_status st = get_full_plan(c, W, H, cx, cy, plan);
   if (st != LPF_OK) return st;
   const FullShape &sh = plan->sh;
-  const int nph = nph_of(phase_mask);
-  const int nv = (int)plan->nv;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if ((e = c->ext.ensure((size_t)H * sh.we * sizeof(uint32_t))) != hipSuccess)
     return hip_fail(e, "lpf_full: scratch");
-  const bool direct = sh.ntiles == 1 && out_layout == LPF_OUT_HALF;
-  uint32_t *dst = counts;
-  if (!direct) {
-    if ((e = c->part.ensure((size_t)sh.ntiles * nph * nv * sizeof(uint32_t))) != hipSuccess)
-      return hip_fail(e, "lpf_full: scratch");
-    dst = (uint32_t *)c->part.p;
-  }
   uint32_t *ext = (uint32_t *)c->ext.p;
   if ((e = launch_ext(bits, W, H, sh.we, ext, s)) != hipSuccess) return hip_fail(e, "lpf_full: ext");
-  if ((e = launch_full(sh, ext, W, H, cy, plan->vecs, plan->bin_off, phase_mask, dst, nv, s)) != hipSuccess)
-    return hip_fail(e, "lpf_full: kernel");
-  if (!direct) {
-    if ((e = launch_finish(dst, sh.ntiles, nph, nv, plan->dxdy, cx, cy, out_layout, counts, s)) != hipSuccess)
-      return hip_fail(e, "lpf_full: finish");
-  }
+  const FullImg I = make_img(*plan, ext, counts, W, H, cx, cy, out_layout);
+  if ((e = launch_full(I, sh, phase_mask, s)) != hipSuccess) return hip_fail(e, "lpf_full: kernel");
   return LPF_OK;
 }
 
@@ -767,6 +827,223 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->ksel.release();
   }
   delete a;
+}
+
+lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc *descs,
+                     int n_images, unsigned phase_mask, int out_layout, uint32_t *counts_pool,
+                     void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_batch: ctx is NULL");
+  if (n_images < 0 || n_images > 65535) return fail(LPF_E_INVAL, "lpf_batch: n_images outside [0, 65535]");
+  if (n_images == 0) return LPF_OK;
+  if (!bits_pool || !descs || !counts_pool) return fail(LPF_E_INVAL, "lpf_batch: NULL buffer");
+  if (phase_mask < 1 || phase_mask > 3) return fail(LPF_E_INVAL, "lpf_batch: phase_mask");
+  if (out_layout != LPF_OUT_HALF && out_layout != LPF_OUT_GRID)
+    return fail(LPF_E_INVAL, "lpf_batch: out_layout");
+  for (int i = 0; i < n_images; ++i) {
+    const lpf_image_desc &d = descs[i];
+    lpf_status st = check_image_args("lpf_batch", d.W, d.H, d.cx, d.cy, phase_mask);
+    if (st != LPF_OK) return fail(st, std::string(lpf_last_error()) + " (image " + std::to_string(i) + ")");
+    if (d.bits_off < 0 || d.counts_off < 0)
+      return fail(LPF_E_INVAL, "lpf_batch: negative offset (image " + std::to_string(i) + ")");
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_batch: cannot select the context's device");
+  hipStream_t s = (hipStream_t)stream;
+  // cache key: buffers, layout and every descriptor
+  std::string key;
+  {
+    char buf[96];
+    snprintf(buf, sizeof buf, "%p|%p|%u|%d|%d|%d%d%d%d|", (const void *)bits_pool,
+             (void *)counts_pool, phase_mask, out_layout, n_images, c->force_R, c->force_S,
+             c->force_wpg, c->force_lds);
+    key = buf;
+    key.append(reinterpret_cast<const char *>(descs), sizeof(lpf_image_desc) * (size_t)n_images);
+  }
+  auto it = c->batch_graphs.find(key);
+  if (it == c->batch_graphs.end()) {
+    const int wpg = 8;
+    std::vector<FullImg> imgs(n_images);
+    std::vector<int64_t> bits_off(n_images), ext_off(n_images);
+    std::vector<std::pair<int64_t, int2>> items;
+    int64_t ext_total = 0;
+    size_t stage_max = 0;
+    bool any_tiled = false;
+    int max_we = 1, max_h = 1;
+    for (int i = 0; i < n_images; ++i) {
+      const lpf_image_desc &d = descs[i];
+      FullPlan *plan = nullptr;
+      const int saved_wpg = c->force_wpg;
+      c->force_wpg = wpg;
+      lpf_status st = get_full_plan(c, d.W, d.H, d.cx, d.cy, plan);
+      c->force_wpg = saved_wpg;
+      if (st != LPF_OK) return st;
+      const FullShape &sh = plan->sh;
+      ext_off[i] = ext_total;
+      bits_off[i] = d.bits_off;
+      ext_total += (int64_t)d.H * sh.we;
+      imgs[i] = make_img(*plan, nullptr, counts_pool + d.counts_off, d.W, d.H, d.cx, d.cy, out_layout);
+      stage_max = std::max(stage_max, (size_t)sh.lds_rows * sh.rst);
+      any_tiled = any_tiled || sh.ntiles > 1;
+      max_we = std::max(max_we, sh.we);
+      max_h = std::max(max_h, d.H);
+      const int64_t rows_work = (int64_t)d.H * sh.S;
+      for (int b0 = 0; b0 < sh.nbins; b0 += wpg) {
+        int64_t cst = 0;
+        for (int b = b0; b < std::min(b0 + wpg, sh.nbins); ++b) cst = std::max(cst, plan->bin_cost[b]);
+        items.push_back({cst * rows_work * sh.R + (int64_t)sh.lds_rows * sh.we, make_int2(i, b0)});
+      }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<int64_t, int2> &a, const std::pair<int64_t, int2> &b) {
+                       return a.first > b.first;
+                     });
+    std::vector<int2> item_list(items.size());
+    for (size_t k = 0; k < items.size(); ++k) item_list[k] = items[k].second;
+    const size_t lds_bytes = stage_max * 4 + (any_tiled ? (size_t)wpg * kMaxBin * 2 * 4 : 0);
+    if (lds_bytes > (size_t)kMaxLds) return fail(LPF_E_UNSUPPORTED, "lpf_batch: staging exceeds LDS");
+    BatchGraph *b = new (std::nothrow) BatchGraph();
+    if (!b) return fail(LPF_E_NOMEM, "lpf_batch: host memory");
+    hipError_t e;
+    if ((e = hipMalloc(&b->ext, sizeof(uint32_t) * (size_t)std::max<int64_t>(ext_total, 1))) != hipSuccess ||
+        (e = hipMalloc(&b->imgs, sizeof(FullImg) * n_images)) != hipSuccess ||
+        (e = hipMalloc(&b->items, sizeof(int2) * item_list.size())) != hipSuccess ||
+        (e = hipMalloc(&b->bits_off, sizeof(int64_t) * n_images)) != hipSuccess ||
+        (e = hipMalloc(&b->ext_off, sizeof(int64_t) * n_images)) != hipSuccess ||
+        (e = hipMalloc(&b->counter, sizeof(int))) != hipSuccess) {
+      free_batch_graph(b);
+      return hip_fail(e, "lpf_batch: allocation");
+    }
+    for (int i = 0; i < n_images; ++i) imgs[i].E = b->ext + ext_off[i];
+    if ((e = hipMemcpy(b->imgs, imgs.data(), sizeof(FullImg) * n_images, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->items, item_list.data(), sizeof(int2) * item_list.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->bits_off, bits_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->ext_off, ext_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess) {
+      free_batch_graph(b);
+      return hip_fail(e, "lpf_batch: upload");
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
+    const int per_cu = std::max<int>(1, std::min<int>(4, (int)(kMaxLds / std::max<size_t>(lds_bytes, 1))));
+    b->n_items = (int)item_list.size();
+    b->n_wg = std::max(1, std::min(b->n_items, cus * per_cu));
+    // capture on a private stream, launch on the caller's
+    hipStream_t cap;
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
+      free_batch_graph(b);
+      return hip_fail(e, "lpf_batch: capture stream");
+    }
+    hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+      hipError_t e1 = launch_ext_batch(b->imgs, n_images, max_we, max_h, bits_pool, b->bits_off,
+                                       b->ext, b->ext_off, cap);
+      hipError_t e2 = launch_batch(b->imgs, b->items, b->n_items, b->counter, wpg, phase_mask,
+                                   lds_bytes, (int)stage_max, b->n_wg, cap);
+      ce = hipStreamEndCapture(cap, &b->graph);
+      if (ce == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) ce = e1 != hipSuccess ? e1 : e2;
+    }
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (ce != hipSuccess) {
+      free_batch_graph(b);
+      return hip_fail(ce, "lpf_batch: graph capture");
+    }
+    it = c->batch_graphs.emplace(key, b).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "lpf_batch: graph launch");
+  return LPF_OK;
+}
+
+lpf_status lpf_autotune_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, void *stream, double *best_ms) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_autotune_full: ctx is NULL");
+  lpf_status st = check_image_args("lpf_autotune_full", W, H, cx, cy, phase_mask);
+  if (st != LPF_OK) return st;
+  if (!bits) return fail(LPF_E_INVAL, "lpf_autotune_full: bits is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nv = lpf_num_vectors(cx, cy);
+  const int nph = nph_of(phase_mask);
+  uint32_t *tmp = nullptr;
+  hipError_t e;
+  {
+    DeviceGuard g(c->dev);
+    if ((e = hipMalloc(&tmp, sizeof(uint32_t) * (size_t)nph * nv)) != hipSuccess)
+      return hip_fail(e, "lpf_autotune_full: allocation");
+  }
+  const int saved[4] = {c->force_R, c->force_S, c->force_wpg, c->force_lds};
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->tuned.erase(std::make_tuple(W, H, cx, cy));
+  }
+  TunedShape best{};
+  best.ms = 1e30;
+  const int swd = (W + 31) / 32;
+  hipEvent_t e0, e1;
+  {
+    DeviceGuard g(c->dev);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+  }
+  for (int R : {2, 4, 8, 16}) {
+    if (R > 2 * next_pow2(swd) && R > 2) continue;
+    for (int wpg : {4, 8}) {
+      for (int lds : {64 * 1024, kMaxLds}) {
+        c->force_R = R;
+        c->force_S = 0;
+        c->force_wpg = wpg;
+        c->force_lds = lds;
+        float ms_best = 1e30f;
+        bool ok = true;
+        for (int rep = 0; rep < 3 && ok; ++rep) {
+          DeviceGuard g(c->dev);
+          (void)hipEventRecord(e0, s);
+          ok = lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, tmp, stream) == LPF_OK;
+          (void)hipEventRecord(e1, s);
+          if (ok && hipEventSynchronize(e1) == hipSuccess) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep) ms_best = std::min(ms_best, ms);  // first run builds the plan
+          }
+        }
+        if (ok && ms_best < best.ms) {
+          best.R = R;
+          best.wpg = wpg;
+          best.lds = lds;
+          best.ms = ms_best;
+        }
+      }
+    }
+  }
+  c->force_R = saved[0];
+  c->force_S = saved[1];
+  c->force_wpg = saved[2];
+  c->force_lds = saved[3];
+  {
+    DeviceGuard g(c->dev);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(tmp);
+  }
+  if (best.ms >= 1e29) return fail(LPF_E_UNSUPPORTED, "lpf_autotune_full: no shape ran");
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->tuned[std::make_tuple(W, H, cx, cy)] = best;
+  }
+  if (best_ms) *best_ms = best.ms;
+  return LPF_OK;
+}
+
+lpf_status lpf_get_tuned_shape(lpf_ctx c, int W, int H, int cx, int cy, int *R, int *wpg,
+                               int *lds_bytes) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_get_tuned_shape: ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->tuned.find(std::make_tuple(W, H, cx, cy));
+  if (it == c->tuned.end()) return fail(LPF_E_INVAL, "lpf_get_tuned_shape: not tuned");
+  if (R) *R = it->second.R;
+  if (wpg) *wpg = it->second.wpg;
+  if (lds_bytes) *lds_bytes = it->second.lds;
+  return LPF_OK;
 }
 
 }  // extern "C"

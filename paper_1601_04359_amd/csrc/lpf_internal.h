@@ -22,7 +22,19 @@ struct VecDesc {
 //   lds_rows rows staged in LDS per workgroup: tile + cy + 64/S
 struct FullShape {
   int R, S, wpg, tile, ntiles, rst, we, lds_rows;
-  int nbins;  // wave-level vector bins per tile
+  int nbins;  // wave-level vector bins (a multiple of wpg), at most kMaxBin vectors each
+};
+
+// Most vectors in one wave-level bin (count slots in LDS when an image has several row tiles).
+constexpr int kMaxBin = 128;
+
+// One image as seen by the full-evaluation kernels.
+struct FullImg {
+  const uint32_t *E;        // extended image, H x we dwords
+  uint32_t *out;            // counts in the output layout
+  const VecDesc *vecs;      // vectors in bin order
+  const int32_t *bin_off;   // nbins + 1
+  int W, H, cx, cy, R, S, we, rst, tile, ntiles, lds_rows, nv, layout, nbins;
 };
 
 // Geometry of one extended image used by the delta kernel (see k_delta.hip): width, height,
@@ -100,11 +112,15 @@ hipError_t prepare_delta_kernels(int max_lds_bytes);
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
                       hipStream_t stream);
-hipError_t launch_full(const FullShape &sh, const uint32_t *ext, int W, int H, int cy,
-                       const VecDesc *vecs, const int32_t *bin_off, unsigned phase_mask,
-                       uint32_t *out, int nv, hipStream_t stream);
-hipError_t launch_finish(const uint32_t *part, int ntiles, int nph, int nv, const int16_t *dxdy,
-                         int cx, int cy, int layout, uint32_t *out, hipStream_t stream);
+hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                       hipStream_t stream);
+size_t full_lds_bytes(const FullShape &sh, int wpg);
+hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
+                        int wpg, unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
+                        hipStream_t stream);
+hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int max_h,
+                            const uint64_t *pool, const int64_t *bits_off, uint32_t *ext,
+                            const int64_t *ext_off, hipStream_t stream);
 hipError_t prepare_full_kernels(int max_lds_bytes);
 
 }  // namespace lpf
