@@ -336,11 +336,16 @@ hipError_t prepare_full_kernels(int max_lds_bytes) {
   hipError_t e = hipSuccess;
   const void *fns[] = {(const void *)k_lpf_full<1>, (const void *)k_lpf_full<2>,
                        (const void *)k_lpf_full<4>, (const void *)k_lpf_full<8>,
-                       (const void *)k_lpf_full<16>, (const void *)k_lpf_batch};
+                       (const void *)k_lpf_full<16>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
     if (r != hipSuccess) e = r;
   }
+  // the batch kernel also holds one static LDS word
+  hipError_t r = hipFuncSetAttribute((const void *)k_lpf_batch,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     max_lds_bytes - kBatchStaticLds);
+  if (r != hipSuccess) e = r;
   return e;
 }
 

@@ -131,6 +131,9 @@ int bank_score(int rst, int R, int S) {
 }
 
 constexpr int kMaxLds = 160 * 1024;
+// staging budget used when an image needs more than the default: leaves room for the batch
+// kernel's own LDS word
+constexpr int kBigLds = kMaxLds - kBatchStaticLds;
 
 }  // namespace
 
@@ -239,11 +242,11 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
       sh.tile = tile;
       break;
     }
-    if (budget >= kMaxLds) {
+    if (budget >= kBigLds) {
       why = "cutoff cy too large for on-chip staging of the halo rows";
       return false;
     }
-    budget = kMaxLds;
+    budget = kBigLds;
   }
   sh.ntiles = (H + sh.tile - 1) / sh.tile;
   sh.lds_rows = sh.tile + cy + rpw;
@@ -901,7 +904,8 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     std::vector<int2> item_list(items.size());
     for (size_t k = 0; k < items.size(); ++k) item_list[k] = items[k].second;
     const size_t lds_bytes = stage_max * 4 + (any_tiled ? (size_t)wpg * kMaxBin * 2 * 4 : 0);
-    if (lds_bytes > (size_t)kMaxLds) return fail(LPF_E_UNSUPPORTED, "lpf_batch: staging exceeds LDS");
+    if (lds_bytes > (size_t)(kMaxLds - kBatchStaticLds))
+      return fail(LPF_E_UNSUPPORTED, "lpf_batch: staging exceeds LDS");
     BatchGraph *b = new (std::nothrow) BatchGraph();
     if (!b) return fail(LPF_E_NOMEM, "lpf_batch: host memory");
     hipError_t e;
@@ -988,7 +992,7 @@ lpf_status lpf_autotune_full(lpf_ctx c, const uint64_t *bits, int W, int H, int 
   for (int R : {2, 4, 8, 16}) {
     if (R > 2 * next_pow2(swd) && R > 2) continue;
     for (int wpg : {4, 8}) {
-      for (int lds : {64 * 1024, kMaxLds}) {
+      for (int lds : {64 * 1024, kBigLds}) {
         c->force_R = R;
         c->force_S = 0;
         c->force_wpg = wpg;
