@@ -41,13 +41,12 @@ def measured_traffic():
 
 def path_pixels(cx: int, cy: int) -> int:
     """M_c = sum over the canonical half domain of (max(|dx|,|dy|) + 1)."""
-    tot = 0
-    for dy in range(cy + 1):
-        for dx in range(-cx, cx + 1):
-            if dy == 0 and dx < 0:
-                continue
-            tot += max(abs(dx), dy) + 1
-    return tot
+    import numpy as np
+    dx = np.arange(-cx, cx + 1)[None, :]
+    dy = np.arange(0, cy + 1)[:, None]
+    n = np.maximum(np.abs(dx), dy) + 1
+    keep = ~((dy == 0) & (dx < 0))
+    return int(n[keep].sum())
 
 
 def ops_alg(W: int, H: int, cx: int, cy: int, nph: int) -> float:
@@ -135,6 +134,73 @@ def anneal_bench(args) -> dict:
     return line
 
 
+def batch_bench(args) -> dict:
+    """Uneven batch: 256 Boolean disk images, side ~ U{64,128,256,512,1024}, phi ~ U[0.2,0.6],
+    r ~ U[3,15], cutoff side/2, both phases; one step = one lpf_batch call (persistent launch,
+    replayed hipGraph)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import Context, _abi
+
+    dev = torch.device("cuda:0")
+    spec = wl.batch_spec(256)
+    ctx = Context(0)
+    stream = torch.cuda.Stream(device=dev)
+    items = []
+    with torch.cuda.stream(stream):
+        for b in spec:
+            bits = ctx.pack(torch.from_numpy(wl.batch_image(b)).to(dev), stream=stream)
+            items.append((bits, b.side, b.side, b.side // 2, b.side // 2))
+            b.img = None
+        t_setup = time.perf_counter()
+        counts, offs, pool, descs = ctx.batch(items, 3, 0, stream=stream)  # plans + capture + 1 run
+        stream.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        for _ in range(max(0, args.warmup - 1)):
+            _abi.lpf_batch(ctx.handle, pool, descs, 3, 0, counts, stream)
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            _abi.lpf_batch(ctx.handle, pool, descs, 3, 0, counts, stream)
+            ev[i][1].record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+    kern_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    placements = 0
+    ops = 0.0
+    for b in spec:
+        c = b.side // 2
+        nv = (c + 1) * (c + 1) + c * c
+        placements += nv * b.side * b.side * 2
+        ops += ops_alg(b.side, b.side, c, c, 2)
+    achieved = ops / kern_s / 1e12
+    sides = [b.side for b in spec]
+    line = {
+        "metric": "LPF path-placements/s",
+        "value": round(placements / (wall / args.steps) / 1e9, 3),
+        "unit": "Gplacements/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched full LPF, 256 Boolean disk images, side U{64..1024}, "
+                               "phi U[0.2,0.6], r U[3,15], cutoff side/2, both phases, one "
+                               "persistent launch (hipGraph replay)",
+                   "images_per_side": {str(s): sides.count(s) for s in sorted(set(sides))},
+                   "setup_s": round(t_setup, 2)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(P_INT_TOPS, 3),
+                     "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4), "traffic": None,
+                     "kernel": "k_lpf_batch (+k_ext_batch in the event window)",
+                     "event_ms_mean": round(kern_s * 1e3, 3), "ops_alg_per_launch": ops},
+    }
+    ctx.close()
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,7 +208,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
-    ap.add_argument("--workload", choices=["full", "anneal"], default="full")
+    ap.add_argument("--workload", choices=["full", "anneal", "batch"], default="full")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (5 times) before the timed steps, "
                          "as the reference kernel for HBM byte counters")
@@ -154,6 +220,9 @@ def main() -> int:
 
     if args.workload == "anneal":
         print(json.dumps(anneal_bench(args)), flush=True)
+        return 0
+    if args.workload == "batch":
+        print(json.dumps(batch_bench(args)), flush=True)
         return 0
 
     import numpy as np
