@@ -220,7 +220,7 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
 
 // One image, one workgroup per work item (item = blockIdx.x).
 template <int R>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   process_item<R>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
@@ -228,7 +228,7 @@ k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
 
 // Many images, persistent workgroups drawing work items from a device counter in descending
 // cost order until the list is exhausted (every wave reaches the exit test).
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_lpf_batch(const FullImg *__restrict__ imgs, const int2 *__restrict__ items, int n_items,
             int *__restrict__ counter, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];

@@ -216,6 +216,7 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   const int rpw = 64 / S;
   sh.R = R;
   sh.S = S;
+  // 8 waves per group when one tile fits the default budget (two groups per CU), else 16
   sh.wpg = fW ? fW : 8;
   sh.we = S * R + (cx >> 5) + 1;
   int best = sh.we, best_score = 1 << 30;
@@ -242,6 +243,7 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
       sh.tile = tile;
       break;
     }
+    if (!fW) sh.wpg = 16;
     if (budget >= kBigLds) {
       why = "cutoff cy too large for on-chip staging of the halo rows";
       return false;
@@ -580,10 +582,10 @@ lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int c
 lpf_status lpf_set_full_shape(lpf_ctx c, int R, int S, int waves_per_group, int lds_bytes) {
   if (!c) return fail(LPF_E_INVAL, "lpf_set_full_shape: ctx is NULL");
   auto pow2ok = [](int v, int hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
-  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 8 ||
+  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 16 ||
       lds_bytes < 0 || lds_bytes > kMaxLds)
     return fail(LPF_E_INVAL, "lpf_set_full_shape: R in {1..16}, S in {1..64} powers of two, "
-                             "waves 1..8, lds <= 160 KiB (0 = automatic)");
+                             "waves 1..16, lds <= 160 KiB (0 = automatic)");
   std::lock_guard<std::mutex> lk(c->mu);
   c->force_R = R;
   c->force_S = S;
@@ -865,7 +867,18 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
   }
   auto it = c->batch_graphs.find(key);
   if (it == c->batch_graphs.end()) {
-    const int wpg = 8;
+    // 16 waves per group when some image needs the large staging budget (one group per CU)
+    int wpg = 8;
+    for (int i = 0; i < n_images && wpg == 8; ++i) {
+      FullShape probe{};
+      std::string why;
+      const int saved_wpg = c->force_wpg;
+      c->force_wpg = 8;
+      const bool okp = choose_shape(c, descs[i].W, descs[i].H, descs[i].cx, descs[i].cy, probe, why);
+      c->force_wpg = saved_wpg;
+      if (!okp) return fail(LPF_E_UNSUPPORTED, "lpf_batch: " + why + " (image " + std::to_string(i) + ")");
+      if (full_lds_bytes(probe, 8) > 80 * 1024) wpg = 16;
+    }
     std::vector<FullImg> imgs(n_images);
     std::vector<int64_t> bits_off(n_images), ext_off(n_images);
     std::vector<std::pair<int64_t, int2>> items;
@@ -991,7 +1004,7 @@ lpf_status lpf_autotune_full(lpf_ctx c, const uint64_t *bits, int W, int H, int 
   }
   for (int R : {2, 4, 8, 16}) {
     if (R > 2 * next_pow2(swd) && R > 2) continue;
-    for (int wpg : {4, 8}) {
+    for (int wpg : {4, 8, 16}) {
       for (int lds : {64 * 1024, kBigLds}) {
         c->force_R = R;
         c->force_S = 0;

@@ -26,7 +26,7 @@ struct FullShape {
 };
 
 // Most vectors in one wave-level bin (count slots in LDS when an image has several row tiles).
-constexpr int kMaxBin = 128;
+constexpr int kMaxBin = 64;
 // LDS the persistent batch kernel keeps for itself (the claimed work item), below the 160 KiB.
 constexpr int kBatchStaticLds = 256;
 

@@ -95,7 +95,7 @@ def test_autotune_keeps_counts(ctx):
     before = ctx.full(bits, 256, 256, 64, 64)
     ms = ctx.autotune(bits, 256, 256, 64, 64)
     R, wpg, lds = ctx.tuned_shape(256, 256, 64, 64)
-    assert ms > 0 and R in (2, 4, 8, 16) and wpg in (4, 8) and lds > 0
+    assert ms > 0 and R in (2, 4, 8, 16) and wpg in (4, 8, 16) and lds > 0
     after = ctx.full(bits, 256, 256, 64, 64)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
