@@ -164,7 +164,8 @@ enum { LPF_PROP_UNIFORM = 0, LPF_PROP_INTERFACIAL = 1 };
  *   pixel order.  n1 is read only when pos is given.  seed and step0 select the random stream:
  *   candidate k of step s uses Philox-4x64-10 with counter {s, k, 0, 0} and key {seed, 0x6c7066}:
  *   a = pos1[(r0>>32)*n1 >> 32], b = pos0[(r1>>32)*n0 >> 32], U = (r2>>11) * 2^-53.
- * Requires an image with both phases present; same W, H, cx, cy, phase_mask rules as lpf_full.
+ * Requires an image with both phases present; same W, H, cx, cy, phase_mask rules as lpf_full,
+ * and max(cx, cy) <= 16383.
  * Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
 lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, int cy,
                              unsigned phase_mask, uint32_t *counts, const uint32_t *target,
@@ -175,7 +176,9 @@ lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, 
  * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),
  * compute each one's exact energy change de against the current state, and apply the first, in
  * draw order, with de <= 0 or U < exp(-de/T) (the Metropolis rule for a minimisation).  The
- * step's record is written to *out (device).  Everything stays on the device.
+ * candidates are evaluated in rounds of 512 in draw order and rounds after an acceptance are
+ * skipped, which gives the same result as evaluating all of them.  The step's record is written
+ * to *out (device).  Everything stays on the device.
  * Errors: LPF_E_INVAL (n_candidates outside [1, 2^20], proposal, T <= 0), LPF_E_NOMEM,
  * LPF_E_DEVICE. */
 lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,

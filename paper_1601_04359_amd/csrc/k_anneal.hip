@@ -1,7 +1,7 @@
 // Device-resident simulated annealing on the lineal path function (Sec. 4, Alg. "annealing",
-// objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn, their exact energy
-// changes are evaluated against the current state (k_delta, mode 1), and the first candidate in
-// draw order that passes the Metropolis test is applied.  Rejected candidates leave the state
+// objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn (here), their exact
+// energy changes are evaluated against the current state in draw order and the first candidate
+// that passes the Metropolis test is applied (k_step.hip).  Rejected candidates leave the state
 // unchanged, so this is the sequential chain of the algorithm with the step's later candidates
 // unused.  Nothing returns to the host inside a step.
 //
@@ -71,76 +71,6 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
   U[k] = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
 }
 
-// First accepted candidate (one workgroup).  Writes the step record, the running energy, the
-// selected index and advances the step counter.
-__global__ void __launch_bounds__(1024)
-k_select(AnnealDev *__restrict__ st, const int64_t *__restrict__ S_part, int nchunks, int K,
-         const int2 *__restrict__ cand, const double *__restrict__ U, double T, int64_t N,
-         int64_t Nt, double *__restrict__ e_io, int32_t *__restrict__ k_sel,
-         StepResult *__restrict__ out) {
-  __shared__ int best[1024];
-  int mine = 0x7fffffff;
-  const double denom = (double)N * (double)N * (double)Nt;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    if (cand[k].x < 0) continue;
-    int64_t S = 0;
-    for (int c = 0; c < nchunks; ++c) S += S_part[(size_t)c * K + k];
-    const double de = (double)S / denom;
-    if (de <= 0.0 || U[k] < exp(-de / T)) {
-      mine = min(mine, k);
-      break;  // later k of this thread cannot be smaller
-    }
-  }
-  best[threadIdx.x] = mine;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) best[threadIdx.x] = min(best[threadIdx.x], best[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const int ks = best[0] == 0x7fffffff ? -1 : best[0];
-    StepResult r;
-    r.step = st->step;
-    if (ks >= 0) {
-      int64_t S = 0;
-      for (int c = 0; c < nchunks; ++c) S += S_part[(size_t)c * K + ks];
-      const double de = (double)S / denom;
-      const double e = *e_io + de;
-      *e_io = e;
-      r.k = ks;
-      r.a = cand[ks].x;
-      r.b = cand[ks].y;
-      r.de = de;
-      r.e = e;
-    } else {
-      r.k = -1;
-      r.a = -1;
-      r.b = -1;
-      r.de = 0.0;
-      r.e = *e_io;
-    }
-    r.pad = 0;
-    *out = r;
-    *k_sel = ks;
-    st->step += 1;
-  }
-}
-
-// Apply the selected interchange to the packed image and to the pixel lists.
-__global__ void k_apply_swap(AnnealDev *__restrict__ st, uint64_t *__restrict__ bits, int W,
-                             const int32_t *__restrict__ k_sel, const int2 *__restrict__ cand,
-                             const int2 *__restrict__ slot) {
-  const int ks = *k_sel;
-  if (ks < 0 || threadIdx.x != 0) return;
-  const int wpr = (W + 63) >> 6;
-  const int a = cand[ks].x, b = cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
-  const int ay = a / W, ax = a - ay * W, by = b / W, bx = b - by * W;
-  bits[(size_t)ay * wpr + (ax >> 6)] &= ~(1ull << (ax & 63));
-  bits[(size_t)by * wpr + (bx >> 6)] |= 1ull << (bx & 63);
-  st->pos1[slot[ks].x] = b;
-  st->pos0[slot[ks].y] = a;
-}
-
 // Pixel lists in ascending index order (one workgroup; each thread scans a contiguous range).
 __global__ void __launch_bounds__(1024)
 k_init_lists(AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits, int W, int H) {
@@ -176,15 +106,6 @@ k_init_lists(AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits, int 
   }
 }
 
-// Pixel counts from caller-provided lists (resume) and the step counter.
-__global__ void k_set_counts(AnnealDev *__restrict__ st, int n1, int n0, uint64_t step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->n1 = n1;
-    st->n0 = n0;
-    st->step = step;
-  }
-}
-
 // eq. (LSE) in canonical order (one thread, fixed order).
 __global__ void k_lse(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ target,
                       int64_t nterms, int64_t N, int64_t Nt, double *__restrict__ e) {
@@ -205,28 +126,9 @@ hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int 
   return hipGetLastError();
 }
 
-hipError_t launch_select(AnnealDev *st, const int64_t *S_part, int nchunks, int K,
-                         const int2 *cand, const double *U, double T, int64_t N, int64_t Nt,
-                         double *e, int32_t *k_sel, StepResult *out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, st, S_part, nchunks, K, cand, U, T,
-                     N, Nt, e, k_sel, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_apply_swap(AnnealDev *st, uint64_t *bits, int W, const int32_t *k_sel,
-                             const int2 *cand, const int2 *slot, hipStream_t stream) {
-  hipLaunchKernelGGL(k_apply_swap, dim3(1), dim3(64), 0, stream, st, bits, W, k_sel, cand, slot);
-  return hipGetLastError();
-}
-
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream) {
   hipLaunchKernelGGL(k_init_lists, dim3(1), dim3(1024), 0, stream, st, bits, W, H);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_counts(AnnealDev *st, int n1, int n0, uint64_t step, hipStream_t stream) {
-  hipLaunchKernelGGL(k_set_counts, dim3(1), dim3(64), 0, stream, st, n1, n0, step);
   return hipGetLastError();
 }
 

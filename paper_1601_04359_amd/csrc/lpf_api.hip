@@ -162,8 +162,7 @@ struct lpf_anneal_s {
   uint64_t seed = 0;
   AnnealDev *dev = nullptr;  // device struct
   int32_t *pos = nullptr;    // device, W*H: phase-1 list then phase-0 list (reserved in place)
-  DevBuf E3, cand, U, slot, S_part, ksel;
-  int K_cap = 0;
+  DevBuf E3, cand, U, slot, S_part, ksel, dl, ctl;
 };
 
 // A captured lpf_batch launch (extended images, counter reset, persistent kernel).
@@ -355,7 +354,10 @@ FullImg make_img(const FullPlan &p, const uint32_t *ext, uint32_t *out, int W, i
   return I;
 }
 
-constexpr int kDeltaLdsMax = 64 * 1024;
+// delta-kernel staging of the three image frames (below 64 KiB, the kernels' static words aside)
+constexpr int kDeltaLdsMax = 60 * 1024;
+// candidates per evaluation round of an annealing step
+constexpr int kRound = 512;
 
 // Geometry of the three frames used by the delta kernel (image, transposed, anti-transposed).
 DeltaGeo delta_geometry(int W, int H, int cx, int cy) {
@@ -511,6 +513,7 @@ lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out) {
   DeviceGuard g(c->dev);
   hipError_t e = prepare_full_kernels(kMaxLds);
   if (e == hipSuccess) e = prepare_delta_kernels(kDeltaLdsMax);
+  if (e == hipSuccess) e = prepare_step_kernels(kDeltaLdsMax);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "lpf_ctx_create: kernel attributes");
@@ -630,7 +633,7 @@ lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx,
   L.delta_out = delta;
   L.nchunks = plan->nchunks;
   L.use_lds = plan->use_lds;
-  if ((e = launch_delta(0, L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
+  if ((e = launch_delta(L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
   return LPF_OK;
 }
 
@@ -648,6 +651,8 @@ lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, in
   const int64_t N = (int64_t)W * H;
   if (N < 2 || N > ((int64_t)1 << 26)) return fail(LPF_E_INVAL, "lpf_anneal_create: W*H outside [2, 2^26]");
   if (pos && (n1 < 1 || n1 > N - 1)) return fail(LPF_E_INVAL, "lpf_anneal_create: n1");
+  if (std::max(cx, cy) > 16383)
+    return fail(LPF_E_INVAL, "lpf_anneal_create: cutoff above 16383 (per-candidate deltas are int16)");
   // full evaluation for the initial counts (also validates the tile shape)
   st = lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
   if (st != LPF_OK) return st;
@@ -737,18 +742,22 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
   DeltaPlan *plan = nullptr;
-  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, delta_chunks(K), plan);
+  const int C = std::min(K, kRound);
+  const int nchunks_req = std::max(1, 2048 / ((C + 255) / 256));
+  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, nchunks_req, plan);
   if (st != LPF_OK) return st;
-  DeltaPlan *plan1 = nullptr;
-  if ((st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, delta_chunks(1), plan1)) != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   const bool first = a->E3.p == nullptr;
+  const int nph = nph_of(a->mask);
+  const size_t nterms = (size_t)nph * plan->nv;
   if ((e = a->E3.ensure((size_t)plan->geo.total * 4)) != hipSuccess ||
       (e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
       (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
-      (e = a->S_part.ensure(sizeof(int64_t) * (size_t)K * plan->nchunks)) != hipSuccess ||
+      (e = a->S_part.ensure(sizeof(int64_t) * (size_t)C * plan->nchunks)) != hipSuccess ||
+      (e = a->dl.ensure(sizeof(int16_t) * nterms * (size_t)K)) != hipSuccess ||
+      (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
       (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess)
     return hip_fail(e, "anneal_step: scratch");
   uint32_t *E = (uint32_t *)a->E3.p;
@@ -759,43 +768,41 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cand,
                           (double *)a->U.p, (int2 *)a->slot.p, s)) != hipSuccess)
     return hip_fail(e, "anneal_step: propose");
-  DeltaLaunch L{};
+  StepLaunch L{};
   L.E = E;
   L.geo = plan->geo;
   L.bits = a->bits;
+  L.bits_rw = a->bits;
   L.W = a->W;
   L.H = a->H;
   L.cand = cand;
+  L.slot = (const int2 *)a->slot.p;
+  L.U = (const double *)a->U.p;
   L.K = K;
+  L.C = C;
   L.vecs = plan->vecs;
   L.chunk_off = plan->chunk_off;
+  L.nchunks = plan->nchunks;
   L.runs = plan->runs;
   L.phase_mask = a->mask;
   L.nv = (int)plan->nv;
+  L.nterms = (int)nterms;
   L.counts = a->counts;
+  L.counts_rw = a->counts;
   L.target = a->target;
   L.N = N;
   L.Nt = a->Nt;
+  L.T = T;
   L.S_part = (int64_t *)a->S_part.p;
-  L.nchunks = plan->nchunks;
+  L.dl = (int16_t *)a->dl.p;
+  L.ctl = (StepCtl *)a->ctl.p;
+  L.st = a->dev;
+  L.e = a->e;
+  L.k_sel = (int32_t *)a->ksel.p;
+  L.out = reinterpret_cast<StepResult *>(out);
   L.use_lds = plan->use_lds;
-  if ((e = launch_delta(1, L, s)) != hipSuccess) return hip_fail(e, "anneal_step: delta");
-  if ((e = launch_select(a->dev, (const int64_t *)a->S_part.p, plan->nchunks, K, cand,
-                         (const double *)a->U.p, T, N, a->Nt, a->e, (int32_t *)a->ksel.p,
-                         reinterpret_cast<StepResult *>(out), s)) != hipSuccess)
-    return hip_fail(e, "anneal_step: select");
-  DeltaLaunch L1 = L;
-  L1.vecs = plan1->vecs;
-  L1.chunk_off = plan1->chunk_off;
-  L1.runs = plan1->runs;
-  L1.nchunks = plan1->nchunks;
-  L1.counts_rw = a->counts;
-  L1.k_sel = (const int32_t *)a->ksel.p;
-  if ((e = launch_delta(2, L1, s)) != hipSuccess) return hip_fail(e, "anneal_step: apply counts");
-  if ((e = launch_apply_swap(a->dev, a->bits, a->W, (const int32_t *)a->ksel.p, cand,
-                             (const int2 *)a->slot.p, s)) != hipSuccess)
-    return hip_fail(e, "anneal_step: apply swap");
-  if ((e = launch_ext3(a->bits, a->W, a->H, plan->geo, E, s)) != hipSuccess)
+  if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal_step: evaluation");
+  if ((e = launch_ext3_if(a->bits, a->W, a->H, plan->geo, E, (const int32_t *)a->ksel.p, s)) != hipSuccess)
     return hip_fail(e, "anneal_step: ext3");
   return LPF_OK;
 }
@@ -830,6 +837,8 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->slot.release();
     a->S_part.release();
     a->ksel.release();
+    a->dl.release();
+    a->ctl.release();
   }
   delete a;
 }

@@ -68,19 +68,54 @@ struct DeltaLaunch {
   const uint32_t *runs;
   unsigned phase_mask;
   int nv;
-  int32_t *delta_out;        // mode 0
-  const uint32_t *counts;    // mode 1
-  const uint32_t *target;    // mode 1
-  int64_t N, Nt;             // mode 1
-  int64_t *S_part;           // mode 1: [nchunks][K]
-  uint32_t *counts_rw;       // mode 2
-  const int32_t *k_sel;      // mode 2
+  int32_t *delta_out;
   int nchunks;
+  bool use_lds;
+};
+
+// Per-step control block of the round-wise evaluation (k_step.hip).
+struct StepCtl {
+  int32_t done;  // a round has accepted
+  int32_t ks;    // accepted candidate, -1 when none
+  long long S;   // its integer energy sum
+};
+
+struct StepLaunch {
+  const uint32_t *E;
+  DeltaGeo geo;
+  const uint64_t *bits;
+  uint64_t *bits_rw;
+  int W, H;
+  const int2 *cand;
+  const int2 *slot;
+  const double *U;
+  int K, C;                  // candidates per step, candidates per round
+  const DeltaVec *vecs;
+  const int32_t *chunk_off;
+  int nchunks;
+  const uint32_t *runs;
+  unsigned phase_mask;
+  int nv, nterms;            // nterms = phases * vectors
+  const uint32_t *counts;
+  uint32_t *counts_rw;
+  const uint32_t *target;
+  int64_t N, Nt;
+  double T;
+  int64_t *S_part;           // [nchunks][C]
+  int16_t *dl;               // [phases][vectors][K]
+  StepCtl *ctl;
+  struct AnnealDev *st;
+  double *e;
+  int32_t *k_sel;
+  struct StepResult *out;
   bool use_lds;
 };
 
 hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
                        hipStream_t stream);
+// Same, skipped on the device when *flag < 0 (no interchange was applied).
+hipError_t launch_ext3_if(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
+                          const int32_t *flag, hipStream_t stream);
 
 // Device-side annealing state (k_anneal.hip).
 struct AnnealDev {
@@ -97,18 +132,14 @@ struct StepResult {
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, int2 *cand, double *U, int2 *slot,
                           hipStream_t stream);
-hipError_t launch_select(AnnealDev *st, const int64_t *S_part, int nchunks, int K,
-                         const int2 *cand, const double *U, double T, int64_t N, int64_t Nt,
-                         double *e, int32_t *k_sel, StepResult *out, hipStream_t stream);
-hipError_t launch_apply_swap(AnnealDev *st, uint64_t *bits, int W, const int32_t *k_sel,
-                             const int2 *cand, const int2 *slot, hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream);
-hipError_t launch_set_counts(AnnealDev *st, int n1, int n0, uint64_t step, hipStream_t stream);
 hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,
                       int64_t Nt, double *e, hipStream_t stream);
-hipError_t launch_delta(int mode, const DeltaLaunch &L, hipStream_t stream);
+hipError_t launch_delta(const DeltaLaunch &L, hipStream_t stream);
 hipError_t prepare_delta_kernels(int max_lds_bytes);
+hipError_t launch_step(const StepLaunch &L, hipStream_t stream);
+hipError_t prepare_step_kernels(int max_lds_bytes);
 
 // Kernel launchers (defined in k_full.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
