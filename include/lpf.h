@@ -193,6 +193,49 @@ lpf_status lpf_anneal_export(lpf_anneal st, int32_t *pos, int *n1, uint64_t *nex
 /* Release the chain's device state (waits for the device).  NULL is a no-op. */
 void lpf_anneal_destroy(lpf_anneal st);
 
+/* ---- swap-proposal CNN --------------------------------------------------------------------
+ * Not in the paper, which leaves the modification operator open (Sec. 4): a small CNN scores
+ * every pixel of a cell so that candidate interchanges can be drawn where they are likely to
+ * lower the error; the exact lineal-path change still judges every move (anneal_step).
+ * Network: input (pixel value, interface flag) -> 3 x [conv3x3, 16 channels, periodic padding,
+ * relu] -> 1x1 head, one score per pixel.  bfloat16 weights and activations, fp32 accumulation
+ * (MFMA).  Parameters: LPF_CNN_PARAMS fp32 values packed as W1 [9][16][2], b1 [16],
+ * W2 [9][16][16], b2, W3 [9][16][16], b3, W4 [16], b4 [1]; tap t = 3 dy + dx reads the input at
+ * offset (dy-1, dx-1).  Training loss for samples (image, a, b, y): mean (S[a] + S[b] - y)^2. */
+#define LPF_CNN_PARAMS 4961
+
+typedef struct lpf_cnn_s *lpf_cnn;
+typedef struct {
+  int32_t img;  /* index of the image in the batch */
+  int32_t a, b; /* linear pixel indices y*W + x */
+  float y;      /* regression target for S[a] + S[b] */
+} lpf_cnn_sample;
+
+/* Network for W x H cells, batches of up to max_batch images and max_samples samples.
+ * params: LPF_CNN_PARAMS fp32 values (device), or NULL for all zeros.  Errors: LPF_E_INVAL,
+ * LPF_E_NOMEM, LPF_E_DEVICE. */
+lpf_status lpf_cnn_create(lpf_ctx ctx, int W, int H, int max_batch, int max_samples,
+                          const float *params, lpf_cnn *out, void *stream);
+/* Replace the parameters (device, LPF_CNN_PARAMS fp32) and clear the Adam moments. */
+lpf_status lpf_cnn_set_params(lpf_cnn net, const float *params, void *stream);
+/* Copy the parameters to params (device, LPF_CNN_PARAMS fp32). */
+lpf_status lpf_cnn_get_params(lpf_cnn net, float *params, void *stream);
+/* Scores of a batch of packed cells (bits: batch images back to back, device) into
+ * scores[batch][H][W] (fp32, device). */
+lpf_status lpf_cnn_forward(lpf_cnn net, const uint64_t *bits, int batch, float *scores,
+                           void *stream);
+/* Loss and its gradient for n samples on a batch of cells: grad (device, LPF_CNN_PARAMS fp32),
+ * loss (device, one fp32).  A sample with an out-of-range image or pixel contributes a zero
+ * residual.  The score gradient is accumulated in 2^-40 fixed point, so the result does not
+ * depend on the order of the samples.  Errors: LPF_E_INVAL (batch, n), LPF_E_DEVICE. */
+lpf_status lpf_cnn_grad(lpf_cnn net, const uint64_t *bits, int batch,
+                        const lpf_cnn_sample *samples, int n, float *grad, float *loss,
+                        void *stream);
+/* One Adam step (Kingma & Ba) with gradient grad (device) at step t >= 1. */
+lpf_status lpf_cnn_adam(lpf_cnn net, const float *grad, int t, float lr, float beta1, float beta2,
+                        float eps, void *stream);
+void lpf_cnn_destroy(lpf_cnn net);
+
 /* Tile-shape override for lpf_full (and the kernels that share its launch plans); used by the
  * autotuner.  R = 32-pixel words per lane (1,2,4,8,16), S = lanes per image row (power of two,
  * <= 64), waves_per_group (1..16), lds_bytes = staging budget per workgroup (<= 160 KiB).

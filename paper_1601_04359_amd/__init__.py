@@ -160,3 +160,63 @@ class Anneal:
             self.close()
         except Exception:
             pass
+
+
+def cnn_samples(img_idx, a, b, y, device) -> torch.Tensor:
+    """Pack interchange samples as the C ABI's lpf_cnn_sample records (int32 x3, float32)."""
+    n = len(a)
+    rec = _np.zeros((n, 4), _np.int32)
+    rec[:, 0] = _np.asarray(img_idx, _np.int32)
+    rec[:, 1] = _np.asarray(a, _np.int32)
+    rec[:, 2] = _np.asarray(b, _np.int32)
+    rec[:, 3] = _np.asarray(y, _np.float32).view(_np.int32)
+    return torch.from_numpy(rec).to(device)
+
+
+class ProposalNet:
+    """The swap-proposal CNN (lpf_cnn_*): scores every pixel of W x H cells."""
+
+    def __init__(self, ctx: Context, W: int, H: int, max_batch: int, max_samples: int,
+                 params: torch.Tensor | None = None, stream=None):
+        self.ctx, self.W, self.H = ctx, W, H
+        self.max_batch, self.max_samples = max_batch, max_samples
+        self.handle = _abi.lpf_cnn_create(ctx.handle, W, H, max_batch, max_samples,
+                                          None if params is None else params.contiguous(), stream)
+        self.t = 0
+
+    def params(self, stream=None) -> torch.Tensor:
+        out = torch.empty(_abi.LPF_CNN_PARAMS, dtype=torch.float32, device="cuda")
+        _abi.lpf_cnn_get_params(self.handle, out, stream)
+        return out
+
+    def set_params(self, p: torch.Tensor, stream=None) -> None:
+        _abi.lpf_cnn_set_params(self.handle, p.contiguous(), stream)
+        self.t = 0
+
+    def forward(self, bits: torch.Tensor, batch: int, out=None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((batch, self.H, self.W), dtype=torch.float32, device=bits.device)
+        _abi.lpf_cnn_forward(self.handle, bits.contiguous(), batch, out, stream)
+        return out
+
+    def grad(self, bits: torch.Tensor, batch: int, samples: torch.Tensor, stream=None):
+        g = torch.empty(_abi.LPF_CNN_PARAMS, dtype=torch.float32, device=bits.device)
+        loss = torch.empty(1, dtype=torch.float32, device=bits.device)
+        _abi.lpf_cnn_grad(self.handle, bits.contiguous(), batch, samples, samples.shape[0], g,
+                          loss, stream)
+        return g, loss
+
+    def adam(self, grad: torch.Tensor, lr: float, stream=None) -> None:
+        self.t += 1
+        _abi.lpf_cnn_adam(self.handle, grad, self.t, lr, stream=stream)
+
+    def close(self) -> None:
+        if getattr(self, "handle", 0):
+            _abi.lpf_cnn_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -65,6 +65,16 @@ _sig("lpf_autotune_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P,
 _sig("lpf_get_tuned_shape", _i32, _P, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32),
      ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 
+_sig("lpf_cnn_create", _i32, _P, _i32, _i32, _i32, _i32, _P, ctypes.POINTER(_P), _P)
+_sig("lpf_cnn_set_params", _i32, _P, _P, _P)
+_sig("lpf_cnn_get_params", _i32, _P, _P, _P)
+_sig("lpf_cnn_forward", _i32, _P, _P, _i32, _P, _P)
+_sig("lpf_cnn_grad", _i32, _P, _P, _i32, _P, _i32, _P, _P, _P)
+_sig("lpf_cnn_adam", _i32, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+     ctypes.c_float, _P)
+_sig("lpf_cnn_destroy", None, _P)
+LPF_CNN_PARAMS = 4961
+
 LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL = 0, 1
 
 
@@ -224,3 +234,45 @@ def lpf_get_tuned_shape(ctx: int, W: int, H: int, cx: int, cy: int):
 def lpf_set_full_shape(ctx: int, R: int = 0, S: int = 0, waves_per_group: int = 0,
                        lds_bytes: int = 0) -> None:
     _check(_lib.lpf_set_full_shape(ctx, R, S, waves_per_group, lds_bytes))
+
+
+def lpf_cnn_create(ctx: int, W: int, H: int, max_batch: int, max_samples: int, params=None,
+                   stream=None) -> int:
+    h = _P()
+    _check(_lib.lpf_cnn_create(ctx, W, H, max_batch, max_samples,
+                               _dev(params, torch.float32, "params") if params is not None else None,
+                               ctypes.byref(h), _stream(stream)))
+    return h.value
+
+
+def lpf_cnn_set_params(net: int, params: torch.Tensor, stream=None) -> None:
+    _check(_lib.lpf_cnn_set_params(net, _dev(params, torch.float32, "params"), _stream(stream)))
+
+
+def lpf_cnn_get_params(net: int, params: torch.Tensor, stream=None) -> None:
+    _check(_lib.lpf_cnn_get_params(net, _dev(params, torch.float32, "params"), _stream(stream)))
+
+
+def lpf_cnn_forward(net: int, bits: torch.Tensor, batch: int, scores: torch.Tensor,
+                    stream=None) -> None:
+    _check(_lib.lpf_cnn_forward(net, _dev(bits, torch.int64, "bits"), batch,
+                                _dev(scores, torch.float32, "scores"), _stream(stream)))
+
+
+def lpf_cnn_grad(net: int, bits: torch.Tensor, batch: int, samples: torch.Tensor, n: int,
+                 grad: torch.Tensor, loss: torch.Tensor, stream=None) -> None:
+    """samples: int32 tensor (n, 4) holding (img, a, b, float32 bits of y)."""
+    _check(_lib.lpf_cnn_grad(net, _dev(bits, torch.int64, "bits"), batch,
+                             _dev(samples, torch.int32, "samples"), n,
+                             _dev(grad, torch.float32, "grad"), _dev(loss, torch.float32, "loss"),
+                             _stream(stream)))
+
+
+def lpf_cnn_adam(net: int, grad: torch.Tensor, t: int, lr: float, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(_lib.lpf_cnn_adam(net, _dev(grad, torch.float32, "grad"), t, lr, beta1, beta2, eps,
+                             _stream(stream)))
+
+
+def lpf_cnn_destroy(net: int) -> None:
+    _lib.lpf_cnn_destroy(net)

@@ -1,6 +1,7 @@
 // liblpf C ABI: argument checks, per-context caches and scratch, launch plans.
 // Declarations and the contract of every entry point are in include/lpf.h.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -175,6 +176,13 @@ struct BatchGraph {
   int *counter = nullptr;
   uint32_t *ext = nullptr;
   int n_items = 0, n_wg = 0;
+};
+
+struct lpf_cnn_s {
+  lpf_ctx ctx = nullptr;
+  int W = 0, H = 0, max_batch = 0, max_samples = 0;
+  CnnBufs b{};
+  std::vector<void *> allocs;
 };
 
 namespace {
@@ -1070,6 +1078,129 @@ lpf_status lpf_get_tuned_shape(lpf_ctx c, int W, int H, int cx, int cy, int *R, 
   if (wpg) *wpg = it->second.wpg;
   if (lds_bytes) *lds_bytes = it->second.lds;
   return LPF_OK;
+}
+
+lpf_status lpf_cnn_create(lpf_ctx c, int W, int H, int max_batch, int max_samples,
+                          const float *params, lpf_cnn *out, void *stream) {
+  if (!out) return fail(LPF_E_INVAL, "lpf_cnn_create: out is NULL");
+  *out = nullptr;
+  if (!c) return fail(LPF_E_INVAL, "lpf_cnn_create: ctx is NULL");
+  if (W < 1 || H < 1 || W > 65535 || H > 65535 || max_batch < 1 || max_samples < 1 ||
+      (int64_t)W * H * max_batch > ((int64_t)1 << 28) || max_samples > (1 << 26))
+    return fail(LPF_E_INVAL, "lpf_cnn_create: sizes");
+  lpf_cnn n = new (std::nothrow) lpf_cnn_s();
+  if (!n) return fail(LPF_E_NOMEM, "lpf_cnn_create: host memory");
+  n->ctx = c;
+  n->W = W;
+  n->H = H;
+  n->max_batch = max_batch;
+  n->max_samples = max_samples;
+  DeviceGuard g(c->dev);
+  const int64_t np = (int64_t)W * H * max_batch;
+  const int64_t cb = cnn_conv_blocks(np), hb = (np + 255) / 256;
+  hipError_t e = hipSuccess;
+  auto get = [&](void **p, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    if (e == hipSuccess) n->allocs.push_back(*p);
+  };
+  CnnBufs &B = n->b;
+  get((void **)&B.prm, 4 * kCnnParams);
+  get((void **)&B.mom, 4 * kCnnParams);
+  get((void **)&B.vel, 4 * kCnnParams);
+  get((void **)&B.Wf, 2 * 3 * 2304);
+  get((void **)&B.Wt, 2 * 3 * 2304);
+  get((void **)&B.W4bf, 4 * 16);
+  get((void **)&B.X0, 2 * 4 * (size_t)np);
+  get((void **)&B.A1, 2 * 16 * (size_t)np);
+  get((void **)&B.A2, 2 * 16 * (size_t)np);
+  get((void **)&B.A3, 2 * 16 * (size_t)np);
+  get((void **)&B.dZ1, 2 * 16 * (size_t)np);
+  get((void **)&B.dZ2, 2 * 16 * (size_t)np);
+  get((void **)&B.dZ3, 2 * 16 * (size_t)np);
+  get((void **)&B.S, 4 * (size_t)np);
+  get((void **)&B.r, 4 * (size_t)max_samples);
+  get((void **)&B.dS, 8 * (size_t)np);
+  get((void **)&B.part1, 4 * (size_t)cb * (9 * 256 + 16));
+  get((void **)&B.part2, 4 * (size_t)cb * (9 * 256 + 16));
+  get((void **)&B.part3, 4 * (size_t)cb * (9 * 256 + 16));
+  get((void **)&B.part_h, 4 * (size_t)hb * 17);
+  hipStream_t s = (hipStream_t)stream;
+  if (e == hipSuccess) {
+    if (params) e = hipMemcpyAsync(B.prm, params, 4 * kCnnParams, hipMemcpyDeviceToDevice, s);
+    else e = hipMemsetAsync(B.prm, 0, 4 * kCnnParams, s);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(B.mom, 0, 4 * kCnnParams, s);
+  if (e == hipSuccess) e = hipMemsetAsync(B.vel, 0, 4 * kCnnParams, s);
+  if (e == hipSuccess) e = cnn_pack(B, s);
+  if (e != hipSuccess) {
+    lpf_cnn_destroy(n);
+    return hip_fail(e, "lpf_cnn_create");
+  }
+  *out = n;
+  return LPF_OK;
+}
+
+lpf_status lpf_cnn_set_params(lpf_cnn n, const float *params, void *stream) {
+  if (!n || !params) return fail(LPF_E_INVAL, "lpf_cnn_set_params: NULL argument");
+  DeviceGuard g(n->ctx->dev);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(n->b.prm, params, 4 * kCnnParams, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(n->b.mom, 0, 4 * kCnnParams, s);
+  if (e == hipSuccess) e = hipMemsetAsync(n->b.vel, 0, 4 * kCnnParams, s);
+  if (e == hipSuccess) e = cnn_pack(n->b, s);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_set_params");
+}
+
+lpf_status lpf_cnn_get_params(lpf_cnn n, float *params, void *stream) {
+  if (!n || !params) return fail(LPF_E_INVAL, "lpf_cnn_get_params: NULL argument");
+  DeviceGuard g(n->ctx->dev);
+  hipError_t e = hipMemcpyAsync(params, n->b.prm, 4 * kCnnParams, hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_get_params");
+}
+
+lpf_status lpf_cnn_forward(lpf_cnn n, const uint64_t *bits, int batch, float *scores,
+                           void *stream) {
+  if (!n || !bits || !scores) return fail(LPF_E_INVAL, "lpf_cnn_forward: NULL argument");
+  if (batch < 1 || batch > n->max_batch) return fail(LPF_E_INVAL, "lpf_cnn_forward: batch");
+  DeviceGuard g(n->ctx->dev);
+  hipError_t e = cnn_forward(n->b, bits, n->W, n->H, batch, scores, (hipStream_t)stream);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_forward");
+}
+
+lpf_status lpf_cnn_grad(lpf_cnn n, const uint64_t *bits, int batch, const lpf_cnn_sample *samples,
+                        int ns, float *grad, float *loss, void *stream) {
+  if (!n || !bits || !samples || !grad || !loss) return fail(LPF_E_INVAL, "lpf_cnn_grad: NULL argument");
+  if (batch < 1 || batch > n->max_batch) return fail(LPF_E_INVAL, "lpf_cnn_grad: batch");
+  if (ns < 1 || ns > n->max_samples) return fail(LPF_E_INVAL, "lpf_cnn_grad: n");
+  DeviceGuard g(n->ctx->dev);
+  hipError_t e = cnn_grad(n->b, bits, n->W, n->H, batch,
+                          reinterpret_cast<const CnnSample *>(samples), ns, grad, loss,
+                          (hipStream_t)stream);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_grad");
+}
+
+lpf_status lpf_cnn_adam(lpf_cnn n, const float *grad, int t, float lr, float beta1, float beta2,
+                        float eps, void *stream) {
+  if (!n || !grad) return fail(LPF_E_INVAL, "lpf_cnn_adam: NULL argument");
+  if (t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(LPF_E_INVAL, "lpf_cnn_adam: t >= 1, lr > 0, 0 <= beta < 1, eps > 0");
+  DeviceGuard g(n->ctx->dev);
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+  hipError_t e = cnn_adam(n->b, grad, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_adam");
+}
+
+void lpf_cnn_destroy(lpf_cnn n) {
+  if (!n) return;
+  {
+    DeviceGuard g(n->ctx->dev);
+    (void)hipDeviceSynchronize();
+    for (void *p : n->allocs) (void)hipFree(p);
+  }
+  delete n;
 }
 
 }  // extern "C"

@@ -141,6 +141,30 @@ hipError_t prepare_delta_kernels(int max_lds_bytes);
 hipError_t launch_step(const StepLaunch &L, hipStream_t stream);
 hipError_t prepare_step_kernels(int max_lds_bytes);
 
+// ---- swap-proposal CNN (k_cnn.hip) ----
+constexpr int kCnnParams = 4961;  // W1 288, b1 16, W2 2304, b2 16, W3 2304, b3 16, W4 16, b4 1
+struct CnnSample {
+  int32_t img, a, b;
+  float y;
+};
+struct CnnBufs {
+  float *prm, *mom, *vel;                        // fp32 parameters and Adam moments
+  uint16_t *Wf, *Wt;                             // bf16 [3][9][16][16] forward / transposed
+  float *W4bf;                                   // head weights rounded to bf16
+  uint16_t *X0, *A1, *A2, *A3, *dZ1, *dZ2, *dZ3;  // channels-last activations and gradients
+  float *S, *r;                                  // scores, residuals
+  int64_t *dS;                                   // score gradient, 2^-40 fixed point
+  float *part1, *part2, *part3, *part_h;         // per-block gradient partials
+};
+hipError_t cnn_forward(const CnnBufs &B, const uint64_t *bits, int W, int H, int batch,
+                       float *S, hipStream_t s);
+hipError_t cnn_grad(const CnnBufs &B, const uint64_t *bits, int W, int H, int batch,
+                    const CnnSample *smp, int n, float *grad, float *loss, hipStream_t s);
+hipError_t cnn_pack(const CnnBufs &B, hipStream_t s);
+hipError_t cnn_adam(const CnnBufs &B, const float *grad, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t s);
+int cnn_conv_blocks(int64_t npix);
+
 // Kernel launchers (defined in k_full.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,

@@ -1,0 +1,146 @@
+"""Swap-proposal CNN kernels (bf16 MFMA) against the float64 oracle on bf16-rounded values."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_04359_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed):
+    p = cnn.unpack(cnn.init_params(seed).astype(np.float64))
+    g = np.random.default_rng(seed)
+    for k in ("b1", "b2", "b3"):
+        p[k] = g.uniform(0.0, 0.2, size=p[k].shape)
+    p["b4"] = np.array([0.1])
+    return cnn.pack(p)
+
+
+def _net(ctx, W, H, batch, nsmp, params):
+    import torch
+    from paper_1601_04359_amd import ProposalNet
+    return ProposalNet(ctx, W, H, batch, nsmp, torch.from_numpy(params).cuda())
+
+
+def _bits(ctx, imgs):
+    import torch
+    return torch.cat([ctx.pack(torch.from_numpy(im).cuda()).reshape(-1) for im in imgs])
+
+
+# Tolerance: activations and weights are bf16 (8 significant bits, relative spacing 2^-8).  The
+# GPU accumulates in fp32 and the oracle in fp64, so a pre-activation within a rounding error of
+# a bf16 rounding boundary can round to the neighbouring bf16 value (one ulp, 2^-8 relative) on
+# one side only; through three layers such flips stay well below 2^-5 of the score scale.
+def _close(got, ref, frac=2.0 ** -5):
+    scale = np.sqrt(np.mean(ref ** 2)) + 1e-12
+    err = np.abs(got - ref)
+    assert np.max(err) <= frac * scale, (np.max(err), scale)
+
+
+@pytest.mark.parametrize("W,H,batch", [(16, 16, 1), (24, 40, 2), (128, 128, 2), (37, 29, 3)])
+def test_forward_matches_oracle(ctx, W, H, batch):
+    print(f"[gpu] cnn forward {W}x{H} batch {batch}", flush=True)
+    prm = _params(1)
+    imgs = [wl.boolean_disks(W, H, 3.0, 0.4, 10 + i) for i in range(batch)]
+    net = _net(ctx, W, H, batch, 8, prm)
+    S = net.forward(_bits(ctx, imgs), batch).cpu().numpy()
+    for i, im in enumerate(imgs):
+        ref = cnn.forward(prm, im)["S"]
+        _close(S[i], ref)
+    net.close()
+
+
+def test_grad_matches_oracle(ctx):
+    import torch
+    from paper_1601_04359_amd import cnn_samples
+    print("[gpu] cnn gradient", flush=True)
+    W = H = 32
+    prm = _params(2)
+    imgs = [wl.boolean_disks(W, H, 3.0, 0.45, 20 + i) for i in range(2)]
+    g = np.random.default_rng(3)
+    n = 300
+    idx = g.integers(0, 2, n)
+    a = g.integers(0, W * H, n)
+    b = g.integers(0, W * H, n)
+    y = g.normal(size=n).astype(np.float32)
+    net = _net(ctx, W, H, 2, n, prm)
+    grad, loss = net.grad(_bits(ctx, imgs), 2, cnn_samples(idx, a, b, y, "cuda"))
+    torch.cuda.synchronize()
+    ref_loss, ref_grad = cnn.loss_and_grad(prm, imgs, np.stack([idx, a, b, y], 1))
+    assert abs(float(loss.cpu()[0]) - ref_loss) <= 2.0 ** -5 * ref_loss
+    got = grad.cpu().numpy().astype(np.float64)
+    for k, off, size in _groups():
+        gk, rk = got[off:off + size], ref_grad[off:off + size]
+        scale = np.sqrt(np.mean(rk ** 2)) + 1e-12
+        assert np.max(np.abs(gk - rk)) <= 2.0 ** -4 * scale + 1e-7, (k, np.max(np.abs(gk - rk)), scale)
+        # direction: cosine similarity of each group
+        cos = np.dot(gk, rk) / (np.linalg.norm(gk) * np.linalg.norm(rk) + 1e-30)
+        assert cos > 0.999, (k, cos)
+    net.close()
+
+
+def _groups():
+    out, o = [], 0
+    for k, s in cnn.SHAPES:
+        n = int(np.prod(s))
+        out.append((k, o, n))
+        o += n
+    return out
+
+
+def test_adam_matches_oracle(ctx):
+    import torch
+    prm = _params(4)
+    net = _net(ctx, 16, 16, 1, 4, prm)
+    g = np.random.default_rng(5)
+    m = np.zeros(cnn.N_PARAMS, np.float32)
+    v = np.zeros(cnn.N_PARAMS, np.float32)
+    p = prm.copy()
+    for t in range(1, 4):
+        grad = g.normal(size=cnn.N_PARAMS).astype(np.float32)
+        net.adam(torch.from_numpy(grad).cuda(), 1e-3)
+        p, m, v = cnn.adam(p, grad, m, v, t, lr=1e-3)
+    got = net.params().cpu().numpy()
+    assert np.allclose(got, p, rtol=1e-6, atol=1e-7)
+    net.close()
+
+
+def test_training_reduces_loss(ctx):
+    # a few Adam steps on a fixed batch lower the loss (end-to-end: forward, backward, update)
+    import torch
+    from paper_1601_04359_amd import cnn_samples
+    W = H = 32
+    prm = _params(6)
+    imgs = [wl.boolean_disks(W, H, 3.0, 0.45, 30 + i) for i in range(2)]
+    g = np.random.default_rng(7)
+    n = 512
+    idx = g.integers(0, 2, n)
+    a = g.integers(0, W * H, n)
+    b = g.integers(0, W * H, n)
+    X = [cnn.features(im) for im in imgs]
+    y = np.array([X[i][a_ // W, a_ % W, 1] - X[i][b_ // W, b_ % W, 1] for i, a_, b_ in zip(idx, a, b)],
+                 np.float32)
+    net = _net(ctx, W, H, 2, n, prm)
+    bits = _bits(ctx, imgs)
+    smp = cnn_samples(idx, a, b, y, "cuda")
+    losses = []
+    for _ in range(60):
+        grad, loss = net.grad(bits, 2, smp)
+        net.adam(grad, 3e-3)
+        losses.append(float(loss.cpu()[0]))
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
+    net.close()
