@@ -47,6 +47,7 @@ extern "C" {
 #endif
 
 typedef struct lpf_ctx_s *lpf_ctx;
+typedef struct lpf_cnn_s *lpf_cnn; /* swap-proposal network, see lpf_cnn_create */
 
 typedef enum {
   LPF_OK = 0,
@@ -150,7 +151,7 @@ typedef struct {
   uint64_t step;
 } lpf_step_result;
 
-enum { LPF_PROP_UNIFORM = 0, LPF_PROP_INTERFACIAL = 1 };
+enum { LPF_PROP_UNIFORM = 0, LPF_PROP_INTERFACIAL = 1, LPF_PROP_LEARNED = 2 };
 
 /* Create an annealing chain on a W x H image (the "cell").  The caller owns and keeps alive:
  *   bits    packed image (device), updated in place by every accepted step;
@@ -184,6 +185,27 @@ lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, 
 lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
                        lpf_step_result *out, void *stream);
 
+/* Learned proposals (LPF_PROP_LEARNED): before each draw the cell is scored, by `net` (an
+ * lpf_cnn for this cell size, run on the current cell) or, when net is NULL, by the caller's
+ * field scores (device, W*H fp32, read at every learned draw).  With probability eps_uniform a
+ * candidate is drawn as LPF_PROP_UNIFORM (random stream word r3); otherwise a is drawn from the
+ * phase-1 pixels with probability proportional to exp(clamp(beta * score[a], -60, 60)) and b
+ * likewise from the phase-0 pixels (inversion of r0, r1 on fp64 prefix sums in pixel-list
+ * order).  The exact energy change still decides acceptance; no proposal-ratio correction is
+ * applied (the chain minimises, it does not sample).  Errors: LPF_E_INVAL. */
+lpf_status lpf_anneal_set_proposal(lpf_anneal st, lpf_cnn net, const float *scores, float beta,
+                                   float eps_uniform);
+
+/* The current step's K candidates as int32 (a, b) pairs into cand (device, [K][2]), without
+ * evaluating them or advancing the chain (a = -1 marks a void interfacial draw). */
+lpf_status lpf_anneal_propose(lpf_anneal st, int K, int proposal, int32_t *cand, void *stream);
+
+/* Exact energy change de[i] (device, double) of n interchanges swaps (device, int32 [n][2]) on
+ * the chain's current state, with the same integer formula as anneal_step (invalid or
+ * same-phase pairs give 0).  Used to label training samples for the proposal network. */
+lpf_status lpf_anneal_delta_energy(lpf_anneal st, const int32_t *swaps, int n, double *de,
+                                   void *stream);
+
 /* Copy the chain's pixel lists to pos (device, int32[W*H]: phase-1 list then phase-0 list) and
  * return, after synchronising the stream, the number of phase-1 pixels and the next step index
  * (host).  With the caller's bits, counts and e this is everything a resumed chain needs. */
@@ -204,7 +226,6 @@ void lpf_anneal_destroy(lpf_anneal st);
  * offset (dy-1, dx-1).  Training loss for samples (image, a, b, y): mean (S[a] + S[b] - y)^2. */
 #define LPF_CNN_PARAMS 4961
 
-typedef struct lpf_cnn_s *lpf_cnn;
 typedef struct {
   int32_t img;  /* index of the image in the batch */
   int32_t a, b; /* linear pixel indices y*W + x */

@@ -10,8 +10,8 @@ import torch
 
 from . import _abi
 from ._abi import (LPF_BOTH, LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1,
-                   LPF_PROP_INTERFACIAL, LPF_PROP_UNIFORM, LpfError, counts_shape,
-                   lpf_num_vectors, lpf_vectors)
+                   LPF_PROP_INTERFACIAL, LPF_PROP_LEARNED, LPF_PROP_UNIFORM, LpfError,
+                   counts_shape, lpf_num_vectors, lpf_vectors)
 
 import numpy as _np
 
@@ -144,6 +144,25 @@ class Anneal:
         for i, T in enumerate(Ts):
             _abi.anneal_step(self.handle, n_candidates, proposal, float(T), recs[i], stream)
         return recs
+
+    def set_proposal(self, net=None, scores: torch.Tensor | None = None, beta: float = 1.0,
+                     eps_uniform: float = 0.1) -> None:
+        """Learned proposals from a ProposalNet (scored on the current cell) or a score field."""
+        self._scores = scores  # keep the caller's field alive
+        self._net = net
+        _abi.lpf_anneal_set_proposal(self.handle, net.handle if net is not None else None,
+                                     scores, beta, eps_uniform)
+
+    def propose(self, K: int, proposal: int = LPF_PROP_UNIFORM, stream=None) -> torch.Tensor:
+        out = torch.empty((K, 2), dtype=torch.int32, device=self.bits.device)
+        _abi.lpf_anneal_propose(self.handle, K, proposal, out, stream)
+        return out
+
+    def delta_energy(self, swaps: torch.Tensor, stream=None) -> torch.Tensor:
+        n = swaps.shape[0]
+        de = torch.empty(n, dtype=torch.float64, device=self.bits.device)
+        _abi.lpf_anneal_delta_energy(self.handle, swaps.contiguous(), n, de, stream)
+        return de
 
     def export(self, stream=None):
         pos = torch.empty(self.W * self.H, dtype=torch.int32, device=self.bits.device)

@@ -74,8 +74,11 @@ _sig("lpf_cnn_adam", _i32, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.
      ctypes.c_float, _P)
 _sig("lpf_cnn_destroy", None, _P)
 LPF_CNN_PARAMS = 4961
+_sig("lpf_anneal_set_proposal", _i32, _P, _P, _P, ctypes.c_float, ctypes.c_float)
+_sig("lpf_anneal_propose", _i32, _P, _i32, _i32, _P, _P)
+_sig("lpf_anneal_delta_energy", _i32, _P, _P, _i32, _P, _P)
 
-LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL = 0, 1
+LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL, LPF_PROP_LEARNED = 0, 1, 2
 
 
 class lpf_image_desc(ctypes.Structure):
@@ -276,3 +279,25 @@ def lpf_cnn_adam(net: int, grad: torch.Tensor, t: int, lr: float, beta1: float =
 
 def lpf_cnn_destroy(net: int) -> None:
     _lib.lpf_cnn_destroy(net)
+
+
+def lpf_anneal_set_proposal(st: int, net: int | None, scores: torch.Tensor | None, beta: float,
+                            eps_uniform: float) -> None:
+    _check(_lib.lpf_anneal_set_proposal(
+        st, net, _dev(scores, torch.float32, "scores") if scores is not None else None,
+        beta, eps_uniform))
+
+
+def lpf_anneal_propose(st: int, K: int, proposal: int, cand: torch.Tensor, stream=None) -> None:
+    if cand.numel() < 2 * K:
+        raise ValueError("lpf_anneal_propose: cand must hold K pairs")
+    _check(_lib.lpf_anneal_propose(st, K, proposal, _dev(cand, torch.int32, "cand"),
+                                   _stream(stream)))
+
+
+def lpf_anneal_delta_energy(st: int, swaps: torch.Tensor, n: int, de: torch.Tensor,
+                            stream=None) -> None:
+    if swaps.numel() != 2 * n or de.numel() < n:
+        raise ValueError("lpf_anneal_delta_energy: sizes")
+    _check(_lib.lpf_anneal_delta_energy(st, _dev(swaps, torch.int32, "swaps"), n,
+                                        _dev(de, torch.float64, "de"), _stream(stream)))

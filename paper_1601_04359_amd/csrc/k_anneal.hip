@@ -50,17 +50,41 @@ __device__ __forceinline__ bool interfacial(const uint64_t *__restrict__ bits, i
 }
 
 // Candidate k of the current step: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
+// proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void unless both pixels are
+// interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn with probability
+// proportional to the weights whose inclusive prefix sums are cw1 (over pos1) and b likewise
+// with cw0 (over pos0), by inversion of r0, r1.
+__device__ __forceinline__ int upper_index(const double *__restrict__ cw, int n, double u) {
+  int lo = 0, hi = n - 1;  // first i with cw[i] > u
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cw[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits,
                           int W, int H, uint64_t seed, int K, int proposal,
-                          int2 *__restrict__ cand, double *__restrict__ U,
+                          const double *__restrict__ cw1, const double *__restrict__ cw0,
+                          double eps, int2 *__restrict__ cand, double *__restrict__ U,
                           int2 *__restrict__ slot) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
   philox4x64_10(c, seed, 0x6c7066ull);
-  const uint64_t n1 = (uint64_t)st->n1, n0 = (uint64_t)st->n0;
-  const int ia = (int)(((c[0] >> 32) * n1) >> 32);
-  const int ib = (int)(((c[1] >> 32) * n0) >> 32);
+  const int n1 = st->n1, n0 = st->n0;
+  int ia, ib;
+  const double u3 = (double)(c[3] >> 11) * (1.0 / 9007199254740992.0);
+  if (proposal == 2 && !(u3 < eps)) {
+    const double ua = (double)(c[0] >> 11) * (1.0 / 9007199254740992.0) * cw1[n1 - 1];
+    const double ub = (double)(c[1] >> 11) * (1.0 / 9007199254740992.0) * cw0[n0 - 1];
+    ia = upper_index(cw1, n1, ua);
+    ib = upper_index(cw0, n0, ub);
+  } else {
+    ia = (int)(((c[0] >> 32) * (uint64_t)n1) >> 32);
+    ib = (int)(((c[1] >> 32) * (uint64_t)n0) >> 32);
+  }
   int a = st->pos1[ia], b = st->pos0[ib];
   if (proposal == 1 && !(interfacial(bits, W, H, a) && interfacial(bits, W, H, b))) {
     a = -1;
@@ -69,6 +93,42 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
   cand[k] = make_int2(a, b);
   slot[k] = make_int2(ia, ib);
   U[k] = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Inclusive prefix sums of w(p) = exp(clamp(beta * score[p], -60, 60)) over the pixel lists
+// pos1 (into cw1) and pos0 (into cw0), in a fixed order (one workgroup: contiguous ranges per
+// thread, then a scan of the range totals).
+__global__ void __launch_bounds__(1024)
+k_learn_weights(const AnnealDev *__restrict__ st, const float *__restrict__ score, double beta,
+                double *__restrict__ cw1, double *__restrict__ cw0) {
+  __shared__ double tot[1024];
+  for (int list = 0; list < 2; ++list) {
+    const int n = list == 0 ? st->n1 : st->n0;
+    const int32_t *pos = list == 0 ? st->pos1 : st->pos0;
+    double *cw = list == 0 ? cw1 : cw0;
+    const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int lo = min(n, per * (int)threadIdx.x), hi = min(n, lo + per);
+    double s = 0.0;
+    for (int i = lo; i < hi; ++i) {
+      const double z = fmin(60.0, fmax(-60.0, beta * (double)score[pos[i]]));
+      s += exp(z);
+      cw[i] = s;
+    }
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double run = 0.0;
+      for (int t = 0; t < (int)blockDim.x; ++t) {
+        const double v = tot[t];
+        tot[t] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    const double off = tot[threadIdx.x];
+    for (int i = lo; i < hi; ++i) cw[i] += off;
+    __syncthreads();
+  }
 }
 
 // Pixel lists in ascending index order (one workgroup; each thread scans a contiguous range).
@@ -119,10 +179,30 @@ __global__ void k_lse(const uint32_t *__restrict__ counts, const uint32_t *__res
 }
 
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
-                          int K, int proposal, int2 *cand, double *U, int2 *slot,
-                          hipStream_t stream) {
+                          int K, int proposal, const double *cw1, const double *cw0, double eps,
+                          int2 *cand, double *U, int2 *slot, hipStream_t stream) {
   hipLaunchKernelGGL(k_propose, dim3((K + 255) / 256), dim3(256), 0, stream, st, bits, W, H, seed,
-                     K, proposal, cand, U, slot);
+                     K, proposal, cw1, cw0, eps, cand, U, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
+                                double *cw0, hipStream_t stream) {
+  hipLaunchKernelGGL(k_learn_weights, dim3(1), dim3(1024), 0, stream, st, score, beta, cw1, cw0);
+  return hipGetLastError();
+}
+
+// Copy of the step's candidates as (a, b) pairs.
+__global__ void k_copy_cand(const int2 *__restrict__ cand, int K, int32_t *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) {
+    out[2 * k] = cand[k].x;
+    out[2 * k + 1] = cand[k].y;
+  }
+}
+
+hipError_t launch_copy_cand(const int2 *cand, int K, int32_t *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_copy_cand, dim3((K + 255) / 256), dim3(256), 0, stream, cand, K, out);
   return hipGetLastError();
 }
 

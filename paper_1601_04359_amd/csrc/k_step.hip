@@ -68,13 +68,13 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
     if (phase_mask & 1) {
       const int64_t L = counts[(size_t)p * nv + dv.idx], T = target[(size_t)p * nv + dv.idx];
       S += (int64_t)d0 * (Nt * ((int64_t)d0 + 2 * L) - 2 * N * T);
-      if (in) dl[((size_t)p * nv + dv.idx) * K + k] = (int16_t)d0;
+      if (in && dl) dl[((size_t)p * nv + dv.idx) * K + k] = (int16_t)d0;
       ++p;
     }
     if (phase_mask & 2) {
       const int64_t L = counts[(size_t)p * nv + dv.idx], T = target[(size_t)p * nv + dv.idx];
       S += (int64_t)d1 * (Nt * ((int64_t)d1 + 2 * L) - 2 * N * T);
-      if (in) dl[((size_t)p * nv + dv.idx) * K + k] = (int16_t)d1;
+      if (in && dl) dl[((size_t)p * nv + dv.idx) * K + k] = (int16_t)d1;
     }
   }
   if (kr < C) S_part[(size_t)c * C + kr] = S;
@@ -187,6 +187,35 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, L.st, L.ctl, L.K, L.cand,
                      L.slot, L.dl, L.nterms, L.N, L.Nt, L.e, L.counts_rw, L.bits_rw, L.W, L.k_sel,
                      L.out);
+  return hipGetLastError();
+}
+
+__global__ void k_energy_sum(const int64_t *__restrict__ S_part, int nchunks, int n, int64_t N,
+                             int64_t Nt, double *__restrict__ de) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t S = 0;
+  for (int c = 0; c < nchunks; ++c) S += S_part[(size_t)c * n + i];
+  de[i] = (double)S / ((double)N * (double)N * (double)Nt);
+}
+
+hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream) {
+  hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, stream, L.ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((L.K + 255) / 256), (unsigned)L.nchunks);
+  if (L.use_lds)
+    hipLaunchKernelGGL(k_round_delta<true>, grid, dim3(256),
+                       (size_t)L.geo.total * sizeof(uint32_t), stream, L.E, L.geo, L.bits, L.W,
+                       L.H, L.cand, L.K, 0, L.K, L.vecs, L.chunk_off, L.runs, L.phase_mask, L.nv,
+                       L.counts, L.target, L.N, L.Nt, L.S_part, (int16_t *)nullptr, L.ctl);
+  else
+    hipLaunchKernelGGL(k_round_delta<false>, grid, dim3(256), 0, stream, L.E, L.geo, L.bits, L.W,
+                       L.H, L.cand, L.K, 0, L.K, L.vecs, L.chunk_off, L.runs, L.phase_mask, L.nv,
+                       L.counts, L.target, L.N, L.Nt, L.S_part, (int16_t *)nullptr, L.ctl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_sum, dim3((L.K + 255) / 256), dim3(256), 0, stream, L.S_part,
+                     L.nchunks, L.K, L.N, L.Nt, de);
   return hipGetLastError();
 }
 

@@ -164,6 +164,11 @@ struct lpf_anneal_s {
   AnnealDev *dev = nullptr;  // device struct
   int32_t *pos = nullptr;    // device, W*H: phase-1 list then phase-0 list (reserved in place)
   DevBuf E3, cand, U, slot, S_part, ksel, dl, ctl;
+  // learned proposals: a network scoring the current cell, or a caller's score field
+  lpf_cnn net = nullptr;
+  const float *scores_ext = nullptr;
+  double beta = 1.0, eps = 0.1;
+  DevBuf scores, cw1, cw0, eS, eCtl;
 };
 
 // A captured lpf_batch launch (extended images, counter reset, persistent kernel).
@@ -480,6 +485,38 @@ int delta_chunks(int K) {
   return std::max(1, 2048 / groups);
 }
 
+// Candidates of the chain's current step into a->cand / U / slot (learned weights first).
+lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s) {
+  hipError_t e;
+  const int64_t N = (int64_t)a->W * a->H;
+  if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
+      (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
+      (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess)
+    return hip_fail(e, "anneal: candidate scratch");
+  const double *cw1 = nullptr, *cw0 = nullptr;
+  if (proposal == LPF_PROP_LEARNED) {
+    if ((e = a->cw1.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+        (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess)
+      return hip_fail(e, "anneal: proposal scratch");
+    const float *sc = a->scores_ext;
+    if (a->net) {
+      if ((e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess)
+        return hip_fail(e, "anneal: score scratch");
+      if ((e = cnn_forward(a->net->b, a->bits, a->W, a->H, 1, (float *)a->scores.p, s)) != hipSuccess)
+        return hip_fail(e, "anneal: proposal network");
+      sc = (const float *)a->scores.p;
+    }
+    if ((e = launch_learn_weights(a->dev, sc, a->beta, (double *)a->cw1.p, (double *)a->cw0.p, s)) != hipSuccess)
+      return hip_fail(e, "anneal: proposal weights");
+    cw1 = (const double *)a->cw1.p;
+    cw0 = (const double *)a->cw0.p;
+  }
+  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cw1, cw0, a->eps,
+                          (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, s)) != hipSuccess)
+    return hip_fail(e, "anneal: propose");
+  return LPF_OK;
+}
+
 lpf_status check_image_args(const char *fn, int W, int H, int cx, int cy, unsigned mask) {
   if (W < 1 || H < 1 || W > 65535 || H > 65535)
     return fail(LPF_E_INVAL, std::string(fn) + ": W/H out of range");
@@ -742,8 +779,11 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
                        void *stream) {
   if (!a) return fail(LPF_E_INVAL, "anneal_step: state is NULL");
   if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, "anneal_step: n_candidates outside [1, 2^20]");
-  if (proposal != LPF_PROP_UNIFORM && proposal != LPF_PROP_INTERFACIAL)
+  if (proposal != LPF_PROP_UNIFORM && proposal != LPF_PROP_INTERFACIAL &&
+      proposal != LPF_PROP_LEARNED)
     return fail(LPF_E_INVAL, "anneal_step: proposal");
+  if (proposal == LPF_PROP_LEARNED && !a->net && !a->scores_ext)
+    return fail(LPF_E_INVAL, "anneal_step: learned proposal without lpf_anneal_set_proposal");
   if (!(T > 0.0)) return fail(LPF_E_INVAL, "anneal_step: T must be > 0");
   if (!out) return fail(LPF_E_INVAL, "anneal_step: out is NULL");
   lpf_ctx c = a->ctx;
@@ -773,9 +813,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   const int64_t N = (int64_t)a->W * a->H;
   if (first && (e = launch_ext3(a->bits, a->W, a->H, plan->geo, E, s)) != hipSuccess)
     return hip_fail(e, "anneal_step: ext3");
-  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cand,
-                          (double *)a->U.p, (int2 *)a->slot.p, s)) != hipSuccess)
-    return hip_fail(e, "anneal_step: propose");
+  if ((st = draw_candidates(a, K, proposal, s)) != LPF_OK) return st;
   StepLaunch L{};
   L.E = E;
   L.geo = plan->geo;
@@ -847,6 +885,11 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->ksel.release();
     a->dl.release();
     a->ctl.release();
+    a->scores.release();
+    a->cw1.release();
+    a->cw0.release();
+    a->eS.release();
+    a->eCtl.release();
   }
   delete a;
 }
@@ -1201,6 +1244,82 @@ void lpf_cnn_destroy(lpf_cnn n) {
     for (void *p : n->allocs) (void)hipFree(p);
   }
   delete n;
+}
+
+lpf_status lpf_anneal_set_proposal(lpf_anneal a, lpf_cnn net, const float *scores, float beta,
+                                   float eps_uniform) {
+  if (!a) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: state is NULL");
+  if (net && (net->W != a->W || net->H != a->H))
+    return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: network built for another cell size");
+  if (!(beta >= 0.f) || !(eps_uniform >= 0.f && eps_uniform <= 1.f))
+    return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: beta >= 0, 0 <= eps_uniform <= 1");
+  a->net = net;
+  a->scores_ext = net ? nullptr : scores;
+  a->beta = beta;
+  a->eps = eps_uniform;
+  return LPF_OK;
+}
+
+lpf_status lpf_anneal_propose(lpf_anneal a, int K, int proposal, int32_t *cand_out, void *stream) {
+  if (!a || !cand_out) return fail(LPF_E_INVAL, "lpf_anneal_propose: NULL argument");
+  if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, "lpf_anneal_propose: K");
+  if (proposal < LPF_PROP_UNIFORM || proposal > LPF_PROP_LEARNED)
+    return fail(LPF_E_INVAL, "lpf_anneal_propose: proposal");
+  if (proposal == LPF_PROP_LEARNED && !a->net && !a->scores_ext)
+    return fail(LPF_E_INVAL, "lpf_anneal_propose: learned proposal without lpf_anneal_set_proposal");
+  std::lock_guard<std::mutex> lk(a->ctx->mu);
+  DeviceGuard g(a->ctx->dev);
+  hipStream_t s = (hipStream_t)stream;
+  lpf_status st = draw_candidates(a, K, proposal, s);
+  if (st != LPF_OK) return st;
+  hipError_t e = launch_copy_cand((const int2 *)a->cand.p, K, cand_out, s);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_anneal_propose");
+}
+
+lpf_status lpf_anneal_delta_energy(lpf_anneal a, const int32_t *swaps, int n, double *de,
+                                   void *stream) {
+  if (!a || (n > 0 && (!swaps || !de))) return fail(LPF_E_INVAL, "lpf_anneal_delta_energy: NULL argument");
+  if (n < 0 || n > (1 << 20)) return fail(LPF_E_INVAL, "lpf_anneal_delta_energy: n");
+  if (n == 0) return LPF_OK;
+  lpf_ctx c = a->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  DeltaPlan *plan = nullptr;
+  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, std::max(1, 2048 / ((n + 255) / 256)), plan);
+  if (st != LPF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  const bool first = a->E3.p == nullptr;
+  if ((e = a->E3.ensure((size_t)plan->geo.total * 4)) != hipSuccess ||
+      (e = a->eS.ensure(sizeof(int64_t) * (size_t)n * plan->nchunks)) != hipSuccess ||
+      (e = a->eCtl.ensure(sizeof(StepCtl))) != hipSuccess)
+    return hip_fail(e, "lpf_anneal_delta_energy: scratch");
+  if (first && (e = launch_ext3(a->bits, a->W, a->H, plan->geo, (uint32_t *)a->E3.p, s)) != hipSuccess)
+    return hip_fail(e, "lpf_anneal_delta_energy: ext3");
+  StepLaunch L{};
+  L.E = (const uint32_t *)a->E3.p;
+  L.geo = plan->geo;
+  L.bits = a->bits;
+  L.W = a->W;
+  L.H = a->H;
+  L.cand = reinterpret_cast<const int2 *>(swaps);
+  L.K = n;
+  L.C = n;
+  L.vecs = plan->vecs;
+  L.chunk_off = plan->chunk_off;
+  L.nchunks = plan->nchunks;
+  L.runs = plan->runs;
+  L.phase_mask = a->mask;
+  L.nv = (int)plan->nv;
+  L.counts = a->counts;
+  L.target = a->target;
+  L.N = (int64_t)a->W * a->H;
+  L.Nt = a->Nt;
+  L.S_part = (int64_t *)a->eS.p;
+  L.ctl = (StepCtl *)a->eCtl.p;
+  L.use_lds = plan->use_lds;
+  e = launch_energy(L, de, s);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_anneal_delta_energy");
 }
 
 }  // extern "C"

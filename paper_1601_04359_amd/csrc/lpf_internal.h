@@ -130,8 +130,14 @@ struct StepResult {
   uint64_t step;
 };
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
-                          int K, int proposal, int2 *cand, double *U, int2 *slot,
-                          hipStream_t stream);
+                          int K, int proposal, const double *cw1, const double *cw0, double eps,
+                          int2 *cand, double *U, int2 *slot, hipStream_t stream);
+hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
+                                double *cw0, hipStream_t stream);
+hipError_t launch_copy_cand(const int2 *cand, int K, int32_t *out, hipStream_t stream);
+// Exact energy change of n given interchanges on a chain's state: S partials per chunk, then
+// de[i] = (sum over chunks) / (N^2 Nt).
+hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream);
 hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,
