@@ -134,6 +134,109 @@ def anneal_bench(args) -> dict:
     return line
 
 
+def learned_bench(args) -> dict:
+    """Learned-proposal annealing vs plain uniform proposals at equal final error: 256 x 256
+    cell, LPF (|dx|,|dy| <= 48, both phases) of a 2048 x 2048 Boolean disk image (phi 0.35,
+    r 6, seed 1605); 4096 candidates per step, T_s = 1e-3 * 0.01^(s/steps).  E* = the plain
+    chain's final error; value = wall time of the learned chain to reach e <= E* (network
+    inference included; training reported separately)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import (Anneal, Context, LPF_PROP_LEARNED, LPF_PROP_UNIFORM,
+                                      ProposalNet, step_records)
+    from paper_1601_04359_amd import learn
+    from oracle import cnn as _cnn_init  # initial weights only (seeded He-uniform)
+
+    dev = torch.device("cuda:0")
+    side, tside, c, K = 256, 2048, 48, 4096
+    nsteps = args.steps
+    ctx = Context(0)
+    tgt_img = wl.anneal_target(tside, 0.35, 6.0, 1605)
+    phi = float(tgt_img.mean())
+    target = ctx.full(ctx.pack(torch.from_numpy(tgt_img).to(dev)), tside, tside, c, c, 3)
+    cell = wl.random_cell(side, side, int(round(phi * side * side)), 1)
+    Ts = 1e-3 * (0.01 ** (1.0 / nsteps)) ** np.arange(nsteps)
+    Nt = tside * tside
+
+    def chain(seed):
+        return Anneal(ctx, ctx.pack(torch.from_numpy(cell).to(dev)), side, side, c, c, 3,
+                      target, Nt, seed)
+
+    # plain chain: defines E*
+    plain = chain(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = step_records(plain.run(K, Ts, LPF_PROP_UNIFORM))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    e_star = float(rp["e"][-1])
+    e0 = float(plain.e.cpu()[0]) if False else float(rp["e"][0] - rp["de"][0])
+    plain.close()
+
+    # training data from an independent plain run, then training
+    t0 = time.perf_counter()
+    src = chain(2)
+    every = max(1, nsteps // args.snapshots)
+    data = learn.collect(src, args.snapshots, every, args.per_snapshot, K, Ts, seed=7)
+    src.close()
+    t_data = time.perf_counter() - t0
+    net = ProposalNet(ctx, side, side, 8, 8 * args.per_snapshot,
+                      torch.from_numpy(_cnn_init.init_params(11)).to(dev))
+    t0 = time.perf_counter()
+    losses = learn.train(net, data, args.train_steps, 8, 2e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # learned chain, timed to the first block whose error reaches E*
+    lch = chain(1)
+    lch.set_proposal(net=net, beta=args.beta, eps_uniform=0.1)
+    recs = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_hit, s_hit = None, None
+    block = 50
+    for s0 in range(0, nsteps, block):
+        for s in range(s0, min(nsteps, s0 + block)):
+            lch.step(K, float(Ts[s]), recs[s], LPF_PROP_LEARNED)
+        torch.cuda.synchronize()
+        r = step_records(recs[s0:min(nsteps, s0 + block)])
+        hit = np.flatnonzero(r["e"] <= e_star)
+        if len(hit):
+            t_hit, s_hit = time.perf_counter() - t0, s0 + int(hit[0])
+            break
+    t_full = time.perf_counter() - t0
+    rl = step_records(recs[: (s_hit + 1) if s_hit is not None else nsteps])
+    lch.close()
+    net.close()
+    ctx.close()
+    value = t_hit if t_hit is not None else float("inf")
+    return {
+        "metric": "anneal time to fixed LPF error",
+        "value": round(value, 3) if t_hit is not None else None,
+        "unit": "s", "n_gpus": 1, "steps": nsteps, "warmup": 0,
+        "ms_per_step": round(value * 1e3 / (s_hit + 1), 3) if s_hit is not None else None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+f64 (CNN bf16/fp32)", "data": "synthetic",
+        "config": {"workload": "learned vs uniform proposals, 256x256 cell, LPF |dx|,|dy|<=48 "
+                               "both phases of a 2048x2048 Boolean disk image (phi 0.35, r 6), "
+                               "4096 candidates/step, T0 1e-3 geometric to 1e-5",
+                   "steps": nsteps, "beta": args.beta, "eps_uniform": 0.1,
+                   "samples": int(len(data.de)), "snapshots": args.snapshots,
+                   "train_steps": args.train_steps},
+        "e_start": e0, "e_star_plain_final": e_star,
+        "plain_s": round(t_plain, 3), "plain_steps": nsteps,
+        "learned_steps_to_e_star": None if s_hit is None else s_hit + 1,
+        "learned_reached": t_hit is not None,
+        "learned_e_at_end": float(rl["e"][-1]),
+        "speedup_vs_plain": None if t_hit is None else round(t_plain / t_hit, 3),
+        "train_s": round(t_train, 2), "data_s": round(t_data, 2),
+        "train_loss_first_last": [losses[0], losses[-1]],
+        "accept_rate_plain": round(float((rp["k"] >= 0).mean()), 4),
+        "accept_rate_learned": round(float((rl["k"] >= 0).mean()), 4),
+    }
+
+
 def batch_bench(args) -> dict:
     """Uneven batch: 256 Boolean disk images, side ~ U{64,128,256,512,1024}, phi ~ U[0.2,0.6],
     r ~ U[3,15], cutoff side/2, both phases; one step = one lpf_batch call (persistent launch,
@@ -208,7 +311,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
-    ap.add_argument("--workload", choices=["full", "anneal", "batch"], default="full")
+    ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned"], default="full")
+    ap.add_argument("--snapshots", type=int, default=256)
+    ap.add_argument("--per-snapshot", type=int, default=4096)
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (5 times) before the timed steps, "
                          "as the reference kernel for HBM byte counters")
@@ -223,6 +330,9 @@ def main() -> int:
         return 0
     if args.workload == "batch":
         print(json.dumps(batch_bench(args)), flush=True)
+        return 0
+    if args.workload == "learned":
+        print(json.dumps(learned_bench(args)), flush=True)
         return 0
 
     import numpy as np
