@@ -146,7 +146,6 @@ def learned_bench(args) -> dict:
     from paper_1601_04359_amd import (Anneal, Context, LPF_PROP_LEARNED, LPF_PROP_UNIFORM,
                                       ProposalNet, step_records)
     from paper_1601_04359_amd import learn
-    from oracle import cnn as _cnn_init  # initial weights only (seeded He-uniform)
 
     dev = torch.device("cuda:0")
     side, tside, c, K = 256, 2048, 48, 4096
@@ -182,7 +181,7 @@ def learned_bench(args) -> dict:
     src.close()
     t_data = time.perf_counter() - t0
     net = ProposalNet(ctx, side, side, 8, 8 * args.per_snapshot,
-                      torch.from_numpy(_cnn_init.init_params(11)).to(dev))
+                      learn.init_params(11, dev))
     t0 = time.perf_counter()
     losses = learn.train(net, data, args.train_steps, 8, 2e-3, seed=3)
     torch.cuda.synchronize()

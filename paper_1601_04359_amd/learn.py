@@ -29,6 +29,23 @@ class Dataset:
     H: int
 
 
+def init_params(seed: int, device) -> torch.Tensor:
+    """Initial network parameters (packed like LPF_CNN_PARAMS): weights uniform in
+    +-sqrt(6 / fan_in) (He initialisation), biases zero, drawn from PCG64(seed)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, shape in ((18, (9, 16, 2)), (0, (16,)), (144, (9, 16, 16)), (0, (16,)),
+                          (144, (9, 16, 16)), (0, (16,)), (16, (16,)), (0, (1,))):
+        if fan_in:
+            lim = np.sqrt(6.0 / fan_in)
+            parts.append(g.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == _abi.LPF_CNN_PARAMS
+    return torch.from_numpy(p).to(device)
+
+
 def unpack_bits(bits: torch.Tensor, W: int, H: int) -> np.ndarray:
     b = bits.detach().cpu().numpy().view(np.uint64).reshape(H, -1)
     out = np.zeros((H, W), np.uint8)
