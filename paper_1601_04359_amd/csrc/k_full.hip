@@ -77,23 +77,69 @@ hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
 
 // Path product of one segment for the lane's R words: A &= t, O |= t over all pixels.
 // XM: x is the major axis.  Q2: the vector has dx < 0 (mirrored in x, shifted by |dx|).
+// Pixels are taken in pairs: two funnel shifts, one 3-input AND (v_bitop3_b32) and one 3-input
+// OR (v_or3_b32) per word; when both pixels of a pair read the same dwords (same row, same
+// word column) the dwords are loaded once.
 template <int R, bool XM, bool Q2>
 __device__ __forceinline__ void path_product(const uint32_t *__restrict__ base, int rst, int adx,
                                              int n, int m, uint32_t (&A)[R], uint32_t (&O)[R]) {
   int err = n, q = 0;
-  for (int k = 0; k <= n; ++k) {
-    if (k) {
-      err += 2 * m;
-      if (err >= 2 * n) {
-        err -= 2 * n;
-        ++q;
-      }
+  auto advance = [&]() {
+    err += 2 * m;
+    if (err >= 2 * n) {
+      err -= 2 * n;
+      ++q;
     }
+  };
+  auto pixel = [&](int k, int &off, int &sh) {
     const int X = XM ? k : q;
     const int Y = XM ? q : k;
     const int px = Q2 ? adx - X : X;
-    const uint32_t *p = base + Y * rst + (px >> 5);
-    const int sh = px & 31;
+    off = Y * rst + (px >> 5);
+    sh = px & 31;
+  };
+  int k = 0;
+  for (; k + 1 <= n; k += 2) {
+    int off0, sh0, off1, sh1;
+    pixel(k, off0, sh0);
+    advance();
+    pixel(k + 1, off1, sh1);
+    advance();
+    const uint32_t *p0 = base + off0;
+    uint32_t t0[R], t1[R];
+    if (off0 == off1) {
+      uint32_t d[R + 1];
+#pragma unroll
+      for (int c = 0; c <= R; ++c) d[c] = p0[c];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        t0[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh0);
+        t1[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh1);
+      }
+    } else {
+      const uint32_t *p1 = base + off1;
+      uint32_t d0[R + 1], d1[R + 1];
+#pragma unroll
+      for (int c = 0; c <= R; ++c) {
+        d0[c] = p0[c];
+        d1[c] = p1[c];
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        t0[i] = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
+        t1[i] = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0[i], t1[i], 0x80);
+      O[i] = O[i] | t0[i] | t1[i];
+    }
+  }
+  if (k == n) {  // odd pixel count: the last pixel alone
+    int off, sh;
+    pixel(k, off, sh);
+    const uint32_t *p = base + off;
     uint32_t d[R + 1];
 #pragma unroll
     for (int c = 0; c <= R; ++c) d[c] = p[c];
