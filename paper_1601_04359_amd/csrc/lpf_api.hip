@@ -241,9 +241,9 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   }
   sh.rst = best;
   int budget = fL ? fL : 64 * 1024;
-  const int slots = sh.wpg * kMaxBin * 2 * 4;  // count slots when the image needs row tiles
   for (;;) {
     int tile;
+    const int slots = sh.wpg * kMaxBin * 2 * 4;  // count slots when the image needs row tiles
     const int rows_all = budget / (sh.rst * 4);
     if (rows_all - cy - rpw >= H) {
       tile = H;
@@ -255,12 +255,12 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
       sh.tile = tile;
       break;
     }
-    if (!fW) sh.wpg = 16;
     if (budget >= kBigLds) {
       why = "cutoff cy too large for on-chip staging of the halo rows";
       return false;
     }
     budget = kBigLds;
+    if (!fW) sh.wpg = 16;  // one group per CU: use all of its waves
   }
   sh.ntiles = (H + sh.tile - 1) / sh.tile;
   sh.lds_rows = sh.tile + cy + rpw;
@@ -271,6 +271,8 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
   FullShape sh{};
   std::string why;
   if (!choose_shape(c, W, H, cx, cy, sh, why)) return fail(LPF_E_UNSUPPORTED, "lpf_full: " + why);
+  if (full_lds_bytes(sh, sh.wpg) > (size_t)kMaxLds)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full: tile shape needs more than 160 KiB of LDS");
   auto key = std::make_tuple(W, H, cx, cy, sh.R * 1000 + sh.S, sh.wpg, sh.tile);
   auto it = c->full_plans.find(key);
   if (it != c->full_plans.end()) {
