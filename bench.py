@@ -28,7 +28,7 @@ P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 # HBM bytes per k_lpf_full launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by the
 # same counters on a 256 MiB copy), profiles/k_lpf_full_512_c128.md.  Valid only for the kernel
 # source the counters were taken on; reported as null once that source changes.
-MEASURED_TRAFFIC = {"src_sha256_16": "00871149f810cf37", "bytes": 2198 * 1024}
+MEASURED_TRAFFIC = {"src_sha256_16": "4987b0f362ee7f9a", "bytes": int(1998.25 * 1024)}
 
 
 def measured_traffic():
