@@ -76,7 +76,9 @@ def cpu_baseline(img, cx, cy, stride=16):
 def anneal_bench(args) -> dict:
     """Reconstruction workload: 128 x 128 cell matching the phase-1 LPF (|dx|,|dy| <= 32) of a
     1024 x 1024 Boolean disk image (phi 0.35, r 6, seed 1604); 4096 uniform interchanges per
-    step, geometric cooling T_s = 1e-3 * 0.01^(s/20000).  One step = one anneal_step call."""
+    step, geometric cooling T_s = 1e-3 * 0.01^(s/20000), 20000 steps.  The fixed error E* is the
+    final error of this plain chain (median over the chains); value = median wall time of a
+    chain's whole schedule, from its creation state to E*."""
     import numpy as np
     import torch
     import workloads as wl
@@ -87,26 +89,39 @@ def anneal_bench(args) -> dict:
     tgt = torch.from_numpy(wl.anneal_target()).to(dev)
     target = ctx.full(ctx.pack(tgt), 1024, 1024, 32, 32, 2)
     cell = wl.random_cell(128, 128, int(round(0.35 * 128 * 128)), 1)
-    bits = ctx.pack(torch.from_numpy(cell).to(dev))
     nsteps = args.steps
-    alpha = 0.01 ** (1.0 / 20000)
-    Ts = 1e-3 * alpha ** np.arange(args.warmup + nsteps)
-    ch = Anneal(ctx, bits, 128, 128, 32, 32, 2, target, 1024 * 1024, seed=1)
-    recs = torch.empty((args.warmup + nsteps, 5), dtype=torch.int64, device=dev)
+    Ts = 1e-3 * (0.01 ** (1.0 / 20000)) ** np.arange(nsteps)
+
+    def chain(seed):
+        return Anneal(ctx, ctx.pack(torch.from_numpy(cell).to(dev)), 128, 128, 32, 32, 2, target,
+                      1024 * 1024, seed=seed)
+
+    warm = chain(1000)
+    warm.run(4096, Ts[:max(1, args.warmup)])
     torch.cuda.synchronize()
-    e0 = float(ch.e.cpu()[0])
-    for i in range(args.warmup):
-        ch.step(4096, float(Ts[i]), recs[i])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + nsteps):
-        ch.step(4096, float(Ts[i]), recs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    r = step_records(recs)
-    fresh = ctx.full(ch.bits, 128, 128, 32, 32, 2)
-    drift_ok = bool(torch.equal(fresh, ch.counts))
-    line = {
+    warm.close()
+    walls, finals, accepted, e0, drift_ok, method = [], [], [], None, True, None
+    for seed in range(1, args.chains + 1):
+        ch = chain(seed)
+        method = ch.method
+        recs = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        e0 = float(ch.e.cpu()[0])
+        t0 = time.perf_counter()
+        for i in range(nsteps):
+            ch.step(4096, float(Ts[i]), recs[i])
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        r = step_records(recs)
+        finals.append(float(r["e"][-1]))
+        accepted.append(int((r["k"] >= 0).sum()))
+        drift_ok &= bool(torch.equal(ctx.full(ch.bits, 128, 128, 32, 32, 2), ch.counts))
+        print(f"  chain {seed}: {walls[-1]:.3f} s, e {e0:.6g} -> {finals[-1]:.6g}", file=sys.stderr,
+              flush=True)
+        ch.close()
+    ctx.close()
+    wall = float(np.median(walls))
+    return {
         "metric": "anneal time to fixed LPF error",
         "value": round(wall, 4),
         "unit": "s",
@@ -120,26 +135,28 @@ def anneal_bench(args) -> dict:
         "dtype": "u32+f64",
         "data": "synthetic",
         "config": {"workload": "SA reconstruction, 128x128 cell, phase-1 LPF |dx|,|dy|<=32 of a "
-                               "1024x1024 Boolean disk image (phi 0.35, r 6), 4096 uniform swaps "
-                               "per step, T0 1e-3, geometric to 1e-5 over 20000 steps",
-                   "steps_timed": nsteps},
+                               "1024x1024 Boolean disk image (phi 0.35, r 6, seed 1604), 4096 "
+                               "uniform swaps per step, T0 1e-3, geometric to 1e-5 over 20000 "
+                               "steps",
+                   "chains": args.chains,
+                   "method": {1: "recount", 2: "records"}.get(method, method)},
         "e_start": e0,
-        "e_final": float(r["e"][-1]),
-        "accepted": int((r["k"] >= 0).sum()),
-        "candidates_per_s": round(4096 * nsteps / wall, 1),
+        "e_star": float(np.median(finals)),
+        "e_final_per_chain": finals,
+        "wall_s_per_chain": [round(w, 4) for w in walls],
+        "accepted_per_chain": accepted,
         "counts_equal_full_recount": drift_ok,
     }
-    ch.close()
-    ctx.close()
-    return line
 
 
 def learned_bench(args) -> dict:
     """Learned-proposal annealing vs plain uniform proposals at equal final error: 256 x 256
     cell, LPF (|dx|,|dy| <= 48, both phases) of a 2048 x 2048 Boolean disk image (phi 0.35,
-    r 6, seed 1605); 4096 candidates per step, T_s = 1e-3 * 0.01^(s/steps).  E* = the plain
-    chain's final error; value = wall time of the learned chain to reach e <= E* (network
-    inference included; training reported separately)."""
+    r 6, seed 1605); 4096 candidates per step, T_s = 1e-3 * 0.01^(s/steps).  E* = median final
+    error of the plain chains; value = median wall time of the learned chains (same seeds and
+    start cell) to the first step with e <= E*, network inference included; the network is
+    trained beforehand on labelled interchanges of an independent plain chain (reported
+    separately)."""
     import numpy as np
     import torch
     import workloads as wl
@@ -157,82 +174,107 @@ def learned_bench(args) -> dict:
     cell = wl.random_cell(side, side, int(round(phi * side * side)), 1)
     Ts = 1e-3 * (0.01 ** (1.0 / nsteps)) ** np.arange(nsteps)
     Nt = tside * tside
+    seeds = list(range(1, args.chains + 1))
+    block = 100
 
     def chain(seed):
         return Anneal(ctx, ctx.pack(torch.from_numpy(cell).to(dev)), side, side, c, c, 3,
                       target, Nt, seed)
 
-    # plain chain: defines E*
-    plain = chain(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rp = step_records(plain.run(K, Ts, LPF_PROP_UNIFORM))
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    e_star = float(rp["e"][-1])
-    e0 = float(plain.e.cpu()[0]) if False else float(rp["e"][0] - rp["de"][0])
-    plain.close()
+    def note(msg):
+        print("  " + msg, file=sys.stderr, flush=True)
 
-    # training data from an independent plain run, then training
+    # plain chains: E*
+    warm = chain(1000)
+    warm.run(K, Ts[:max(1, args.warmup)])
+    torch.cuda.synchronize()
+    warm.close()
+    t_plain, e_plain, acc_plain, e0 = [], [], [], None
+    for sd in seeds:
+        ch = chain(sd)
+        torch.cuda.synchronize()
+        e0 = float(ch.e.cpu()[0])
+        t0 = time.perf_counter()
+        r = step_records(ch.run(K, Ts, LPF_PROP_UNIFORM))
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+        e_plain.append(float(r["e"][-1]))
+        acc_plain.append(float((r["k"] >= 0).mean()))
+        note(f"plain chain {sd}: {t_plain[-1]:.3f} s, e -> {e_plain[-1]:.6g}")
+        ch.close()
+    e_star = float(np.median(e_plain))
+
+    # training data from an independent plain chain, then training
     t0 = time.perf_counter()
-    src = chain(2)
+    src = chain(2000)
     every = max(1, nsteps // args.snapshots)
     data = learn.collect(src, args.snapshots, every, args.per_snapshot, K, Ts, seed=7)
     src.close()
+    torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    net = ProposalNet(ctx, side, side, 8, 8 * args.per_snapshot,
-                      learn.init_params(11, dev))
+    net = ProposalNet(ctx, side, side, 8, 8 * args.per_snapshot, learn.init_params(11, dev))
     t0 = time.perf_counter()
     losses = learn.train(net, data, args.train_steps, 8, 2e-3, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    note(f"data {t_data:.2f} s ({len(data.de)} samples), training {t_train:.2f} s, "
+         f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
 
-    # learned chain, timed to the first block whose error reaches E*
-    lch = chain(1)
-    lch.set_proposal(net=net, beta=args.beta, eps_uniform=0.1)
-    recs = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    t_hit, s_hit = None, None
-    block = 50
-    for s0 in range(0, nsteps, block):
-        for s in range(s0, min(nsteps, s0 + block)):
-            lch.step(K, float(Ts[s]), recs[s], LPF_PROP_LEARNED)
+    # learned chains, each timed to the first step with e <= E*
+    t_hit, s_hit, acc_learned = [], [], []
+    for sd in seeds:
+        ch = chain(sd)
+        ch.set_proposal(net=net, beta=args.beta, eps_uniform=0.1, refresh=args.refresh)
+        recs = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
         torch.cuda.synchronize()
-        r = step_records(recs[s0:min(nsteps, s0 + block)])
-        hit = np.flatnonzero(r["e"] <= e_star)
-        if len(hit):
-            t_hit, s_hit = time.perf_counter() - t0, s0 + int(hit[0])
-            break
-    t_full = time.perf_counter() - t0
-    rl = step_records(recs[: (s_hit + 1) if s_hit is not None else nsteps])
-    lch.close()
+        t0 = time.perf_counter()
+        hit = None
+        for s0 in range(0, nsteps, block):
+            s1 = min(nsteps, s0 + block)
+            for s in range(s0, s1):
+                ch.step(K, float(Ts[s]), recs[s], LPF_PROP_LEARNED)
+            r = step_records(recs[s0:s1])
+            h = np.flatnonzero(r["e"] <= e_star)
+            if len(h):
+                hit = (time.perf_counter() - t0, s0 + int(h[0]) + 1)
+                break
+        t_full = time.perf_counter() - t0
+        rl = step_records(recs[:s1])
+        acc_learned.append(float((rl["k"] >= 0).mean()))
+        t_hit.append(hit[0] if hit else float("inf"))
+        s_hit.append(hit[1] if hit else None)
+        note(f"learned chain {sd}: " + (f"E* at step {hit[1]} after {hit[0]:.3f} s" if hit else
+                                         f"E* not reached in {t_full:.3f} s, e {rl['e'][-1]:.6g}"))
+        ch.close()
     net.close()
     ctx.close()
-    value = t_hit if t_hit is not None else float("inf")
+    value = float(np.median(t_hit))
+    reached = bool(np.isfinite(value))
+    plain_med = float(np.median(t_plain))
     return {
         "metric": "anneal time to fixed LPF error",
-        "value": round(value, 3) if t_hit is not None else None,
-        "unit": "s", "n_gpus": 1, "steps": nsteps, "warmup": 0,
-        "ms_per_step": round(value * 1e3 / (s_hit + 1), 3) if s_hit is not None else None,
+        "value": round(value, 4) if reached else None,
+        "unit": "s", "n_gpus": 1, "steps": nsteps, "warmup": args.warmup,
+        "ms_per_step": None,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32+f64 (CNN bf16/fp32)", "data": "synthetic",
         "config": {"workload": "learned vs uniform proposals, 256x256 cell, LPF |dx|,|dy|<=48 "
-                               "both phases of a 2048x2048 Boolean disk image (phi 0.35, r 6), "
-                               "4096 candidates/step, T0 1e-3 geometric to 1e-5",
-                   "steps": nsteps, "beta": args.beta, "eps_uniform": 0.1,
+                               "both phases of a 2048x2048 Boolean disk image (phi 0.35, r 6, "
+                               "seed 1605), 4096 candidates/step, T0 1e-3 geometric to 1e-5",
+                   "schedule_steps": nsteps, "chains": len(seeds), "beta": args.beta,
+                   "eps_uniform": 0.1, "refresh": args.refresh,
                    "samples": int(len(data.de)), "snapshots": args.snapshots,
                    "train_steps": args.train_steps},
-        "e_start": e0, "e_star_plain_final": e_star,
-        "plain_s": round(t_plain, 3), "plain_steps": nsteps,
-        "learned_steps_to_e_star": None if s_hit is None else s_hit + 1,
-        "learned_reached": t_hit is not None,
-        "learned_e_at_end": float(rl["e"][-1]),
-        "speedup_vs_plain": None if t_hit is None else round(t_plain / t_hit, 3),
+        "e_start": e0, "e_star": e_star,
+        "plain_s_median": round(plain_med, 4),
+        "plain_s_per_chain": [round(t, 4) for t in t_plain],
+        "learned_s_per_chain": [round(t, 4) if np.isfinite(t) else None for t in t_hit],
+        "learned_steps_to_e_star": s_hit,
+        "speedup_vs_plain": round(plain_med / value, 3) if reached else None,
         "train_s": round(t_train, 2), "data_s": round(t_data, 2),
         "train_loss_first_last": [losses[0], losses[-1]],
-        "accept_rate_plain": round(float((rp["k"] >= 0).mean()), 4),
-        "accept_rate_learned": round(float((rl["k"] >= 0).mean()), 4),
+        "accept_rate_plain": [round(a, 4) for a in acc_plain],
+        "accept_rate_learned": [round(a, 4) for a in acc_learned],
     }
 
 
@@ -306,7 +348,8 @@ def batch_bench(args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 20000 annealing steps for anneal/learned)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
@@ -314,11 +357,16 @@ def main() -> int:
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
     ap.add_argument("--train-steps", type=int, default=400)
-    ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--beta", type=float, default=3.0)
+    ap.add_argument("--refresh", type=int, default=1,
+                    help="learned draws between re-scorings of the cell")
+    ap.add_argument("--chains", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (5 times) before the timed steps, "
                          "as the reference kernel for HBM byte counters")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 20000 if args.workload in ("anneal", "learned") else 20
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is a design note, not an implemented path)", file=sys.stderr)

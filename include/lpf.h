@@ -166,8 +166,10 @@ enum { LPF_PROP_UNIFORM = 0, LPF_PROP_INTERFACIAL = 1, LPF_PROP_LEARNED = 2 };
  *   candidate k of step s uses Philox-4x64-10 with counter {s, k, 0, 0} and key {seed, 0x6c7066}:
  *   a = pos1[(r0>>32)*n1 >> 32], b = pos0[(r1>>32)*n0 >> 32], U = (r2>>11) * 2^-53.
  * Requires an image with both phases present; same W, H, cx, cy, phase_mask rules as lpf_full,
- * and max(cx, cy) <= 16383.
- * Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
+ * and max(cx, cy) <= 16383.  Energy changes are exact int64 sums: creation fails with
+ * LPF_E_UNSUPPORTED when nph * |D_c| * d * Nt * (d + 4 W H), d = 2 (max(cx, cy) + 1), exceeds
+ * 2^63 - 1 (e.g. a 256 x 256 cell, cutoff 48, both phases, Nt = 2048^2 gives 1.0e18).
+ * Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE, LPF_E_UNSUPPORTED. */
 lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, int cy,
                              unsigned phase_mask, uint32_t *counts, const uint32_t *target,
                              int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
@@ -177,9 +179,10 @@ lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, 
  * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),
  * compute each one's exact energy change de against the current state, and apply the first, in
  * draw order, with de <= 0 or U < exp(-de/T) (the Metropolis rule for a minimisation).  The
- * candidates are evaluated in rounds of 512 in draw order and rounds after an acceptance are
- * skipped, which gives the same result as evaluating all of them.  The step's record is written
- * to *out (device).  Everything stays on the device.
+ * candidates are evaluated in rounds in draw order (64, 64, 128, 256, ... candidates, at most
+ * 8192 per round) and rounds after an acceptance are skipped, which gives the same result as
+ * evaluating all of them.  The step's record is written to *out (device).  Everything stays on
+ * the device.
  * Errors: LPF_E_INVAL (n_candidates outside [1, 2^20], proposal, T <= 0), LPF_E_NOMEM,
  * LPF_E_DEVICE. */
 lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
@@ -192,9 +195,13 @@ lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
  * phase-1 pixels with probability proportional to exp(clamp(beta * score[a], -60, 60)) and b
  * likewise from the phase-0 pixels (inversion of r0, r1 on fp64 prefix sums in pixel-list
  * order).  The exact energy change still decides acceptance; no proposal-ratio correction is
- * applied (the chain minimises, it does not sample).  Errors: LPF_E_INVAL. */
+ * applied (the chain minimises, it does not sample).  refresh >= 1: the scores and prefix sums
+ * are recomputed at the first learned draw and then every `refresh` learned draws (steps or
+ * lpf_anneal_propose calls); in between, the pixel-list slots keep the weights of the last
+ * scoring (an interchange leaves both slots' old weights in place), which only changes which
+ * candidates are proposed, never how they are judged.  Errors: LPF_E_INVAL. */
 lpf_status lpf_anneal_set_proposal(lpf_anneal st, lpf_cnn net, const float *scores, float beta,
-                                   float eps_uniform);
+                                   float eps_uniform, int refresh);
 
 /* The current step's K candidates as int32 (a, b) pairs into cand (device, [K][2]), without
  * evaluating them or advancing the chain (a = -1 marks a void interfacial draw). */
@@ -205,6 +212,24 @@ lpf_status lpf_anneal_propose(lpf_anneal st, int K, int proposal, int32_t *cand,
  * same-phase pairs give 0).  Used to label training samples for the proposal network. */
 lpf_status lpf_anneal_delta_energy(lpf_anneal st, const int32_t *swaps, int n, double *de,
                                    void *stream);
+
+/* How a chain evaluates candidates; every method gives the same exact integer changes.
+ *   LPF_DELTA_RECOUNT  recount the placements through the two pixels from the image (no state
+ *                      beyond three copies of the image; cost grows with the square of the
+ *                      segment length per vector and candidate);
+ *   LPF_DELTA_RECORDS  keep, for every pixel q, the state of every placement whose segment
+ *                      passes through q (bits [ones == 0], [ones == 1], [ones == n], [ones == n+1]
+ *                      of its phase-1 pixel count) plus the counts themselves, so that a
+ *                      candidate reads two contiguous records; memory W*H*(4*nph*sum(n_v+1)/32
+ *                      + |D_c|) bytes, requires max(cx, cy) <= 254;
+ *   LPF_DELTA_AUTO     (default) records when they fit in 16 GiB and in half the free device
+ *                      memory, else recount.
+ * Errors: LPF_E_INVAL, LPF_E_UNSUPPORTED (records for a cutoff above 254 or a too large cell). */
+enum { LPF_DELTA_AUTO = 0, LPF_DELTA_RECOUNT = 1, LPF_DELTA_RECORDS = 2 };
+lpf_status lpf_anneal_set_method(lpf_anneal st, int method);
+
+/* The method the chain's next step uses (LPF_DELTA_RECOUNT or LPF_DELTA_RECORDS), -1 on error. */
+int lpf_anneal_get_method(lpf_anneal st);
 
 /* Copy the chain's pixel lists to pos (device, int32[W*H]: phase-1 list then phase-0 list) and
  * return, after synchronising the stream, the number of phase-1 pixels and the next step index

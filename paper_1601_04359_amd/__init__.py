@@ -9,7 +9,8 @@ from __future__ import annotations
 import torch
 
 from . import _abi
-from ._abi import (LPF_BOTH, LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1,
+from ._abi import (LPF_BOTH, LPF_DELTA_AUTO, LPF_DELTA_RECORDS, LPF_DELTA_RECOUNT,
+                   LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1,
                    LPF_PROP_INTERFACIAL, LPF_PROP_LEARNED, LPF_PROP_UNIFORM, LpfError,
                    counts_shape, lpf_num_vectors, lpf_vectors)
 
@@ -146,12 +147,21 @@ class Anneal:
         return recs
 
     def set_proposal(self, net=None, scores: torch.Tensor | None = None, beta: float = 1.0,
-                     eps_uniform: float = 0.1) -> None:
-        """Learned proposals from a ProposalNet (scored on the current cell) or a score field."""
+                     eps_uniform: float = 0.1, refresh: int = 1) -> None:
+        """Learned proposals from a ProposalNet (scored on the current cell) or a score field,
+        re-scored every `refresh` learned draws."""
         self._scores = scores  # keep the caller's field alive
         self._net = net
         _abi.lpf_anneal_set_proposal(self.handle, net.handle if net is not None else None,
-                                     scores, beta, eps_uniform)
+                                     scores, beta, eps_uniform, refresh)
+
+    def set_method(self, method: int) -> None:
+        """Candidate evaluation method: LPF_DELTA_AUTO, LPF_DELTA_RECOUNT or LPF_DELTA_RECORDS."""
+        _abi.lpf_anneal_set_method(self.handle, method)
+
+    @property
+    def method(self) -> int:
+        return _abi.lpf_anneal_get_method(self.handle)
 
     def propose(self, K: int, proposal: int = LPF_PROP_UNIFORM, stream=None) -> torch.Tensor:
         out = torch.empty((K, 2), dtype=torch.int32, device=self.bits.device)

@@ -26,6 +26,7 @@ LPF_E_DEVICE = -5
 LPF_E_UNSUPPORTED = -95
 LPF_PHASE0, LPF_PHASE1, LPF_BOTH = 1, 2, 3
 LPF_OUT_HALF, LPF_OUT_GRID = 0, 1
+LPF_DELTA_AUTO, LPF_DELTA_RECOUNT, LPF_DELTA_RECORDS = 0, 1, 2
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_uint64
@@ -74,9 +75,11 @@ _sig("lpf_cnn_adam", _i32, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.
      ctypes.c_float, _P)
 _sig("lpf_cnn_destroy", None, _P)
 LPF_CNN_PARAMS = 4961
-_sig("lpf_anneal_set_proposal", _i32, _P, _P, _P, ctypes.c_float, ctypes.c_float)
+_sig("lpf_anneal_set_proposal", _i32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _i32)
 _sig("lpf_anneal_propose", _i32, _P, _i32, _i32, _P, _P)
 _sig("lpf_anneal_delta_energy", _i32, _P, _P, _i32, _P, _P)
+_sig("lpf_anneal_set_method", _i32, _P, _i32)
+_sig("lpf_anneal_get_method", _i32, _P)
 
 LPF_PROP_UNIFORM, LPF_PROP_INTERFACIAL, LPF_PROP_LEARNED = 0, 1, 2
 
@@ -282,10 +285,10 @@ def lpf_cnn_destroy(net: int) -> None:
 
 
 def lpf_anneal_set_proposal(st: int, net: int | None, scores: torch.Tensor | None, beta: float,
-                            eps_uniform: float) -> None:
+                            eps_uniform: float, refresh: int = 1) -> None:
     _check(_lib.lpf_anneal_set_proposal(
         st, net, _dev(scores, torch.float32, "scores") if scores is not None else None,
-        beta, eps_uniform))
+        beta, eps_uniform, refresh))
 
 
 def lpf_anneal_propose(st: int, K: int, proposal: int, cand: torch.Tensor, stream=None) -> None:
@@ -301,3 +304,14 @@ def lpf_anneal_delta_energy(st: int, swaps: torch.Tensor, n: int, de: torch.Tens
         raise ValueError("lpf_anneal_delta_energy: sizes")
     _check(_lib.lpf_anneal_delta_energy(st, _dev(swaps, torch.int32, "swaps"), n,
                                         _dev(de, torch.float64, "de"), _stream(stream)))
+
+
+def lpf_anneal_set_method(st: int, method: int) -> None:
+    _check(_lib.lpf_anneal_set_method(st, method))
+
+
+def lpf_anneal_get_method(st: int) -> int:
+    m = _lib.lpf_anneal_get_method(st)
+    if m < 0:
+        raise LpfError(LPF_E_INVAL, _lib.lpf_last_error().decode())
+    return m

@@ -68,9 +68,16 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
                           int W, int H, uint64_t seed, int K, int proposal,
                           const double *__restrict__ cw1, const double *__restrict__ cw0,
                           double eps, int2 *__restrict__ cand, double *__restrict__ U,
-                          int2 *__restrict__ slot) {
+                          int2 *__restrict__ slot, int64_t *__restrict__ S_acc,
+                          StepCtl *__restrict__ ctl) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ctl && k == 0) {  // the step's control block and energy sums start at zero
+    ctl->done = 0;
+    ctl->ks = -1;
+    ctl->S = 0;
+  }
   if (k >= K) return;
+  if (S_acc) S_acc[k] = 0;
   uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
   philox4x64_10(c, seed, 0x6c7066ull);
   const int n1 = st->n1, n0 = st->n0;
@@ -96,39 +103,84 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
 }
 
 // Inclusive prefix sums of w(p) = exp(clamp(beta * score[p], -60, 60)) over the pixel lists
-// pos1 (into cw1) and pos0 (into cw0), in a fixed order (one workgroup: contiguous ranges per
-// thread, then a scan of the range totals).
-__global__ void __launch_bounds__(1024)
-k_learn_weights(const AnnealDev *__restrict__ st, const float *__restrict__ score, double beta,
-                double *__restrict__ cw1, double *__restrict__ cw0) {
-  __shared__ double tot[1024];
-  for (int list = 0; list < 2; ++list) {
-    const int n = list == 0 ? st->n1 : st->n0;
-    const int32_t *pos = list == 0 ? st->pos1 : st->pos0;
-    double *cw = list == 0 ? cw1 : cw0;
-    const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int lo = min(n, per * (int)threadIdx.x), hi = min(n, lo + per);
-    double s = 0.0;
-    for (int i = lo; i < hi; ++i) {
-      const double z = fmin(60.0, fmax(-60.0, beta * (double)score[pos[i]]));
-      s += exp(z);
-      cw[i] = s;
-    }
-    tot[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double run = 0.0;
-      for (int t = 0; t < (int)blockDim.x; ++t) {
-        const double v = tot[t];
-        tot[t] = run;
-        run += v;
-      }
-    }
-    __syncthreads();
-    const double off = tot[threadIdx.x];
-    for (int i = lo; i < hi; ++i) cw[i] += off;
-    __syncthreads();
+// pos1 (into cw1) and pos0 (into cw0), in a fixed order: scans of 1024-entry blocks
+// (k_learn_block), a scan of the block totals (k_learn_scan), block offsets added (k_learn_add).
+// Blocks (b, list) past the list's length exit at once.
+__device__ __forceinline__ double block_scan_1024(double x, double *wtot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
+  if (lane == 63) wtot[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    double t = lane < 16 ? wtot[lane] : 0.0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const double y = __shfl_up(t, o);
+      if (lane >= o) t += y;
+    }
+    if (lane < 16) wtot[lane] = t;
+  }
+  __syncthreads();
+  return x + (wave ? wtot[wave - 1] : 0.0);
+}
+
+__global__ void __launch_bounds__(1024)
+k_learn_block(const AnnealDev *__restrict__ st, const float *__restrict__ score, double beta,
+              double *__restrict__ cw1, double *__restrict__ cw0, double *__restrict__ bsum,
+              int nb) {
+  __shared__ double wtot[16];
+  const int list = blockIdx.y;
+  const int n = list == 0 ? st->n1 : st->n0;
+  const int64_t i0 = (int64_t)blockIdx.x * 1024;
+  if (i0 >= n) return;
+  const int32_t *pos = list == 0 ? st->pos1 : st->pos0;
+  double *cw = list == 0 ? cw1 : cw0;
+  const int64_t i = i0 + threadIdx.x;
+  double w = 0.0;
+  if (i < n) w = exp(fmin(60.0, fmax(-60.0, beta * (double)score[pos[i]])));
+  const double incl = block_scan_1024(w, wtot);
+  if (i < n) cw[i] = incl;
+  if (threadIdx.x == 1023) bsum[(size_t)list * nb + blockIdx.x] = incl;
+}
+
+// Exclusive scan of the block totals of one list (one wave per list): contiguous ranges per
+// lane, then a scan of the lane totals.
+__global__ void __launch_bounds__(64)
+k_learn_scan(const AnnealDev *__restrict__ st, const double *__restrict__ bsum,
+             double *__restrict__ boff, int nb) {
+  const int list = blockIdx.x;
+  const int n = list == 0 ? st->n1 : st->n0;
+  const int m = (n + 1023) / 1024;
+  const int lane = threadIdx.x;
+  const int per = (m + 63) / 64;
+  const int lo = min(m, per * lane), hi = min(m, lo + per);
+  const double *bs = bsum + (size_t)list * nb;
+  double *bo = boff + (size_t)list * nb;
+  double s = 0.0;
+  for (int b = lo; b < hi; ++b) s += bs[b];
+  double x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  double run = x - s;
+  for (int b = lo; b < hi; ++b) {
+    bo[b] = run;
+    run += bs[b];
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+k_learn_add(const AnnealDev *__restrict__ st, double *__restrict__ cw1, double *__restrict__ cw0,
+            const double *__restrict__ boff, int nb) {
+  const int list = blockIdx.y;
+  const int n = list == 0 ? st->n1 : st->n0;
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (blockIdx.x == 0 || i >= n) return;
+  double *cw = list == 0 ? cw1 : cw0;
+  cw[i] += boff[(size_t)list * nb + blockIdx.x];
 }
 
 // Pixel lists in ascending index order (one workgroup; each thread scans a contiguous range).
@@ -180,15 +232,25 @@ __global__ void k_lse(const uint32_t *__restrict__ counts, const uint32_t *__res
 
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
-                          int2 *cand, double *U, int2 *slot, hipStream_t stream) {
+                          int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
+                          hipStream_t stream) {
   hipLaunchKernelGGL(k_propose, dim3((K + 255) / 256), dim3(256), 0, stream, st, bits, W, H, seed,
-                     K, proposal, cw1, cw0, eps, cand, U, slot);
+                     K, proposal, cw1, cw0, eps, cand, U, slot, S_acc, ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
-                                double *cw0, hipStream_t stream) {
-  hipLaunchKernelGGL(k_learn_weights, dim3(1), dim3(1024), 0, stream, st, score, beta, cw1, cw0);
+                                double *cw0, int64_t N, double *scratch, hipStream_t stream) {
+  const int nb = (int)((N + 1023) / 1024);
+  double *bsum = scratch, *boff = scratch + 2 * (size_t)nb;
+  hipLaunchKernelGGL(k_learn_block, dim3((unsigned)nb, 2), dim3(1024), 0, stream, st, score, beta,
+                     cw1, cw0, bsum, nb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_learn_scan, dim3(2), dim3(64), 0, stream, st, bsum, boff, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_learn_add, dim3((unsigned)nb, 2), dim3(1024), 0, stream, st, cw1, cw0, boff,
+                     nb);
   return hipGetLastError();
 }
 

@@ -1,0 +1,305 @@
+// Placement-state records: exact evaluation of interchange candidates by reading two
+// contiguous records per candidate (the annealer's evaluation method when they fit in memory).
+//
+// For vector v and placement x let ones(v, x) be the number of phase-1 pixels on x + path(v)
+// (n + 1 pixels).  x counts for phase 1 iff ones = n + 1 and for phase 0 iff ones = 0 (Sec. 2.2
+// definition).  An interchange of a (phase 1 -> 0) and b (phase 0 -> 1) lowers ones by one on
+// P_a = {a - p_k} and raises it by one on P_b, and leaves P_a ∩ P_b unchanged, so
+//   dL1(v) = #{x in P_b \ P_a : ones = n} - #{x in P_a \ P_b : ones = n + 1},
+//   dL0(v) = #{x in P_a \ P_b : ones = 1} - #{x in P_b \ P_a : ones = 0}.
+// The record of pixel q stores, at bit off(v) + k, the state of placement q - p_k: plane A
+// ([ones == 1] for phase 0, [ones == n + 1] for phase 1) and plane B ([ones == 0], [ones == n]).
+// A candidate therefore reads plane A of a and plane B of b over [off(v), off(v) + n] for every
+// v: a contiguous, coalesced read of 2 * nph * sum(n + 1) bits, with lanes running over vectors.
+// Placements in P_a ∩ P_b (only when a and b are within the vector's reach) are taken out of
+// both sums with a membership test on the digitised path.  After an accepted interchange the
+// ones field is updated on P_a and P_b, and record bits flip only where a placement's state
+// changed.
+#include "step_dev.h"
+
+namespace lpf {
+
+namespace {
+
+__device__ __forceinline__ int wrapi(int v, int n) {  // v in (-n, 2n)
+  v += v < 0 ? n : 0;
+  v -= v >= n ? n : 0;
+  return v;
+}
+
+__device__ __forceinline__ int pix_dx(int32_t p) { return (int)(int16_t)(p & 0xffff); }
+__device__ __forceinline__ int pix_dy(int32_t p) { return p >> 16; }
+
+__device__ __forceinline__ int image_bit(const uint64_t *__restrict__ bits, int wpr, int x, int y) {
+  return (int)((bits[(size_t)y * wpr + (x >> 6)] >> (x & 63)) & 1ull);
+}
+
+// Number of set bits j of `plane` with off <= j < off + len.
+__device__ __forceinline__ int popcount_range(const uint32_t *__restrict__ plane, int off, int len) {
+  int c = 0;
+  for (int s = 0; s < len; s += 32) {
+    const int j = off + s;
+    const int w = j >> 5;
+    uint32_t x = __builtin_amdgcn_alignbit(plane[w + 1], plane[w], (uint32_t)(j & 31));
+    const int l = len - s;
+    if (l < 32) x &= (1u << l) - 1u;
+    c += __popc(x);
+  }
+  return c;
+}
+
+__device__ __forceinline__ int plane_bit(const uint32_t *__restrict__ plane, int j) {
+  return (int)((plane[j >> 5] >> (j & 31)) & 1u);
+}
+
+// Is (rx, ry), taken modulo (W, H), a pixel of the digitised path of v = (dx, dy) (n = max
+// extent, dy >= 0)?  The path is the segment's pixel set of Sec. 2.2 with the minor coordinate
+// sgn(m) floor((2 i |m| + n) / (2 n)), i = 0..n, of the major step i; its extents are below
+// (W, H), so the residues are unique.
+__device__ __forceinline__ bool on_path(int rx, int ry, int dx, int dy, int n, int W, int H) {
+  int rxm = rx % W;
+  rxm += rxm < 0 ? W : 0;
+  int rym = ry % H;
+  rym += rym < 0 ? H : 0;
+  const int adx = dx < 0 ? -dx : dx;
+  if (adx >= dy) {  // major axis x (also v = 0)
+    const int i = dx >= 0 ? rxm : (rxm ? W - rxm : 0);
+    if (i > n) return false;
+    const int f = n ? (int)((2ll * i * dy + n) / (2ll * n)) : 0;
+    return rym == f;
+  }
+  const int i = rym;
+  if (i > n) return false;
+  const int g = (int)((2ll * i * adx + n) / (2ll * n));
+  const int gx = dx < 0 ? (g ? W - g : 0) : g;
+  return rxm == gx;
+}
+
+// Is some residue of d modulo M within [-r, r]?
+__device__ __forceinline__ bool within(int d, int M, int r) {
+  int m = d % M;
+  m += m < 0 ? M : 0;
+  return m <= r || M - m <= r;
+}
+
+// The plane conditions: side 0 (A) / 1 (B), phase 0 / 1.
+__device__ __forceinline__ bool plane_cond(int side, int phase, int o, int n) {
+  return side == 0 ? (phase ? o == n + 1 : o == 1) : (phase ? o == n : o == 0);
+}
+
+__device__ __forceinline__ int slot_phase(int p, int nph, unsigned mask) {
+  return nph == 2 ? p : (mask == 2u ? 1 : 0);
+}
+
+}  // namespace
+
+// ones(v, x) for every vector and placement: lanes over placements, one vector per block row.
+__global__ void __launch_bounds__(256)
+k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
+  const int v = blockIdx.x;
+  const int64_t N = (int64_t)g.W * g.H;
+  const int64_t x = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int4 m = g.meta[v];
+  const int wpr = (g.W + 63) >> 6;
+  const int py = (int)(x / g.W), px = (int)(x - (int64_t)py * g.W);
+  int o = 0;
+  for (int k = 0; k <= m.y; ++k) {
+    const int32_t p = g.pix[m.x + k];
+    o += image_bit(bits, wpr, wrapi(px + pix_dx(p), g.W), wrapi(py + pix_dy(p), g.H));
+  }
+  g.ones[(size_t)v * N + x] = (uint8_t)o;
+}
+
+// Records of 64 pixels (one wave) over one 32-dword tile of the record per workgroup, staged in
+// LDS so that each pixel's record is written with contiguous stores.
+__global__ void __launch_bounds__(64)
+k_rec_build(RecGeo g) {
+  const int32_t *__restrict__ vbit = g.vbit;
+  const unsigned mask = g.mask;
+  __shared__ uint32_t tile[4][64][33];
+  const int64_t N = (int64_t)g.W * g.H;
+  const int lane = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * 64;
+  const int64_t q = q0 + lane;
+  const bool valid = q < N;
+  const int qy = valid ? (int)(q / g.W) : 0, qx = valid ? (int)(q - (int64_t)qy * g.W) : 0;
+  const int nplanes = 2 * g.nph;
+  const int w0 = blockIdx.y * 32;
+  const int nw = min(32, g.Rw - w0);
+  for (int wd = 0; wd < nw; ++wd) {
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+    for (int t = 0; t < 32; ++t) {
+      const int j = (w0 + wd) * 32 + t;
+      if (j >= g.Mc) break;
+      const int v = vbit[j];
+      const int n = g.meta[v].y;
+      const int32_t p = g.pix[j];
+      const int xx = wrapi(qx - pix_dx(p), g.W), yy = wrapi(qy - pix_dy(p), g.H);
+      const int o = valid ? (int)g.ones[(size_t)v * N + (size_t)yy * g.W + xx] : -1;
+      for (int pl = 0; pl < nplanes; ++pl) {
+        const int side = pl / g.nph, ph = slot_phase(pl % g.nph, g.nph, mask);
+        acc[pl] |= (plane_cond(side, ph, o, n) ? 1u : 0u) << t;
+      }
+    }
+    for (int pl = 0; pl < nplanes; ++pl) tile[pl][lane][wd] = acc[pl];
+  }
+  __syncthreads();
+  for (int pq = 0; pq < 64 && q0 + pq < N; ++pq) {
+    uint32_t *R = g.rec + (size_t)(q0 + pq) * g.rstride + w0;
+    if (lane < nw)
+      for (int pl = 0; pl < nplanes; ++pl) R[(size_t)pl * g.Rw + lane] = tile[pl][pq][lane];
+  }
+}
+
+// Exact dL of interchange (a, b) for vector v, one entry per kept phase.  Invalid or same-phase
+// pairs change nothing.
+__device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__restrict__ bits,
+                                          int a, int b, int v, int (&d)[2]) {
+  d[0] = 0;
+  d[1] = 0;
+  const int64_t N = (int64_t)g.W * g.H;
+  if (a < 0 || b < 0 || a >= N || b >= N || a == b || v >= g.nv) return;
+  const int wpr = (g.W + 63) >> 6;
+  int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
+  const int va = image_bit(bits, wpr, ax, ay), vb = image_bit(bits, wpr, bx, by);
+  if (va == vb) return;
+  if (va == 0) {  // a leaves phase 1, b enters it
+    int t = a; a = b; b = t;
+    t = ax; ax = bx; bx = t;
+    t = ay; ay = by; by = t;
+  }
+  const unsigned mask = g.mask;
+  const int4 m = g.meta[v];
+  const int off = m.x, n = m.y, len = n + 1;
+  const uint32_t *RA = g.rec + (size_t)a * g.rstride;                // planes A of a
+  const uint32_t *RB = g.rec + (size_t)b * g.rstride + g.nph * g.Rw;  // planes B of b
+  for (int p = 0; p < g.nph; ++p) {
+    const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
+    const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
+    d[p] = slot_phase(p, g.nph, mask) ? cB - cA : cA - cB;
+  }
+  // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k on the path
+  const int DX = bx - ax, DY = by - ay;
+  if (within(DX, g.W, m.z < 0 ? -m.z : m.z) && within(DY, g.H, m.w)) {
+    const uint32_t *RBa = g.rec + (size_t)a * g.rstride + g.nph * g.Rw;  // planes B of a
+    for (int kk = 0; kk <= n; ++kk) {
+      const int32_t p = g.pix[off + kk];
+      if (!on_path(DX + pix_dx(p), DY + pix_dy(p), m.z, m.w, n, g.W, g.H)) continue;
+      for (int s = 0; s < g.nph; ++s)
+        d[s] -= slot_phase(s, g.nph, mask) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
+                                           : plane_bit(RA + (size_t)s * g.Rw, off + kk);
+    }
+  }
+}
+
+// One round: block (vector block, candidate slot); the slots stride over the round's candidates.
+// Lanes run over vectors; the candidate is uniform.  Each block adds its part of a candidate's
+// energy sum into S_acc[k] and stores the candidate's dL when dl is given.
+__global__ void __launch_bounds__(256)
+k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict__ cand, int K,
+            int k0, int C, const uint32_t *__restrict__ counts,
+            const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
+            int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
+            const StepCtl *__restrict__ ctl) {
+  __shared__ long long s_part[4];
+  if (ctl->done) return;  // an earlier round accepted
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int kr = blockIdx.y; kr < C; kr += gridDim.y) {
+    const int k = k0 + kr;
+    if (k >= K) break;
+    const int2 ab = cand[k];
+    int d[2];
+    rec_delta(g, bits, ab.x, ab.y, v, d);
+    int64_t S = 0;
+    if (v < g.nv) {
+      for (int p = 0; p < g.nph; ++p) {
+        const size_t t = (size_t)p * g.nv + v;
+        S += energy_term(d[p], counts[t], target[t], N, Nt);
+        if (dl) dl[(int64_t)t * dl_t + (int64_t)k * dl_k] = (int16_t)d[p];
+      }
+    }
+    // block sum (int64: exact), one accumulation per block
+    for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_part[w];
+      add_acc(&S_acc[k], tot);
+    }
+    __syncthreads();
+  }
+}
+
+// The accepted interchange (ctl->ks; a now in phase 0, b in phase 1) applied to ones and the
+// records.  One lane per (side, path pixel j): placement x = (a or b) - p_j of vector v(j).
+__global__ void __launch_bounds__(256)
+k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__ cand) {
+  const int ks = ctl->ks;
+  if (ks < 0) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * (int64_t)g.Mc) return;
+  const unsigned mask = g.mask;
+  const int64_t N = (int64_t)g.W * g.H;
+  const int side = t >= g.Mc;
+  const int j = (int)(side ? t - g.Mc : t);
+  const int v = g.vbit[j];
+  const int4 m = g.meta[v];
+  const int off = m.x, n = m.y;
+  const int a = cand[ks].x, b = cand[ks].y;
+  const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
+  const int32_t p = g.pix[j];
+  const int x = wrapi((side ? bx : ax) - pix_dx(p), g.W);
+  const int y = wrapi((side ? by : ay) - pix_dy(p), g.H);
+  // x in both P_a and P_b: its count does not change
+  const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
+  if (on_path(ox + pix_dx(p), oy + pix_dy(p), m.z, m.w, n, g.W, g.H)) return;
+  uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
+  const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
+  *op = (uint8_t)o1;
+  const int nplanes = 2 * g.nph;
+  unsigned chg = 0;
+  for (int pl = 0; pl < nplanes; ++pl) {
+    const int s = pl / g.nph, ph = slot_phase(pl % g.nph, g.nph, mask);
+    if (plane_cond(s, ph, o0, n) != plane_cond(s, ph, o1, n)) chg |= 1u << pl;
+  }
+  if (!chg) return;
+  for (int kk = 0; kk <= n; ++kk) {
+    const int32_t pp = g.pix[off + kk];
+    const int qx = wrapi(x + pix_dx(pp), g.W), qy = wrapi(y + pix_dy(pp), g.H);
+    uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
+    const int jj = off + kk;
+    for (int pl = 0; pl < nplanes; ++pl)
+      if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (jj >> 5), 1u << (jj & 31));
+  }
+}
+
+hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream) {
+  const int64_t N = (int64_t)g.W * g.H;
+  hipLaunchKernelGGL(k_rec_ones, dim3((unsigned)g.nv, (unsigned)((N + 255) / 256)), dim3(256), 0,
+                     stream, g, bits);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rec_build, dim3((unsigned)((N + 63) / 64), (unsigned)((g.Rw + 31) / 32)),
+                     dim3(64), 0, stream, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_update(const RecGeo &g, const StepCtl *ctl, const int2 *cand,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_rec_update, dim3((unsigned)((2 * (int64_t)g.Mc + 255) / 256)), dim3(256), 0,
+                     stream, g, ctl, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
+                            hipStream_t stream) {
+  dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
+  hipLaunchKernelGGL(k_rec_round, grid, dim3(256), 0, stream, L.rg, L.bits, L.cand,
+                     L.K, r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc,
+                     decide ? L.dl : nullptr, L.dl_t, L.dl_k, L.ctl);
+  return hipGetLastError();
+}
+
+}  // namespace lpf

@@ -163,13 +163,24 @@ struct lpf_anneal_s {
   uint64_t seed = 0;
   AnnealDev *dev = nullptr;  // device struct
   int32_t *pos = nullptr;    // device, W*H: phase-1 list then phase-0 list (reserved in place)
-  DevBuf E3, cand, U, slot, S_part, ksel, dl, ctl;
+  DevBuf E3, cand, U, slot, S_acc, ksel, dl, ctl;
+  bool e3_valid = false;     // E3 holds the current cell (recount method)
+  // placement-state records (records method)
+  int method = LPF_DELTA_AUTO;
+  int rec_choice = -1;  // resolved method (1 records, 0 recount), -1 until first needed
+  bool rec_ready = false, rec_valid = false;
+  RecGeo rg{};
+  DevBuf rmeta, rpix, rvbit, rec, ones;
   // learned proposals: a network scoring the current cell, or a caller's score field
   lpf_cnn net = nullptr;
   const float *scores_ext = nullptr;
   double beta = 1.0, eps = 0.1;
-  DevBuf scores, cw1, cw0, eS, eCtl;
+  int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
+  DevBuf scores, cw1, cw0, cwb, eS, eCtl;
 };
+
+// device memory the records method may take by itself (records + ones)
+constexpr int64_t kRecBudget = (int64_t)16 << 30;
 
 // A captured lpf_batch launch (extended images, counter reset, persistent kernel).
 struct BatchGraph {
@@ -371,8 +382,6 @@ FullImg make_img(const FullPlan &p, const uint32_t *ext, uint32_t *out, int W, i
 
 // delta-kernel staging of the three image frames (below 64 KiB, the kernels' static words aside)
 constexpr int kDeltaLdsMax = 60 * 1024;
-// candidates per evaluation round of an annealing step
-constexpr int kRound = 512;
 
 // Geometry of the three frames used by the delta kernel (image, transposed, anti-transposed).
 DeltaGeo delta_geometry(int W, int H, int cx, int cy) {
@@ -488,7 +497,8 @@ int delta_chunks(int K) {
 }
 
 // Candidates of the chain's current step into a->cand / U / slot (learned weights first).
-lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s) {
+lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
+                           int64_t *S_acc = nullptr, StepCtl *ctl = nullptr) {
   hipError_t e;
   const int64_t N = (int64_t)a->W * a->H;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
@@ -498,24 +508,188 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s) {
   const double *cw1 = nullptr, *cw0 = nullptr;
   if (proposal == LPF_PROP_LEARNED) {
     if ((e = a->cw1.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
-        (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess)
+        (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+        (e = a->cwb.ensure(sizeof(double) * 4 * (size_t)((N + 1023) / 1024))) != hipSuccess)
       return hip_fail(e, "anneal: proposal scratch");
-    const float *sc = a->scores_ext;
-    if (a->net) {
-      if ((e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess)
-        return hip_fail(e, "anneal: score scratch");
-      if ((e = cnn_forward(a->net->b, a->bits, a->W, a->H, 1, (float *)a->scores.p, s)) != hipSuccess)
-        return hip_fail(e, "anneal: proposal network");
-      sc = (const float *)a->scores.p;
+    if (a->learn_age == 0 || a->learn_age >= a->refresh) {
+      const float *sc = a->scores_ext;
+      if (a->net) {
+        if ((e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess)
+          return hip_fail(e, "anneal: score scratch");
+        if ((e = cnn_forward(a->net->b, a->bits, a->W, a->H, 1, (float *)a->scores.p, s)) != hipSuccess)
+          return hip_fail(e, "anneal: proposal network");
+        sc = (const float *)a->scores.p;
+      }
+      if ((e = launch_learn_weights(a->dev, sc, a->beta, (double *)a->cw1.p, (double *)a->cw0.p, N,
+                                    (double *)a->cwb.p, s)) != hipSuccess)
+        return hip_fail(e, "anneal: proposal weights");
+      a->learn_age = 0;
     }
-    if ((e = launch_learn_weights(a->dev, sc, a->beta, (double *)a->cw1.p, (double *)a->cw0.p, s)) != hipSuccess)
-      return hip_fail(e, "anneal: proposal weights");
+    ++a->learn_age;
     cw1 = (const double *)a->cw1.p;
     cw0 = (const double *)a->cw0.p;
   }
   if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cw1, cw0, a->eps,
-                          (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, s)) != hipSuccess)
+                          (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, S_acc, ctl,
+                          s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
+  return LPF_OK;
+}
+
+// Candidate rounds of a step: 64, 448, then the rest in rounds of at most 8192.  A step whose
+// first candidates are accepted costs one small round; a skipped round costs two empty launches.
+std::vector<RoundPlan> step_rounds(int K, bool decide) {
+  std::vector<RoundPlan> r;
+  int k0 = 0;
+  while (k0 < K) {
+    int C = decide ? (k0 == 0 ? 64 : (k0 == 64 ? 448 : 8192)) : 8192;
+    C = std::min(std::min(C, 8192), K - k0);
+    RoundPlan p{};
+    p.k0 = k0;
+    p.C = C;
+    r.push_back(p);
+    k0 += C;
+  }
+  return r;
+}
+
+// Memory the records method needs, and whether it applies at all.
+bool records_fit(lpf_anneal a, int64_t *bytes, std::string *why) {
+  const int64_t N = (int64_t)a->W * a->H;
+  const int64_t nv = lpf_num_vectors(a->cx, a->cy);
+  const int nph = nph_of(a->mask);
+  int64_t Mc = 0;
+  {
+    std::vector<int16_t> can;
+    canonical_vectors(a->cx, a->cy, can);
+    for (int64_t i = 0; i < nv; ++i) Mc += std::max(std::abs((int)can[2 * i]), (int)can[2 * i + 1]) + 1;
+  }
+  const int64_t Rw = (Mc + 31) / 32 + 1;
+  const int64_t b = N * 2 * nph * Rw * 4 + nv * N;
+  if (bytes) *bytes = b;
+  if (std::max(a->cx, a->cy) > 254) {
+    if (why) *why = "cutoff above 254 (path counts are bytes)";
+    return false;
+  }
+  if ((N + 255) / 256 > 65535 || nv > 65535LL * 256) {
+    if (why) *why = "image too large for the records kernels";
+    return false;
+  }
+  return true;
+}
+
+bool use_records(lpf_anneal a) {
+  if (a->rec_choice >= 0) return a->rec_choice == 1;
+  int64_t bytes = 0;
+  bool rec;
+  if (a->method == LPF_DELTA_RECOUNT || !records_fit(a, &bytes, nullptr)) {
+    rec = false;
+  } else if (a->method == LPF_DELTA_RECORDS) {
+    rec = true;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    rec = hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes <= kRecBudget &&
+          bytes <= (int64_t)(free_b / 2);
+  }
+  a->rec_choice = rec ? 1 : 0;
+  return rec;
+}
+
+// Host tables and device buffers of the records method; records built from the current cell
+// when they are not valid.
+lpf_status setup_records(lpf_anneal a, hipStream_t s) {
+  hipError_t e;
+  if (!a->rec_ready) {
+    std::vector<int16_t> can;
+    canonical_vectors(a->cx, a->cy, can);
+    const int64_t nv = (int64_t)can.size() / 2;
+    std::vector<int4> meta(nv);
+    std::vector<int32_t> pix, vbit;
+    for (int64_t i = 0; i < nv; ++i) {
+      const int dx = can[2 * i], dy = can[2 * i + 1];
+      const int adx = std::abs(dx), n = std::max(adx, dy);
+      meta[i] = make_int4((int)pix.size(), n, dx, dy);
+      // the digitised segment (Sec. 2.2), minor coordinate sgn(m) floor((2k|m| + n) / (2n))
+      for (int k = 0; k <= n; ++k) {
+        int px, py;
+        if (adx >= dy) {
+          px = dx >= 0 ? k : -k;
+          py = n ? (int)((2LL * k * dy + n) / (2LL * n)) : 0;
+        } else {
+          py = k;
+          const int g = (int)((2LL * k * adx + n) / (2LL * n));
+          px = dx >= 0 ? g : -g;
+        }
+        pix.push_back((int32_t)((uint32_t)(uint16_t)(int16_t)px | ((uint32_t)py << 16)));
+        vbit.push_back((int32_t)i);
+      }
+    }
+    RecGeo g{};
+    g.nv = (int)nv;
+    g.Mc = (int)pix.size();
+    g.Rw = (g.Mc + 31) / 32 + 1;
+    g.nph = nph_of(a->mask);
+    g.W = a->W;
+    g.H = a->H;
+    g.rstride = (int64_t)2 * g.nph * g.Rw;
+    g.mask = a->mask;
+    const int64_t N = (int64_t)a->W * a->H;
+    if ((e = a->rmeta.ensure(sizeof(int4) * meta.size())) != hipSuccess ||
+        (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||
+        (e = a->rvbit.ensure(sizeof(int32_t) * vbit.size())) != hipSuccess ||
+        (e = a->rec.ensure(sizeof(uint32_t) * (size_t)(N * g.rstride))) != hipSuccess ||
+        (e = a->ones.ensure((size_t)(nv * N))) != hipSuccess)
+      return hip_fail(e, "anneal: records allocation");
+    if ((e = hipMemcpyAsync(a->rmeta.p, meta.data(), sizeof(int4) * meta.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(a->rpix.p, pix.data(), sizeof(int32_t) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(a->rvbit.p, vbit.data(), sizeof(int32_t) * vbit.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "anneal: records tables");
+    g.meta = (const int4 *)a->rmeta.p;
+    g.pix = (const int32_t *)a->rpix.p;
+    g.vbit = (const int32_t *)a->rvbit.p;
+    g.rec = (uint32_t *)a->rec.p;
+    g.ones = (uint8_t *)a->ones.p;
+    a->rg = g;
+    a->rec_ready = true;
+  }
+  if (!a->rec_valid) {
+    if ((e = launch_rec_build(a->rg, a->bits, s)) != hipSuccess) return hip_fail(e, "anneal: records");
+    a->rec_valid = true;
+  }
+  return LPF_OK;
+}
+
+// Round plans of the recount method: candidates per workgroup and vector chunks per round.
+lpf_status recount_rounds(lpf_anneal a, std::vector<RoundPlan> &rounds, DeltaPlan *&any) {
+  for (RoundPlan &r : rounds) {
+    r.block = r.C <= 64 ? 64 : (r.C <= 128 ? 128 : 256);
+    const int groups = (r.C + r.block - 1) / r.block;
+    DeltaPlan *plan = nullptr;
+    lpf_status st = get_delta_plan(a->ctx, a->W, a->H, a->cx, a->cy, std::max(1, 2048 / groups), plan);
+    if (st != LPF_OK) return st;
+    r.vecs = plan->vecs;
+    r.chunk_off = plan->chunk_off;
+    r.nchunks = plan->nchunks;
+    any = plan;
+  }
+  return LPF_OK;
+}
+
+void records_rounds(std::vector<RoundPlan> &rounds) {
+  for (RoundPlan &r : rounds) r.block = 256;
+}
+
+// The evaluation state of the chosen method: records, or the three image frames.
+lpf_status prepare_eval(lpf_anneal a, bool rec, const DeltaGeo &geo, hipStream_t s) {
+  if (rec) return setup_records(a, s);
+  hipError_t e;
+  if ((e = a->E3.ensure((size_t)geo.total * 4)) != hipSuccess) return hip_fail(e, "anneal: frames");
+  if (!a->e3_valid) {
+    if ((e = launch_ext3(a->bits, a->W, a->H, geo, (uint32_t *)a->E3.p, s)) != hipSuccess)
+      return hip_fail(e, "anneal: frames");
+    a->e3_valid = true;
+  }
   return LPF_OK;
 }
 
@@ -700,6 +874,15 @@ lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, in
   if (pos && (n1 < 1 || n1 > N - 1)) return fail(LPF_E_INVAL, "lpf_anneal_create: n1");
   if (std::max(cx, cy) > 16383)
     return fail(LPF_E_INVAL, "lpf_anneal_create: cutoff above 16383 (per-candidate deltas are int16)");
+  {
+    // exact energy sums: |dL| <= 2 (n + 1) per term, so every partial sum of
+    // dL (Nt (dL + 2L) - 2 N T) is below nterms * dmax * Nt * (dmax + 4N); keep it in int64
+    const __int128 dmax = 2 * ((__int128)std::max(cx, cy) + 1);
+    const __int128 bound = (__int128)nph_of(phase_mask) * lpf_num_vectors(cx, cy) * dmax *
+                           (__int128)Nt * (dmax + 4 * (__int128)W * H);
+    if (bound > (__int128)INT64_MAX)
+      return fail(LPF_E_UNSUPPORTED, "lpf_anneal_create: cell, cutoff and Nt too large for exact int64 energy sums");
+  }
   // full evaluation for the initial counts (also validates the tile shape)
   st = lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
   if (st != LPF_OK) return st;
@@ -791,67 +974,77 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   lpf_ctx c = a->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
-  DeltaPlan *plan = nullptr;
-  const int C = std::min(K, kRound);
-  const int nchunks_req = std::max(1, 2048 / ((C + 255) / 256));
-  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, nchunks_req, plan);
-  if (st != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const bool first = a->E3.p == nullptr;
+  const bool rec = use_records(a);
+  StepLaunch L{};
+  L.records = rec;
+  L.rounds = step_rounds(K, true);
+  DeltaPlan *plan = nullptr;
+  lpf_status st;
+  if (rec) {
+    if ((st = setup_records(a, s)) != LPF_OK) return st;
+    records_rounds(L.rounds);
+  } else {
+    if ((st = recount_rounds(a, L.rounds, plan)) != LPF_OK) return st;
+    if ((st = prepare_eval(a, false, plan->geo, s)) != LPF_OK) return st;
+  }
   const int nph = nph_of(a->mask);
-  const size_t nterms = (size_t)nph * plan->nv;
-  if ((e = a->E3.ensure((size_t)plan->geo.total * 4)) != hipSuccess ||
-      (e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
+  const int64_t nv = lpf_num_vectors(a->cx, a->cy);
+  const size_t nterms = (size_t)nph * nv;
+  if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
       (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
-      (e = a->S_part.ensure(sizeof(int64_t) * (size_t)C * plan->nchunks)) != hipSuccess ||
+      (e = a->S_acc.ensure(sizeof(int64_t) * (size_t)K)) != hipSuccess ||
       (e = a->dl.ensure(sizeof(int16_t) * nterms * (size_t)K)) != hipSuccess ||
       (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
       (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess)
     return hip_fail(e, "anneal_step: scratch");
-  uint32_t *E = (uint32_t *)a->E3.p;
-  int2 *cand = (int2 *)a->cand.p;
-  const int64_t N = (int64_t)a->W * a->H;
-  if (first && (e = launch_ext3(a->bits, a->W, a->H, plan->geo, E, s)) != hipSuccess)
-    return hip_fail(e, "anneal_step: ext3");
-  if ((st = draw_candidates(a, K, proposal, s)) != LPF_OK) return st;
-  StepLaunch L{};
-  L.E = E;
-  L.geo = plan->geo;
+  if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p)) != LPF_OK)
+    return st;
+  L.reset_done = true;
+  if (!rec) {
+    L.E = (const uint32_t *)a->E3.p;
+    L.geo = plan->geo;
+    L.runs = plan->runs;
+    L.use_lds = plan->use_lds;
+  }
+  L.rg = a->rg;
   L.bits = a->bits;
   L.bits_rw = a->bits;
   L.W = a->W;
   L.H = a->H;
-  L.cand = cand;
+  L.cand = (const int2 *)a->cand.p;
   L.slot = (const int2 *)a->slot.p;
   L.U = (const double *)a->U.p;
   L.K = K;
-  L.C = C;
-  L.vecs = plan->vecs;
-  L.chunk_off = plan->chunk_off;
-  L.nchunks = plan->nchunks;
-  L.runs = plan->runs;
   L.phase_mask = a->mask;
-  L.nv = (int)plan->nv;
+  L.nv = (int)nv;
   L.nterms = (int)nterms;
   L.counts = a->counts;
   L.counts_rw = a->counts;
   L.target = a->target;
-  L.N = N;
+  L.N = (int64_t)a->W * a->H;
   L.Nt = a->Nt;
   L.T = T;
-  L.S_part = (int64_t *)a->S_part.p;
+  L.S_acc = (int64_t *)a->S_acc.p;
   L.dl = (int16_t *)a->dl.p;
+  L.dl_t = rec ? 1 : K;
+  L.dl_k = rec ? (int64_t)nterms : 1;
   L.ctl = (StepCtl *)a->ctl.p;
   L.st = a->dev;
   L.e = a->e;
   L.k_sel = (int32_t *)a->ksel.p;
   L.out = reinterpret_cast<StepResult *>(out);
-  L.use_lds = plan->use_lds;
   if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal_step: evaluation");
-  if ((e = launch_ext3_if(a->bits, a->W, a->H, plan->geo, E, (const int32_t *)a->ksel.p, s)) != hipSuccess)
-    return hip_fail(e, "anneal_step: ext3");
+  if (rec) {
+    a->e3_valid = false;
+  } else {
+    a->rec_valid = false;
+    if ((e = launch_ext3_if(a->bits, a->W, a->H, plan->geo, (uint32_t *)a->E3.p,
+                            (const int32_t *)a->ksel.p, s)) != hipSuccess)
+      return hip_fail(e, "anneal_step: ext3");
+  }
   return LPF_OK;
 }
 
@@ -883,13 +1076,19 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->cand.release();
     a->U.release();
     a->slot.release();
-    a->S_part.release();
+    a->S_acc.release();
     a->ksel.release();
+    a->rmeta.release();
+    a->rpix.release();
+    a->rvbit.release();
+    a->rec.release();
+    a->ones.release();
     a->dl.release();
     a->ctl.release();
     a->scores.release();
     a->cw1.release();
     a->cw0.release();
+    a->cwb.release();
     a->eS.release();
     a->eCtl.release();
   }
@@ -1249,12 +1448,15 @@ void lpf_cnn_destroy(lpf_cnn n) {
 }
 
 lpf_status lpf_anneal_set_proposal(lpf_anneal a, lpf_cnn net, const float *scores, float beta,
-                                   float eps_uniform) {
+                                   float eps_uniform, int refresh) {
   if (!a) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: state is NULL");
   if (net && (net->W != a->W || net->H != a->H))
     return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: network built for another cell size");
   if (!(beta >= 0.f) || !(eps_uniform >= 0.f && eps_uniform <= 1.f))
     return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: beta >= 0, 0 <= eps_uniform <= 1");
+  if (refresh < 1) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: refresh >= 1");
+  a->refresh = refresh;
+  a->learn_age = 0;
   a->net = net;
   a->scores_ext = net ? nullptr : scores;
   a->beta = beta;
@@ -1286,42 +1488,67 @@ lpf_status lpf_anneal_delta_energy(lpf_anneal a, const int32_t *swaps, int n, do
   lpf_ctx c = a->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
-  DeltaPlan *plan = nullptr;
-  lpf_status st = get_delta_plan(c, a->W, a->H, a->cx, a->cy, std::max(1, 2048 / ((n + 255) / 256)), plan);
-  if (st != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const bool first = a->E3.p == nullptr;
-  if ((e = a->E3.ensure((size_t)plan->geo.total * 4)) != hipSuccess ||
-      (e = a->eS.ensure(sizeof(int64_t) * (size_t)n * plan->nchunks)) != hipSuccess ||
+  const bool rec = use_records(a);
+  StepLaunch L{};
+  L.records = rec;
+  L.rounds = step_rounds(n, false);
+  DeltaPlan *plan = nullptr;
+  lpf_status st;
+  if (rec) {
+    if ((st = setup_records(a, s)) != LPF_OK) return st;
+    records_rounds(L.rounds);
+  } else {
+    if ((st = recount_rounds(a, L.rounds, plan)) != LPF_OK) return st;
+    if ((st = prepare_eval(a, false, plan->geo, s)) != LPF_OK) return st;
+    L.E = (const uint32_t *)a->E3.p;
+    L.geo = plan->geo;
+    L.runs = plan->runs;
+    L.use_lds = plan->use_lds;
+  }
+  if ((e = a->eS.ensure(sizeof(int64_t) * (size_t)n)) != hipSuccess ||
       (e = a->eCtl.ensure(sizeof(StepCtl))) != hipSuccess)
     return hip_fail(e, "lpf_anneal_delta_energy: scratch");
-  if (first && (e = launch_ext3(a->bits, a->W, a->H, plan->geo, (uint32_t *)a->E3.p, s)) != hipSuccess)
-    return hip_fail(e, "lpf_anneal_delta_energy: ext3");
-  StepLaunch L{};
-  L.E = (const uint32_t *)a->E3.p;
-  L.geo = plan->geo;
+  L.rg = a->rg;
   L.bits = a->bits;
   L.W = a->W;
   L.H = a->H;
   L.cand = reinterpret_cast<const int2 *>(swaps);
   L.K = n;
-  L.C = n;
-  L.vecs = plan->vecs;
-  L.chunk_off = plan->chunk_off;
-  L.nchunks = plan->nchunks;
-  L.runs = plan->runs;
   L.phase_mask = a->mask;
-  L.nv = (int)plan->nv;
+  L.nv = (int)lpf_num_vectors(a->cx, a->cy);
   L.counts = a->counts;
   L.target = a->target;
   L.N = (int64_t)a->W * a->H;
   L.Nt = a->Nt;
-  L.S_part = (int64_t *)a->eS.p;
+  L.S_acc = (int64_t *)a->eS.p;
   L.ctl = (StepCtl *)a->eCtl.p;
-  L.use_lds = plan->use_lds;
   e = launch_energy(L, de, s);
   return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_anneal_delta_energy");
+}
+
+lpf_status lpf_anneal_set_method(lpf_anneal a, int method) {
+  if (!a) return fail(LPF_E_INVAL, "lpf_anneal_set_method: state is NULL");
+  if (method != LPF_DELTA_AUTO && method != LPF_DELTA_RECOUNT && method != LPF_DELTA_RECORDS)
+    return fail(LPF_E_INVAL, "lpf_anneal_set_method: method");
+  std::string why;
+  if (method == LPF_DELTA_RECORDS && !records_fit(a, nullptr, &why))
+    return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: records: " + why);
+  std::lock_guard<std::mutex> lk(a->ctx->mu);
+  a->method = method;
+  a->rec_choice = -1;
+  return LPF_OK;
+}
+
+int lpf_anneal_get_method(lpf_anneal a) {
+  if (!a) {
+    fail(LPF_E_INVAL, "lpf_anneal_get_method: state is NULL");
+    return -1;
+  }
+  std::lock_guard<std::mutex> lk(a->ctx->mu);
+  DeviceGuard g(a->ctx->dev);
+  return use_records(a) ? LPF_DELTA_RECORDS : LPF_DELTA_RECOUNT;
 }
 
 }  // extern "C"

@@ -1,6 +1,8 @@
 // Internal declarations shared by the HIP sources of liblpf (not part of the C ABI).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -75,12 +77,39 @@ struct DeltaLaunch {
 
 // Per-step control block of the round-wise evaluation (k_step.hip).
 struct StepCtl {
-  int32_t done;  // a round has accepted
-  int32_t ks;    // accepted candidate, -1 when none
-  long long S;   // its integer energy sum
+  int32_t done;      // a round has accepted
+  int32_t ks;        // accepted candidate, -1 when none
+  long long S;       // its integer energy sum
+};
+
+// One round of candidates k0 .. k0 + C - 1.  Recount method: `block` candidates per workgroup
+// and the vector chunking used (plan arrays); records method: vectors per workgroup.
+struct RoundPlan {
+  int k0, C, block, nchunks;
+  const DeltaVec *vecs;
+  const int32_t *chunk_off;
+};
+
+// Placement-state records of an annealing chain (k_rec.hip).  For vector v (canonical order)
+// and placement x, ones(v, x) counts the phase-1 pixels on x + path(v).  The record of pixel q
+// holds, for every v and every path index k, the state of placement q - p_k: plane A (read for
+// the pixel leaving phase 1) = [ones == 1] (phase 0) and [ones == n+1] (phase 1); plane B (read
+// for the pixel entering phase 1) = [ones == 0] and [ones == n].  Bit j = off(v) + k.
+struct RecGeo {
+  int nv, Mc, Rw, nph;  // vectors, path pixels in total, dwords per plane, phases kept
+  int W, H;
+  int64_t rstride;      // dwords per pixel record = 2 * nph * Rw
+  const int4 *meta;     // per vector {off, n, dx, dy}
+  const int32_t *pix;   // [Mc] path pixel offsets, (dx & 0xffff) | (dy << 16)
+  uint32_t *rec;        // [W*H][plane A phases, plane B phases][Rw]
+  uint8_t *ones;        // [nv][W*H]
+  const int32_t *vbit;  // [Mc] vector of each record bit
+  unsigned mask;        // phases kept (LPF_PHASE0 | LPF_PHASE1 bits)
 };
 
 struct StepLaunch {
+  bool records;              // evaluation method: placement-state records, else recount
+  bool reset_done;           // ctl and S_acc already zeroed by the candidate draw
   const uint32_t *E;
   DeltaGeo geo;
   const uint64_t *bits;
@@ -88,21 +117,21 @@ struct StepLaunch {
   int W, H;
   const int2 *cand;
   const int2 *slot;
-  const double *U;
-  int K, C;                  // candidates per step, candidates per round
-  const DeltaVec *vecs;
-  const int32_t *chunk_off;
-  int nchunks;
+  const double *U;           // nullptr: energies only, no decision
+  int K;                     // candidates per step
+  std::vector<RoundPlan> rounds;
   const uint32_t *runs;
   unsigned phase_mask;
   int nv, nterms;            // nterms = phases * vectors
+  RecGeo rg;
   const uint32_t *counts;
   uint32_t *counts_rw;
   const uint32_t *target;
   int64_t N, Nt;
   double T;
-  int64_t *S_part;           // [nchunks][C]
-  int16_t *dl;               // [phases][vectors][K]
+  int64_t *S_acc;            // [K] exact energy sums
+  int16_t *dl;               // per (term t, candidate k) at t * dl_t + k * dl_k
+  int64_t dl_t, dl_k;
   StepCtl *ctl;
   struct AnnealDev *st;
   double *e;
@@ -129,15 +158,24 @@ struct StepResult {
   double de, e;
   uint64_t step;
 };
+// S_acc, ctl: when given, also zeroed for the step (the step's reset folded into the draw).
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
-                          int2 *cand, double *U, int2 *slot, hipStream_t stream);
+                          int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
+                          hipStream_t stream);
+// scratch: 4 * ceil(W*H / 1024) doubles
 hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
-                                double *cw0, hipStream_t stream);
+                                double *cw0, int64_t N, double *scratch, hipStream_t stream);
 hipError_t launch_copy_cand(const int2 *cand, int K, int32_t *out, hipStream_t stream);
-// Exact energy change of n given interchanges on a chain's state: S partials per chunk, then
-// de[i] = (sum over chunks) / (N^2 Nt).
+// Exact energy change of K given interchanges on a chain's state: de[i] = S_i / (N^2 Nt).
 hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
+// Placement-state records: build ones and records from the packed image, and apply the
+// interchange accepted by the step (skipped on the device when none was).
+hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream);
+hipError_t launch_rec_update(const RecGeo &g, const StepCtl *ctl, const int2 *cand,
+                             hipStream_t stream);
+hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
+                            hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream);
 hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,

@@ -28,13 +28,20 @@ def _problem(cell_side, tgt_side, cx, mask, seed, phi=0.4, r=3.0):
     return tgt, target, cell
 
 
-def _gpu_chain(ctx, cell, cx, mask, target, Nt, seed, step0=0, pos=None, n1=0):
+METHODS = {"recount": 1, "records": 2}
+
+
+def _gpu_chain(ctx, cell, cx, mask, target, Nt, seed, step0=0, pos=None, n1=0, method=0, cy=None):
     import torch
     from paper_1601_04359_amd import Anneal
     H, W = cell.shape
     bits = ctx.pack(torch.from_numpy(cell).cuda())
     t = torch.from_numpy(target.astype(np.int32)).cuda()
-    return Anneal(ctx, bits, W, H, cx, cx, mask, t, Nt, seed, step0, pos, n1)
+    ch = Anneal(ctx, bits, W, H, cx, cx if cy is None else cy, mask, t, Nt, seed, step0, pos, n1)
+    if method:
+        ch.set_method(method)
+        assert ch.method == method
+    return ch
 
 
 def _unpack(bits, W, H):
@@ -45,15 +52,16 @@ def _unpack(bits, W, H):
     return out
 
 
-@pytest.mark.parametrize("proposal,mask", [(0, 3), (1, 3), (0, 2)])
-def test_chain_matches_oracle(ctx, proposal, mask):
+@pytest.mark.parametrize("method", ["recount", "records"])
+@pytest.mark.parametrize("proposal,mask,K", [(0, 3, 64), (1, 3, 200), (0, 2, 64), (0, 1, 333)])
+def test_chain_matches_oracle(ctx, proposal, mask, K, method):
     import torch
     from paper_1601_04359_amd import step_records
-    print(f"[gpu] anneal chain proposal={proposal} mask={mask}", flush=True)
+    print(f"[gpu] anneal chain proposal={proposal} mask={mask} K={K} {method}", flush=True)
     tgt, target, cell = _problem(16, 48, 5, mask, 21)
-    seed, K, nsteps = 99, 64, 60
+    seed, nsteps = 99, 60
     Ts = 3e-4 * 0.93 ** np.arange(nsteps)
-    ch = _gpu_chain(ctx, cell, 5, mask, target, tgt.size, seed)
+    ch = _gpu_chain(ctx, cell, 5, mask, target, tgt.size, seed, method=METHODS[method])
     recs = step_records(ch.run(K, Ts, proposal))
     torch.cuda.synchronize()
     ref = oracle.AnnealState(cell, 5, 5, mask, target, tgt.size, seed)
@@ -97,19 +105,81 @@ def test_resume_from_export(ctx):
         c.close()
 
 
-def test_reconstruction_cell_128_c32(ctx):
+@pytest.mark.parametrize("method", ["recount", "records"])
+def test_ragged_cell_long_vectors(ctx, method):
+    # a 21 x 17 cell with cutoffs (20, 16): segments wrap around the cell and many candidates
+    # have both pixels on one placement's segment; chain equals the oracle's
+    import torch
+    from paper_1601_04359_amd import step_records
+    print(f"[gpu] anneal ragged 21x17 c=(20,16) {method}", flush=True)
+    tgt = wl.boolean_disks(40, 40, 3.0, 0.45, 7)
+    target = oracle.lpf(tgt, 20, 16, 3)
+    cell = wl.random_cell(21, 17, int(round(0.45 * 21 * 17)), 8)
+    Ts = 2e-3 * 0.9 ** np.arange(30)
+    ch = _gpu_chain(ctx, cell, 20, 3, target, tgt.size, 4, method=METHODS[method], cy=16)
+    recs = step_records(ch.run(100, Ts))
+    torch.cuda.synchronize()
+    ref = oracle.AnnealState(cell, 20, 16, 3, target, tgt.size, 4)
+    rres = ref.run(30, 100, Ts)
+    assert [(int(r["k"]), int(r["a"]), int(r["b"])) for r in recs] == \
+        [(int(r["k"]), int(r["a"]), int(r["b"])) for r in rres]
+    assert np.array_equal(recs["de"], rres["de"])
+    assert np.array_equal(ch.counts.cpu().numpy().astype(np.uint32), ref.counts)
+    ch.close()
+
+
+def test_records_agree_with_recount(ctx):
+    # after many accepted interchanges (incremental record updates), the records method's exact
+    # energy changes of random and neighbouring interchanges equal the recount method's, and the
+    # counts equal a fresh full evaluation
+    import torch
+    from paper_1601_04359_amd import LPF_DELTA_RECORDS, LPF_DELTA_RECOUNT
+    print("[gpu] anneal records vs recount 48x40 c=(9,7)", flush=True)
+    tgt = wl.boolean_disks(96, 96, 4.0, 0.35, 11)
+    target = oracle.lpf(tgt, 9, 7, 3)
+    cell = wl.random_cell(48, 40, int(round(0.35 * 48 * 40)), 12)
+    ch = _gpu_chain(ctx, cell, 9, 3, target, tgt.size, 6, method=LPF_DELTA_RECORDS, cy=7)
+    ch.run(64, np.full(300, 1e-2))       # hot: most steps accept
+    torch.cuda.synchronize()
+    assert torch.equal(ctx.full(ch.bits, 48, 40, 9, 7, 3), ch.counts)
+    img = _unpack(ch.bits, 48, 40).ravel()
+    g = np.random.default_rng(3)
+    ones, zeros = np.flatnonzero(img == 1), np.flatnonzero(img == 0)
+    a = g.choice(ones, 600)
+    b = g.choice(zeros, 600)
+    near = (a[:300] + g.integers(-3, 4, 300) + 48 * g.integers(-3, 4, 300)) % img.size
+    b[:300] = np.where(img[near] == 0, near, b[:300])
+    sw = torch.from_numpy(np.stack([a, b], 1).astype(np.int32)).cuda()
+    de_rec = ch.delta_energy(sw).cpu().numpy()
+    ch.set_method(LPF_DELTA_RECOUNT)
+    de_cnt = ch.delta_energy(sw).cpu().numpy()
+    assert np.array_equal(de_rec, de_cnt)
+    # and against the oracle's deltas through the integer energy formula of eq. (LSE)
+    swn = sw.cpu().numpy()[:60]
+    dl = oracle.delta_swap(_unpack(ch.bits, 48, 40), 9, 7, swn, 3).astype(object)
+    L = ch.counts.cpu().numpy().astype(object)
+    T = target.astype(object)
+    N, Nt = 48 * 40, tgt.size
+    for i in range(len(swn)):
+        S = int(np.sum(dl[i] * (Nt * (dl[i] + 2 * L) - 2 * N * T)))
+        assert de_rec[i] == float(S) / (float(N) * float(N) * float(Nt)), i
+    ch.close()
+
+
+@pytest.mark.parametrize("method", ["recount", "records"])
+def test_reconstruction_cell_128_c32(ctx, method):
     # the reconstruction workload's shapes: 128 x 128 cell, phase-1 LPF with cutoff 32 of a
     # 1024 x 1024 disk image (phi 0.35, r 6), 4096 candidates per step.  Drift guard: the
     # incrementally updated counts equal a fresh lpf_full of the cell; the running energy equals
     # eq. (LSE) recomputed by the oracle; the first step agrees with the oracle's chain.
     import torch
     from paper_1601_04359_amd import step_records
-    print("[gpu] anneal 128x128 c=32 K=4096", flush=True)
+    print(f"[gpu] anneal 128x128 c=32 K=4096 {method}", flush=True)
     tgt = wl.anneal_target()
     bt = torch.from_numpy(tgt).cuda()
     target = ctx.full(ctx.pack(bt), 1024, 1024, 32, 32, 2)
     cell = wl.random_cell(128, 128, int(round(0.35 * 128 * 128)), 1)
-    ch = _gpu_chain(ctx, cell, 32, 2, target.cpu().numpy(), 1024 * 1024, 1)
+    ch = _gpu_chain(ctx, cell, 32, 2, target.cpu().numpy(), 1024 * 1024, 1, method=METHODS[method])
     Ts = 1e-3 * (0.01 ** (1 / 20000)) ** np.arange(12)
     recs = step_records(ch.run(4096, Ts))
     torch.cuda.synchronize()

@@ -39,11 +39,14 @@ def _problem(side=24, cx=5, mask=3, seed=3):
     return tgt, target, cell
 
 
-def test_delta_energy_exact(ctx):
+@pytest.mark.parametrize("method", [1, 2])
+def test_delta_energy_exact(ctx, method):
     # de of given interchanges equals the exact rational change of eq. (LSE)
     import torch
+    print(f"[gpu] delta energy exact, method {method}", flush=True)
     tgt, target, cell = _problem()
     ch = _chain(ctx, cell, 5, 3, target, tgt.size, 1)
+    ch.set_method(method)
     g = np.random.default_rng(0)
     ones = np.flatnonzero(cell.ravel() == 1)
     zeros = np.flatnonzero(cell.ravel() == 0)
@@ -90,15 +93,17 @@ def test_learned_draws_follow_scores(ctx):
     ch.close()
 
 
-def test_learned_chain_stays_exact(ctx):
+@pytest.mark.parametrize("refresh", [1, 4])
+def test_learned_chain_stays_exact(ctx, refresh):
     # learned steps keep counts equal to a full recount and e equal to eq. (LSE)
     import torch
     from paper_1601_04359_amd import ProposalNet, step_records
     from oracle import cnn
+    print(f"[gpu] learned chain refresh {refresh}", flush=True)
     tgt, target, cell = _problem(side=32)
     ch = _chain(ctx, cell, 5, 3, target, tgt.size, 3)
     net = ProposalNet(ctx, 32, 32, 1, 4, torch.from_numpy(cnn.init_params(9)).cuda())
-    ch.set_proposal(net=net, beta=1.0, eps_uniform=0.2)
+    ch.set_proposal(net=net, beta=1.0, eps_uniform=0.2, refresh=refresh)
     recs = step_records(ch.run(64, np.full(80, 5e-5), 2))
     torch.cuda.synchronize()
     assert (recs["k"] >= 0).sum() > 5
