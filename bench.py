@@ -224,7 +224,8 @@ def learned_bench(args) -> dict:
     t_hit, s_hit, acc_learned = [], [], []
     for sd in seeds:
         ch = chain(sd)
-        ch.set_proposal(net=net, beta=args.beta, eps_uniform=0.1, refresh=args.refresh)
+        ch.set_proposal(net=net, beta=args.beta, eps_uniform=0.1, refresh=args.refresh,
+                        rank=bool(args.rank))
         recs = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -262,7 +263,7 @@ def learned_bench(args) -> dict:
                                "both phases of a 2048x2048 Boolean disk image (phi 0.35, r 6, "
                                "seed 1605), 4096 candidates/step, T0 1e-3 geometric to 1e-5",
                    "schedule_steps": nsteps, "chains": len(seeds), "beta": args.beta,
-                   "eps_uniform": 0.1, "refresh": args.refresh,
+                   "eps_uniform": 0.1, "refresh": args.refresh, "rank": bool(args.rank),
                    "samples": int(len(data.de)), "snapshots": args.snapshots,
                    "train_steps": args.train_steps},
         "e_start": e0, "e_star": e_star,
@@ -357,10 +358,13 @@ def main() -> int:
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
     ap.add_argument("--train-steps", type=int, default=400)
-    ap.add_argument("--beta", type=float, default=3.0)
-    ap.add_argument("--refresh", type=int, default=1,
+    ap.add_argument("--beta", type=float, default=0.0,
+                    help="learned workload: draw weights exp(beta * score); 0 = uniform draws")
+    ap.add_argument("--refresh", type=int, default=4,
                     help="learned draws between re-scorings of the cell")
     ap.add_argument("--chains", type=int, default=5)
+    ap.add_argument("--rank", type=int, default=1,
+                    help="learned workload: the network also ranks each step's candidates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (5 times) before the timed steps, "
                          "as the reference kernel for HBM byte counters")

@@ -194,14 +194,20 @@ lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
  * candidate is drawn as LPF_PROP_UNIFORM (random stream word r3); otherwise a is drawn from the
  * phase-1 pixels with probability proportional to exp(clamp(beta * score[a], -60, 60)) and b
  * likewise from the phase-0 pixels (inversion of r0, r1 on fp64 prefix sums in pixel-list
- * order).  The exact energy change still decides acceptance; no proposal-ratio correction is
+ * order); beta = 0 draws exactly the LPF_PROP_UNIFORM candidates (then the scores serve the
+ * ranking below only).  The exact energy change still decides acceptance; no proposal-ratio correction is
  * applied (the chain minimises, it does not sample).  refresh >= 1: the scores and prefix sums
  * are recomputed at the first learned draw and then every `refresh` learned draws (steps or
  * lpf_anneal_propose calls); in between, the pixel-list slots keep the weights of the last
  * scoring (an interchange leaves both slots' old weights in place), which only changes which
- * candidates are proposed, never how they are judged.  Errors: LPF_E_INVAL. */
+ * candidates are proposed, never how they are judged.  rank = 1: the network also ranks the
+ * step's candidates: the 64 draws with the highest predicted gain score[a] + score[b] (fp32 sum;
+ * ties by draw index; void draws lowest) among the first min(K, 4096) are evaluated first, best
+ * first, then every other draw in draw order, and the first of that order to pass the Metropolis
+ * test is applied (the record's accepted_k is still the draw index); rank = 0 keeps draw order.
+ * Errors: LPF_E_INVAL. */
 lpf_status lpf_anneal_set_proposal(lpf_anneal st, lpf_cnn net, const float *scores, float beta,
-                                   float eps_uniform, int refresh);
+                                   float eps_uniform, int refresh, int rank);
 
 /* The current step's K candidates as int32 (a, b) pairs into cand (device, [K][2]), without
  * evaluating them or advancing the chain (a = -1 marks a void interfacial draw). */

@@ -147,13 +147,14 @@ class Anneal:
         return recs
 
     def set_proposal(self, net=None, scores: torch.Tensor | None = None, beta: float = 1.0,
-                     eps_uniform: float = 0.1, refresh: int = 1) -> None:
+                     eps_uniform: float = 0.1, refresh: int = 1, rank: bool = False) -> None:
         """Learned proposals from a ProposalNet (scored on the current cell) or a score field,
-        re-scored every `refresh` learned draws."""
+        re-scored every `refresh` learned draws; with `rank` the step's candidates are evaluated
+        by descending predicted gain."""
         self._scores = scores  # keep the caller's field alive
         self._net = net
         _abi.lpf_anneal_set_proposal(self.handle, net.handle if net is not None else None,
-                                     scores, beta, eps_uniform, refresh)
+                                     scores, beta, eps_uniform, refresh, int(bool(rank)))
 
     def set_method(self, method: int) -> None:
         """Candidate evaluation method: LPF_DELTA_AUTO, LPF_DELTA_RECOUNT or LPF_DELTA_RECORDS."""

@@ -75,7 +75,7 @@ _sig("lpf_cnn_adam", _i32, _P, _P, _i32, ctypes.c_float, ctypes.c_float, ctypes.
      ctypes.c_float, _P)
 _sig("lpf_cnn_destroy", None, _P)
 LPF_CNN_PARAMS = 4961
-_sig("lpf_anneal_set_proposal", _i32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _i32)
+_sig("lpf_anneal_set_proposal", _i32, _P, _P, _P, ctypes.c_float, ctypes.c_float, _i32, _i32)
 _sig("lpf_anneal_propose", _i32, _P, _i32, _i32, _P, _P)
 _sig("lpf_anneal_delta_energy", _i32, _P, _P, _i32, _P, _P)
 _sig("lpf_anneal_set_method", _i32, _P, _i32)
@@ -285,10 +285,10 @@ def lpf_cnn_destroy(net: int) -> None:
 
 
 def lpf_anneal_set_proposal(st: int, net: int | None, scores: torch.Tensor | None, beta: float,
-                            eps_uniform: float, refresh: int = 1) -> None:
+                            eps_uniform: float, refresh: int = 1, rank: int = 0) -> None:
     _check(_lib.lpf_anneal_set_proposal(
         st, net, _dev(scores, torch.float32, "scores") if scores is not None else None,
-        beta, eps_uniform, refresh))
+        beta, eps_uniform, refresh, rank))
 
 
 def lpf_anneal_propose(st: int, K: int, proposal: int, cand: torch.Tensor, stream=None) -> None:

@@ -1,15 +1,17 @@
 // Device-resident simulated annealing on the lineal path function (Sec. 4, Alg. "annealing",
 // objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn (here), their exact
-// energy changes are evaluated against the current state in draw order and the first candidate
-// that passes the Metropolis test is applied (k_step.hip).  Rejected candidates leave the state
-// unchanged, so this is the sequential chain of the algorithm with the step's later candidates
-// unused.  Nothing returns to the host inside a step.
+// energy changes are evaluated against the current state in evaluation order (draw order, or the
+// learned ranking of k_rank) and the first candidate that passes the Metropolis test is applied
+// (k_step.hip).  Rejected candidates leave the state unchanged, so this is the sequential chain
+// of the algorithm over those draws with the step's later candidates unused.  Nothing returns to
+// the host inside a step.
 //
 // Energy: e = sum_{i,v} (T_i(v)/Nt - L_i(v)/N)^2 over the phases of the mask and the canonical
 // half domain, T = target counts over Nt pixels, L = current counts over N = W*H pixels.  The
 // change of one interchange is exact in integers,
 //     S = sum dL * (Nt * (dL + 2 L) - 2 N T),   de = S / (N^2 Nt),
 // and converted to double once, so it does not depend on summation order.
+#include <limits.h>
 #include <math.h>
 
 #include "lpf_internal.h"
@@ -251,6 +253,127 @@ hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_learn_add, dim3((unsigned)nb, 2), dim3(1024), 0, stream, st, cw1, cw0, boff,
                      nb);
+  return hipGetLastError();
+}
+
+// Evaluation order of a step's candidates: the kRankTop draws with the highest predicted gain
+// score[a] + score[b] (fp32; void draws and NaN lowest; ties by draw index) among the first
+// R = min(K, kRankMax), best first, then every other draw in draw order.  k_rank_chunks sorts
+// chunks of 512 draws (one workgroup each) and keeps each chunk's best kRankTop; k_rank_merge
+// sorts those (the overall best kRankTop are among them) and writes the order.
+__device__ __forceinline__ bool rank_before(float ka, int ia, float kb, int ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+// Bitonic sort of 512 (key, index) pairs, one per thread of a 512-thread workgroup, best first;
+// partners under 64 apart exchange through wave shuffles, the others through LDS.
+__device__ __forceinline__ void bitonic512(float &key, int &id, float *sk, int *si) {
+  const int e = threadIdx.x;
+  for (int size = 2; size <= 512; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      float pk;
+      int pi;
+      if (stride >= 64) {
+        sk[e] = key;
+        si[e] = id;
+        __syncthreads();
+        pk = sk[e ^ stride];
+        pi = si[e ^ stride];
+        __syncthreads();
+      } else {
+        pk = __shfl_xor(key, stride);
+        pi = __shfl_xor(id, stride);
+      }
+      const bool keep_first = ((e & stride) == 0) == ((e & size) == 0);
+      const bool p_first = rank_before(pk, pi, key, id);
+      if (keep_first ? p_first : !p_first) {
+        key = pk;
+        id = pi;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512)
+k_rank_chunks(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
+              float *__restrict__ top_key, int *__restrict__ top_id) {
+  __shared__ float sk[512];
+  __shared__ int si[512];
+  const int R = min(K, kRankMax);
+  const int i = blockIdx.x * 512 + threadIdx.x;
+  float key = -INFINITY;
+  int id = INT_MAX;
+  if (i < R) {
+    id = i;
+    const int2 ab = cand[i];
+    if (ab.x >= 0 && ab.y >= 0) {
+      const float sc = score[ab.x] + score[ab.y];
+      key = sc == sc ? sc : -INFINITY;
+    }
+  }
+  bitonic512(key, id, sk, si);
+  if (threadIdx.x < kRankTop) {
+    top_key[blockIdx.x * kRankTop + threadIdx.x] = key;
+    top_id[blockIdx.x * kRankTop + threadIdx.x] = id;
+  }
+}
+
+__global__ void __launch_bounds__(512)
+k_rank_merge(const float *__restrict__ top_key, const int *__restrict__ top_id, int K,
+             int32_t *__restrict__ order) {
+  __shared__ float sk[512];
+  __shared__ int si[512];
+  __shared__ uint32_t sel[kRankMax / 32];
+  __shared__ int part[512];
+  const int R = min(K, kRankMax);
+  const int nchunks = (R + 511) / 512;
+  const int t = threadIdx.x;
+  float key = -INFINITY;
+  int id = INT_MAX;
+  if (t < nchunks * kRankTop) {
+    key = top_key[t];
+    id = top_id[t];
+  }
+  for (int w = t; w < kRankMax / 32; w += 512) sel[w] = 0u;
+  bitonic512(key, id, sk, si);
+  const int T = min(R, kRankTop);
+  if (t < T) {
+    order[t] = id;
+    atomicOr(&sel[id >> 5], 1u << (id & 31));
+  }
+  __syncthreads();
+  // the other draws of [0, R) in draw order: consecutive draws per thread, exclusive scan
+  constexpr int per = kRankMax / 512;
+  const int i0 = t * per;
+  int cnt = 0;
+  for (int j = 0; j < per; ++j) {
+    const int i = i0 + j;
+    cnt += (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) ? 1 : 0;
+  }
+  part[t] = cnt;
+  __syncthreads();
+  for (int o = 1; o < 512; o <<= 1) {
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int pos = T + part[t] - cnt;
+  for (int j = 0; j < per; ++j) {
+    const int i = i0 + j;
+    if (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) order[pos++] = i;
+  }
+  for (int i = R + t; i < K; i += 512) order[i] = i;
+}
+
+hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
+                       float *top_key, int *top_id, hipStream_t stream) {
+  const int R = std::min(K, kRankMax);
+  hipLaunchKernelGGL(k_rank_chunks, dim3((unsigned)((R + 511) / 512)), dim3(512), 0, stream, cand,
+                     score, K, top_key, top_id);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_merge, dim3(1), dim3(512), 0, stream, top_key, top_id, K, order);
   return hipGetLastError();
 }
 

@@ -87,9 +87,16 @@ __device__ __forceinline__ bool plane_cond(int side, int phase, int o, int n) {
   return side == 0 ? (phase ? o == n + 1 : o == 1) : (phase ? o == n : o == 0);
 }
 
-__device__ __forceinline__ int slot_phase(int p, int nph, unsigned mask) {
-  return nph == 2 ? p : (mask == 2u ? 1 : 0);
-}
+// Record layout for a phase mask: planes A of the kept phases, then planes B (phase 0 first).
+template <unsigned MASK>
+struct Planes {
+  static constexpr int nph = MASK == 3u ? 2 : 1;
+  static constexpr int n = 2 * nph;
+  static __device__ __forceinline__ constexpr int side(int pl) { return pl / nph; }
+  static __device__ __forceinline__ constexpr int phase(int pl) {
+    return nph == 2 ? pl % 2 : (MASK == 2u ? 1 : 0);
+  }
+};
 
 }  // namespace
 
@@ -113,22 +120,24 @@ k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
 
 // Records of 64 pixels (one wave) over one 32-dword tile of the record per workgroup, staged in
 // LDS so that each pixel's record is written with contiguous stores.
+template <unsigned MASK>
 __global__ void __launch_bounds__(64)
 k_rec_build(RecGeo g) {
+  using P = Planes<MASK>;
   const int32_t *__restrict__ vbit = g.vbit;
-  const unsigned mask = g.mask;
-  __shared__ uint32_t tile[4][64][33];
+  __shared__ uint32_t tile[P::n][64][33];
   const int64_t N = (int64_t)g.W * g.H;
   const int lane = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * 64;
   const int64_t q = q0 + lane;
   const bool valid = q < N;
   const int qy = valid ? (int)(q / g.W) : 0, qx = valid ? (int)(q - (int64_t)qy * g.W) : 0;
-  const int nplanes = 2 * g.nph;
   const int w0 = blockIdx.y * 32;
   const int nw = min(32, g.Rw - w0);
   for (int wd = 0; wd < nw; ++wd) {
-    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+    uint32_t acc[P::n];
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl) acc[pl] = 0u;
     for (int t = 0; t < 32; ++t) {
       const int j = (w0 + wd) * 32 + t;
       if (j >= g.Mc) break;
@@ -137,25 +146,28 @@ k_rec_build(RecGeo g) {
       const int32_t p = g.pix[j];
       const int xx = wrapi(qx - pix_dx(p), g.W), yy = wrapi(qy - pix_dy(p), g.H);
       const int o = valid ? (int)g.ones[(size_t)v * N + (size_t)yy * g.W + xx] : -1;
-      for (int pl = 0; pl < nplanes; ++pl) {
-        const int side = pl / g.nph, ph = slot_phase(pl % g.nph, g.nph, mask);
-        acc[pl] |= (plane_cond(side, ph, o, n) ? 1u : 0u) << t;
-      }
+#pragma unroll
+      for (int pl = 0; pl < P::n; ++pl)
+        acc[pl] |= (plane_cond(P::side(pl), P::phase(pl), o, n) ? 1u : 0u) << t;
     }
-    for (int pl = 0; pl < nplanes; ++pl) tile[pl][lane][wd] = acc[pl];
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl) tile[pl][lane][wd] = acc[pl];
   }
   __syncthreads();
   for (int pq = 0; pq < 64 && q0 + pq < N; ++pq) {
     uint32_t *R = g.rec + (size_t)(q0 + pq) * g.rstride + w0;
     if (lane < nw)
-      for (int pl = 0; pl < nplanes; ++pl) R[(size_t)pl * g.Rw + lane] = tile[pl][pq][lane];
+#pragma unroll
+      for (int pl = 0; pl < P::n; ++pl) R[(size_t)pl * g.Rw + lane] = tile[pl][pq][lane];
   }
 }
 
 // Exact dL of interchange (a, b) for vector v, one entry per kept phase.  Invalid or same-phase
 // pairs change nothing.
+template <unsigned MASK>
 __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__restrict__ bits,
-                                          int a, int b, int v, int (&d)[2]) {
+                                          int a, int b, int v, int4 m, int (&d)[2]) {
+  using P = Planes<MASK>;
   d[0] = 0;
   d[1] = 0;
   const int64_t N = (int64_t)g.W * g.H;
@@ -169,54 +181,67 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
     t = ax; ax = bx; bx = t;
     t = ay; ay = by; by = t;
   }
-  const unsigned mask = g.mask;
-  const int4 m = g.meta[v];
   const int off = m.x, n = m.y, len = n + 1;
   const uint32_t *RA = g.rec + (size_t)a * g.rstride;                // planes A of a
-  const uint32_t *RB = g.rec + (size_t)b * g.rstride + g.nph * g.Rw;  // planes B of b
-  for (int p = 0; p < g.nph; ++p) {
+  const uint32_t *RB = g.rec + (size_t)b * g.rstride + P::nph * g.Rw;  // planes B of b
+#pragma unroll
+  for (int p = 0; p < P::nph; ++p) {
     const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
     const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
-    d[p] = slot_phase(p, g.nph, mask) ? cB - cA : cA - cB;
+    d[p] = P::phase(p) ? cB - cA : cA - cB;
   }
   // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k on the path
   const int DX = bx - ax, DY = by - ay;
   if (within(DX, g.W, m.z < 0 ? -m.z : m.z) && within(DY, g.H, m.w)) {
-    const uint32_t *RBa = g.rec + (size_t)a * g.rstride + g.nph * g.Rw;  // planes B of a
+    const uint32_t *RBa = g.rec + (size_t)a * g.rstride + P::nph * g.Rw;  // planes B of a
     for (int kk = 0; kk <= n; ++kk) {
       const int32_t p = g.pix[off + kk];
       if (!on_path(DX + pix_dx(p), DY + pix_dy(p), m.z, m.w, n, g.W, g.H)) continue;
-      for (int s = 0; s < g.nph; ++s)
-        d[s] -= slot_phase(s, g.nph, mask) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
-                                           : plane_bit(RA + (size_t)s * g.Rw, off + kk);
+#pragma unroll
+      for (int s = 0; s < P::nph; ++s)
+        d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
+                            : plane_bit(RA + (size_t)s * g.Rw, off + kk);
     }
   }
 }
 
-// One round: block (vector block, candidate slot); the slots stride over the round's candidates.
-// Lanes run over vectors; the candidate is uniform.  Each block adds its part of a candidate's
+// One round: block (vector block, candidate slot); the slots stride over the round's evaluation
+// positions k0 .. k0 + C - 1 (candidate order[i], or i without an order).  Lanes run over
+// vectors; the candidate is uniform.  Each block adds its part of a candidate's
 // energy sum into S_acc[k] and stores the candidate's dL when dl is given.
+template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict__ cand, int K,
             int k0, int C, const uint32_t *__restrict__ counts,
             const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
             int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
-            const StepCtl *__restrict__ ctl) {
+            const StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
+  using P = Planes<MASK>;
   __shared__ long long s_part[4];
   if (ctl->done) return;  // an earlier round accepted
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool vin = v < g.nv;
+  // candidate-independent operands first, so that their loads overlap the candidate's
+  const int4 m = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  int64_t L[2] = {0, 0}, T[2] = {0, 0};
+#pragma unroll
+  for (int p = 0; p < P::nph; ++p)
+    if (vin) {
+      L[p] = counts[(size_t)p * g.nv + v];
+      T[p] = target[(size_t)p * g.nv + v];
+    }
   for (int kr = blockIdx.y; kr < C; kr += gridDim.y) {
-    const int k = k0 + kr;
-    if (k >= K) break;
+    if (k0 + kr >= K) break;
+    const int k = order ? order[k0 + kr] : k0 + kr;  // candidate (draw index)
     const int2 ab = cand[k];
     int d[2];
-    rec_delta(g, bits, ab.x, ab.y, v, d);
+    rec_delta<MASK>(g, bits, ab.x, ab.y, v, m, d);
     int64_t S = 0;
-    if (v < g.nv) {
-      for (int p = 0; p < g.nph; ++p) {
-        const size_t t = (size_t)p * g.nv + v;
-        S += energy_term(d[p], counts[t], target[t], N, Nt);
-        if (dl) dl[(int64_t)t * dl_t + (int64_t)k * dl_k] = (int16_t)d[p];
+    if (vin) {
+#pragma unroll
+      for (int p = 0; p < P::nph; ++p) {
+        S += energy_term(d[p], L[p], T[p], N, Nt);
+        if (dl) dl[(int64_t)((size_t)p * g.nv + v) * dl_t + (int64_t)k * dl_k] = (int16_t)d[p];
       }
     }
     // block sum (int64: exact), one accumulation per block
@@ -234,13 +259,14 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
 
 // The accepted interchange (ctl->ks; a now in phase 0, b in phase 1) applied to ones and the
 // records.  One lane per (side, path pixel j): placement x = (a or b) - p_j of vector v(j).
+template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__ cand) {
+  using P = Planes<MASK>;
   const int ks = ctl->ks;
   if (ks < 0) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * (int64_t)g.Mc) return;
-  const unsigned mask = g.mask;
   const int64_t N = (int64_t)g.W * g.H;
   const int side = t >= g.Mc;
   const int j = (int)(side ? t - g.Mc : t);
@@ -258,22 +284,29 @@ k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__
   uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
   const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
   *op = (uint8_t)o1;
-  const int nplanes = 2 * g.nph;
   unsigned chg = 0;
-  for (int pl = 0; pl < nplanes; ++pl) {
-    const int s = pl / g.nph, ph = slot_phase(pl % g.nph, g.nph, mask);
-    if (plane_cond(s, ph, o0, n) != plane_cond(s, ph, o1, n)) chg |= 1u << pl;
-  }
+#pragma unroll
+  for (int pl = 0; pl < P::n; ++pl)
+    if (plane_cond(P::side(pl), P::phase(pl), o0, n) != plane_cond(P::side(pl), P::phase(pl), o1, n))
+      chg |= 1u << pl;
   if (!chg) return;
   for (int kk = 0; kk <= n; ++kk) {
     const int32_t pp = g.pix[off + kk];
     const int qx = wrapi(x + pix_dx(pp), g.W), qy = wrapi(y + pix_dy(pp), g.H);
     uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
     const int jj = off + kk;
-    for (int pl = 0; pl < nplanes; ++pl)
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl)
       if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (jj >> 5), 1u << (jj & 31));
   }
 }
+
+#define LPF_REC_MASK_SWITCH(mask, CALL) \
+  switch (mask) {                             \
+    case 1u: CALL(1u); break;                 \
+    case 2u: CALL(2u); break;                 \
+    default: CALL(3u); break;                 \
+  }
 
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream) {
   const int64_t N = (int64_t)g.W * g.H;
@@ -281,25 +314,35 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
                      stream, g, bits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rec_build, dim3((unsigned)((N + 63) / 64), (unsigned)((g.Rw + 31) / 32)),
-                     dim3(64), 0, stream, g);
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((g.Rw + 31) / 32));
+#define LPF_BUILD(M) hipLaunchKernelGGL(k_rec_build<M>, grid, dim3(64), 0, stream, g)
+  LPF_REC_MASK_SWITCH(g.mask, LPF_BUILD)
+#undef LPF_BUILD
   return hipGetLastError();
 }
 
 hipError_t launch_rec_update(const RecGeo &g, const StepCtl *ctl, const int2 *cand,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_rec_update, dim3((unsigned)((2 * (int64_t)g.Mc + 255) / 256)), dim3(256), 0,
-                     stream, g, ctl, cand);
+  const dim3 grid((unsigned)((2 * (int64_t)g.Mc + 255) / 256));
+#define LPF_UPDATE(M) hipLaunchKernelGGL(k_rec_update<M>, grid, dim3(256), 0, stream, g, ctl, cand)
+  LPF_REC_MASK_SWITCH(g.mask, LPF_UPDATE)
+#undef LPF_UPDATE
   return hipGetLastError();
 }
 
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream) {
-  dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
-  hipLaunchKernelGGL(k_rec_round, grid, dim3(256), 0, stream, L.rg, L.bits, L.cand,
-                     L.K, r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc,
-                     decide ? L.dl : nullptr, L.dl_t, L.dl_k, L.ctl);
+  const dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
+  int16_t *dl = decide ? L.dl : nullptr;
+#define LPF_ROUND(M)                                                                          \
+  hipLaunchKernelGGL(k_rec_round<M>, grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K,    \
+                     r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k, \
+                     L.ctl, L.order)
+  LPF_REC_MASK_SWITCH(L.rg.mask, LPF_ROUND)
+#undef LPF_ROUND
   return hipGetLastError();
 }
+
+#undef LPF_REC_MASK_SWITCH
 
 }  // namespace lpf

@@ -1,12 +1,13 @@
 // One annealing step's evaluation in rounds, with early exit.
 //
-// The K candidates of a step are evaluated in draw order, in rounds of 64, 448 and then the rest
+// The K candidates of a step are evaluated in evaluation order (draw order, or the ranking of
+// k_rank when an order array is given), in rounds of 64, 448 and then the rest
 // (at most 8192 each), so that a step whose first candidates are accepted costs one small round.
 // Each round is an evaluation kernel (recount method here, records method in k_rec.hip) that
 // adds every candidate's integer energy sum S = sum dL (Nt (dL + 2L) - 2 N T) into S_acc and
 // stores its dL (int16 per term and candidate), followed by k_round_decide, which applies the
 // Metropolis test of Alg. "annealing" (accept iff de <= 0 or U < exp(-de / T), de = S / (N^2 Nt),
-// eq. (LSE)) in draw order and records the first accepted candidate.  Rounds after an acceptance
+// eq. (LSE)) in evaluation order and records the first accepted candidate.  Rounds after an acceptance
 // return at once.  The step's result is the first accepted candidate over all K, exactly as if
 // every candidate had been evaluated.
 #include <limits.h>
@@ -36,12 +37,13 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
               const uint32_t *__restrict__ runs, unsigned phase_mask, int nv,
               const uint32_t *__restrict__ counts, const uint32_t *__restrict__ target, int64_t N,
               int64_t Nt, int64_t *__restrict__ S_acc, int16_t *__restrict__ dl,
-              const StepCtl *__restrict__ ctl) {
+              const StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
   extern __shared__ uint32_t lds[];
   if (ctl->done) return;  // an earlier round accepted
   const int kr = blockIdx.x * blockDim.x + threadIdx.x;  // index within the round
-  const int k = k0 + kr;
-  bool ok = kr < C && k < K;
+  const int i = k0 + kr;                                 // evaluation position
+  bool ok = kr < C && i < K;
+  const int k = ok && order ? order[i] : i;              // candidate (draw index)
   const bool in = ok;
   int a = -1, b = -1;
   if (ok) {
@@ -90,14 +92,15 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
 __global__ void __launch_bounds__(1024)
 k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
                const double *__restrict__ U, int k0, int C, double T, int64_t N, int64_t Nt,
-               StepCtl *__restrict__ ctl) {
+               StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
   __shared__ int s_first;
   if (ctl->done) return;
   if (threadIdx.x == 0) s_first = INT_MAX;
   __syncthreads();
   const double scale = (double)N * (double)N * (double)Nt;
   for (int base = 0; base < C; base += blockDim.x) {
-    const int kr = base + threadIdx.x, k = k0 + kr;
+    const int kr = base + threadIdx.x;
+    const int k = kr < C ? (order ? order[k0 + kr] : k0 + kr) : 0;
     if (kr < C && cand[k].x >= 0) {
       const double de = (double)S_acc[k] / scale;
       if (de <= 0.0 || U[k] < exp(-de / T)) atomicMin(&s_first, kr);
@@ -108,7 +111,7 @@ k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
     if (f != INT_MAX) break;
   }
   if (threadIdx.x == 0 && s_first != INT_MAX) {
-    const int ks = k0 + s_first;
+    const int ks = order ? order[k0 + s_first] : k0 + s_first;
     ctl->ks = ks;
     ctl->S = S_acc[ks];
     ctl->done = 1;
@@ -171,11 +174,12 @@ hipError_t launch_round_recount(const StepLaunch &L, const RoundPlan &r, bool de
     hipLaunchKernelGGL(k_round_delta<true>, grid, dim3(r.block),
                        (size_t)L.geo.total * sizeof(uint32_t), stream, L.E, L.geo, L.bits, L.W,
                        L.H, L.cand, L.K, r.k0, r.C, r.vecs, r.chunk_off, L.runs, L.phase_mask,
-                       L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl);
+                       L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl, L.order);
   else
     hipLaunchKernelGGL(k_round_delta<false>, grid, dim3(r.block), 0, stream, L.E, L.geo, L.bits,
                        L.W, L.H, L.cand, L.K, r.k0, r.C, r.vecs, r.chunk_off, L.runs,
-                       L.phase_mask, L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl);
+                       L.phase_mask, L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl,
+                       L.order);
   return hipGetLastError();
 }
 
@@ -192,7 +196,7 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
     e = L.records ? launch_rec_round(L, r, true, stream) : launch_round_recount(L, r, true, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_round_decide, dim3(1), dim3(std::min(1024, ((r.C + 63) / 64) * 64)), 0,
-                       stream, L.S_acc, L.cand, L.U, r.k0, r.C, L.T, L.N, L.Nt, L.ctl);
+                       stream, L.S_acc, L.cand, L.U, r.k0, r.C, L.T, L.N, L.Nt, L.ctl, L.order);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, L.st, L.ctl, L.K, L.cand,

@@ -176,7 +176,8 @@ struct lpf_anneal_s {
   const float *scores_ext = nullptr;
   double beta = 1.0, eps = 0.1;
   int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
-  DevBuf scores, cw1, cw0, cwb, eS, eCtl;
+  bool rank = false;               // evaluate learned draws by descending predicted gain
+  DevBuf scores, cw1, cw0, cwb, eS, eCtl, order;
 };
 
 // device memory the records method may take by itself (records + ones)
@@ -506,10 +507,13 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess)
     return hip_fail(e, "anneal: candidate scratch");
   const double *cw1 = nullptr, *cw0 = nullptr;
+  int draw = proposal;
   if (proposal == LPF_PROP_LEARNED) {
-    if ((e = a->cw1.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
-        (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
-        (e = a->cwb.ensure(sizeof(double) * 4 * (size_t)((N + 1023) / 1024))) != hipSuccess)
+    // beta = 0 draws exactly the uniform candidates; the scores then only rank them
+    const bool weighted = a->beta > 0.0;
+    if (weighted && ((e = a->cw1.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+                     (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+                     (e = a->cwb.ensure(sizeof(double) * 4 * (size_t)((N + 1023) / 1024))) != hipSuccess))
       return hip_fail(e, "anneal: proposal scratch");
     if (a->learn_age == 0 || a->learn_age >= a->refresh) {
       const float *sc = a->scores_ext;
@@ -520,16 +524,21 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
           return hip_fail(e, "anneal: proposal network");
         sc = (const float *)a->scores.p;
       }
-      if ((e = launch_learn_weights(a->dev, sc, a->beta, (double *)a->cw1.p, (double *)a->cw0.p, N,
+      if (weighted &&
+          (e = launch_learn_weights(a->dev, sc, a->beta, (double *)a->cw1.p, (double *)a->cw0.p, N,
                                     (double *)a->cwb.p, s)) != hipSuccess)
         return hip_fail(e, "anneal: proposal weights");
       a->learn_age = 0;
     }
     ++a->learn_age;
-    cw1 = (const double *)a->cw1.p;
-    cw0 = (const double *)a->cw0.p;
+    if (weighted) {
+      cw1 = (const double *)a->cw1.p;
+      cw0 = (const double *)a->cw0.p;
+    } else {
+      draw = LPF_PROP_UNIFORM;
+    }
   }
-  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, proposal, cw1, cw0, a->eps,
+  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, draw, cw1, cw0, a->eps,
                           (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, S_acc, ctl,
                           s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
@@ -1003,6 +1012,18 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p)) != LPF_OK)
     return st;
   L.reset_done = true;
+  if (proposal == LPF_PROP_LEARNED && a->rank) {
+    const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
+    const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
+    if ((e = a->order.ensure(sizeof(int32_t) * (size_t)K + 8 * ntop)) != hipSuccess)
+      return hip_fail(e, "anneal_step: order");
+    int32_t *ord = (int32_t *)a->order.p;
+    float *top_key = (float *)(ord + K);
+    int *top_id = (int *)(top_key + ntop);
+    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, top_key, top_id, s)) != hipSuccess)
+      return hip_fail(e, "anneal_step: ranking");
+    L.order = (const int32_t *)a->order.p;
+  }
   if (!rec) {
     L.E = (const uint32_t *)a->E3.p;
     L.geo = plan->geo;
@@ -1089,6 +1110,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->cw1.release();
     a->cw0.release();
     a->cwb.release();
+    a->order.release();
     a->eS.release();
     a->eCtl.release();
   }
@@ -1448,14 +1470,16 @@ void lpf_cnn_destroy(lpf_cnn n) {
 }
 
 lpf_status lpf_anneal_set_proposal(lpf_anneal a, lpf_cnn net, const float *scores, float beta,
-                                   float eps_uniform, int refresh) {
+                                   float eps_uniform, int refresh, int rank) {
   if (!a) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: state is NULL");
   if (net && (net->W != a->W || net->H != a->H))
     return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: network built for another cell size");
   if (!(beta >= 0.f) || !(eps_uniform >= 0.f && eps_uniform <= 1.f))
     return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: beta >= 0, 0 <= eps_uniform <= 1");
   if (refresh < 1) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: refresh >= 1");
+  if (rank != 0 && rank != 1) return fail(LPF_E_INVAL, "lpf_anneal_set_proposal: rank is 0 or 1");
   a->refresh = refresh;
+  a->rank = rank != 0;
   a->learn_age = 0;
   a->net = net;
   a->scores_ext = net ? nullptr : scores;

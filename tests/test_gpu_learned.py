@@ -90,6 +90,9 @@ def test_learned_draws_follow_scores(ctx):
     # eps = 1 falls back to uniform draws: the same candidates as LPF_PROP_UNIFORM
     ch.set_proposal(scores=sc, beta=beta, eps_uniform=1.0)
     assert torch.equal(ch.propose(256, 2), ch.propose(256, 0))
+    # beta = 0 draws exactly the uniform candidates too
+    ch.set_proposal(scores=sc, beta=0.0, eps_uniform=0.0, rank=True)
+    assert torch.equal(ch.propose(4096, 2), ch.propose(4096, 0))
     ch.close()
 
 
@@ -113,3 +116,50 @@ def test_learned_chain_stays_exact(ctx, refresh):
     assert abs(float(ch.e.cpu()[0]) - e) <= 1e-12 * max(e, 1e-30)
     ch.close()
     net.close()
+
+
+@pytest.mark.parametrize("K", [300, 5000])
+def test_ranked_step_takes_first_accepted_in_rank_order(ctx, K):
+    # with rank on, a step evaluates the 64 draws with the highest fp32 score[a] + score[b] among
+    # the first min(K, 4096) (best first, ties by draw index), then every other draw in draw
+    # order, and applies the first that passes the Metropolis test: checked against exact
+    # energies and the Philox uniforms of each draw
+    import torch
+    from paper_1601_04359_amd import step_records
+    print(f"[gpu] ranked learned step K={K}", flush=True)
+    tgt, target, cell = _problem(side=32)
+    seed = 13
+    ch = _chain(ctx, cell, 5, 3, target, tgt.size, seed)
+    g = np.random.default_rng(5)
+    score = g.normal(size=32 * 32).astype(np.float32)
+    score[:40] = score[40]  # ties
+    sc = torch.from_numpy(score).cuda()
+    ch.set_proposal(scores=sc, beta=1.0, eps_uniform=0.2, rank=True)
+    rec = torch.empty((1, 5), dtype=torch.int64, device="cuda")
+    taken = 0
+    for step, T in enumerate([2e-4, 5e-5, 1e-5, 1e-6, 1e-7]):
+        cand = ch.propose(K, 2).cpu().numpy()
+        de = ch.delta_energy(torch.from_numpy(cand).cuda()).cpu().numpy()
+        R = min(K, 4096)
+        a, b = cand[:R, 0], cand[:R, 1]
+        void = (a < 0) | (b < 0)
+        key = np.where(void, -np.inf, score[np.maximum(a, 0)] + score[np.maximum(b, 0)])
+        top = list(np.lexsort((np.arange(R), -key.astype(np.float64)))[:64])
+        chosen = set(top)
+        order = top + [k for k in range(K) if k not in chosen]
+        expect = -1
+        for k in order:
+            if cand[k, 0] < 0:
+                continue
+            c = oracle.philox4x64(np.array([step, k, 0, 0], np.uint64),
+                                  np.array([seed, 0x6C7066], np.uint64))
+            U = float(c[2] >> np.uint64(11)) * 2.0 ** -53
+            if de[k] <= 0.0 or U < np.exp(-de[k] / T):
+                expect = k
+                break
+        ch.step(K, T, rec[0], 2)
+        r = step_records(rec)
+        assert int(r["k"][0]) == expect, (step, int(r["k"][0]), expect)
+        taken += expect >= 0
+    assert taken >= 3
+    ch.close()
