@@ -27,16 +27,26 @@ P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # HBM bytes per k_lpf_full launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by the
 # same counters on a 256 MiB copy), profiles/k_lpf_full_512_c128.md.  Valid only for the kernel
-# source the counters were taken on; reported as null once that source changes.
-MEASURED_TRAFFIC = {"src_sha256_16": "4987b0f362ee7f9a", "bytes": int(1998.25 * 1024)}
+# source and tile-shape choice the counters were taken on; reported as null once either changes.
+MEASURED_TRAFFIC = {"src_sha256_16": "1461ceece28f4d80", "bytes": int(2055.15 * 1024)}
+
+
+def source_hash() -> str:
+    """Hash of the kernel source and of the host function that picks its tile shape."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1601_04359_amd", "csrc")
+    h = hashlib.sha256()
+    with open(os.path.join(csrc, "k_full.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(csrc, "lpf_api.hip"), "rb") as f:
+        api = f.read()
+    i = api.index(b"bool choose_shape(")
+    h.update(api[i:api.index(b"\n}\n", i)])
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
-    import hashlib
-    path = os.path.join(ROOT, "paper_1601_04359_amd", "csrc", "k_full.hip")
-    with open(path, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC["bytes"] if sha == MEASURED_TRAFFIC["src_sha256_16"] else None
+    return MEASURED_TRAFFIC["bytes"] if source_hash() == MEASURED_TRAFFIC["src_sha256_16"] else None
 
 
 def path_pixels(cx: int, cy: int) -> int:

@@ -227,7 +227,8 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   int fR = c->force_R ? c->force_R : (tuned ? tuned->R : 0);
   int fW = c->force_wpg ? c->force_wpg : (tuned ? tuned->wpg : 0);
   int fL = c->force_lds ? c->force_lds : (tuned ? tuned->lds : 0);
-  int R = fR ? fR : std::min(8, next_pow2(swd));
+  // up to 16 words per lane (the autotuner's choice at W = 128, 256, 512 and 1024)
+  int R = fR ? fR : std::min(16, next_pow2(swd));
   int S = c->force_S ? c->force_S : next_pow2((swd + R - 1) / R);
   if (S > 64) {
     why = "image too wide for the lane layout (W > 64*R*32)";
