@@ -324,7 +324,7 @@ k_rank_merge(const float *__restrict__ top_key, const int *__restrict__ top_id, 
   __shared__ float sk[512];
   __shared__ int si[512];
   __shared__ uint32_t sel[kRankMax / 32];
-  __shared__ int part[512];
+  __shared__ int part[8];
   const int R = min(K, kRankMax);
   const int nchunks = (R + 511) / 512;
   const int t = threadIdx.x;
@@ -350,15 +350,18 @@ k_rank_merge(const float *__restrict__ top_key, const int *__restrict__ top_id, 
     const int i = i0 + j;
     cnt += (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) ? 1 : 0;
   }
-  part[t] = cnt;
-  __syncthreads();
-  for (int o = 1; o < 512; o <<= 1) {
-    const int v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  // inclusive scan of the counts: within the wave by shuffles, then over the 8 wave totals
+  int x = cnt;
+  const int lane = t & 63, wave = t >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  int pos = T + part[t] - cnt;
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += part[w];
+  int pos = T + off + x - cnt;
   for (int j = 0; j < per; ++j) {
     const int i = i0 + j;
     if (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) order[pos++] = i;

@@ -294,35 +294,49 @@ k_cnn_conv_bwd_weight(const uint16_t *__restrict__ dZ, const uint16_t *__restric
 }
 
 // --------------------------------------------------------------------- gradient assembly
-// Sums the per-block partials in block order and writes the packed gradient:
-// W1 [9][16][2], b1, W2 [9][16][16], b2, W3 [9][16][16], b3, W4 [16], b4.
-__global__ void k_cnn_grad_sum(const float *__restrict__ p1, const float *__restrict__ p2,
-                               const float *__restrict__ p3, int nb_conv,
-                               const float *__restrict__ ph, int nb_head,
-                               float *__restrict__ grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kCnnParams) return;
+// The packed gradient (W1 [9][16][2], b1, W2 [9][16][16], b2, W3 [9][16][16], b3, W4 [16], b4)
+// from the per-block partials, in a fixed order: slice s of kGradSlices sums its contiguous range
+// of blocks in block order (k_cnn_grad_part), then the slices are added in slice order
+// (k_cnn_grad_sum).
+constexpr int kGradSlices = 64;
+
+__device__ __forceinline__ float grad_partial(const float *__restrict__ p1,
+                                              const float *__restrict__ p2,
+                                              const float *__restrict__ p3,
+                                              const float *__restrict__ ph, int i, int b) {
   const int stride = 9 * 256 + 16;
-  float s = 0.f;
   if (i < 288) {  // W1[t][co][ci<2]
     const int t = i / 32, co = (i / 2) % 16, ci = i % 2;
-    for (int b = 0; b < nb_conv; ++b) s += p1[(size_t)b * stride + t * 256 + co * 16 + ci];
-  } else if (i < 304) {
-    for (int b = 0; b < nb_conv; ++b) s += p1[(size_t)b * stride + 9 * 256 + (i - 288)];
-  } else if (i < 2608) {
-    const int k = i - 304;
-    for (int b = 0; b < nb_conv; ++b) s += p2[(size_t)b * stride + k];
-  } else if (i < 2624) {
-    for (int b = 0; b < nb_conv; ++b) s += p2[(size_t)b * stride + 9 * 256 + (i - 2608)];
-  } else if (i < 4928) {
-    const int k = i - 2624;
-    for (int b = 0; b < nb_conv; ++b) s += p3[(size_t)b * stride + k];
-  } else if (i < 4944) {
-    for (int b = 0; b < nb_conv; ++b) s += p3[(size_t)b * stride + 9 * 256 + (i - 4928)];
-  } else {
-    const int c = i - 4944;  // 0..15: W4, 16: b4
-    for (int b = 0; b < nb_head; ++b) s += ph[(size_t)b * 17 + c];
+    return p1[(size_t)b * stride + t * 256 + co * 16 + ci];
   }
+  if (i < 304) return p1[(size_t)b * stride + 9 * 256 + (i - 288)];
+  if (i < 2608) return p2[(size_t)b * stride + (i - 304)];
+  if (i < 2624) return p2[(size_t)b * stride + 9 * 256 + (i - 2608)];
+  if (i < 4928) return p3[(size_t)b * stride + (i - 2624)];
+  if (i < 4944) return p3[(size_t)b * stride + 9 * 256 + (i - 4928)];
+  return ph[(size_t)b * 17 + (i - 4944)];  // 0..15: W4, 16: b4
+}
+
+__global__ void k_cnn_grad_part(const float *__restrict__ p1, const float *__restrict__ p2,
+                                const float *__restrict__ p3, int nb_conv,
+                                const float *__restrict__ ph, int nb_head,
+                                float *__restrict__ slices) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kCnnParams) return;
+  const int sl = blockIdx.y;
+  const int nb = i < 4944 ? nb_conv : nb_head;
+  const int per = (nb + kGradSlices - 1) / kGradSlices;
+  const int b0 = min(nb, sl * per), b1 = min(nb, b0 + per);
+  float s = 0.f;
+  for (int b = b0; b < b1; ++b) s += grad_partial(p1, p2, p3, ph, i, b);
+  slices[(size_t)sl * kCnnParams + i] = s;
+}
+
+__global__ void k_cnn_grad_sum(const float *__restrict__ slices, float *__restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kCnnParams) return;
+  float s = 0.f;
+  for (int sl = 0; sl < kGradSlices; ++sl) s += slices[(size_t)sl * kCnnParams + i];
   grad[i] = s;
 }
 
@@ -403,8 +417,10 @@ hipError_t cnn_grad(const CnnBufs &B, const uint64_t *bits, int W, int H, int ba
                      B.dZ1, W, H, np);
   hipLaunchKernelGGL(k_cnn_conv_bwd_weight, dim3(cb), dim3(256), 0, s, B.dZ1, B.X0, 4, W, H, np,
                      B.part1);
-  hipLaunchKernelGGL(k_cnn_grad_sum, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, B.part1,
-                     B.part2, B.part3, cb, B.part_h, nb, grad);
+  hipLaunchKernelGGL(k_cnn_grad_part, dim3((kCnnParams + 255) / 256, kGradSlices), dim3(256), 0, s,
+                     B.part1, B.part2, B.part3, cb, B.part_h, nb, B.slices);
+  hipLaunchKernelGGL(k_cnn_grad_sum, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, B.slices,
+                     grad);
   return hipGetLastError();
 }
 

@@ -118,32 +118,34 @@ k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
   g.ones[(size_t)v * N + x] = (uint8_t)o;
 }
 
-// Records of 64 pixels (one wave) over one 32-dword tile of the record per workgroup, staged in
-// LDS so that each pixel's record is written with contiguous stores.
+// Records of 64 pixels over one 32-dword tile of the record per workgroup (the waves of the
+// workgroup take the tile's dwords in turn), staged in LDS so that each pixel's record is written with contiguous stores.  Per record
+// bit j the tables give vbit[j] = (v << 8) | n and pix[j] = p_k, independent scalar loads.
 template <unsigned MASK>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_rec_build(RecGeo g) {
   using P = Planes<MASK>;
   const int32_t *__restrict__ vbit = g.vbit;
   __shared__ uint32_t tile[P::n][64][33];
   const int64_t N = (int64_t)g.W * g.H;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t q0 = (int64_t)blockIdx.x * 64;
   const int64_t q = q0 + lane;
   const bool valid = q < N;
   const int qy = valid ? (int)(q / g.W) : 0, qx = valid ? (int)(q - (int64_t)qy * g.W) : 0;
   const int w0 = blockIdx.y * 32;
   const int nw = min(32, g.Rw - w0);
-  for (int wd = 0; wd < nw; ++wd) {
+  const int nwaves = (int)(blockDim.x >> 6);
+  for (int wd = wv; wd < nw; wd += nwaves) {
     uint32_t acc[P::n];
 #pragma unroll
     for (int pl = 0; pl < P::n; ++pl) acc[pl] = 0u;
-    for (int t = 0; t < 32; ++t) {
-      const int j = (w0 + wd) * 32 + t;
-      if (j >= g.Mc) break;
-      const int v = vbit[j];
-      const int n = g.meta[v].y;
-      const int32_t p = g.pix[j];
+    const int jb = (w0 + wd) * 32;
+    const int tn = min(32, g.Mc - jb);
+    for (int t = 0; t < tn; ++t) {
+      const int vn = vbit[jb + t];
+      const int32_t p = g.pix[jb + t];
+      const int v = vn >> 8, n = vn & 255;
       const int xx = wrapi(qx - pix_dx(p), g.W), yy = wrapi(qy - pix_dy(p), g.H);
       const int o = valid ? (int)g.ones[(size_t)v * N + (size_t)yy * g.W + xx] : -1;
 #pragma unroll
@@ -154,7 +156,8 @@ k_rec_build(RecGeo g) {
     for (int pl = 0; pl < P::n; ++pl) tile[pl][lane][wd] = acc[pl];
   }
   __syncthreads();
-  for (int pq = 0; pq < 64 && q0 + pq < N; ++pq) {
+  // write out: wave wv writes pixels wv, wv + nwaves, ...; lanes over the tile's dwords
+  for (int pq = wv; pq < 64 && q0 + pq < N; pq += nwaves) {
     uint32_t *R = g.rec + (size_t)(q0 + pq) * g.rstride + w0;
     if (lane < nw)
 #pragma unroll
@@ -270,7 +273,7 @@ k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__
   const int64_t N = (int64_t)g.W * g.H;
   const int side = t >= g.Mc;
   const int j = (int)(side ? t - g.Mc : t);
-  const int v = g.vbit[j];
+  const int v = g.vbit[j] >> 8;
   const int4 m = g.meta[v];
   const int off = m.x, n = m.y;
   const int a = cand[ks].x, b = cand[ks].y;
@@ -315,7 +318,7 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((g.Rw + 31) / 32));
-#define LPF_BUILD(M) hipLaunchKernelGGL(k_rec_build<M>, grid, dim3(64), 0, stream, g)
+#define LPF_BUILD(M) hipLaunchKernelGGL(k_rec_build<M>, grid, dim3(256), 0, stream, g)
   LPF_REC_MASK_SWITCH(g.mask, LPF_BUILD)
 #undef LPF_BUILD
   return hipGetLastError();

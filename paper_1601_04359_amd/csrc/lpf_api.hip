@@ -631,7 +631,7 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
           px = dx >= 0 ? g : -g;
         }
         pix.push_back((int32_t)((uint32_t)(uint16_t)(int16_t)px | ((uint32_t)py << 16)));
-        vbit.push_back((int32_t)i);
+        vbit.push_back((int32_t)((i << 8) | n));
       }
     }
     RecGeo g{};
@@ -1392,6 +1392,7 @@ lpf_status lpf_cnn_create(lpf_ctx c, int W, int H, int max_batch, int max_sample
   get((void **)&B.part2, 4 * (size_t)cb * (9 * 256 + 16));
   get((void **)&B.part3, 4 * (size_t)cb * (9 * 256 + 16));
   get((void **)&B.part_h, 4 * (size_t)hb * 17);
+  get((void **)&B.slices, 4 * (size_t)64 * kCnnParams);
   hipStream_t s = (hipStream_t)stream;
   if (e == hipSuccess) {
     if (params) e = hipMemcpyAsync(B.prm, params, 4 * kCnnParams, hipMemcpyDeviceToDevice, s);

@@ -103,7 +103,7 @@ struct RecGeo {
   const int32_t *pix;   // [Mc] path pixel offsets, (dx & 0xffff) | (dy << 16)
   uint32_t *rec;        // [W*H][plane A phases, plane B phases][Rw]
   uint8_t *ones;        // [nv][W*H]
-  const int32_t *vbit;  // [Mc] vector of each record bit
+  const int32_t *vbit;  // [Mc] (v << 8) | n of the vector of each record bit
   unsigned mask;        // phases kept (LPF_PHASE0 | LPF_PHASE1 bits)
 };
 
@@ -208,6 +208,7 @@ struct CnnBufs {
   float *S, *r;                                  // scores, residuals
   int64_t *dS;                                   // score gradient, 2^-40 fixed point
   float *part1, *part2, *part3, *part_h;         // per-block gradient partials
+  float *slices;                                 // [64][kCnnParams] partial sums of the partials
 };
 hipError_t cnn_forward(const CnnBufs &B, const uint64_t *bits, int W, int H, int batch,
                        float *S, hipStream_t s);
