@@ -179,8 +179,7 @@ lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, 
  * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),
  * compute each one's exact energy change de against the current state, and apply the first, in
  * draw order, with de <= 0 or U < exp(-de/T) (the Metropolis rule for a minimisation).  The
- * candidates are evaluated in rounds in draw order (64, 64, 128, 256, ... candidates, at most
- * 8192 per round) and rounds after an acceptance are skipped, which gives the same result as
+ * candidates are evaluated in rounds (64 candidates, then the rest, at most 8192 per round) and rounds after an acceptance are skipped, which gives the same result as
  * evaluating all of them.  The step's record is written to *out (device).  Everything stays on
  * the device.
  * Errors: LPF_E_INVAL (n_candidates outside [1, 2^20], proposal, T <= 0), LPF_E_NOMEM,

@@ -1,7 +1,7 @@
 // Device-resident simulated annealing on the lineal path function (Sec. 4, Alg. "annealing",
 // objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn (here), their exact
 // energy changes are evaluated against the current state in evaluation order (draw order, or the
-// learned ranking of k_rank) and the first candidate that passes the Metropolis test is applied
+// learned ranking of k_rank_chunks / k_rank_merge) and the first candidate that passes the Metropolis test is applied
 // (k_step.hip).  Rejected candidates leave the state unchanged, so this is the sequential chain
 // of the algorithm over those draws with the step's later candidates unused.  Nothing returns to
 // the host inside a step.

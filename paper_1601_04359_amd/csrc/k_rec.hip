@@ -167,7 +167,9 @@ k_rec_build(RecGeo g) {
 
 // Exact dL of interchange (a, b) for vector v, one entry per kept phase.  Invalid or same-phase
 // pairs change nothing.
-template <unsigned MASK>
+// ORDERED: the pair is known to be (phase-1 pixel, phase-0 pixel), as the annealer's draws are,
+// so the image is not read.
+template <unsigned MASK, bool ORDERED>
 __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__restrict__ bits,
                                           int a, int b, int v, int4 m, int (&d)[2]) {
   using P = Planes<MASK>;
@@ -175,14 +177,16 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
   d[1] = 0;
   const int64_t N = (int64_t)g.W * g.H;
   if (a < 0 || b < 0 || a >= N || b >= N || a == b || v >= g.nv) return;
-  const int wpr = (g.W + 63) >> 6;
   int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
-  const int va = image_bit(bits, wpr, ax, ay), vb = image_bit(bits, wpr, bx, by);
-  if (va == vb) return;
-  if (va == 0) {  // a leaves phase 1, b enters it
-    int t = a; a = b; b = t;
-    t = ax; ax = bx; bx = t;
-    t = ay; ay = by; by = t;
+  if (!ORDERED) {
+    const int wpr = (g.W + 63) >> 6;
+    const int va = image_bit(bits, wpr, ax, ay), vb = image_bit(bits, wpr, bx, by);
+    if (va == vb) return;
+    if (va == 0) {  // a leaves phase 1, b enters it
+      int t = a; a = b; b = t;
+      t = ax; ax = bx; bx = t;
+      t = ay; ay = by; by = t;
+    }
   }
   const int off = m.x, n = m.y, len = n + 1;
   const uint32_t *RA = g.rec + (size_t)a * g.rstride;                // planes A of a
@@ -212,7 +216,7 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
 // positions k0 .. k0 + C - 1 (candidate order[i], or i without an order).  Lanes run over
 // vectors; the candidate is uniform.  Each block adds its part of a candidate's
 // energy sum into S_acc[k] and stores the candidate's dL when dl is given.
-template <unsigned MASK>
+template <unsigned MASK, bool ORDERED>
 __global__ void __launch_bounds__(256)
 k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict__ cand, int K,
             int k0, int C, const uint32_t *__restrict__ counts,
@@ -238,7 +242,7 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
     const int k = order ? order[k0 + kr] : k0 + kr;  // candidate (draw index)
     const int2 ab = cand[k];
     int d[2];
-    rec_delta<MASK>(g, bits, ab.x, ab.y, v, m, d);
+    rec_delta<MASK, ORDERED>(g, bits, ab.x, ab.y, v, m, d);
     int64_t S = 0;
     if (vin) {
 #pragma unroll
@@ -337,12 +341,18 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
                             hipStream_t stream) {
   const dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
   int16_t *dl = decide ? L.dl : nullptr;
-#define LPF_ROUND(M)                                                                          \
-  hipLaunchKernelGGL(k_rec_round<M>, grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K,    \
-                     r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k, \
+#define LPF_ROUND_O(M, O)                                                                      \
+  hipLaunchKernelGGL((k_rec_round<M, O>), grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K, \
+                     r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k,   \
                      L.ctl, L.order)
+#define LPF_ROUND(M)               \
+  if (L.ordered)                   \
+    LPF_ROUND_O(M, true);          \
+  else                             \
+    LPF_ROUND_O(M, false);
   LPF_REC_MASK_SWITCH(L.rg.mask, LPF_ROUND)
 #undef LPF_ROUND
+#undef LPF_ROUND_O
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // One annealing step's evaluation in rounds, with early exit.
 //
 // The K candidates of a step are evaluated in evaluation order (draw order, or the ranking of
-// k_rank when an order array is given), in rounds of 64, 448 and then the rest
+// k_rank_chunks / k_rank_merge when an order array is given), in rounds of 64 and then the rest
 // (at most 8192 each), so that a step whose first candidates are accepted costs one small round.
 // Each round is an evaluation kernel (recount method here, records method in k_rec.hip) that
 // adds every candidate's integer energy sum S = sum dL (Nt (dL + 2L) - 2 N T) into S_acc and

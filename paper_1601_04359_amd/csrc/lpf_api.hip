@@ -546,13 +546,13 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   return LPF_OK;
 }
 
-// Candidate rounds of a step: 64, 448, then the rest in rounds of at most 8192.  A step whose
-// first candidates are accepted costs one small round; a skipped round costs two empty launches.
+// Candidate rounds of a step: 64, then the rest in rounds of at most 8192.  A step whose first
+// candidates are accepted costs one small round; a skipped round costs two empty launches.
 std::vector<RoundPlan> step_rounds(int K, bool decide) {
   std::vector<RoundPlan> r;
   int k0 = 0;
   while (k0 < K) {
-    int C = decide ? (k0 == 0 ? 64 : (k0 == 64 ? 448 : 8192)) : 8192;
+    int C = decide ? (k0 == 0 ? 64 : 8192) : 8192;
     C = std::min(std::min(C, 8192), K - k0);
     RoundPlan p{};
     p.k0 = k0;
@@ -1013,6 +1013,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p)) != LPF_OK)
     return st;
   L.reset_done = true;
+  L.ordered = true;  // draws take a from the phase-1 list and b from the phase-0 list
   if (proposal == LPF_PROP_LEARNED && a->rank) {
     const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
     const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;

@@ -110,6 +110,7 @@ struct RecGeo {
 struct StepLaunch {
   bool records;              // evaluation method: placement-state records, else recount
   bool reset_done;           // ctl and S_acc already zeroed by the candidate draw
+  bool ordered;              // candidates are (phase-1 pixel, phase-0 pixel) pairs
   const uint32_t *E;
   DeltaGeo geo;
   const uint64_t *bits;
