@@ -70,6 +70,16 @@ class Context:
         _abi.lpf_full(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
         return out
 
+    def full_enhanced(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                      phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF, out=None,
+                      stream=None) -> torch.Tensor:
+        """Same counts as full(), with segments abandoned once no start pixel can still count."""
+        if out is None:
+            out = torch.empty(counts_shape(cx, cy, phase_mask, layout), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_full_enhanced(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
+        return out
+
     def delta_swap(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                    swaps: torch.Tensor, phase_mask: int = LPF_BOTH, out=None,
                    stream=None) -> torch.Tensor:

@@ -80,9 +80,15 @@ hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
 // Pixels are taken in pairs: two funnel shifts, one 3-input AND (v_bitop3_b32) and one 3-input
 // OR (v_or3_b32) per word; when both pixels of a pair read the same dwords (same row, same
 // word column) the dwords are loaded once.
-template <int R, bool XM, bool Q2>
+//
+// SKIP (the paper's "enhanced" evaluation, Sec. 3.3, done per wave): every 16 pixels the wave
+// stops when no start pixel of its rows can still count for a requested phase (phase 1 needs a
+// set bit of A, phase 0 a clear bit of O, both under the lane's valid-bit mask mk).  Further
+// pixels only clear bits of A and set bits of O, so the counts are those of the full product.
+template <int R, bool XM, bool Q2, bool SKIP>
 __device__ __forceinline__ void path_product(const uint32_t *__restrict__ base, int rst, int adx,
-                                             int n, int m, uint32_t (&A)[R], uint32_t (&O)[R]) {
+                                             int n, int m, uint32_t (&A)[R], uint32_t (&O)[R],
+                                             const uint32_t (&mk)[R], unsigned phase_mask) {
   int err = n, q = 0;
   auto advance = [&]() {
     err += 2 * m;
@@ -135,6 +141,17 @@ __device__ __forceinline__ void path_product(const uint32_t *__restrict__ base, 
       A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0[i], t1[i], 0x80);
       O[i] = O[i] | t0[i] | t1[i];
     }
+    if constexpr (SKIP) {
+      if ((k & 15) == 14) {
+        uint32_t live = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (phase_mask & 2u) live |= A[i] & mk[i];
+          if (phase_mask & 1u) live |= ~O[i] & mk[i];
+        }
+        if (!__any(live != 0u)) return;
+      }
+    }
   }
   if (k == n) {  // odd pixel count: the last pixel alone
     int off, sh;
@@ -176,7 +193,7 @@ __device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int 
 // their vectors over every row tile of the image.  lds: staged rows; cnt: per-wave count slots
 // (used only when the image has several row tiles).  Each count is written once, by lane 0 of
 // the wave owning the vector.
-template <int R>
+template <int R, bool SKIP>
 __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg,
                                              unsigned phase_mask, uint32_t *__restrict__ lds,
                                              uint32_t *__restrict__ cnt) {
@@ -215,27 +232,27 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
       for (int band = 0; band < nbands; ++band) {
         const int row = band * rpw + r_in;
         const uint32_t *base = lds + row * I.rst + strip * R;
-        uint32_t A[R], O[R];
+        const bool row_ok = row < rows_here;
+        uint32_t A[R], O[R], mk[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           A[i] = 0xffffffffu;
           O[i] = 0u;
+          const int w = strip * R + i;
+          const uint32_t mw = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
+          mk[i] = row_ok ? mw : 0u;
         }
         if (xm) {
-          if (dx < 0) path_product<R, true, true>(base, I.rst, adx, n, m, A, O);
-          else path_product<R, true, false>(base, I.rst, adx, n, m, A, O);
+          if (dx < 0) path_product<R, true, true, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
+          else path_product<R, true, false, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
         } else {
-          if (dx < 0) path_product<R, false, true>(base, I.rst, adx, n, m, A, O);
-          else path_product<R, false, false>(base, I.rst, adx, n, m, A, O);
+          if (dx < 0) path_product<R, false, true, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
+          else path_product<R, false, false, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
         }
-        const bool row_ok = row < rows_here;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-          const int w = strip * R + i;
-          uint32_t mk = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
-          mk = row_ok ? mk : 0u;
-          c1 += __popc(A[i] & mk);
-          c0 += __popc(~O[i] & mk);
+          c1 += __popc(A[i] & mk[i]);
+          c0 += __popc(~O[i] & mk[i]);
         }
       }
       c0 = wave_sum(c0);
@@ -265,11 +282,11 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
 }
 
 // One image, one workgroup per work item (item = blockIdx.x).
-template <int R>
+template <int R, bool SKIP>
 __global__ void __launch_bounds__(1024)
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
-  process_item<R>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
+  process_item<R, SKIP>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
 }
 
 // Many images, persistent workgroups drawing work items from a device counter in descending
@@ -288,11 +305,11 @@ k_lpf_batch(const FullImg *__restrict__ imgs, const int2 *__restrict__ items, in
     const int2 w = items[it];
     const FullImg I = imgs[w.x];
     switch (I.R) {
-      case 1: process_item<1>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 2: process_item<2>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 4: process_item<4>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 8: process_item<8>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      default: process_item<16>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 1: process_item<1, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 2: process_item<2, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 4: process_item<4, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      case 8: process_item<8, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      default: process_item<16, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
     }
     __syncthreads();  // the item's last tile is no longer read before the next staging
   }
@@ -308,27 +325,34 @@ size_t full_lds_bytes(const FullShape &sh, int wpg) {
   return b;
 }
 
-template <int R>
+template <int R, bool SKIP>
 static hipError_t launch_full_r(const FullImg &I, const FullShape &sh, unsigned phase_mask,
                                 hipStream_t stream) {
   const int nwg = sh.nbins / sh.wpg;
   const size_t lds = full_lds_bytes(sh, sh.wpg);
   const int cnt_off = sh.lds_rows * sh.rst;
-  hipLaunchKernelGGL(k_lpf_full<R>, dim3(nwg), dim3(64 * sh.wpg), lds, stream, I, sh.wpg,
+  hipLaunchKernelGGL((k_lpf_full<R, SKIP>), dim3(nwg), dim3(64 * sh.wpg), lds, stream, I, sh.wpg,
                      phase_mask, cnt_off);
   return hipGetLastError();
 }
 
-hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask,
-                       hipStream_t stream) {
+template <bool SKIP>
+static hipError_t launch_full_s(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                                hipStream_t stream) {
   switch (sh.R) {
-    case 1: return launch_full_r<1>(I, sh, phase_mask, stream);
-    case 2: return launch_full_r<2>(I, sh, phase_mask, stream);
-    case 4: return launch_full_r<4>(I, sh, phase_mask, stream);
-    case 8: return launch_full_r<8>(I, sh, phase_mask, stream);
-    case 16: return launch_full_r<16>(I, sh, phase_mask, stream);
+    case 1: return launch_full_r<1, SKIP>(I, sh, phase_mask, stream);
+    case 2: return launch_full_r<2, SKIP>(I, sh, phase_mask, stream);
+    case 4: return launch_full_r<4, SKIP>(I, sh, phase_mask, stream);
+    case 8: return launch_full_r<8, SKIP>(I, sh, phase_mask, stream);
+    case 16: return launch_full_r<16, SKIP>(I, sh, phase_mask, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask, bool skip,
+                       hipStream_t stream) {
+  return skip ? launch_full_s<true>(I, sh, phase_mask, stream)
+              : launch_full_s<false>(I, sh, phase_mask, stream);
 }
 
 hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
@@ -380,9 +404,11 @@ hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int m
 
 hipError_t prepare_full_kernels(int max_lds_bytes) {
   hipError_t e = hipSuccess;
-  const void *fns[] = {(const void *)k_lpf_full<1>, (const void *)k_lpf_full<2>,
-                       (const void *)k_lpf_full<4>, (const void *)k_lpf_full<8>,
-                       (const void *)k_lpf_full<16>};
+  const void *fns[] = {(const void *)k_lpf_full<1, false>, (const void *)k_lpf_full<2, false>,
+                       (const void *)k_lpf_full<4, false>, (const void *)k_lpf_full<8, false>,
+                       (const void *)k_lpf_full<16, false>, (const void *)k_lpf_full<1, true>,
+                       (const void *)k_lpf_full<2, true>, (const void *)k_lpf_full<4, true>,
+                       (const void *)k_lpf_full<8, true>, (const void *)k_lpf_full<16, true>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
     if (r != hipSuccess) e = r;

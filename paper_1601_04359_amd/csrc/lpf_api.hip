@@ -784,8 +784,10 @@ lpf_status lpf_pack(lpf_ctx c, const uint8_t *img, int W, int H, uint64_t *bits,
   return LPF_OK;
 }
 
-lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
-                    unsigned phase_mask, int out_layout, uint32_t *counts, void *stream) {
+namespace {
+lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream,
+                     bool skip) {
   if (!c) return fail(LPF_E_INVAL, "lpf_full: ctx is NULL");
   if (!bits || !counts) return fail(LPF_E_INVAL, "lpf_full: NULL buffer");
   if (W < 1 || H < 1 || W > 65535 || H > 65535) return fail(LPF_E_INVAL, "lpf_full: W/H out of range");
@@ -808,8 +810,20 @@ lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int c
   uint32_t *ext = (uint32_t *)c->ext.p;
   if ((e = launch_ext(bits, W, H, sh.we, ext, s)) != hipSuccess) return hip_fail(e, "lpf_full: ext");
   const FullImg I = make_img(*plan, ext, counts, W, H, cx, cy, out_layout);
-  if ((e = launch_full(I, sh, phase_mask, s)) != hipSuccess) return hip_fail(e, "lpf_full: kernel");
+  if ((e = launch_full(I, sh, phase_mask, skip, s)) != hipSuccess) return hip_fail(e, "lpf_full: kernel");
   return LPF_OK;
+}
+}  // namespace
+
+lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                    unsigned phase_mask, int out_layout, uint32_t *counts, void *stream) {
+  return full_impl(c, bits, W, H, cx, cy, phase_mask, out_layout, counts, stream, false);
+}
+
+lpf_status lpf_full_enhanced(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, int out_layout, uint32_t *counts,
+                             void *stream) {
+  return full_impl(c, bits, W, H, cx, cy, phase_mask, out_layout, counts, stream, true);
 }
 
 // Tile-shape override used by the autotuner and by tests (0 = automatic choice).

@@ -224,7 +224,8 @@ int cnn_conv_blocks(int64_t npix);
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
                       hipStream_t stream);
-hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+// skip: the enhanced evaluation (waves stop a segment once no start pixel can still count).
+hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask, bool skip,
                        hipStream_t stream);
 size_t full_lds_bytes(const FullShape &sh, int wpg);
 hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,

@@ -180,3 +180,54 @@ def test_tiled_large_image(ctx):
     idx = np.unique(np.concatenate([g.choice(len(v), 40, replace=False), [0, 1, len(v) - 1]]))
     assert np.array_equal(got[:, idx], oracle.lpf_vectors(big, v[idx], 3))
     _property_checks(big, got, 512, 512)
+
+
+def _both(ctx, img, cx, cy, mask=3, layout=0):
+    import torch
+    H, W = img.shape
+    bits = ctx.pack(torch.from_numpy(np.ascontiguousarray(img)).cuda())
+    std = ctx.full(bits, W, H, cx, cy, mask, layout)
+    enh = ctx.full_enhanced(bits, W, H, cx, cy, mask, layout)
+    torch.cuda.synchronize()
+    return std.cpu().numpy(), enh.cpu().numpy()
+
+
+@pytest.mark.parametrize("mask", [1, 2, 3])
+def test_enhanced_equals_standard_rsa_512(ctx, mask):
+    # the enhanced evaluation (segments abandoned per wave once nothing can still count) gives
+    # the standard counts bit for bit on the benchmark image, for every phase mask
+    _announce(f"enhanced 512x512 cutoff 128 mask {mask}")
+    std, enh = _both(ctx, wl.rsa_512(), 128, 128, mask)
+    assert np.array_equal(std, enh)
+
+
+@pytest.mark.parametrize("name", ["checker", "stripes", "random", "boolean_ragged", "grid"])
+def test_enhanced_equals_standard_shapes(ctx, name):
+    _announce(f"enhanced {name}")
+    if name == "checker":
+        img, c = wl.checkerboard(200, 160, 10), (60, 60)
+    elif name == "stripes":
+        img, c = wl.stripes(192, 96, 24, 7), (90, 40)
+    elif name == "random":
+        img, c = wl.random_binary(150, 90, 0.5, 4), (40, 30)
+    elif name == "boolean_ragged":
+        img, c = wl.boolean_disks(333, 257, 5.0, 0.45, 9), (100, 80)
+    else:
+        img, c = wl.small_boolean_64(), (16, 16)
+    layout = 1 if name == "grid" else 0
+    std, enh = _both(ctx, img, c[0], c[1], 3, layout)
+    assert np.array_equal(std, enh)
+    if name in ("grid", "random"):
+        assert np.array_equal(enh.astype(np.uint32), oracle.lpf(img, c[0], c[1], 3, layout=layout))
+
+
+def test_enhanced_tiled(ctx):
+    # several row tiles (forced small staging budget) and a large cutoff
+    _announce("enhanced tiled 1024x512 cutoff 300")
+    img = wl.boolean_disks(1024, 512, 6.0, 0.3, 31)
+    try:
+        ctx.set_full_shape(0, 0, 0, 65536)
+        std, enh = _both(ctx, img, 300, 300)
+    finally:
+        ctx.set_full_shape(0, 0, 0, 0)
+    assert np.array_equal(std, enh)
