@@ -222,20 +222,25 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
             int k0, int C, const uint32_t *__restrict__ counts,
             const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
             int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
-            const StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
+            StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
+            const double *__restrict__ U, double T, int pi0, int pC) {
   using P = Planes<MASK>;
   __shared__ long long s_part[4];
+  __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
+  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, T, (double)N * (double)N * (double)Nt,
+                          ctl, &s_prev))
+    return;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool vin = v < g.nv;
   // candidate-independent operands first, so that their loads overlap the candidate's
   const int4 m = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
-  int64_t L[2] = {0, 0}, T[2] = {0, 0};
+  int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
 #pragma unroll
   for (int p = 0; p < P::nph; ++p)
     if (vin) {
-      L[p] = counts[(size_t)p * g.nv + v];
-      T[p] = target[(size_t)p * g.nv + v];
+      Lc[p] = counts[(size_t)p * g.nv + v];
+      Tc[p] = target[(size_t)p * g.nv + v];
     }
   for (int kr = blockIdx.y; kr < C; kr += gridDim.y) {
     if (k0 + kr >= K) break;
@@ -247,7 +252,7 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
     if (vin) {
 #pragma unroll
       for (int p = 0; p < P::nph; ++p) {
-        S += energy_term(d[p], L[p], T[p], N, Nt);
+        S += energy_term(d[p], Lc[p], Tc[p], N, Nt);
         if (dl) dl[(int64_t)((size_t)p * g.nv + v) * dl_t + (int64_t)k * dl_k] = (int16_t)d[p];
       }
     }
@@ -344,7 +349,7 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
 #define LPF_ROUND_O(M, O)                                                                      \
   hipLaunchKernelGGL((k_rec_round<M, O>), grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K, \
                      r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k,   \
-                     L.ctl, L.order)
+                     L.ctl, L.order, L.U, L.T, decide ? r.pi0 : 0, decide ? r.pC : 0)
 #define LPF_ROUND(M)               \
   if (L.ordered)                   \
     LPF_ROUND_O(M, true);          \

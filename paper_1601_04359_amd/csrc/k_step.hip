@@ -37,9 +37,14 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
               const uint32_t *__restrict__ runs, unsigned phase_mask, int nv,
               const uint32_t *__restrict__ counts, const uint32_t *__restrict__ target, int64_t N,
               int64_t Nt, int64_t *__restrict__ S_acc, int16_t *__restrict__ dl,
-              const StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
+              StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
+              const double *__restrict__ U, double T, int pi0, int pC) {
   extern __shared__ uint32_t lds[];
+  __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
+  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, T, (double)N * (double)N * (double)Nt,
+                          ctl, &s_prev))
+    return;
   const int kr = blockIdx.x * blockDim.x + threadIdx.x;  // index within the round
   const int i = k0 + kr;                                 // evaluation position
   bool ok = kr < C && i < K;
@@ -121,13 +126,42 @@ k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
 // Step result, running energy, and the accepted interchange applied to counts, image and pixel
 // lists (one workgroup).
 __global__ void __launch_bounds__(1024)
-k_step_final(AnnealDev *__restrict__ st, const StepCtl *__restrict__ ctl, int K,
+k_step_final(AnnealDev *__restrict__ st, StepCtl *__restrict__ ctl, int K,
              const int2 *__restrict__ cand, const int2 *__restrict__ slot,
              const int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k, int nterms, int64_t N,
              int64_t Nt,
              double *__restrict__ e_io, uint32_t *__restrict__ counts, uint64_t *__restrict__ bits,
-             int W, int32_t *__restrict__ k_sel, StepResult *__restrict__ out) {
-  const int ks = ctl->ks;
+             int W, int32_t *__restrict__ k_sel, StepResult *__restrict__ out,
+             const int64_t *__restrict__ S_acc, const double *__restrict__ U, double T,
+             const int32_t *__restrict__ order, int li0, int lC) {
+  // decision of the last round when no earlier round accepted
+  __shared__ int s_first;
+  int ks = ctl->ks;
+  if (ks < 0 && lC > 0) {
+    if (threadIdx.x == 0) s_first = INT_MAX;
+    __syncthreads();
+    const double scale = (double)N * (double)N * (double)Nt;
+    for (int base = 0; base < lC; base += blockDim.x) {
+      const int kr = base + threadIdx.x;
+      if (kr < lC) {
+        const int k = order ? order[li0 + kr] : li0 + kr;
+        if (cand[k].x >= 0) {
+          const double de = (double)S_acc[k] / scale;
+          if (de <= 0.0 || U[k] < exp(-de / T)) atomicMin(&s_first, kr);
+        }
+      }
+      __syncthreads();
+      const int f = s_first;
+      __syncthreads();
+      if (f != INT_MAX) break;
+    }
+    if (s_first != INT_MAX) ks = order ? order[li0 + s_first] : li0 + s_first;
+    if (threadIdx.x == 0 && ks >= 0) {
+      ctl->ks = ks;
+      ctl->S = S_acc[ks];
+      ctl->done = 1;
+    }
+  }
   if (ks >= 0)
     for (int t = threadIdx.x; t < nterms; t += blockDim.x)
       counts[t] = (uint32_t)((int32_t)counts[t] + (int32_t)dl[t * dl_t + ks * dl_k]);
@@ -136,7 +170,7 @@ k_step_final(AnnealDev *__restrict__ st, const StepCtl *__restrict__ ctl, int K,
     r.step = st->step;
     r.pad = 0;
     if (ks >= 0) {
-      const double de = (double)ctl->S / ((double)N * (double)N * (double)Nt);
+      const double de = (double)S_acc[ks] / ((double)N * (double)N * (double)Nt);
       const double e = *e_io + de;
       *e_io = e;
       const int a = cand[ks].x, b = cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
@@ -174,12 +208,13 @@ hipError_t launch_round_recount(const StepLaunch &L, const RoundPlan &r, bool de
     hipLaunchKernelGGL(k_round_delta<true>, grid, dim3(r.block),
                        (size_t)L.geo.total * sizeof(uint32_t), stream, L.E, L.geo, L.bits, L.W,
                        L.H, L.cand, L.K, r.k0, r.C, r.vecs, r.chunk_off, L.runs, L.phase_mask,
-                       L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl, L.order);
+                       L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl, L.order, L.U,
+                       L.T, decide ? r.pi0 : 0, decide ? r.pC : 0);
   else
     hipLaunchKernelGGL(k_round_delta<false>, grid, dim3(r.block), 0, stream, L.E, L.geo, L.bits,
                        L.W, L.H, L.cand, L.K, r.k0, r.C, r.vecs, r.chunk_off, L.runs,
                        L.phase_mask, L.nv, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.ctl,
-                       L.order);
+                       L.order, L.U, L.T, decide ? r.pi0 : 0, decide ? r.pC : 0);
   return hipGetLastError();
 }
 
@@ -192,16 +227,30 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
                        L.S_acc, L.K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (const RoundPlan &r : L.rounds) {
+  // Decisions: round 0 (64 candidates) is decided at the start of round 1 by every workgroup,
+  // middle rounds by k_round_decide, the last round by k_step_final.
+  const int nr = (int)L.rounds.size();
+  for (int j = 0; j < nr; ++j) {
+    RoundPlan r = L.rounds[j];
+    r.pi0 = 0;
+    r.pC = 0;
+    if (j == 1 && L.rounds[0].C <= 64) {
+      r.pi0 = L.rounds[0].k0;
+      r.pC = L.rounds[0].C;
+    }
     e = L.records ? launch_rec_round(L, r, true, stream) : launch_round_recount(L, r, true, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_round_decide, dim3(1), dim3(std::min(1024, ((r.C + 63) / 64) * 64)), 0,
-                       stream, L.S_acc, L.cand, L.U, r.k0, r.C, L.T, L.N, L.Nt, L.ctl, L.order);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const bool decided_later = j == nr - 1 || (j == 0 && L.rounds[0].C <= 64);
+    if (!decided_later) {
+      hipLaunchKernelGGL(k_round_decide, dim3(1), dim3(std::min(1024, ((r.C + 63) / 64) * 64)), 0,
+                         stream, L.S_acc, L.cand, L.U, r.k0, r.C, L.T, L.N, L.Nt, L.ctl, L.order);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
+  const int li0 = nr ? L.rounds[nr - 1].k0 : 0, lC = nr ? L.rounds[nr - 1].C : 0;
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, L.st, L.ctl, L.K, L.cand,
                      L.slot, L.dl, L.dl_t, L.dl_k, L.nterms, L.N, L.Nt, L.e, L.counts_rw,
-                     L.bits_rw, L.W, L.k_sel, L.out);
+                     L.bits_rw, L.W, L.k_sel, L.out, L.S_acc, L.U, L.T, L.order, li0, lC);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (L.records) e = launch_rec_update(L.rg, L.ctl, L.cand, stream);
   return e;

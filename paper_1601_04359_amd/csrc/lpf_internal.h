@@ -86,6 +86,7 @@ struct StepCtl {
 // and the vector chunking used (plan arrays); records method: vectors per workgroup.
 struct RoundPlan {
   int k0, C, block, nchunks;
+  int pi0, pC;  // the previous round, decided at the start of this one (pC = 0: none)
   const DeltaVec *vecs;
   const int32_t *chunk_off;
 };
