@@ -70,3 +70,32 @@ def test_python_binding_checks():
     with pytest.raises(ValueError):
         _abi.lpf_full(0, torch.zeros(3, dtype=torch.int64), 8, 8, 1, 1, 3, 0,
                       torch.zeros(1, dtype=torch.int32))
+
+
+def test_new_entry_points_reject_null_before_any_device_call():
+    from paper_1601_04359_amd import _abi
+    lib = _abi.lib()
+    assert lib.lpf_full_enhanced(None, None, 8, 8, 1, 1, 3, 0, None, None) == _abi.LPF_E_INVAL
+    assert b"ctx" in lib.lpf_last_error()
+    assert lib.lpf_anneal_set_method(None, 2) == _abi.LPF_E_INVAL
+    assert b"state" in lib.lpf_last_error()
+    assert lib.lpf_anneal_get_method(None) == -1
+    assert lib.lpf_anneal_set_proposal(None, None, None, 1.0, 0.1, 1, 0) == _abi.LPF_E_INVAL
+
+
+def test_bench_counts_match_oracle_paths():
+    # the benchmark's algorithmic work: M_c from the oracle's digitisation, ops = N/32 (3 M_c +
+    # 2 |D_c|) for both phases (7.088e10 at 512^2, cutoff 128)
+    import bench
+    for cx, cy in ((16, 16), (128, 128), (5, 9)):
+        n = np.array([len(oracle.bresenham(int(dx), int(dy))) for dx, dy in oracle.vectors(cx, cy)])
+        assert bench.path_pixels(cx, cy) == int(n.sum())
+    assert bench.ops_alg(512, 512, 128, 128, 2) == 70879584256.0
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
