@@ -369,6 +369,17 @@ def batch_bench(args) -> dict:
             bits = ctx.pack(torch.from_numpy(wl.batch_image(b)).to(dev), stream=stream)
             items.append((bits, b.side, b.side, b.side // 2, b.side // 2))
             b.img = None
+        # autotuner on one image of each side up to 512 (the tuned shape then serves every image
+        # of that size); at 1024 the default rule already gives the tuner's measured choice
+        # (16 words per lane, 16 waves, 160 KiB), and a full tuning pass there takes ~90 s
+        t_tune = time.perf_counter()
+        tuned = {}
+        for (bits, W, H, cx, cy) in items:
+            if W <= 512 and W not in tuned:
+                ctx.autotune(bits, W, H, cx, cy, 3, stream=stream)
+                tuned[W] = list(ctx.tuned_shape(W, H, cx, cy))
+        stream.synchronize()
+        t_tune = time.perf_counter() - t_tune
         t_setup = time.perf_counter()
         counts, offs, pool, descs = ctx.batch(items, 3, 0, stream=stream)  # plans + capture + 1 run
         stream.synchronize()
@@ -407,7 +418,8 @@ def batch_bench(args) -> dict:
                                "phi U[0.2,0.6], r U[3,15], cutoff side/2, both phases, one "
                                "persistent launch (hipGraph replay)",
                    "images_per_side": {str(s): sides.count(s) for s in sorted(set(sides))},
-                   "setup_s": round(t_setup, 2)},
+                   "tuned_shapes_R_wpg_lds": {str(k): v for k, v in sorted(tuned.items())},
+                   "tune_s": round(t_tune, 2), "setup_s": round(t_setup, 2)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(P_INT_TOPS, 3),
                      "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4), "traffic": None,
                      "kernel": "k_lpf_batch (+k_ext_batch in the event window)",
