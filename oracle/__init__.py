@@ -5,7 +5,8 @@ this package.  The product package never imports it, and it imports nothing from
 
 The arithmetic lives in ``lpf_oracle.c`` (plain definitions from Havelka, Kucerova & Sykora,
 arXiv:1601.04359: Sec. 2.2 segments and symmetry, Alg. "L2_eval", Sec. 4 interchange operator,
-Alg. "annealing" with eq. (LSE)); ``brute.py`` is a second, independent pure-Python/numpy
+Alg. "annealing" with eq. (LSE), and the two-point probability of Sec. 2.1, eq. (S2dis), with
+its interchange update); ``brute.py`` is a second, independent pure-Python/numpy
 implementation for tiny images that pins it.  This module only marshals numpy arrays.
 
 Parity unpinned: the pixel choice on Bresenham tie vectors (reading R1 in ``lpf_oracle.c``) is
@@ -58,6 +59,15 @@ def _load():
     lib.oracle_anneal_run.argtypes = [P, i32, i32, i32, i32, u32, P, P, i64, u64, u64, i32, i32,
                                       P, i32, P, P, P, P, i32]
     lib.oracle_anneal_run.restype = i32
+    lib.oracle_anneal_run_desc.argtypes = [P, i32, i32, i32, i32, u32, i32, P, P, i64, u64, u64,
+                                           i32, i32, P, i32, P, P, P, P, i32]
+    lib.oracle_anneal_run_desc.restype = i32
+    lib.oracle_s2_vectors.argtypes = [P, i32, i32, P, i64, u32, P, i32]
+    lib.oracle_s2_vectors.restype = i32
+    lib.oracle_s2.argtypes = [P, i32, i32, i32, i32, u32, i32, P, i32]
+    lib.oracle_s2.restype = i32
+    lib.oracle_s2_delta_swap.argtypes = [P, i32, i32, i32, i32, u32, P, i32, P, i32]
+    lib.oracle_s2_delta_swap.restype = i32
     _lib = lib
     return lib
 
@@ -140,6 +150,50 @@ def delta_swap(img, cx: int, cy: int, swaps, phase_mask: int = 3, full: bool = F
     return out
 
 
+def s2(img, cx: int, cy: int, phase_mask: int = 3, layout: int = 0, nthreads: int = 0) -> np.ndarray:
+    """Two-point counts W*H*S2 (eq. (S2dis)), uint32 [nph][|D_c|] (layout 0) or
+    [nph][2cy+1][2cx+1] (layout 1)."""
+    a = _img(img)
+    H, W = a.shape
+    nph = nphases(phase_mask)
+    if layout == 0:
+        out = np.zeros((nph, num_vectors(cx, cy)), np.uint32)
+    else:
+        out = np.zeros((nph, 2 * cy + 1, 2 * cx + 1), np.uint32)
+    rc = _load().oracle_s2(_ptr(a), W, H, cx, cy, phase_mask, layout, _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_s2 failed ({rc})")
+    return out
+
+
+def s2_vectors(img, dxdy, phase_mask: int = 3, nthreads: int = 0) -> np.ndarray:
+    a = _img(img)
+    H, W = a.shape
+    v = np.ascontiguousarray(dxdy, dtype=np.int16).reshape(-1, 2)
+    out = np.zeros((nphases(phase_mask), len(v)), np.uint32)
+    rc = _load().oracle_s2_vectors(_ptr(a), W, H, _ptr(v), len(v), phase_mask, _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_s2_vectors failed ({rc})")
+    return out
+
+
+def s2_delta_swap(img, cx: int, cy: int, swaps, phase_mask: int = 3,
+                  nthreads: int = 0) -> np.ndarray:
+    """delta int32 [n][nph][|D_c|] = C(I') - C(I) of the two-point counts per interchange."""
+    a = _img(img)
+    H, W = a.shape
+    sw = np.ascontiguousarray(swaps, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros((len(sw), nphases(phase_mask), num_vectors(cx, cy)), np.int32)
+    rc = _load().oracle_s2_delta_swap(_ptr(a), W, H, cx, cy, phase_mask, _ptr(sw), len(sw),
+                                      _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_s2_delta_swap failed ({rc})")
+    return out
+
+
+DESC_LPF, DESC_S2 = 0, 1
+
+
 def philox4x64(counter, key) -> np.ndarray:
     c = np.ascontiguousarray(counter, dtype=np.uint64)
     k = np.ascontiguousarray(key, dtype=np.uint64)
@@ -161,7 +215,8 @@ STEP_DTYPE = np.dtype([("k", np.int32), ("a", np.int32), ("b", np.int32), ("pad"
 class AnnealState:
     """Host copy of an annealing chain: image, counts, target counts, pixel lists, error."""
 
-    def __init__(self, img, cx, cy, phase_mask, target, Nt, seed, nthreads=0):
+    def __init__(self, img, cx, cy, phase_mask, target, Nt, seed, nthreads=0,
+                 descriptor: int = DESC_LPF):
         self.img = _img(img).copy()
         self.H, self.W = self.img.shape
         self.cx, self.cy, self.phase_mask = cx, cy, phase_mask
@@ -173,7 +228,13 @@ class AnnealState:
         flat = self.img.ravel()
         self.pos1 = np.flatnonzero(flat == 1).astype(np.int32)
         self.pos0 = np.flatnonzero(flat == 0).astype(np.int32)
-        self.counts = lpf(self.img, cx, cy, phase_mask, 0, nthreads)
+        self.descriptor = descriptor
+        if descriptor == DESC_LPF:
+            self.counts = lpf(self.img, cx, cy, phase_mask, 0, nthreads)
+        elif descriptor == DESC_S2:
+            self.counts = s2(self.img, cx, cy, phase_mask, 0, nthreads)
+        else:
+            raise ValueError("descriptor")
         self.e = lse(self.counts, self.target, self.W * self.H, self.Nt)
 
     def run(self, nsteps: int, K: int, Ts, proposal: int = 0) -> np.ndarray:
@@ -181,8 +242,9 @@ class AnnealState:
         assert Ts.size == nsteps
         res = np.zeros(nsteps, STEP_DTYPE)
         e = np.array([self.e], np.float64)
-        rc = _load().oracle_anneal_run(
-            _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask, _ptr(self.counts),
+        rc = _load().oracle_anneal_run_desc(
+            _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask, self.descriptor,
+            _ptr(self.counts),
             _ptr(self.target), self.Nt, self.seed, self.step, nsteps, K, _ptr(Ts), proposal,
             _ptr(self.pos1), _ptr(self.pos0), _ptr(e), _ptr(res), self.nthreads)
         if rc:

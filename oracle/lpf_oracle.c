@@ -16,8 +16,12 @@
  *   - oracle_delta_swap*    Sec. 4 modification operator (two-pixel interchange), evaluated as
  *                           L(I') - L(I): by two full evaluations, and by a recount restricted
  *                           to the translations whose segment covers a swapped pixel.
+ *   - oracle_s2*            Sec. 2.1, eq. (S2dis): two-point probability counts (definition sum).
+ *   - oracle_s2_delta_swap  Sec. 4 interchange applied to eq. (S2dis), recounting the pairs that
+ *                           contain a swapped pixel.
  *   - oracle_anneal_run     Sec. 4, Alg. "annealing" + eq. (LSE): Metropolis rule on pixel
- *                           interchanges, with the batched first-accept step described there.
+ *                           interchanges, with the batched first-accept step described there;
+ *                           oracle_anneal_run_desc also anneals against S2 (Sec. 5 comparison).
  *   - oracle_philox4x64     Salmon et al., SC'11 "Parallel random numbers: as easy as 1, 2, 3",
  *                           Philox-4x64 with 10 rounds.
  *
@@ -207,6 +211,71 @@ int oracle_lpf(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Two-point probability (Sec. 2.1, eq. (S2dis)) as integer counts C_p(v) = W H S2^p(v):
+ * the number of pixels x of the periodic image with x and x + v both in phase p.  Written as
+ * the definition's double sum; the paper evaluates the same sum through the FFT, which the
+ * tests use as a pin.  S2 does not depend on any digitised path, only on the end point v.
+ * ------------------------------------------------------------------------------------------ */
+static uint32_t s2_one(const uint8_t *img, int W, int H, int dx, int dy, uint8_t phase) {
+  uint32_t count = 0;
+  for (int y1 = 0; y1 < H; ++y1)
+    for (int x1 = 0; x1 < W; ++x1)
+      if (img[(size_t)y1 * W + x1] == phase &&
+          img[(size_t)wrap(y1 + dy, H) * W + wrap(x1 + dx, W)] == phase)
+        count += 1;
+  return count;
+}
+
+/* S2 counts for an explicit list of vectors; counts[p][i], phase 0 first. */
+int oracle_s2_vectors(const uint8_t *img, int W, int H, const int16_t *dxdy, int64_t nv,
+                      unsigned phase_mask, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || nv < 0 || (phase_mask & ~3u) || !phase_mask) return -22;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nv; ++i) {
+    int p = 0;
+    for (int ph = 0; ph < 2; ++ph) {
+      if (!(phase_mask & (1u << ph))) continue;
+      counts[(size_t)p * nv + i] = s2_one(img, W, H, dxdy[2 * i], dxdy[2 * i + 1], (uint8_t)ph);
+      ++p;
+    }
+  }
+  return 0;
+}
+
+/* S2 counts over the canonical half domain (out_layout 0: counts[nph][|D_c|]) or over the whole
+ * (2cy+1) x (2cx+1) grid of vectors (out_layout 1: counts[nph][dy+cy][dx+cx]), every grid entry
+ * evaluated from the definition (no symmetry is used here). */
+int oracle_s2(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+              int out_layout, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1) return -22;
+  if (out_layout != 0 && out_layout != 1) return -22;
+  int64_t nv;
+  int16_t *v;
+  if (out_layout == 0) {
+    nv = oracle_num_vectors(cx, cy);
+    v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
+    oracle_vectors(cx, cy, v);
+  } else {
+    nv = (int64_t)(2 * cx + 1) * (2 * cy + 1);
+    v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
+    int64_t i = 0;
+    for (int dy = -cy; dy <= cy; ++dy)
+      for (int dx = -cx; dx <= cx; ++dx, ++i) {
+        v[2 * i] = (int16_t)dx;
+        v[2 * i + 1] = (int16_t)dy;
+      }
+  }
+  int rc = oracle_s2_vectors(img, W, H, v, nv, phase_mask, counts, nthreads);
+  free(v);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------------
  * Pixel interchange (Sec. 4): I' equals I with the values of pixels a and b exchanged
  * (linear indices y*W + x).  delta[s][p][i] = L_p(I')(v_i) - L_p(I)(v_i).
  * ------------------------------------------------------------------------------------------ */
@@ -325,6 +394,68 @@ int oracle_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned
 }
 
 /* ------------------------------------------------------------------------------------------
+ * S2 change under a pixel interchange (Sec. 4 operator applied to eq. (S2dis)):
+ * delta[s][p][i] = C_p(I')(v_i) - C_p(I)(v_i) over the canonical half domain.  Only the pairs
+ * (x, x + v) that contain a or b can change, i.e. the start pixels x in {a, b, a - v, b - v};
+ * each distinct start pixel is counted once, before and after the interchange.
+ * ------------------------------------------------------------------------------------------ */
+static inline uint8_t pix_swapped(const uint8_t *img, int q, int a, int b) {
+  if (q == a) return img[b];
+  if (q == b) return img[a];
+  return img[q];
+}
+
+int oracle_s2_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                         const int32_t *swaps, int n, int32_t *delta, int nthreads) {
+  if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1) return -22;
+  if (!phase_mask || (phase_mask & ~3u)) return -22;
+  int64_t nv = oracle_num_vectors(cx, cy);
+  int nph = (phase_mask & 1) + ((phase_mask >> 1) & 1);
+  size_t N = (size_t)W * H;
+  for (int s = 0; s < n; ++s)
+    if (swaps[2 * s] < 0 || swaps[2 * s + 1] < 0 || (size_t)swaps[2 * s] >= N ||
+        (size_t)swaps[2 * s + 1] >= N)
+      return -22;
+  int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
+  oracle_vectors(cx, cy, v);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+  for (int s = 0; s < n; ++s)
+    for (int64_t i = 0; i < nv; ++i) {
+      int a = swaps[2 * s], b = swaps[2 * s + 1];
+      int dx = v[2 * i], dy = v[2 * i + 1];
+      int start[4];
+      int ns = 0;
+      int cand[4] = {a, b, wrap(a % W - dx, W) + wrap(a / W - dy, H) * W,
+                     wrap(b % W - dx, W) + wrap(b / W - dy, H) * W};
+      for (int j = 0; j < 4; ++j) {
+        int seen = 0;
+        for (int t = 0; t < ns; ++t) seen |= start[t] == cand[j];
+        if (!seen) start[ns++] = cand[j];
+      }
+      int p = 0;
+      for (int ph = 0; ph < 2; ++ph) {
+        if (!(phase_mask & (1u << ph))) continue;
+        int32_t d = 0;
+        for (int t = 0; t < ns; ++t) {
+          int x = start[t];
+          int y = wrap(x / W + dy, H) * W + wrap(x % W + dx, W);
+          d += (pix_swapped(img, x, a, b) == ph && pix_swapped(img, y, a, b) == ph) -
+               (img[x] == ph && img[y] == ph);
+        }
+        delta[((size_t)s * nph + p) * nv + i] = d;
+        ++p;
+      }
+    }
+  free(v);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
  * Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the 4-word Philox S-box
  * with multipliers 0xD2E7470EE14C6C93 / 0xCA5A826395121157 and Weyl key increments
  * 0x9E3779B97F4A7C15 / 0xBB67AE8584CAA73B.
@@ -393,13 +524,17 @@ double oracle_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms
   return e / ((double)N * (double)N * (double)Nt * (double)Nt);
 }
 
-int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
-                      uint32_t *counts /* [nph][nv], must equal L(img) on entry */,
-                      const uint32_t *target /* [nph][nv] */, int64_t Nt, uint64_t seed,
-                      uint64_t step0, int nsteps, int K, const double *Ts /* [nsteps] */,
-                      int proposal, int32_t *pos1, int32_t *pos0 /* in/out */, double *e_io,
-                      oracle_step_result *res /* [nsteps] */, int nthreads) {
+/* descriptor 0: the lineal path function (counts = L); descriptor 1: the two-point probability
+ * (counts = W H S2, Sec. 2.1), the descriptor the paper compares against in Sec. 5. */
+int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                           int descriptor,
+                           uint32_t *counts /* [nph][nv], must equal the descriptor of img */,
+                           const uint32_t *target /* [nph][nv] */, int64_t Nt, uint64_t seed,
+                           uint64_t step0, int nsteps, int K, const double *Ts /* [nsteps] */,
+                           int proposal, int32_t *pos1, int32_t *pos0 /* in/out */,
+                           double *e_io, oracle_step_result *res /* [nsteps] */, int nthreads) {
   if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1 || K < 1) return -22;
+  if (descriptor != 0 && descriptor != 1) return -22;
   int64_t nv = oracle_num_vectors(cx, cy);
   int nph = (phase_mask & 1) + ((phase_mask >> 1) & 1);
   int64_t N = (int64_t)W * H;
@@ -425,7 +560,10 @@ int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase
       if (proposal == 1 && !(interfacial(img, W, H, a) && interfacial(img, W, H, b))) continue;
       sw[0] = a;
       sw[1] = b;
-      oracle_delta_swap(img, W, H, cx, cy, phase_mask, sw, 1, dl, nthreads);
+      if (descriptor == 0)
+        oracle_delta_swap(img, W, H, cx, cy, phase_mask, sw, 1, dl, nthreads);
+      else
+        oracle_s2_delta_swap(img, W, H, cx, cy, phase_mask, sw, 1, dl, nthreads);
       int64_t S = 0;
       for (int64_t j = 0; j < (int64_t)nph * nv; ++j) {
         int64_t d = dl[j];
@@ -454,4 +592,13 @@ int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase
   free(v);
   free(dl);
   return 0;
+}
+
+int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                      uint32_t *counts, const uint32_t *target, int64_t Nt, uint64_t seed,
+                      uint64_t step0, int nsteps, int K, const double *Ts, int proposal,
+                      int32_t *pos1, int32_t *pos0, double *e_io, oracle_step_result *res,
+                      int nthreads) {
+  return oracle_anneal_run_desc(img, W, H, cx, cy, phase_mask, 0, counts, target, Nt, seed, step0,
+                                nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
 }

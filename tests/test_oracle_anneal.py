@@ -31,14 +31,16 @@ def _lse_exact(counts, target, N, Nt):
                for c, t in zip(counts.ravel(), target.ravel()))
 
 
-def _reference_chain(img, cx, cy, mask, target, Nt, seed, step0, nsteps, K, Ts, proposal):
+def _reference_chain(img, cx, cy, mask, target, Nt, seed, step0, nsteps, K, Ts, proposal,
+                     descriptor=oracle.DESC_LPF):
     img = img.copy()
     H, W = img.shape
     N = W * H
     flat = img.ravel()
     pos1 = list(np.flatnonzero(flat == 1))
     pos0 = list(np.flatnonzero(flat == 0))
-    counts = oracle.lpf(img, cx, cy, mask).astype(np.int64)
+    evaluate = oracle.lpf if descriptor == oracle.DESC_LPF else oracle.s2
+    counts = evaluate(img, cx, cy, mask).astype(np.int64)
     out = []
     for s in range(nsteps):
         res = (-1, -1, -1)
@@ -56,7 +58,9 @@ def _reference_chain(img, cx, cy, mask, target, Nt, seed, step0, nsteps, K, Ts, 
                             img[(y + 1) % H, x] != v or img[(y - 1) % H, x] != v)
                 if not (itf(a) and itf(b)):
                     continue
-            dl = oracle.delta_swap(img, cx, cy, [[a, b]], mask, full=True)[0].astype(np.int64)
+            img2 = img.copy()
+            img2.flat[a], img2.flat[b] = 0, 1
+            dl = evaluate(img2, cx, cy, mask).astype(np.int64) - counts
             de_exact = _lse_exact(counts + dl, target, N, Nt) - _lse_exact(counts, target, N, Nt)
             # the oracle rounds the exact rational once (integer sum / N^2 Nt)
             de = float(de_exact)
@@ -87,6 +91,29 @@ def test_anneal_matches_reference_chain(proposal):
     res = st.run(nsteps, K, Ts, proposal)
     ref, img_ref, counts_ref = _reference_chain(cell, cx, cy, mask, target, Nt, seed, 1,
                                                 nsteps, K, Ts, proposal)
+    got = [(int(r["k"]), int(r["a"]), int(r["b"])) for r in res]
+    assert got == ref
+    assert np.array_equal(st.img, img_ref)
+    assert np.array_equal(st.counts.astype(np.int64), counts_ref)
+    assert sum(r[0] >= 0 for r in got) > 3
+
+
+@pytest.mark.parametrize("proposal,mask", [(0, 3), (1, 3), (0, 2)])
+def test_s2_anneal_matches_reference_chain(proposal, mask):
+    # the same chain with the two-point probability as the descriptor (Sec. 2.1 and Sec. 5)
+    tgt = wl.square_particles(40, 40, 4, 16, 5)
+    cx = cy = 5
+    target = oracle.s2(tgt, cx, cy, mask)
+    Nt = tgt.size
+    cell = wl.random_cell(14, 14, int(round(0.16 * 196)), 9)
+    seed = 78
+    nsteps, K = 25, 16
+    Ts = 2e-4 * 0.9 ** np.arange(nsteps)
+    st = oracle.AnnealState(cell, cx, cy, mask, target, Nt, seed, descriptor=oracle.DESC_S2)
+    st.step = 1
+    res = st.run(nsteps, K, Ts, proposal)
+    ref, img_ref, counts_ref = _reference_chain(cell, cx, cy, mask, target, Nt, seed, 1,
+                                                nsteps, K, Ts, proposal, oracle.DESC_S2)
     got = [(int(r["k"]), int(r["a"]), int(r["b"])) for r in res]
     assert got == ref
     assert np.array_equal(st.img, img_ref)

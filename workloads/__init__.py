@@ -117,6 +117,30 @@ def checkerboard(W: int, H: int, s: int) -> np.ndarray:
     return ((x + y) % 2).astype(np.uint8)
 
 
+def square_particles(W: int, H: int, size: int, n: int, seed: int, tries: int = 100000) -> np.ndarray:
+    """Particulate suspension of Sec. 5: n equal size x size phase-1 squares placed one by one
+    at uniform random positions of the periodic W x H cell, a placement rejected when it would
+    overlap or touch (share an edge with) a square already placed."""
+    g = rng(seed)
+    occ = np.zeros((H, W), bool)
+    img = np.zeros((H, W), np.uint8)
+    placed = 0
+    for _ in range(tries):
+        if placed == n:
+            break
+        x0, y0 = int(g.integers(W)), int(g.integers(H))
+        ys = np.arange(y0 - 1, y0 + size + 1) % H
+        xs = np.arange(x0 - 1, x0 + size + 1) % W
+        if occ[np.ix_(ys, xs)].any():
+            continue
+        occ[np.ix_(ys[1:-1], xs[1:-1])] = True
+        img[np.ix_(ys[1:-1], xs[1:-1])] = 1
+        placed += 1
+    if placed != n:
+        raise ValueError("could not place every square")
+    return img
+
+
 def random_binary(W: int, H: int, p: float, seed: int) -> np.ndarray:
     return (rng(seed).random((H, W)) < p).astype(np.uint8)
 
