@@ -114,6 +114,27 @@ lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int c
                           unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
                           void *stream);
 
+/* ---- two-point probability (Sec. 2.1, eq. (S2dis)), the descriptor compared with in Sec. 5 --- */
+
+/* Two-point counts C_p(v) = W H S2^p(v): the number of pixels x of the periodic image with x and
+ * x + v both in phase p, for every vector v of D_c (only its end point matters, no segment) and
+ * every phase of phase_mask, exact uint32 counts in `out_layout` (GRID: the entry of -v equals
+ * that of v).  The paper evaluates S2 through the FFT over all W x H shifts; here the pairs are
+ * counted directly, 32 start pixels per AND and popcount (cx = W-1, cy = H-1 covers every
+ * shift).  Phase 0 follows from phase 1 by eq. (S2add) in counts: C_0(v) = W H - 2 N_1 + C_1(v).
+ * bits, counts, W, H, cx, cy, phase_mask, out_layout: as lpf_full.
+ * Errors: LPF_E_INVAL (arguments), LPF_E_NOMEM / LPF_E_DEVICE (HIP). */
+lpf_status lpf_s2(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                  unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
+
+/* Exact change of the two-point counts under pixel interchanges: delta[s][p][i] =
+ * C_p(I')(v_i) - C_p(I)(v_i), canonical order, from the closed form over the pairs that contain
+ * a or b (the same value for both phases, since N_1 is unchanged).  Arguments, the zero rows and
+ * the errors as lpf_delta_swap. */
+lpf_status lpf_s2_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
+                             void *stream);
+
 /* One image of a batch: its size, cutoff, the offset of its packed rows in bits_pool (uint64
  * words) and of its counts in counts_pool (uint32 elements, sized for the batch's layout). */
 typedef struct {
@@ -184,6 +205,18 @@ lpf_status lpf_anneal_create(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, 
                              int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
                              int n1, double *e, lpf_anneal *out, void *stream);
 
+/* An annealing chain with the two-point probability as the descriptor (the S2-based
+ * reconstruction the paper compares with, Sec. 5): counts receives lpf_s2 of the cell (HALF
+ * layout) and target holds lpf_s2 counts of the original image over Nt pixels; the energy is
+ * eq. (LSE) over those counts.  Every other argument, and every other lpf_anneal_* call, as for
+ * lpf_anneal_create; the exact int64 bound uses d = 6 (the largest change of one S2 count).
+ * lpf_anneal_set_method accepts only LPF_DELTA_AUTO for such a chain and lpf_anneal_get_method
+ * returns LPF_DELTA_S2.  Errors: as lpf_anneal_create. */
+lpf_status lpf_anneal_create_s2(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, int cy,
+                                unsigned phase_mask, uint32_t *counts, const uint32_t *target,
+                                int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
+                                int n1, double *e, lpf_anneal *out, void *stream);
+
 /* One step: draw n_candidates interchanges (a phase-1 pixel with a phase-0 pixel; with
  * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),
  * compute each one's exact energy change de against the current state, and apply the first, in
@@ -239,10 +272,11 @@ lpf_status lpf_anneal_delta_energy(lpf_anneal st, const int32_t *swaps, int n, d
  *   LPF_DELTA_AUTO     (default) records when they fit in 16 GiB and in half the free device
  *                      memory, else recount.
  * Errors: LPF_E_INVAL, LPF_E_UNSUPPORTED (records for a cutoff above 254 or a too large cell). */
-enum { LPF_DELTA_AUTO = 0, LPF_DELTA_RECOUNT = 1, LPF_DELTA_RECORDS = 2 };
+enum { LPF_DELTA_AUTO = 0, LPF_DELTA_RECOUNT = 1, LPF_DELTA_RECORDS = 2, LPF_DELTA_S2 = 3 };
 lpf_status lpf_anneal_set_method(lpf_anneal st, int method);
 
-/* The method the chain's next step uses (LPF_DELTA_RECOUNT or LPF_DELTA_RECORDS), -1 on error. */
+/* The method the chain's next step uses (LPF_DELTA_RECOUNT or LPF_DELTA_RECORDS; LPF_DELTA_S2
+ * for a chain made by lpf_anneal_create_s2), -1 on error. */
 int lpf_anneal_get_method(lpf_anneal st);
 
 /* Copy the chain's pixel lists to pos (device, int32[W*H]: phase-1 list then phase-0 list) and

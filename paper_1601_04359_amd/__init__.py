@@ -9,7 +9,7 @@ from __future__ import annotations
 import torch
 
 from . import _abi
-from ._abi import (LPF_BOTH, LPF_DELTA_AUTO, LPF_DELTA_RECORDS, LPF_DELTA_RECOUNT,
+from ._abi import (LPF_BOTH, LPF_DELTA_AUTO, LPF_DELTA_RECORDS, LPF_DELTA_RECOUNT, LPF_DELTA_S2,
                    LPF_OUT_GRID, LPF_OUT_HALF, LPF_PHASE0, LPF_PHASE1,
                    LPF_PROP_INTERFACIAL, LPF_PROP_LEARNED, LPF_PROP_UNIFORM, LpfError,
                    counts_shape, lpf_num_vectors, lpf_vectors)
@@ -80,6 +80,29 @@ class Context:
         _abi.lpf_full_enhanced(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
         return out
 
+    def s2(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+           phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF, out=None,
+           stream=None) -> torch.Tensor:
+        """Two-point counts W*H*S2 (eq. (S2dis)) in the layout of full()."""
+        if out is None:
+            out = torch.empty(counts_shape(cx, cy, phase_mask, layout), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_s2(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
+        return out
+
+    def s2_delta_swap(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                      swaps: torch.Tensor, phase_mask: int = LPF_BOTH, out=None,
+                      stream=None) -> torch.Tensor:
+        """delta int32 (n, nph, |D_c|) of the two-point counts for interchanges (n, 2)."""
+        n = swaps.shape[0]
+        nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+        if out is None:
+            out = torch.empty((n, nph, lpf_num_vectors(cx, cy)), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_s2_delta_swap(self.handle, bits, W, H, cx, cy, phase_mask, swaps.contiguous(),
+                               n, out, stream)
+        return out
+
     def delta_swap(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                    swaps: torch.Tensor, phase_mask: int = LPF_BOTH, out=None,
                    stream=None) -> torch.Tensor:
@@ -128,11 +151,17 @@ class Anneal:
     """A device-resident annealing chain (anneal_step); the tensors below are its state.
 
     bits (packed cell, updated in place), counts (int32 [nph][|D_c|]), e (float64 [1]) are
-    allocated here and owned by this object; target (int32 [nph][|D_c|]) is the caller's."""
+    allocated here and owned by this object; target (int32 [nph][|D_c|]) is the caller's.
+    descriptor "lpf" (the lineal path function) or "s2" (two-point counts, lpf_anneal_create_s2;
+    target then holds Context.s2 counts of the original)."""
 
     def __init__(self, ctx: Context, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                  phase_mask: int, target: torch.Tensor, Nt: int, seed: int, step0: int = 0,
-                 pos: torch.Tensor | None = None, n1: int = 0, stream=None):
+                 pos: torch.Tensor | None = None, n1: int = 0, stream=None,
+                 descriptor: str = "lpf"):
+        if descriptor not in ("lpf", "s2"):
+            raise ValueError("descriptor is 'lpf' or 's2'")
+        self.descriptor = descriptor
         self.ctx, self.W, self.H, self.cx, self.cy, self.phase_mask = ctx, W, H, cx, cy, phase_mask
         dev = bits.device
         self.bits = bits.clone().contiguous()
@@ -142,7 +171,7 @@ class Anneal:
         self.e = torch.zeros(1, dtype=torch.float64, device=dev)
         self.handle = _abi.lpf_anneal_create(ctx.handle, self.bits, W, H, cx, cy, phase_mask,
                                              self.counts, self.target, Nt, seed, step0, pos, n1,
-                                             self.e, stream)
+                                             self.e, stream, s2=descriptor == "s2")
 
     def step(self, n_candidates: int, T: float, out: torch.Tensor,
              proposal: int = LPF_PROP_UNIFORM, stream=None) -> None:

@@ -26,7 +26,7 @@ LPF_E_DEVICE = -5
 LPF_E_UNSUPPORTED = -95
 LPF_PHASE0, LPF_PHASE1, LPF_BOTH = 1, 2, 3
 LPF_OUT_HALF, LPF_OUT_GRID = 0, 1
-LPF_DELTA_AUTO, LPF_DELTA_RECOUNT, LPF_DELTA_RECORDS = 0, 1, 2
+LPF_DELTA_AUTO, LPF_DELTA_RECOUNT, LPF_DELTA_RECORDS, LPF_DELTA_S2 = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_uint64
@@ -57,6 +57,10 @@ _sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
 _sig("lpf_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
      _P, _i32, _P, ctypes.POINTER(_P), _P)
+_sig("lpf_anneal_create_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
+     _P, _i32, _P, ctypes.POINTER(_P), _P)
+_sig("lpf_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_s2_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
 _sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
 _sig("lpf_anneal_destroy", None, _P)
@@ -197,11 +201,38 @@ def lpf_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: in
                                _dev(delta, torch.int32, "delta") if n else None, _stream(stream)))
 
 
+def lpf_s2(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, phase_mask: int,
+           out_layout: int, counts: torch.Tensor, stream=None) -> None:
+    if bits.numel() != ((W + 63) // 64) * H:
+        raise ValueError("lpf_s2: bits size does not match W, H")
+    shp = counts_shape(cx, cy, phase_mask, out_layout) if 0 <= cx and 0 <= cy else None
+    if shp is not None and counts.numel() != int(torch.Size(shp).numel()):
+        raise ValueError(f"lpf_s2: counts must hold {shp} elements")
+    _check(_lib.lpf_s2(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+                       out_layout, _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_s2_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                      phase_mask: int, swaps: torch.Tensor, n: int, delta: torch.Tensor,
+                      stream=None) -> None:
+    if swaps.numel() != 2 * n:
+        raise ValueError("lpf_s2_delta_swap: swaps must hold n pairs")
+    nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+    if n and delta.numel() != n * nph * lpf_num_vectors(cx, cy):
+        raise ValueError("lpf_s2_delta_swap: delta must hold n * nph * |D_c| elements")
+    _check(_lib.lpf_s2_delta_swap(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy,
+                                  phase_mask, _dev(swaps, torch.int32, "swaps") if n else None, n,
+                                  _dev(delta, torch.int32, "delta") if n else None,
+                                  _stream(stream)))
+
+
 def lpf_anneal_create(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                       phase_mask: int, counts: torch.Tensor, target: torch.Tensor, Nt: int,
-                      seed: int, step0: int, pos, n1: int, e: torch.Tensor, stream=None) -> int:
+                      seed: int, step0: int, pos, n1: int, e: torch.Tensor, stream=None,
+                      s2: bool = False) -> int:
     h = _P()
-    _check(_lib.lpf_anneal_create(
+    fn = _lib.lpf_anneal_create_s2 if s2 else _lib.lpf_anneal_create
+    _check(fn(
         ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
         _dev(counts, torch.int32, "counts"), _dev(target, torch.int32, "target"), Nt, seed, step0,
         _dev(pos, torch.int32, "pos") if pos is not None else None, n1,

@@ -3,7 +3,8 @@
 // The K candidates of a step are evaluated in evaluation order (draw order, or the ranking of
 // k_rank_chunks / k_rank_merge when an order array is given), in rounds of 64 and then the rest
 // (at most 8192 each), so that a step whose first candidates are accepted costs one small round.
-// Each round is an evaluation kernel (recount method here, records method in k_rec.hip) that
+// Each round is an evaluation kernel (recount method here, records method in k_rec.hip, the
+// two-point probability descriptor in k_s2.hip) that
 // adds every candidate's integer energy sum S = sum dL (Nt (dL + 2L) - 2 N T) into S_acc and
 // stores its dL (int16 per term and candidate), followed by k_round_decide, which applies the
 // Metropolis test of Alg. "annealing" (accept iff de <= 0 or U < exp(-de / T), de = S / (N^2 Nt),
@@ -238,7 +239,9 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
       r.pi0 = L.rounds[0].k0;
       r.pC = L.rounds[0].C;
     }
-    e = L.records ? launch_rec_round(L, r, true, stream) : launch_round_recount(L, r, true, stream);
+    e = L.s2        ? launch_s2_round(L, r, true, stream)
+        : L.records ? launch_rec_round(L, r, true, stream)
+                    : launch_round_recount(L, r, true, stream);
     if (e != hipSuccess) return e;
     const bool decided_later = j == nr - 1 || (j == 0 && L.rounds[0].C <= 64);
     if (!decided_later) {
@@ -252,7 +255,7 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
                      L.slot, L.dl, L.dl_t, L.dl_k, L.nterms, L.N, L.Nt, L.e, L.counts_rw,
                      L.bits_rw, L.W, L.k_sel, L.out, L.S_acc, L.U, L.T, L.order, li0, lC);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (L.records) e = launch_rec_update(L.rg, L.ctl, L.cand, stream);
+  if (L.records && !L.s2) e = launch_rec_update(L.rg, L.ctl, L.cand, stream);
   return e;
 }
 
@@ -268,8 +271,9 @@ hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (const RoundPlan &r : L.rounds) {
-    e = L.records ? launch_rec_round(L, r, false, stream)
-                  : launch_round_recount(L, r, false, stream);
+    e = L.s2        ? launch_s2_round(L, r, false, stream)
+        : L.records ? launch_rec_round(L, r, false, stream)
+                    : launch_round_recount(L, r, false, stream);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_energy_sum, dim3((L.K + 255) / 256), dim3(256), 0, stream, L.S_acc, L.K,

@@ -91,6 +91,16 @@ struct DeltaPlan {
   bool use_lds = false;
 };
 
+// Launch plan of the two-point counts (k_s2.hip).
+struct S2Plan {
+  VecDesc *vecs = nullptr;   // device, sorted by (dy, dx)
+  int4 *groups = nullptr;    // device: {first, end, dy of first, dy of last}
+  int32_t *vec = nullptr;    // device, canonical order: (dx & 0xffff) | (dy << 16)
+  int ngroups = 0, rb = 0, nrb = 0, we = 0, swd = 0, rstB = 0;
+  size_t lds = 0;
+  int64_t nv = 0;
+};
+
 // Canonical half domain (eq. (segments) with a cutoff, one of each {v, -v}).
 void canonical_vectors(int cx, int cy, std::vector<int16_t> &out) {
   out.clear();
@@ -143,8 +153,9 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
+  std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
   std::map<std::string, struct BatchGraph *> batch_graphs;
-  DevBuf ext, ext3;
+  DevBuf ext, ext3, s2ext, s2acc;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -153,6 +164,7 @@ struct lpf_ctx_s {
 
 struct lpf_anneal_s {
   lpf_ctx ctx = nullptr;
+  bool s2 = false;  // descriptor: two-point probability, else lineal path
   int W = 0, H = 0, cx = 0, cy = 0;
   unsigned mask = 0;
   uint64_t *bits = nullptr;
@@ -355,6 +367,91 @@ void release_batch_graphs(lpf_ctx c) {
   for (auto &kv : c->batch_graphs) free_batch_graph(kv.second);
   c->batch_graphs.clear();
 }
+
+// Two-point counts plan: vectors sorted by (dy, dx), cut into groups of at most 256 whose dy
+// range keeps the staged rows within the LDS budget; start rows in blocks of rb.
+lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
+  auto key = std::make_tuple(W, H, cx, cy);
+  auto it = c->s2_plans.find(key);
+  if (it != c->s2_plans.end()) {
+    plan = &it->second;
+    return LPF_OK;
+  }
+  S2Plan p;
+  p.swd = (W + 31) / 32;
+  p.we = p.swd + ((W - 1) >> 5) + 1;  // start word + shift word + 1 for every s = dx mod W
+  p.rstB = p.we | 1;
+  auto bytes = [&](int rb, int span) {
+    return ((size_t)rb * p.swd + (size_t)(rb + span) * p.rstB) * sizeof(uint32_t);
+  };
+  size_t budget = 64 * 1024;
+  int rb = std::min(32, H);
+  while (rb > 1 && 2 * bytes(rb, 0) > budget) rb = (rb + 1) / 2;
+  if (bytes(rb, 0) > budget) budget = kMaxLds;
+  if (bytes(rb, 0) > budget) return fail(LPF_E_UNSUPPORTED, "lpf_s2: rows too wide for LDS staging");
+  const int span_max = (int)((budget / 4 - (size_t)rb * p.swd) / p.rstB) - rb;
+  std::vector<int16_t> can;
+  canonical_vectors(cx, cy, can);
+  const int64_t nv = (int64_t)can.size() / 2;
+  if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_s2: too many vectors");
+  std::vector<VecDesc> sorted(nv);
+  std::vector<int32_t> packed(nv);
+  for (int64_t i = 0; i < nv; ++i) {
+    sorted[i] = VecDesc{can[2 * i], can[2 * i + 1], (int32_t)i};
+    packed[i] = (int32_t)((uint32_t)(uint16_t)can[2 * i] | ((uint32_t)(uint16_t)can[2 * i + 1] << 16));
+  }
+  std::stable_sort(sorted.begin(), sorted.end(), [](const VecDesc &a, const VecDesc &b) {
+    return a.dy != b.dy ? a.dy < b.dy : a.dx < b.dx;
+  });
+  std::vector<int4> groups;
+  int max_span = 0;
+  for (int64_t i = 0; i < nv;) {
+    int64_t j = i;
+    const int dy0 = sorted[i].dy;
+    while (j < nv && j - i < 256 && sorted[j].dy - dy0 <= span_max) ++j;
+    groups.push_back(make_int4((int)i, (int)j, dy0, sorted[j - 1].dy));
+    max_span = std::max(max_span, (int)sorted[j - 1].dy - dy0);
+    i = j;
+  }
+  p.rb = rb;
+  p.nrb = (H + rb - 1) / rb;
+  p.ngroups = (int)groups.size();
+  p.lds = bytes(rb, max_span);
+  p.nv = nv;
+  hipError_t e;
+  if ((e = hipMalloc(&p.vecs, sizeof(VecDesc) * nv)) != hipSuccess ||
+      (e = hipMalloc(&p.groups, sizeof(int4) * groups.size())) != hipSuccess ||
+      (e = hipMalloc(&p.vec, sizeof(int32_t) * nv)) != hipSuccess) {
+    (void)hipFree(p.vecs);
+    (void)hipFree(p.groups);
+    (void)hipFree(p.vec);
+    return hip_fail(e, "lpf_s2: plan allocation");
+  }
+  if ((e = hipMemcpy(p.vecs, sorted.data(), sizeof(VecDesc) * nv, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.groups, groups.data(), sizeof(int4) * groups.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.vec, packed.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(p.vecs);
+    (void)hipFree(p.groups);
+    (void)hipFree(p.vec);
+    return hip_fail(e, "lpf_s2: plan upload");
+  }
+  auto res = c->s2_plans.emplace(key, p);
+  plan = &res.first->second;
+  return LPF_OK;
+}
+
+// Rounds of an S2 chain: candidates per workgroup and vector chunks (enough workgroups to fill
+// the device, at least 8 vectors per thread).
+void s2_rounds(std::vector<RoundPlan> &rounds, int64_t nv) {
+  for (RoundPlan &r : rounds) {
+    r.block = r.C <= 64 ? 64 : (r.C <= 128 ? 128 : 256);
+    const int groups = (r.C + r.block - 1) / r.block;
+    r.nchunks = (int)std::max<int64_t>(1, std::min<int64_t>(2048 / groups, nv / 8));
+  }
+}
+
+// The packed cell fits the S2 round kernel's LDS staging.
+bool s2_img_lds(int W, int H) { return (size_t)H * ((W + 63) / 64) * 8 <= 64 * 1024; }
 
 int nph_of(unsigned mask) { return (int)(mask & 1u) + (int)((mask >> 1) & 1u); }
 
@@ -745,6 +842,7 @@ lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out) {
   hipError_t e = prepare_full_kernels(kMaxLds);
   if (e == hipSuccess) e = prepare_delta_kernels(kDeltaLdsMax);
   if (e == hipSuccess) e = prepare_step_kernels(kDeltaLdsMax);
+  if (e == hipSuccess) e = prepare_s2_kernels(kMaxLds);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "lpf_ctx_create: kernel attributes");
@@ -768,8 +866,15 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.chunk_off);
       (void)hipFree(kv.second.runs);
     }
+    for (auto &kv : c->s2_plans) {
+      (void)hipFree(kv.second.vecs);
+      (void)hipFree(kv.second.groups);
+      (void)hipFree(kv.second.vec);
+    }
     c->ext.release();
     c->ext3.release();
+    c->s2ext.release();
+    c->s2acc.release();
   }
   delete c;
 }
@@ -882,10 +987,75 @@ lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx,
   return LPF_OK;
 }
 
-lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
-                             unsigned phase_mask, uint32_t *counts, const uint32_t *target,
-                             int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
-                             int n1, double *e_dev, lpf_anneal *out, void *stream) {
+lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                  unsigned phase_mask, int out_layout, uint32_t *counts, void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_s2: ctx is NULL");
+  lpf_status st = check_image_args("lpf_s2", W, H, cx, cy, phase_mask);
+  if (st != LPF_OK) return st;
+  if (!bits || !counts) return fail(LPF_E_INVAL, "lpf_s2: NULL buffer");
+  if (out_layout != LPF_OUT_HALF && out_layout != LPF_OUT_GRID)
+    return fail(LPF_E_INVAL, "lpf_s2: out_layout");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_s2: cannot select the context's device");
+  S2Plan *plan = nullptr;
+  if ((st = get_s2_plan(c, W, H, cx, cy, plan)) != LPF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = c->s2ext.ensure((size_t)H * plan->we * sizeof(uint32_t))) != hipSuccess ||
+      (e = c->s2acc.ensure((size_t)plan->nv * sizeof(uint32_t))) != hipSuccess)
+    return hip_fail(e, "lpf_s2: scratch");
+  if ((e = launch_ext(bits, W, H, plan->we, (uint32_t *)c->s2ext.p, s)) != hipSuccess)
+    return hip_fail(e, "lpf_s2: ext");
+  S2Launch L{};
+  L.E = (const uint32_t *)c->s2ext.p;
+  L.W = W;
+  L.H = H;
+  L.we = plan->we;
+  L.swd = plan->swd;
+  L.rb = plan->rb;
+  L.nrb = plan->nrb;
+  L.rstB = plan->rstB;
+  L.ngroups = plan->ngroups;
+  L.cx = cx;
+  L.cy = cy;
+  L.layout = out_layout;
+  L.vecs = plan->vecs;
+  L.groups = plan->groups;
+  L.lds_bytes = plan->lds;
+  L.acc = (uint32_t *)c->s2acc.p;
+  L.nv = plan->nv;
+  L.phase_mask = phase_mask;
+  L.out = counts;
+  if ((e = launch_s2_full(L, s)) != hipSuccess) return hip_fail(e, "lpf_s2: kernel");
+  return LPF_OK;
+}
+
+lpf_status lpf_s2_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
+                             void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_s2_delta_swap: ctx is NULL");
+  lpf_status st = check_image_args("lpf_s2_delta_swap", W, H, cx, cy, phase_mask);
+  if (st != LPF_OK) return st;
+  if (n < 0 || n > (1 << 24)) return fail(LPF_E_INVAL, "lpf_s2_delta_swap: n outside [0, 2^24]");
+  if (n == 0) return LPF_OK;
+  if (!bits || !swaps || !delta) return fail(LPF_E_INVAL, "lpf_s2_delta_swap: NULL buffer");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_s2_delta_swap: cannot select the context's device");
+  S2Plan *plan = nullptr;
+  if ((st = get_s2_plan(c, W, H, cx, cy, plan)) != LPF_OK) return st;
+  hipError_t e = launch_s2_delta(bits, W, H, reinterpret_cast<const int2 *>(swaps), n, plan->vec,
+                                 plan->nv, phase_mask, delta, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lpf_s2_delta_swap: kernel");
+  return LPF_OK;
+}
+
+namespace {
+lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
+                         unsigned phase_mask, uint32_t *counts, const uint32_t *target, int64_t Nt,
+                         uint64_t seed, uint64_t step0, const int32_t *pos, int n1, double *e_dev,
+                         lpf_anneal *out, void *stream, bool s2) {
   if (!out) return fail(LPF_E_INVAL, "lpf_anneal_create: out is NULL");
   *out = nullptr;
   if (!c) return fail(LPF_E_INVAL, "lpf_anneal_create: ctx is NULL");
@@ -901,18 +1071,20 @@ lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, in
   {
     // exact energy sums: |dL| <= 2 (n + 1) per term, so every partial sum of
     // dL (Nt (dL + 2L) - 2 N T) is below nterms * dmax * Nt * (dmax + 4N); keep it in int64
-    const __int128 dmax = 2 * ((__int128)std::max(cx, cy) + 1);
+    const __int128 dmax = s2 ? 6 : 2 * ((__int128)std::max(cx, cy) + 1);
     const __int128 bound = (__int128)nph_of(phase_mask) * lpf_num_vectors(cx, cy) * dmax *
                            (__int128)Nt * (dmax + 4 * (__int128)W * H);
     if (bound > (__int128)INT64_MAX)
       return fail(LPF_E_UNSUPPORTED, "lpf_anneal_create: cell, cutoff and Nt too large for exact int64 energy sums");
   }
   // full evaluation for the initial counts (also validates the tile shape)
-  st = lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
+  st = s2 ? lpf_s2(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream)
+          : lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
   if (st != LPF_OK) return st;
   lpf_anneal a = new (std::nothrow) lpf_anneal_s();
   if (!a) return fail(LPF_E_NOMEM, "lpf_anneal_create: host memory");
   a->ctx = c;
+  a->s2 = s2;
   a->W = W; a->H = H; a->cx = cx; a->cy = cy; a->mask = phase_mask;
   a->bits = bits; a->counts = counts; a->target = target; a->e = e_dev;
   a->Nt = Nt; a->seed = seed;
@@ -983,6 +1155,23 @@ lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, in
   *out = a;
   return LPF_OK;
 }
+}  // namespace
+
+lpf_status lpf_anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
+                             unsigned phase_mask, uint32_t *counts, const uint32_t *target,
+                             int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
+                             int n1, double *e_dev, lpf_anneal *out, void *stream) {
+  return anneal_create(c, bits, W, H, cx, cy, phase_mask, counts, target, Nt, seed, step0, pos,
+                       n1, e_dev, out, stream, false);
+}
+
+lpf_status lpf_anneal_create_s2(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
+                                unsigned phase_mask, uint32_t *counts, const uint32_t *target,
+                                int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
+                                int n1, double *e_dev, lpf_anneal *out, void *stream) {
+  return anneal_create(c, bits, W, H, cx, cy, phase_mask, counts, target, Nt, seed, step0, pos,
+                       n1, e_dev, out, stream, true);
+}
 
 lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
                        void *stream) {
@@ -1000,13 +1189,20 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   DeviceGuard g(c->dev);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const bool rec = use_records(a);
+  const bool rec = !a->s2 && use_records(a);
   StepLaunch L{};
+  L.s2 = a->s2;
   L.records = rec;
   L.rounds = step_rounds(K, true);
   DeltaPlan *plan = nullptr;
   lpf_status st;
-  if (rec) {
+  if (a->s2) {
+    S2Plan *sp = nullptr;
+    if ((st = get_s2_plan(c, a->W, a->H, a->cx, a->cy, sp)) != LPF_OK) return st;
+    L.s2vec = sp->vec;
+    L.use_lds = s2_img_lds(a->W, a->H);
+    s2_rounds(L.rounds, sp->nv);
+  } else if (rec) {
     if ((st = setup_records(a, s)) != LPF_OK) return st;
     records_rounds(L.rounds);
   } else {
@@ -1040,7 +1236,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
       return hip_fail(e, "anneal_step: ranking");
     L.order = (const int32_t *)a->order.p;
   }
-  if (!rec) {
+  if (plan) {
     L.E = (const uint32_t *)a->E3.p;
     L.geo = plan->geo;
     L.runs = plan->runs;
@@ -1074,7 +1270,9 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   L.k_sel = (int32_t *)a->ksel.p;
   L.out = reinterpret_cast<StepResult *>(out);
   if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal_step: evaluation");
-  if (rec) {
+  if (a->s2) {
+    // the S2 rounds read the packed cell itself: nothing else to keep current
+  } else if (rec) {
     a->e3_valid = false;
   } else {
     a->rec_valid = false;
@@ -1531,13 +1729,20 @@ lpf_status lpf_anneal_delta_energy(lpf_anneal a, const int32_t *swaps, int n, do
   DeviceGuard g(c->dev);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const bool rec = use_records(a);
+  const bool rec = !a->s2 && use_records(a);
   StepLaunch L{};
+  L.s2 = a->s2;
   L.records = rec;
   L.rounds = step_rounds(n, false);
   DeltaPlan *plan = nullptr;
   lpf_status st;
-  if (rec) {
+  if (a->s2) {
+    S2Plan *sp = nullptr;
+    if ((st = get_s2_plan(c, a->W, a->H, a->cx, a->cy, sp)) != LPF_OK) return st;
+    L.s2vec = sp->vec;
+    L.use_lds = s2_img_lds(a->W, a->H);
+    s2_rounds(L.rounds, sp->nv);
+  } else if (rec) {
     if ((st = setup_records(a, s)) != LPF_OK) return st;
     records_rounds(L.rounds);
   } else {
@@ -1573,6 +1778,8 @@ lpf_status lpf_anneal_set_method(lpf_anneal a, int method) {
   if (!a) return fail(LPF_E_INVAL, "lpf_anneal_set_method: state is NULL");
   if (method != LPF_DELTA_AUTO && method != LPF_DELTA_RECOUNT && method != LPF_DELTA_RECORDS)
     return fail(LPF_E_INVAL, "lpf_anneal_set_method: method");
+  if (a->s2 && method != LPF_DELTA_AUTO)
+    return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: an S2 chain has a single method");
   std::string why;
   if (method == LPF_DELTA_RECORDS && !records_fit(a, nullptr, &why))
     return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: records: " + why);
@@ -1587,6 +1794,7 @@ int lpf_anneal_get_method(lpf_anneal a) {
     fail(LPF_E_INVAL, "lpf_anneal_get_method: state is NULL");
     return -1;
   }
+  if (a->s2) return LPF_DELTA_S2;
   std::lock_guard<std::mutex> lk(a->ctx->mu);
   DeviceGuard g(a->ctx->dev);
   return use_records(a) ? LPF_DELTA_RECORDS : LPF_DELTA_RECOUNT;

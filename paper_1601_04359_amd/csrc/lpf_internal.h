@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP sources of liblpf (not part of the C ABI).
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -109,6 +110,8 @@ struct RecGeo {
 };
 
 struct StepLaunch {
+  bool s2;                   // descriptor: two-point probability (k_s2.hip), else lineal path
+  const int32_t *s2vec;      // S2: canonical vectors, (dx & 0xffff) | (dy << 16)
   bool records;              // evaluation method: placement-state records, else recount
   bool reset_done;           // ctl and S_acc already zeroed by the candidate draw
   bool ordered;              // candidates are (phase-1 pixel, phase-0 pixel) pairs
@@ -236,5 +239,27 @@ hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int m
                             const uint64_t *pool, const int64_t *bits_off, uint32_t *ext,
                             const int64_t *ext_off, hipStream_t stream);
 hipError_t prepare_full_kernels(int max_lds_bytes);
+
+// ---- two-point probability (k_s2.hip) ----
+// Full evaluation: vectors sorted by (dy, dx) in groups of at most 256 (one workgroup each),
+// start rows in blocks of rb; acc holds the phase-1 sums [nv] before the output is written.
+struct S2Launch {
+  const uint32_t *E;        // extended image, H x we dwords, we >= swd + ((W - 1) >> 5) + 1
+  int W, H, we, swd, rb, nrb, rstB, ngroups, cx, cy, layout;
+  const VecDesc *vecs;      // dy-sorted
+  const int4 *groups;       // {first, end, dy of first, dy of last}
+  size_t lds_bytes;
+  uint32_t *acc;
+  int64_t nv;
+  unsigned phase_mask;
+  uint32_t *out;
+};
+hipError_t launch_s2_full(const S2Launch &L, hipStream_t stream);
+hipError_t launch_s2_delta(const uint64_t *bits, int W, int H, const int2 *swaps, int n,
+                           const int32_t *vec, int64_t nv, unsigned phase_mask, int32_t *delta,
+                           hipStream_t stream);
+hipError_t launch_s2_round(const StepLaunch &L, const RoundPlan &r, bool decide,
+                           hipStream_t stream);
+hipError_t prepare_s2_kernels(int max_lds_bytes);
 
 }  // namespace lpf
