@@ -66,6 +66,13 @@ def ops_alg(W: int, H: int, cx: int, cy: int, nph: int) -> float:
     return W * H / 32.0 * per_word
 
 
+def s2_ops_alg(W: int, H: int, cx: int, cy: int) -> float:
+    """Algorithmic integer ops of the two-point counts: one AND and one popcount per vector of
+    D_c per 32 start pixels (phase 1; phase 0 follows from eq. (S2add))."""
+    nv = (cx + 1) * (cy + 1) + cx * cy
+    return float(2 * nv * H * ((W + 31) // 32))
+
+
 def cpu_baseline(img, cx, cy, stride=16):
     """The CPU oracle on every `stride`-th vector of the same workload (all host threads)."""
     import numpy as np
@@ -350,6 +357,89 @@ def paper_bench(args) -> dict:
             "rows": rows}
 
 
+# Sec. 5, Table mutual: errors of the compressed particulate suspension under both descriptors
+# (the paper's normalisation of e is not stated; context only).
+PAPER_MUTUAL = {"random": (3.12e-1, 1.68e1), "S2": (9.20e-3, 2.35e0), "L2": (3.09e-1, 2.73e-2),
+                "L2w": (3.53e-1, 1.08e0), "L2b": (6.52e-1, 9.60e-1)}
+
+
+def mutual_run(ctx, steps, K=256, c=24, seed=1605, log=True):
+    """Compress the 100 x 100 particulate suspension (4 x 4 squares, phi 0.16) into a 50 x 50 cell
+    with each descriptor (S2 of the particle phase; L2 of both phases; L2 of the particles, w; L2
+    of the matrix, b) from one random start, then evaluate every result under S2 (particle phase)
+    and L2 (both phases) over |dx|, |dy| <= c.  Returns rows and the total annealing wall time."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import Anneal, step_records
+
+    dev = torch.device("cuda:0")
+    orig = wl.square_particles(100, 100, 4, 100, seed)
+    Nt, side = orig.size, 50
+    ob = ctx.pack(torch.from_numpy(orig).to(dev))
+    TL = ctx.full(ob, 100, 100, c, c, 3)
+    TS = ctx.s2(ob, 100, 100, c, c, 2)
+    cell = wl.random_cell(side, side, int(round(orig.mean() * side * side)), seed + 1)
+    TLh = TL.cpu().numpy().astype(np.float64)
+    TSh = TS.cpu().numpy().astype(np.float64)
+    N = side * side
+
+    def errors(bits):
+        L = ctx.full(bits, side, side, c, c, 3).cpu().numpy().astype(np.float64)
+        S = ctx.s2(bits, side, side, c, c, 2).cpu().numpy().astype(np.float64)
+        return float(((S / N - TSh / Nt) ** 2).sum()), float(((L / N - TLh / Nt) ** 2).sum())
+
+    bits0 = ctx.pack(torch.from_numpy(cell).to(dev))
+    rows = {"random": dict(zip(("e_S2", "e_L2"), errors(bits0)))}
+    plans = {"S2": ("s2", 2, TS), "L2": ("lpf", 3, TL), "L2w": ("lpf", 2, TL[1:2].clone()),
+             "L2b": ("lpf", 1, TL[0:1].clone())}
+    wall = 0.0
+    for name, (desc, mask, tgt) in plans.items():
+        ch = Anneal(ctx, bits0, side, side, c, c, mask, tgt, Nt, seed=7, descriptor=desc)
+        e0 = float(ch.e.cpu()[0])
+        Ts = e0 * 1e-3 * (1e-4 ** (1.0 / steps)) ** np.arange(steps)
+        recs = torch.empty((steps, 5), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ch.step(K, float(Ts[i]), recs[i])
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        r = step_records(recs)
+        eS, eL = errors(ch.bits)
+        rows[name] = {"e_S2": eS, "e_L2": eL, "own_e_start": e0, "own_e_final": float(r["e"][-1]),
+                      "accepted": int((r["k"] >= 0).sum())}
+        if log:
+            print(f"  {name}: own e {e0:.4g} -> {float(r['e'][-1]):.4g}, e(S2) {eS:.4g}, "
+                  f"e(L2) {eL:.4g}", file=sys.stderr, flush=True)
+        ch.close()
+    return rows, wall
+
+
+def mutual_bench(args) -> dict:
+    """Sec. 5 particulate-suspension comparison (Table mutual) on synthetic media."""
+    from paper_1601_04359_amd import Context
+    ctx = Context(0)
+    mutual_run(ctx, 50, log=False)  # warm-up: plans, kernels
+    rows, wall = mutual_run(ctx, args.steps)
+    ctx.close()
+    for k, v in rows.items():
+        v["paper_e_S2"], v["paper_e_L2"] = PAPER_MUTUAL[k]
+    total = 4 * args.steps
+    return {"metric": "annealing steps/s", "value": round(total / wall, 1), "unit": "steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 50,
+            "ms_per_step": round(wall * 1e3 / total, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+            "config": {"workload": "Sec. 5 particulate suspension: 100x100, 100 non-touching 4x4 "
+                                   "squares (phi 0.16, seed 1605) compressed to a 50x50 cell by "
+                                   "S2 (particle phase), L2 (both), L2w (particles), L2b "
+                                   "(matrix) annealing, |dx|,|dy| <= 24, 256 swaps per step, "
+                                   "T from 1e-3 e0 down by 1e-4 geometrically",
+                       "errors": "e = sum over D_c (and phases) of (C/N - C_t/N_t)^2 with "
+                                 "C = W H S2 or L; e(S2) on the particle phase, e(L2) on both"},
+            "rows": rows}
+
+
 def batch_bench(args) -> dict:
     """Uneven batch: 256 Boolean disk images, side ~ U{64,128,256,512,1024}, phi ~ U[0.2,0.6],
     r ~ U[3,15], cutoff side/2, both phases; one step = one lpf_batch call (persistent launch,
@@ -437,7 +527,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
-    ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper"],
+    ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper",
+                                           "mutual"],
                     default="full")
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
@@ -454,7 +545,7 @@ def main() -> int:
                          "as the reference kernel for HBM byte counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 20000 if args.workload in ("anneal", "learned") else 20
+        args.steps = {"anneal": 20000, "learned": 20000, "mutual": 20000}.get(args.workload, 20)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is a design note, not an implemented path)", file=sys.stderr)
@@ -471,6 +562,9 @@ def main() -> int:
         return 0
     if args.workload == "paper":
         print(json.dumps(paper_bench(args)), flush=True)
+        return 0
+    if args.workload == "mutual":
+        print(json.dumps(mutual_bench(args)), flush=True)
         return 0
 
     import numpy as np
@@ -523,6 +617,21 @@ def main() -> int:
             ctx.full_enhanced(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=enh, stream=stream)
             eevs[i][1].record(stream)
         stream.synchronize()
+        # two-point counts (eq. (S2dis)) of the same image and cutoff, for comparison
+        s2o = torch.empty_like(out)
+        ctx.s2(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=s2o, stream=stream)
+        unit = ctx.full(bits, W, H, 1, 1, 3, LPF_OUT_HALF, stream=stream)
+        s2u = ctx.s2(bits, W, H, 1, 1, 3, LPF_OUT_HALF, stream=stream)
+        stream.synchronize()
+        s2_unit_ok = bool(torch.equal(unit, s2u))
+        sevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+        for i in range(args.steps):
+            sevs[i][0].record(stream)
+            ctx.s2(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=s2o, stream=stream)
+            sevs[i][1].record(stream)
+        stream.synchronize()
+    s2_ms = float(np.mean([a.elapsed_time(b) for a, b in sevs]))
     step_ms = [a.elapsed_time(b) for a, b in evs]
     enh_ms = float(np.mean([a.elapsed_time(b) for a, b in eevs]))
     ms = wall * 1e3 / args.steps
@@ -561,6 +670,19 @@ def main() -> int:
                      "note": "segments abandoned per wave once no start pixel can still count "
                              "(Sec. 3.3 enhanced evaluation); not used for the roofline"},
     }
+    s2_ops = s2_ops_alg(W, H, cx, cy)
+    s2_ach = s2_ops / (s2_ms / 1e3) / 1e12
+    line["s2"] = {"ms_per_step": round(s2_ms, 4),
+                  "pair_placements_per_s_G": round(placements / (s2_ms / 1e3) / 1e9, 3),
+                  "roofline": {"bound": "alu", "achieved": round(s2_ach, 3),
+                               "peak": round(P_INT_TOPS, 3), "unit": "Tops/s",
+                               "frac": round(s2_ach / P_INT_TOPS, 4),
+                               "kernel": "k_s2_full (+k_ext, k_s2_zero, k_s2_finish inside the "
+                                         "event window)",
+                               "ops_alg_per_launch": s2_ops},
+                  "unit_steps_equal_lpf": s2_unit_ok,
+                  "note": "two-point counts W*H*S2 of the same image and cutoff (Sec. 2.1), "
+                          "both phases (phase 0 by eq. (S2add))"}
     ctx.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img, cx, cy, args.cpu_stride)
