@@ -6,11 +6,12 @@
 // periodic image.  The paper evaluates S2 with the FFT over all W x H shifts; over a cutoff
 // domain the direct count is exact in integers and costs one AND and one popcount per 32 start
 // pixels and vector, so it is done that way here:
-//   - a lane owns one vector v = (dx, dy) and walks the rows of its workgroup's row block; for
-//     start word w of row y it forms t = bits [32w + s, 32w + s + 32) of row y + dy of the
-//     extended image (s = dx mod W, one v_alignbit_b32) and adds popcount(row_y[w] & t);
-//   - row_y[w] is the same for every lane (an LDS broadcast), the shifted word is a gather from
-//     LDS; vectors are sorted by dy so that one workgroup needs few distinct rows;
+//   - a lane owns a family of up to J vectors (dx0 + 32 j, dy) and walks the rows of its
+//     workgroup's row block; for start word w of row y it forms t = bits [32w + s, 32w + s + 32)
+//     of row y + dy of the extended image (s = dx0 + W, one v_alignbit_b32), which is also member
+//     j's shifted word at w - j, and adds popcount(row_y[w] & t) into the members' counters;
+//   - row_y[w] is the same for every lane (an LDS broadcast), the shifted words are gathers from
+//     LDS; families are sorted by dy so that one workgroup needs few distinct rows;
 //   - phase 0 follows from eq. (S2add) in counts, C_0(v) = N - 2 N_1 + C_1(v), with
 //     N_1 = C_1(0) (v = 0 is the first vector of the canonical order).
 //
@@ -31,26 +32,31 @@ __global__ void k_s2_zero(uint32_t *__restrict__ acc, int64_t n) {
   if (i < n) acc[i] = 0;
 }
 
-// Phase-1 counts of the vectors of group blockIdx.x over start rows [y0, y0 + rb), y0 =
-// blockIdx.y * rb, added into acc (integer atomics: the sum does not depend on the order).
-// group = {first vector, end, dy of the first, dy of the last} in the dy-sorted list.
-// LDS: A = the block's rows (swd dwords each, bits past W cleared), B = rows y0 + dy_lo ..
+// Phase-1 counts over start rows [y0, y0 + rb), y0 = blockIdx.y * rb, for the vector families of
+// group blockIdx.x, added into acc (integer atomics: the sum does not depend on the order).
+// A family {dx0, dy, nj} is the vectors (dx0 + 32 j, dy), j < nj <= J, of one lane: with
+// s = dx0 + W (the same pairs as dx0 on the periodic image) member j's shifted word at start word
+// w is the family's shifted word at w + j, so one v_alignbit_b32 per word serves all J members.
+// group = {first family, end, dy of the first, dy of the last}, families sorted by dy.
+// LDS: A = the block's rows (swdp dwords each, zero past W), B = rows y0 + dy_lo ..
 // y0 + dy_hi + rb - 1 (mod H) of the extended image, rstB dwords apart.
+template <int J>
 __global__ void __launch_bounds__(256)
-k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int rb, int rstB,
-          const VecDesc *__restrict__ vecs, const int4 *__restrict__ groups,
-          uint32_t *__restrict__ acc) {
+k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swdp, int rb,
+          int rstB, int cx, int q1, const int4 *__restrict__ fams,
+          const int4 *__restrict__ groups, uint32_t *__restrict__ acc) {
+  constexpr int CW = 8;  // start words per chunk (swdp is a multiple of CW)
   extern __shared__ uint32_t lds[];
   const int4 g = groups[blockIdx.x];
   const int y0 = blockIdx.y * rb;
   const int rows = min(rb, H - y0);
   const int nB = rows + g.w - g.z;
   uint32_t *A = lds;
-  uint32_t *B = lds + rb * swd;
+  uint32_t *B = lds + rb * swdp;
   const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
-  for (int i = threadIdx.x; i < rows * swd; i += blockDim.x) {
-    const int r = i / swd, w = i - r * swd;
-    uint32_t v = E[(size_t)(y0 + r) * we + w];
+  for (int i = threadIdx.x; i < rows * swdp; i += blockDim.x) {
+    const int r = i / swdp, w = i - r * swdp;
+    uint32_t v = w < swd ? E[(size_t)(y0 + r) * we + w] : 0u;
     if (w == swd - 1) v &= lastmask;
     A[i] = v;
   }
@@ -60,33 +66,40 @@ k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int rb,
     B[r * rstB + e] = E[(size_t)y * we + e];
   }
   __syncthreads();
-  const int j = g.x + (int)threadIdx.x;
-  if (j >= g.y) return;  // no barrier follows
-  const VecDesc v = vecs[j];
-  const int s = v.dx >= 0 ? v.dx : v.dx + W;
-  const int sh = s & 31;
-  const uint32_t *b = B + (v.dy - g.z) * rstB + (s >> 5);
-  uint32_t c = 0;
+  const int f = g.x + (int)threadIdx.x;
+  if (f >= g.y) return;  // no barrier follows
+  const int4 fm = fams[f];
+  const int s0 = fm.x + W;
+  const int sh = s0 & 31;
+  const uint32_t *b = B + (fm.y - g.z) * rstB + (s0 >> 5);
+  uint32_t c[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) c[j] = 0;
   for (int r = 0; r < rows; ++r) {
-    const uint32_t *a = A + r * swd;
+    const uint32_t *a = A + r * swdp;
     const uint32_t *bb = b + r * rstB;
-    uint32_t lo = bb[0];
-    int w = 0;
-    for (; w + 4 <= swd; w += 4) {
-      const uint32_t h0 = bb[w + 1], h1 = bb[w + 2], h2 = bb[w + 3], h3 = bb[w + 4];
-      c += __popc(a[w] & __builtin_amdgcn_alignbit(h0, lo, sh));
-      c += __popc(a[w + 1] & __builtin_amdgcn_alignbit(h1, h0, sh));
-      c += __popc(a[w + 2] & __builtin_amdgcn_alignbit(h2, h1, sh));
-      c += __popc(a[w + 3] & __builtin_amdgcn_alignbit(h3, h2, sh));
-      lo = h3;
-    }
-    for (; w < swd; ++w) {
-      const uint32_t hi = bb[w + 1];
-      c += __popc(a[w] & __builtin_amdgcn_alignbit(hi, lo, sh));
-      lo = hi;
+    for (int w0 = 0; w0 < swdp; w0 += CW) {
+      uint32_t av[CW], d[CW + J], t[CW + J - 1];
+#pragma unroll
+      for (int i = 0; i < CW; ++i) av[i] = a[w0 + i];
+#pragma unroll
+      for (int k = 0; k < CW + J; ++k) d[k] = bb[w0 + k];
+#pragma unroll
+      for (int k = 0; k < CW + J - 1; ++k) t[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int i = 0; i < CW; ++i) c[j] += __popc(av[i] & t[i + j]);
     }
   }
-  if (c) atomicAdd(&acc[v.idx], c);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < fm.z && c[j]) {
+      const int dx = fm.x + 32 * j, dy = fm.y;
+      const int idx = dx >= 0 ? dy * (cx + 1) + dx : q1 + (dy - 1) * cx + (dx + cx);
+      atomicAdd(&acc[idx], c[j]);
+    }
+  }
 }
 
 // Canonical vector i of the half domain with cutoff (cx, cy): the rectangle [0,cx] x [0,cy] row
@@ -136,8 +149,19 @@ hipError_t launch_s2_full(const S2Launch &L, hipStream_t stream) {
                      L.nv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_s2_full, dim3((unsigned)L.ngroups, (unsigned)L.nrb), dim3(256), L.lds_bytes,
-                     stream, L.E, L.W, L.H, L.we, L.swd, L.rb, L.rstB, L.vecs, L.groups, L.acc);
+  const dim3 grid((unsigned)L.ngroups, (unsigned)L.nrb);
+  const int q1 = (L.cx + 1) * (L.cy + 1);
+#define LPF_S2_FULL(JJ)                                                                        \
+  hipLaunchKernelGGL((k_s2_full<JJ>), grid, dim3(256), L.lds_bytes, stream, L.E, L.W, L.H, L.we, \
+                     L.swd, L.swdp, L.rb, L.rstB, L.cx, q1, L.fams, L.groups, L.acc)
+  switch (L.J) {
+    case 1: LPF_S2_FULL(1); break;
+    case 2: LPF_S2_FULL(2); break;
+    case 4: LPF_S2_FULL(4); break;
+    case 8: LPF_S2_FULL(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LPF_S2_FULL
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_s2_finish, dim3((unsigned)((L.nv + 255) / 256)), dim3(256), 0, stream,
                      L.acc, L.nv, L.cx, L.cy, (int64_t)L.W * L.H, L.phase_mask, L.layout, L.out);
@@ -310,9 +334,14 @@ hipError_t launch_s2_round(const StepLaunch &L, const RoundPlan &r, bool decide,
 hipError_t prepare_s2_kernels(int max_lds_bytes) {
   hipError_t e = hipFuncSetAttribute((const void *)k_s2_round<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-  hipError_t r = hipFuncSetAttribute((const void *)k_s2_full,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
-  return e != hipSuccess ? e : r;
+  const void *full[] = {(const void *)k_s2_full<1>, (const void *)k_s2_full<2>,
+                        (const void *)k_s2_full<4>, (const void *)k_s2_full<8>};
+  for (const void *fn : full) {
+    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       max_lds_bytes);
+    if (e == hipSuccess) e = r;
+  }
+  return e;
 }
 
 }  // namespace lpf

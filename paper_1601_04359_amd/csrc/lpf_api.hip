@@ -93,10 +93,10 @@ struct DeltaPlan {
 
 // Launch plan of the two-point counts (k_s2.hip).
 struct S2Plan {
-  VecDesc *vecs = nullptr;   // device, sorted by (dy, dx)
+  int4 *fams = nullptr;      // device: vector families {dx0, dy, members}, sorted by dy
   int4 *groups = nullptr;    // device: {first, end, dy of first, dy of last}
   int32_t *vec = nullptr;    // device, canonical order: (dx & 0xffff) | (dy << 16)
-  int ngroups = 0, rb = 0, nrb = 0, we = 0, swd = 0, rstB = 0;
+  int ngroups = 0, rb = 0, nrb = 0, we = 0, swd = 0, swdp = 0, J = 1, rstB = 0;
   size_t lds = 0;
   int64_t nv = 0;
 };
@@ -368,8 +368,11 @@ void release_batch_graphs(lpf_ctx c) {
   c->batch_graphs.clear();
 }
 
-// Two-point counts plan: vectors sorted by (dy, dx), cut into groups of at most 256 whose dy
-// range keeps the staged rows within the LDS budget; start rows in blocks of rb.
+// Two-point counts plan.  Vector families {dx0, dy, nj}: for each dy, the dx of D_c taken in
+// 32 residue classes, each class cut into runs of at most J members 32 apart (J = 1, 2, 4 or 8
+// from the widest dx range); families sorted by dy and cut into groups of at most 256 whose dy
+// range keeps the staged rows within the LDS budget; start rows in blocks of rb, halved (down to
+// 4) until the launch has about 2048 workgroups.
 lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
   auto key = std::make_tuple(W, H, cx, cy);
   auto it = c->s2_plans.find(key);
@@ -377,41 +380,52 @@ lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
     plan = &it->second;
     return LPF_OK;
   }
+  const int64_t nv = lpf_num_vectors(cx, cy);
+  if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_s2: too many vectors");
   S2Plan p;
+  const int range = cy > 0 ? 2 * cx + 1 : cx + 1;  // widest dx range of one dy
+  p.J = std::min(8, next_pow2((range + 31) / 32));
   p.swd = (W + 31) / 32;
-  p.we = p.swd + ((W - 1) >> 5) + 1;  // start word + shift word + 1 for every s = dx mod W
+  p.swdp = (p.swd + 7) / 8 * 8;
+  p.we = ((W + cx) >> 5) + p.swdp + p.J;  // the last gather of a family: (s0 >> 5) + swdp + J - 1
   p.rstB = p.we | 1;
   auto bytes = [&](int rb, int span) {
-    return ((size_t)rb * p.swd + (size_t)(rb + span) * p.rstB) * sizeof(uint32_t);
+    return ((size_t)rb * p.swdp + (size_t)(rb + span) * p.rstB) * sizeof(uint32_t);
   };
   size_t budget = 64 * 1024;
   int rb = std::min(32, H);
   while (rb > 1 && 2 * bytes(rb, 0) > budget) rb = (rb + 1) / 2;
   if (bytes(rb, 0) > budget) budget = kMaxLds;
   if (bytes(rb, 0) > budget) return fail(LPF_E_UNSUPPORTED, "lpf_s2: rows too wide for LDS staging");
-  const int span_max = (int)((budget / 4 - (size_t)rb * p.swd) / p.rstB) - rb;
-  std::vector<int16_t> can;
-  canonical_vectors(cx, cy, can);
-  const int64_t nv = (int64_t)can.size() / 2;
-  if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_s2: too many vectors");
-  std::vector<VecDesc> sorted(nv);
-  std::vector<int32_t> packed(nv);
-  for (int64_t i = 0; i < nv; ++i) {
-    sorted[i] = VecDesc{can[2 * i], can[2 * i + 1], (int32_t)i};
-    packed[i] = (int32_t)((uint32_t)(uint16_t)can[2 * i] | ((uint32_t)(uint16_t)can[2 * i + 1] << 16));
+  const int span_max = (int)((budget / 4 - (size_t)rb * p.swdp) / p.rstB) - rb;
+  std::vector<int4> fams;
+  for (int dy = 0; dy <= cy; ++dy) {
+    const int lo = dy == 0 ? 0 : -cx;
+    const int n = dy == 0 ? cx + 1 : 2 * cx + 1;
+    for (int r = 0; r < std::min(32, n); ++r) {
+      const int members = (n - r + 31) / 32;
+      for (int m = 0; m < members; m += p.J)
+        fams.push_back(make_int4(lo + r + 32 * m, dy, std::min(p.J, members - m), 0));
+    }
   }
-  std::stable_sort(sorted.begin(), sorted.end(), [](const VecDesc &a, const VecDesc &b) {
-    return a.dy != b.dy ? a.dy < b.dy : a.dx < b.dx;
-  });
   std::vector<int4> groups;
   int max_span = 0;
-  for (int64_t i = 0; i < nv;) {
+  const int64_t nf = (int64_t)fams.size();
+  for (int64_t i = 0; i < nf;) {
     int64_t j = i;
-    const int dy0 = sorted[i].dy;
-    while (j < nv && j - i < 256 && sorted[j].dy - dy0 <= span_max) ++j;
-    groups.push_back(make_int4((int)i, (int)j, dy0, sorted[j - 1].dy));
-    max_span = std::max(max_span, (int)sorted[j - 1].dy - dy0);
+    const int dy0 = fams[i].y;
+    while (j < nf && j - i < 256 && fams[j].y - dy0 <= span_max) ++j;
+    groups.push_back(make_int4((int)i, (int)j, dy0, fams[j - 1].y));
+    max_span = std::max(max_span, fams[j - 1].y - dy0);
     i = j;
+  }
+  while (rb > 4 && (int64_t)groups.size() * ((H + rb - 1) / rb) < 2048) rb /= 2;
+  std::vector<int32_t> packed(nv);
+  {
+    std::vector<int16_t> can;
+    canonical_vectors(cx, cy, can);
+    for (int64_t i = 0; i < nv; ++i)
+      packed[i] = (int32_t)((uint32_t)(uint16_t)can[2 * i] | ((uint32_t)(uint16_t)can[2 * i + 1] << 16));
   }
   p.rb = rb;
   p.nrb = (H + rb - 1) / rb;
@@ -419,18 +433,18 @@ lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
   p.lds = bytes(rb, max_span);
   p.nv = nv;
   hipError_t e;
-  if ((e = hipMalloc(&p.vecs, sizeof(VecDesc) * nv)) != hipSuccess ||
+  if ((e = hipMalloc(&p.fams, sizeof(int4) * fams.size())) != hipSuccess ||
       (e = hipMalloc(&p.groups, sizeof(int4) * groups.size())) != hipSuccess ||
       (e = hipMalloc(&p.vec, sizeof(int32_t) * nv)) != hipSuccess) {
-    (void)hipFree(p.vecs);
+    (void)hipFree(p.fams);
     (void)hipFree(p.groups);
     (void)hipFree(p.vec);
     return hip_fail(e, "lpf_s2: plan allocation");
   }
-  if ((e = hipMemcpy(p.vecs, sorted.data(), sizeof(VecDesc) * nv, hipMemcpyHostToDevice)) != hipSuccess ||
+  if ((e = hipMemcpy(p.fams, fams.data(), sizeof(int4) * fams.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p.groups, groups.data(), sizeof(int4) * groups.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p.vec, packed.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
-    (void)hipFree(p.vecs);
+    (void)hipFree(p.fams);
     (void)hipFree(p.groups);
     (void)hipFree(p.vec);
     return hip_fail(e, "lpf_s2: plan upload");
@@ -867,7 +881,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.runs);
     }
     for (auto &kv : c->s2_plans) {
-      (void)hipFree(kv.second.vecs);
+      (void)hipFree(kv.second.fams);
       (void)hipFree(kv.second.groups);
       (void)hipFree(kv.second.vec);
     }
@@ -1013,6 +1027,8 @@ lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
   L.H = H;
   L.we = plan->we;
   L.swd = plan->swd;
+  L.swdp = plan->swdp;
+  L.J = plan->J;
   L.rb = plan->rb;
   L.nrb = plan->nrb;
   L.rstB = plan->rstB;
@@ -1020,7 +1036,7 @@ lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
   L.cx = cx;
   L.cy = cy;
   L.layout = out_layout;
-  L.vecs = plan->vecs;
+  L.fams = plan->fams;
   L.groups = plan->groups;
   L.lds_bytes = plan->lds;
   L.acc = (uint32_t *)c->s2acc.p;

@@ -241,12 +241,13 @@ hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int m
 hipError_t prepare_full_kernels(int max_lds_bytes);
 
 // ---- two-point probability (k_s2.hip) ----
-// Full evaluation: vectors sorted by (dy, dx) in groups of at most 256 (one workgroup each),
-// start rows in blocks of rb; acc holds the phase-1 sums [nv] before the output is written.
+// Full evaluation: vector families {dx0, dy, nj} (members dx0 + 32 j, j < nj <= J) sorted by
+// dy, in groups of at most 256 (one workgroup each), start rows in blocks of rb; acc holds the
+// phase-1 sums [nv] before the output is written.
 struct S2Launch {
-  const uint32_t *E;        // extended image, H x we dwords, we >= swd + ((W - 1) >> 5) + 1
-  int W, H, we, swd, rb, nrb, rstB, ngroups, cx, cy, layout;
-  const VecDesc *vecs;      // dy-sorted
+  const uint32_t *E;        // extended image, H x we dwords, we >= ((W + cx) >> 5) + swdp + J
+  int W, H, we, swd, swdp, J, rb, nrb, rstB, ngroups, cx, cy, layout;
+  const int4 *fams;         // dy-sorted families
   const int4 *groups;       // {first, end, dy of first, dy of last}
   size_t lds_bytes;
   uint32_t *acc;
