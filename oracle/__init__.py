@@ -62,6 +62,13 @@ def _load():
     lib.oracle_anneal_run_desc.argtypes = [P, i32, i32, i32, i32, u32, i32, P, P, i64, u64, u64,
                                            i32, i32, P, i32, P, P, P, P, i32]
     lib.oracle_anneal_run_desc.restype = i32
+    lib.oracle_lpf_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, i32]
+    lib.oracle_lpf_sampled.restype = i32
+    lib.oracle_delta_swap_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, i32, P, i32]
+    lib.oracle_delta_swap_sampled.restype = i32
+    lib.oracle_anneal_run_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, P, i64, u64, u64,
+                                              i32, i32, P, i32, P, P, P, P, i32]
+    lib.oracle_anneal_run_sampled.restype = i32
     lib.oracle_s2_vectors.argtypes = [P, i32, i32, P, i64, u32, P, i32]
     lib.oracle_s2_vectors.restype = i32
     lib.oracle_s2.argtypes = [P, i32, i32, i32, i32, u32, i32, P, i32]
@@ -150,6 +157,41 @@ def delta_swap(img, cx: int, cy: int, swaps, phase_mask: int = 3, full: bool = F
     return out
 
 
+def _sample(sample, shape) -> np.ndarray:
+    m = np.ascontiguousarray(sample, dtype=np.uint8)
+    if m.shape != shape:
+        raise ValueError("sample mask must have the image's shape")
+    return m
+
+
+def lpf_sampled(img, cx: int, cy: int, sample, phase_mask: int = 3,
+                nthreads: int = 0) -> np.ndarray:
+    """Monte-Carlo approximation in counts: uint32 [nph][|D_c|], segments tested only at the start
+    positions where the (H, W) mask `sample` is nonzero."""
+    a = _img(img)
+    H, W = a.shape
+    m = _sample(sample, a.shape)
+    out = np.zeros((nphases(phase_mask), num_vectors(cx, cy)), np.uint32)
+    rc = _load().oracle_lpf_sampled(_ptr(a), W, H, cx, cy, phase_mask, _ptr(m), _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_lpf_sampled failed ({rc})")
+    return out
+
+
+def delta_swap_sampled(img, cx: int, cy: int, sample, swaps, phase_mask: int = 3,
+                       nthreads: int = 0) -> np.ndarray:
+    a = _img(img)
+    H, W = a.shape
+    m = _sample(sample, a.shape)
+    sw = np.ascontiguousarray(swaps, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros((len(sw), nphases(phase_mask), num_vectors(cx, cy)), np.int32)
+    rc = _load().oracle_delta_swap_sampled(_ptr(a), W, H, cx, cy, phase_mask, _ptr(m), _ptr(sw),
+                                           len(sw), _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_delta_swap_sampled failed ({rc})")
+    return out
+
+
 def s2(img, cx: int, cy: int, phase_mask: int = 3, layout: int = 0, nthreads: int = 0) -> np.ndarray:
     """Two-point counts W*H*S2 (eq. (S2dis)), uint32 [nph][|D_c|] (layout 0) or
     [nph][2cy+1][2cx+1] (layout 1)."""
@@ -216,7 +258,7 @@ class AnnealState:
     """Host copy of an annealing chain: image, counts, target counts, pixel lists, error."""
 
     def __init__(self, img, cx, cy, phase_mask, target, Nt, seed, nthreads=0,
-                 descriptor: int = DESC_LPF):
+                 descriptor: int = DESC_LPF, sample=None):
         self.img = _img(img).copy()
         self.H, self.W = self.img.shape
         self.cx, self.cy, self.phase_mask = cx, cy, phase_mask
@@ -229,24 +271,37 @@ class AnnealState:
         self.pos1 = np.flatnonzero(flat == 1).astype(np.int32)
         self.pos0 = np.flatnonzero(flat == 0).astype(np.int32)
         self.descriptor = descriptor
-        if descriptor == DESC_LPF:
+        self.sample = None if sample is None else _sample(sample, self.img.shape).copy()
+        if self.sample is not None:
+            if descriptor != DESC_LPF:
+                raise ValueError("a position set applies to the lineal path function only")
+            self.counts = lpf_sampled(self.img, cx, cy, self.sample, phase_mask, nthreads)
+        elif descriptor == DESC_LPF:
             self.counts = lpf(self.img, cx, cy, phase_mask, 0, nthreads)
         elif descriptor == DESC_S2:
             self.counts = s2(self.img, cx, cy, phase_mask, 0, nthreads)
         else:
             raise ValueError("descriptor")
-        self.e = lse(self.counts, self.target, self.W * self.H, self.Nt)
+        self.N = self.W * self.H if self.sample is None else int(np.count_nonzero(self.sample))
+        self.e = lse(self.counts, self.target, self.N, self.Nt)
 
     def run(self, nsteps: int, K: int, Ts, proposal: int = 0) -> np.ndarray:
         Ts = np.ascontiguousarray(Ts, dtype=np.float64)
         assert Ts.size == nsteps
         res = np.zeros(nsteps, STEP_DTYPE)
         e = np.array([self.e], np.float64)
-        rc = _load().oracle_anneal_run_desc(
-            _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask, self.descriptor,
-            _ptr(self.counts),
-            _ptr(self.target), self.Nt, self.seed, self.step, nsteps, K, _ptr(Ts), proposal,
-            _ptr(self.pos1), _ptr(self.pos0), _ptr(e), _ptr(res), self.nthreads)
+        if self.sample is not None:
+            rc = _load().oracle_anneal_run_sampled(
+                _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask,
+                _ptr(self.sample), _ptr(self.counts), _ptr(self.target), self.Nt, self.seed,
+                self.step, nsteps, K, _ptr(Ts), proposal, _ptr(self.pos1), _ptr(self.pos0), _ptr(e),
+                _ptr(res), self.nthreads)
+        else:
+            rc = _load().oracle_anneal_run_desc(
+                _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask,
+                self.descriptor, _ptr(self.counts), _ptr(self.target), self.Nt, self.seed,
+                self.step, nsteps, K, _ptr(Ts), proposal, _ptr(self.pos1), _ptr(self.pos0), _ptr(e),
+                _ptr(res), self.nthreads)
         if rc:
             raise ValueError(f"oracle_anneal_run failed ({rc})")
         self.e = float(e[0])

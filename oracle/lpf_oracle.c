@@ -16,6 +16,9 @@
  *   - oracle_delta_swap*    Sec. 4 modification operator (two-pixel interchange), evaluated as
  *                           L(I') - L(I): by two full evaluations, and by a recount restricted
  *                           to the translations whose segment covers a swapped pixel.
+ *   - oracle_lpf_sampled    Sec. 3 opening: the Monte-Carlo approximation, segments compared at a
+ *                           given set of start positions only (and its interchange update and
+ *                           chain: oracle_delta_swap_sampled, oracle_anneal_run_sampled).
  *   - oracle_s2*            Sec. 2.1, eq. (S2dis): two-point probability counts (definition sum).
  *   - oracle_s2_delta_swap  Sec. 4 interchange applied to eq. (S2dis), recounting the pairs that
  *                           contain a swapped pixel.
@@ -211,6 +214,55 @@ int oracle_lpf(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Monte-Carlo approximation (Sec. 3, opening paragraph): the segments are compared with the
+ * image only at a chosen set X of start positions.  counts[p][i] = #{x in X : every pixel of
+ * x + path(v_i) is in phase p}, canonical half domain; X is given as a W x H byte mask (nonzero
+ * = x in X).  With X = every pixel this is oracle_lpf.
+ * ------------------------------------------------------------------------------------------ */
+int oracle_lpf_sampled(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                       const uint8_t *sample, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1) return -22;
+  if (!phase_mask || (phase_mask & ~3u)) return -22;
+  int64_t nv = oracle_num_vectors(cx, cy);
+  int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
+  oracle_vectors(cx, cy, v);
+  int maxlen = (cx > cy ? cx : cy) + 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel
+  {
+    int *px = (int *)malloc(sizeof(int) * maxlen);
+    int *py = (int *)malloc(sizeof(int) * maxlen);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nv; ++i) {
+      int np = oracle_bresenham(v[2 * i], v[2 * i + 1], px, py);
+      int p = 0;
+      for (int ph = 0; ph < 2; ++ph) {
+        if (!(phase_mask & (1u << ph))) continue;
+        uint32_t count = 0;
+        for (int y = 0; y < H; ++y)
+          for (int x = 0; x < W; ++x) {
+            if (!sample[(size_t)y * W + x]) continue;
+            int k;
+            for (k = 0; k < np; ++k)
+              if (img[(size_t)wrap(y + py[k], H) * W + wrap(x + px[k], W)] != ph) break;
+            if (k == np) count += 1;
+          }
+        counts[(size_t)p * nv + i] = count;
+        ++p;
+      }
+    }
+    free(px);
+    free(py);
+  }
+  free(v);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
  * Two-point probability (Sec. 2.1, eq. (S2dis)) as integer counts C_p(v) = W H S2^p(v):
  * the number of pixels x of the periodic image with x and x + v both in phase p.  Written as
  * the definition's double sum; the paper evaluates the same sum through the FFT, which the
@@ -328,7 +380,8 @@ static inline int seg_in_phase(const uint8_t *img, int W, int H, int x, int y, c
 /* Restricted recount: only translations whose segment covers a or b can change, so
  * delta = sum over x in (P_a u P_b) of [lambda(x; I') - lambda(x; I)], P_a = {a - p_k}. */
 static void delta_one(const uint8_t *img, int W, int H, const int *px, const int *py, int np,
-                      int a, int b, unsigned phase_mask, int32_t *out /* [nph] */) {
+                      int a, int b, unsigned phase_mask, const uint8_t *sample /* or NULL */,
+                      int32_t *out /* [nph] */) {
   int ax = a % W, ay = a / W, bx = b % W, by = b / W;
   int p = 0;
   for (int ph = 0; ph < 2; ++ph) {
@@ -346,6 +399,7 @@ static void delta_one(const uint8_t *img, int W, int H, const int *px, const int
               if (wrap(x + px[j], W) == ax && wrap(y + py[j], H) == ay) dup = 1;
             if (dup) continue;
           }
+          if (sample && !sample[(size_t)y * W + x]) continue;  /* x not in the position set */
           d += seg_in_phase(img, W, H, x, y, px, py, np, (uint8_t)ph, a, b) -
                seg_in_phase(img, W, H, x, y, px, py, np, (uint8_t)ph, -1, -1);
         }
@@ -355,8 +409,9 @@ static void delta_one(const uint8_t *img, int W, int H, const int *px, const int
   }
 }
 
-int oracle_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
-                      const int32_t *swaps, int n, int32_t *delta, int nthreads) {
+static int delta_swap_impl(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                           const int32_t *swaps, int n, const uint8_t *sample, int32_t *delta,
+                           int nthreads) {
   if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1) return -22;
   if (!phase_mask || (phase_mask & ~3u)) return -22;
   int64_t nv = oracle_num_vectors(cx, cy);
@@ -383,7 +438,7 @@ int oracle_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned
     for (int s = 0; s < n; ++s)
       for (int64_t i = 0; i < nv; ++i) {
         int np = oracle_bresenham(v[2 * i], v[2 * i + 1], px, py);
-        delta_one(img, W, H, px, py, np, swaps[2 * s], swaps[2 * s + 1], phase_mask, tmp);
+        delta_one(img, W, H, px, py, np, swaps[2 * s], swaps[2 * s + 1], phase_mask, sample, tmp);
         for (int p = 0; p < nph; ++p) delta[((size_t)s * nph + p) * nv + i] = tmp[p];
       }
     free(px);
@@ -391,6 +446,19 @@ int oracle_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned
   }
   free(v);
   return 0;
+}
+
+int oracle_delta_swap(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                      const int32_t *swaps, int n, int32_t *delta, int nthreads) {
+  return delta_swap_impl(img, W, H, cx, cy, phase_mask, swaps, n, NULL, delta, nthreads);
+}
+
+/* The change of the sampled counts (oracle_lpf_sampled) under pixel interchanges: the restricted
+ * recount over the placements through a or b that lie in the position set. */
+int oracle_delta_swap_sampled(const uint8_t *img, int W, int H, int cx, int cy,
+                              unsigned phase_mask, const uint8_t *sample, const int32_t *swaps,
+                              int n, int32_t *delta, int nthreads) {
+  return delta_swap_impl(img, W, H, cx, cy, phase_mask, swaps, n, sample, delta, nthreads);
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -526,21 +594,27 @@ double oracle_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms
 
 /* descriptor 0: the lineal path function (counts = L); descriptor 1: the two-point probability
  * (counts = W H S2, Sec. 2.1), the descriptor the paper compares against in Sec. 5. */
-int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
-                           int descriptor,
-                           uint32_t *counts /* [nph][nv], must equal the descriptor of img */,
-                           const uint32_t *target /* [nph][nv] */, int64_t Nt, uint64_t seed,
-                           uint64_t step0, int nsteps, int K, const double *Ts /* [nsteps] */,
-                           int proposal, int32_t *pos1, int32_t *pos0 /* in/out */,
-                           double *e_io, oracle_step_result *res /* [nsteps] */, int nthreads) {
+/* sample (LPF only): the Monte-Carlo position set of the cell; the counts are then sampled
+ * counts and N in the objective is the number of sampled positions. */
+static int anneal_core(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                       int descriptor, const uint8_t *sample, uint32_t *counts,
+                       const uint32_t *target, int64_t Nt, uint64_t seed, uint64_t step0,
+                       int nsteps, int K, const double *Ts, int proposal, int32_t *pos1,
+                       int32_t *pos0, double *e_io, oracle_step_result *res, int nthreads) {
   if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1 || K < 1) return -22;
   if (descriptor != 0 && descriptor != 1) return -22;
+  if (sample && descriptor != 0) return -22;
   int64_t nv = oracle_num_vectors(cx, cy);
   int nph = (phase_mask & 1) + ((phase_mask >> 1) & 1);
   int64_t N = (int64_t)W * H;
+  if (sample) {
+    N = 0;
+    for (int64_t q = 0; q < (int64_t)W * H; ++q) N += sample[q] != 0;
+    if (N < 1) return -22;
+  }
   int n1 = 0;
-  for (int64_t q = 0; q < N; ++q) n1 += img[q] == 1;
-  int n0 = (int)N - n1;
+  for (int64_t q = 0; q < (int64_t)W * H; ++q) n1 += img[q] == 1;
+  int n0 = W * H - n1;
   if (n1 == 0 || n0 == 0) return -22;
   int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
   oracle_vectors(cx, cy, v);
@@ -561,7 +635,7 @@ int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned 
       sw[0] = a;
       sw[1] = b;
       if (descriptor == 0)
-        oracle_delta_swap(img, W, H, cx, cy, phase_mask, sw, 1, dl, nthreads);
+        delta_swap_impl(img, W, H, cx, cy, phase_mask, sw, 1, sample, dl, nthreads);
       else
         oracle_s2_delta_swap(img, W, H, cx, cy, phase_mask, sw, 1, dl, nthreads);
       int64_t S = 0;
@@ -594,11 +668,34 @@ int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned 
   return 0;
 }
 
+int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                           int descriptor,
+                           uint32_t *counts /* [nph][nv], must equal the descriptor of img */,
+                           const uint32_t *target /* [nph][nv] */, int64_t Nt, uint64_t seed,
+                           uint64_t step0, int nsteps, int K, const double *Ts /* [nsteps] */,
+                           int proposal, int32_t *pos1, int32_t *pos0 /* in/out */,
+                           double *e_io, oracle_step_result *res /* [nsteps] */, int nthreads) {
+  return anneal_core(img, W, H, cx, cy, phase_mask, descriptor, NULL, counts, target, Nt, seed,
+                     step0, nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+}
+
 int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
                       uint32_t *counts, const uint32_t *target, int64_t Nt, uint64_t seed,
                       uint64_t step0, int nsteps, int K, const double *Ts, int proposal,
                       int32_t *pos1, int32_t *pos0, double *e_io, oracle_step_result *res,
                       int nthreads) {
-  return oracle_anneal_run_desc(img, W, H, cx, cy, phase_mask, 0, counts, target, Nt, seed, step0,
-                                nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+  return anneal_core(img, W, H, cx, cy, phase_mask, 0, NULL, counts, target, Nt, seed, step0,
+                     nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+}
+
+/* The chain driven by the Monte-Carlo approximation: counts = oracle_lpf_sampled of img over the
+ * cell's position set `sample`, target = sampled counts of the original over Nt positions. */
+int oracle_anneal_run_sampled(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                              const uint8_t *sample, uint32_t *counts, const uint32_t *target,
+                              int64_t Nt, uint64_t seed, uint64_t step0, int nsteps, int K,
+                              const double *Ts, int proposal, int32_t *pos1, int32_t *pos0,
+                              double *e_io, oracle_step_result *res, int nthreads) {
+  if (!sample) return -22;
+  return anneal_core(img, W, H, cx, cy, phase_mask, 0, sample, counts, target, Nt, seed, step0,
+                     nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
 }

@@ -141,6 +141,15 @@ def square_particles(W: int, H: int, size: int, n: int, seed: int, tries: int = 
     return img
 
 
+def sample_positions(W: int, H: int, n: int, seed: int) -> np.ndarray:
+    """Monte-Carlo position set (Sec. 3): a uniformly random n-combination, without repetition,
+    of the W x H start pixels, as a uint8 mask (1 = sampled)."""
+    g = rng(seed)
+    flat = np.zeros(W * H, np.uint8)
+    flat[g.permutation(W * H)[:n]] = 1
+    return flat.reshape(H, W)
+
+
 def random_binary(W: int, H: int, p: float, seed: int) -> np.ndarray:
     return (rng(seed).random((H, W)) < p).astype(np.uint8)
 
