@@ -102,6 +102,16 @@ lpf_status lpf_full_enhanced(lpf_ctx ctx, const uint64_t *bits, int W, int H, in
                              unsigned phase_mask, int out_layout, uint32_t *counts,
                              void *stream);
 
+/* The Monte-Carlo approximation the paper compares with (Sec. 3, opening paragraph; Sec. 5
+ * reconstruction study): segments are compared with the image only at a chosen set X of start
+ * positions, counts[p][i] = #{x in X : every pixel of x + path(v_i) is in phase p} (divide by
+ * |X| for the approximated probability).  sample: packed mask of X (device, same layout as bits,
+ * bit set = start pixel in X; bits past W ignored), read only.  With every bit set this is
+ * lpf_full.  Other arguments and errors as lpf_full (LPF_E_INVAL also for sample == NULL). */
+lpf_status lpf_full_sampled(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                            unsigned phase_mask, int out_layout, const uint64_t *sample,
+                            uint32_t *counts, void *stream);
+
 /* Exact change of the lineal path function under pixel interchanges (Sec. 4 modification
  * operator: the values of pixels a and b are exchanged, which preserves the volume fractions).
  * swaps: int32[n][2] linear pixel indices y*W + x (device).  delta: int32[n][nph][|D_c|] (device,
@@ -216,6 +226,21 @@ lpf_status lpf_anneal_create_s2(lpf_ctx ctx, uint64_t *bits, int W, int H, int c
                                 unsigned phase_mask, uint32_t *counts, const uint32_t *target,
                                 int64_t Nt, uint64_t seed, uint64_t step0, const int32_t *pos,
                                 int n1, double *e, lpf_anneal *out, void *stream);
+
+/* An annealing chain driven by the Monte-Carlo approximation (the paper's reconstruction from
+ * the approximated function, Sec. 5): sample is the cell's position set X (device, packed like
+ * bits, read only, kept alive by the caller); counts receives lpf_full_sampled of the cell over X
+ * and target holds the original's sampled counts over its own Nt positions; the objective is
+ * eq. (LSE) with N = |X| (the approximated probabilities counts/|X| and target/Nt).  Every
+ * candidate's change is exact for the sampled counts.  Uses the records method (only it carries
+ * a position set): requires max(cx, cy) <= 126 and the records' memory; lpf_anneal_set_method
+ * refuses LPF_DELTA_RECOUNT.  Other arguments and calls as lpf_anneal_create.
+ * Errors: as lpf_anneal_create (LPF_E_INVAL also for a NULL or empty sample). */
+lpf_status lpf_anneal_create_sampled(lpf_ctx ctx, uint64_t *bits, int W, int H, int cx, int cy,
+                                     unsigned phase_mask, const uint64_t *sample,
+                                     uint32_t *counts, const uint32_t *target, int64_t Nt,
+                                     uint64_t seed, uint64_t step0, const int32_t *pos, int n1,
+                                     double *e, lpf_anneal *out, void *stream);
 
 /* One step: draw n_candidates interchanges (a phase-1 pixel with a phase-0 pixel; with
  * LPF_PROP_INTERFACIAL a draw where either pixel has no 4-neighbour of the other phase is void),

@@ -227,6 +227,13 @@ int oracle_lpf_sampled(const uint8_t *img, int W, int H, int cx, int cy, unsigne
   int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 2 * nv);
   oracle_vectors(cx, cy, v);
   int maxlen = (cx > cy ? cx : cy) + 1;
+  /* the position set as a list, row by row */
+  int64_t ns = 0;
+  for (int64_t q = 0; q < (int64_t)W * H; ++q) ns += sample[q] != 0;
+  int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (ns ? ns : 1));
+  ns = 0;
+  for (int64_t q = 0; q < (int64_t)W * H; ++q)
+    if (sample[q]) pos[ns++] = (int32_t)q;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -243,14 +250,13 @@ int oracle_lpf_sampled(const uint8_t *img, int W, int H, int cx, int cy, unsigne
       for (int ph = 0; ph < 2; ++ph) {
         if (!(phase_mask & (1u << ph))) continue;
         uint32_t count = 0;
-        for (int y = 0; y < H; ++y)
-          for (int x = 0; x < W; ++x) {
-            if (!sample[(size_t)y * W + x]) continue;
-            int k;
-            for (k = 0; k < np; ++k)
-              if (img[(size_t)wrap(y + py[k], H) * W + wrap(x + px[k], W)] != ph) break;
-            if (k == np) count += 1;
-          }
+        for (int64_t t = 0; t < ns; ++t) {
+          const int y = pos[t] / W, x = pos[t] % W;
+          int k;
+          for (k = 0; k < np; ++k)
+            if (img[(size_t)wrap(y + py[k], H) * W + wrap(x + px[k], W)] != ph) break;
+          if (k == np) count += 1;
+        }
         counts[(size_t)p * nv + i] = count;
         ++p;
       }
@@ -258,6 +264,7 @@ int oracle_lpf_sampled(const uint8_t *img, int W, int H, int cx, int cy, unsigne
     free(px);
     free(py);
   }
+  free(pos);
   free(v);
   return 0;
 }

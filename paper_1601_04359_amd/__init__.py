@@ -80,6 +80,18 @@ class Context:
         _abi.lpf_full_enhanced(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
         return out
 
+    def full_sampled(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                     sample: torch.Tensor, phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF,
+                     out=None, stream=None) -> torch.Tensor:
+        """Monte-Carlo approximation in counts: segments tested only at the start pixels set in
+        the packed mask `sample` (pack() of a uint8 mask)."""
+        if out is None:
+            out = torch.empty(counts_shape(cx, cy, phase_mask, layout), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_full_sampled(self.handle, bits, W, H, cx, cy, phase_mask, layout,
+                              sample.contiguous(), out, stream)
+        return out
+
     def s2(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
            phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF, out=None,
            stream=None) -> torch.Tensor:
@@ -153,15 +165,20 @@ class Anneal:
     bits (packed cell, updated in place), counts (int32 [nph][|D_c|]), e (float64 [1]) are
     allocated here and owned by this object; target (int32 [nph][|D_c|]) is the caller's.
     descriptor "lpf" (the lineal path function) or "s2" (two-point counts, lpf_anneal_create_s2;
-    target then holds Context.s2 counts of the original)."""
+    target then holds Context.s2 counts of the original).  sample: a packed position set of the
+    cell for the Monte-Carlo approximation (lpf_anneal_create_sampled; target then holds the
+    original's sampled counts and Nt its number of positions)."""
 
     def __init__(self, ctx: Context, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                  phase_mask: int, target: torch.Tensor, Nt: int, seed: int, step0: int = 0,
                  pos: torch.Tensor | None = None, n1: int = 0, stream=None,
-                 descriptor: str = "lpf"):
+                 descriptor: str = "lpf", sample: torch.Tensor | None = None):
         if descriptor not in ("lpf", "s2"):
             raise ValueError("descriptor is 'lpf' or 's2'")
+        if sample is not None and descriptor != "lpf":
+            raise ValueError("a position set applies to the lineal path function only")
         self.descriptor = descriptor
+        self.sample = None if sample is None else sample.contiguous()
         self.ctx, self.W, self.H, self.cx, self.cy, self.phase_mask = ctx, W, H, cx, cy, phase_mask
         dev = bits.device
         self.bits = bits.clone().contiguous()
@@ -169,9 +186,14 @@ class Anneal:
                                   device=dev)
         self.target = target.contiguous()
         self.e = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.handle = _abi.lpf_anneal_create(ctx.handle, self.bits, W, H, cx, cy, phase_mask,
-                                             self.counts, self.target, Nt, seed, step0, pos, n1,
-                                             self.e, stream, s2=descriptor == "s2")
+        if self.sample is not None:
+            self.handle = _abi.lpf_anneal_create_sampled(
+                ctx.handle, self.bits, W, H, cx, cy, phase_mask, self.sample, self.counts,
+                self.target, Nt, seed, step0, pos, n1, self.e, stream)
+        else:
+            self.handle = _abi.lpf_anneal_create(ctx.handle, self.bits, W, H, cx, cy, phase_mask,
+                                                 self.counts, self.target, Nt, seed, step0, pos,
+                                                 n1, self.e, stream, s2=descriptor == "s2")
 
     def step(self, n_candidates: int, T: float, out: torch.Tensor,
              proposal: int = LPF_PROP_UNIFORM, stream=None) -> None:

@@ -60,6 +60,9 @@ _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i
 _sig("lpf_anneal_create_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
      _P, _i32, _P, ctypes.POINTER(_P), _P)
 _sig("lpf_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_full_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P, _P)
+_sig("lpf_anneal_create_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _P, _i64,
+     _u64, _u64, _P, _i32, _P, ctypes.POINTER(_P), _P)
 _sig("lpf_s2_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
 _sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
@@ -210,6 +213,35 @@ def lpf_s2(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, phase
         raise ValueError(f"lpf_s2: counts must hold {shp} elements")
     _check(_lib.lpf_s2(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
                        out_layout, _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_full_sampled(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                     phase_mask: int, out_layout: int, sample: torch.Tensor, counts: torch.Tensor,
+                     stream=None) -> None:
+    if bits.numel() != ((W + 63) // 64) * H or sample.numel() != bits.numel():
+        raise ValueError("lpf_full_sampled: bits / sample sizes do not match W, H")
+    shp = counts_shape(cx, cy, phase_mask, out_layout) if 0 <= cx and 0 <= cy else None
+    if shp is not None and counts.numel() != int(torch.Size(shp).numel()):
+        raise ValueError(f"lpf_full_sampled: counts must hold {shp} elements")
+    _check(_lib.lpf_full_sampled(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+                                 out_layout, _dev(sample, torch.int64, "sample"),
+                                 _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_anneal_create_sampled(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                              phase_mask: int, sample: torch.Tensor, counts: torch.Tensor,
+                              target: torch.Tensor, Nt: int, seed: int, step0: int, pos, n1: int,
+                              e: torch.Tensor, stream=None) -> int:
+    if sample.numel() != bits.numel():
+        raise ValueError("lpf_anneal_create_sampled: sample must be packed like bits")
+    h = _P()
+    _check(_lib.lpf_anneal_create_sampled(
+        ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
+        _dev(sample, torch.int64, "sample"), _dev(counts, torch.int32, "counts"),
+        _dev(target, torch.int32, "target"), Nt, seed, step0,
+        _dev(pos, torch.int32, "pos") if pos is not None else None, n1,
+        _dev(e, torch.float64, "e"), ctypes.byref(h), _stream(stream)))
+    return h.value
 
 
 def lpf_s2_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,

@@ -242,6 +242,16 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
           const uint32_t mw = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
           mk[i] = row_ok ? mw : 0u;
         }
+        if (I.sample && row_ok) {
+          // Monte-Carlo approximation: only start pixels of the position set count.  Lane bit b
+          // of word w stands for the placement whose first pixel is 32w + b (+ |dx| for a
+          // mirrored vector), so the set's extended row is read at that shift.
+          const uint32_t *srow = I.sample + (size_t)(Y0 + row) * I.sample_stride + strip * R;
+          const int so = dx < 0 ? (adx >> 5) : 0, ssh = dx < 0 ? (adx & 31) : 0;
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            mk[i] &= __builtin_amdgcn_alignbit(srow[so + i + 1], srow[so + i], ssh);
+        }
         if (xm) {
           if (dx < 0) path_product<R, true, true, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
           else path_product<R, true, false, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);

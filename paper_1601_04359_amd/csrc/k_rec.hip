@@ -115,6 +115,7 @@ k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
     const int32_t p = g.pix[m.x + k];
     o += image_bit(bits, wpr, wrapi(px + pix_dx(p), g.W), wrapi(py + pix_dy(p), g.H));
   }
+  if (g.sample && !image_bit(g.sample, wpr, px, py)) o += 128;  // outside the position set
   g.ones[(size_t)v * N + x] = (uint8_t)o;
 }
 

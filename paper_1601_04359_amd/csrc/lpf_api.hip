@@ -155,7 +155,7 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
   std::map<std::string, struct BatchGraph *> batch_graphs;
-  DevBuf ext, ext3, s2ext, s2acc;
+  DevBuf ext, ext3, s2ext, s2acc, sext;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -165,6 +165,8 @@ struct lpf_ctx_s {
 struct lpf_anneal_s {
   lpf_ctx ctx = nullptr;
   bool s2 = false;  // descriptor: two-point probability, else lineal path
+  const uint64_t *sample = nullptr;  // Monte-Carlo position set of the cell (caller's), or none
+  int64_t Neff = 0;                  // N of the objective: W*H, or the number of sampled positions
   int W = 0, H = 0, cx = 0, cy = 0;
   unsigned mask = 0;
   uint64_t *bits = nullptr;
@@ -701,6 +703,10 @@ bool records_fit(lpf_anneal a, int64_t *bytes, std::string *why) {
 
 bool use_records(lpf_anneal a) {
   if (a->rec_choice >= 0) return a->rec_choice == 1;
+  if (a->sample) {  // only the records carry a position set (checked at creation)
+    a->rec_choice = 1;
+    return true;
+  }
   int64_t bytes = 0;
   bool rec;
   if (a->method == LPF_DELTA_RECOUNT || !records_fit(a, &bytes, nullptr)) {
@@ -754,6 +760,7 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     g.H = a->H;
     g.rstride = (int64_t)2 * g.nph * g.Rw;
     g.mask = a->mask;
+    g.sample = a->sample;
     const int64_t N = (int64_t)a->W * a->H;
     if ((e = a->rmeta.ensure(sizeof(int4) * meta.size())) != hipSuccess ||
         (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||
@@ -889,6 +896,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
     c->ext3.release();
     c->s2ext.release();
     c->s2acc.release();
+    c->sext.release();
   }
   delete c;
 }
@@ -906,7 +914,7 @@ lpf_status lpf_pack(lpf_ctx c, const uint8_t *img, int W, int H, uint64_t *bits,
 namespace {
 lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
                      unsigned phase_mask, int out_layout, uint32_t *counts, void *stream,
-                     bool skip) {
+                     bool skip, const uint64_t *sample = nullptr) {
   if (!c) return fail(LPF_E_INVAL, "lpf_full: ctx is NULL");
   if (!bits || !counts) return fail(LPF_E_INVAL, "lpf_full: NULL buffer");
   if (W < 1 || H < 1 || W > 65535 || H > 65535) return fail(LPF_E_INVAL, "lpf_full: W/H out of range");
@@ -928,7 +936,15 @@ lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int 
     return hip_fail(e, "lpf_full: scratch");
   uint32_t *ext = (uint32_t *)c->ext.p;
   if ((e = launch_ext(bits, W, H, sh.we, ext, s)) != hipSuccess) return hip_fail(e, "lpf_full: ext");
-  const FullImg I = make_img(*plan, ext, counts, W, H, cx, cy, out_layout);
+  FullImg I = make_img(*plan, ext, counts, W, H, cx, cy, out_layout);
+  if (sample) {
+    if ((e = c->sext.ensure((size_t)H * sh.we * sizeof(uint32_t))) != hipSuccess)
+      return hip_fail(e, "lpf_full_sampled: scratch");
+    if ((e = launch_ext(sample, W, H, sh.we, (uint32_t *)c->sext.p, s)) != hipSuccess)
+      return hip_fail(e, "lpf_full_sampled: ext");
+    I.sample = (const uint32_t *)c->sext.p;
+    I.sample_stride = sh.we;
+  }
   if ((e = launch_full(I, sh, phase_mask, skip, s)) != hipSuccess) return hip_fail(e, "lpf_full: kernel");
   return LPF_OK;
 }
@@ -943,6 +959,13 @@ lpf_status lpf_full_enhanced(lpf_ctx c, const uint64_t *bits, int W, int H, int 
                              unsigned phase_mask, int out_layout, uint32_t *counts,
                              void *stream) {
   return full_impl(c, bits, W, H, cx, cy, phase_mask, out_layout, counts, stream, true);
+}
+
+lpf_status lpf_full_sampled(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                            unsigned phase_mask, int out_layout, const uint64_t *sample,
+                            uint32_t *counts, void *stream) {
+  if (!sample) return fail(LPF_E_INVAL, "lpf_full_sampled: sample is NULL");
+  return full_impl(c, bits, W, H, cx, cy, phase_mask, out_layout, counts, stream, false, sample);
 }
 
 // Tile-shape override used by the autotuner and by tests (0 = automatic choice).
@@ -1071,7 +1094,8 @@ namespace {
 lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
                          unsigned phase_mask, uint32_t *counts, const uint32_t *target, int64_t Nt,
                          uint64_t seed, uint64_t step0, const int32_t *pos, int n1, double *e_dev,
-                         lpf_anneal *out, void *stream, bool s2) {
+                         lpf_anneal *out, void *stream, bool s2,
+                         const uint64_t *sample = nullptr) {
   if (!out) return fail(LPF_E_INVAL, "lpf_anneal_create: out is NULL");
   *out = nullptr;
   if (!c) return fail(LPF_E_INVAL, "lpf_anneal_create: ctx is NULL");
@@ -1093,17 +1117,50 @@ lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy
     if (bound > (__int128)INT64_MAX)
       return fail(LPF_E_UNSUPPORTED, "lpf_anneal_create: cell, cutoff and Nt too large for exact int64 energy sums");
   }
+  int64_t Neff = N;
+  if (sample) {
+    if (std::max(cx, cy) > 126)
+      return fail(LPF_E_UNSUPPORTED, "lpf_anneal_create_sampled: cutoff above 126 (the position set rides on the placement counts)");
+    // the number of sampled positions (bits past W ignored)
+    const int wpr = (W + 63) / 64;
+    std::vector<uint64_t> hm((size_t)wpr * H);
+    DeviceGuard g0(c->dev);
+    hipError_t e0 = hipMemcpyAsync(hm.data(), sample, hm.size() * 8, hipMemcpyDeviceToHost,
+                                   (hipStream_t)stream);
+    if (e0 == hipSuccess) e0 = hipStreamSynchronize((hipStream_t)stream);
+    if (e0 != hipSuccess) return hip_fail(e0, "lpf_anneal_create_sampled: position set");
+    Neff = 0;
+    for (int y = 0; y < H; ++y)
+      for (int w = 0; w < wpr; ++w) {
+        uint64_t v = hm[(size_t)y * wpr + w];
+        const int valid = std::min(64, W - 64 * w);
+        if (valid < 64) v &= (1ull << valid) - 1ull;
+        Neff += __builtin_popcountll(v);
+      }
+    if (Neff < 1) return fail(LPF_E_INVAL, "lpf_anneal_create_sampled: empty position set");
+  }
   // full evaluation for the initial counts (also validates the tile shape)
-  st = s2 ? lpf_s2(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream)
-          : lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
+  st = s2       ? lpf_s2(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream)
+       : sample ? lpf_full_sampled(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, sample,
+                                   counts, stream)
+                : lpf_full(c, bits, W, H, cx, cy, phase_mask, LPF_OUT_HALF, counts, stream);
   if (st != LPF_OK) return st;
   lpf_anneal a = new (std::nothrow) lpf_anneal_s();
   if (!a) return fail(LPF_E_NOMEM, "lpf_anneal_create: host memory");
   a->ctx = c;
   a->s2 = s2;
+  a->sample = sample;
+  a->Neff = Neff;
   a->W = W; a->H = H; a->cx = cx; a->cy = cy; a->mask = phase_mask;
   a->bits = bits; a->counts = counts; a->target = target; a->e = e_dev;
   a->Nt = Nt; a->seed = seed;
+  if (sample) {
+    std::string why;
+    if (!records_fit(a, nullptr, &why)) {
+      delete a;
+      return fail(LPF_E_UNSUPPORTED, "lpf_anneal_create_sampled: " + why);
+    }
+  }
   DeviceGuard g(c->dev);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
@@ -1164,7 +1221,7 @@ lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy
   }
   const int nph = nph_of(phase_mask);
   const int64_t nv = lpf_num_vectors(cx, cy);
-  if ((e = launch_lse(counts, target, nph * nv, N, Nt, e_dev, s)) != hipSuccess) {
+  if ((e = launch_lse(counts, target, nph * nv, Neff, Nt, e_dev, s)) != hipSuccess) {
     lpf_anneal_destroy(a);
     return hip_fail(e, "lpf_anneal_create: energy");
   }
@@ -1187,6 +1244,19 @@ lpf_status lpf_anneal_create_s2(lpf_ctx c, uint64_t *bits, int W, int H, int cx,
                                 int n1, double *e_dev, lpf_anneal *out, void *stream) {
   return anneal_create(c, bits, W, H, cx, cy, phase_mask, counts, target, Nt, seed, step0, pos,
                        n1, e_dev, out, stream, true);
+}
+
+lpf_status lpf_anneal_create_sampled(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy,
+                                     unsigned phase_mask, const uint64_t *sample,
+                                     uint32_t *counts, const uint32_t *target, int64_t Nt,
+                                     uint64_t seed, uint64_t step0, const int32_t *pos, int n1,
+                                     double *e_dev, lpf_anneal *out, void *stream) {
+  if (!sample) {
+    if (out) *out = nullptr;
+    return fail(LPF_E_INVAL, "lpf_anneal_create_sampled: sample is NULL");
+  }
+  return anneal_create(c, bits, W, H, cx, cy, phase_mask, counts, target, Nt, seed, step0, pos,
+                       n1, e_dev, out, stream, false, sample);
 }
 
 lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
@@ -1273,7 +1343,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   L.counts = a->counts;
   L.counts_rw = a->counts;
   L.target = a->target;
-  L.N = (int64_t)a->W * a->H;
+  L.N = a->Neff;
   L.Nt = a->Nt;
   L.T = T;
   L.S_acc = (int64_t *)a->S_acc.p;
@@ -1782,7 +1852,7 @@ lpf_status lpf_anneal_delta_energy(lpf_anneal a, const int32_t *swaps, int n, do
   L.nv = (int)lpf_num_vectors(a->cx, a->cy);
   L.counts = a->counts;
   L.target = a->target;
-  L.N = (int64_t)a->W * a->H;
+  L.N = a->Neff;
   L.Nt = a->Nt;
   L.S_acc = (int64_t *)a->eS.p;
   L.ctl = (StepCtl *)a->eCtl.p;
@@ -1796,12 +1866,14 @@ lpf_status lpf_anneal_set_method(lpf_anneal a, int method) {
     return fail(LPF_E_INVAL, "lpf_anneal_set_method: method");
   if (a->s2 && method != LPF_DELTA_AUTO)
     return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: an S2 chain has a single method");
+  if (a->sample && method == LPF_DELTA_RECOUNT)
+    return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: a sampled chain uses the records");
   std::string why;
   if (method == LPF_DELTA_RECORDS && !records_fit(a, nullptr, &why))
     return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: records: " + why);
   std::lock_guard<std::mutex> lk(a->ctx->mu);
   a->method = method;
-  a->rec_choice = -1;
+  a->rec_choice = a->sample ? 1 : -1;
   return LPF_OK;
 }
 

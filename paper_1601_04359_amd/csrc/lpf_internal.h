@@ -40,6 +40,10 @@ struct FullImg {
   const VecDesc *vecs;      // vectors in bin order
   const int32_t *bin_off;   // nbins + 1
   int W, H, cx, cy, R, S, we, rst, tile, ntiles, lds_rows, nv, layout, nbins;
+  // Monte-Carlo position set: extended rows of its mask like E (bit j of row y = position
+  // (j mod W, y) is counted), sample_stride = we dwords per row; nullptr = every pixel
+  const uint32_t *sample;
+  int sample_stride;
 };
 
 // Geometry of one extended image used by the delta kernel (see k_delta.hip): width, height,
@@ -107,6 +111,10 @@ struct RecGeo {
   uint8_t *ones;        // [nv][W*H]
   const int32_t *vbit;  // [Mc] (v << 8) | n of the vector of each record bit
   unsigned mask;        // phases kept (LPF_PHASE0 | LPF_PHASE1 bits)
+  // Monte-Carlo position set (packed like the image), nullptr = every placement.  A placement
+  // outside it keeps ones + 128 (n <= 126), which meets no plane condition before or after any
+  // interchange, so it never counts.
+  const uint64_t *sample;
 };
 
 struct StepLaunch {

@@ -98,6 +98,18 @@ def test_s2_entry_points_reject_bad_arguments_before_any_device_call():
     assert b"out" in lib.lpf_last_error()
 
 
+def test_sampled_entry_points_reject_bad_arguments_before_any_device_call():
+    import ctypes
+    from paper_1601_04359_amd import _abi
+    lib = _abi.lib()
+    assert lib.lpf_full_sampled(None, None, 8, 8, 1, 1, 3, 0, None, None, None) == _abi.LPF_E_INVAL
+    assert b"sample" in lib.lpf_last_error()
+    h = ctypes.c_void_p(1)
+    assert lib.lpf_anneal_create_sampled(None, None, 8, 8, 1, 1, 3, None, None, None, 1, 0, 0,
+                                         None, 0, None, ctypes.byref(h), None) == _abi.LPF_E_INVAL
+    assert h.value is None
+
+
 def test_bench_counts_match_oracle_paths():
     # the benchmark's algorithmic work: M_c from the oracle's digitisation, ops = N/32 (3 M_c +
     # 2 |D_c|) for both phases (7.088e10 at 512^2, cutoff 128)
