@@ -28,7 +28,7 @@ P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 # HBM bytes per k_lpf_full launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by the
 # same counters on a 256 MiB copy), profiles/k_lpf_full_512_c128.md.  Valid only for the kernel
 # source and tile-shape choice the counters were taken on; reported as null once either changes.
-MEASURED_TRAFFIC = {"src_sha256_16": "b077168973c06c2a", "bytes": int(2053.78 * 1024)}
+MEASURED_TRAFFIC = {"src_sha256_16": "7431cbc5c17c54d1", "bytes": int(2057.78125 * 1024)}
 
 
 def source_hash() -> str:
@@ -440,6 +440,106 @@ def mutual_bench(args) -> dict:
             "rows": rows}
 
 
+def mc_bench(args) -> dict:
+    """Monte-Carlo approximation study (Sec. 3 opening, Fig. MC_LP; Sec. 5, Fig. ComMicRec) on
+    synthetic media: (1) error of the approximated function against the entire one,
+    e = sum over D and phase of (L/N - L~/n)^2, for n random start positions (5 position sets
+    each), chess (10-px squares) and particulate (4 x 4 squares, phi 0.16) images of 100 x 100,
+    full domain; (2) reconstruction of the 50 x 50 versions from the approximation with
+    n = 10, 100, 1000 and from the entire function (n = 2500): the final cell's entire-function
+    error relative to that of the random start."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import Anneal, Context
+
+    dev = torch.device("cuda:0")
+    ctx = Context(0)
+    pk = lambda a: ctx.pack(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    media = {"chess": lambda s: wl.checkerboard(s, s, s // 10),
+             "particulate": lambda s: wl.square_particles(s, s, 4, int(0.16 * s * s) // 16, 1606)}
+    ns = [10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000]
+    curves, t_eval, n_eval = {}, 0.0, 0
+    for name, make in media.items():
+        img = make(100)
+        b = pk(img)
+        c = 99
+        full = ctx.full(b, 100, 100, c, c, 3).double().cpu().numpy() / 1e4
+        rows = []
+        for n in ns:
+            errs = []
+            for seed in range(5):
+                X = pk(wl.sample_positions(100, 100, n, 100 * n + seed))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                approx = ctx.full_sampled(b, 100, 100, c, c, X, 3)
+                torch.cuda.synchronize()
+                t_eval += time.perf_counter() - t0
+                n_eval += 1
+                a = approx.double().cpu().numpy() / n
+                errs.append([float(((full[p] - a[p]) ** 2).sum()) for p in range(2)])
+            e = np.mean(errs, axis=0)
+            rows.append({"n": n, "e_phase0": float(e[0]), "e_phase1": float(e[1])})
+        curves[name] = rows
+        print(f"  {name}: e(n=10) {rows[0]['e_phase1']:.4g} .. e(n=10000) "
+              f"{rows[-1]['e_phase1']:.4g}", file=sys.stderr, flush=True)
+    # reconstruction from the approximation
+    side, c, steps, K = 50, 24, args.steps, 256
+    recon = {}
+    wall = 0.0
+    for name, make in media.items():
+        orig = make(side)
+        ob = pk(orig)
+        Lfull = ctx.full(ob, side, side, c, c, 3)
+        Lf = Lfull.double().cpu().numpy() / (side * side)
+        cell = wl.random_cell(side, side, int(orig.sum()), 1607)
+        cb = pk(cell)
+
+        def err(bits):
+            L = ctx.full(bits, side, side, c, c, 3).double().cpu().numpy() / (side * side)
+            return float(((L - Lf) ** 2).sum())
+        e_rand = err(cb)
+        out = {}
+        for n in (10, 100, 1000, side * side):
+            if n == side * side:
+                ch = Anneal(ctx, cb, side, side, c, c, 3, Lfull, side * side, seed=3)
+            else:
+                Xt = pk(wl.sample_positions(side, side, n, 7 + n))
+                tgt = ctx.full_sampled(ob, side, side, c, c, Xt, 3)
+                Xc = pk(wl.sample_positions(side, side, n, 11 + n))
+                ch = Anneal(ctx, cb, side, side, c, c, 3, tgt, n, seed=3, sample=Xc)
+            e0 = float(ch.e.cpu()[0])
+            Ts = max(e0, 1e-12) * 1e-3 * (1e-4 ** (1.0 / steps)) ** np.arange(steps)
+            recs = torch.empty((steps, 5), dtype=torch.int64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                ch.step(K, float(Ts[i]), recs[i])
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            e_fin = err(ch.bits)
+            out[str(n)] = {"e_entire": e_fin, "relative_to_random": e_fin / e_rand}
+            ch.close()
+        recon[name] = {"e_random_start": e_rand, "by_n": out}
+        print(f"  reconstruction {name}: " + ", ".join(
+            f"n={k}: {v['relative_to_random']:.3g}" for k, v in out.items()), file=sys.stderr,
+            flush=True)
+    ctx.close()
+    total = 8 * steps
+    return {"metric": "annealing steps/s", "value": round(total / wall, 1), "unit": "steps/s",
+            "n_gpus": 1, "steps": steps, "warmup": 0,
+            "ms_per_step": round(wall * 1e3 / total, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+            "config": {"workload": "Monte-Carlo approximation: error vs n on 100x100 chess "
+                                   "(10-px squares) and particulate (4x4 squares, phi 0.16) "
+                                   "images, full domain, both phases, 5 position sets per n; "
+                                   "reconstruction of the 50x50 versions from n = 10, 100, 1000 "
+                                   "positions and from the entire function, cutoff 24, 256 "
+                                   "swaps per step",
+                       "sampled_eval_ms_mean_100x100_full_domain": round(t_eval * 1e3 / n_eval, 4)},
+            "error_vs_n": curves, "reconstruction": recon}
+
+
 def batch_bench(args) -> dict:
     """Uneven batch: 256 Boolean disk images, side ~ U{64,128,256,512,1024}, phi ~ U[0.2,0.6],
     r ~ U[3,15], cutoff side/2, both phases; one step = one lpf_batch call (persistent launch,
@@ -528,7 +628,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper",
-                                           "mutual"],
+                                           "mutual", "mc"],
                     default="full")
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
@@ -545,7 +645,8 @@ def main() -> int:
                          "as the reference kernel for HBM byte counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"anneal": 20000, "learned": 20000, "mutual": 20000}.get(args.workload, 20)
+        args.steps = {"anneal": 20000, "learned": 20000, "mutual": 20000,
+                      "mc": 10000}.get(args.workload, 20)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is a design note, not an implemented path)", file=sys.stderr)
@@ -565,6 +666,9 @@ def main() -> int:
         return 0
     if args.workload == "mutual":
         print(json.dumps(mutual_bench(args)), flush=True)
+        return 0
+    if args.workload == "mc":
+        print(json.dumps(mc_bench(args)), flush=True)
         return 0
 
     import numpy as np
