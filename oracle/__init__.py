@@ -69,6 +69,14 @@ def _load():
     lib.oracle_anneal_run_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, P, i64, u64, u64,
                                               i32, i32, P, i32, P, P, P, P, i32]
     lib.oracle_anneal_run_sampled.restype = i32
+    lib.oracle_bresenham3.argtypes = [i32, i32, i32, P, P, P]
+    lib.oracle_bresenham3.restype = i32
+    lib.oracle_num_vectors3.argtypes = [i32, i32, i32]
+    lib.oracle_num_vectors3.restype = i64
+    lib.oracle_vectors3.argtypes = [i32, i32, i32, P]
+    lib.oracle_vectors3.restype = i32
+    lib.oracle_lpf3.argtypes = [P, i32, i32, i32, i32, i32, i32, u32, P, i32]
+    lib.oracle_lpf3.restype = i32
     lib.oracle_s2_vectors.argtypes = [P, i32, i32, P, i64, u32, P, i32]
     lib.oracle_s2_vectors.restype = i32
     lib.oracle_s2.argtypes = [P, i32, i32, i32, i32, u32, i32, P, i32]
@@ -234,6 +242,40 @@ def s2_delta_swap(img, cx: int, cy: int, swaps, phase_mask: int = 3,
 
 
 DESC_LPF, DESC_S2 = 0, 1
+
+
+def bresenham3(dx: int, dy: int, dz: int) -> np.ndarray:
+    """Voxels (px, py, pz) of the digitised 3-D segment: shape (n+1, 3)."""
+    n = max(abs(dx), abs(dy), abs(dz))
+    p = [np.zeros(n + 1, np.int32) for _ in range(3)]
+    m = _load().oracle_bresenham3(int(dx), int(dy), int(dz), *(_ptr(a) for a in p))
+    assert m == n + 1
+    return np.stack(p, axis=1)
+
+
+def num_vectors3(cx: int, cy: int, cz: int) -> int:
+    return int(_load().oracle_num_vectors3(cx, cy, cz))
+
+
+def vectors3(cx: int, cy: int, cz: int) -> np.ndarray:
+    """Canonical 3-D half domain, int16 (n, 3) of (dx, dy, dz)."""
+    out = np.zeros((num_vectors3(cx, cy, cz), 3), np.int16)
+    if _load().oracle_vectors3(cx, cy, cz, _ptr(out)):
+        raise ValueError("bad cutoff")
+    return out
+
+
+def lpf3(vol, cx: int, cy: int, cz: int, phase_mask: int = 3, nthreads: int = 0) -> np.ndarray:
+    """Counts uint32 [nph][|D_c|] of a periodic volume vol[z][y][x] (uint8)."""
+    a = np.ascontiguousarray(vol, dtype=np.uint8)
+    if a.ndim != 3:
+        raise ValueError("volume must be 3-D (D, H, W)")
+    D, H, W = a.shape
+    out = np.zeros((nphases(phase_mask), num_vectors3(cx, cy, cz)), np.uint32)
+    rc = _load().oracle_lpf3(_ptr(a), W, H, D, cx, cy, cz, phase_mask, _ptr(out), nthreads)
+    if rc:
+        raise ValueError(f"oracle_lpf3 failed ({rc})")
+    return out
 
 
 def philox4x64(counter, key) -> np.ndarray:

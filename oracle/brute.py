@@ -73,3 +73,44 @@ def s2_fft(img: np.ndarray, phase: int) -> np.ndarray:
     F = np.fft.fft2(chi)
     corr = np.fft.ifft2(np.conj(F) * F).real
     return np.rint(corr).astype(np.int64)
+
+
+def _round_r1(num: int, n: int, tie_rule: str) -> int:
+    exact = Fraction(num, n)
+    return floor(exact + Fraction(1, 2)) if tie_rule == "up" else ceil(exact - Fraction(1, 2))
+
+
+def path3(dx: int, dy: int, dz: int, tie_rule: str = "up") -> list[tuple[int, int, int]]:
+    """3-D digitised segment by exact rational rounding of every minor coordinate; the major
+    axis is the first of x, y, z with the largest extent."""
+    d = (dx, dy, dz)
+    a = [abs(t) for t in d]
+    n = max(a)
+    if n == 0:
+        return [(0, 0, 0)]
+    major = a.index(n)
+    out = []
+    for k in range(n + 1):
+        c = [k if ax == major else _round_r1(a[ax] * k, n, tie_rule) for ax in range(3)]
+        out.append(tuple(-c[ax] if d[ax] < 0 else c[ax] for ax in range(3)))
+    return out
+
+
+def half_domain3(cx: int, cy: int, cz: int) -> set[tuple[int, int, int]]:
+    """The set of canonical vectors: of each pair {v, -v} of the cutoff box, the one whose last
+    nonzero coordinate among (dz, dy) is positive, or (dx >= 0, 0, 0)."""
+    out = set()
+    for dz in range(-cz, cz + 1):
+        for dy in range(-cy, cy + 1):
+            for dx in range(-cx, cx + 1):
+                if dz > 0 or (dz == 0 and dy > 0) or (dz == 0 and dy == 0 and dx >= 0):
+                    out.add((dx, dy, dz))
+    return out
+
+
+def lpf3_vector(vol: np.ndarray, dx: int, dy: int, dz: int, phase: int) -> int:
+    ind = (np.asarray(vol) == phase)
+    acc = np.ones_like(ind, dtype=bool)
+    for (px, py, pz) in set(path3(dx, dy, dz)):
+        acc &= np.roll(ind, shift=(-pz, -py, -px), axis=(0, 1, 2))
+    return int(acc.sum())

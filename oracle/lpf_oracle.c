@@ -19,6 +19,8 @@
  *   - oracle_lpf_sampled    Sec. 3 opening: the Monte-Carlo approximation, segments compared at a
  *                           given set of start positions only (and its interchange update and
  *                           chain: oracle_delta_swap_sampled, oracle_anneal_run_sampled).
+ *   - oracle_*3             the 3-D extension (Sec. 2): segments, half domain and counts on a
+ *                           periodic volume.
  *   - oracle_s2*            Sec. 2.1, eq. (S2dis): two-point probability counts (definition sum).
  *   - oracle_s2_delta_swap  Sec. 4 interchange applied to eq. (S2dis), recounting the pairs that
  *                           contain a swapped pixel.
@@ -332,6 +334,129 @@ int oracle_s2(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_m
   int rc = oracle_s2_vectors(img, W, H, v, nv, phase_mask, counts, nthreads);
   free(v);
   return rc;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Three-dimensional extension (Sec. 2 calls it straightforward; Sec. 5 uses a 3-D specimen).
+ * Voxel (x, y, z) of a W x H x D periodic volume is vol[(z*H + y)*W + x].
+ *
+ * Digitised segment from (0,0,0) to (dx,dy,dz): n = max(|dx|,|dy|,|dz|); the major axis is x
+ * when |dx| = n, else y when |dy| = n, else z; k = 0..n along it, and every minor coordinate m
+ * follows reading R1 on its own: sgn(m) floor((2k|m| + n) / (2n)), kept as an error term that
+ * starts at n, grows by 2|m| per major step and steps when it reaches 2n.  With dz = 0 this is
+ * oracle_bresenham.  Returns n + 1.
+ * ------------------------------------------------------------------------------------------ */
+int oracle_bresenham3(int dx, int dy, int dz, int *px, int *py, int *pz) {
+  int a[3] = {dx < 0 ? -dx : dx, dy < 0 ? -dy : dy, dz < 0 ? -dz : dz};
+  int sg[3] = {dx < 0 ? -1 : 1, dy < 0 ? -1 : 1, dz < 0 ? -1 : 1};
+  int n = a[0];
+  if (a[1] > n) n = a[1];
+  if (a[2] > n) n = a[2];
+  int major = a[0] == n ? 0 : (a[1] == n ? 1 : 2);
+  long err[3] = {n, n, n};
+  int c[3] = {0, 0, 0};
+  for (int k = 0; k <= n; ++k) {
+    if (k > 0) {
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax == major) {
+          c[ax] = k;
+          continue;
+        }
+        err[ax] += 2L * a[ax];
+        if (err[ax] >= 2L * n) {
+          err[ax] -= 2L * n;
+          c[ax] += 1;
+        }
+      }
+    }
+    px[k] = sg[0] * c[0];
+    py[k] = sg[1] * c[1];
+    pz[k] = sg[2] * c[2];
+  }
+  return n + 1;
+}
+
+/* Canonical half of the 3-D cutoff box (one of each {v, -v}): the 2-D half domain at dz = 0 in
+ * its own order, then for dz = 1..cz the rectangle [-cx,cx] x [-cy,cy] row by row (dy outer). */
+int64_t oracle_num_vectors3(int cx, int cy, int cz) {
+  return oracle_num_vectors(cx, cy) + (int64_t)cz * (2 * cx + 1) * (2 * cy + 1);
+}
+
+int oracle_vectors3(int cx, int cy, int cz, int16_t *v) {
+  if (cx < 0 || cy < 0 || cz < 0) return -22;
+  int64_t n2 = oracle_num_vectors(cx, cy);
+  int16_t *t = (int16_t *)malloc(sizeof(int16_t) * 2 * n2);
+  oracle_vectors(cx, cy, t);
+  int64_t i = 0;
+  for (int64_t j = 0; j < n2; ++j, ++i) {
+    v[3 * i] = t[2 * j];
+    v[3 * i + 1] = t[2 * j + 1];
+    v[3 * i + 2] = 0;
+  }
+  free(t);
+  for (int dz = 1; dz <= cz; ++dz)
+    for (int dy = -cy; dy <= cy; ++dy)
+      for (int dx = -cx; dx <= cx; ++dx, ++i) {
+        v[3 * i] = (int16_t)dx;
+        v[3 * i + 1] = (int16_t)dy;
+        v[3 * i + 2] = (int16_t)dz;
+      }
+  return 0;
+}
+
+/* L_p(v) of a periodic volume over the canonical 3-D half domain: counts[p][i], phase 0 first;
+ * the loops of Alg. "L2_eval" with one more coordinate. */
+int oracle_lpf3(const uint8_t *vol, int W, int H, int D, int cx, int cy, int cz,
+                unsigned phase_mask, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || D < 1 || cx < 0 || cy < 0 || cz < 0 || cx > W - 1 || cy > H - 1 ||
+      cz > D - 1)
+    return -22;
+  if (!phase_mask || (phase_mask & ~3u)) return -22;
+  int64_t nv = oracle_num_vectors3(cx, cy, cz);
+  int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 3 * nv);
+  oracle_vectors3(cx, cy, cz, v);
+  int maxlen = cx;
+  if (cy > maxlen) maxlen = cy;
+  if (cz > maxlen) maxlen = cz;
+  maxlen += 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel
+  {
+    int *px = (int *)malloc(sizeof(int) * maxlen);
+    int *py = (int *)malloc(sizeof(int) * maxlen);
+    int *pz = (int *)malloc(sizeof(int) * maxlen);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nv; ++i) {
+      int np = oracle_bresenham3(v[3 * i], v[3 * i + 1], v[3 * i + 2], px, py, pz);
+      int p = 0;
+      for (int ph = 0; ph < 2; ++ph) {
+        if (!(phase_mask & (1u << ph))) continue;
+        uint32_t count = 0;
+        for (int z = 0; z < D; ++z)
+          for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+              int k;
+              for (k = 0; k < np; ++k) {
+                size_t q = ((size_t)wrap(z + pz[k], D) * H + wrap(y + py[k], H)) * W +
+                           wrap(x + px[k], W);
+                if (vol[q] != ph) break;
+              }
+              if (k == np) count += 1;
+            }
+        counts[(size_t)p * nv + i] = count;
+        ++p;
+      }
+    }
+    free(px);
+    free(py);
+    free(pz);
+  }
+  free(v);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------------------------
