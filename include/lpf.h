@@ -124,6 +124,29 @@ lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int c
                           unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
                           void *stream);
 
+/* ---- 3-D volumes (the extension of Sec. 2; the ensemble of cuts of Sec. 5) ---------------- */
+
+/* Canonical half of the 3-D cutoff box: the 2-D half domain (lpf_vectors order) at dz = 0, then
+ * for dz = 1..cz the rectangle [-cx,cx] x [-cy,cy] row by row (dy outer).  Count
+ * |D_c|(cx, cy) + cz (2cx+1)(2cy+1), or -1 for a negative cutoff. */
+int64_t lpf_num_vectors3(int cx, int cy, int cz);
+/* dxdydz: int16[n][3] (host).  Errors: LPF_E_INVAL (cutoff outside [0, 32767], NULL). */
+lpf_status lpf_vectors3(int cx, int cy, int cz, int16_t *dxdydz);
+
+/* Entire lineal path function of a periodic W x H x D two-phase volume: counts[p][i] (uint32,
+ * device, written in full) = number of voxels x with every voxel of x + path(v_i) in phase p,
+ * for the canonical 3-D vectors and the phases of phase_mask.  The digitised 3-D segment: n =
+ * max(|dx|,|dy|,|dz|), major axis the first of x, y, z with extent n, every minor coordinate
+ * sgn(m) floor((2k|m| + n)/(2n)) (the 2-D rule per axis).  bits: the volume as D*H packed rows
+ * (row z*H + y, lpf_pack of the (D*H) x W byte array), read only.  With cz = 0 the counts are the
+ * sums over the D xy-cuts of their 2-D functions (lpf_full), the ensemble average of Sec. 5 times
+ * D*W*H.  Requires 1 <= W, H, D <= 65535, W*H*D < 2^32, 0 <= cx <= W-1, 0 <= cy <= H-1,
+ * 0 <= cz <= D-1, cutoffs <= 32767, phase_mask in {1,2,3}.
+ * Errors: LPF_E_INVAL, LPF_E_UNSUPPORTED (W > 32768, too many vectors), LPF_E_NOMEM,
+ * LPF_E_DEVICE. */
+lpf_status lpf_full3d(lpf_ctx ctx, const uint64_t *bits, int W, int H, int D, int cx, int cy,
+                      int cz, unsigned phase_mask, uint32_t *counts, void *stream);
+
 /* ---- two-point probability (Sec. 2.1, eq. (S2dis)), the descriptor compared with in Sec. 5 --- */
 
 /* Two-point counts C_p(v) = W H S2^p(v): the number of pixels x of the periodic image with x and

@@ -75,6 +75,8 @@ def _load():
     lib.oracle_num_vectors3.restype = i64
     lib.oracle_vectors3.argtypes = [i32, i32, i32, P]
     lib.oracle_vectors3.restype = i32
+    lib.oracle_lpf3_vectors.argtypes = [P, i32, i32, i32, P, i64, u32, P, i32]
+    lib.oracle_lpf3_vectors.restype = i32
     lib.oracle_lpf3.argtypes = [P, i32, i32, i32, i32, i32, i32, u32, P, i32]
     lib.oracle_lpf3.restype = i32
     lib.oracle_s2_vectors.argtypes = [P, i32, i32, P, i64, u32, P, i32]
@@ -349,3 +351,16 @@ class AnnealState:
         self.e = float(e[0])
         self.step += nsteps
         return res
+
+
+def lpf3_vectors(vol, v3, phase_mask: int = 3, nthreads: int = 0) -> np.ndarray:
+    """Counts uint32 [nph][n] of a periodic volume for the vectors v3 (n, 3) of (dx, dy, dz)."""
+    a = np.ascontiguousarray(vol, dtype=np.uint8)
+    D, H, W = a.shape
+    v = np.ascontiguousarray(v3, dtype=np.int16).reshape(-1, 3)
+    out = np.zeros((nphases(phase_mask), len(v)), np.uint32)
+    rc = _load().oracle_lpf3_vectors(_ptr(a), W, H, D, _ptr(v), len(v), phase_mask, _ptr(out),
+                                     nthreads)
+    if rc:
+        raise ValueError(f"oracle_lpf3_vectors failed ({rc})")
+    return out

@@ -404,21 +404,21 @@ int oracle_vectors3(int cx, int cy, int cz, int16_t *v) {
   return 0;
 }
 
-/* L_p(v) of a periodic volume over the canonical 3-D half domain: counts[p][i], phase 0 first;
- * the loops of Alg. "L2_eval" with one more coordinate. */
-int oracle_lpf3(const uint8_t *vol, int W, int H, int D, int cx, int cy, int cz,
-                unsigned phase_mask, uint32_t *counts, int nthreads) {
-  if (W < 1 || H < 1 || D < 1 || cx < 0 || cy < 0 || cz < 0 || cx > W - 1 || cy > H - 1 ||
-      cz > D - 1)
-    return -22;
+/* L_p(v) of a periodic volume for an explicit list of 3-D vectors (|dx| <= W-1, |dy| <= H-1,
+ * |dz| <= D-1): counts[p][i], phase 0 first; the loops of Alg. "L2_eval" with one more
+ * coordinate. */
+int oracle_lpf3_vectors(const uint8_t *vol, int W, int H, int D, const int16_t *v, int64_t nv,
+                        unsigned phase_mask, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || D < 1 || nv < 0) return -22;
   if (!phase_mask || (phase_mask & ~3u)) return -22;
-  int64_t nv = oracle_num_vectors3(cx, cy, cz);
-  int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 3 * nv);
-  oracle_vectors3(cx, cy, cz, v);
-  int maxlen = cx;
-  if (cy > maxlen) maxlen = cy;
-  if (cz > maxlen) maxlen = cz;
-  maxlen += 1;
+  int maxlen = 1;
+  for (int64_t i = 0; i < nv; ++i) {
+    int a0 = abs(v[3 * i]), a1 = abs(v[3 * i + 1]), a2 = abs(v[3 * i + 2]);
+    if (a0 > W - 1 || a1 > H - 1 || a2 > D - 1) return -22;
+    if (a0 + 1 > maxlen) maxlen = a0 + 1;
+    if (a1 + 1 > maxlen) maxlen = a1 + 1;
+    if (a2 + 1 > maxlen) maxlen = a2 + 1;
+  }
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -455,8 +455,21 @@ int oracle_lpf3(const uint8_t *vol, int W, int H, int D, int cx, int cy, int cz,
     free(py);
     free(pz);
   }
-  free(v);
   return 0;
+}
+
+/* The same over the canonical 3-D half domain. */
+int oracle_lpf3(const uint8_t *vol, int W, int H, int D, int cx, int cy, int cz,
+                unsigned phase_mask, uint32_t *counts, int nthreads) {
+  if (W < 1 || H < 1 || D < 1 || cx < 0 || cy < 0 || cz < 0 || cx > W - 1 || cy > H - 1 ||
+      cz > D - 1)
+    return -22;
+  int64_t nv = oracle_num_vectors3(cx, cy, cz);
+  int16_t *v = (int16_t *)malloc(sizeof(int16_t) * 3 * nv);
+  oracle_vectors3(cx, cy, cz, v);
+  int rc = oracle_lpf3_vectors(vol, W, H, D, v, nv, phase_mask, counts, nthreads);
+  free(v);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------------------------

@@ -80,6 +80,22 @@ class Context:
         _abi.lpf_full_enhanced(self.handle, bits, W, H, cx, cy, phase_mask, layout, out, stream)
         return out
 
+    def pack3d(self, vol: torch.Tensor, stream=None) -> torch.Tensor:
+        """uint8 (D, H, W) device volume -> packed int64 rows (D*H, ceil(W/64))."""
+        D, H, W = vol.shape
+        return self.pack(vol.reshape(D * H, W), stream)
+
+    def full3d(self, bits: torch.Tensor, W: int, H: int, D: int, cx: int, cy: int, cz: int,
+               phase_mask: int = LPF_BOTH, out=None, stream=None) -> torch.Tensor:
+        """Counts int32 (nph, |D_c|) of a periodic volume over the canonical 3-D vectors
+        (lpf_vectors3); cz = 0 gives the sum of the xy-cuts' 2-D functions."""
+        if out is None:
+            nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+            out = torch.empty((nph, _abi.lpf_num_vectors3(cx, cy, cz)), dtype=torch.int32,
+                              device=bits.device)
+        _abi.lpf_full3d(self.handle, bits, W, H, D, cx, cy, cz, phase_mask, out, stream)
+        return out
+
     def full_sampled(self, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
                      sample: torch.Tensor, phase_mask: int = LPF_BOTH, layout: int = LPF_OUT_HALF,
                      out=None, stream=None) -> torch.Tensor:

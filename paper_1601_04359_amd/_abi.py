@@ -60,6 +60,9 @@ _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i
 _sig("lpf_anneal_create_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
      _P, _i32, _P, ctypes.POINTER(_P), _P)
 _sig("lpf_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_num_vectors3", _i64, _i32, _i32, _i32)
+_sig("lpf_vectors3", _i32, _i32, _i32, _i32, _P)
+_sig("lpf_full3d", _i32, _P, _P, _i32, _i32, _i32, _i32, _i32, _i32, _u32, _P, _P)
 _sig("lpf_full_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P, _P)
 _sig("lpf_anneal_create_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _P, _i64,
      _u64, _u64, _P, _i32, _P, ctypes.POINTER(_P), _P)
@@ -213,6 +216,31 @@ def lpf_s2(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, phase
         raise ValueError(f"lpf_s2: counts must hold {shp} elements")
     _check(_lib.lpf_s2(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
                        out_layout, _dev(counts, torch.int32, "counts"), _stream(stream)))
+
+
+def lpf_num_vectors3(cx: int, cy: int, cz: int) -> int:
+    return int(_lib.lpf_num_vectors3(cx, cy, cz))
+
+
+def lpf_vectors3(cx: int, cy: int, cz: int):
+    import numpy as np
+    n = lpf_num_vectors3(cx, cy, cz)
+    if n < 0:
+        raise ValueError("lpf_vectors3: negative cutoff")
+    out = np.zeros((n, 3), np.int16)
+    _check(_lib.lpf_vectors3(cx, cy, cz, out.ctypes.data_as(_P)))
+    return out
+
+
+def lpf_full3d(ctx: int, bits: torch.Tensor, W: int, H: int, D: int, cx: int, cy: int, cz: int,
+               phase_mask: int, counts: torch.Tensor, stream=None) -> None:
+    if bits.numel() != ((W + 63) // 64) * H * D:
+        raise ValueError("lpf_full3d: bits size does not match W, H, D")
+    nph = (phase_mask & 1) + ((phase_mask >> 1) & 1)
+    if min(cx, cy, cz) >= 0 and counts.numel() != nph * lpf_num_vectors3(cx, cy, cz):
+        raise ValueError("lpf_full3d: counts must hold nph * |D_c| elements")
+    _check(_lib.lpf_full3d(ctx, _dev(bits, torch.int64, "bits"), W, H, D, cx, cy, cz, phase_mask,
+                           _dev(counts, torch.int32, "counts"), _stream(stream)))
 
 
 def lpf_full_sampled(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,

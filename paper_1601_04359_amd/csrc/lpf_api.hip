@@ -154,6 +154,7 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
+  std::map<std::tuple<int, int, int>, short4 *> vec3;  // canonical 3-D vectors per cutoff
   std::map<std::string, struct BatchGraph *> batch_graphs;
   DevBuf ext, ext3, s2ext, s2acc, sext;
   std::mutex mu;
@@ -887,6 +888,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.chunk_off);
       (void)hipFree(kv.second.runs);
     }
+    for (auto &kv : c->vec3) (void)hipFree(kv.second);
     for (auto &kv : c->s2_plans) {
       (void)hipFree(kv.second.fams);
       (void)hipFree(kv.second.groups);
@@ -1021,6 +1023,85 @@ lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx,
   L.nchunks = plan->nchunks;
   L.use_lds = plan->use_lds;
   if ((e = launch_delta(L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
+  return LPF_OK;
+}
+
+int64_t lpf_num_vectors3(int cx, int cy, int cz) {
+  if (cx < 0 || cy < 0 || cz < 0) return -1;
+  return lpf_num_vectors(cx, cy) + (int64_t)cz * (2 * cx + 1) * (2 * cy + 1);
+}
+
+lpf_status lpf_vectors3(int cx, int cy, int cz, int16_t *dxdydz) {
+  if (cx < 0 || cy < 0 || cz < 0 || cx > 32767 || cy > 32767 || cz > 32767)
+    return fail(LPF_E_INVAL, "lpf_vectors3: cutoff");
+  if (!dxdydz) return fail(LPF_E_INVAL, "lpf_vectors3: NULL buffer");
+  std::vector<int16_t> can;
+  canonical_vectors(cx, cy, can);
+  size_t i = 0;
+  for (size_t j = 0; j < can.size(); j += 2, ++i) {
+    dxdydz[3 * i] = can[j];
+    dxdydz[3 * i + 1] = can[j + 1];
+    dxdydz[3 * i + 2] = 0;
+  }
+  for (int dz = 1; dz <= cz; ++dz)
+    for (int dy = -cy; dy <= cy; ++dy)
+      for (int dx = -cx; dx <= cx; ++dx, ++i) {
+        dxdydz[3 * i] = (int16_t)dx;
+        dxdydz[3 * i + 1] = (int16_t)dy;
+        dxdydz[3 * i + 2] = (int16_t)dz;
+      }
+  return LPF_OK;
+}
+
+lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int cx, int cy,
+                      int cz, unsigned phase_mask, uint32_t *counts, void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_full3d: ctx is NULL");
+  if (!bits || !counts) return fail(LPF_E_INVAL, "lpf_full3d: NULL buffer");
+  if (W < 1 || H < 1 || D < 1 || W > 65535 || H > 65535 || D > 65535 || (int64_t)H * D > 65535LL * 65535LL)
+    return fail(LPF_E_INVAL, "lpf_full3d: W/H/D out of range");
+  if (cx < 0 || cy < 0 || cz < 0 || cx > W - 1 || cy > H - 1 || cz > D - 1 || cx > 32767 ||
+      cy > 32767 || cz > 32767)
+    return fail(LPF_E_INVAL, "lpf_full3d: cutoff must satisfy 0 <= c <= size - 1 on each axis");
+  if (phase_mask < 1 || phase_mask > 3) return fail(LPF_E_INVAL, "lpf_full3d: phase_mask must be 1, 2 or 3");
+  const int64_t nv = lpf_num_vectors3(cx, cy, cz);
+  if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_full3d: too many vectors");
+  if ((int64_t)W * H * D > ((int64_t)1 << 32) - 1)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full3d: more than 2^32 - 1 voxels (uint32 counts)");
+  const int swd = (W + 31) / 32;
+  const int R = std::min(16, next_pow2(swd));
+  const int S = next_pow2((swd + R - 1) / R);
+  if (S > 64) return fail(LPF_E_UNSUPPORTED, "lpf_full3d: rows too wide (W > 32768)");
+  const int we = S * R + (cx >> 5) + 1;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_full3d: cannot select the context's device");
+  hipError_t e;
+  short4 *vec = nullptr;
+  auto key = std::make_tuple(cx, cy, cz);
+  auto it = c->vec3.find(key);
+  if (it != c->vec3.end()) {
+    vec = it->second;
+  } else {
+    std::vector<int16_t> v3((size_t)nv * 3);
+    lpf_vectors3(cx, cy, cz, v3.data());
+    std::vector<short4> hv(nv);
+    for (int64_t i = 0; i < nv; ++i) hv[i] = make_short4(v3[3 * i], v3[3 * i + 1], v3[3 * i + 2], 0);
+    if ((e = hipMalloc(&vec, sizeof(short4) * nv)) != hipSuccess) return hip_fail(e, "lpf_full3d: vectors");
+    if ((e = hipMemcpy(vec, hv.data(), sizeof(short4) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipFree(vec);
+      return hip_fail(e, "lpf_full3d: vectors");
+    }
+    c->vec3[key] = vec;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int rows = H * D;
+  if ((e = c->ext.ensure((size_t)rows * we * sizeof(uint32_t))) != hipSuccess)
+    return hip_fail(e, "lpf_full3d: scratch");
+  if ((e = launch_ext(bits, W, rows, we, (uint32_t *)c->ext.p, s)) != hipSuccess)
+    return hip_fail(e, "lpf_full3d: ext");
+  if ((e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,
+                       counts, s)) != hipSuccess)
+    return hip_fail(e, "lpf_full3d: kernel");
   return LPF_OK;
 }
 

@@ -248,6 +248,13 @@ hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int m
                             const int64_t *ext_off, hipStream_t stream);
 hipError_t prepare_full_kernels(int max_lds_bytes);
 
+// ---- 3-D volumes (k_lpf3.hip) ----
+// E: extended rows of the volume (row z*H + y, we >= S*R + (cx >> 5) + 1 dwords), vec: the
+// canonical 3-D vectors {dx, dy, dz, 0}; counts[p][nv].
+hipError_t launch_lpf3(const uint32_t *E, int W, int H, int D, int we, int R, int S,
+                       const short4 *vec, int nv, unsigned phase_mask, uint32_t *counts,
+                       hipStream_t stream);
+
 // ---- two-point probability (k_s2.hip) ----
 // Full evaluation: vector families {dx0, dy, nj} (members dx0 + 32 j, j < nj <= J) sorted by
 // dy, in groups of at most 256 (one workgroup each), start rows in blocks of rb; acc holds the

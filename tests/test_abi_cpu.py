@@ -126,3 +126,14 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_3d_entry_points_on_the_host():
+    from paper_1601_04359_amd import _abi
+    lib = _abi.lib()
+    assert _abi.lpf_num_vectors3(-1, 0, 0) == -1
+    for c in ((0, 0, 0), (3, 2, 1), (5, 0, 4), (4, 4, 4)):
+        assert _abi.lpf_num_vectors3(*c) == oracle.num_vectors3(*c)
+        assert np.array_equal(_abi.lpf_vectors3(*c), oracle.vectors3(*c))
+    assert lib.lpf_full3d(None, None, 8, 8, 8, 1, 1, 1, 3, None, None) == _abi.LPF_E_INVAL
+    assert b"ctx" in lib.lpf_last_error()
