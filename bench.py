@@ -540,6 +540,103 @@ def mc_bench(args) -> dict:
             "error_vs_n": curves, "reconstruction": recon}
 
 
+def path_pixels3(cx: int, cy: int, cz: int) -> int:
+    """Sum of n + 1 over the canonical 3-D vectors (the 3-D segment has n + 1 voxels)."""
+    n2 = path_pixels(cx, cy)
+    tot = 0
+    for dz in range(1, cz + 1):
+        for dy in range(-cy, cy + 1):
+            for dx in range(-cx, cx + 1):
+                tot += max(abs(dx), abs(dy), dz) + 1
+    return n2 + tot
+
+
+def volume_bench(args) -> dict:
+    """3-D extension: a 100^3 periodic level-cut Gaussian volume (phi 0.5, correlation 2 voxels,
+    seed 1608; the morphology of the trabecular-bone specimen of Sec. 5), both phases:
+    (1) the 3-D function, cutoff 16 on every axis (17 969 vectors); (2) the ensemble of its 100
+    xy-cuts with the full in-plane domain (cutoff 99, cz = 0: 19 801 vectors), the descriptor the
+    paper averages over the cuts, by lpf_full3d and by 100 lpf_full calls; (3) a 50 x 50 cell
+    annealed to the ensemble descriptor (cutoff 24, Nt = 10^6)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import Anneal, Context
+
+    dev = torch.device("cuda:0")
+    ctx = Context(0)
+    vol = wl.gaussian_field_3d(100, 100, 100, 2.0, 0.5, 1608)
+    dv = torch.from_numpy(vol).to(dev)
+    bits = ctx.pack3d(dv)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            ev[0].record(stream)
+            fn()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]) / 1e3)
+        return float(np.median(ts))
+
+    N = vol.size
+    out3 = torch.empty((2, 17969), dtype=torch.int32, device=dev)
+    t3 = timed(lambda: ctx.full3d(bits, 100, 100, 100, 16, 16, 16, 3, out=out3), max(3, args.steps))
+    ops3 = (N / 32) * (3 * path_pixels3(16, 16, 16) + 2 * 17969) * 1.0
+    oute = torch.empty((2, 19801), dtype=torch.int32, device=dev)
+    te = timed(lambda: ctx.full3d(bits, 100, 100, 100, 99, 99, 0, 3, out=oute), max(3, args.steps))
+    cuts = [ctx.pack(dv[z].contiguous()) for z in range(100)]
+    outc = torch.empty((2, 19801), dtype=torch.int32, device=dev)
+
+    def per_cut():
+        for b in cuts:
+            ctx.full(b, 100, 100, 99, 99, 3, out=outc)
+    tc = timed(per_cut, 3)
+    opse = (N / 32) * (3 * path_pixels(99, 99) + 2 * 19801)
+    # reconstruction of a 50 x 50 cell from the ensemble descriptor of the cuts
+    side, c = 50, 24
+    target = ctx.full3d(bits, 100, 100, 100, c, c, 0, 3)
+    cell = wl.random_cell(side, side, int(round(vol.mean() * side * side)), 1609)
+    ch = Anneal(ctx, ctx.pack(torch.from_numpy(cell).to(dev)), side, side, c, c, 3, target, N,
+                seed=5)
+    e0 = float(ch.e.cpu()[0])
+    steps = 10000
+    Ts = e0 * 1e-3 * (1e-4 ** (1.0 / steps)) ** np.arange(steps)
+    recs = torch.empty((steps, 5), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ch.step(256, float(Ts[i]), recs[i])
+    torch.cuda.synchronize()
+    t_anneal = time.perf_counter() - t0
+    e_fin = float(ch.e.cpu()[0])
+    ch.close()
+    ctx.close()
+    ach = ops3 / t3 / 1e12
+    return {"metric": "LPF path-placements/s", "value": round(17969 * N * 2 / t3 / 1e9, 3),
+            "unit": "Gplacements/s", "n_gpus": 1, "steps": max(3, args.steps), "warmup": 1,
+            "ms_per_step": round(t3 * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "3-D LPF of a 100^3 periodic level-cut Gaussian volume (phi "
+                                   "0.5, correlation 2 voxels, seed 1608), cutoff 16 on every "
+                                   "axis, both phases"},
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(P_INT_TOPS, 3),
+                         "unit": "Tops/s", "frac": round(ach / P_INT_TOPS, 4),
+                         "kernel": "k_lpf3 (+k_ext inside the event window)",
+                         "ops_alg_per_launch": ops3},
+            "ensemble_of_cuts": {"vectors": 19801, "lpf_full3d_ms": round(te * 1e3, 3),
+                                 "per_cut_lpf_full_ms": round(tc * 1e3, 3),
+                                 "frac_lpf_full3d": round(opse / te / 1e12 / P_INT_TOPS, 4),
+                                 "frac_per_cut": round(opse / tc / 1e12 / P_INT_TOPS, 4)},
+            "reconstruction_from_cuts": {"cell": "50x50", "cutoff": c, "steps": steps,
+                                         "e_start": e0, "e_final": e_fin,
+                                         "wall_s": round(t_anneal, 3)}}
+
+
 def batch_bench(args) -> dict:
     """Uneven batch: 256 Boolean disk images, side ~ U{64,128,256,512,1024}, phi ~ U[0.2,0.6],
     r ~ U[3,15], cutoff side/2, both phases; one step = one lpf_batch call (persistent launch,
@@ -628,7 +725,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper",
-                                           "mutual", "mc"],
+                                           "mutual", "mc", "volume"],
                     default="full")
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
@@ -669,6 +766,9 @@ def main() -> int:
         return 0
     if args.workload == "mc":
         print(json.dumps(mc_bench(args)), flush=True)
+        return 0
+    if args.workload == "volume":
+        print(json.dumps(volume_bench(args)), flush=True)
         return 0
 
     import numpy as np

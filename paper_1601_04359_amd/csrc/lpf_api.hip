@@ -154,7 +154,12 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
-  std::map<std::tuple<int, int, int>, short4 *> vec3;  // canonical 3-D vectors per cutoff
+  // 3-D vectors per cutoff: sorted by major axis, longest first within each; the axis ranges
+  struct Vec3 {
+    int4 *vec = nullptr;
+    int maj_off[4] = {0, 0, 0, 0};
+  };
+  std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
   DevBuf ext, ext3, s2ext, s2acc, sext;
   std::mutex mu;
@@ -865,6 +870,7 @@ lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out) {
   if (e == hipSuccess) e = prepare_delta_kernels(kDeltaLdsMax);
   if (e == hipSuccess) e = prepare_step_kernels(kDeltaLdsMax);
   if (e == hipSuccess) e = prepare_s2_kernels(kMaxLds);
+  if (e == hipSuccess) e = prepare_lpf3_kernels(kMaxLds);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "lpf_ctx_create: kernel attributes");
@@ -888,7 +894,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.chunk_off);
       (void)hipFree(kv.second.runs);
     }
-    for (auto &kv : c->vec3) (void)hipFree(kv.second);
+    for (auto &kv : c->vec3) (void)hipFree(kv.second.vec);
     for (auto &kv : c->s2_plans) {
       (void)hipFree(kv.second.fams);
       (void)hipFree(kv.second.groups);
@@ -1076,32 +1082,58 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
   DeviceGuard g(c->dev);
   if (!g.ok) return fail(LPF_E_DEVICE, "lpf_full3d: cannot select the context's device");
   hipError_t e;
-  short4 *vec = nullptr;
+  lpf_ctx_s::Vec3 *v3p = nullptr;
   auto key = std::make_tuple(cx, cy, cz);
   auto it = c->vec3.find(key);
   if (it != c->vec3.end()) {
-    vec = it->second;
+    v3p = &it->second;
   } else {
+    // launch order: by major axis (one kernel instance each), longest segments first, so that
+    // the waves of a workgroup walk segments of equal length and the long ones start early
     std::vector<int16_t> v3((size_t)nv * 3);
     lpf_vectors3(cx, cy, cz, v3.data());
-    std::vector<short4> hv(nv);
-    for (int64_t i = 0; i < nv; ++i) hv[i] = make_short4(v3[3 * i], v3[3 * i + 1], v3[3 * i + 2], 0);
-    if ((e = hipMalloc(&vec, sizeof(short4) * nv)) != hipSuccess) return hip_fail(e, "lpf_full3d: vectors");
-    if ((e = hipMemcpy(vec, hv.data(), sizeof(short4) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
-      (void)hipFree(vec);
+    std::vector<int4> hv(nv);
+    for (int64_t i = 0; i < nv; ++i) hv[i] = make_int4(v3[3 * i], v3[3 * i + 1], v3[3 * i + 2], (int)i);
+    auto len = [](const int4 &a) { return std::max(std::abs(a.x), std::max(std::abs(a.y), std::abs(a.z))); };
+    auto maj = [&](const int4 &a) { const int n = len(a); return std::abs(a.x) == n ? 0 : (std::abs(a.y) == n ? 1 : 2); };
+    std::stable_sort(hv.begin(), hv.end(), [&](const int4 &a, const int4 &b) {
+      return maj(a) != maj(b) ? maj(a) < maj(b) : len(a) > len(b);
+    });
+    lpf_ctx_s::Vec3 rec;
+    for (int m = 0; m < 3; ++m) {
+      int64_t k = 0;
+      while (k < nv && maj(hv[k]) <= m) ++k;
+      rec.maj_off[m + 1] = (int)k;
+    }
+    if ((e = hipMalloc(&rec.vec, sizeof(int4) * nv)) != hipSuccess) return hip_fail(e, "lpf_full3d: vectors");
+    if ((e = hipMemcpy(rec.vec, hv.data(), sizeof(int4) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipFree(rec.vec);
       return hip_fail(e, "lpf_full3d: vectors");
     }
-    c->vec3[key] = vec;
+    v3p = &(c->vec3[key] = rec);
   }
+  const int4 *vec = v3p->vec;
   hipStream_t s = (hipStream_t)stream;
   const int rows = H * D;
   if ((e = c->ext.ensure((size_t)rows * we * sizeof(uint32_t))) != hipSuccess)
     return hip_fail(e, "lpf_full3d: scratch");
   if ((e = launch_ext(bits, W, rows, we, (uint32_t *)c->ext.p, s)) != hipSuccess)
     return hip_fail(e, "lpf_full3d: ext");
-  if ((e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,
-                       counts, s)) != hipSuccess)
-    return hip_fail(e, "lpf_full3d: kernel");
+  // slabs in LDS when at least cz + 1 planes fit the 64 KiB budget (two workgroups per CU) or
+  // the full LDS; otherwise rows from global memory
+  const int rst = we | 1;
+  const size_t plane = (size_t)H * rst * sizeof(uint32_t);
+  size_t budget = 64 * 1024;
+  if ((size_t)(cz + 1) * plane > budget) budget = kMaxLds;
+  if ((size_t)(cz + 1) * plane <= budget) {
+    const int zb = (int)std::min<int64_t>(D, (int64_t)(budget / plane) - cz);
+    e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, zb, cz, vec,
+                         v3p->maj_off, (int)nv, phase_mask, counts, s);
+  } else {
+    e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,
+                    counts, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "lpf_full3d: kernel");
   return LPF_OK;
 }
 

@@ -250,10 +250,18 @@ hipError_t prepare_full_kernels(int max_lds_bytes);
 
 // ---- 3-D volumes (k_lpf3.hip) ----
 // E: extended rows of the volume (row z*H + y, we >= S*R + (cx >> 5) + 1 dwords), vec: the
-// canonical 3-D vectors {dx, dy, dz, 0}; counts[p][nv].
+// canonical 3-D vectors {dx, dy, dz, canonical index} in launch order; counts[p][nv].
 hipError_t launch_lpf3(const uint32_t *E, int W, int H, int D, int we, int R, int S,
-                       const short4 *vec, int nv, unsigned phase_mask, uint32_t *counts,
+                       const int4 *vec, int nv, unsigned phase_mask, uint32_t *counts,
                        hipStream_t stream);
+// Slabs of zb start planes staged with their cz-plane halo in LDS ((zb + cz) * H * rst dwords),
+// counts accumulated with atomics (zeroed here first).
+// vec sorted by major axis (x, then y, then z; maj_off[0..3] the ranges, host array), longest
+// first within each.
+hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst,
+                            int zb, int cz, const int4 *vec, const int *maj_off, int nv,
+                            unsigned phase_mask, uint32_t *counts, hipStream_t stream);
+hipError_t prepare_lpf3_kernels(int max_lds_bytes);
 
 // ---- two-point probability (k_s2.hip) ----
 // Full evaluation: vector families {dx0, dy, nj} (members dx0 + 32 j, j < nj <= J) sorted by

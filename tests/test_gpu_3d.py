@@ -83,3 +83,18 @@ def test_full3d_bone_volume_sampled_vectors(ctx):
     assert np.array_equal(got[:, pick], oracle.lpf3_vectors(vol, v[pick], 3))
     n1 = int(vol.sum())
     assert got[1, 0] == n1 and got[0, 0] == vol.size - n1
+
+
+def test_full3d_global_rows_path(ctx):
+    # planes too large for cz + 1 of them in LDS (256 x 256 rows, cz = 18): rows from global
+    # memory; sampled vectors against the oracle
+    import torch
+    print("[gpu] lpf3 256x256x20 c=(3,3,18) global rows", flush=True)
+    vol = wl.gaussian_field_3d(256, 256, 20, 1.5, 0.45, 9)
+    got = ctx.full3d(ctx.pack3d(_dev(vol)), 256, 256, 20, 3, 3, 18, 3)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.uint32)
+    v = oracle.vectors3(3, 3, 18)
+    pick = np.unique(np.concatenate([[0, len(v) - 1],
+                                     np.random.default_rng(4).integers(0, len(v), 40)]))
+    assert np.array_equal(got[:, pick], oracle.lpf3_vectors(vol, v[pick], 3))
