@@ -88,8 +88,9 @@ lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bit
  * vector of D_c and every phase of phase_mask, exact uint32 counts in `out_layout`.
  * bits: packed image as above (read only).  counts: see "Output layouts" (written in full).
  * Requires 1 <= W, H <= 65535, 0 <= cx <= W-1, 0 <= cy <= H-1, phase_mask in {1,2,3}.
- * Errors: LPF_E_INVAL (arguments), LPF_E_UNSUPPORTED (an image whose halo rows exceed the
- * on-chip staging limit), LPF_E_NOMEM / LPF_E_DEVICE (HIP). */
+ * Errors: LPF_E_INVAL (arguments), LPF_E_UNSUPPORTED (a cutoff above 32767, the int16 range of
+ * the vectors, or an image whose halo rows exceed the on-chip staging limit), LPF_E_NOMEM /
+ * LPF_E_DEVICE (HIP).  The same cutoff limit applies to every entry point below. */
 lpf_status lpf_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
 

@@ -6,8 +6,8 @@
 // periodic image.  The paper evaluates S2 with the FFT over all W x H shifts; over a cutoff
 // domain the direct count is exact in integers and costs one AND and one popcount per 32 start
 // pixels and vector, so it is done that way here:
-//   - a lane owns a family of up to J vectors (dx0 + 32 j, dy) and walks the rows of its
-//     workgroup's row block; for start word w of row y it forms t = bits [32w + s, 32w + s + 32)
+//   - a lane owns a family of up to J vectors (dx0 + 32 j, dy) and walks its wave's share of the
+//     workgroup's row block (the four waves of a workgroup share 64 families); for start word w of row y it forms t = bits [32w + s, 32w + s + 32)
 //     of row y + dy of the extended image (s = dx0 + W, one v_alignbit_b32), which is also member
 //     j's shifted word at w - j, and adds popcount(row_y[w] & t) into the members' counters;
 //   - row_y[w] is the same for every lane (an LDS broadcast), the shifted words are gathers from
@@ -33,13 +33,15 @@ __global__ void k_s2_zero(uint32_t *__restrict__ acc, int64_t n) {
 }
 
 // Phase-1 counts over start rows [y0, y0 + rb), y0 = blockIdx.y * rb, for the vector families of
-// group blockIdx.x, added into acc (integer atomics: the sum does not depend on the order).
+// group blockIdx.x (at most 64: one per lane), added into acc (integer atomics: the sum does not
+// depend on the order).  The workgroup's waves share the families and split the rows (wave w
+// takes rows w, w + waves, ...); their counts are summed in LDS before one atomic per member.
 // A family {dx0, dy, nj} is the vectors (dx0 + 32 j, dy), j < nj <= J, of one lane: with
 // s = dx0 + W (the same pairs as dx0 on the periodic image) member j's shifted word at start word
 // w is the family's shifted word at w + j, so one v_alignbit_b32 per word serves all J members.
 // group = {first family, end, dy of the first, dy of the last}, families sorted by dy.
 // LDS: A = the block's rows (swdp dwords each, zero past W), B = rows y0 + dy_lo ..
-// y0 + dy_hi + rb - 1 (mod H) of the extended image, rstB dwords apart.
+// y0 + dy_hi + rb - 1 (mod H) of the extended image, rstB dwords apart, then the reduction.
 template <int J>
 __global__ void __launch_bounds__(256)
 k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swdp, int rb,
@@ -51,6 +53,7 @@ k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swd
   const int y0 = blockIdx.y * rb;
   const int rows = min(rb, H - y0);
   const int nB = rows + g.w - g.z;
+  const int span = g.w - g.z;
   uint32_t *A = lds;
   uint32_t *B = lds + rb * swdp;
   const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
@@ -66,38 +69,51 @@ k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swd
     B[r * rstB + e] = E[(size_t)y * we + e];
   }
   __syncthreads();
-  const int f = g.x + (int)threadIdx.x;
-  if (f >= g.y) return;  // no barrier follows
-  const int4 fm = fams[f];
-  const int s0 = fm.x + W;
-  const int sh = s0 & 31;
-  const uint32_t *b = B + (fm.y - g.z) * rstB + (s0 >> 5);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int f = g.x + lane;
+  const bool live = f < g.y;
+  const int4 fm = live ? fams[f] : make_int4(0, g.z, 0, 0);
   uint32_t c[J];
 #pragma unroll
-  for (int j = 0; j < J; ++j) c[j] = 0;
-  for (int r = 0; r < rows; ++r) {
-    const uint32_t *a = A + r * swdp;
-    const uint32_t *bb = b + r * rstB;
-    for (int w0 = 0; w0 < swdp; w0 += CW) {
-      uint32_t av[CW], d[CW + J], t[CW + J - 1];
+  for (int jj = 0; jj < J; ++jj) c[jj] = 0;
+  if (live) {
+    const int s0 = fm.x + W;
+    const int sh = s0 & 31;
+    const uint32_t *b = B + (fm.y - g.z) * rstB + (s0 >> 5);
+    for (int r = wave; r < rows; r += waves) {
+      const uint32_t *a = A + r * swdp;
+      const uint32_t *bb = b + r * rstB;
+      for (int w0 = 0; w0 < swdp; w0 += CW) {
+        uint32_t av[CW], d[CW + J], t[CW + J - 1];
 #pragma unroll
-      for (int i = 0; i < CW; ++i) av[i] = a[w0 + i];
+        for (int i = 0; i < CW; ++i) av[i] = a[w0 + i];
 #pragma unroll
-      for (int k = 0; k < CW + J; ++k) d[k] = bb[w0 + k];
+        for (int k = 0; k < CW + J; ++k) d[k] = bb[w0 + k];
 #pragma unroll
-      for (int k = 0; k < CW + J - 1; ++k) t[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
+        for (int k = 0; k < CW + J - 1; ++k) t[k] = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
 #pragma unroll
-      for (int j = 0; j < J; ++j)
+        for (int jj = 0; jj < J; ++jj)
 #pragma unroll
-        for (int i = 0; i < CW; ++i) c[j] += __popc(av[i] & t[i + j]);
+          for (int i = 0; i < CW; ++i) c[jj] += __popc(av[i] & t[i + jj]);
+      }
     }
   }
+  // sum the waves' counts of each family member in LDS (after the staged rows)
+  uint32_t *red = B + (rb + span) * rstB;
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    if (j < fm.z && c[j]) {
-      const int dx = fm.x + 32 * j, dy = fm.y;
-      const int idx = dx >= 0 ? dy * (cx + 1) + dx : q1 + (dy - 1) * cx + (dx + cx);
-      atomicAdd(&acc[idx], c[j]);
+  for (int jj = 0; jj < J; ++jj) red[(wave * J + jj) * 64 + lane] = c[jj];
+  __syncthreads();
+  if (wave == 0 && live) {
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      uint32_t sum = 0;
+      for (int w = 0; w < waves; ++w) sum += red[(w * J + jj) * 64 + lane];
+      if (jj < fm.z && sum) {
+        const int dx = fm.x + 32 * jj, dy = fm.y;
+        const int idx = dx >= 0 ? dy * (cx + 1) + dx : q1 + (dy - 1) * cx + (dx + cx);
+        atomicAdd(&acc[idx], sum);
+      }
     }
   }
 }

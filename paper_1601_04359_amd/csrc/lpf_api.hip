@@ -378,9 +378,10 @@ void release_batch_graphs(lpf_ctx c) {
 
 // Two-point counts plan.  Vector families {dx0, dy, nj}: for each dy, the dx of D_c taken in
 // 32 residue classes, each class cut into runs of at most J members 32 apart (J = 1, 2, 4 or 8
-// from the widest dx range); families sorted by dy and cut into groups of at most 256 whose dy
-// range keeps the staged rows within the LDS budget; start rows in blocks of rb, halved (down to
-// 4) until the launch has about 2048 workgroups.
+// from the widest dx range); families sorted by dy and cut into groups of at most 64 (one per
+// lane; the four waves of a workgroup share them) whose dy range keeps the staged rows within
+// the LDS budget; start rows in blocks of rb (32, halved down to 8 while the launch has fewer
+// than about 1024 workgroups).
 lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
   auto key = std::make_tuple(W, H, cx, cy);
   auto it = c->s2_plans.find(key);
@@ -397,15 +398,17 @@ lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
   p.swdp = (p.swd + 7) / 8 * 8;
   p.we = ((W + cx) >> 5) + p.swdp + p.J;  // the last gather of a family: (s0 >> 5) + swdp + J - 1
   p.rstB = p.we | 1;
+  // rows A and B, then the cross-wave reduction (4 waves x J members x 64 lanes)
   auto bytes = [&](int rb, int span) {
-    return ((size_t)rb * p.swdp + (size_t)(rb + span) * p.rstB) * sizeof(uint32_t);
+    return ((size_t)rb * p.swdp + (size_t)(rb + span) * p.rstB + (size_t)4 * p.J * 64) *
+           sizeof(uint32_t);
   };
   size_t budget = 64 * 1024;
   int rb = std::min(32, H);
   while (rb > 1 && 2 * bytes(rb, 0) > budget) rb = (rb + 1) / 2;
   if (bytes(rb, 0) > budget) budget = kMaxLds;
   if (bytes(rb, 0) > budget) return fail(LPF_E_UNSUPPORTED, "lpf_s2: rows too wide for LDS staging");
-  const int span_max = (int)((budget / 4 - (size_t)rb * p.swdp) / p.rstB) - rb;
+  const int span_max = (int)((budget / 4 - (size_t)rb * p.swdp - (size_t)4 * p.J * 64) / p.rstB) - rb;
   std::vector<int4> fams;
   for (int dy = 0; dy <= cy; ++dy) {
     const int lo = dy == 0 ? 0 : -cx;
@@ -422,12 +425,12 @@ lpf_status get_s2_plan(lpf_ctx c, int W, int H, int cx, int cy, S2Plan *&plan) {
   for (int64_t i = 0; i < nf;) {
     int64_t j = i;
     const int dy0 = fams[i].y;
-    while (j < nf && j - i < 256 && fams[j].y - dy0 <= span_max) ++j;
+    while (j < nf && j - i < 64 && fams[j].y - dy0 <= span_max) ++j;
     groups.push_back(make_int4((int)i, (int)j, dy0, fams[j - 1].y));
     max_span = std::max(max_span, fams[j - 1].y - dy0);
     i = j;
   }
-  while (rb > 4 && (int64_t)groups.size() * ((H + rb - 1) / rb) < 2048) rb /= 2;
+  while (rb > 8 && (int64_t)groups.size() * ((H + rb - 1) / rb) < 1024) rb /= 2;
   std::vector<int32_t> packed(nv);
   {
     std::vector<int16_t> can;
@@ -832,6 +835,8 @@ lpf_status check_image_args(const char *fn, int W, int H, int cx, int cy, unsign
     return fail(LPF_E_INVAL, std::string(fn) + ": W/H out of range");
   if (cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1)
     return fail(LPF_E_INVAL, std::string(fn) + ": cutoff must satisfy 0 <= cx <= W-1, 0 <= cy <= H-1");
+  if (cx > 32767 || cy > 32767)
+    return fail(LPF_E_UNSUPPORTED, std::string(fn) + ": cutoff above 32767 (vectors are int16)");
   if (mask < 1 || mask > 3) return fail(LPF_E_INVAL, std::string(fn) + ": phase_mask must be 1, 2 or 3");
   return LPF_OK;
 }
@@ -928,6 +933,8 @@ lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int 
   if (W < 1 || H < 1 || W > 65535 || H > 65535) return fail(LPF_E_INVAL, "lpf_full: W/H out of range");
   if (cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1)
     return fail(LPF_E_INVAL, "lpf_full: cutoff must satisfy 0 <= cx <= W-1, 0 <= cy <= H-1");
+  if (cx > 32767 || cy > 32767)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full: cutoff above 32767 (vectors are int16)");
   if (phase_mask < 1 || phase_mask > 3) return fail(LPF_E_INVAL, "lpf_full: phase_mask must be 1, 2 or 3");
   if (out_layout != LPF_OUT_HALF && out_layout != LPF_OUT_GRID)
     return fail(LPF_E_INVAL, "lpf_full: out_layout");

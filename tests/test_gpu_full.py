@@ -231,3 +231,16 @@ def test_enhanced_tiled(ctx):
     finally:
         ctx.set_full_shape(0, 0, 0, 0)
     assert np.array_equal(std, enh)
+
+
+def test_cutoff_beyond_int16_is_refused(ctx):
+    # vectors are int16: a cutoff above 32767 must fail before any launch, not wrap
+    import torch
+    from paper_1601_04359_amd import LpfError
+    W = 40000
+    bits = ctx.pack(torch.zeros((1, W), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(LpfError) as e:
+        ctx.full(bits, W, 1, 32768, 0, 3)
+    assert e.value.status == -95
+    with pytest.raises(LpfError):
+        ctx.s2(bits, W, 1, 32768, 0, 3)
