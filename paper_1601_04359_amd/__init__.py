@@ -218,9 +218,21 @@ class Anneal:
 
     def run(self, n_candidates: int, Ts, proposal: int = LPF_PROP_UNIFORM,
             stream=None) -> torch.Tensor:
+        """len(Ts) steps, one anneal_step call each; records (n, 5) int64 on the device."""
         recs = torch.empty((len(Ts), 5), dtype=torch.int64, device=self.bits.device)
         for i, T in enumerate(Ts):
             _abi.anneal_step(self.handle, n_candidates, proposal, float(T), recs[i], stream)
+        return recs
+
+    def run_schedule(self, n_candidates: int, Ts, proposal: int = LPF_PROP_UNIFORM,
+                     stream=None) -> torch.Tensor:
+        """The same steps in one lpf_anneal_run call (temperatures uploaded once; graph replays
+        for uniform and interfacial proposals)."""
+        dev = self.bits.device
+        T = torch.as_tensor(Ts, dtype=torch.float64).to(dev).contiguous()
+        recs = torch.empty((T.numel(), 5), dtype=torch.int64, device=dev)
+        self._T_sched = T  # alive until the stream has consumed it
+        _abi.lpf_anneal_run(self.handle, n_candidates, proposal, T, recs, stream)
         return recs
 
     def set_proposal(self, net=None, scores: torch.Tensor | None = None, beta: float = 1.0,

@@ -68,6 +68,7 @@ _sig("lpf_anneal_create_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P
      _u64, _u64, _P, _i32, _P, ctypes.POINTER(_P), _P)
 _sig("lpf_s2_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
+_sig("lpf_anneal_run", _i32, _P, _i32, _i32, _P, _i32, _P, _P)
 _sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
 _sig("lpf_anneal_destroy", None, _P)
 
@@ -298,6 +299,17 @@ def lpf_anneal_create(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy:
         _dev(pos, torch.int32, "pos") if pos is not None else None, n1,
         _dev(e, torch.float64, "e"), ctypes.byref(h), _stream(stream)))
     return h.value
+
+
+def lpf_anneal_run(st: int, n_candidates: int, proposal: int, T_sched: torch.Tensor,
+                   out: torch.Tensor, stream=None) -> None:
+    n = T_sched.numel()
+    if out.device.type != "cuda" or out.dtype != torch.int64 or out.numel() < 5 * n:
+        raise ValueError("lpf_anneal_run: out must be a device int64 tensor of >= 5 * n elements")
+    if n == 0:
+        return
+    _check(_lib.lpf_anneal_run(st, n_candidates, proposal, _dev(T_sched, torch.float64, "T_sched"),
+                               n, _dev(out, torch.int64, "out"), _stream(stream)))
 
 
 def anneal_step(st: int, n_candidates: int, proposal: int, T: float, out: torch.Tensor,

@@ -71,13 +71,15 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
                           const double *__restrict__ cw1, const double *__restrict__ cw0,
                           double eps, int2 *__restrict__ cand, double *__restrict__ U,
                           int2 *__restrict__ slot, int64_t *__restrict__ S_acc,
-                          StepCtl *__restrict__ ctl) {
+                          StepCtl *__restrict__ ctl, const double *__restrict__ T_sched,
+                          int64_t T_base, double T, double *__restrict__ T_cur) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (ctl && k == 0) {  // the step's control block and energy sums start at zero
     ctl->done = 0;
     ctl->ks = -1;
     ctl->S = 0;
   }
+  if (T_cur && k == 0) *T_cur = T_sched ? T_sched[(int64_t)st->step - T_base] : T;
   if (k >= K) return;
   if (S_acc) S_acc[k] = 0;
   uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
@@ -235,9 +237,11 @@ __global__ void k_lse(const uint32_t *__restrict__ counts, const uint32_t *__res
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
                           int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
+                          const double *T_sched, int64_t T_base, double T, double *T_cur,
                           hipStream_t stream) {
   hipLaunchKernelGGL(k_propose, dim3((K + 255) / 256), dim3(256), 0, stream, st, bits, W, H, seed,
-                     K, proposal, cw1, cw0, eps, cand, U, slot, S_acc, ctl);
+                     K, proposal, cw1, cw0, eps, cand, U, slot, S_acc, ctl, T_sched, T_base, T,
+                     T_cur);
   return hipGetLastError();
 }
 

@@ -224,12 +224,12 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
             const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
             int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
             StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
-            const double *__restrict__ U, double T, int pi0, int pC) {
+            const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
   using P = Planes<MASK>;
   __shared__ long long s_part[4];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, T, (double)N * (double)N * (double)Nt,
+  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
                           ctl, &s_prev))
     return;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;

@@ -279,11 +279,11 @@ k_s2_round(const uint64_t *__restrict__ bits, int W, int H, const int2 *__restri
            unsigned phase_mask, const uint32_t *__restrict__ counts,
            const uint32_t *__restrict__ target, int64_t N, int64_t Nt, int64_t *__restrict__ S_acc,
            int16_t *__restrict__ dl, StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
-           const double *__restrict__ U, double T, int pi0, int pC) {
+           const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, T, (double)N * (double)N * (double)Nt,
+  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
                           ctl, &s_prev))
     return;
   const int wpr32 = 2 * ((W + 63) >> 6);

@@ -39,11 +39,11 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
               const uint32_t *__restrict__ counts, const uint32_t *__restrict__ target, int64_t N,
               int64_t Nt, int64_t *__restrict__ S_acc, int16_t *__restrict__ dl,
               StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
-              const double *__restrict__ U, double T, int pi0, int pC) {
+              const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, T, (double)N * (double)N * (double)Nt,
+  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
                           ctl, &s_prev))
     return;
   const int kr = blockIdx.x * blockDim.x + threadIdx.x;  // index within the round
@@ -97,10 +97,12 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
 // Decision for the round's candidates k0 .. k0 + C - 1 (one workgroup).
 __global__ void __launch_bounds__(1024)
 k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
-               const double *__restrict__ U, int k0, int C, double T, int64_t N, int64_t Nt,
-               StepCtl *__restrict__ ctl, const int32_t *__restrict__ order) {
+               const double *__restrict__ U, int k0, int C, const double *__restrict__ Tp,
+               int64_t N, int64_t Nt, StepCtl *__restrict__ ctl,
+               const int32_t *__restrict__ order) {
   __shared__ int s_first;
   if (ctl->done) return;
+  const double T = *Tp;
   if (threadIdx.x == 0) s_first = INT_MAX;
   __syncthreads();
   const double scale = (double)N * (double)N * (double)Nt;
@@ -133,10 +135,14 @@ k_step_final(AnnealDev *__restrict__ st, StepCtl *__restrict__ ctl, int K,
              int64_t Nt,
              double *__restrict__ e_io, uint32_t *__restrict__ counts, uint64_t *__restrict__ bits,
              int W, int32_t *__restrict__ k_sel, StepResult *__restrict__ out,
-             const int64_t *__restrict__ S_acc, const double *__restrict__ U, double T,
-             const int32_t *__restrict__ order, int li0, int lC) {
+             const int64_t *__restrict__ S_acc, const double *__restrict__ U,
+             const double *__restrict__ Tp, const int32_t *__restrict__ order, int li0, int lC,
+             int64_t out_base) {
   // decision of the last round when no earlier round accepted
   __shared__ int s_first;
+  const double T = *Tp;
+  // a run of steps writes its records at out[step - out_base]
+  if (out_base >= 0) out += (int64_t)st->step - out_base;
   int ks = ctl->ks;
   if (ks < 0 && lC > 0) {
     if (threadIdx.x == 0) s_first = INT_MAX;
@@ -253,7 +259,8 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
   const int li0 = nr ? L.rounds[nr - 1].k0 : 0, lC = nr ? L.rounds[nr - 1].C : 0;
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, L.st, L.ctl, L.K, L.cand,
                      L.slot, L.dl, L.dl_t, L.dl_k, L.nterms, L.N, L.Nt, L.e, L.counts_rw,
-                     L.bits_rw, L.W, L.k_sel, L.out, L.S_acc, L.U, L.T, L.order, li0, lC);
+                     L.bits_rw, L.W, L.k_sel, L.out, L.S_acc, L.U, L.T, L.order, li0, lC,
+                     L.out_base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (L.records && !L.s2) e = launch_rec_update(L.rg, L.ctl, L.cand, stream);
   return e;

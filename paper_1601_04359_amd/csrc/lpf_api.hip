@@ -198,6 +198,9 @@ struct lpf_anneal_s {
   int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
   bool rank = false;               // evaluate learned draws by descending predicted gain
   DevBuf scores, cw1, cw0, cwb, eS, eCtl, order;
+  DevBuf Tcur;             // the current step's temperature (device scalar)
+  uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
+  hipStream_t cap = nullptr;  // private stream for capturing runs of steps
 };
 
 // device memory the records method may take by itself (records + ones)
@@ -622,7 +625,9 @@ int delta_chunks(int K) {
 
 // Candidates of the chain's current step into a->cand / U / slot (learned weights first).
 lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
-                           int64_t *S_acc = nullptr, StepCtl *ctl = nullptr) {
+                           int64_t *S_acc = nullptr, StepCtl *ctl = nullptr,
+                           const double *T_sched = nullptr, int64_t T_base = 0, double T = 0.0,
+                           double *T_cur = nullptr) {
   hipError_t e;
   const int64_t N = (int64_t)a->W * a->H;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
@@ -663,7 +668,7 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   }
   if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, draw, cw1, cw0, a->eps,
                           (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, S_acc, ctl,
-                          s)) != hipSuccess)
+                          T_sched, T_base, T, T_cur, s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
   return LPF_OK;
 }
@@ -1286,6 +1291,7 @@ lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy
   hipError_t e;
   AnnealDev host{};
   host.step = step0;
+  a->host_step = step0;
   if ((e = hipMalloc(&a->dev, sizeof(AnnealDev))) != hipSuccess ||
       (e = hipMalloc(&a->pos, sizeof(int32_t) * (size_t)N)) != hipSuccess) {
     lpf_anneal_destroy(a);
@@ -1379,28 +1385,31 @@ lpf_status lpf_anneal_create_sampled(lpf_ctx c, uint64_t *bits, int W, int H, in
                        n1, e_dev, out, stream, false, sample);
 }
 
-lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
-                       void *stream) {
-  if (!a) return fail(LPF_E_INVAL, "anneal_step: state is NULL");
-  if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, "anneal_step: n_candidates outside [1, 2^20]");
+namespace {
+
+lpf_status step_args(const char *fn, lpf_anneal a, int K, int proposal) {
+  if (!a) return fail(LPF_E_INVAL, std::string(fn) + ": state is NULL");
+  if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, std::string(fn) + ": n_candidates outside [1, 2^20]");
   if (proposal != LPF_PROP_UNIFORM && proposal != LPF_PROP_INTERFACIAL &&
       proposal != LPF_PROP_LEARNED)
-    return fail(LPF_E_INVAL, "anneal_step: proposal");
+    return fail(LPF_E_INVAL, std::string(fn) + ": proposal");
   if (proposal == LPF_PROP_LEARNED && !a->net && !a->scores_ext)
-    return fail(LPF_E_INVAL, "anneal_step: learned proposal without lpf_anneal_set_proposal");
-  if (!(T > 0.0)) return fail(LPF_E_INVAL, "anneal_step: T must be > 0");
-  if (!out) return fail(LPF_E_INVAL, "anneal_step: out is NULL");
+    return fail(LPF_E_INVAL, std::string(fn) + ": learned proposal without lpf_anneal_set_proposal");
+  return LPF_OK;
+}
+
+// Plans, scratch and the evaluation state of a step with K candidates (records or frames are
+// rebuilt on the stream when stale); fills L except the per-step fields.
+lpf_status step_setup(lpf_anneal a, int K, hipStream_t s, StepLaunch &L, DeltaPlan *&plan,
+                      bool &rec) {
   lpf_ctx c = a->ctx;
-  std::lock_guard<std::mutex> lk(c->mu);
-  DeviceGuard g(c->dev);
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const bool rec = !a->s2 && use_records(a);
-  StepLaunch L{};
+  rec = !a->s2 && use_records(a);
+  L = StepLaunch{};
   L.s2 = a->s2;
   L.records = rec;
   L.rounds = step_rounds(K, true);
-  DeltaPlan *plan = nullptr;
+  plan = nullptr;
   lpf_status st;
   if (a->s2) {
     S2Plan *sp = nullptr;
@@ -1418,30 +1427,17 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   const int nph = nph_of(a->mask);
   const int64_t nv = lpf_num_vectors(a->cx, a->cy);
   const size_t nterms = (size_t)nph * nv;
+  const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
       (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
       (e = a->S_acc.ensure(sizeof(int64_t) * (size_t)K)) != hipSuccess ||
       (e = a->dl.ensure(sizeof(int16_t) * nterms * (size_t)K)) != hipSuccess ||
       (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
-      (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess)
-    return hip_fail(e, "anneal_step: scratch");
-  if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p)) != LPF_OK)
-    return st;
-  L.reset_done = true;
-  L.ordered = true;  // draws take a from the phase-1 list and b from the phase-0 list
-  if (proposal == LPF_PROP_LEARNED && a->rank) {
-    const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
-    const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
-    if ((e = a->order.ensure(sizeof(int32_t) * (size_t)K + 8 * ntop)) != hipSuccess)
-      return hip_fail(e, "anneal_step: order");
-    int32_t *ord = (int32_t *)a->order.p;
-    float *top_key = (float *)(ord + K);
-    int *top_id = (int *)(top_key + ntop);
-    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, top_key, top_id, s)) != hipSuccess)
-      return hip_fail(e, "anneal_step: ranking");
-    L.order = (const int32_t *)a->order.p;
-  }
+      (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess ||
+      (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
+      (e = a->order.ensure(sizeof(int32_t) * (size_t)K + 8 * ntop)) != hipSuccess)
+    return hip_fail(e, "anneal: scratch");
   if (plan) {
     L.E = (const uint32_t *)a->E3.p;
     L.geo = plan->geo;
@@ -1465,7 +1461,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   L.target = a->target;
   L.N = a->Neff;
   L.Nt = a->Nt;
-  L.T = T;
+  L.T = (const double *)a->Tcur.p;
   L.S_acc = (int64_t *)a->S_acc.p;
   L.dl = (int16_t *)a->dl.p;
   L.dl_t = rec ? 1 : K;
@@ -1474,8 +1470,37 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   L.st = a->dev;
   L.e = a->e;
   L.k_sel = (int32_t *)a->ksel.p;
+  L.reset_done = true;  // the draw zeroes the step's sums and control block
+  L.ordered = true;     // draws take a from the phase-1 list and b from the phase-0 list
+  return LPF_OK;
+}
+
+// One step on the stream after step_setup: draw (T from T_sched[step - T_base], or T), ranking,
+// rounds, decision, state upkeep.  No allocation and no host synchronisation (capturable, except
+// learned proposals, whose re-scoring cadence is kept on the host).
+lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaPlan *plan,
+                        bool rec, const double *T_sched, int64_t T_base, double T,
+                        lpf_step_result *out, int64_t out_base, hipStream_t s) {
+  hipError_t e;
+  lpf_status st;
+  if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p,
+                            T_sched, T_base, T, (double *)a->Tcur.p)) != LPF_OK)
+    return st;
+  L.order = nullptr;
+  if (proposal == LPF_PROP_LEARNED && a->rank) {
+    const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
+    const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
+    int32_t *ord = (int32_t *)a->order.p;
+    float *top_key = (float *)(ord + K);
+    int *top_id = (int *)(top_key + ntop);
+    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, top_key, top_id, s)) != hipSuccess)
+      return hip_fail(e, "anneal: ranking");
+    L.order = ord;
+  }
   L.out = reinterpret_cast<StepResult *>(out);
-  if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal_step: evaluation");
+  L.out_base = out_base;
+  if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal: evaluation");
+  a->host_step += 1;
   if (a->s2) {
     // the S2 rounds read the packed cell itself: nothing else to keep current
   } else if (rec) {
@@ -1484,8 +1509,85 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
     a->rec_valid = false;
     if ((e = launch_ext3_if(a->bits, a->W, a->H, plan->geo, (uint32_t *)a->E3.p,
                             (const int32_t *)a->ksel.p, s)) != hipSuccess)
-      return hip_fail(e, "anneal_step: ext3");
+      return hip_fail(e, "anneal: ext3");
   }
+  return LPF_OK;
+}
+
+}  // namespace
+
+lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
+                       void *stream) {
+  lpf_status st = step_args("anneal_step", a, K, proposal);
+  if (st != LPF_OK) return st;
+  if (!(T > 0.0)) return fail(LPF_E_INVAL, "anneal_step: T must be > 0");
+  if (!out) return fail(LPF_E_INVAL, "anneal_step: out is NULL");
+  std::lock_guard<std::mutex> lk(a->ctx->mu);
+  DeviceGuard g(a->ctx->dev);
+  hipStream_t s = (hipStream_t)stream;
+  StepLaunch L;
+  DeltaPlan *plan = nullptr;
+  bool rec = false;
+  if ((st = step_setup(a, K, s, L, plan, rec)) != LPF_OK) return st;
+  return step_enqueue(a, K, proposal, L, plan, rec, nullptr, 0, T, out, -1, s);
+}
+
+lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sched, int nsteps,
+                          lpf_step_result *out, void *stream) {
+  lpf_status st = step_args("lpf_anneal_run", a, K, proposal);
+  if (st != LPF_OK) return st;
+  if (nsteps < 0) return fail(LPF_E_INVAL, "lpf_anneal_run: nsteps < 0");
+  if (nsteps == 0) return LPF_OK;
+  if (!T_sched || !out) return fail(LPF_E_INVAL, "lpf_anneal_run: NULL buffer");
+  std::lock_guard<std::mutex> lk(a->ctx->mu);
+  DeviceGuard g(a->ctx->dev);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  StepLaunch L;
+  DeltaPlan *plan = nullptr;
+  bool rec = false;
+  if ((st = step_setup(a, K, s, L, plan, rec)) != LPF_OK) return st;
+  const int64_t base = (int64_t)a->host_step;
+  int done = 0;
+  // runs of kGraphSteps steps as one captured graph (uniform and interfacial proposals), the rest
+  // enqueued one by one
+  constexpr int kGraphSteps = 32;
+  if (proposal != LPF_PROP_LEARNED && nsteps >= kGraphSteps) {
+    if (!a->cap && (e = hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "lpf_anneal_run: capture stream");
+    // the capture enqueues nothing; the replays run on the caller's stream s
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const uint64_t step_before = a->host_step;
+    const bool e3_before = a->e3_valid, rec_before = a->rec_valid;
+    if ((e = hipStreamBeginCapture(a->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "lpf_anneal_run: capture");
+    lpf_status cst = LPF_OK;
+    for (int i = 0; i < kGraphSteps && cst == LPF_OK; ++i)
+      cst = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, a->cap);
+    hipError_t ce = hipStreamEndCapture(a->cap, &graph);
+    // the capture enqueued nothing: restore the host counters it advanced
+    a->host_step = step_before;
+    a->e3_valid = e3_before;
+    a->rec_valid = rec_before;
+    if (cst != LPF_OK || ce != hipSuccess ||
+        (ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst != LPF_OK ? cst : hip_fail(ce, "lpf_anneal_run: graph");
+    }
+    for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+      if ((e = hipGraphLaunch(exec, s)) != hipSuccess) break;
+      a->host_step += kGraphSteps;
+      if (!rec && !a->s2) a->rec_valid = false;
+      if (rec) a->e3_valid = false;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "lpf_anneal_run: graph launch");
+  }
+  for (; done < nsteps; ++done)
+    if ((st = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, s)) != LPF_OK)
+      return st;
   return LPF_OK;
 }
 
@@ -1533,6 +1635,8 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->order.release();
     a->eS.release();
     a->eCtl.release();
+    a->Tcur.release();
+    if (a->cap) (void)hipStreamDestroy(a->cap);
   }
   delete a;
 }

@@ -142,7 +142,8 @@ struct StepLaunch {
   uint32_t *counts_rw;
   const uint32_t *target;
   int64_t N, Nt;
-  double T;
+  const double *T;           // device: the step's temperature (written by k_propose)
+  int64_t out_base;          // >= 0: the step's record goes to out[step - out_base]
   int64_t *S_acc;            // [K] exact energy sums
   int16_t *dl;               // per (term t, candidate k) at t * dl_t + k * dl_k
   int64_t dl_t, dl_k;
@@ -173,9 +174,12 @@ struct StepResult {
   uint64_t step;
 };
 // S_acc, ctl: when given, also zeroed for the step (the step's reset folded into the draw).
+// T_cur (when given) receives the step's temperature: T_sched[step - T_base] when T_sched is
+// given, else T.
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
                           int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
+                          const double *T_sched, int64_t T_base, double T, double *T_cur,
                           hipStream_t stream);
 // scratch: 4 * ceil(W*H / 1024) doubles
 hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,

@@ -42,11 +42,12 @@ __device__ __forceinline__ bool prev_round_accepted(const int64_t *__restrict__ 
                                                    const int2 *__restrict__ cand,
                                                    const double *__restrict__ U,
                                                    const int32_t *__restrict__ order, int pi0,
-                                                   int pC, double T, double scale,
-                                                   StepCtl *__restrict__ ctl, int *s_prev) {
+                                                   int pC, const double *__restrict__ Tp,
+                                                   double scale, StepCtl *__restrict__ ctl,
+                                                   int *s_prev) {
   if (pC <= 0) return false;
   if (threadIdx.x < 64) {
-    const int f = wave_first_accepted(S_acc, cand, U, order, pi0, pC, T, scale);
+    const int f = wave_first_accepted(S_acc, cand, U, order, pi0, pC, *Tp, scale);
     if (threadIdx.x == 0) *s_prev = f;
   }
   __syncthreads();
