@@ -99,7 +99,7 @@ def anneal_bench(args) -> dict:
     import numpy as np
     import torch
     import workloads as wl
-    from paper_1601_04359_amd import Anneal, Context, step_records
+    from paper_1601_04359_amd import Anneal, Context, _abi, step_records
 
     dev = torch.device("cuda:0")
     ctx = Context(0)
@@ -118,6 +118,7 @@ def anneal_bench(args) -> dict:
     torch.cuda.synchronize()
     warm.close()
     walls, finals, accepted, e0, drift_ok, method = [], [], [], None, True, None
+    T_dev = torch.from_numpy(Ts).to(dev)
     for seed in range(1, args.chains + 1):
         ch = chain(seed)
         method = ch.method
@@ -125,8 +126,7 @@ def anneal_bench(args) -> dict:
         torch.cuda.synchronize()
         e0 = float(ch.e.cpu()[0])
         t0 = time.perf_counter()
-        for i in range(nsteps):
-            ch.step(4096, float(Ts[i]), recs[i])
+        _abi.lpf_anneal_run(ch.handle, 4096, 0, T_dev, recs)  # graph replays of 32 steps
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         r = step_records(recs)
@@ -136,6 +136,16 @@ def anneal_bench(args) -> dict:
         print(f"  chain {seed}: {walls[-1]:.3f} s, e {e0:.6g} -> {finals[-1]:.6g}", file=sys.stderr,
               flush=True)
         ch.close()
+    # the first chain again, one anneal_step call per step: same records, host-launched
+    ch = chain(1)
+    recs_e = torch.empty((nsteps, 5), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nsteps):
+        ch.step(4096, float(Ts[i]), recs_e[i])
+    torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t0
+    ch.close()
     ctx.close()
     wall = float(np.median(walls))
     return {
@@ -163,6 +173,9 @@ def anneal_bench(args) -> dict:
         "wall_s_per_chain": [round(w, 4) for w in walls],
         "accepted_per_chain": accepted,
         "counts_equal_full_recount": drift_ok,
+        "eager_s_chain1": round(wall_eager, 4),
+        "note": "each chain is one lpf_anneal_run call (hipGraph replays of 32 captured steps); "
+                "eager_s_chain1 is the first chain stepped by one anneal_step call per step",
     }
 
 
@@ -247,6 +260,8 @@ def learned_bench(args) -> dict:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hit = None
+        # one anneal_step call per step (a captured run per block of 100 steps was slower: the
+        # step is bound by its kernels, and each run captures its graph afresh)
         for s0 in range(0, nsteps, block):
             s1 = min(nsteps, s0 + block)
             for s in range(s0, s1):

@@ -280,9 +280,10 @@ lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
 
 /* nsteps consecutive steps, step i at temperature T_sched[i] (device, double[nsteps]), records
  * to out[i] (device, lpf_step_result[nsteps]); the same chain, bit for bit, as nsteps calls of
- * anneal_step.  With uniform or interfacial proposals the steps are enqueued as replays of a
- * hipGraph of 32 captured steps (the temperature and the record slot are read on the device from
- * the chain's step counter), the remainder one by one; learned proposals are enqueued one by one.
+ * anneal_step.  The steps are enqueued as replays of a hipGraph of 32 captured steps (the
+ * temperature and the record slot are read on the device from the chain's step counter), the
+ * remainder one by one; learned proposals are captured only when their re-scoring interval
+ * (refresh) divides 32, else enqueued one by one.
  * Nothing is synchronised.  Errors: as anneal_step (LPF_E_INVAL also for nsteps < 0 or NULL
  * buffers when nsteps > 0); temperatures are not checked on the host (they live on the device). */
 lpf_status lpf_anneal_run(lpf_anneal st, int n_candidates, int proposal, const double *T_sched,

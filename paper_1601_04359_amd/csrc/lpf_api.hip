@@ -1400,8 +1400,8 @@ lpf_status step_args(const char *fn, lpf_anneal a, int K, int proposal) {
 
 // Plans, scratch and the evaluation state of a step with K candidates (records or frames are
 // rebuilt on the stream when stale); fills L except the per-step fields.
-lpf_status step_setup(lpf_anneal a, int K, hipStream_t s, StepLaunch &L, DeltaPlan *&plan,
-                      bool &rec) {
+lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaunch &L,
+                      DeltaPlan *&plan, bool &rec) {
   lpf_ctx c = a->ctx;
   hipError_t e;
   rec = !a->s2 && use_records(a);
@@ -1438,6 +1438,14 @@ lpf_status step_setup(lpf_anneal a, int K, hipStream_t s, StepLaunch &L, DeltaPl
       (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
       (e = a->order.ensure(sizeof(int32_t) * (size_t)K + 8 * ntop)) != hipSuccess)
     return hip_fail(e, "anneal: scratch");
+  if (proposal == LPF_PROP_LEARNED) {  // the draw's buffers, so that it allocates nothing
+    const int64_t N = (int64_t)a->W * a->H;
+    if ((a->net && (e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess) ||
+        (a->beta > 0.0 && ((e = a->cw1.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+                           (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
+                           (e = a->cwb.ensure(sizeof(double) * 4 * (size_t)((N + 1023) / 1024))) != hipSuccess)))
+      return hip_fail(e, "anneal: proposal scratch");
+  }
   if (plan) {
     L.E = (const uint32_t *)a->E3.p;
     L.geo = plan->geo;
@@ -1528,7 +1536,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   StepLaunch L;
   DeltaPlan *plan = nullptr;
   bool rec = false;
-  if ((st = step_setup(a, K, s, L, plan, rec)) != LPF_OK) return st;
+  if ((st = step_setup(a, K, proposal, s, L, plan, rec)) != LPF_OK) return st;
   return step_enqueue(a, K, proposal, L, plan, rec, nullptr, 0, T, out, -1, s);
 }
 
@@ -1546,13 +1554,22 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
   StepLaunch L;
   DeltaPlan *plan = nullptr;
   bool rec = false;
-  if ((st = step_setup(a, K, s, L, plan, rec)) != LPF_OK) return st;
+  if ((st = step_setup(a, K, proposal, s, L, plan, rec)) != LPF_OK) return st;
   const int64_t base = (int64_t)a->host_step;
   int done = 0;
-  // runs of kGraphSteps steps as one captured graph (uniform and interfacial proposals), the rest
-  // enqueued one by one
+  // runs of kGraphSteps steps as one captured graph, the rest enqueued one by one.  Learned
+  // proposals re-score the cell every `refresh` draws (host counter): a graph replays the same
+  // pattern when kGraphSteps is a multiple of refresh.
   constexpr int kGraphSteps = 32;
-  if (proposal != LPF_PROP_LEARNED && nsteps >= kGraphSteps) {
+  const bool graphable = proposal != LPF_PROP_LEARNED || kGraphSteps % a->refresh == 0;
+  auto age_after = [&](int age, int n) {  // the draw's re-scoring counter after n draws
+    for (int i = 0; i < n; ++i) {
+      if (age == 0 || age >= a->refresh) age = 0;
+      ++age;
+    }
+    return age;
+  };
+  if (graphable && nsteps >= kGraphSteps) {
     if (!a->cap && (e = hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "lpf_anneal_run: capture stream");
     // the capture enqueues nothing; the replays run on the caller's stream s
@@ -1560,6 +1577,7 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     hipGraphExec_t exec = nullptr;
     const uint64_t step_before = a->host_step;
     const bool e3_before = a->e3_valid, rec_before = a->rec_valid;
+    const int age_before = a->learn_age;
     if ((e = hipStreamBeginCapture(a->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(e, "lpf_anneal_run: capture");
     lpf_status cst = LPF_OK;
@@ -1570,6 +1588,7 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     a->host_step = step_before;
     a->e3_valid = e3_before;
     a->rec_valid = rec_before;
+    a->learn_age = age_before;
     if (cst != LPF_OK || ce != hipSuccess ||
         (ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1578,6 +1597,7 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
       if ((e = hipGraphLaunch(exec, s)) != hipSuccess) break;
       a->host_step += kGraphSteps;
+      if (proposal == LPF_PROP_LEARNED) a->learn_age = age_after(a->learn_age, kGraphSteps);
       if (!rec && !a->s2) a->rec_valid = false;
       if (rec) a->e3_valid = false;
     }

@@ -93,19 +93,33 @@ def test_run_equals_stepwise(ctx, kind, proposal, K):
     b.close()
 
 
-def test_run_learned_proposals_stepwise(ctx):
-    # learned proposals are enqueued one by one by lpf_anneal_run: same chain as anneal_step
+@pytest.mark.parametrize("refresh,use_net", [(3, False), (4, False), (4, True), (1, True)])
+def test_run_learned_proposals(ctx, refresh, use_net):
+    # learned proposals: captured when refresh divides 32 (the re-scoring pattern repeats in
+    # every replay), else enqueued one by one; either way the chain of anneal_step
     import torch
-    from paper_1601_04359_amd import LPF_PROP_LEARNED, step_records
-    print("[gpu] anneal run learned", flush=True)
+    from paper_1601_04359_amd import LPF_PROP_LEARNED, ProposalNet, learn, step_records
+    print(f"[gpu] anneal run learned refresh={refresh} net={use_net}", flush=True)
     a, b = _pair(ctx, "records", seed=9)
+    net = None
+    if use_net:
+        net = ProposalNet(ctx, 24, 24, 1, 16, learn.init_params(4, torch.device("cuda:0")))
     sc = _dev(np.random.default_rng(2).standard_normal(24 * 24).astype(np.float32))
     for ch in (a, b):
-        ch.set_proposal(scores=sc, beta=1.5, eps_uniform=0.2, refresh=3, rank=True)
-    Ts = 1e-4 * np.ones(40)
-    ra = step_records(a.run_schedule(128, Ts, LPF_PROP_LEARNED))
+        if net is not None:
+            ch.set_proposal(net=net, beta=1.5, eps_uniform=0.2, refresh=refresh, rank=True)
+        else:
+            ch.set_proposal(scores=sc, beta=1.5, eps_uniform=0.2, refresh=refresh, rank=True)
+    Ts = 1e-4 * np.ones(100)
+    ra = [step_records(a.run_schedule(128, Ts[:70], LPF_PROP_LEARNED))]
+    torch.cuda.synchronize()
+    ra.append(step_records(a.run(128, Ts[70:75], LPF_PROP_LEARNED)))
+    ra.append(step_records(a.run_schedule(128, Ts[75:], LPF_PROP_LEARNED)))
     rb = step_records(b.run(128, Ts, LPF_PROP_LEARNED))
     torch.cuda.synchronize()
-    assert np.array_equal(ra, rb)
+    assert np.array_equal(np.concatenate(ra), rb)
+    assert torch.equal(a.bits, b.bits)
     a.close()
     b.close()
+    if net is not None:
+        net.close()
