@@ -198,17 +198,46 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
     const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
     d[p] = P::phase(p) ? cB - cA : cA - cB;
   }
-  // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k on the path
+  // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k = p_j on the path
   const int DX = bx - ax, DY = by - ay;
-  if (within(DX, g.W, m.z < 0 ? -m.z : m.z) && within(DY, g.H, m.w)) {
+  if (n > 0 && within(DX, g.W, m.z < 0 ? -m.z : m.z) && within(DY, g.H, m.w)) {
     const uint32_t *RBa = g.rec + (size_t)a * g.rstride + P::nph * g.Rw;  // planes B of a
-    for (int kk = 0; kk <= n; ++kk) {
-      const int32_t p = g.pix[off + kk];
-      if (!on_path(DX + pix_dx(p), DY + pix_dy(p), m.z, m.w, n, g.W, g.H)) continue;
+    // Along the major axis p_j - p_k has the index difference t = j - k, so t is fixed modulo
+    // the period by b - a: t = t0 for k <= n - t0 and t = t0 - P for k >= P - t0.  For those k
+    // the minor coordinates of k and k + t (kept as error terms, no division in the loop) must
+    // differ by the minor part of b - a modulo its period.
+    const int dxv = m.z, dyv = m.w;
+    const int adx = dxv < 0 ? -dxv : dxv;
+    const bool xm = adx >= dyv;
+    const int sx = dxv < 0 ? -1 : 1;
+    const int Pm = xm ? g.W : g.H, Qm = xm ? g.H : g.W;
+    int t0 = xm ? sx * DX : DY;  // in (-Pm, Pm)
+    t0 += t0 < 0 ? Pm : 0;
+    int mm = xm ? DY : sx * DX;  // in (-Qm, Qm)
+    mm += mm < 0 ? Qm : 0;
+    const int mext = xm ? dyv : adx;
+    for (int ps = 0; ps < 2; ++ps) {
+      const int t = ps == 0 ? t0 : t0 - Pm;
+      const int k0 = ps == 0 ? 0 : Pm - t0;
+      const int k1 = ps == 0 ? n - t0 : n;
+      if (k0 > k1) continue;
+      const int va = n + 2 * k0 * mext, vb = n + 2 * (k0 + t) * mext;
+      int fa = va / (2 * n), ea = va - 2 * n * fa;
+      int fb = vb / (2 * n), eb = vb - 2 * n * fb;
+      for (int kk = k0; kk <= k1; ++kk) {
+        if (kk > k0) {
+          ea += 2 * mext;
+          if (ea >= 2 * n) { ea -= 2 * n; ++fa; }
+          eb += 2 * mext;
+          if (eb >= 2 * n) { eb -= 2 * n; ++fb; }
+        }
+        const int diff = fb - fa;
+        if (diff != mm && diff != mm - Qm) continue;
 #pragma unroll
-      for (int s = 0; s < P::nph; ++s)
-        d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
-                            : plane_bit(RA + (size_t)s * g.Rw, off + kk);
+        for (int s = 0; s < P::nph; ++s)
+          d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
+                              : plane_bit(RA + (size_t)s * g.Rw, off + kk);
+      }
     }
   }
 }
