@@ -289,6 +289,15 @@ lpf_status anneal_step(lpf_anneal st, int n_candidates, int proposal, double T,
 lpf_status lpf_anneal_run(lpf_anneal st, int n_candidates, int proposal, const double *T_sched,
                           int nsteps, lpf_step_result *out, void *stream);
 
+/* The evaluation order of a ranked learned step: order[0..K) (int32, device) lists the kRankTop
+ * = 64 draws with the highest fp32 key score[a] + score[b] among the first R = min(K, 4096)
+ * (best first; ties, including -0 and +0, by draw index; a draw with a < 0 or b < 0, or a NaN
+ * key, counts as -inf), then every other draw in draw order.  cand: int32[K][2] (device);
+ * score: float per pixel (device); scratch from the context.
+ * Errors: LPF_E_INVAL (K outside [1, 2^20], NULL), LPF_E_NOMEM, LPF_E_DEVICE. */
+lpf_status lpf_rank(lpf_ctx ctx, const int32_t *cand, const float *score, int K, int32_t *order,
+                    void *stream);
+
 /* Learned proposals (LPF_PROP_LEARNED): before each draw the cell is scored, by `net` (an
  * lpf_cnn for this cell size, run on the current cell) or, when net is NULL, by the caller's
  * field scores (device, W*H fp32, read at every learned draw).  With probability eps_uniform a

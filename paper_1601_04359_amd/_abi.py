@@ -69,6 +69,7 @@ _sig("lpf_anneal_create_sampled", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P
 _sig("lpf_s2_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("anneal_step", _i32, _P, _i32, _i32, ctypes.c_double, _P, _P)
 _sig("lpf_anneal_run", _i32, _P, _i32, _i32, _P, _i32, _P, _P)
+_sig("lpf_rank", _i32, _P, _P, _P, _i32, _P, _P)
 _sig("lpf_anneal_export", _i32, _P, _P, ctypes.POINTER(_i32), ctypes.POINTER(_u64), _P)
 _sig("lpf_anneal_destroy", None, _P)
 
@@ -299,6 +300,15 @@ def lpf_anneal_create(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy:
         _dev(pos, torch.int32, "pos") if pos is not None else None, n1,
         _dev(e, torch.float64, "e"), ctypes.byref(h), _stream(stream)))
     return h.value
+
+
+def lpf_rank(ctx: int, cand: torch.Tensor, score: torch.Tensor, order: torch.Tensor,
+             stream=None) -> None:
+    K = cand.numel() // 2
+    if cand.numel() != 2 * K or order.numel() != K:
+        raise ValueError("lpf_rank: cand must be (K, 2) and order K elements")
+    _check(_lib.lpf_rank(ctx, _dev(cand, torch.int32, "cand"), _dev(score, torch.float32, "score"),
+                         K, _dev(order, torch.int32, "order"), _stream(stream)))
 
 
 def lpf_anneal_run(st: int, n_candidates: int, proposal: int, T_sched: torch.Tensor,

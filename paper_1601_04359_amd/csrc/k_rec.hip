@@ -65,12 +65,12 @@ __device__ __forceinline__ bool on_path(int rx, int ry, int dx, int dy, int n, i
   if (adx >= dy) {  // major axis x (also v = 0)
     const int i = dx >= 0 ? rxm : (rxm ? W - rxm : 0);
     if (i > n) return false;
-    const int f = n ? (int)((2ll * i * dy + n) / (2ll * n)) : 0;
+    const int f = n ? (2 * i * dy + n) / (2 * n) : 0;  // n <= 254 for the records
     return rym == f;
   }
   const int i = rym;
   if (i > n) return false;
-  const int g = (int)((2ll * i * adx + n) / (2ll * n));
+  const int g = (2 * i * adx + n) / (2 * n);
   const int gx = dx < 0 ? (g ? W - g : 0) : g;
   return rxm == gx;
 }
@@ -320,9 +320,12 @@ k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__
   const int32_t p = g.pix[j];
   const int x = wrapi((side ? bx : ax) - pix_dx(p), g.W);
   const int y = wrapi((side ? by : ay) - pix_dy(p), g.H);
-  // x in both P_a and P_b: its count does not change
+  // x in both P_a and P_b: its count does not change (only possible when b - a is within the
+  // vector's box, which the cheap test settles for most lanes)
   const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
-  if (on_path(ox + pix_dx(p), oy + pix_dy(p), m.z, m.w, n, g.W, g.H)) return;
+  if (within(ox, g.W, m.z < 0 ? -m.z : m.z) && within(oy, g.H, m.w) &&
+      on_path(ox + pix_dx(p), oy + pix_dy(p), m.z, m.w, n, g.W, g.H))
+    return;
   uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
   const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
   *op = (uint8_t)o1;

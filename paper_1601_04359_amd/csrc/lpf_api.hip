@@ -161,7 +161,7 @@ struct lpf_ctx_s {
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
-  DevBuf ext, ext3, s2ext, s2acc, sext;
+  DevBuf ext, ext3, s2ext, s2acc, sext, rank_top;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -915,6 +915,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
     c->s2ext.release();
     c->s2acc.release();
     c->sext.release();
+    c->rank_top.release();
   }
   delete c;
 }
@@ -2031,6 +2032,24 @@ lpf_status lpf_anneal_set_proposal(lpf_anneal a, lpf_cnn net, const float *score
   a->beta = beta;
   a->eps = eps_uniform;
   return LPF_OK;
+}
+
+lpf_status lpf_rank(lpf_ctx c, const int32_t *cand, const float *score, int K, int32_t *order,
+                    void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_rank: ctx is NULL");
+  if (K < 1 || K > (1 << 20)) return fail(LPF_E_INVAL, "lpf_rank: K outside [1, 2^20]");
+  if (!cand || !score || !order) return fail(LPF_E_INVAL, "lpf_rank: NULL buffer");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_rank: cannot select the context's device");
+  const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
+  hipError_t e = c->rank_top.ensure(8 * ntop);
+  if (e != hipSuccess) return hip_fail(e, "lpf_rank: scratch");
+  float *top_key = (float *)c->rank_top.p;
+  int *top_id = (int *)(top_key + ntop);
+  e = launch_rank(reinterpret_cast<const int2 *>(cand), score, K, order, top_key, top_id,
+                  (hipStream_t)stream);
+  return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_rank");
 }
 
 lpf_status lpf_anneal_propose(lpf_anneal a, int K, int proposal, int32_t *cand_out, void *stream) {

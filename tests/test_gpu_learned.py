@@ -163,3 +163,50 @@ def test_ranked_step_takes_first_accepted_in_rank_order(ctx, K):
         taken += expect >= 0
     assert taken >= 3
     ch.close()
+
+
+def _expected_order(cand, score):
+    K = len(cand)
+    R = min(K, 4096)
+    a, b = cand[:R, 0], cand[:R, 1]
+    void = (a < 0) | (b < 0)
+    with np.errstate(invalid="ignore"):
+        key = (score[np.maximum(a, 0)] + score[np.maximum(b, 0)]).astype(np.float32)
+    key = np.where(void | np.isnan(key), -np.inf, key).astype(np.float64)
+    key = np.where(key == 0.0, 0.0, key)  # -0 and +0 are equal keys
+    top = list(np.lexsort((np.arange(R), -key))[:min(R, 64)])
+    chosen = set(top)
+    return np.array(top + [k for k in range(K) if k not in chosen], np.int32)
+
+
+@pytest.mark.parametrize("K,case", [(1, "random"), (40, "random"), (64, "random"),
+                                    (65, "ties"), (300, "ties"), (4096, "random"),
+                                    (4096, "zeros"), (5000, "void_nan"), (9000, "all_equal"),
+                                    (2048, "void_nan")])
+def test_rank_order_matches_definition(ctx, K, case):
+    # lpf_rank: the whole evaluation order against its definition (lexsort on the host)
+    import torch
+    from paper_1601_04359_amd import _abi
+    print(f"[gpu] rank order K={K} {case}", flush=True)
+    g = np.random.default_rng(K)
+    npix = 900
+    score = g.normal(size=npix).astype(np.float32)
+    if case == "ties":
+        score[: npix // 2] = np.round(score[: npix // 2])
+    if case == "zeros":
+        score[:] = 0.0
+        score[::2] = -0.0
+        score[5::7] = 1.0
+    if case == "all_equal":
+        score[:] = 0.25
+    if case == "void_nan":
+        score[3] = np.nan
+    cand = g.integers(0, npix, (K, 2)).astype(np.int32)
+    if case == "void_nan":
+        cand[::5] = -1
+    order = torch.empty(K, dtype=torch.int32, device="cuda")
+    _abi.lpf_rank(ctx.handle, torch.from_numpy(cand).cuda(), torch.from_numpy(score).cuda(), order)
+    torch.cuda.synchronize()
+    got = order.cpu().numpy()
+    want = _expected_order(cand, score)
+    assert np.array_equal(got, want)
