@@ -1,7 +1,7 @@
 // Device-resident simulated annealing on the lineal path function (Sec. 4, Alg. "annealing",
 // objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn (here), their exact
 // energy changes are evaluated against the current state in evaluation order (draw order, or the
-// learned ranking of k_rank_chunks / k_rank_merge) and the first candidate that passes the Metropolis test is applied
+// learned ranking of k_rank) and the first candidate that passes the Metropolis test is applied
 // (k_step.hip).  Rejected candidates leave the state unchanged, so this is the sequential chain
 // of the algorithm over those draws with the step's later candidates unused.  Nothing returns to
 // the host inside a step.
@@ -262,125 +262,152 @@ hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double 
 
 // Evaluation order of a step's candidates: the kRankTop draws with the highest predicted gain
 // score[a] + score[b] (fp32; void draws and NaN lowest; ties by draw index) among the first
-// R = min(K, kRankMax), best first, then every other draw in draw order.  k_rank_chunks sorts
-// chunks of 512 draws (one workgroup each) and keeps each chunk's best kRankTop; k_rank_merge
-// sorts those (the overall best kRankTop are among them) and writes the order.
-__device__ __forceinline__ bool rank_before(float ka, int ia, float kb, int ib) {
-  return ka > kb || (ka == kb && ia < ib);
+// R = min(K, kRankMax), best first, then every other draw in draw order.  One workgroup of 1024
+// threads: each wave sorts four columns of 64 keys across its lanes (bitonic), merges them into
+// its best 64, the 16 wave lists are merged pairwise through LDS, and the remaining draws are
+// compacted in draw order with ballot prefix counts.
+
+// 64-bit rank key: the gain in an order-preserving unsigned encoding (void draws and NaN as -inf,
+// -0 as +0) above the complement of the draw index, so that a larger key ranks first and equal
+// gains go to the earlier draw.  Every real key exceeds 0, the key of an empty slot.
+__device__ __forceinline__ uint64_t rank_key(const int2 *__restrict__ cand,
+                                             const float *__restrict__ score, int i) {
+  float g = -INFINITY;
+  const int2 ab = cand[i];
+  if (ab.x >= 0 && ab.y >= 0) {
+    const float s = score[ab.x] + score[ab.y];
+    g = s == s ? s : -INFINITY;
+    if (g == 0.0f) g = 0.0f;
+  }
+  const uint32_t u = __float_as_uint(g);
+  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)o << 32) | (uint64_t)(~(uint32_t)i);
 }
 
-// Bitonic sort of 512 (key, index) pairs, one per thread of a 512-thread workgroup, best first;
-// partners under 64 apart exchange through wave shuffles, the others through LDS.
-__device__ __forceinline__ void bitonic512(float &key, int &id, float *sk, int *si) {
-  const int e = threadIdx.x;
-  for (int size = 2; size <= 512; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      float pk;
-      int pi;
-      if (stride >= 64) {
-        sk[e] = key;
-        si[e] = id;
-        __syncthreads();
-        pk = sk[e ^ stride];
-        pi = si[e ^ stride];
-        __syncthreads();
-      } else {
-        pk = __shfl_xor(key, stride);
-        pi = __shfl_xor(id, stride);
-      }
-      const bool keep_first = ((e & stride) == 0) == ((e & size) == 0);
-      const bool p_first = rank_before(pk, pi, key, id);
-      if (keep_first ? p_first : !p_first) {
-        key = pk;
-        id = pi;
-      }
+// Value of lane (lane ^ S): DPP for S = 1, 2 (quad permutations) and 8 (row rotation by 8),
+// ds_bpermute otherwise.
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v) {
+  if constexpr (S == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+  else return (uint32_t)__shfl_xor((int)v, S);
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+  return ((uint64_t)xor_lane32<S>((uint32_t)(v >> 32)) << 32) | xor_lane32<S>((uint32_t)v);
+}
+
+__device__ __forceinline__ uint64_t lane64(uint64_t v, int src) {
+  return ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src) << 32) |
+         (uint32_t)__shfl((int)(uint32_t)v, src);
+}
+
+// Compare-exchange steps STRIDE, STRIDE/2, ..., 1 of the bitonic network at block size SIZE over
+// NC independent columns (one key per lane each); blocks with (lane & SIZE) == 0 end descending.
+template <int SIZE, int STRIDE, int NC>
+__device__ __forceinline__ void bitonic_steps(uint64_t (&k)[NC], int lane) {
+  if constexpr (STRIDE > 0) {
+    const bool take_max = ((lane & STRIDE) == 0) == ((lane & SIZE) == 0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint64_t p = xor_lane64<STRIDE>(k[c]);
+      k[c] = (take_max == (p > k[c])) ? p : k[c];
     }
+    bitonic_steps<SIZE, STRIDE / 2, NC>(k, lane);
   }
 }
 
-__global__ void __launch_bounds__(512)
-k_rank_chunks(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
-              float *__restrict__ top_key, int *__restrict__ top_id) {
-  __shared__ float sk[512];
-  __shared__ int si[512];
-  const int R = min(K, kRankMax);
-  const int i = blockIdx.x * 512 + threadIdx.x;
-  float key = -INFINITY;
-  int id = INT_MAX;
-  if (i < R) {
-    id = i;
-    const int2 ab = cand[i];
-    if (ab.x >= 0 && ab.y >= 0) {
-      const float sc = score[ab.x] + score[ab.y];
-      key = sc == sc ? sc : -INFINITY;
-    }
-  }
-  bitonic512(key, id, sk, si);
-  if (threadIdx.x < kRankTop) {
-    top_key[blockIdx.x * kRankTop + threadIdx.x] = key;
-    top_id[blockIdx.x * kRankTop + threadIdx.x] = id;
+// Sort each column descending across the 64 lanes.
+template <int SIZE, int NC>
+__device__ __forceinline__ void wave_sort_desc(uint64_t (&k)[NC], int lane) {
+  if constexpr (SIZE <= 64) {
+    bitonic_steps<SIZE, SIZE / 2, NC>(k, lane);
+    wave_sort_desc<SIZE * 2, NC>(k, lane);
   }
 }
 
-__global__ void __launch_bounds__(512)
-k_rank_merge(const float *__restrict__ top_key, const int *__restrict__ top_id, int K,
-             int32_t *__restrict__ order) {
-  __shared__ float sk[512];
-  __shared__ int si[512];
-  __shared__ uint32_t sel[kRankMax / 32];
-  __shared__ int part[8];
+// Best 64 of two descending columns, descending: lane l takes the larger of a[l] and b[63 - l]
+// (a bitonic sequence holding the 64 largest), then a bitonic merge.
+__device__ __forceinline__ uint64_t merge_top64(uint64_t a, uint64_t b_rev, int lane) {
+  uint64_t m[1] = {a > b_rev ? a : b_rev};
+  bitonic_steps<64, 32, 1>(m, lane);
+  return m[0];
+}
+
+__global__ void __launch_bounds__(1024)
+k_rank(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
+       int32_t *__restrict__ order) {
+  static_assert(kRankMax == 4 * 1024 && kRankTop == 64, "k_rank: 4 keys per thread, 64 best");
+  __shared__ uint64_t list[2][8][64];
+  __shared__ int cnt[4][16];
+  __shared__ uint64_t thr_s;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int R = min(K, kRankMax);
-  const int nchunks = (R + 511) / 512;
-  const int t = threadIdx.x;
-  float key = -INFINITY;
-  int id = INT_MAX;
-  if (t < nchunks * kRankTop) {
-    key = top_key[t];
-    id = top_id[t];
+  uint64_t own[4], k[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = j * 1024 + t;
+    own[j] = i < R ? rank_key(cand, score, i) : 0ull;
+    k[j] = own[j];
   }
-  for (int w = t; w < kRankMax / 32; w += 512) sel[w] = 0u;
-  bitonic512(key, id, sk, si);
+  wave_sort_desc<2, 4>(k, lane);
+  // cross-lane reads stay outside conditional expressions: a lane shuffle evaluated under a
+  // partial execution mask reads nothing from the masked-off lanes
+  const uint64_t r1 = lane64(k[1], 63 - lane), r3 = lane64(k[3], 63 - lane);
+  uint64_t m2[2] = {k[0] > r1 ? k[0] : r1, k[2] > r3 ? k[2] : r3};
+  bitonic_steps<64, 32, 2>(m2, lane);
+  const uint64_t r = lane64(m2[1], 63 - lane);
+  uint64_t m = merge_top64(m2[0], r, lane);
+  // pairwise merges of the wave lists: waves [h, n) hand theirs to waves [0, h) through LDS;
+  // the two buffers alternate so one barrier per level suffices
+  int buf = 0;
+#pragma unroll
+  for (int n = 16; n > 1; n >>= 1) {
+    const int h = n >> 1;
+    if (w >= h && w < n) list[buf][w - h][lane] = m;
+    __syncthreads();
+    if (w < h) m = merge_top64(m, list[buf][w][63 - lane], lane);
+    buf ^= 1;
+  }
   const int T = min(R, kRankTop);
-  if (t < T) {
-    order[t] = id;
-    atomicOr(&sel[id >> 5], 1u << (id & 31));
+  if (w == 0) {
+    if (lane < T) order[lane] = (int32_t)~(uint32_t)m;
+    if (lane == T - 1) thr_s = m;
   }
   __syncthreads();
-  // the other draws of [0, R) in draw order: consecutive draws per thread, exclusive scan
-  constexpr int per = kRankMax / 512;
-  const int i0 = t * per;
-  int cnt = 0;
-  for (int j = 0; j < per; ++j) {
-    const int i = i0 + j;
-    cnt += (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) ? 1 : 0;
+  // every other draw of [0, R) in draw order (draw j * 1024 + t), after the best T
+  const uint64_t thr = thr_s;
+  uint64_t bal[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = j * 1024 + t;
+    bal[j] = __ballot(i < R && own[j] < thr);
+    if (lane == 0) cnt[j][w] = __popcll(bal[j]);
   }
-  // inclusive scan of the counts: within the wave by shuffles, then over the 8 wave totals
-  int x = cnt;
-  const int lane = t & 63, wave = t >> 6;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) part[wave] = x;
   __syncthreads();
-  int off = 0;
-  for (int w = 0; w < wave; ++w) off += part[w];
-  int pos = T + off + x - cnt;
-  for (int j = 0; j < per; ++j) {
-    const int i = i0 + j;
-    if (i < R && !((sel[i >> 5] >> (i & 31)) & 1u)) order[pos++] = i;
+  int base = T;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int before = 0, total = 0;
+    for (int v = 0; v < 16; ++v) {
+      before += v < w ? cnt[j][v] : 0;
+      total += cnt[j][v];
+    }
+    if ((bal[j] >> lane) & 1ull) {
+      const int below = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(bal[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+      order[base + before + below] = j * 1024 + t;
+    }
+    base += total;
   }
-  for (int i = R + t; i < K; i += 512) order[i] = i;
+  for (int i = R + t; i < K; i += 1024) order[i] = i;
 }
 
 hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
-                       float *top_key, int *top_id, hipStream_t stream) {
-  const int R = std::min(K, kRankMax);
-  hipLaunchKernelGGL(k_rank_chunks, dim3((unsigned)((R + 511) / 512)), dim3(512), 0, stream, cand,
-                     score, K, top_key, top_id);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rank_merge, dim3(1), dim3(512), 0, stream, top_key, top_id, K, order);
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(k_rank, dim3(1), dim3(1024), 0, stream, cand, score, K, order);
   return hipGetLastError();
 }
 

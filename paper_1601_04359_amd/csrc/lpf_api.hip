@@ -161,7 +161,7 @@ struct lpf_ctx_s {
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
-  DevBuf ext, ext3, s2ext, s2acc, sext, rank_top;
+  DevBuf ext, ext3, s2ext, s2acc, sext;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -915,7 +915,6 @@ void lpf_ctx_destroy(lpf_ctx c) {
     c->s2ext.release();
     c->s2acc.release();
     c->sext.release();
-    c->rank_top.release();
   }
   delete c;
 }
@@ -1428,7 +1427,6 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
   const int nph = nph_of(a->mask);
   const int64_t nv = lpf_num_vectors(a->cx, a->cy);
   const size_t nterms = (size_t)nph * nv;
-  const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
       (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
@@ -1437,7 +1435,7 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
       (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
       (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess ||
       (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
-      (e = a->order.ensure(sizeof(int32_t) * (size_t)K + 8 * ntop)) != hipSuccess)
+      (e = a->order.ensure(sizeof(int32_t) * (size_t)K)) != hipSuccess)
     return hip_fail(e, "anneal: scratch");
   if (proposal == LPF_PROP_LEARNED) {  // the draw's buffers, so that it allocates nothing
     const int64_t N = (int64_t)a->W * a->H;
@@ -1498,11 +1496,8 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
   L.order = nullptr;
   if (proposal == LPF_PROP_LEARNED && a->rank) {
     const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
-    const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
     int32_t *ord = (int32_t *)a->order.p;
-    float *top_key = (float *)(ord + K);
-    int *top_id = (int *)(top_key + ntop);
-    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, top_key, top_id, s)) != hipSuccess)
+    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, s)) != hipSuccess)
       return hip_fail(e, "anneal: ranking");
     L.order = ord;
   }
@@ -2042,13 +2037,8 @@ lpf_status lpf_rank(lpf_ctx c, const int32_t *cand, const float *score, int K, i
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
   if (!g.ok) return fail(LPF_E_DEVICE, "lpf_rank: cannot select the context's device");
-  const size_t ntop = (size_t)(kRankMax / 512) * kRankTop;
-  hipError_t e = c->rank_top.ensure(8 * ntop);
-  if (e != hipSuccess) return hip_fail(e, "lpf_rank: scratch");
-  float *top_key = (float *)c->rank_top.p;
-  int *top_id = (int *)(top_key + ntop);
-  e = launch_rank(reinterpret_cast<const int2 *>(cand), score, K, order, top_key, top_id,
-                  (hipStream_t)stream);
+  const hipError_t e =
+      launch_rank(reinterpret_cast<const int2 *>(cand), score, K, order, (hipStream_t)stream);
   return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_rank");
 }
 

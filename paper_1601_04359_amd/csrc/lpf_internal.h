@@ -187,12 +187,11 @@ hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double 
 hipError_t launch_copy_cand(const int2 *cand, int K, int32_t *out, hipStream_t stream);
 // Evaluation order of a step's K candidates: the kRankTop draws with the highest predicted gain
 // score[a] + score[b] among the first min(K, kRankMax) (best first, ties by draw index, void
-// draws lowest), then every other draw in draw order.  top_key, top_id: kRankMax / 512 * kRankTop
-// entries of scratch each.
+// draws lowest), then every other draw in draw order.  One workgroup; no scratch.
 constexpr int kRankMax = 4096;
 constexpr int kRankTop = 64;
 hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
-                       float *top_key, int *top_id, hipStream_t stream);
+                       hipStream_t stream);
 // Exact energy change of K given interchanges on a chain's state: de[i] = S_i / (N^2 Nt).
 hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 // Placement-state records: build ones and records from the packed image, and apply the
