@@ -1,7 +1,7 @@
 // Device-resident simulated annealing on the lineal path function (Sec. 4, Alg. "annealing",
 // objective eq. (LSE)).  One step: K candidate pixel interchanges are drawn (here), their exact
 // energy changes are evaluated against the current state in evaluation order (draw order, or the
-// learned ranking of k_rank) and the first candidate that passes the Metropolis test is applied
+// learned ranking of k_propose / k_rank_merge) and the first candidate that passes the Metropolis test is applied
 // (k_step.hip).  Rejected candidates leave the state unchanged, so this is the sequential chain
 // of the algorithm over those draws with the step's later candidates unused.  Nothing returns to
 // the host inside a step.
@@ -51,6 +51,97 @@ __device__ __forceinline__ bool interfacial(const uint64_t *__restrict__ bits, i
          bit_at(bits, wpr, x, yu) != v || bit_at(bits, wpr, x, yd) != v;
 }
 
+// Evaluation order of a step's candidates (learned ranking): the kRankTop draws with the highest
+// predicted gain score[a] + score[b] (fp32; void draws and NaN lowest; ties by draw index) among
+// the first R = min(K, kRankMax), best first, then every other draw in draw order.  Each
+// 256-draw workgroup (of k_propose, or k_rank_blocks) sorts its keys per wave (bitonic, across
+// lanes) and merges the four wave lists into its best 64; k_rank_merge merges the workgroup lists
+// and compacts the remaining draws in draw order with ballot prefix counts.
+
+// 64-bit rank key: the gain in an order-preserving unsigned encoding (void draws and NaN as -inf,
+// -0 as +0) above the complement of the draw index, so that a larger key ranks first and equal
+// gains go to the earlier draw.  Every real key exceeds 0, the key of an empty slot.
+__device__ __forceinline__ uint64_t rank_key(int a, int b, int i, const float *__restrict__ score) {
+  float g = -INFINITY;
+  if (a >= 0 && b >= 0) {
+    const float s = score[a] + score[b];
+    g = s == s ? s : -INFINITY;
+    if (g == 0.0f) g = 0.0f;
+  }
+  const uint32_t u = __float_as_uint(g);
+  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)o << 32) | (uint64_t)(~(uint32_t)i);
+}
+
+// Value of lane (lane ^ S): DPP for S = 1, 2 (quad permutations) and 8 (row rotation by 8),
+// ds_bpermute otherwise.  Like every cross-lane read here, call it with the whole wave active.
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v) {
+  if constexpr (S == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+  else return (uint32_t)__shfl_xor((int)v, S);
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+  return ((uint64_t)xor_lane32<S>((uint32_t)(v >> 32)) << 32) | xor_lane32<S>((uint32_t)v);
+}
+
+__device__ __forceinline__ uint64_t lane64(uint64_t v, int src) {
+  return ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src) << 32) |
+         (uint32_t)__shfl((int)(uint32_t)v, src);
+}
+
+// Compare-exchange steps STRIDE, STRIDE/2, ..., 1 of the bitonic network at block size SIZE over
+// NC independent columns (one key per lane each); blocks with (lane & SIZE) == 0 end descending.
+template <int SIZE, int STRIDE, int NC>
+__device__ __forceinline__ void bitonic_steps(uint64_t (&k)[NC], int lane) {
+  if constexpr (STRIDE > 0) {
+    const bool take_max = ((lane & STRIDE) == 0) == ((lane & SIZE) == 0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint64_t p = xor_lane64<STRIDE>(k[c]);
+      k[c] = (take_max == (p > k[c])) ? p : k[c];
+    }
+    bitonic_steps<SIZE, STRIDE / 2, NC>(k, lane);
+  }
+}
+
+// Sort each column descending across the 64 lanes.
+template <int SIZE, int NC>
+__device__ __forceinline__ void wave_sort_desc(uint64_t (&k)[NC], int lane) {
+  if constexpr (SIZE <= 64) {
+    bitonic_steps<SIZE, SIZE / 2, NC>(k, lane);
+    wave_sort_desc<SIZE * 2, NC>(k, lane);
+  }
+}
+
+// Best 64 of two descending columns, descending: lane l takes the larger of a[l] and b[63 - l]
+// (a bitonic sequence holding the 64 largest), then a bitonic merge.
+__device__ __forceinline__ uint64_t merge_top64(uint64_t a, uint64_t b_rev, int lane) {
+  uint64_t m[1] = {a > b_rev ? a : b_rev};
+  bitonic_steps<64, 32, 1>(m, lane);
+  return m[0];
+}
+
+// Best 64 keys of a 256-thread workgroup (one key per thread), descending, into list[0..63].
+// Called by every thread of the workgroup; sl is 2 x 64 keys of LDS.
+__device__ __forceinline__ void block_top64(uint64_t key, uint64_t (*sl)[64],
+                                            uint64_t *__restrict__ list) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t k[1] = {key};
+  wave_sort_desc<2, 1>(k, lane);
+  uint64_t m = k[0];
+  if (w >= 2) sl[w - 2][lane] = m;
+  __syncthreads();
+  if (w < 2) m = merge_top64(m, sl[w][63 - lane], lane);
+  __syncthreads();
+  if (w == 1) sl[0][lane] = m;
+  __syncthreads();
+  if (w == 0) list[lane] = merge_top64(m, sl[0][63 - lane], lane);
+}
+
 // Candidate k of the current step: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
 // proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void unless both pixels are
 // interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn with probability
@@ -66,13 +157,15 @@ __device__ __forceinline__ int upper_index(const double *__restrict__ cw, int n,
   return lo;
 }
 
-__global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits,
-                          int W, int H, uint64_t seed, int K, int proposal,
-                          const double *__restrict__ cw1, const double *__restrict__ cw0,
-                          double eps, int2 *__restrict__ cand, double *__restrict__ U,
-                          int2 *__restrict__ slot, int64_t *__restrict__ S_acc,
-                          StepCtl *__restrict__ ctl, const double *__restrict__ T_sched,
-                          int64_t T_base, double T, double *__restrict__ T_cur) {
+__global__ void __launch_bounds__(256)
+k_propose(const AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits, int W, int H,
+          uint64_t seed, int K, int proposal, const double *__restrict__ cw1,
+          const double *__restrict__ cw0, double eps, int2 *__restrict__ cand,
+          double *__restrict__ U, int2 *__restrict__ slot, int64_t *__restrict__ S_acc,
+          StepCtl *__restrict__ ctl, const double *__restrict__ T_sched, int64_t T_base, double T,
+          double *__restrict__ T_cur, const float *__restrict__ rank_score,
+          uint64_t *__restrict__ rank_keys, uint64_t *__restrict__ rank_lists) {
+  __shared__ uint64_t sl[2][64];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (ctl && k == 0) {  // the step's control block and energy sums start at zero
     ctl->done = 0;
@@ -80,30 +173,40 @@ __global__ void k_propose(const AnnealDev *__restrict__ st, const uint64_t *__re
     ctl->S = 0;
   }
   if (T_cur && k == 0) *T_cur = T_sched ? T_sched[(int64_t)st->step - T_base] : T;
-  if (k >= K) return;
-  if (S_acc) S_acc[k] = 0;
-  uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
-  philox4x64_10(c, seed, 0x6c7066ull);
-  const int n1 = st->n1, n0 = st->n0;
-  int ia, ib;
-  const double u3 = (double)(c[3] >> 11) * (1.0 / 9007199254740992.0);
-  if (proposal == 2 && !(u3 < eps)) {
-    const double ua = (double)(c[0] >> 11) * (1.0 / 9007199254740992.0) * cw1[n1 - 1];
-    const double ub = (double)(c[1] >> 11) * (1.0 / 9007199254740992.0) * cw0[n0 - 1];
-    ia = upper_index(cw1, n1, ua);
-    ib = upper_index(cw0, n0, ub);
-  } else {
-    ia = (int)(((c[0] >> 32) * (uint64_t)n1) >> 32);
-    ib = (int)(((c[1] >> 32) * (uint64_t)n0) >> 32);
+  int a = -1, b = -1;
+  if (k < K) {
+    if (S_acc) S_acc[k] = 0;
+    uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
+    philox4x64_10(c, seed, 0x6c7066ull);
+    const int n1 = st->n1, n0 = st->n0;
+    int ia, ib;
+    const double u3 = (double)(c[3] >> 11) * (1.0 / 9007199254740992.0);
+    if (proposal == 2 && !(u3 < eps)) {
+      const double ua = (double)(c[0] >> 11) * (1.0 / 9007199254740992.0) * cw1[n1 - 1];
+      const double ub = (double)(c[1] >> 11) * (1.0 / 9007199254740992.0) * cw0[n0 - 1];
+      ia = upper_index(cw1, n1, ua);
+      ib = upper_index(cw0, n0, ub);
+    } else {
+      ia = (int)(((c[0] >> 32) * (uint64_t)n1) >> 32);
+      ib = (int)(((c[1] >> 32) * (uint64_t)n0) >> 32);
+    }
+    a = st->pos1[ia];
+    b = st->pos0[ib];
+    if (proposal == 1 && !(interfacial(bits, W, H, a) && interfacial(bits, W, H, b))) {
+      a = -1;
+      b = -1;
+    }
+    cand[k] = make_int2(a, b);
+    slot[k] = make_int2(ia, ib);
+    U[k] = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
   }
-  int a = st->pos1[ia], b = st->pos0[ib];
-  if (proposal == 1 && !(interfacial(bits, W, H, a) && interfacial(bits, W, H, b))) {
-    a = -1;
-    b = -1;
+  // learned ranking: this workgroup's keys and its best 64 (the condition is workgroup-uniform)
+  if (rank_score && (int)(blockIdx.x * blockDim.x) < min(K, kRankMax)) {
+    const bool ranked = k < min(K, kRankMax);
+    const uint64_t key = ranked ? rank_key(a, b, k, rank_score) : 0ull;
+    if (ranked) rank_keys[k] = key;
+    block_top64(key, sl, rank_lists + (size_t)blockIdx.x * kRankTop);
   }
-  cand[k] = make_int2(a, b);
-  slot[k] = make_int2(ia, ib);
-  U[k] = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
 }
 
 // Inclusive prefix sums of w(p) = exp(clamp(beta * score[p], -60, 60)) over the pixel lists
@@ -238,10 +341,11 @@ hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int 
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
                           int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
                           const double *T_sched, int64_t T_base, double T, double *T_cur,
+                          const float *rank_score, uint64_t *rank_keys, uint64_t *rank_lists,
                           hipStream_t stream) {
   hipLaunchKernelGGL(k_propose, dim3((K + 255) / 256), dim3(256), 0, stream, st, bits, W, H, seed,
                      K, proposal, cw1, cw0, eps, cand, U, slot, S_acc, ctl, T_sched, T_base, T,
-                     T_cur);
+                     T_cur, rank_score, rank_keys, rank_lists);
   return hipGetLastError();
 }
 
@@ -260,108 +364,36 @@ hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double 
   return hipGetLastError();
 }
 
-// Evaluation order of a step's candidates: the kRankTop draws with the highest predicted gain
-// score[a] + score[b] (fp32; void draws and NaN lowest; ties by draw index) among the first
-// R = min(K, kRankMax), best first, then every other draw in draw order.  One workgroup of 1024
-// threads: each wave sorts four columns of 64 keys across its lanes (bitonic), merges them into
-// its best 64, the 16 wave lists are merged pairwise through LDS, and the remaining draws are
-// compacted in draw order with ballot prefix counts.
-
-// 64-bit rank key: the gain in an order-preserving unsigned encoding (void draws and NaN as -inf,
-// -0 as +0) above the complement of the draw index, so that a larger key ranks first and equal
-// gains go to the earlier draw.  Every real key exceeds 0, the key of an empty slot.
-__device__ __forceinline__ uint64_t rank_key(const int2 *__restrict__ cand,
-                                             const float *__restrict__ score, int i) {
-  float g = -INFINITY;
-  const int2 ab = cand[i];
-  if (ab.x >= 0 && ab.y >= 0) {
-    const float s = score[ab.x] + score[ab.y];
-    g = s == s ? s : -INFINITY;
-    if (g == 0.0f) g = 0.0f;
+// Keys and workgroup lists of the first min(K, kRankMax) candidates (k_propose does the same when
+// it draws them).
+__global__ void __launch_bounds__(256)
+k_rank_blocks(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
+              uint64_t *__restrict__ keys, uint64_t *__restrict__ lists) {
+  __shared__ uint64_t sl[2][64];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool ranked = i < min(K, kRankMax);
+  uint64_t key = 0ull;
+  if (ranked) {
+    const int2 ab = cand[i];
+    key = rank_key(ab.x, ab.y, i, score);
+    keys[i] = key;
   }
-  const uint32_t u = __float_as_uint(g);
-  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-  return ((uint64_t)o << 32) | (uint64_t)(~(uint32_t)i);
+  block_top64(key, sl, lists + (size_t)blockIdx.x * kRankTop);
 }
 
-// Value of lane (lane ^ S): DPP for S = 1, 2 (quad permutations) and 8 (row rotation by 8),
-// ds_bpermute otherwise.
-template <int S>
-__device__ __forceinline__ uint32_t xor_lane32(uint32_t v) {
-  if constexpr (S == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-  else if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-  else if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
-  else return (uint32_t)__shfl_xor((int)v, S);
-}
-
-template <int S>
-__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
-  return ((uint64_t)xor_lane32<S>((uint32_t)(v >> 32)) << 32) | xor_lane32<S>((uint32_t)v);
-}
-
-__device__ __forceinline__ uint64_t lane64(uint64_t v, int src) {
-  return ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src) << 32) |
-         (uint32_t)__shfl((int)(uint32_t)v, src);
-}
-
-// Compare-exchange steps STRIDE, STRIDE/2, ..., 1 of the bitonic network at block size SIZE over
-// NC independent columns (one key per lane each); blocks with (lane & SIZE) == 0 end descending.
-template <int SIZE, int STRIDE, int NC>
-__device__ __forceinline__ void bitonic_steps(uint64_t (&k)[NC], int lane) {
-  if constexpr (STRIDE > 0) {
-    const bool take_max = ((lane & STRIDE) == 0) == ((lane & SIZE) == 0);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const uint64_t p = xor_lane64<STRIDE>(k[c]);
-      k[c] = (take_max == (p > k[c])) ? p : k[c];
-    }
-    bitonic_steps<SIZE, STRIDE / 2, NC>(k, lane);
-  }
-}
-
-// Sort each column descending across the 64 lanes.
-template <int SIZE, int NC>
-__device__ __forceinline__ void wave_sort_desc(uint64_t (&k)[NC], int lane) {
-  if constexpr (SIZE <= 64) {
-    bitonic_steps<SIZE, SIZE / 2, NC>(k, lane);
-    wave_sort_desc<SIZE * 2, NC>(k, lane);
-  }
-}
-
-// Best 64 of two descending columns, descending: lane l takes the larger of a[l] and b[63 - l]
-// (a bitonic sequence holding the 64 largest), then a bitonic merge.
-__device__ __forceinline__ uint64_t merge_top64(uint64_t a, uint64_t b_rev, int lane) {
-  uint64_t m[1] = {a > b_rev ? a : b_rev};
-  bitonic_steps<64, 32, 1>(m, lane);
-  return m[0];
-}
-
+// Evaluation order from the workgroup lists and keys: the lists are merged pairwise (waves
+// [h, n) hand theirs to waves [0, h) through LDS; two buffers alternate so that one barrier per
+// level suffices), then every other draw of [0, R) follows in draw order, then draws R..K-1.
 __global__ void __launch_bounds__(1024)
-k_rank(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
-       int32_t *__restrict__ order) {
-  static_assert(kRankMax == 4 * 1024 && kRankTop == 64, "k_rank: 4 keys per thread, 64 best");
+k_rank_merge(const uint64_t *__restrict__ lists, const uint64_t *__restrict__ keys, int K,
+             int32_t *__restrict__ order) {
+  static_assert(kRankMax == 4 * 1024 && kRankTop == 64, "k_rank_merge: 16 lists, 4 keys per thread");
   __shared__ uint64_t list[2][8][64];
   __shared__ int cnt[4][16];
   __shared__ uint64_t thr_s;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int R = min(K, kRankMax);
-  uint64_t own[4], k[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int i = j * 1024 + t;
-    own[j] = i < R ? rank_key(cand, score, i) : 0ull;
-    k[j] = own[j];
-  }
-  wave_sort_desc<2, 4>(k, lane);
-  // cross-lane reads stay outside conditional expressions: a lane shuffle evaluated under a
-  // partial execution mask reads nothing from the masked-off lanes
-  const uint64_t r1 = lane64(k[1], 63 - lane), r3 = lane64(k[3], 63 - lane);
-  uint64_t m2[2] = {k[0] > r1 ? k[0] : r1, k[2] > r3 ? k[2] : r3};
-  bitonic_steps<64, 32, 2>(m2, lane);
-  const uint64_t r = lane64(m2[1], 63 - lane);
-  uint64_t m = merge_top64(m2[0], r, lane);
-  // pairwise merges of the wave lists: waves [h, n) hand theirs to waves [0, h) through LDS;
-  // the two buffers alternate so one barrier per level suffices
+  const int R = min(K, kRankMax), nl = (R + 255) >> 8;
+  uint64_t m = w < nl ? lists[w * kRankTop + lane] : 0ull;
   int buf = 0;
 #pragma unroll
   for (int n = 16; n > 1; n >>= 1) {
@@ -383,7 +415,8 @@ k_rank(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int i = j * 1024 + t;
-    bal[j] = __ballot(i < R && own[j] < thr);
+    const uint64_t own = i < R ? keys[i] : 0ull;
+    bal[j] = __ballot(i < R && own < thr);
     if (lane == 0) cnt[j][w] = __popcll(bal[j]);
   }
   __syncthreads();
@@ -405,10 +438,19 @@ k_rank(const int2 *__restrict__ cand, const float *__restrict__ score, int K,
   for (int i = R + t; i < K; i += 1024) order[i] = i;
 }
 
-hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL(k_rank, dim3(1), dim3(1024), 0, stream, cand, score, K, order);
+hipError_t launch_rank_merge(const uint64_t *lists, const uint64_t *keys, int K, int32_t *order,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_rank_merge, dim3(1), dim3(1024), 0, stream, lists, keys, K, order);
   return hipGetLastError();
+}
+
+hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
+                       uint64_t *keys, uint64_t *lists, hipStream_t stream) {
+  const int R = std::min(K, kRankMax);
+  hipLaunchKernelGGL(k_rank_blocks, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, cand,
+                     score, K, keys, lists);
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_rank_merge(lists, keys, K, order, stream);
 }
 
 // Copy of the step's candidates as (a, b) pairs.

@@ -161,7 +161,7 @@ struct lpf_ctx_s {
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
-  DevBuf ext, ext3, s2ext, s2acc, sext;
+  DevBuf ext, ext3, s2ext, s2acc, sext, rank_buf;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -197,7 +197,7 @@ struct lpf_anneal_s {
   double beta = 1.0, eps = 0.1;
   int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
   bool rank = false;               // evaluate learned draws by descending predicted gain
-  DevBuf scores, cw1, cw0, cwb, eS, eCtl, order;
+  DevBuf scores, cw1, cw0, cwb, eS, eCtl, order, rank_buf;
   DevBuf Tcur;             // the current step's temperature (device scalar)
   uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
   hipStream_t cap = nullptr;  // private stream for capturing runs of steps
@@ -623,11 +623,12 @@ int delta_chunks(int K) {
   return std::max(1, 2048 / groups);
 }
 
-// Candidates of the chain's current step into a->cand / U / slot (learned weights first).
+// Candidates of the chain's current step into a->cand / U / slot (learned weights first); with
+// rank, learned draws also leave their rank keys and workgroup lists in a->rank_buf.
 lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
                            int64_t *S_acc = nullptr, StepCtl *ctl = nullptr,
                            const double *T_sched = nullptr, int64_t T_base = 0, double T = 0.0,
-                           double *T_cur = nullptr) {
+                           double *T_cur = nullptr, bool rank = false) {
   hipError_t e;
   const int64_t N = (int64_t)a->W * a->H;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
@@ -635,6 +636,8 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
       (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess)
     return hip_fail(e, "anneal: candidate scratch");
   const double *cw1 = nullptr, *cw0 = nullptr;
+  const float *rank_score = nullptr;
+  uint64_t *rank_keys = nullptr;
   int draw = proposal;
   if (proposal == LPF_PROP_LEARNED) {
     // beta = 0 draws exactly the uniform candidates; the scores then only rank them
@@ -665,10 +668,17 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
     } else {
       draw = LPF_PROP_UNIFORM;
     }
+    if (rank) {
+      if ((e = a->rank_buf.ensure(kRankScratch)) != hipSuccess)
+        return hip_fail(e, "anneal: rank scratch");
+      rank_score = a->net ? (const float *)a->scores.p : a->scores_ext;
+      rank_keys = (uint64_t *)a->rank_buf.p;
+    }
   }
   if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, draw, cw1, cw0, a->eps,
                           (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, S_acc, ctl,
-                          T_sched, T_base, T, T_cur, s)) != hipSuccess)
+                          T_sched, T_base, T, T_cur, rank_score, rank_keys,
+                          rank_keys ? rank_keys + kRankMax : nullptr, s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
   return LPF_OK;
 }
@@ -915,6 +925,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
     c->s2ext.release();
     c->s2acc.release();
     c->sext.release();
+    c->rank_buf.release();
   }
   delete c;
 }
@@ -1435,7 +1446,8 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
       (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
       (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess ||
       (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
-      (e = a->order.ensure(sizeof(int32_t) * (size_t)K)) != hipSuccess)
+      (e = a->order.ensure(sizeof(int32_t) * (size_t)K)) != hipSuccess ||
+      (e = a->rank_buf.ensure(kRankScratch)) != hipSuccess)
     return hip_fail(e, "anneal: scratch");
   if (proposal == LPF_PROP_LEARNED) {  // the draw's buffers, so that it allocates nothing
     const int64_t N = (int64_t)a->W * a->H;
@@ -1490,14 +1502,15 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
                         lpf_step_result *out, int64_t out_base, hipStream_t s) {
   hipError_t e;
   lpf_status st;
+  const bool rank = proposal == LPF_PROP_LEARNED && a->rank;
   if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p,
-                            T_sched, T_base, T, (double *)a->Tcur.p)) != LPF_OK)
+                            T_sched, T_base, T, (double *)a->Tcur.p, rank)) != LPF_OK)
     return st;
   L.order = nullptr;
-  if (proposal == LPF_PROP_LEARNED && a->rank) {
-    const float *sc = a->net ? (const float *)a->scores.p : a->scores_ext;
+  if (rank) {
+    const uint64_t *keys = (const uint64_t *)a->rank_buf.p;
     int32_t *ord = (int32_t *)a->order.p;
-    if ((e = launch_rank((const int2 *)a->cand.p, sc, K, ord, s)) != hipSuccess)
+    if ((e = launch_rank_merge(keys + kRankMax, keys, K, ord, s)) != hipSuccess)
       return hip_fail(e, "anneal: ranking");
     L.order = ord;
   }
@@ -1649,6 +1662,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->cw0.release();
     a->cwb.release();
     a->order.release();
+    a->rank_buf.release();
     a->eS.release();
     a->eCtl.release();
     a->Tcur.release();
@@ -2037,8 +2051,11 @@ lpf_status lpf_rank(lpf_ctx c, const int32_t *cand, const float *score, int K, i
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
   if (!g.ok) return fail(LPF_E_DEVICE, "lpf_rank: cannot select the context's device");
-  const hipError_t e =
-      launch_rank(reinterpret_cast<const int2 *>(cand), score, K, order, (hipStream_t)stream);
+  hipError_t e = c->rank_buf.ensure(kRankScratch);
+  if (e != hipSuccess) return hip_fail(e, "lpf_rank: scratch");
+  uint64_t *keys = (uint64_t *)c->rank_buf.p;
+  e = launch_rank(reinterpret_cast<const int2 *>(cand), score, K, order, keys, keys + kRankMax,
+                  (hipStream_t)stream);
   return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_rank");
 }
 

@@ -173,25 +173,33 @@ struct StepResult {
   double de, e;
   uint64_t step;
 };
+// Evaluation order of a step's K candidates: the kRankTop draws with the highest predicted gain
+// score[a] + score[b] among the first min(K, kRankMax) (best first, ties by draw index, void
+// draws lowest), then every other draw in draw order.  Rank scratch: kRankMax keys and
+// kRankMax / 256 lists of kRankTop keys (uint64).
+constexpr int kRankMax = 4096;
+constexpr int kRankTop = 64;
+constexpr size_t kRankScratch = sizeof(uint64_t) * (kRankMax + (kRankMax / 256) * kRankTop);
 // S_acc, ctl: when given, also zeroed for the step (the step's reset folded into the draw).
 // T_cur (when given) receives the step's temperature: T_sched[step - T_base] when T_sched is
-// given, else T.
+// given, else T.  rank_score (when given): the draws' rank keys go to rank_keys and each
+// 256-draw workgroup's best kRankTop to rank_lists, for launch_rank_merge.
 hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
                           int K, int proposal, const double *cw1, const double *cw0, double eps,
                           int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
                           const double *T_sched, int64_t T_base, double T, double *T_cur,
+                          const float *rank_score, uint64_t *rank_keys, uint64_t *rank_lists,
                           hipStream_t stream);
 // scratch: 4 * ceil(W*H / 1024) doubles
 hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
                                 double *cw0, int64_t N, double *scratch, hipStream_t stream);
 hipError_t launch_copy_cand(const int2 *cand, int K, int32_t *out, hipStream_t stream);
-// Evaluation order of a step's K candidates: the kRankTop draws with the highest predicted gain
-// score[a] + score[b] among the first min(K, kRankMax) (best first, ties by draw index, void
-// draws lowest), then every other draw in draw order.  One workgroup; no scratch.
-constexpr int kRankMax = 4096;
-constexpr int kRankTop = 64;
+// Evaluation order from the keys and lists that launch_propose (or launch_rank) wrote.
+hipError_t launch_rank_merge(const uint64_t *lists, const uint64_t *keys, int K, int32_t *order,
+                             hipStream_t stream);
+// Evaluation order of given candidates (keys and lists: the rank scratch).
 hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *order,
-                       hipStream_t stream);
+                       uint64_t *keys, uint64_t *lists, hipStream_t stream);
 // Exact energy change of K given interchanges on a chain's state: de[i] = S_i / (N^2 Nt).
 hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 // Placement-state records: build ones and records from the packed image, and apply the
