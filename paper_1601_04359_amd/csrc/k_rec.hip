@@ -299,15 +299,12 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
   }
 }
 
-// The accepted interchange (ctl->ks; a now in phase 0, b in phase 1) applied to ones and the
-// records.  One lane per (side, path pixel j): placement x = (a or b) - p_j of vector v(j).
+// The accepted interchange ks (a now in phase 0, b in phase 1) applied to ones and the records,
+// lane t of 2 Mc: one per (side, path pixel j), placement x = (a or b) - p_j of vector v(j).
 template <unsigned MASK>
-__global__ void __launch_bounds__(256)
-k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__ cand) {
+__device__ __forceinline__ void rec_update_lane(const RecGeo &g, const int2 *__restrict__ cand,
+                                                int ks, int64_t t) {
   using P = Planes<MASK>;
-  const int ks = ctl->ks;
-  if (ks < 0) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * (int64_t)g.Mc) return;
   const int64_t N = (int64_t)g.W * g.H;
   const int side = t >= g.Mc;
@@ -346,6 +343,26 @@ k_rec_update(RecGeo g, const StepCtl *__restrict__ ctl, const int2 *__restrict__
   }
 }
 
+// End of a step under the records method: workgroups 0 .. nupd - 1 apply the accepted
+// interchange to ones and records (rec_update_lane), workgroup nupd does the step's upkeep
+// (step_apply).  Each workgroup takes the step's decision itself (ctl->ks, or the same scan of the
+// last round), so one launch replaces the upkeep kernel followed by the update kernel: the upkeep
+// touches counts, image bits, pixel lists and energy, none of which the update reads.
+template <unsigned MASK>
+__global__ void __launch_bounds__(256)
+k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
+  __shared__ int s_ks0, s_first;
+  if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
+  __syncthreads();
+  const int ks0 = s_ks0;
+  const int ks = step_choice(f, ks0, &s_first);
+  if ((int)blockIdx.x == nupd) {
+    step_apply(f, ks, ks0 < 0 && ks >= 0);
+    return;
+  }
+  if (ks >= 0) rec_update_lane<MASK>(g, f.cand, ks, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 #define LPF_REC_MASK_SWITCH(mask, CALL) \
   switch (mask) {                             \
     case 1u: CALL(1u); break;                 \
@@ -366,12 +383,12 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_rec_update(const RecGeo &g, const StepCtl *ctl, const int2 *cand,
-                             hipStream_t stream) {
-  const dim3 grid((unsigned)((2 * (int64_t)g.Mc + 255) / 256));
-#define LPF_UPDATE(M) hipLaunchKernelGGL(k_rec_update<M>, grid, dim3(256), 0, stream, g, ctl, cand)
-  LPF_REC_MASK_SWITCH(g.mask, LPF_UPDATE)
-#undef LPF_UPDATE
+hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
+  const int nupd = (int)((2 * (int64_t)g.Mc + 255) / 256);
+#define LPF_END(M) \
+  hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
+  LPF_REC_MASK_SWITCH(g.mask, LPF_END)
+#undef LPF_END
   return hipGetLastError();
 }
 

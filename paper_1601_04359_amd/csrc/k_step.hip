@@ -128,81 +128,13 @@ k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
 
 // Step result, running energy, and the accepted interchange applied to counts, image and pixel
 // lists (one workgroup).
-__global__ void __launch_bounds__(1024)
-k_step_final(AnnealDev *__restrict__ st, StepCtl *__restrict__ ctl, int K,
-             const int2 *__restrict__ cand, const int2 *__restrict__ slot,
-             const int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k, int nterms, int64_t N,
-             int64_t Nt,
-             double *__restrict__ e_io, uint32_t *__restrict__ counts, uint64_t *__restrict__ bits,
-             int W, int32_t *__restrict__ k_sel, StepResult *__restrict__ out,
-             const int64_t *__restrict__ S_acc, const double *__restrict__ U,
-             const double *__restrict__ Tp, const int32_t *__restrict__ order, int li0, int lC,
-             int64_t out_base) {
-  // decision of the last round when no earlier round accepted
-  __shared__ int s_first;
-  const double T = *Tp;
-  // a run of steps writes its records at out[step - out_base]
-  if (out_base >= 0) out += (int64_t)st->step - out_base;
-  int ks = ctl->ks;
-  if (ks < 0 && lC > 0) {
-    if (threadIdx.x == 0) s_first = INT_MAX;
-    __syncthreads();
-    const double scale = (double)N * (double)N * (double)Nt;
-    for (int base = 0; base < lC; base += blockDim.x) {
-      const int kr = base + threadIdx.x;
-      if (kr < lC) {
-        const int k = order ? order[li0 + kr] : li0 + kr;
-        if (cand[k].x >= 0) {
-          const double de = (double)S_acc[k] / scale;
-          if (de <= 0.0 || U[k] < exp(-de / T)) atomicMin(&s_first, kr);
-        }
-      }
-      __syncthreads();
-      const int f = s_first;
-      __syncthreads();
-      if (f != INT_MAX) break;
-    }
-    if (s_first != INT_MAX) ks = order ? order[li0 + s_first] : li0 + s_first;
-    if (threadIdx.x == 0 && ks >= 0) {
-      ctl->ks = ks;
-      ctl->S = S_acc[ks];
-      ctl->done = 1;
-    }
-  }
-  if (ks >= 0)
-    for (int t = threadIdx.x; t < nterms; t += blockDim.x)
-      counts[t] = (uint32_t)((int32_t)counts[t] + (int32_t)dl[t * dl_t + ks * dl_k]);
-  if (threadIdx.x == 0) {
-    StepResult r;
-    r.step = st->step;
-    r.pad = 0;
-    if (ks >= 0) {
-      const double de = (double)S_acc[ks] / ((double)N * (double)N * (double)Nt);
-      const double e = *e_io + de;
-      *e_io = e;
-      const int a = cand[ks].x, b = cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
-      const int wpr = (W + 63) >> 6;
-      const int ay = a / W, ax = a - ay * W, by = b / W, bx = b - by * W;
-      bits[(size_t)ay * wpr + (ax >> 6)] &= ~(1ull << (ax & 63));
-      bits[(size_t)by * wpr + (bx >> 6)] |= 1ull << (bx & 63);
-      st->pos1[slot[ks].x] = b;
-      st->pos0[slot[ks].y] = a;
-      r.k = ks;
-      r.a = a;
-      r.b = b;
-      r.de = de;
-      r.e = e;
-    } else {
-      r.k = -1;
-      r.a = -1;
-      r.b = -1;
-      r.de = 0.0;
-      r.e = *e_io;
-    }
-    *out = r;
-    *k_sel = ks;
-    st->step += 1;
-  }
+__global__ void __launch_bounds__(1024) k_step_final(FinalArgs f) {
+  __shared__ int s_ks0, s_first;
+  if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
+  __syncthreads();
+  const int ks0 = s_ks0;
+  const int ks = step_choice(f, ks0, &s_first);
+  step_apply(f, ks, ks0 < 0 && ks >= 0);
 }
 
 namespace {
@@ -256,14 +188,34 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
-  const int li0 = nr ? L.rounds[nr - 1].k0 : 0, lC = nr ? L.rounds[nr - 1].C : 0;
-  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, L.st, L.ctl, L.K, L.cand,
-                     L.slot, L.dl, L.dl_t, L.dl_k, L.nterms, L.N, L.Nt, L.e, L.counts_rw,
-                     L.bits_rw, L.W, L.k_sel, L.out, L.S_acc, L.U, L.T, L.order, li0, lC,
-                     L.out_base);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (L.records && !L.s2) e = launch_rec_update(L.rg, L.ctl, L.cand, stream);
-  return e;
+  FinalArgs f;
+  f.st = L.st;
+  f.ctl = L.ctl;
+  f.cand = L.cand;
+  f.slot = L.slot;
+  f.dl = L.dl;
+  f.dl_t = L.dl_t;
+  f.dl_k = L.dl_k;
+  f.nterms = L.nterms;
+  f.N = L.N;
+  f.Nt = L.Nt;
+  f.e_io = L.e;
+  f.counts = L.counts_rw;
+  f.bits = L.bits_rw;
+  f.W = L.W;
+  f.k_sel = L.k_sel;
+  f.out = L.out;
+  f.S_acc = L.S_acc;
+  f.U = L.U;
+  f.Tp = L.T;
+  f.order = L.order;
+  f.li0 = nr ? L.rounds[nr - 1].k0 : 0;
+  f.lC = nr ? L.rounds[nr - 1].C : 0;
+  f.out_base = L.out_base;
+  // records: the upkeep and the update of ones and records share one launch
+  if (L.records && !L.s2) return launch_rec_step_end(L.rg, f, stream);
+  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, f);
+  return hipGetLastError();
 }
 
 __global__ void k_energy_sum(const int64_t *__restrict__ S_acc, int n, int64_t N, int64_t Nt,

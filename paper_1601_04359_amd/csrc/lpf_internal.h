@@ -173,6 +173,30 @@ struct StepResult {
   double de, e;
   uint64_t step;
 };
+// End of a step: the decision of the last round (when no earlier round accepted) and the state
+// upkeep (control block, counts += dL, image bits, pixel lists, energy, record, step counter).
+struct FinalArgs {
+  AnnealDev *st;
+  StepCtl *ctl;
+  const int2 *cand;
+  const int2 *slot;
+  const int16_t *dl;
+  int64_t dl_t, dl_k;
+  int nterms;
+  int64_t N, Nt;
+  double *e_io;
+  uint32_t *counts;
+  uint64_t *bits;
+  int W;
+  int32_t *k_sel;
+  StepResult *out;
+  const int64_t *S_acc;
+  const double *U;
+  const double *Tp;
+  const int32_t *order;
+  int li0, lC;         // the last round: evaluation positions li0 .. li0 + lC - 1
+  int64_t out_base;    // >= 0: the record goes to out[step - out_base]
+};
 // Evaluation order of a step's K candidates: the kRankTop draws with the highest predicted gain
 // score[a] + score[b] among the first min(K, kRankMax) (best first, ties by draw index, void
 // draws lowest), then every other draw in draw order.  Rank scratch: kRankMax keys and
@@ -202,11 +226,10 @@ hipError_t launch_rank(const int2 *cand, const float *score, int K, int32_t *ord
                        uint64_t *keys, uint64_t *lists, hipStream_t stream);
 // Exact energy change of K given interchanges on a chain's state: de[i] = S_i / (N^2 Nt).
 hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
-// Placement-state records: build ones and records from the packed image, and apply the
-// interchange accepted by the step (skipped on the device when none was).
+// Placement-state records: build ones and records from the packed image; end a step (its
+// decision and upkeep, and the accepted interchange applied to ones and records) in one launch.
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream);
-hipError_t launch_rec_update(const RecGeo &g, const StepCtl *ctl, const int2 *cand,
-                             hipStream_t stream);
+hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream);
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,

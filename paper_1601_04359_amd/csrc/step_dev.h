@@ -4,6 +4,7 @@
 // then applies the Metropolis test in draw order.
 #pragma once
 
+#include <limits.h>
 #include <math.h>
 
 #include "lpf_internal.h"
@@ -60,6 +61,79 @@ __device__ __forceinline__ bool prev_round_accepted(const int64_t *__restrict__ 
     ctl->done = 1;
   }
   return true;
+}
+
+// The step's accepted candidate when no earlier round accepted (ks0 < 0): the first candidate of
+// the last round, in evaluation order, that passes the Metropolis test, -1 when none.  Called by
+// every thread of a workgroup of any size; all get the same value.
+__device__ __forceinline__ int step_choice(const FinalArgs &f, int ks0, int *s_first) {
+  if (ks0 >= 0 || f.lC <= 0) return ks0;
+  if (threadIdx.x == 0) *s_first = INT_MAX;
+  __syncthreads();
+  const double T = *f.Tp;
+  const double scale = (double)f.N * (double)f.N * (double)f.Nt;
+  for (int base = 0; base < f.lC; base += blockDim.x) {
+    const int kr = base + threadIdx.x;
+    if (kr < f.lC) {
+      const int k = f.order ? f.order[f.li0 + kr] : f.li0 + kr;
+      if (f.cand[k].x >= 0) {
+        const double de = (double)f.S_acc[k] / scale;
+        if (de <= 0.0 || f.U[k] < exp(-de / T)) atomicMin(s_first, kr);
+      }
+    }
+    __syncthreads();
+    const int fst = *s_first;
+    __syncthreads();
+    if (fst != INT_MAX) break;
+  }
+  const int fst = *s_first;
+  return fst == INT_MAX ? -1 : (f.order ? f.order[f.li0 + fst] : f.li0 + fst);
+}
+
+// The step's upkeep by one workgroup, given its accepted candidate ks (or -1): the control block
+// when this step's decision was taken here (decided), counts += dL, image bits, pixel lists,
+// energy, the step's record and the step counter.
+__device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool decided) {
+  if (ks >= 0)
+    for (int t = threadIdx.x; t < f.nterms; t += blockDim.x)
+      f.counts[t] = (uint32_t)((int32_t)f.counts[t] + (int32_t)f.dl[t * f.dl_t + ks * f.dl_k]);
+  if (threadIdx.x != 0) return;
+  AnnealDev *st = f.st;
+  StepResult *out = f.out_base >= 0 ? f.out + ((int64_t)st->step - f.out_base) : f.out;
+  StepResult r;
+  r.step = st->step;
+  r.pad = 0;
+  if (ks >= 0) {
+    if (decided) {
+      f.ctl->ks = ks;
+      f.ctl->S = f.S_acc[ks];
+      f.ctl->done = 1;
+    }
+    const double de = (double)f.S_acc[ks] / ((double)f.N * (double)f.N * (double)f.Nt);
+    const double e = *f.e_io + de;
+    *f.e_io = e;
+    const int a = f.cand[ks].x, b = f.cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
+    const int W = f.W, wpr = (W + 63) >> 6;
+    const int ay = a / W, ax = a - ay * W, by = b / W, bx = b - by * W;
+    f.bits[(size_t)ay * wpr + (ax >> 6)] &= ~(1ull << (ax & 63));
+    f.bits[(size_t)by * wpr + (bx >> 6)] |= 1ull << (bx & 63);
+    st->pos1[f.slot[ks].x] = b;
+    st->pos0[f.slot[ks].y] = a;
+    r.k = ks;
+    r.a = a;
+    r.b = b;
+    r.de = de;
+    r.e = e;
+  } else {
+    r.k = -1;
+    r.a = -1;
+    r.b = -1;
+    r.de = 0.0;
+    r.e = *f.e_io;
+  }
+  *out = r;
+  *f.k_sel = ks;
+  st->step += 1;
 }
 
 // Energy sum of one term: dL (Nt (dL + 2L) - 2 N T); every partial sum of a candidate stays in
