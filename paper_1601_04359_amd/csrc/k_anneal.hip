@@ -14,42 +14,10 @@
 #include <limits.h>
 #include <math.h>
 
+#include "draw_dev.h"
 #include "lpf_internal.h"
 
 namespace lpf {
-
-// Philox-4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11).
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += W0;
-    k1 += W1;
-  }
-}
-
-__device__ __forceinline__ int bit_at(const uint64_t *__restrict__ bits, int wpr, int x, int y) {
-  return (int)((bits[(size_t)y * wpr + (x >> 6)] >> (x & 63)) & 1ull);
-}
-
-// A pixel with a periodic 4-neighbour of the other phase.
-__device__ __forceinline__ bool interfacial(const uint64_t *__restrict__ bits, int W, int H, int q) {
-  const int wpr = (W + 63) >> 6;
-  const int y = q / W, x = q - y * W;
-  const int v = bit_at(bits, wpr, x, y);
-  const int xl = x ? x - 1 : W - 1, xr = x + 1 == W ? 0 : x + 1;
-  const int yu = y ? y - 1 : H - 1, yd = y + 1 == H ? 0 : y + 1;
-  return bit_at(bits, wpr, xl, y) != v || bit_at(bits, wpr, xr, y) != v ||
-         bit_at(bits, wpr, x, yu) != v || bit_at(bits, wpr, x, yd) != v;
-}
 
 // Evaluation order of a step's candidates (learned ranking): the kRankTop draws with the highest
 // predicted gain score[a] + score[b] (fp32; void draws and NaN lowest; ties by draw index) among
@@ -142,70 +110,18 @@ __device__ __forceinline__ void block_top64(uint64_t key, uint64_t (*sl)[64],
   if (w == 0) list[lane] = merge_top64(m, sl[0][63 - lane], lane);
 }
 
-// Candidate k of the current step: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
-// proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void unless both pixels are
-// interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn with probability
-// proportional to the weights whose inclusive prefix sums are cw1 (over pos1) and b likewise
-// with cw0 (over pos0), by inversion of r0, r1.
-__device__ __forceinline__ int upper_index(const double *__restrict__ cw, int n, double u) {
-  int lo = 0, hi = n - 1;  // first i with cw[i] > u
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (cw[mid] > u) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
-}
-
-__global__ void __launch_bounds__(256)
-k_propose(const AnnealDev *__restrict__ st, const uint64_t *__restrict__ bits, int W, int H,
-          uint64_t seed, int K, int proposal, const double *__restrict__ cw1,
-          const double *__restrict__ cw0, double eps, int2 *__restrict__ cand,
-          double *__restrict__ U, int2 *__restrict__ slot, int64_t *__restrict__ S_acc,
-          StepCtl *__restrict__ ctl, const double *__restrict__ T_sched, int64_t T_base, double T,
-          double *__restrict__ T_cur, const float *__restrict__ rank_score,
-          uint64_t *__restrict__ rank_keys, uint64_t *__restrict__ rank_lists) {
+// Draws of a step (draw_dev.h), plus the learned ranking's keys and workgroup lists when
+// p.rank_score is given (the condition is workgroup-uniform).
+__global__ void __launch_bounds__(256) k_propose(ProposeArgs p) {
   __shared__ uint64_t sl[2][64];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ctl && k == 0) {  // the step's control block and energy sums start at zero
-    ctl->done = 0;
-    ctl->ks = -1;
-    ctl->S = 0;
-  }
-  if (T_cur && k == 0) *T_cur = T_sched ? T_sched[(int64_t)st->step - T_base] : T;
   int a = -1, b = -1;
-  if (k < K) {
-    if (S_acc) S_acc[k] = 0;
-    uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
-    philox4x64_10(c, seed, 0x6c7066ull);
-    const int n1 = st->n1, n0 = st->n0;
-    int ia, ib;
-    const double u3 = (double)(c[3] >> 11) * (1.0 / 9007199254740992.0);
-    if (proposal == 2 && !(u3 < eps)) {
-      const double ua = (double)(c[0] >> 11) * (1.0 / 9007199254740992.0) * cw1[n1 - 1];
-      const double ub = (double)(c[1] >> 11) * (1.0 / 9007199254740992.0) * cw0[n0 - 1];
-      ia = upper_index(cw1, n1, ua);
-      ib = upper_index(cw0, n0, ub);
-    } else {
-      ia = (int)(((c[0] >> 32) * (uint64_t)n1) >> 32);
-      ib = (int)(((c[1] >> 32) * (uint64_t)n0) >> 32);
-    }
-    a = st->pos1[ia];
-    b = st->pos0[ib];
-    if (proposal == 1 && !(interfacial(bits, W, H, a) && interfacial(bits, W, H, b))) {
-      a = -1;
-      b = -1;
-    }
-    cand[k] = make_int2(a, b);
-    slot[k] = make_int2(ia, ib);
-    U[k] = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
-  }
-  // learned ranking: this workgroup's keys and its best 64 (the condition is workgroup-uniform)
-  if (rank_score && (int)(blockIdx.x * blockDim.x) < min(K, kRankMax)) {
-    const bool ranked = k < min(K, kRankMax);
-    const uint64_t key = ranked ? rank_key(a, b, k, rank_score) : 0ull;
-    if (ranked) rank_keys[k] = key;
-    block_top64(key, sl, rank_lists + (size_t)blockIdx.x * kRankTop);
+  propose_draw(p, k, a, b);
+  if (p.rank_score && (int)(blockIdx.x * blockDim.x) < min(p.K, kRankMax)) {
+    const bool ranked = k < min(p.K, kRankMax);
+    const uint64_t key = ranked ? rank_key(a, b, k, p.rank_score) : 0ull;
+    if (ranked) p.rank_keys[k] = key;
+    block_top64(key, sl, p.rank_lists + (size_t)blockIdx.x * kRankTop);
   }
 }
 
@@ -337,15 +253,8 @@ __global__ void k_lse(const uint32_t *__restrict__ counts, const uint32_t *__res
   *e = s / ((double)N * (double)N * (double)Nt * (double)Nt);
 }
 
-hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
-                          int K, int proposal, const double *cw1, const double *cw0, double eps,
-                          int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
-                          const double *T_sched, int64_t T_base, double T, double *T_cur,
-                          const float *rank_score, uint64_t *rank_keys, uint64_t *rank_lists,
-                          hipStream_t stream) {
-  hipLaunchKernelGGL(k_propose, dim3((K + 255) / 256), dim3(256), 0, stream, st, bits, W, H, seed,
-                     K, proposal, cw1, cw0, eps, cand, U, slot, S_acc, ctl, T_sched, T_base, T,
-                     T_cur, rank_score, rank_keys, rank_lists);
+hipError_t launch_propose(const ProposeArgs &p, hipStream_t stream) {
+  hipLaunchKernelGGL(k_propose, dim3((p.K + 255) / 256), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 

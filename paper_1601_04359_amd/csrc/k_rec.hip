@@ -15,6 +15,7 @@
 // both sums with a membership test on the digitised path.  After an accepted interchange the
 // ones field is updated on P_a and P_b, and record bits flip only where a placement's state
 // changed.
+#include "draw_dev.h"
 #include "step_dev.h"
 
 namespace lpf {
@@ -253,13 +254,14 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
             const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
             int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
             StepCtl *__restrict__ ctl, const int32_t *__restrict__ order,
-            const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
+            const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC,
+            const int64_t *__restrict__ S0) {
   using P = Planes<MASK>;
   __shared__ long long s_part[4];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
-                          ctl, &s_prev))
+  if (prev_round_accepted(S_acc, S0, cand, U, order, pi0, pC, Tp,
+                          (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool vin = v < g.nv;
@@ -296,6 +298,61 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
       add_acc(&S_acc[k], tot);
     }
     __syncthreads();
+  }
+}
+
+// Round 0 of a step in the launch of the step's draws (unranked draws, K > 64): workgroups
+// [0, nprop) are the draws of k_propose (propose_draw); workgroup nprop + kr * nvb + vb takes
+// vector block vb of draw kr < C0, which it draws again itself (the same counter gives the same
+// draw, so it does not wait for the draw blocks), and adds its block sum into S0[kr] instead of
+// S_acc, which the draw blocks are zeroing.  S0 is zero at the start of every step (cleared at
+// allocation and by the end of each step); round 1 reads it when it decides round 0.
+template <unsigned MASK>
+__global__ void __launch_bounds__(256)
+k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__restrict__ counts,
+                  const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
+                  int64_t *__restrict__ S0, int16_t *__restrict__ dl, int64_t dl_t,
+                  int64_t dl_k) {
+  using P = Planes<MASK>;
+  __shared__ long long s_part[4];
+  if ((int)blockIdx.x < nprop) {
+    int a, b;
+    propose_draw(p, (int)(blockIdx.x * blockDim.x + threadIdx.x), a, b);
+    return;
+  }
+  const int nvb = (g.nv + 255) >> 8;
+  const int bi = (int)blockIdx.x - nprop, kr = bi / nvb, vb = bi - kr * nvb;
+  if (kr >= C0) return;
+  const int v = vb * 256 + (int)threadIdx.x;
+  const bool vin = v < g.nv;
+  const int4 m = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < P::nph; ++q)
+    if (vin) {
+      Lc[q] = counts[(size_t)q * g.nv + v];
+      Tc[q] = target[(size_t)q * g.nv + v];
+    }
+  int a, b, ia, ib;
+  double u;
+  draw_candidate(p, kr, a, b, ia, ib, u);
+  int d[2];
+  rec_delta<MASK, true>(g, p.bits, a, b, v, m, d);
+  int64_t S = 0;
+  if (vin) {
+#pragma unroll
+    for (int q = 0; q < P::nph; ++q) {
+      S += energy_term(d[q], Lc[q], Tc[q], N, Nt);
+      dl[(int64_t)((size_t)q * g.nv + v) * dl_t + (int64_t)kr * dl_k] = (int16_t)d[q];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_part[w];
+    add_acc(&S0[kr], tot);
   }
 }
 
@@ -396,10 +453,12 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
                             hipStream_t stream) {
   const dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
   int16_t *dl = decide ? L.dl : nullptr;
+  // round 1 after a round 0 evaluated with the draws: round 0's sums are in S0
+  const int64_t *S0 = decide && L.fuse_draw && r.pC > 0 ? L.S0 : nullptr;
 #define LPF_ROUND_O(M, O)                                                                      \
   hipLaunchKernelGGL((k_rec_round<M, O>), grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K, \
                      r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k,   \
-                     L.ctl, L.order, L.U, L.T, decide ? r.pi0 : 0, decide ? r.pC : 0)
+                     L.ctl, L.order, L.U, L.T, decide ? r.pi0 : 0, decide ? r.pC : 0, S0)
 #define LPF_ROUND(M)               \
   if (L.ordered)                   \
     LPF_ROUND_O(M, true);          \
@@ -408,6 +467,18 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
   LPF_REC_MASK_SWITCH(L.rg.mask, LPF_ROUND)
 #undef LPF_ROUND
 #undef LPF_ROUND_O
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_draw_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream) {
+  const int nprop = (L.draw.K + 255) / 256;
+  const int nvb = (L.rg.nv + 255) / 256;
+  const unsigned grid = (unsigned)(nprop + nvb * r.C);
+#define LPF_R0(M)                                                                            \
+  hipLaunchKernelGGL(k_rec_draw_round0<M>, dim3(grid), dim3(256), 0, stream, L.rg, L.draw, nprop, \
+                     r.C, L.counts, L.target, L.N, L.Nt, L.S0, L.dl, L.dl_t, L.dl_k)
+  LPF_REC_MASK_SWITCH(L.rg.mask, LPF_R0)
+#undef LPF_R0
   return hipGetLastError();
 }
 

@@ -283,8 +283,8 @@ k_s2_round(const uint64_t *__restrict__ bits, int W, int H, const int2 *__restri
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
-                          ctl, &s_prev))
+  if (prev_round_accepted(S_acc, nullptr, cand, U, order, pi0, pC, Tp,
+                          (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;
   const int wpr32 = 2 * ((W + 63) >> 6);
   const uint32_t *img = reinterpret_cast<const uint32_t *>(bits);

@@ -43,8 +43,8 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
   if (ctl->done) return;  // an earlier round accepted
-  if (prev_round_accepted(S_acc, cand, U, order, pi0, pC, Tp, (double)N * (double)N * (double)Nt,
-                          ctl, &s_prev))
+  if (prev_round_accepted(S_acc, nullptr, cand, U, order, pi0, pC, Tp,
+                          (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;
   const int kr = blockIdx.x * blockDim.x + threadIdx.x;  // index within the round
   const int i = k0 + kr;                                 // evaluation position
@@ -177,9 +177,12 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
       r.pi0 = L.rounds[0].k0;
       r.pC = L.rounds[0].C;
     }
-    e = L.s2        ? launch_s2_round(L, r, true, stream)
-        : L.records ? launch_rec_round(L, r, true, stream)
-                    : launch_round_recount(L, r, true, stream);
+    if (j == 0 && L.fuse_draw)
+      e = launch_rec_draw_round0(L, r, stream);
+    else
+      e = L.s2        ? launch_s2_round(L, r, true, stream)
+          : L.records ? launch_rec_round(L, r, true, stream)
+                      : launch_round_recount(L, r, true, stream);
     if (e != hipSuccess) return e;
     const bool decided_later = j == nr - 1 || (j == 0 && L.rounds[0].C <= 64);
     if (!decided_later) {
@@ -212,6 +215,7 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
   f.li0 = nr ? L.rounds[nr - 1].k0 : 0;
   f.lC = nr ? L.rounds[nr - 1].C : 0;
   f.out_base = L.out_base;
+  f.S0 = L.fuse_draw ? L.S0 : nullptr;
   // records: the upkeep and the update of ones and records share one launch
   if (L.records && !L.s2) return launch_rec_step_end(L.rg, f, stream);
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, f);

@@ -68,6 +68,15 @@ struct DevBuf {
   }
 };
 
+// A buffer that is filled with zeros on stream s when (re)allocated; never called while s is
+// being captured.
+hipError_t ensure_zeroed(DevBuf &b, size_t n, hipStream_t s) {
+  if (n <= b.bytes) return hipSuccess;
+  hipError_t e = b.ensure(n);
+  if (e == hipSuccess) e = hipMemsetAsync(b.p, 0, n, s);
+  return e;
+}
+
 struct FullPlan {
   FullShape sh{};
   VecDesc *vecs = nullptr;   // device, bin order
@@ -197,7 +206,7 @@ struct lpf_anneal_s {
   double beta = 1.0, eps = 0.1;
   int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
   bool rank = false;               // evaluate learned draws by descending predicted gain
-  DevBuf scores, cw1, cw0, cwb, eS, eCtl, order, rank_buf;
+  DevBuf scores, cw1, cw0, cwb, eS, eCtl, order, rank_buf, S0;
   DevBuf Tcur;             // the current step's temperature (device scalar)
   uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
   hipStream_t cap = nullptr;  // private stream for capturing runs of steps
@@ -624,11 +633,14 @@ int delta_chunks(int K) {
 }
 
 // Candidates of the chain's current step into a->cand / U / slot (learned weights first); with
-// rank, learned draws also leave their rank keys and workgroup lists in a->rank_buf.
+// rank, learned draws also leave their rank keys and workgroup lists in a->rank_buf.  With defer,
+// the draws' arguments go to *defer for a launch that also evaluates round 0, and nothing but the
+// learned weights is launched here.
 lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
                            int64_t *S_acc = nullptr, StepCtl *ctl = nullptr,
                            const double *T_sched = nullptr, int64_t T_base = 0, double T = 0.0,
-                           double *T_cur = nullptr, bool rank = false) {
+                           double *T_cur = nullptr, bool rank = false,
+                           ProposeArgs *defer = nullptr) {
   hipError_t e;
   const int64_t N = (int64_t)a->W * a->H;
   if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
@@ -675,10 +687,34 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
       rank_keys = (uint64_t *)a->rank_buf.p;
     }
   }
-  if ((e = launch_propose(a->dev, a->bits, a->W, a->H, a->seed, K, draw, cw1, cw0, a->eps,
-                          (int2 *)a->cand.p, (double *)a->U.p, (int2 *)a->slot.p, S_acc, ctl,
-                          T_sched, T_base, T, T_cur, rank_score, rank_keys,
-                          rank_keys ? rank_keys + kRankMax : nullptr, s)) != hipSuccess)
+  ProposeArgs p;
+  p.st = a->dev;
+  p.bits = a->bits;
+  p.W = a->W;
+  p.H = a->H;
+  p.seed = a->seed;
+  p.K = K;
+  p.proposal = draw;
+  p.cw1 = cw1;
+  p.cw0 = cw0;
+  p.eps = a->eps;
+  p.cand = (int2 *)a->cand.p;
+  p.U = (double *)a->U.p;
+  p.slot = (int2 *)a->slot.p;
+  p.S_acc = S_acc;
+  p.ctl = ctl;
+  p.T_sched = T_sched;
+  p.T_base = T_base;
+  p.T = T;
+  p.T_cur = T_cur;
+  p.rank_score = rank_score;
+  p.rank_keys = rank_keys;
+  p.rank_lists = rank_keys ? rank_keys + kRankMax : nullptr;
+  if (defer) {
+    *defer = p;
+    return LPF_OK;
+  }
+  if ((e = launch_propose(p, s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
   return LPF_OK;
 }
@@ -1447,7 +1483,8 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
       (e = a->ksel.ensure(sizeof(int32_t))) != hipSuccess ||
       (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
       (e = a->order.ensure(sizeof(int32_t) * (size_t)K)) != hipSuccess ||
-      (e = a->rank_buf.ensure(kRankScratch)) != hipSuccess)
+      (e = a->rank_buf.ensure(kRankScratch)) != hipSuccess ||
+      (e = ensure_zeroed(a->S0, sizeof(int64_t) * 64, s)) != hipSuccess)
     return hip_fail(e, "anneal: scratch");
   if (proposal == LPF_PROP_LEARNED) {  // the draw's buffers, so that it allocates nothing
     const int64_t N = (int64_t)a->W * a->H;
@@ -1503,8 +1540,12 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
   hipError_t e;
   lpf_status st;
   const bool rank = proposal == LPF_PROP_LEARNED && a->rank;
+  // records method, unranked: the draws and round 0 share one launch
+  L.fuse_draw = rec && !rank && L.rounds.size() >= 2 && L.rounds[0].C == 64;
+  L.S0 = (int64_t *)a->S0.p;
   if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p,
-                            T_sched, T_base, T, (double *)a->Tcur.p, rank)) != LPF_OK)
+                            T_sched, T_base, T, (double *)a->Tcur.p, rank,
+                            L.fuse_draw ? &L.draw : nullptr)) != LPF_OK)
     return st;
   L.order = nullptr;
   if (rank) {
@@ -1663,6 +1704,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->cwb.release();
     a->order.release();
     a->rank_buf.release();
+    a->S0.release();
     a->eS.release();
     a->eCtl.release();
     a->Tcur.release();

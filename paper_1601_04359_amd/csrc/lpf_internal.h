@@ -117,6 +117,32 @@ struct RecGeo {
   const uint64_t *sample;
 };
 
+struct AnnealDev;
+// Arguments of a step's candidate draws (draw_dev.h).  S_acc, ctl: when given, also zeroed for
+// the step (the step's reset folded into the draw).  T_cur (when given) receives the step's
+// temperature: T_sched[step - T_base] when T_sched is given, else T.  rank_score (when given):
+// the draws' rank keys go to rank_keys and each 256-draw workgroup's best kRankTop to
+// rank_lists, for launch_rank_merge.
+struct ProposeArgs {
+  const AnnealDev *st;
+  const uint64_t *bits;
+  int W, H;
+  uint64_t seed;
+  int K, proposal;
+  const double *cw1, *cw0;
+  double eps;
+  int2 *cand;
+  double *U;
+  int2 *slot;
+  int64_t *S_acc;
+  StepCtl *ctl;
+  const double *T_sched;
+  int64_t T_base;
+  double T;
+  double *T_cur;
+  const float *rank_score;
+  uint64_t *rank_keys, *rank_lists;
+};
 struct StepLaunch {
   bool s2;                   // descriptor: two-point probability (k_s2.hip), else lineal path
   const int32_t *s2vec;      // S2: canonical vectors, (dx & 0xffff) | (dy << 16)
@@ -153,6 +179,11 @@ struct StepLaunch {
   int32_t *k_sel;
   struct StepResult *out;
   bool use_lds;
+  // records method, unranked draws, K > 64: round 0 draws its own candidates in the launch of
+  // the draws (draw) and adds its energy sums into S0 (64 entries, zero at the start of a step)
+  bool fuse_draw;
+  ProposeArgs draw;
+  int64_t *S0;
 };
 
 hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
@@ -196,6 +227,7 @@ struct FinalArgs {
   const int32_t *order;
   int li0, lC;         // the last round: evaluation positions li0 .. li0 + lC - 1
   int64_t out_base;    // >= 0: the record goes to out[step - out_base]
+  int64_t *S0;         // when given: round 0's sums of a fused round 0, cleared here
 };
 // Evaluation order of a step's K candidates: the kRankTop draws with the highest predicted gain
 // score[a] + score[b] among the first min(K, kRankMax) (best first, ties by draw index, void
@@ -204,16 +236,7 @@ struct FinalArgs {
 constexpr int kRankMax = 4096;
 constexpr int kRankTop = 64;
 constexpr size_t kRankScratch = sizeof(uint64_t) * (kRankMax + (kRankMax / 256) * kRankTop);
-// S_acc, ctl: when given, also zeroed for the step (the step's reset folded into the draw).
-// T_cur (when given) receives the step's temperature: T_sched[step - T_base] when T_sched is
-// given, else T.  rank_score (when given): the draws' rank keys go to rank_keys and each
-// 256-draw workgroup's best kRankTop to rank_lists, for launch_rank_merge.
-hipError_t launch_propose(const AnnealDev *st, const uint64_t *bits, int W, int H, uint64_t seed,
-                          int K, int proposal, const double *cw1, const double *cw0, double eps,
-                          int2 *cand, double *U, int2 *slot, int64_t *S_acc, StepCtl *ctl,
-                          const double *T_sched, int64_t T_base, double T, double *T_cur,
-                          const float *rank_score, uint64_t *rank_keys, uint64_t *rank_lists,
-                          hipStream_t stream);
+hipError_t launch_propose(const ProposeArgs &p, hipStream_t stream);
 // scratch: 4 * ceil(W*H / 1024) doubles
 hipError_t launch_learn_weights(const AnnealDev *st, const float *score, double beta, double *cw1,
                                 double *cw0, int64_t N, double *scratch, hipStream_t stream);
@@ -232,6 +255,8 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream);
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream);
+// Round 0 (r.C <= 64 candidates) together with the step's draws L.draw (L.fuse_draw).
+hipError_t launch_rec_draw_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream);
 hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,

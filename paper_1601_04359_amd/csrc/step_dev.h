@@ -15,10 +15,18 @@ __device__ __forceinline__ void add_acc(int64_t *p, int64_t v) {
   if (v != 0) atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Energy sum of the candidate at round slot kr: S_acc[k], or S0[kr] for a round 0 that was
+// evaluated in the launch of the draws (which zero S_acc meanwhile).
+__device__ __forceinline__ int64_t round_sum(const int64_t *__restrict__ S_acc,
+                                             const int64_t *__restrict__ S0, int kr, int k) {
+  return S0 ? S0[kr] : S_acc[k];
+}
+
 // First accepted evaluation position among i0 .. i0 + C - 1 (C <= 64), tested by the calling
 // wave, one candidate per lane (accept iff de <= 0 or U < exp(-de / T)); every lane gets the
 // answer, -1 when none.
 __device__ __forceinline__ int wave_first_accepted(const int64_t *__restrict__ S_acc,
+                                                   const int64_t *__restrict__ S0,
                                                    const int2 *__restrict__ cand,
                                                    const double *__restrict__ U,
                                                    const int32_t *__restrict__ order, int i0, int C,
@@ -28,7 +36,7 @@ __device__ __forceinline__ int wave_first_accepted(const int64_t *__restrict__ S
   if (lane < C) {
     const int k = order ? order[i0 + lane] : i0 + lane;
     if (cand[k].x >= 0) {
-      const double de = (double)S_acc[k] / scale;
+      const double de = (double)round_sum(S_acc, S0, lane, k) / scale;
       acc = de <= 0.0 || U[k] < exp(-de / T);
     }
   }
@@ -37,9 +45,11 @@ __device__ __forceinline__ int wave_first_accepted(const int64_t *__restrict__ S
 }
 
 // Start of a round that also decides the previous round (pC > 0 candidates at positions pi0..):
-// every workgroup evaluates that decision; when it accepted, workgroup (0, 0) records it and all
-// workgroups return true (skip the round).
-__device__ __forceinline__ bool prev_round_accepted(const int64_t *__restrict__ S_acc,
+// every workgroup evaluates that decision; when it accepted, workgroup (0, 0) records it (and
+// copies its energy sum from S0 to S_acc when given) and all workgroups return true (skip the
+// round).
+__device__ __forceinline__ bool prev_round_accepted(int64_t *__restrict__ S_acc,
+                                                   const int64_t *__restrict__ S0,
                                                    const int2 *__restrict__ cand,
                                                    const double *__restrict__ U,
                                                    const int32_t *__restrict__ order, int pi0,
@@ -48,7 +58,7 @@ __device__ __forceinline__ bool prev_round_accepted(const int64_t *__restrict__ 
                                                    int *s_prev) {
   if (pC <= 0) return false;
   if (threadIdx.x < 64) {
-    const int f = wave_first_accepted(S_acc, cand, U, order, pi0, pC, *Tp, scale);
+    const int f = wave_first_accepted(S_acc, S0, cand, U, order, pi0, pC, *Tp, scale);
     if (threadIdx.x == 0) *s_prev = f;
   }
   __syncthreads();
@@ -56,8 +66,10 @@ __device__ __forceinline__ bool prev_round_accepted(const int64_t *__restrict__ 
   if (f < 0) return false;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     const int ks = order ? order[f] : f;
+    const int64_t S = round_sum(S_acc, S0, f - pi0, ks);
+    if (S0) S_acc[ks] = S;
     ctl->ks = ks;
-    ctl->S = S_acc[ks];
+    ctl->S = S;
     ctl->done = 1;
   }
   return true;
@@ -92,8 +104,9 @@ __device__ __forceinline__ int step_choice(const FinalArgs &f, int ks0, int *s_f
 
 // The step's upkeep by one workgroup, given its accepted candidate ks (or -1): the control block
 // when this step's decision was taken here (decided), counts += dL, image bits, pixel lists,
-// energy, the step's record and the step counter.
+// energy, the step's record and the step counter; S0 (when given) is cleared.
 __device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool decided) {
+  if (f.S0 && threadIdx.x < 64) f.S0[threadIdx.x] = 0;  // clear for the next step's round 0
   if (ks >= 0)
     for (int t = threadIdx.x; t < f.nterms; t += blockDim.x)
       f.counts[t] = (uint32_t)((int32_t)f.counts[t] + (int32_t)f.dl[t * f.dl_t + ks * f.dl_k]);
