@@ -16,6 +16,7 @@
 // ones field is updated on P_a and P_b, and record bits flip only where a placement's state
 // changed.
 #include "draw_dev.h"
+#include "rank_dev.h"
 #include "step_dev.h"
 
 namespace lpf {
@@ -356,6 +357,95 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
   }
 }
 
+// Round 0 of a ranked step together with the merge of the ranking (records method, K > 64,
+// after k_propose wrote the rank keys and workgroup lists): every workgroup merges the lists
+// itself (merge_lists16).  Workgroup 0 writes the evaluation order for the later rounds (the best
+// 64, then the other draws of [0, R) in draw order, then R .. K - 1); workgroup
+// 1 + kr * nvb + vb evaluates vector block vb of the kr-th best draw and adds its block sum into
+// S_acc, which k_propose zeroed.
+template <unsigned MASK>
+__global__ void __launch_bounds__(256)
+k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *__restrict__ keys,
+                  int K, int32_t *__restrict__ order, const uint64_t *__restrict__ bits,
+                  const int2 *__restrict__ cand, int C0, const uint32_t *__restrict__ counts,
+                  const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
+                  int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t,
+                  int64_t dl_k) {
+  using P = Planes<MASK>;
+  __shared__ uint64_t sl[2][64];
+  __shared__ uint64_t s_key;
+  __shared__ int s_cnt[4];
+  __shared__ long long s_part[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int R = min(K, kRankMax), T = min(R, kRankTop), nl = (R + 255) >> 8;
+  const uint64_t m = merge_lists16(lists, nl, sl);
+  if (blockIdx.x == 0) {
+    if (w == 0) {
+      if (lane < T) order[lane] = (int32_t)~(uint32_t)m;
+      if (lane == T - 1) s_key = m;  // the T-th best key: every other draw is below it
+    }
+    __syncthreads();
+    const uint64_t thr = s_key;
+    int base = T;
+    for (int c0 = 0; c0 < R; c0 += 256) {
+      const int i = c0 + (int)threadIdx.x;
+      const bool rest = i < R && keys[i] < thr;
+      const uint64_t bal = __ballot(rest);
+      if (lane == 0) s_cnt[w] = __popcll(bal);
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int v = 0; v < 4; ++v) {
+        before += v < w ? s_cnt[v] : 0;
+        total += s_cnt[v];
+      }
+      if (rest) {
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        order[base + before + below] = i;
+      }
+      base += total;
+      __syncthreads();
+    }
+    for (int i = R + (int)threadIdx.x; i < K; i += 256) order[i] = i;
+    return;
+  }
+  const int nvb = (g.nv + 255) >> 8;
+  const int bi = (int)blockIdx.x - 1, kr = bi / nvb, vb = bi - kr * nvb;
+  if (w == 0 && lane == kr) s_key = m;
+  __syncthreads();
+  if (kr >= C0 || kr >= T) return;
+  const int k = (int)~(uint32_t)s_key;  // draw index of the kr-th best
+  const int v = vb * 256 + (int)threadIdx.x;
+  const bool vin = v < g.nv;
+  const int4 mv = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < P::nph; ++q)
+    if (vin) {
+      Lc[q] = counts[(size_t)q * g.nv + v];
+      Tc[q] = target[(size_t)q * g.nv + v];
+    }
+  const int2 ab = cand[k];
+  int d[2];
+  rec_delta<MASK, true>(g, bits, ab.x, ab.y, v, mv, d);
+  int64_t S = 0;
+  if (vin) {
+#pragma unroll
+    for (int q = 0; q < P::nph; ++q) {
+      S += energy_term(d[q], Lc[q], Tc[q], N, Nt);
+      dl[(int64_t)((size_t)q * g.nv + v) * dl_t + (int64_t)k * dl_k] = (int16_t)d[q];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += s_part[q];
+    add_acc(&S_acc[k], tot);
+  }
+}
+
 // The accepted interchange ks (a now in phase 0, b in phase 1) applied to ones and the records,
 // lane t of 2 Mc: one per (side, path pixel j), placement x = (a or b) - p_j of vector v(j).
 template <unsigned MASK>
@@ -479,6 +569,18 @@ hipError_t launch_rec_draw_round0(const StepLaunch &L, const RoundPlan &r, hipSt
                      r.C, L.counts, L.target, L.N, L.Nt, L.S0, L.dl, L.dl_t, L.dl_k)
   LPF_REC_MASK_SWITCH(L.rg.mask, LPF_R0)
 #undef LPF_R0
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_rank_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream) {
+  const int nvb = (L.rg.nv + 255) / 256;
+  const unsigned grid = (unsigned)(1 + nvb * r.C);
+#define LPF_RR0(M)                                                                             \
+  hipLaunchKernelGGL(k_rec_rank_round0<M>, dim3(grid), dim3(256), 0, stream, L.rg,               \
+                     L.rank_keys + kRankMax, L.rank_keys, L.K, L.order_rw, L.bits, L.cand, r.C, \
+                     L.counts, L.target, L.N, L.Nt, L.S_acc, L.dl, L.dl_t, L.dl_k)
+  LPF_REC_MASK_SWITCH(L.rg.mask, LPF_RR0)
+#undef LPF_RR0
   return hipGetLastError();
 }
 

@@ -179,6 +179,8 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
     }
     if (j == 0 && L.fuse_draw)
       e = launch_rec_draw_round0(L, r, stream);
+    else if (j == 0 && L.fuse_rank)
+      e = launch_rec_rank_round0(L, r, stream);
     else
       e = L.s2        ? launch_s2_round(L, r, true, stream)
           : L.records ? launch_rec_round(L, r, true, stream)

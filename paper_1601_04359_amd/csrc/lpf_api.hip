@@ -1548,10 +1548,15 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
                             L.fuse_draw ? &L.draw : nullptr)) != LPF_OK)
     return st;
   L.order = nullptr;
+  L.fuse_rank = false;
   if (rank) {
     const uint64_t *keys = (const uint64_t *)a->rank_buf.p;
     int32_t *ord = (int32_t *)a->order.p;
-    if ((e = launch_rank_merge(keys + kRankMax, keys, K, ord, s)) != hipSuccess)
+    // records method: round 0 merges the ranking itself and writes the order for later rounds
+    L.fuse_rank = rec && L.rounds.size() >= 2 && L.rounds[0].C == 64;
+    L.rank_keys = keys;
+    L.order_rw = ord;
+    if (!L.fuse_rank && (e = launch_rank_merge(keys + kRankMax, keys, K, ord, s)) != hipSuccess)
       return hip_fail(e, "anneal: ranking");
     L.order = ord;
   }

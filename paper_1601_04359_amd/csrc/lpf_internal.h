@@ -184,6 +184,11 @@ struct StepLaunch {
   bool fuse_draw;
   ProposeArgs draw;
   int64_t *S0;
+  // records method, ranked draws, K > 64: every round-0 workgroup merges the ranking's workgroup
+  // lists (rank_keys + kRankMax) itself, and one writes the order (order_rw) for the later rounds
+  bool fuse_rank;
+  const uint64_t *rank_keys;
+  int32_t *order_rw;
 };
 
 hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
@@ -257,6 +262,8 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
                             hipStream_t stream);
 // Round 0 (r.C <= 64 candidates) together with the step's draws L.draw (L.fuse_draw).
 hipError_t launch_rec_draw_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream);
+// Round 0 (r.C = 64 candidates) together with the merge of the ranking (L.fuse_rank).
+hipError_t launch_rec_rank_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream);
 hipError_t launch_init_lists(AnnealDev *st, const uint64_t *bits, int W, int H,
                              hipStream_t stream);
 hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms, int64_t N,
