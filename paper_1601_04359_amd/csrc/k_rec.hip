@@ -541,7 +541,11 @@ hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t 
 
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream) {
-  const dim3 grid((unsigned)((L.rg.nv + 255) / 256), (unsigned)std::min(r.C, 512));
+  // about 2048 workgroups (what the device holds at once at this kernel's register use): more
+  // only queue behind them, and a round after an accepting round is all early exits
+  const int nvb = (L.rg.nv + 255) / 256;
+  const int gy = std::max(1, std::min(std::min(r.C, 512), (2048 + nvb - 1) / nvb));
+  const dim3 grid((unsigned)nvb, (unsigned)gy);
   int16_t *dl = decide ? L.dl : nullptr;
   // round 1 after a round 0 evaluated with the draws: round 0's sums are in S0
   const int64_t *S0 = decide && L.fuse_draw && r.pC > 0 ? L.S0 : nullptr;
