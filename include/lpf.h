@@ -384,7 +384,8 @@ lpf_status lpf_cnn_set_params(lpf_cnn net, const float *params, void *stream);
 /* Copy the parameters to params (device, LPF_CNN_PARAMS fp32). */
 lpf_status lpf_cnn_get_params(lpf_cnn net, float *params, void *stream);
 /* Scores of a batch of packed cells (bits: batch images back to back, device) into
- * scores[batch][H][W] (fp32, device). */
+ * scores[batch][H][W] (fp32, device).  A single image is scored in one launch (16 x 16 tiles with
+ * their halo in LDS), with the same scores bit for bit as the layer-by-layer batch path. */
 lpf_status lpf_cnn_forward(lpf_cnn net, const uint64_t *bits, int batch, float *scores,
                            void *stream);
 /* Loss and its gradient for n samples on a batch of cells: grad (device, LPF_CNN_PARAMS fp32),

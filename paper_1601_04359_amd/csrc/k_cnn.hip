@@ -112,15 +112,103 @@ k_cnn_conv_fwd(const uint16_t *__restrict__ X, int cin, const uint16_t *__restri
   }
 }
 
-// S[p] = sum_c A3[p][c] W4[c] + b4 (W4 rounded to bf16).
+// Score of one pixel from its 16 layer-3 activations: sum_c A3[c] W4[c] + b4 (W4 rounded to
+// bf16), summed in channel order.
+__device__ __forceinline__ float head_score(const uint16_t *a3, const float *__restrict__ W4bf,
+                                            const float *__restrict__ b4) {
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s += bf2f(a3[c]) * W4bf[c];
+  return s + b4[0];
+}
+
+// S[p] = sum_c A3[p][c] W4[c] + b4.
 __global__ void k_cnn_head_fwd(const uint16_t *__restrict__ A3, const float *__restrict__ W4bf,
                                const float *__restrict__ b4, int64_t npix, float *__restrict__ S) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  float s = 0.f;
+  S[p] = head_score(A3 + p * 16, W4bf, b4);
+}
+
+// ---------------------------------------------------------------- single-image scores, fused
+// The annealer's re-scoring of its cell in one launch.  A workgroup computes a 16 x 16 tile of
+// scores: the features of the tile and a 3-pixel periodic halo (22 x 22), then each layer's
+// activations on a halo one pixel narrower (20 x 20, 18 x 18, 16 x 16), all in LDS.  Halo pixels
+// are real pixels of the periodic cell, so their activations are the ones the layered kernels
+// compute; each output uses the same MFMA taps in the same order, the same bias, ReLU and bf16
+// rounding and the same head, so the scores equal cnn_forward's bit for bit.
+constexpr int kScoreTile = 16;
+
+// One 3x3 layer on LDS regions: `in` is a (wout + 2)^2 region with cin (4 or 16) channels per
+// pixel, `out` the wout^2 region inside it with 16; 4 waves take 16-pixel tiles in turn.
+__device__ __forceinline__ void conv_region(const uint16_t *in, int cin, uint16_t *out, int wout,
+                                            const uint16_t *__restrict__ Wf,
+                                            const float *__restrict__ bias) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  const int win = wout + 2, nout = wout * wout;
+  s4v Bw[9];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) s += bf2f(A3[p * 16 + c]) * W4bf[c];
-  S[p] = s + b4[0];
+  for (int t = 0; t < 9; ++t)
+    Bw[t] = *reinterpret_cast<const s4v *>(Wf + (t * 16 + m) * 16 + 4 * g);
+  const float bco = bias[m];
+  for (int tile = wave; tile * 16 < nout; tile += 4) {
+    const int i = tile * 16 + m;
+    const bool pin = i < nout;
+    const int ry = pin ? i / wout : 0, rx = pin ? i - ry * wout : 0;
+    f4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int src = (ry + t / 3) * win + rx + t % 3;  // input offset (t / 3 - 1, t % 3 - 1)
+      s4v a = {0, 0, 0, 0};
+      if (pin && 4 * g < cin) a = *reinterpret_cast<const s4v *>(in + src * cin + 4 * g);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, Bw[t], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int po = tile * 16 + 4 * g + j;
+      if (po < nout) out[po * 16 + m] = f2bf(fmaxf(acc[j] + bco, 0.f));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_cnn_score(const uint64_t *__restrict__ bits, int W, int H, const uint16_t *__restrict__ Wf,
+            const float *__restrict__ prm, const float *__restrict__ W4bf,
+            float *__restrict__ S) {
+  constexpr int T = kScoreTile;
+  __shared__ __attribute__((aligned(16))) uint16_t X0[(T + 6) * (T + 6) * 4];
+  __shared__ __attribute__((aligned(16))) uint16_t A1[(T + 4) * (T + 4) * 16];
+  __shared__ __attribute__((aligned(16))) uint16_t A2[(T + 2) * (T + 2) * 16];
+  __shared__ __attribute__((aligned(16))) uint16_t A3[T * T * 16];
+  const int tx0 = blockIdx.x * T, ty0 = blockIdx.y * T;
+  const int wpr = (W + 63) >> 6;
+  auto at = [&](int y, int x) -> int {
+    return (int)((bits[(size_t)y * wpr + (x >> 6)] >> (x & 63)) & 1ull);
+  };
+  for (int i = threadIdx.x; i < (T + 6) * (T + 6); i += blockDim.x) {
+    const int ry = i / (T + 6), rx = i - ry * (T + 6);
+    const int y = (((ty0 - 3 + ry) % H) + H) % H, x = (((tx0 - 3 + rx) % W) + W) % W;
+    const int v = at(y, x);
+    const int xl = x ? x - 1 : W - 1, xr = x + 1 == W ? 0 : x + 1;
+    const int yu = y ? y - 1 : H - 1, yd = y + 1 == H ? 0 : y + 1;
+    const int itf = at(y, xl) != v || at(y, xr) != v || at(yu, x) != v || at(yd, x) != v;
+    uint2 o;
+    o.x = (uint32_t)(v ? 0x3f80u : 0u) | ((uint32_t)(itf ? 0x3f80u : 0u) << 16);
+    o.y = 0;
+    *reinterpret_cast<uint2 *>(X0 + 4 * i) = o;
+  }
+  __syncthreads();
+  conv_region(X0, 4, A1, T + 4, Wf, prm + 288);
+  __syncthreads();
+  conv_region(A1, 16, A2, T + 2, Wf + 2304, prm + 2608);
+  __syncthreads();
+  conv_region(A2, 16, A3, T, Wf + 4608, prm + 4928);
+  __syncthreads();
+  const int ry = threadIdx.x / T, rx = threadIdx.x - ry * T;
+  const int y = ty0 + ry, x = tx0 + rx;
+  if (threadIdx.x < T * T && y < H && x < W)
+    S[(size_t)y * W + x] = head_score(A3 + threadIdx.x * 16, W4bf, prm + 4960);
 }
 
 // ------------------------------------------------------------------------------ loss / head
@@ -391,6 +479,14 @@ hipError_t cnn_forward(const CnnBufs &B, const uint64_t *bits, int W, int H, int
   hipLaunchKernelGGL(k_cnn_conv_fwd, dim3(cb), dim3(256), 0, s, B.A2, 16, B.Wf + 4608,
                      B.prm + 4928, B.A3, W, H, np);
   hipLaunchKernelGGL(k_cnn_head_fwd, dim3(nb), dim3(256), 0, s, B.A3, B.W4bf, B.prm + 4960, np, S);
+  return hipGetLastError();
+}
+
+hipError_t cnn_score(const CnnBufs &B, const uint64_t *bits, int W, int H, float *S,
+                     hipStream_t s) {
+  const dim3 grid((unsigned)((W + kScoreTile - 1) / kScoreTile),
+                  (unsigned)((H + kScoreTile - 1) / kScoreTile));
+  hipLaunchKernelGGL(k_cnn_score, grid, dim3(256), 0, s, bits, W, H, B.Wf, B.prm, B.W4bf, S);
   return hipGetLastError();
 }
 

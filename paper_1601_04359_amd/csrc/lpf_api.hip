@@ -663,7 +663,7 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
       if (a->net) {
         if ((e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess)
           return hip_fail(e, "anneal: score scratch");
-        if ((e = cnn_forward(a->net->b, a->bits, a->W, a->H, 1, (float *)a->scores.p, s)) != hipSuccess)
+        if ((e = cnn_score(a->net->b, a->bits, a->W, a->H, (float *)a->scores.p, s)) != hipSuccess)
           return hip_fail(e, "anneal: proposal network");
         sc = (const float *)a->scores.p;
       }
@@ -2033,7 +2033,9 @@ lpf_status lpf_cnn_forward(lpf_cnn n, const uint64_t *bits, int batch, float *sc
   if (!n || !bits || !scores) return fail(LPF_E_INVAL, "lpf_cnn_forward: NULL argument");
   if (batch < 1 || batch > n->max_batch) return fail(LPF_E_INVAL, "lpf_cnn_forward: batch");
   DeviceGuard g(n->ctx->dev);
-  hipError_t e = cnn_forward(n->b, bits, n->W, n->H, batch, scores, (hipStream_t)stream);
+  // one image: the single-launch kernel (same scores, bit for bit)
+  hipError_t e = batch == 1 ? cnn_score(n->b, bits, n->W, n->H, scores, (hipStream_t)stream)
+                            : cnn_forward(n->b, bits, n->W, n->H, batch, scores, (hipStream_t)stream);
   return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_cnn_forward");
 }
 

@@ -291,6 +291,9 @@ struct CnnBufs {
 };
 hipError_t cnn_forward(const CnnBufs &B, const uint64_t *bits, int W, int H, int batch,
                        float *S, hipStream_t s);
+// Scores of one image in one launch (bitwise those of cnn_forward with batch 1).
+hipError_t cnn_score(const CnnBufs &B, const uint64_t *bits, int W, int H, float *S,
+                     hipStream_t s);
 hipError_t cnn_grad(const CnnBufs &B, const uint64_t *bits, int W, int H, int batch,
                     const CnnSample *smp, int n, float *grad, float *loss, hipStream_t s);
 hipError_t cnn_pack(const CnnBufs &B, hipStream_t s);

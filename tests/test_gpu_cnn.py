@@ -51,7 +51,8 @@ def _close(got, ref, frac=2.0 ** -5):
     assert np.max(err) <= frac * scale, (np.max(err), scale)
 
 
-@pytest.mark.parametrize("W,H,batch", [(16, 16, 1), (24, 40, 2), (128, 128, 2), (37, 29, 3)])
+@pytest.mark.parametrize("W,H,batch", [(16, 16, 1), (24, 40, 2), (128, 128, 2), (37, 29, 3),
+                                       (37, 29, 1), (5, 3, 1), (100, 60, 1)])
 def test_forward_matches_oracle(ctx, W, H, batch):
     print(f"[gpu] cnn forward {W}x{H} batch {batch}", flush=True)
     prm = _params(1)
@@ -61,6 +62,21 @@ def test_forward_matches_oracle(ctx, W, H, batch):
     for i, im in enumerate(imgs):
         ref = cnn.forward(prm, im)["S"]
         _close(S[i], ref)
+    net.close()
+
+
+@pytest.mark.parametrize("W,H", [(5, 3), (16, 16), (37, 29), (100, 60), (256, 256)])
+def test_single_image_scores_equal_batch_path(ctx, W, H):
+    # one image is scored by the single-launch kernel (tiles with their halo in LDS), a batch by
+    # the layer-by-layer kernels: the same operations, so the scores agree bit for bit
+    print(f"[gpu] cnn single-launch scores {W}x{H}", flush=True)
+    prm = _params(3)
+    im = wl.boolean_disks(W, H, 3.0, 0.4, W * H)
+    net = _net(ctx, W, H, 2, 8, prm)
+    one = net.forward(_bits(ctx, [im]), 1).cpu().numpy()
+    two = net.forward(_bits(ctx, [im, im]), 2).cpu().numpy()
+    assert np.array_equal(one[0].view(np.uint32), two[0].view(np.uint32))
+    assert np.array_equal(two[0], two[1])
     net.close()
 
 
