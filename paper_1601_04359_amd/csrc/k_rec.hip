@@ -446,52 +446,131 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
   }
 }
 
-// The accepted interchange ks (a now in phase 0, b in phase 1) applied to ones and the records,
-// lane t of 2 Mc: one per (side, path pixel j), placement x = (a or b) - p_j of vector v(j).
+// The accepted interchange (a now in phase 0, b in phase 1) applied to ones and the records of
+// vector v on one side (side 0: the placements through a, 1: through b), by one wave.  Lane k
+// takes placement x_k = s - p_k (s = a or b), updates ones(v, x_k) and finds which plane bits of
+// x_k change; those bits live in the records of the pixels x_k + p_j at bit off + j, j = 0..n.
+// For n + 1 <= 64 the flips are merged before they are issued: with j = k + d, the record pixel
+// is s + (p_{k+d} - p_k), and for a fixed d that difference takes at most two values along a
+// digitised straight line, so lane d gathers, per value, the changed k into one mask and flips
+// mask << (off + d) with at most three atomic XORs per plane, instead of one per (k, j).  (A
+// third value, not expected, is flipped bit by bit.)  Longer paths flip bit by bit.
 template <unsigned MASK>
-__device__ __forceinline__ void rec_update_lane(const RecGeo &g, const int2 *__restrict__ cand,
-                                                int ks, int64_t t) {
+__device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, int v, int side,
+                                                int32_t *path) {
   using P = Planes<MASK>;
-  if (t >= 2 * (int64_t)g.Mc) return;
+  const int lane = threadIdx.x & 63;
   const int64_t N = (int64_t)g.W * g.H;
-  const int side = t >= g.Mc;
-  const int j = (int)(side ? t - g.Mc : t);
-  const int v = g.vbit[j] >> 8;
   const int4 m = g.meta[v];
   const int off = m.x, n = m.y;
-  const int a = cand[ks].x, b = cand[ks].y;
   const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
-  const int32_t p = g.pix[j];
-  const int x = wrapi((side ? bx : ax) - pix_dx(p), g.W);
-  const int y = wrapi((side ? by : ay) - pix_dy(p), g.H);
-  // x in both P_a and P_b: its count does not change (only possible when b - a is within the
-  // vector's box, which the cheap test settles for most lanes)
+  const int sx = side ? bx : ax, sy = side ? by : ay;
+  // placements in both P_a and P_b keep their count (possible only when b - a is within reach)
   const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
-  if (within(ox, g.W, m.z < 0 ? -m.z : m.z) && within(oy, g.H, m.w) &&
-      on_path(ox + pix_dx(p), oy + pix_dy(p), m.z, m.w, n, g.W, g.H))
-    return;
-  uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
-  const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
-  *op = (uint8_t)o1;
-  unsigned chg = 0;
-#pragma unroll
-  for (int pl = 0; pl < P::n; ++pl)
-    if (plane_cond(P::side(pl), P::phase(pl), o0, n) != plane_cond(P::side(pl), P::phase(pl), o1, n))
-      chg |= 1u << pl;
-  if (!chg) return;
-  for (int kk = 0; kk <= n; ++kk) {
-    const int32_t pp = g.pix[off + kk];
-    const int qx = wrapi(x + pix_dx(pp), g.W), qy = wrapi(y + pix_dy(pp), g.H);
-    uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
-    const int jj = off + kk;
+  const bool near = within(ox, g.W, m.z < 0 ? -m.z : m.z) && within(oy, g.H, m.w);
+  auto update = [&](int k, int32_t pk) -> unsigned {
+    const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
+    if (near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H)) return 0u;
+    uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
+    const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
+    *op = (uint8_t)o1;
+    unsigned chg = 0;
 #pragma unroll
     for (int pl = 0; pl < P::n; ++pl)
-      if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (jj >> 5), 1u << (jj & 31));
+      if (plane_cond(P::side(pl), P::phase(pl), o0, n) != plane_cond(P::side(pl), P::phase(pl), o1, n))
+        chg |= 1u << pl;
+    return chg;
+  };
+  auto flip_bit = [&](int qx, int qy, unsigned chg, int bit) {
+    uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl)
+      if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (bit >> 5), 1u << (bit & 31));
+  };
+  if (n + 1 > 64) {
+    for (int kc = 0; kc <= n; kc += 64) {
+      const int k = kc + lane;
+      if (k > n) continue;
+      const int32_t pk = g.pix[off + k];
+      const unsigned chg = update(k, pk);
+      if (!chg) continue;
+      const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
+      for (int j = 0; j <= n; ++j) {
+        const int32_t pj = g.pix[off + j];
+        flip_bit(wrapi(x + pix_dx(pj), g.W), wrapi(y + pix_dy(pj), g.H), chg, off + j);
+      }
+    }
+    return;
+  }
+  unsigned chg = 0;
+  if (lane <= n) {
+    const int32_t pk = g.pix[off + lane];
+    path[lane] = pk;
+    chg = update(lane, pk);
+  }
+  uint64_t M[P::n], any = 0;
+#pragma unroll
+  for (int pl = 0; pl < P::n; ++pl) {
+    M[pl] = __ballot((chg >> pl) & 1u);
+    any |= M[pl];
+  }
+  if (!any) return;
+  __builtin_amdgcn_wave_barrier();  // path[] written by this wave's lanes, read below
+  for (int dd = lane; dd <= 2 * n; dd += 64) {
+    const int d = dd - n;
+    const int k0 = d < 0 ? -d : 0, k1 = d > 0 ? n - d : n;
+    const uint64_t range = ((~0ull) >> (63 - k1)) & ((~0ull) << k0);
+    uint64_t todo = any & range;
+    int ncls = 0;
+    int cdx[2] = {0, 0}, cdy[2] = {0, 0};
+    uint64_t cm[2][P::n];
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl) cm[0][pl] = cm[1][pl] = 0ull;
+    while (todo) {
+      const int k = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const int32_t p0 = path[k], p1 = path[k + d];
+      const int ddx = pix_dx(p1) - pix_dx(p0), ddy = pix_dy(p1) - pix_dy(p0);
+      int c = -1;
+      for (int q = 0; q < ncls; ++q)
+        if (cdx[q] == ddx && cdy[q] == ddy) c = q;
+      if (c < 0 && ncls < 2) {
+        c = ncls++;
+        cdx[c] = ddx;
+        cdy[c] = ddy;
+      }
+      if (c < 0) {  // a third difference: flip this placement's bits one by one
+        unsigned ck = 0;
+#pragma unroll
+        for (int pl = 0; pl < P::n; ++pl) ck |= (unsigned)((M[pl] >> k) & 1ull) << pl;
+        flip_bit(wrapi(sx + ddx % g.W, g.W), wrapi(sy + ddy % g.H, g.H), ck, off + k + d);
+        continue;
+      }
+#pragma unroll
+      for (int pl = 0; pl < P::n; ++pl) cm[c][pl] |= M[pl] & (1ull << k);
+    }
+    const int base = off + d;
+    for (int c = 0; c < ncls; ++c) {
+      const int qx = wrapi(sx + cdx[c] % g.W, g.W), qy = wrapi(sy + cdy[c] % g.H, g.H);
+      uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride + (base >> 5);
+#pragma unroll
+      for (int pl = 0; pl < P::n; ++pl) {
+        if (!cm[c][pl]) continue;
+        const int sh = base & 31;
+        const uint32_t w0 = (uint32_t)(cm[c][pl] << sh);
+        const uint32_t w1 = (uint32_t)((cm[c][pl] << sh) >> 32);
+        const uint32_t w2 = sh ? (uint32_t)(cm[c][pl] >> (64 - sh)) : 0u;
+        uint32_t *Rp = R + (size_t)pl * g.Rw;
+        if (w0) atomicXor(Rp, w0);
+        if (w1) atomicXor(Rp + 1, w1);
+        if (w2) atomicXor(Rp + 2, w2);
+      }
+    }
   }
 }
 
 // End of a step under the records method: workgroups 0 .. nupd - 1 apply the accepted
-// interchange to ones and records (rec_update_lane), workgroup nupd does the step's upkeep
+// interchange to ones and records (rec_update_wave), workgroup nupd does the step's upkeep
 // (step_apply).  Each workgroup takes the step's decision itself (ctl->ks, or the same scan of the
 // last round), so one launch replaces the upkeep kernel followed by the update kernel: the upkeep
 // touches counts, image bits, pixel lists and energy, none of which the update reads.
@@ -499,6 +578,7 @@ template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __shared__ int s_ks0, s_first;
+  __shared__ int32_t path[4][64];
   if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
   __syncthreads();
   const int ks0 = s_ks0;
@@ -507,7 +587,12 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
     step_apply(f, ks, ks0 < 0 && ks >= 0);
     return;
   }
-  if (ks >= 0) rec_update_lane<MASK>(g, f.cand, ks, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (ks < 0) return;
+  const int wave = threadIdx.x >> 6, wid = (int)blockIdx.x * 4 + wave;
+  const int v = wid >> 1;
+  if (v >= g.nv) return;
+  const int2 ab = f.cand[ks];
+  rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, path[wave]);
 }
 
 #define LPF_REC_MASK_SWITCH(mask, CALL) \
@@ -531,7 +616,7 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
 }
 
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
-  const int nupd = (int)((2 * (int64_t)g.Mc + 255) / 256);
+  const int nupd = (2 * g.nv + 3) / 4;  // one wave per (vector, side)
 #define LPF_END(M) \
   hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
