@@ -1,16 +1,17 @@
 // One annealing step's evaluation in rounds, with early exit.
 //
-// The K candidates of a step are evaluated in evaluation order (draw order, or the ranking of
-// k_rank_chunks / k_rank_merge when an order array is given), in rounds of 64 and then the rest
-// (at most 8192 each), so that a step whose first candidates are accepted costs one small round.
-// Each round is an evaluation kernel (recount method here, records method in k_rec.hip, the
-// two-point probability descriptor in k_s2.hip) that
-// adds every candidate's integer energy sum S = sum dL (Nt (dL + 2L) - 2 N T) into S_acc and
-// stores its dL (int16 per term and candidate), followed by k_round_decide, which applies the
-// Metropolis test of Alg. "annealing" (accept iff de <= 0 or U < exp(-de / T), de = S / (N^2 Nt),
-// eq. (LSE)) in evaluation order and records the first accepted candidate.  Rounds after an acceptance
-// return at once.  The step's result is the first accepted candidate over all K, exactly as if
-// every candidate had been evaluated.
+// The K candidates of a step are evaluated in evaluation order (draw order, or the learned
+// ranking when an order array is given), in rounds of 64 and then the rest (at most 8192 each),
+// so that a step whose first candidates are accepted costs one small round.  Each round is an
+// evaluation kernel (recount method here, records method in k_rec.hip, the two-point probability
+// descriptor in k_s2.hip) that adds every candidate's integer energy sum
+// S = sum dL (Nt (dL + 2L) - 2 N T) into S_acc and stores its dL (int16 per term and candidate).
+// The Metropolis test of Alg. "annealing" (accept iff de <= 0 or U < exp(-de / T),
+// de = S / (N^2 Nt), eq. (LSE)) is applied in evaluation order to a round's candidates at the start
+// of the next round (round 0), by k_round_decide (middle rounds), or at the end of the step (last
+// round), and the first accepted candidate is recorded.  Rounds after an acceptance return at
+// once.  The step's result is the first accepted candidate over all K, exactly as if every
+// candidate had been evaluated.
 #include <limits.h>
 #include <math.h>
 

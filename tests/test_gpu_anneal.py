@@ -128,6 +128,44 @@ def test_ragged_cell_long_vectors(ctx, method):
     ch.close()
 
 
+def test_records_long_paths(ctx):
+    # cutoff (80, 1) on a 150 x 40 cell: paths of up to 81 pixels, longer than one wave, take the
+    # bit-by-bit record update; the shorter ones the merged one; K = 70 runs round 0 in the launch
+    # of the draws and a second round of 6.  Started from a crop of the target at T ~ 0, this seed
+    # has steps accepted in round 0, steps accepted in round 1 and steps with no acceptance.
+    import torch
+    from paper_1601_04359_amd import step_records
+    print("[gpu] anneal records long paths 150x40 c=(80,1)", flush=True)
+    tgt = wl.boolean_disks(300, 80, 3.0, 0.4, 17)
+    target = oracle.lpf(tgt, 80, 1, 3)
+    cell = np.ascontiguousarray(tgt[:40, :150])
+    Ts = np.full(60, 1e-9)
+    ch = _gpu_chain(ctx, cell, 80, 3, target, tgt.size, 16, method=METHODS["records"], cy=1)
+    recs = step_records(ch.run(70, Ts))
+    torch.cuda.synchronize()
+    ref = oracle.AnnealState(cell, 80, 1, 3, target, tgt.size, 16)
+    rres = ref.run(60, 70, Ts)
+    assert [(int(r["k"]), int(r["a"]), int(r["b"])) for r in recs] == \
+        [(int(r["k"]), int(r["a"]), int(r["b"])) for r in rres]
+    assert np.array_equal(recs["de"], rres["de"])
+    k = recs["k"]
+    assert (k >= 64).sum() >= 1 and (k < 0).sum() >= 1 and ((k >= 0) & (k < 64)).sum() >= 20
+    assert np.array_equal(ch.counts.cpu().numpy().astype(np.uint32), ref.counts)
+    # the records after the updates still give the exact change of further interchanges
+    img = _unpack(ch.bits, 150, 40)
+    rng = np.random.default_rng(3)
+    ones, zeros = np.flatnonzero(img.ravel() == 1), np.flatnonzero(img.ravel() == 0)
+    sw = np.stack([rng.choice(ones, 20), rng.choice(zeros, 20)], 1).astype(np.int32)
+    de = ch.delta_energy(torch.from_numpy(sw).cuda()).cpu().numpy()
+    base = oracle.lpf(img, 80, 1, 3).astype(np.int64)
+    dl = oracle.delta_swap(img, 80, 1, sw, 3).astype(np.int64)
+    N, Nt, T = img.size, tgt.size, target.astype(np.int64)
+    for i in range(len(sw)):
+        S = int(np.sum(dl[i] * (Nt * (dl[i] + 2 * base) - 2 * N * T)))
+        assert de[i] == S / (N * N * Nt)
+    ch.close()
+
+
 def test_records_agree_with_recount(ctx):
     # after many accepted interchanges (incremental record updates), the records method's exact
     # energy changes of random and neighbouring interchanges equal the recount method's, and the
