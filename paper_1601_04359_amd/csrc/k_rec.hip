@@ -36,6 +36,14 @@ __device__ __forceinline__ int image_bit(const uint64_t *__restrict__ bits, int 
   return (int)((bits[(size_t)y * wpr + (x >> 6)] >> (x & 63)) & 1ull);
 }
 
+// Set bits of the 64-bit window x[0..2] >> sh, first len (<= 64) of them.
+__device__ __forceinline__ int popcount_window(const uint32_t (&x)[3], uint32_t sh, int len) {
+  const uint32_t lo = __builtin_amdgcn_alignbit(x[1], x[0], sh);
+  const uint32_t hi = __builtin_amdgcn_alignbit(x[2], x[1], sh);
+  const uint64_t v = ((uint64_t)hi << 32) | lo;
+  return __popcll(len == 64 ? v : v & ((1ull << len) - 1ull));
+}
+
 // Number of set bits j of `plane` with off <= j < off + len.
 __device__ __forceinline__ int popcount_range(const uint32_t *__restrict__ plane, int off, int len) {
   int c = 0;
@@ -194,11 +202,31 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
   const int off = m.x, n = m.y, len = n + 1;
   const uint32_t *RA = g.rec + (size_t)a * g.rstride;                // planes A of a
   const uint32_t *RB = g.rec + (size_t)b * g.rstride + P::nph * g.Rw;  // planes B of b
+  if (len <= 64) {
+    // a range of up to 64 bits spans three words (planes carry two padding words): every
+    // plane's words are requested before any is used, so the record reads overlap
+    const int w = off >> 5;
+    const uint32_t sh = (uint32_t)(off & 31);
+    uint32_t xa[P::nph][3], xb[P::nph][3];
 #pragma unroll
-  for (int p = 0; p < P::nph; ++p) {
-    const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
-    const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
-    d[p] = P::phase(p) ? cB - cA : cA - cB;
+    for (int p = 0; p < P::nph; ++p)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        xa[p][i] = RA[(size_t)p * g.Rw + w + i];
+        xb[p][i] = RB[(size_t)p * g.Rw + w + i];
+      }
+#pragma unroll
+    for (int p = 0; p < P::nph; ++p) {
+      const int cA = popcount_window(xa[p], sh, len), cB = popcount_window(xb[p], sh, len);
+      d[p] = P::phase(p) ? cB - cA : cA - cB;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < P::nph; ++p) {
+      const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
+      const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
+      d[p] = P::phase(p) ? cB - cA : cA - cB;
+    }
   }
   // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k = p_j on the path
   const int DX = bx - ax, DY = by - ay;

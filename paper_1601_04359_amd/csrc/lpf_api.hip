@@ -747,7 +747,7 @@ bool records_fit(lpf_anneal a, int64_t *bytes, std::string *why) {
     canonical_vectors(a->cx, a->cy, can);
     for (int64_t i = 0; i < nv; ++i) Mc += std::max(std::abs((int)can[2 * i]), (int)can[2 * i + 1]) + 1;
   }
-  const int64_t Rw = (Mc + 31) / 32 + 1;
+  const int64_t Rw = (Mc + 31) / 32 + 2;  // two padding words per plane
   const int64_t b = N * 2 * nph * Rw * 4 + nv * N;
   if (bytes) *bytes = b;
   if (std::max(a->cx, a->cy) > 254) {
@@ -814,7 +814,7 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     RecGeo g{};
     g.nv = (int)nv;
     g.Mc = (int)pix.size();
-    g.Rw = (g.Mc + 31) / 32 + 1;
+    g.Rw = (g.Mc + 31) / 32 + 2;  // two padding words: ranges read three words at once
     g.nph = nph_of(a->mask);
     g.W = a->W;
     g.H = a->H;
