@@ -295,14 +295,16 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool vin = v < g.nv;
   // candidate-independent operands first, so that their loads overlap the candidate's
-  const int4 m = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  // loads at a clamped index, without a branch, so that they overlap what follows; lanes past
+  // the last vector contribute nothing (rec_delta returns zeros for them)
+  const int vc = vin ? v : g.nv - 1;
+  const int4 m = g.meta[vc];
   int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
 #pragma unroll
-  for (int p = 0; p < P::nph; ++p)
-    if (vin) {
-      Lc[p] = counts[(size_t)p * g.nv + v];
-      Tc[p] = target[(size_t)p * g.nv + v];
-    }
+  for (int p = 0; p < P::nph; ++p) {
+    Lc[p] = counts[(size_t)p * g.nv + vc];
+    Tc[p] = target[(size_t)p * g.nv + vc];
+  }
   for (int kr = blockIdx.y; kr < C; kr += gridDim.y) {
     if (k0 + kr >= K) break;
     const int k = order ? order[k0 + kr] : k0 + kr;  // candidate (draw index)
@@ -354,14 +356,16 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
   if (kr >= C0) return;
   const int v = vb * 256 + (int)threadIdx.x;
   const bool vin = v < g.nv;
-  const int4 m = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  // loads at a clamped index, without a branch, so that they overlap what follows; lanes past
+  // the last vector contribute nothing (rec_delta returns zeros for them)
+  const int vc = vin ? v : g.nv - 1;
+  const int4 m = g.meta[vc];
   int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
 #pragma unroll
-  for (int q = 0; q < P::nph; ++q)
-    if (vin) {
-      Lc[q] = counts[(size_t)q * g.nv + v];
-      Tc[q] = target[(size_t)q * g.nv + v];
-    }
+  for (int q = 0; q < P::nph; ++q) {
+    Lc[q] = counts[(size_t)q * g.nv + vc];
+    Tc[q] = target[(size_t)q * g.nv + vc];
+  }
   int a, b, ia, ib;
   double u;
   draw_candidate(p, kr, a, b, ia, ib, u);
@@ -445,14 +449,16 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
   const int k = (int)~(uint32_t)s_key;  // draw index of the kr-th best
   const int v = vb * 256 + (int)threadIdx.x;
   const bool vin = v < g.nv;
-  const int4 mv = vin ? g.meta[v] : make_int4(0, 0, 0, 0);
+  // loads at a clamped index, without a branch, so that they overlap what follows; lanes past
+  // the last vector contribute nothing (rec_delta returns zeros for them)
+  const int vc = vin ? v : g.nv - 1;
+  const int4 mv = g.meta[vc];
   int64_t Lc[2] = {0, 0}, Tc[2] = {0, 0};
 #pragma unroll
-  for (int q = 0; q < P::nph; ++q)
-    if (vin) {
-      Lc[q] = counts[(size_t)q * g.nv + v];
-      Tc[q] = target[(size_t)q * g.nv + v];
-    }
+  for (int q = 0; q < P::nph; ++q) {
+    Lc[q] = counts[(size_t)q * g.nv + vc];
+    Tc[q] = target[(size_t)q * g.nv + vc];
+  }
   const int2 ab = cand[k];
   int d[2];
   rec_delta<MASK, true>(g, bits, ab.x, ab.y, v, mv, d);
@@ -483,13 +489,13 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
 // digitised straight line, so lane d gathers, per value, the changed k into one mask and flips
 // mask << (off + d) with at most three atomic XORs per plane, instead of one per (k, j).  (A
 // third value, not expected, is flipped bit by bit.)  Longer paths flip bit by bit.
+// m = meta[v]; pk = p_lane (lane <= n, n + 1 <= 64), loaded by the caller ahead of the decision.
 template <unsigned MASK>
 __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, int v, int side,
-                                                int32_t *path) {
+                                                int4 m, int32_t pk_lane, int32_t *path) {
   using P = Planes<MASK>;
   const int lane = threadIdx.x & 63;
   const int64_t N = (int64_t)g.W * g.H;
-  const int4 m = g.meta[v];
   const int off = m.x, n = m.y;
   const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
   const int sx = side ? bx : ax, sy = side ? by : ay;
@@ -532,9 +538,8 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
   }
   unsigned chg = 0;
   if (lane <= n) {
-    const int32_t pk = g.pix[off + lane];
-    path[lane] = pk;
-    chg = update(lane, pk);
+    path[lane] = pk_lane;
+    chg = update(lane, pk_lane);
   }
   uint64_t M[P::n], any = 0;
 #pragma unroll
@@ -607,6 +612,12 @@ __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __shared__ int s_ks0, s_first;
   __shared__ int32_t path[4][64];
+  // the wave's vector and path pixel do not depend on the decision: load them first, at clamped
+  // indices (no branch), so that they overlap the decision's reads
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wid = (int)blockIdx.x * 4 + wave;
+  const int v = wid >> 1;
+  const int4 m = g.meta[min(v, g.nv - 1)];
+  const int32_t pk = g.pix[m.x + min(lane, m.y)];
   if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
   __syncthreads();
   const int ks0 = s_ks0;
@@ -615,12 +626,9 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
     step_apply(f, ks, ks0 < 0 && ks >= 0);
     return;
   }
-  if (ks < 0) return;
-  const int wave = threadIdx.x >> 6, wid = (int)blockIdx.x * 4 + wave;
-  const int v = wid >> 1;
-  if (v >= g.nv) return;
+  if (ks < 0 || v >= g.nv) return;
   const int2 ab = f.cand[ks];
-  rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, path[wave]);
+  rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk, path[wave]);
 }
 
 #define LPF_REC_MASK_SWITCH(mask, CALL) \
