@@ -44,6 +44,13 @@ __device__ __forceinline__ int popcount_window(const uint32_t (&x)[3], uint32_t 
   return __popcll(len == 64 ? v : v & ((1ull << len) - 1ull));
 }
 
+// Byte of placement (x, y) in a vector's plane of ones: 8 x 8-pixel tiles of 64 bytes, row-major
+// inside a tile and over tiles, so that the placements along a path (which step through rows as
+// often as through columns) share cache lines.
+__device__ __forceinline__ int64_t ones_at(const RecGeo &g, int x, int y) {
+  return ((int64_t)(y >> 3) * ((g.W + 7) >> 3) + (x >> 3)) * 64 + ((y & 7) << 3) + (x & 7);
+}
+
 // Number of set bits j of `plane` with off <= j < off + len.
 __device__ __forceinline__ int popcount_range(const uint32_t *__restrict__ plane, int off, int len) {
   int c = 0;
@@ -126,7 +133,7 @@ k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
     o += image_bit(bits, wpr, wrapi(px + pix_dx(p), g.W), wrapi(py + pix_dy(p), g.H));
   }
   if (g.sample && !image_bit(g.sample, wpr, px, py)) o += 128;  // outside the position set
-  g.ones[(size_t)v * N + x] = (uint8_t)o;
+  g.ones[(size_t)v * g.oplane + ones_at(g, px, py)] = (uint8_t)o;
 }
 
 // Records of 64 pixels over one 32-dword tile of the record per workgroup (the waves of the
@@ -158,7 +165,7 @@ k_rec_build(RecGeo g) {
       const int32_t p = g.pix[jb + t];
       const int v = vn >> 8, n = vn & 255;
       const int xx = wrapi(qx - pix_dx(p), g.W), yy = wrapi(qy - pix_dy(p), g.H);
-      const int o = valid ? (int)g.ones[(size_t)v * N + (size_t)yy * g.W + xx] : -1;
+      const int o = valid ? (int)g.ones[(size_t)v * g.oplane + ones_at(g, xx, yy)] : -1;
 #pragma unroll
       for (int pl = 0; pl < P::n; ++pl)
         acc[pl] |= (plane_cond(P::side(pl), P::phase(pl), o, n) ? 1u : 0u) << t;
@@ -495,7 +502,6 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
                                                 int4 m, int32_t pk_lane, int32_t *path) {
   using P = Planes<MASK>;
   const int lane = threadIdx.x & 63;
-  const int64_t N = (int64_t)g.W * g.H;
   const int off = m.x, n = m.y;
   const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
   const int sx = side ? bx : ax, sy = side ? by : ay;
@@ -505,7 +511,7 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
   auto update = [&](int k, int32_t pk) -> unsigned {
     const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
     if (near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H)) return 0u;
-    uint8_t *op = g.ones + (size_t)v * N + (size_t)y * g.W + x;
+    uint8_t *op = g.ones + (size_t)v * g.oplane + ones_at(g, x, y);
     const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
     *op = (uint8_t)o1;
     unsigned chg = 0;

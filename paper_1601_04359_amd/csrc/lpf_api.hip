@@ -748,7 +748,7 @@ bool records_fit(lpf_anneal a, int64_t *bytes, std::string *why) {
     for (int64_t i = 0; i < nv; ++i) Mc += std::max(std::abs((int)can[2 * i]), (int)can[2 * i + 1]) + 1;
   }
   const int64_t Rw = (Mc + 31) / 32 + 2;  // two padding words per plane
-  const int64_t b = N * 2 * nph * Rw * 4 + nv * N;
+  const int64_t b = N * 2 * nph * Rw * 4 + nv * ((int64_t)((a->W + 7) / 8) * ((a->H + 7) / 8) * 64);
   if (bytes) *bytes = b;
   if (std::max(a->cx, a->cy) > 254) {
     if (why) *why = "cutoff above 254 (path counts are bytes)";
@@ -819,6 +819,7 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     g.W = a->W;
     g.H = a->H;
     g.rstride = (int64_t)2 * g.nph * g.Rw;
+    g.oplane = (int64_t)((a->W + 7) / 8) * ((a->H + 7) / 8) * 64;
     g.mask = a->mask;
     g.sample = a->sample;
     const int64_t N = (int64_t)a->W * a->H;
@@ -826,7 +827,7 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
         (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||
         (e = a->rvbit.ensure(sizeof(int32_t) * vbit.size())) != hipSuccess ||
         (e = a->rec.ensure(sizeof(uint32_t) * (size_t)(N * g.rstride))) != hipSuccess ||
-        (e = a->ones.ensure((size_t)(nv * N))) != hipSuccess)
+        (e = a->ones.ensure((size_t)(nv * g.oplane))) != hipSuccess)
       return hip_fail(e, "anneal: records allocation");
     if ((e = hipMemcpyAsync(a->rmeta.p, meta.data(), sizeof(int4) * meta.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(a->rpix.p, pix.data(), sizeof(int32_t) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||

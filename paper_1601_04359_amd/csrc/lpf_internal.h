@@ -108,7 +108,8 @@ struct RecGeo {
   const int4 *meta;     // per vector {off, n, dx, dy}
   const int32_t *pix;   // [Mc] path pixel offsets, (dx & 0xffff) | (dy << 16)
   uint32_t *rec;        // [W*H][plane A phases, plane B phases][Rw]
-  uint8_t *ones;        // [nv][W*H]
+  uint8_t *ones;        // [nv][oplane]: per vector, 8 x 8-pixel tiles of 64 bytes (ones_at)
+  int64_t oplane;       // bytes per vector: ceil(W/8) * ceil(H/8) * 64
   const int32_t *vbit;  // [Mc] (v << 8) | n of the vector of each record bit
   unsigned mask;        // phases kept (LPF_PHASE0 | LPF_PHASE1 bits)
   // Monte-Carlo position set (packed like the image), nullptr = every placement.  A placement
