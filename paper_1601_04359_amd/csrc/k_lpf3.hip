@@ -170,15 +170,22 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
     const int mb = MAJ == 2 ? a1 : a2;  // minor b: y for MAJ 2, else z
     uint32_t c0 = 0, c1 = 0;
     // RPL start rows per lane per band: the scalar voxel walk is shared by their vector work
+    // a voxel's dword offset is the lane's row start (Pq) plus a wave-uniform part, plus or minus
+    // one period of rows when the lane's row wraps in y (from the voxel with qy >= Tq on: the
+    // minor coordinate only grows along the path and stays below H)
+    const int HR = H * rst;
+    const int wadj = s1 > 0 ? -HR : HR;
     for (int r0 = 0; r0 < rows; r0 += rpw * RPL) {
-      int yq[RPL], zq[RPL];
+      int Pq[RPL], Tq[RPL];
       uint32_t A[RPL][R], O[RPL][R], mk[RPL][R];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         const int r = r0 + q * rpw + r_in;
         const bool row_ok = r < rows;
-        zq[q] = row_ok ? r / H : 0;
-        yq[q] = row_ok ? r - zq[q] * H : 0;
+        const int zr = row_ok ? r / H : 0;
+        const int yr = row_ok ? r - zr * H : 0;
+        Pq[q] = (zr * H + yr) * rst;
+        Tq[q] = s1 > 0 ? H - yr : yr + 1;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           A[q][i] = 0xffffffffu;
@@ -203,12 +210,9 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         const int qy = MAJ == 1 ? k : (MAJ == 0 ? qa : qb);
         const int qz = MAJ == 2 ? k : qb;
         const int px = dx < 0 ? a0 - qx : qx;  // mirrored and shifted by |dx| when dx < 0
+        const int su = (qz * H + s1 * qy) * rst + (px >> 5);  // wave-uniform
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-          int yy = yq[q] + s1 * qy;
-          yy = yy >= H ? yy - H : (yy < 0 ? yy + H : yy);
-          off[q] = ((zq[q] + qz) * H + yy) * rst + (px >> 5);
-        }
+        for (int q = 0; q < RPL; ++q) off[q] = Pq[q] + su + (qy >= Tq[q] ? wadj : 0);
         sh = px & 31;
       };
       int k = 0;
