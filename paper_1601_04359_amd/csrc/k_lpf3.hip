@@ -173,7 +173,8 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
     // a voxel's dword offset is the lane's row start (Pq) plus a wave-uniform part, plus or minus
     // one period of rows when the lane's row wraps in y (from the voxel with qy >= Tq on: the
     // minor coordinate only grows along the path and stays below H)
-    const int HR = H * rst;
+    // offsets in bytes, so that they are LDS addresses as they stand
+    const int HR = H * rst * 4;
     const int wadj = s1 > 0 ? -HR : HR;
     for (int r0 = 0; r0 < rows; r0 += rpw * RPL) {
       int Pq[RPL], Tq[RPL];
@@ -184,7 +185,7 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         const bool row_ok = r < rows;
         const int zr = row_ok ? r / H : 0;
         const int yr = row_ok ? r - zr * H : 0;
-        Pq[q] = (zr * H + yr) * rst;
+        Pq[q] = (zr * H + yr) * rst * 4;
         Tq[q] = s1 > 0 ? H - yr : yr + 1;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -195,7 +196,10 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
           mk[q][i] = row_ok ? mw : 0u;
         }
       }
-      const uint32_t *base = lds + strip * R;
+      const char *base = reinterpret_cast<const char *>(lds + strip * R);
+      auto word = [&](int off, int c) -> uint32_t {
+        return *reinterpret_cast<const uint32_t *>(base + off + 4 * c);
+      };
       // Bresenham state of voxel k: minor coordinates qa, qb with error terms ea, eb; voxels in
       // pairs (two funnel shifts, one 3-input AND, one 3-input OR)
       int ea = n, eb = n, qa = 0, qb = 0;
@@ -210,7 +214,7 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         const int qy = MAJ == 1 ? k : (MAJ == 0 ? qa : qb);
         const int qz = MAJ == 2 ? k : qb;
         const int px = dx < 0 ? a0 - qx : qx;  // mirrored and shifted by |dx| when dx < 0
-        const int su = (qz * H + s1 * qy) * rst + (px >> 5);  // wave-uniform
+        const int su = ((qz * H + s1 * qy) * rst + (px >> 5)) * 4;  // wave-uniform
 #pragma unroll
         for (int q = 0; q < RPL; ++q) off[q] = Pq[q] + su + (qy >= Tq[q] ? wadj : 0);
         sh = px & 31;
@@ -227,8 +231,8 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
           uint32_t d0[R + 1], d1[R + 1];
 #pragma unroll
           for (int c = 0; c <= R; ++c) {
-            d0[c] = base[off0[q] + c];
-            d1[c] = base[off1[q] + c];
+            d0[c] = word(off0[q], c);
+            d1[c] = word(off1[q], c);
           }
 #pragma unroll
           for (int i = 0; i < R; ++i) {
@@ -246,7 +250,7 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         for (int q = 0; q < RPL; ++q) {
           uint32_t d[R + 1];
 #pragma unroll
-          for (int c = 0; c <= R; ++c) d[c] = base[off[q] + c];
+          for (int c = 0; c <= R; ++c) d[c] = word(off[q], c);
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const uint32_t t = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);
