@@ -96,18 +96,20 @@ def test_learned_draws_follow_scores(ctx):
     ch.close()
 
 
-@pytest.mark.parametrize("refresh", [1, 4])
-def test_learned_chain_stays_exact(ctx, refresh):
-    # learned steps keep counts equal to a full recount and e equal to eq. (LSE)
+@pytest.mark.parametrize("refresh,K", [(1, 64), (4, 64), (4, 200), (2, 200)])
+def test_learned_chain_stays_exact(ctx, refresh, K):
+    # learned steps keep counts equal to a full recount and e equal to eq. (LSE); with K > 64 the
+    # unranked learned draws (weights, inversion) are redrawn by round 0 in the draws' launch, and
+    # an evaluated pair that differed from the applied one would break the recount
     import torch
     from paper_1601_04359_amd import ProposalNet, step_records
     from oracle import cnn
-    print(f"[gpu] learned chain refresh {refresh}", flush=True)
+    print(f"[gpu] learned chain refresh {refresh} K {K}", flush=True)
     tgt, target, cell = _problem(side=32)
     ch = _chain(ctx, cell, 5, 3, target, tgt.size, 3)
     net = ProposalNet(ctx, 32, 32, 1, 4, torch.from_numpy(cnn.init_params(9)).cuda())
     ch.set_proposal(net=net, beta=1.0, eps_uniform=0.2, refresh=refresh)
-    recs = step_records(ch.run(64, np.full(80, 5e-5), 2))
+    recs = step_records(ch.run(K, np.full(80, 5e-5), 2))
     torch.cuda.synchronize()
     assert (recs["k"] >= 0).sum() > 5
     fresh = ctx.full(ch.bits, 32, 32, 5, 5, 3)
