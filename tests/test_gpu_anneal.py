@@ -166,6 +166,32 @@ def test_records_long_paths(ctx):
     ch.close()
 
 
+@pytest.mark.parametrize("method", ["recount", "records"])
+def test_three_rounds(ctx, method):
+    # K = 9000: rounds of 64, 8192 and 744 (round 0 decided in round 1, round 1 by the middle
+    # decision, round 2 at the end of the step).  From a crop of the target at T ~ 0 this seed
+    # accepts in round 0 (20 steps), round 1 (47), round 2 (steps 64 and 66) and none (1).
+    import torch
+    from paper_1601_04359_amd import step_records
+    print(f"[gpu] anneal three rounds K=9000 {method}", flush=True)
+    tgt = wl.boolean_disks(48, 48, 3.0, 0.4, 21)
+    target = oracle.lpf(tgt, 5, 5, 3)
+    cell = np.ascontiguousarray(tgt[:16, :16])
+    Ts = np.full(70, 1e-12)
+    ch = _gpu_chain(ctx, cell, 5, 3, target, tgt.size, 2, method=METHODS[method])
+    recs = step_records(ch.run(9000, Ts))
+    torch.cuda.synchronize()
+    ref = oracle.AnnealState(cell, 5, 5, 3, target, tgt.size, 2)
+    rres = ref.run(70, 9000, Ts)
+    assert [(int(r["k"]), int(r["a"]), int(r["b"])) for r in recs] == \
+        [(int(r["k"]), int(r["a"]), int(r["b"])) for r in rres]
+    assert np.array_equal(recs["de"], rres["de"])
+    k = recs["k"]
+    assert (k >= 8256).sum() >= 1 and ((k >= 64) & (k < 8256)).sum() >= 10 and (k < 0).sum() >= 1
+    assert np.array_equal(ch.counts.cpu().numpy().astype(np.uint32), ref.counts)
+    ch.close()
+
+
 def test_records_agree_with_recount(ctx):
     # after many accepted interchanges (incremental record updates), the records method's exact
     # energy changes of random and neighbouring interchanges equal the recount method's, and the
