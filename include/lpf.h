@@ -293,7 +293,8 @@ lpf_status lpf_anneal_run(lpf_anneal st, int n_candidates, int proposal, const d
  * = 64 draws with the highest fp32 key score[a] + score[b] among the first R = min(K, 4096)
  * (best first; ties, including -0 and +0, by draw index; a draw with a < 0 or b < 0, or a NaN
  * key, counts as -inf), then every other draw in draw order.  cand: int32[K][2] (device);
- * score: float per pixel (device); scratch from the context.
+ * score: float per pixel (device); scratch (40 KB) from the context, so calls on one context
+ * that are in flight on different streams at once race on it.
  * Errors: LPF_E_INVAL (K outside [1, 2^20], NULL), LPF_E_NOMEM, LPF_E_DEVICE. */
 lpf_status lpf_rank(lpf_ctx ctx, const int32_t *cand, const float *score, int K, int32_t *order,
                     void *stream);
