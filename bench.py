@@ -896,8 +896,8 @@ def main() -> int:
                   "roofline": {"bound": "alu", "achieved": round(s2_ach, 3),
                                "peak": round(P_INT_TOPS, 3), "unit": "Tops/s",
                                "frac": round(s2_ach / P_INT_TOPS, 4),
-                               "kernel": "k_s2_full (+k_ext, k_s2_zero, k_s2_finish inside the "
-                                         "event window)",
+                               "kernel": "k_s2_full (+k_s2_zero, k_s2_finish inside the event "
+                                         "window)",
                                "ops_alg_per_launch": s2_ops},
                   "unit_steps_equal_lpf": s2_unit_ok,
                   "note": "two-point counts W*H*S2 of the same image and cutoff (Sec. 2.1), "

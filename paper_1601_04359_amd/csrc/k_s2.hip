@@ -41,10 +41,29 @@ __global__ void k_s2_zero(uint32_t *__restrict__ acc, int64_t n) {
 // w is the family's shifted word at w + j, so one v_alignbit_b32 per word serves all J members.
 // group = {first family, end, dy of the first, dy of the last}, families sorted by dy.
 // LDS: A = the block's rows (swdp dwords each, zero past W), B = rows y0 + dy_lo ..
-// y0 + dy_hi + rb - 1 (mod H) of the extended image, rstB dwords apart, then the reduction.
+// y0 + dy_hi + rb - 1 (mod H) extended periodically to we dwords (ext_word, from the packed
+// image P, src_stride dwords per row), rstB dwords apart, then the reduction.
+// Word e of the periodic extension of a packed row (row32: the row as 32-bit words): bits
+// [32 e, 32 e + 32) taken modulo W.
+__device__ __forceinline__ uint32_t ext_word(const uint32_t *__restrict__ row32, int W, int e) {
+  const int s = (32 * e) % W;
+  if (s + 32 <= W) {
+    const int q = s >> 5, sh = s & 31;
+    return __builtin_amdgcn_alignbit(sh ? row32[q + 1] : 0u, row32[q], (uint32_t)sh);
+  }
+  uint32_t v = 0;
+  int x = s;
+  for (int b = 0; b < 32; ++b) {
+    v |= ((row32[x >> 5] >> (x & 31)) & 1u) << b;
+    x = x + 1 == W ? 0 : x + 1;
+  }
+  return v;
+}
+
 template <int J>
 __global__ void __launch_bounds__(256)
-k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swdp, int rb,
+k_s2_full(const uint32_t *__restrict__ P, int src_stride, int W, int H, int we, int swd, int swdp,
+          int rb,
           int rstB, int cx, int q1, const int4 *__restrict__ fams,
           const int4 *__restrict__ groups, uint32_t *__restrict__ acc) {
   constexpr int CW = 8;  // start words per chunk (swdp is a multiple of CW)
@@ -59,14 +78,14 @@ k_s2_full(const uint32_t *__restrict__ E, int W, int H, int we, int swd, int swd
   const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
   for (int i = threadIdx.x; i < rows * swdp; i += blockDim.x) {
     const int r = i / swdp, w = i - r * swdp;
-    uint32_t v = w < swd ? E[(size_t)(y0 + r) * we + w] : 0u;
+    uint32_t v = w < swd ? P[(size_t)(y0 + r) * src_stride + w] : 0u;
     if (w == swd - 1) v &= lastmask;
     A[i] = v;
   }
   for (int i = threadIdx.x; i < nB * we; i += blockDim.x) {
     const int r = i / we, e = i - r * we;
     const int y = (y0 + g.z + r) % H;
-    B[r * rstB + e] = E[(size_t)y * we + e];
+    B[r * rstB + e] = ext_word(P + (size_t)y * src_stride, W, e);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -168,7 +187,8 @@ hipError_t launch_s2_full(const S2Launch &L, hipStream_t stream) {
   const dim3 grid((unsigned)L.ngroups, (unsigned)L.nrb);
   const int q1 = (L.cx + 1) * (L.cy + 1);
 #define LPF_S2_FULL(JJ)                                                                        \
-  hipLaunchKernelGGL((k_s2_full<JJ>), grid, dim3(256), L.lds_bytes, stream, L.E, L.W, L.H, L.we, \
+  hipLaunchKernelGGL((k_s2_full<JJ>), grid, dim3(256), L.lds_bytes, stream, L.E,                \
+                     2 * ((L.W + 63) / 64), L.W, L.H, L.we,                                     \
                      L.swd, L.swdp, L.rb, L.rstB, L.cx, q1, L.fams, L.groups, L.acc)
   switch (L.J) {
     case 1: LPF_S2_FULL(1); break;

@@ -1212,13 +1212,10 @@ lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
   if ((st = get_s2_plan(c, W, H, cx, cy, plan)) != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  if ((e = c->s2ext.ensure((size_t)H * plan->we * sizeof(uint32_t))) != hipSuccess ||
-      (e = c->s2acc.ensure((size_t)plan->nv * sizeof(uint32_t))) != hipSuccess)
+  if ((e = c->s2acc.ensure((size_t)plan->nv * sizeof(uint32_t))) != hipSuccess)
     return hip_fail(e, "lpf_s2: scratch");
-  if ((e = launch_ext(bits, W, H, plan->we, (uint32_t *)c->s2ext.p, s)) != hipSuccess)
-    return hip_fail(e, "lpf_s2: ext");
   S2Launch L{};
-  L.E = (const uint32_t *)c->s2ext.p;
+  L.E = reinterpret_cast<const uint32_t *>(bits);  // the kernel extends the rows as it stages them
   L.W = W;
   L.H = H;
   L.we = plan->we;

@@ -338,7 +338,7 @@ hipError_t prepare_lpf3_kernels(int max_lds_bytes);
 // dy, in groups of at most 256 (one workgroup each), start rows in blocks of rb; acc holds the
 // phase-1 sums [nv] before the output is written.
 struct S2Launch {
-  const uint32_t *E;        // extended image, H x we dwords, we >= ((W + cx) >> 5) + swdp + J
+  const uint32_t *E;        // the packed image (rows of 2 ceil(W / 64) dwords), extended by the kernel
   int W, H, we, swd, swdp, J, rb, nrb, rstB, ngroups, cx, cy, layout;
   const int4 *fams;         // dy-sorted families
   const int4 *groups;       // {first, end, dy of first, dy of last}
