@@ -680,12 +680,15 @@ def batch_bench(args) -> dict:
             if W <= 512 and W not in tuned:
                 ctx.autotune(bits, W, H, cx, cy, 3, stream=stream)
                 tuned[W] = list(ctx.tuned_shape(W, H, cx, cy))
+                stream.synchronize()
+                print(f"  batch: tuned {W}x{H}", file=sys.stderr, flush=True)
         stream.synchronize()
         t_tune = time.perf_counter() - t_tune
         t_setup = time.perf_counter()
         counts, offs, pool, descs = ctx.batch(items, 3, 0, stream=stream)  # plans + capture + 1 run
         stream.synchronize()
         t_setup = time.perf_counter() - t_setup
+        print(f"  batch: plans, capture and first run {t_setup:.1f} s", file=sys.stderr, flush=True)
         for _ in range(max(0, args.warmup - 1)):
             _abi.lpf_batch(ctx.handle, pool, descs, 3, 0, counts, stream)
         stream.synchronize()
@@ -696,6 +699,9 @@ def batch_bench(args) -> dict:
             ev[i][0].record(stream)
             _abi.lpf_batch(ctx.handle, pool, descs, 3, 0, counts, stream)
             ev[i][1].record(stream)
+            # a launch takes about 20 s: wait for it (microseconds against the launch) to report
+            ev[i][1].synchronize()
+            print(f"  batch: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
         stream.synchronize()
         wall = time.perf_counter() - t0
     kern_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
@@ -758,7 +764,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"anneal": 20000, "learned": 20000, "mutual": 20000,
-                      "mc": 10000}.get(args.workload, 20)
+                      "mc": 10000, "batch": 3}.get(args.workload, 20)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is a design note, not an implemented path)", file=sys.stderr)
