@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblpf.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"liblpf.so not built at {LIB_PATH}; run `python -m paper_1601_04359_amd.build`")
+    raise ImportError(f"liblpf.so not built at {LIB_PATH}; run `python paper_1601_04359_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
