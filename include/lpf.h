@@ -79,7 +79,10 @@ int64_t lpf_num_vectors(int cx, int cy);
  * 2*|D_c| int16).  Errors: LPF_E_INVAL for negative or > 32767 cutoffs or NULL dxdy. */
 lpf_status lpf_vectors(int cx, int cy, int16_t *dxdy);
 
-/* Pack a uint8 image (row-major W*H bytes, nonzero = phase 1) into the bit layout above.
+/* Pack a uint8 image (row-major W*H bytes, nonzero = phase 1) into the bit layout above: the
+ * phase image that Alg. "L2_eval" reads pixel by pixel (its input A, whose 2 x 2 periodic tiling
+ * the paper builds on the host, Sec. 3.1) held as 64 pixels per word; the periodic halo is added
+ * on the device by each evaluation, so no tiled copy is made.
  * bits: ceil(W/64) * H uint64, written in full (padding bits zero).  One kernel launch.
  * Errors: LPF_E_INVAL for NULL pointers or W, H outside [1, 65535]. */
 lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bits, void *stream);
@@ -94,7 +97,7 @@ lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bit
 lpf_status lpf_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
 
-/* The paper's "enhanced" evaluation (Sec. 3.3: segments whose shorter overlapping segments
+/* The paper's "enhanced" evaluation (Sec. 3.2: segments whose shorter overlapping segments
  * already have no occurrence are not walked to the end), done exactly per wavefront: every 16
  * segment pixels a wavefront stops walking the segment once none of its start pixels can still
  * count for a requested phase.  Same arguments, same counts as lpf_full, bit for bit; the time
@@ -125,7 +128,7 @@ lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int c
                           unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
                           void *stream);
 
-/* ---- 3-D volumes (the extension of Sec. 2; the ensemble of cuts of Sec. 5) ---------------- */
+/* ---- 3-D volumes (the extension of Sec. 2; the ensemble of cuts of Sec. 6.3) ---------------- */
 
 /* Canonical half of the 3-D cutoff box: the 2-D half domain (lpf_vectors order) at dz = 0, then
  * for dz = 1..cz the rectangle [-cx,cx] x [-cy,cy] row by row (dy outer).  Count
@@ -140,7 +143,7 @@ lpf_status lpf_vectors3(int cx, int cy, int cz, int16_t *dxdydz);
  * max(|dx|,|dy|,|dz|), major axis the first of x, y, z with extent n, every minor coordinate
  * sgn(m) floor((2k|m| + n)/(2n)) (the 2-D rule per axis).  bits: the volume as D*H packed rows
  * (row z*H + y, lpf_pack of the (D*H) x W byte array), read only.  With cz = 0 the counts are the
- * sums over the D xy-cuts of their 2-D functions (lpf_full), the ensemble average of Sec. 5 times
+ * sums over the D xy-cuts of their 2-D functions (lpf_full), the ensemble average of Sec. 6.3 times
  * D*W*H.  Requires 1 <= W, H, D <= 65535, W*H*D < 2^32, 0 <= cx <= W-1, 0 <= cy <= H-1,
  * 0 <= cz <= D-1, cutoffs <= 32767, phase_mask in {1,2,3}.
  * Errors: LPF_E_INVAL, LPF_E_UNSUPPORTED (W > 32768, too many vectors), LPF_E_NOMEM,
@@ -148,7 +151,7 @@ lpf_status lpf_vectors3(int cx, int cy, int cz, int16_t *dxdydz);
 lpf_status lpf_full3d(lpf_ctx ctx, const uint64_t *bits, int W, int H, int D, int cx, int cy,
                       int cz, unsigned phase_mask, uint32_t *counts, void *stream);
 
-/* ---- two-point probability (Sec. 2.1, eq. (S2dis)), the descriptor compared with in Sec. 5 --- */
+/* ---- two-point probability (Sec. 2.1, eq. (S2dis)), the descriptor compared with in Secs. 5 and 6.1 --- */
 
 /* Two-point counts C_p(v) = W H S2^p(v): the number of pixels x of the periodic image with x and
  * x + v both in phase p, for every vector v of D_c (only its end point matters, no segment) and

@@ -81,7 +81,7 @@ hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
 // OR (v_or3_b32) per word; when both pixels of a pair read the same dwords (same row, same
 // word column) the dwords are loaded once.
 //
-// SKIP (the paper's "enhanced" evaluation, Sec. 3.3, done per wave): every 16 pixels the wave
+// SKIP (the paper's "enhanced" evaluation, Sec. 3.2, done per wave): every 16 pixels the wave
 // stops when no start pixel of its rows can still count for a requested phase (phase 1 needs a
 // set bit of A, phase 0 a clear bit of O, both under the lane's valid-bit mask mk).  Further
 // pixels only clear bits of A and set bits of O, so the counts are those of the full product.

@@ -1,5 +1,5 @@
 // Lineal path function of a periodic 3-D volume (the extension of Sec. 2; with cz = 0 it is the
-// sum over the xy-cuts of their 2-D functions, the ensemble of cuts of Sec. 5).
+// sum over the xy-cuts of their 2-D functions, the ensemble of cuts of Sec. 6.3).
 //
 // Same bit-parallel product as the 2-D kernel: 32 start voxels of one x-row share a word; for a
 // segment voxel (px, py, pz) a lane forms t = bits [32w + px, 32w + px + 32) of row

@@ -1,6 +1,6 @@
 // Two-point probability (Sec. 2.1, eq. (S2dis)) on gfx950: full evaluation over the canonical
 // half domain, its change under a pixel interchange, and the annealing rounds that use it as the
-// descriptor (the comparison of Sec. 5).
+// descriptor (the comparison of Secs. 5 and 6.1).
 //
 // Counts, not probabilities: C_p(v) = W H S2^p(v) = #{x : I(x) = p and I(x + v) = p} on the
 // periodic image.  The paper evaluates S2 with the FFT over all W x H shifts; over a cutoff

@@ -1,5 +1,5 @@
 """3-D volumes on the GPU (lpf_full3d) against the CPU oracle, bit for bit; with cz = 0 against
-the sum of the 2-D functions of the xy-cuts (the ensemble of cuts of Sec. 5)."""
+the sum of the 2-D functions of the xy-cuts (the ensemble of cuts of Sec. 6.3)."""
 from __future__ import annotations
 
 import numpy as np

@@ -1,4 +1,4 @@
-"""The particulate-suspension comparison of Sec. 5 (Table mutual) on a synthetic medium: a
+"""The particulate-suspension comparison of Sec. 6.1 (Table mutual) on a synthetic medium: a
 100 x 100 image of non-touching 4 x 4 squares compressed into a 50 x 50 cell by annealing on S2,
 on L2 of both phases, of the particles (w) and of the matrix (b), every result evaluated under
 both descriptors.  The run is seeded and every step exact, so it is deterministic; the test

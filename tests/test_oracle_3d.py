@@ -1,4 +1,4 @@
-"""Pins of the oracle's 3-D extension (Sec. 2: the extension to three dimensions; Sec. 5: a 3-D
+"""Pins of the oracle's 3-D extension (Sec. 2: the extension to three dimensions; Sec. 6.3: a 3-D
 specimen described by an ensemble of 2-D cuts), on the CPU."""
 from __future__ import annotations
 

@@ -73,7 +73,7 @@ def test_memory_formula_rect(W, H):
 
 
 def test_paper_op_count_100():
-    # Sec. 5.3: one standard evaluation of one phase at 100 x 100 px takes 6.716e9 operations,
+    # Sec. 6.3: one standard evaluation of one phase at 100 x 100 px takes 6.716e9 operations,
     # i.e. WH times the pixel count of the segments of the first rectangle of eq. (segments).
     W = H = 100
     ops = W * H * _path_len_sum(W, H, quadrant_only=True)

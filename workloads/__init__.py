@@ -118,7 +118,7 @@ def checkerboard(W: int, H: int, s: int) -> np.ndarray:
 
 
 def square_particles(W: int, H: int, size: int, n: int, seed: int, tries: int = 100000) -> np.ndarray:
-    """Particulate suspension of Sec. 5: n equal size x size phase-1 squares placed one by one
+    """Particulate suspension of Sec. 6.1: n equal size x size phase-1 squares placed one by one
     at uniform random positions of the periodic W x H cell, a placement rejected when it would
     overlap or touch (share an edge with) a square already placed."""
     g = rng(seed)
@@ -154,7 +154,7 @@ def gaussian_field_3d(W: int, H: int, D: int, corr: float, phi: float, seed: int
     """Periodic level-cut Gaussian random field, uint8 (D, H, W): white noise smoothed by a
     periodic Gaussian of standard deviation `corr` voxels (FFT), phase 1 where the field exceeds
     its (1 - phi) quantile.  At phi ~ 0.5 both phases form continuous irregular branches, the
-    morphology of the trabecular-bone specimen of Sec. 5."""
+    morphology of the trabecular-bone specimen of Sec. 6.3."""
     g = rng(seed)
     noise = g.standard_normal((D, H, W))
     kz = np.fft.fftfreq(D)[:, None, None]
