@@ -62,6 +62,9 @@ def _load():
     lib.oracle_anneal_run_desc.argtypes = [P, i32, i32, i32, i32, u32, i32, P, P, i64, u64, u64,
                                            i32, i32, P, i32, P, P, P, P, i32]
     lib.oracle_anneal_run_desc.restype = i32
+    lib.oracle_anneal_run_ranked.argtypes = [P, i32, i32, i32, i32, u32, P, P, i64, u64, u64,
+                                             i32, i32, P, i32, P, P, P, P, P, i32]
+    lib.oracle_anneal_run_ranked.restype = i32
     lib.oracle_lpf_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, i32]
     lib.oracle_lpf_sampled.restype = i32
     lib.oracle_delta_swap_sampled.argtypes = [P, i32, i32, i32, i32, u32, P, P, i32, P, i32]
@@ -329,12 +332,24 @@ class AnnealState:
         self.N = self.W * self.H if self.sample is None else int(np.count_nonzero(self.sample))
         self.e = lse(self.counts, self.target, self.N, self.Nt)
 
-    def run(self, nsteps: int, K: int, Ts, proposal: int = 0) -> np.ndarray:
+    def run(self, nsteps: int, K: int, Ts, proposal: int = 0, score=None) -> np.ndarray:
+        """nsteps steps of K draws each; with `score` (float32 per pixel) every step evaluates
+        its draws in the ranked order of that field (reading R18) instead of draw order."""
         Ts = np.ascontiguousarray(Ts, dtype=np.float64)
         assert Ts.size == nsteps
         res = np.zeros(nsteps, STEP_DTYPE)
         e = np.array([self.e], np.float64)
-        if self.sample is not None:
+        if score is not None:
+            if self.sample is not None or self.descriptor != DESC_LPF:
+                raise ValueError("the ranked order is implemented for the plain lineal path chain")
+            sc = np.ascontiguousarray(score, dtype=np.float32).reshape(-1)
+            assert sc.size == self.W * self.H
+            rc = _load().oracle_anneal_run_ranked(
+                _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask,
+                _ptr(self.counts), _ptr(self.target), self.Nt, self.seed, self.step, nsteps, K,
+                _ptr(Ts), proposal, _ptr(sc), _ptr(self.pos1), _ptr(self.pos0), _ptr(e),
+                _ptr(res), self.nthreads)
+        elif self.sample is not None:
             rc = _load().oracle_anneal_run_sampled(
                 _ptr(self.img), self.W, self.H, self.cx, self.cy, self.phase_mask,
                 _ptr(self.sample), _ptr(self.counts), _ptr(self.target), self.Nt, self.seed,

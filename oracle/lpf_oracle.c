@@ -26,7 +26,9 @@
  *                           contain a swapped pixel.
  *   - oracle_anneal_run     Sec. 4, Alg. "annealing" + eq. (LSE): Metropolis rule on pixel
  *                           interchanges, with the batched first-accept step described there;
- *                           oracle_anneal_run_desc also anneals against S2 (Sec. 5 comparison).
+ *                           oracle_anneal_run_desc also anneals against S2 (the comparison of Secs. 5 and 6.1);
+ *                           oracle_anneal_run_ranked evaluates each step's draws in the ranked
+ *                           order of a given score field (reading R18).
  *   - oracle_philox4x64     Salmon et al., SC'11 "Parallel random numbers: as easy as 1, 2, 3",
  *                           Philox-4x64 with 10 rounds.
  *
@@ -337,7 +339,7 @@ int oracle_s2(const uint8_t *img, int W, int H, int cx, int cy, unsigned phase_m
 }
 
 /* ------------------------------------------------------------------------------------------
- * Three-dimensional extension (Sec. 2 calls it straightforward; Sec. 5 uses a 3-D specimen).
+ * Three-dimensional extension (Sec. 2 calls it straightforward; Sec. 6.3 uses a 3-D specimen).
  * Voxel (x, y, z) of a W x H x D periodic volume is vol[(z*H + y)*W + x].
  *
  * Digitised segment from (0,0,0) to (dx,dy,dz): n = max(|dx|,|dy|,|dz|); the major axis is x
@@ -713,6 +715,13 @@ void oracle_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint6
  * Energy change, exact in integers:  S = sum dL * (Nt * (dL + 2 L) - 2 N T),
  *   de = (double)S / ((double)N * (double)N * (double)Nt).
  * Acceptance: de <= 0 or U < exp(-de / T_s).
+ *
+ * Ranked evaluation (reading R18 of the learned proposal; the paper leaves the operator open,
+ * Sec. 4): given a per-pixel score field, the step still draws the same K candidates, but
+ * evaluates first the min(64, R) draws with the largest fp32 key score[a] + score[b] among the
+ * first R = min(K, 4096) draws (largest first, equal keys by draw index; a void draw or a NaN key
+ * counts as -infinity), then every other draw in draw order; the first of this order that
+ * passes the Metropolis test is applied, and its draw index is recorded.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   int32_t k, a, b;
@@ -738,14 +747,44 @@ double oracle_lse(const uint32_t *counts, const uint32_t *target, int64_t nterms
 }
 
 /* descriptor 0: the lineal path function (counts = L); descriptor 1: the two-point probability
- * (counts = W H S2, Sec. 2.1), the descriptor the paper compares against in Sec. 5. */
+ * (counts = W H S2, Sec. 2.1), the descriptor the paper compares against in Secs. 5 and 6.1. */
 /* sample (LPF only): the Monte-Carlo position set of the cell; the counts are then sampled
  * counts and N in the objective is the number of sampled positions. */
+/* The evaluation order of one step (ranked evaluation above): order[0..K). */
+static void ranked_order(const int32_t *ca, const int32_t *cb, int K, const float *score,
+                         int32_t *order, uint8_t *chosen) {
+  int R = K < 4096 ? K : 4096;
+  int top = R < 64 ? R : 64;
+  for (int k = 0; k < K; ++k) chosen[k] = 0;
+  for (int t = 0; t < top; ++t) {
+    int best = -1;
+    float best_key = 0.0f;
+    for (int k = 0; k < R; ++k) {
+      if (chosen[k]) continue;
+      float key = -INFINITY;
+      if (ca[k] >= 0 && cb[k] >= 0) {
+        key = score[ca[k]] + score[cb[k]];
+        if (isnan(key)) key = -INFINITY;
+      }
+      if (best < 0 || key > best_key) {
+        best = k;
+        best_key = key;
+      }
+    }
+    chosen[best] = 1;
+    order[t] = best;
+  }
+  int t = top;
+  for (int k = 0; k < K; ++k)
+    if (!chosen[k]) order[t++] = k;
+}
+
 static int anneal_core(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
                        int descriptor, const uint8_t *sample, uint32_t *counts,
                        const uint32_t *target, int64_t Nt, uint64_t seed, uint64_t step0,
-                       int nsteps, int K, const double *Ts, int proposal, int32_t *pos1,
-                       int32_t *pos0, double *e_io, oracle_step_result *res, int nthreads) {
+                       int nsteps, int K, const double *Ts, int proposal, const float *score,
+                       int32_t *pos1, int32_t *pos0, double *e_io, oracle_step_result *res,
+                       int nthreads) {
   if (W < 1 || H < 1 || cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1 || K < 1) return -22;
   if (descriptor != 0 && descriptor != 1) return -22;
   if (sample && descriptor != 0) return -22;
@@ -765,6 +804,12 @@ static int anneal_core(uint8_t *img, int W, int H, int cx, int cy, unsigned phas
   oracle_vectors(cx, cy, v);
   int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * nph * nv);
   int32_t sw[2];
+  /* the step's draws: slots, pixels (a = -1 for a void draw) and uniforms */
+  int32_t *cia = (int32_t *)malloc(sizeof(int32_t) * K), *cib = (int32_t *)malloc(sizeof(int32_t) * K);
+  int32_t *ca = (int32_t *)malloc(sizeof(int32_t) * K), *cb = (int32_t *)malloc(sizeof(int32_t) * K);
+  double *cu = (double *)malloc(sizeof(double) * K);
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * K);
+  uint8_t *chosen = (uint8_t *)malloc(K);
   double e = *e_io;
   for (int s = 0; s < nsteps; ++s) {
     uint64_t step = step0 + (uint64_t)s;
@@ -772,11 +817,23 @@ static int anneal_core(uint8_t *img, int W, int H, int cx, int cy, unsigned phas
     for (int k = 0; k < K; ++k) {
       uint64_t ctr[4] = {step, (uint64_t)k, 0, 0}, key[2] = {seed, 0x6c7066ULL}, o[4];
       oracle_philox4x64(ctr, key, o);
-      int ia = (int)(((o[0] >> 32) * (uint64_t)n1) >> 32);
-      int ib = (int)(((o[1] >> 32) * (uint64_t)n0) >> 32);
-      double U = (double)(o[2] >> 11) * (1.0 / 9007199254740992.0);
-      int a = pos1[ia], b = pos0[ib];
-      if (proposal == 1 && !(interfacial(img, W, H, a) && interfacial(img, W, H, b))) continue;
+      cia[k] = (int)(((o[0] >> 32) * (uint64_t)n1) >> 32);
+      cib[k] = (int)(((o[1] >> 32) * (uint64_t)n0) >> 32);
+      cu[k] = (double)(o[2] >> 11) * (1.0 / 9007199254740992.0);
+      ca[k] = pos1[cia[k]];
+      cb[k] = pos0[cib[k]];
+      if (proposal == 1 && !(interfacial(img, W, H, ca[k]) && interfacial(img, W, H, cb[k])))
+        ca[k] = cb[k] = -1;
+    }
+    if (score)
+      ranked_order(ca, cb, K, score, order, chosen);
+    else
+      for (int k = 0; k < K; ++k) order[k] = k;
+    for (int t = 0; t < K; ++t) {
+      int k = order[t];
+      int ia = cia[k], ib = cib[k], a = ca[k], b = cb[k];
+      double U = cu[k];
+      if (a < 0) continue;
       sw[0] = a;
       sw[1] = b;
       if (descriptor == 0)
@@ -810,6 +867,13 @@ static int anneal_core(uint8_t *img, int W, int H, int cx, int cy, unsigned phas
   *e_io = e;
   free(v);
   free(dl);
+  free(cia);
+  free(cib);
+  free(ca);
+  free(cb);
+  free(cu);
+  free(order);
+  free(chosen);
   return 0;
 }
 
@@ -821,7 +885,7 @@ int oracle_anneal_run_desc(uint8_t *img, int W, int H, int cx, int cy, unsigned 
                            int proposal, int32_t *pos1, int32_t *pos0 /* in/out */,
                            double *e_io, oracle_step_result *res /* [nsteps] */, int nthreads) {
   return anneal_core(img, W, H, cx, cy, phase_mask, descriptor, NULL, counts, target, Nt, seed,
-                     step0, nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+                     step0, nsteps, K, Ts, proposal, NULL, pos1, pos0, e_io, res, nthreads);
 }
 
 int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
@@ -830,7 +894,18 @@ int oracle_anneal_run(uint8_t *img, int W, int H, int cx, int cy, unsigned phase
                       int32_t *pos1, int32_t *pos0, double *e_io, oracle_step_result *res,
                       int nthreads) {
   return anneal_core(img, W, H, cx, cy, phase_mask, 0, NULL, counts, target, Nt, seed, step0,
-                     nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+                     nsteps, K, Ts, proposal, NULL, pos1, pos0, e_io, res, nthreads);
+}
+
+/* The chain with the ranked evaluation order over a fixed score field (score: float [W*H]). */
+int oracle_anneal_run_ranked(uint8_t *img, int W, int H, int cx, int cy, unsigned phase_mask,
+                             uint32_t *counts, const uint32_t *target, int64_t Nt,
+                             uint64_t seed, uint64_t step0, int nsteps, int K, const double *Ts,
+                             int proposal, const float *score, int32_t *pos1, int32_t *pos0,
+                             double *e_io, oracle_step_result *res, int nthreads) {
+  if (!score) return -22;
+  return anneal_core(img, W, H, cx, cy, phase_mask, 0, NULL, counts, target, Nt, seed, step0,
+                     nsteps, K, Ts, proposal, score, pos1, pos0, e_io, res, nthreads);
 }
 
 /* The chain driven by the Monte-Carlo approximation: counts = oracle_lpf_sampled of img over the
@@ -842,5 +917,5 @@ int oracle_anneal_run_sampled(uint8_t *img, int W, int H, int cx, int cy, unsign
                               double *e_io, oracle_step_result *res, int nthreads) {
   if (!sample) return -22;
   return anneal_core(img, W, H, cx, cy, phase_mask, 0, sample, counts, target, Nt, seed, step0,
-                     nsteps, K, Ts, proposal, pos1, pos0, e_io, res, nthreads);
+                     nsteps, K, Ts, proposal, NULL, pos1, pos0, e_io, res, nthreads);
 }

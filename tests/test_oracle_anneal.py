@@ -31,8 +31,23 @@ def _lse_exact(counts, target, N, Nt):
                for c, t in zip(counts.ravel(), target.ravel()))
 
 
+def _ranked(cands, score):
+    # reading R18, by sorting: the min(64, R) largest fp32 keys among the first R = min(K, 4096)
+    # draws (equal keys by draw index; void draws and NaN keys lowest), then the rest in order
+    K = len(cands)
+    R = min(K, 4096)
+    key = np.full(R, -np.inf)
+    for k in range(R):
+        a, b = cands[k][0], cands[k][1]
+        if a >= 0:
+            v = np.float32(score[a]) + np.float32(score[b])
+            key[k] = -np.inf if np.isnan(v) else float(v) + 0.0  # -0 and +0 are one key
+    top = list(np.lexsort((np.arange(R), -key))[:min(R, 64)])
+    return top + [k for k in range(K) if k not in set(top)]
+
+
 def _reference_chain(img, cx, cy, mask, target, Nt, seed, step0, nsteps, K, Ts, proposal,
-                     descriptor=oracle.DESC_LPF):
+                     descriptor=oracle.DESC_LPF, score=None):
     img = img.copy()
     H, W = img.shape
     N = W * H
@@ -42,22 +57,29 @@ def _reference_chain(img, cx, cy, mask, target, Nt, seed, step0, nsteps, K, Ts, 
     evaluate = oracle.lpf if descriptor == oracle.DESC_LPF else oracle.s2
     counts = evaluate(img, cx, cy, mask).astype(np.int64)
     out = []
+    def itf(q):
+        x, y = q % W, q // W
+        v = img[y, x]
+        return (img[y, (x + 1) % W] != v or img[y, (x - 1) % W] != v or
+                img[(y + 1) % H, x] != v or img[(y - 1) % H, x] != v)
+
     for s in range(nsteps):
         res = (-1, -1, -1)
+        draws = []
         for k in range(K):
             r = _block(seed, step0 + s, k)
             ia = ((r[0] >> 32) * len(pos1)) >> 32
             ib = ((r[1] >> 32) * len(pos0)) >> 32
             U = (r[2] >> 11) * 2.0**-53
             a, b = int(pos1[ia]), int(pos0[ib])
-            if proposal == 1:
-                def itf(q):
-                    x, y = q % W, q // W
-                    v = img[y, x]
-                    return (img[y, (x + 1) % W] != v or img[y, (x - 1) % W] != v or
-                            img[(y + 1) % H, x] != v or img[(y - 1) % H, x] != v)
-                if not (itf(a) and itf(b)):
-                    continue
+            if proposal == 1 and not (itf(a) and itf(b)):
+                a = b = -1
+            draws.append((a, b, ia, ib, U))
+        order = range(K) if score is None else _ranked(draws, score)
+        for k in order:
+            a, b, ia, ib, U = draws[k]
+            if a < 0:
+                continue
             img2 = img.copy()
             img2.flat[a], img2.flat[b] = 0, 1
             dl = evaluate(img2, cx, cy, mask).astype(np.int64) - counts
@@ -100,7 +122,7 @@ def test_anneal_matches_reference_chain(proposal):
 
 @pytest.mark.parametrize("proposal,mask", [(0, 3), (1, 3), (0, 2)])
 def test_s2_anneal_matches_reference_chain(proposal, mask):
-    # the same chain with the two-point probability as the descriptor (Sec. 2.1 and Sec. 5)
+    # the same chain with the two-point probability as the descriptor (Sec. 2.1; Secs. 5 and 6.1)
     tgt = wl.square_particles(40, 40, 4, 16, 5)
     cx = cy = 5
     target = oracle.s2(tgt, cx, cy, mask)
@@ -143,3 +165,37 @@ def test_anneal_invariants():
     acc = res[res["k"] >= 0]
     assert len(acc) > 0
     assert np.allclose(np.cumsum(acc["de"]) + e0, acc["e"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("K,proposal", [(5, 0), (16, 1), (100, 0), (100, 1)])
+def test_ranked_anneal_matches_reference_chain(K, proposal):
+    # the chain that evaluates each step's draws in the ranked order of a fixed score field
+    # (reading R18) against the reference route with the order taken by sorting
+    tgt = wl.boolean_disks(32, 32, 3.0, 0.4, 6)
+    cx = cy = 4
+    mask = 3
+    target = oracle.lpf(tgt, cx, cy, mask)
+    cell = wl.random_cell(12, 12, int(round(0.4 * 144)), 10)
+    g = np.random.default_rng(K + 7 * proposal)
+    score = np.round(g.normal(size=144), 1).astype(np.float32)  # many equal keys
+    score[::11] = -0.0
+    score[5::13] = 0.0
+    score[7] = np.nan
+    seed = 91
+    nsteps = 20
+    Ts = 1e-4 * 0.85 ** np.arange(nsteps)
+    st = oracle.AnnealState(cell, cx, cy, mask, target, tgt.size, seed)
+    st.step = 1
+    res = st.run(nsteps, K, Ts, proposal, score=score)
+    ref, img_ref, counts_ref = _reference_chain(cell, cx, cy, mask, target, tgt.size, seed, 1,
+                                                nsteps, K, Ts, proposal, score=score)
+    got = [(int(r["k"]), int(r["a"]), int(r["b"])) for r in res]
+    assert got == ref
+    assert np.array_equal(st.img, img_ref)
+    assert np.array_equal(st.counts.astype(np.int64), counts_ref)
+    # the order matters: some accepted draw is not the first acceptable one in draw order
+    plain = oracle.AnnealState(cell, cx, cy, mask, target, tgt.size, seed)
+    plain.step = 1
+    pres = plain.run(nsteps, K, Ts, proposal)
+    if K > 5:
+        assert [int(r["k"]) for r in pres] != [r[0] for r in ref]
