@@ -116,6 +116,19 @@ lpf_status lpf_full_sampled(lpf_ctx ctx, const uint64_t *bits, int W, int H, int
                             unsigned phase_mask, int out_layout, const uint64_t *sample,
                             uint32_t *counts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the counts of lpf_full, bit for bit, from a call that
+ * allocates nothing.  Its only scratch, the periodically extended image (H rows of
+ * ceil(W/32) rounded up to the lane layout, plus cx/32 + 1 dwords), lives in a fixed 4 MiB
+ * device array of the library (one per GPU, held until the process ends); it uses no vector
+ * table (each wavefront derives its vectors from their canonical indices), so nothing is cached
+ * either.  Every call on one GPU shares that array: calls that overlap on one GPU (any context,
+ * any stream) race and must be serialised by the caller.  Arguments, layouts and errors as
+ * lpf_full, plus LPF_E_UNSUPPORTED when the extended image exceeds 4 MiB (W = H = 4096 with
+ * cx = 128 needs 4096 * 133 * 4 bytes = 2.1 MiB and fits; W = H = 8192 does not). */
+lpf_status lpf_full_noalloc(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
+                            unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
+
 /* Exact change of the lineal path function under pixel interchanges (Sec. 4 modification
  * operator: the values of pixels a and b are exchanged, which preserves the volume fractions).
  * swaps: int32[n][2] linear pixel indices y*W + x (device).  delta: int32[n][nph][|D_c|] (device,

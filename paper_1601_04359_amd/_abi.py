@@ -53,6 +53,7 @@ _sig("lpf_vectors", _i32, _i32, _i32, _P)
 _sig("lpf_pack", _i32, _P, _P, _i32, _i32, _P, _P)
 _sig("lpf_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
 _sig("lpf_full_enhanced", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_full_noalloc", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
 _sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
 _sig("lpf_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
@@ -194,6 +195,19 @@ def lpf_full_enhanced(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy:
     _check(_lib.lpf_full_enhanced(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy,
                                   phase_mask, out_layout, _dev(counts, torch.int32, "counts"),
                                   _stream(stream)))
+
+
+def lpf_full_noalloc(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,
+                     phase_mask: int, out_layout: int, counts: torch.Tensor,
+                     stream=None) -> None:
+    if bits.numel() != ((W + 63) // 64) * H:
+        raise ValueError("lpf_full_noalloc: bits size does not match W, H")
+    shp = counts_shape(cx, cy, phase_mask, out_layout) if 0 <= cx and 0 <= cy else None
+    if shp is not None and counts.numel() != int(torch.Size(shp).numel()):
+        raise ValueError(f"lpf_full_noalloc: counts must hold {shp} elements")
+    _check(_lib.lpf_full_noalloc(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy,
+                                 phase_mask, out_layout, _dev(counts, torch.int32, "counts"),
+                                 _stream(stream)))
 
 
 def lpf_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,

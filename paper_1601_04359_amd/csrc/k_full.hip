@@ -189,11 +189,31 @@ __device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int 
   }
 }
 
+// Vector i of the canonical half domain: [0,cx] x [0,cy] row by row, then [-cx,-1] x [1,cy].
+__device__ __forceinline__ VecDesc canonical_vec(int i, int cx, int cy) {
+  const int n1 = (cx + 1) * (cy + 1);
+  VecDesc v;
+  v.idx = i;
+  if (i < n1) {
+    const int dy = i / (cx + 1);
+    v.dy = (int16_t)dy;
+    v.dx = (int16_t)(i - dy * (cx + 1));
+  } else {
+    const int r = i - n1;
+    const int dy = r / cx;
+    v.dy = (int16_t)(1 + dy);
+    v.dx = (int16_t)(-cx + (r - dy * cx));
+  }
+  return v;
+}
+
 // One work item: waves w = 0..wpg-1 of the workgroup take bins bin0 + w of image I and count
 // their vectors over every row tile of the image.  lds: staged rows; cnt: per-wave count slots
 // (used only when the image has several row tiles).  Each count is written once, by lane 0 of
 // the wave owning the vector.
-template <int R, bool SKIP>
+// CANON: no vector table; the wave with global index g of the I.nbins waves takes the canonical
+// vectors g, g + nbins, g + 2 nbins, ... (interleaving spreads long and short vectors evenly).
+template <int R, bool SKIP, bool CANON = false>
 __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg,
                                              unsigned phase_mask, uint32_t *__restrict__ lds,
                                              uint32_t *__restrict__ cnt) {
@@ -205,8 +225,18 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
   const int swd = (I.W + 31) >> 5;
   const uint32_t lastmask = (I.W & 31) ? ((1u << (I.W & 31)) - 1u) : 0xffffffffu;
   const int bin = bin0 + wave;
-  const int vb = bin < I.nbins ? I.bin_off[bin] : 0;
-  const int ve = bin < I.nbins ? I.bin_off[bin + 1] : 0;
+  int vb, ve;
+  if constexpr (CANON) {
+    vb = 0;
+    ve = bin < I.nbins && bin < I.nv ? (I.nv - 1 - bin) / I.nbins + 1 : 0;
+  } else {
+    vb = bin < I.nbins ? I.bin_off[bin] : 0;
+    ve = bin < I.nbins ? I.bin_off[bin + 1] : 0;
+  }
+  auto vec_at = [&](int j) -> VecDesc {
+    if constexpr (CANON) return canonical_vec(bin + j * I.nbins, I.cx, I.cy);
+    else return I.vecs[j];
+  };
   const bool tiled = I.ntiles > 1;
   for (int t_id = 0; t_id < I.ntiles; ++t_id) {
     const int Y0 = t_id * I.tile;
@@ -222,7 +252,7 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
     __syncthreads();
     const int nbands = (rows_here + rpw - 1) / rpw;
     for (int j = vb; j < ve; ++j) {
-      const VecDesc v = I.vecs[j];
+      const VecDesc v = vec_at(j);
       const int dx = v.dx, dy = v.dy;
       const int adx = dx < 0 ? -dx : dx;
       const int n = adx > dy ? adx : dy;
@@ -282,7 +312,7 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
   }
   if (tiled && lane == 0) {
     for (int j = vb; j < ve; ++j) {
-      const VecDesc v = I.vecs[j];
+      const VecDesc v = vec_at(j);
       const uint32_t *slot = cnt + 2 * (wave * kMaxBin + (j - vb));
       int p = 0;
       if (phase_mask & 1) put_count(I, p++, v.idx, v.dx, v.dy, slot[0]);
@@ -297,6 +327,14 @@ __global__ void __launch_bounds__(1024)
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   process_item<R, SKIP>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
+}
+
+// One image without a vector table (canonical vectors interleaved over the waves).
+template <int R>
+__global__ void __launch_bounds__(1024)
+k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
+  extern __shared__ uint32_t lds[];
+  process_item<R, false, true>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
 }
 
 // Many images, persistent workgroups drawing work items from a device counter in descending
@@ -355,6 +393,29 @@ static hipError_t launch_full_s(const FullImg &I, const FullShape &sh, unsigned 
     case 4: return launch_full_r<4, SKIP>(I, sh, phase_mask, stream);
     case 8: return launch_full_r<8, SKIP>(I, sh, phase_mask, stream);
     case 16: return launch_full_r<16, SKIP>(I, sh, phase_mask, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int R>
+static hipError_t launch_canon_r(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                                 hipStream_t stream) {
+  const int nwg = sh.nbins / sh.wpg;
+  const size_t lds = full_lds_bytes(sh, sh.wpg);
+  const int cnt_off = sh.lds_rows * sh.rst;
+  hipLaunchKernelGGL((k_lpf_full_canon<R>), dim3(nwg), dim3(64 * sh.wpg), lds, stream, I,
+                     sh.wpg, phase_mask, cnt_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_full_canon(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                             hipStream_t stream) {
+  switch (sh.R) {
+    case 1: return launch_canon_r<1>(I, sh, phase_mask, stream);
+    case 2: return launch_canon_r<2>(I, sh, phase_mask, stream);
+    case 4: return launch_canon_r<4>(I, sh, phase_mask, stream);
+    case 8: return launch_canon_r<8>(I, sh, phase_mask, stream);
+    case 16: return launch_canon_r<16>(I, sh, phase_mask, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -418,7 +479,10 @@ hipError_t prepare_full_kernels(int max_lds_bytes) {
                        (const void *)k_lpf_full<4, false>, (const void *)k_lpf_full<8, false>,
                        (const void *)k_lpf_full<16, false>, (const void *)k_lpf_full<1, true>,
                        (const void *)k_lpf_full<2, true>, (const void *)k_lpf_full<4, true>,
-                       (const void *)k_lpf_full<8, true>, (const void *)k_lpf_full<16, true>};
+                       (const void *)k_lpf_full<8, true>, (const void *)k_lpf_full<16, true>,
+                       (const void *)k_lpf_full_canon<1>, (const void *)k_lpf_full_canon<2>,
+                       (const void *)k_lpf_full_canon<4>, (const void *)k_lpf_full_canon<8>,
+                       (const void *)k_lpf_full_canon<16>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
     if (r != hipSuccess) e = r;

@@ -17,6 +17,12 @@
 
 using namespace lpf;
 
+// Fixed device scratch of lpf_full_noalloc: the extended image (H rows of `we` dwords).  Host
+// code never passes this name to a kernel or a copy: it stands for a host-side shadow, and the
+// device address comes from hipGetSymbolAddress (one per device, taken at context creation).
+constexpr size_t kNoAllocWords = (size_t)1 << 20;  // 4 MiB
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
 namespace {
 
 thread_local std::string g_err;
@@ -157,8 +163,14 @@ constexpr int kBigLds = kMaxLds - kBatchStaticLds;
 
 }  // namespace
 
+// Device address of `scratch` per HIP device (filled once per device at context creation).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices] = {};
+
 struct lpf_ctx_s {
   int dev = 0;
+  uint32_t *noalloc_scratch = nullptr;  // this device's address of `scratch`
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
@@ -932,6 +944,24 @@ lpf_status lpf_ctx_create(int hip_device, lpf_ctx *out) {
     delete c;
     return hip_fail(e, "lpf_ctx_create: kernel attributes");
   }
+  if (hip_device >= kMaxDevices) {
+    delete c;
+    return fail(LPF_E_UNSUPPORTED, "lpf_ctx_create: device index above 63");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[hip_device]) {
+      void *p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        delete c;
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                        "lpf_ctx_create: address of the no-alloc scratch");
+      }
+      g_scratch_ptr[hip_device] = (uint32_t *)p;
+    }
+    c->noalloc_scratch = g_scratch_ptr[hip_device];
+  }
   *out = c;
   return LPF_OK;
 }
@@ -1021,6 +1051,70 @@ lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int 
 lpf_status lpf_full(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream) {
   return full_impl(c, bits, W, H, cx, cy, phase_mask, out_layout, counts, stream, false);
+}
+
+lpf_status lpf_full_noalloc(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
+                            unsigned phase_mask, int out_layout, uint32_t *counts, void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_full_noalloc: ctx is NULL");
+  if (!bits || !counts) return fail(LPF_E_INVAL, "lpf_full_noalloc: NULL buffer");
+  if (W < 1 || H < 1 || W > 65535 || H > 65535)
+    return fail(LPF_E_INVAL, "lpf_full_noalloc: W/H out of range");
+  if (cx < 0 || cy < 0 || cx > W - 1 || cy > H - 1)
+    return fail(LPF_E_INVAL, "lpf_full_noalloc: cutoff must satisfy 0 <= cx <= W-1, 0 <= cy <= H-1");
+  if (cx > 32767 || cy > 32767)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: cutoff above 32767 (vectors are int16)");
+  if (phase_mask < 1 || phase_mask > 3)
+    return fail(LPF_E_INVAL, "lpf_full_noalloc: phase_mask must be 1, 2 or 3");
+  if (out_layout != LPF_OUT_HALF && out_layout != LPF_OUT_GRID)
+    return fail(LPF_E_INVAL, "lpf_full_noalloc: out_layout");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_full_noalloc: cannot select the context's device");
+  if (!c->noalloc_scratch) return fail(LPF_E_DEVICE, "lpf_full_noalloc: no scratch address");
+  FullShape sh{};
+  std::string why;
+  if (!choose_shape(c, W, H, cx, cy, sh, why))
+    return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: " + why);
+  if (full_lds_bytes(sh, sh.wpg) > (size_t)kMaxLds)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: tile shape needs more than 160 KiB of LDS");
+  if ((size_t)H * sh.we > kNoAllocWords)
+    return fail(LPF_E_UNSUPPORTED,
+                "lpf_full_noalloc: extended image of " + std::to_string((size_t)H * sh.we * 4) +
+                    " bytes exceeds the fixed scratch of " + std::to_string(kNoAllocWords * 4) +
+                    " bytes (H * (words per row + cx/32 + 1) * 4)");
+  const int64_t nv = (int64_t)(cx + 1) * (cy + 1) + (int64_t)cx * cy;
+  // waves: as many as lpf_full's bins (at most kMaxBin vectors each when rows are tiled)
+  int64_t nb = std::min<int64_t>(nv, 8192);
+  nb = std::max<int64_t>(nb, (nv + kMaxBin - 1) / kMaxBin);
+  nb = (nb + sh.wpg - 1) / sh.wpg * sh.wpg;
+  if (nv > (int64_t)1 << 30 || nb > (int64_t)1 << 24)
+    return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: too many vectors");
+  sh.nbins = (int)nb;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *ext = c->noalloc_scratch;
+  hipError_t e;
+  if ((e = launch_ext(bits, W, H, sh.we, ext, s)) != hipSuccess)
+    return hip_fail(e, "lpf_full_noalloc: ext");
+  FullImg I{};
+  I.E = ext;
+  I.out = counts;
+  I.W = W;
+  I.H = H;
+  I.cx = cx;
+  I.cy = cy;
+  I.R = sh.R;
+  I.S = sh.S;
+  I.we = sh.we;
+  I.rst = sh.rst;
+  I.tile = sh.tile;
+  I.ntiles = sh.ntiles;
+  I.lds_rows = sh.lds_rows;
+  I.nv = (int)nv;
+  I.layout = out_layout;
+  I.nbins = sh.nbins;
+  if ((e = launch_full_canon(I, sh, phase_mask, s)) != hipSuccess)
+    return hip_fail(e, "lpf_full_noalloc: kernel");
+  return LPF_OK;
 }
 
 lpf_status lpf_full_enhanced(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,

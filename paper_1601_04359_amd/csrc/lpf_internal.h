@@ -309,6 +309,9 @@ hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
 // skip: the enhanced evaluation (waves stop a segment once no start pixel can still count).
 hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask, bool skip,
                        hipStream_t stream);
+// The same counts without a vector table: the waves take the canonical vectors interleaved.
+hipError_t launch_full_canon(const FullImg &I, const FullShape &sh, unsigned phase_mask,
+                             hipStream_t stream);
 size_t full_lds_bytes(const FullShape &sh, int wpg);
 hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
                         int wpg, unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
