@@ -91,9 +91,12 @@ lpf_status lpf_pack(lpf_ctx ctx, const uint8_t *img, int W, int H, uint64_t *bit
  * vector of D_c and every phase of phase_mask, exact uint32 counts in `out_layout`.
  * bits: packed image as above (read only).  counts: see "Output layouts" (written in full).
  * Requires 1 <= W, H <= 65535, 0 <= cx <= W-1, 0 <= cy <= H-1, phase_mask in {1,2,3}.
+ * Rows are staged in LDS with their periodic halo; when a row tile and its cy halo rows do not
+ * fit (e.g. the whole domain, cx = W - 1, cy = H - 1, of a 1024 x 1024 image), the rows are read
+ * from a periodically extended copy of the image in device memory instead (same counts).
  * Errors: LPF_E_INVAL (arguments), LPF_E_UNSUPPORTED (a cutoff above 32767, the int16 range of
- * the vectors, or an image whose halo rows exceed the on-chip staging limit), LPF_E_NOMEM /
- * LPF_E_DEVICE (HIP).  The same cutoff limit applies to every entry point below. */
+ * the vectors, or W > 32768), LPF_E_NOMEM / LPF_E_DEVICE (HIP).  The same cutoff limit applies to
+ * every entry point below. */
 lpf_status lpf_full(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                     unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
 
@@ -125,9 +128,42 @@ lpf_status lpf_full_sampled(lpf_ctx ctx, const uint64_t *bits, int W, int H, int
  * either.  Every call on one GPU shares that array: calls that overlap on one GPU (any context,
  * any stream) race and must be serialised by the caller.  Arguments, layouts and errors as
  * lpf_full, plus LPF_E_UNSUPPORTED when the extended image exceeds 4 MiB (W = H = 4096 with
- * cx = 128 needs 4096 * 133 * 4 bytes = 2.1 MiB and fits; W = H = 8192 does not). */
+ * cx = 128 needs 4096 * 133 * 4 bytes = 2.1 MiB and fits; W = H = 8192 does not) or when a row
+ * tile and its halo rows do not fit in LDS (lpf_full then reads rows from device memory). */
 lpf_status lpf_full_noalloc(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                             unsigned phase_mask, int out_layout, uint32_t *counts, void *stream);
+
+/* Statistics of the chains lpf_full walks for cutoff (cx, cy) (host only; no device, no
+ * context).  A chain is one walked vector v and every vector u of D_c whose digitised path is,
+ * up to a translation, pixels 0..n_u of v's path (a "shorter overlapping segment" of v, Sec.
+ * 3.2); one walk gives the counts of all of them.  out (host, 4 int64): |D_c|, number of chains,
+ * pixels walked per 32 start pixels (sum over chains of the walked length + 1), and M_c = sum
+ * over D_c of (n + 1), the pixels a walk per vector would take.  Returns LPF_E_INVAL for a NULL
+ * out or a cutoff outside [0, 32767], LPF_E_UNSUPPORTED above 2^26 vectors; sets no message. */
+lpf_status lpf_chain_stats(int cx, int cy, int64_t *out);
+
+/* Host check of the launch plan lpf_full builds for cutoff (cx, cy) with nb_want workgroup bins
+ * requested (host only; no device, no context): every vector of D_c is counted exactly once,
+ * each as pixel l of a walked path whose first l + 1 pixels are its own path (checked by the
+ * digitisation rule), members of a piece in increasing l, at most 256 members per bin.  out
+ * (host, 4 int64): bins, chain pieces, largest members in a bin, pixels walked.  Returns LPF_OK
+ * when every check holds, LPF_E_INVAL when one fails or for a NULL out, a cutoff outside
+ * [0, 4096] or nb_want < 1; sets no message. */
+lpf_status lpf_plan_check(int cx, int cy, int64_t nb_want, int64_t *out);
+
+/* Throughput probe (diagnostic; not part of the method): one launch of nwg workgroups of 256
+ * threads whose lanes each run 8 independent dependency chains for `iters` iterations of
+ *   kind 0: two funnel shifts (v_alignbit_b32), a 3-input AND (v_bitop3_b32) and a 3-input OR
+ *           (v_or3_b32) -- the instruction mix of the path product in lpf_full;
+ *   kind 1: 3-input bitwise ops only;  kind 2: funnel shifts only;  kind 3: popcounts;
+ *   kind 4: LDS reads of 16 bytes per lane, conflict-free, 8 per iteration.
+ * *work (host, may be NULL) receives the launch's int32 lane-operations (kinds 0-3) or LDS bytes
+ * read (kind 4); divided by the launch's time on `stream` this is the sustained rate that
+ * roofline fractions are quoted against.  sink: uint32[nwg * 256] (device), written with
+ * values of no meaning.  Errors: LPF_E_INVAL (kind outside 0..4, iters outside [1, 2^40], nwg
+ * outside [1, 65536], NULL), LPF_E_DEVICE. */
+lpf_status lpf_peak_probe(lpf_ctx ctx, int kind, int64_t iters, int nwg, uint32_t *sink,
+                          double *work, void *stream);
 
 /* Exact change of the lineal path function under pixel interchanges (Sec. 4 modification
  * operator: the values of pixels a and b are exchanged, which preserves the volume fractions).
@@ -194,13 +230,15 @@ typedef struct {
 } lpf_image_desc;
 
 /* lpf_full for many images of any sizes in ONE persistent launch: workgroups draw work items
- * (image, group of vector bins) from a device counter, longest first, until the list is empty.
- * descs (host): n_images (<= 65535) descriptors; every image follows lpf_full's rules.  The first call for
- * a set of (buffers, descriptors, phases, layout) builds launch plans and captures the launch
- * sequence in a hipGraph owned by the context; later calls replay it (the pools' contents may
- * change between calls, their addresses may not).  Shapes tuned by lpf_autotune_full for an
- * image size are used.  Errors: LPF_E_INVAL (a descriptor, naming its index), LPF_E_UNSUPPORTED,
- * LPF_E_NOMEM, LPF_E_DEVICE. */
+ * (image, bin of vector chains) from a device counter, longest first, until the list is empty.
+ * descs (host): n_images (<= 65535) descriptors; every image follows lpf_full's rules.  The
+ * first call for a set of (descriptors, phases, layout) builds launch plans and captures the
+ * launch sequence in a hipGraph owned by the context; later calls with the same set replay it,
+ * with any bits_pool and counts_pool (their addresses are written on `stream` before each
+ * replay).  The context keeps the 16 most recently used graphs (releasing one waits for the
+ * device).  Calls on one context must not overlap (the graph's scratch is shared).  Shapes tuned
+ * by lpf_autotune_full for an image size are used.  Errors: LPF_E_INVAL (a descriptor, naming
+ * its index), LPF_E_UNSUPPORTED, LPF_E_NOMEM, LPF_E_DEVICE. */
 lpf_status lpf_batch(lpf_ctx ctx, const uint64_t *bits_pool, const lpf_image_desc *descs,
                      int n_images, unsigned phase_mask, int out_layout, uint32_t *counts_pool,
                      void *stream);
@@ -419,7 +457,8 @@ void lpf_cnn_destroy(lpf_cnn net);
 
 /* Tile-shape override for lpf_full (and the kernels that share its launch plans); used by the
  * autotuner.  R = 32-pixel words per lane (1,2,4,8,16), S = lanes per image row (power of two,
- * <= 64), waves_per_group (1..16), lds_bytes = staging budget per workgroup (<= 160 KiB).
+ * <= 64), waves_per_group (1..16), lds_bytes = staging budget per workgroup (<= 160 KiB; a
+ * budget too small for one row tile and its halo selects rows read from device memory).
  * 0 in any field restores the automatic choice for that field.  This replaces the paper's
  * occupancy rule for the block size, eq. (block).  Errors: LPF_E_INVAL for values out of range.
  * A shape that cannot cover an image makes the later compute call fail with LPF_E_UNSUPPORTED. */

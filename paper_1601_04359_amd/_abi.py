@@ -54,6 +54,9 @@ _sig("lpf_pack", _i32, _P, _P, _i32, _i32, _P, _P)
 _sig("lpf_full", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
 _sig("lpf_full_enhanced", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
 _sig("lpf_full_noalloc", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _i32, _P, _P)
+_sig("lpf_chain_stats", _i32, _i32, _i32, _P)
+_sig("lpf_plan_check", _i32, _i32, _i32, _i64, _P)
+_sig("lpf_peak_probe", _i32, _P, _i32, _i64, _i32, _P, ctypes.POINTER(ctypes.c_double), _P)
 _sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
 _sig("lpf_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
 _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
@@ -208,6 +211,35 @@ def lpf_full_noalloc(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: 
     _check(_lib.lpf_full_noalloc(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy,
                                  phase_mask, out_layout, _dev(counts, torch.int32, "counts"),
                                  _stream(stream)))
+
+
+def lpf_chain_stats(cx: int, cy: int) -> dict:
+    """Chains lpf_full walks for a cutoff (host computation, no device)."""
+    out = (ctypes.c_int64 * 4)()
+    st = _lib.lpf_chain_stats(cx, cy, ctypes.cast(out, _P))
+    if st != LPF_OK:
+        raise LpfError(st, f"lpf_chain_stats({cx}, {cy})")
+    return {"vectors": out[0], "chains": out[1], "walk": out[2], "path_pixels": out[3]}
+
+
+def lpf_plan_check(cx: int, cy: int, nb_want: int) -> dict:
+    """Host check of lpf_full's launch plan (no device); raises LpfError when a check fails."""
+    out = (ctypes.c_int64 * 4)()
+    st = _lib.lpf_plan_check(cx, cy, nb_want, ctypes.cast(out, _P))
+    if st != LPF_OK:
+        raise LpfError(st, f"lpf_plan_check({cx}, {cy}, {nb_want})")
+    return {"bins": out[0], "pieces": out[1], "max_members": out[2], "walk": out[3]}
+
+
+def lpf_peak_probe(ctx: int, kind: int, iters: int, nwg: int, sink: torch.Tensor,
+                   stream=None) -> float:
+    """Enqueue one throughput probe; returns its lane-operations (kinds 0-3) or LDS bytes (4)."""
+    if sink.numel() < nwg * 256:
+        raise ValueError("lpf_peak_probe: sink must hold nwg * 256 uint32")
+    work = ctypes.c_double(0.0)
+    _check(_lib.lpf_peak_probe(ctx, kind, iters, nwg, _dev(sink, torch.int32, "sink"),
+                               ctypes.byref(work), _stream(stream)))
+    return work.value
 
 
 def lpf_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int,

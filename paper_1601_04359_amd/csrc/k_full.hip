@@ -39,13 +39,13 @@ hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStre
 }
 
 // ------------------------------------------------------------------------- extended image
-// E[y][e], e < we: bit b = pixel ((32e + b) mod W, y).
+// E[r][e], e < we, r < rows: bit b = pixel ((32e + b) mod W, r mod H).
 __global__ void k_ext(const uint32_t *__restrict__ src, int W, int H, int src_stride, int we,
-                      uint32_t *__restrict__ E) {
+                      int rows, uint32_t *__restrict__ E) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y;
-  if (e >= we || y >= H) return;
-  const uint32_t *row = src + (size_t)y * src_stride;
+  if (e >= we || y >= rows) return;
+  const uint32_t *row = src + (size_t)(y % H) * src_stride;
   int s = (int)(((int64_t)32 * e) % W);
   uint32_t v;
   if (s + 32 <= W) {
@@ -65,129 +65,33 @@ __global__ void k_ext(const uint32_t *__restrict__ src, int W, int H, int src_st
 }
 
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
-                      hipStream_t stream) {
+                      hipStream_t stream, int rows) {
+  if (rows < H) rows = H;
   int src_stride = 2 * ((W + 63) / 64);
-  dim3 grid((we + 63) / 64, H);
+  dim3 grid((we + 63) / 64, rows);
   hipLaunchKernelGGL(k_ext, grid, dim3(64), 0, stream, reinterpret_cast<const uint32_t *>(bits),
-                     W, H, src_stride, we, ext);
+                     W, H, src_stride, we, rows, ext);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------ full kernel
-
-// Path product of one segment for the lane's R words: A &= t, O |= t over all pixels.
-// XM: x is the major axis.  Q2: the vector has dx < 0 (mirrored in x, shifted by |dx|).
-// Pixels are taken in pairs: two funnel shifts, one 3-input AND (v_bitop3_b32) and one 3-input
-// OR (v_or3_b32) per word; when both pixels of a pair read the same dwords (same row, same
-// word column) the dwords are loaded once.
 //
-// SKIP (the paper's "enhanced" evaluation, Sec. 3.2, done per wave): every 16 pixels the wave
-// stops when no start pixel of its rows can still count for a requested phase (phase 1 needs a
-// set bit of A, phase 0 a clear bit of O, both under the lane's valid-bit mask mk).  Further
-// pixels only clear bits of A and set bits of O, so the counts are those of the full product.
-template <int R, bool XM, bool Q2, bool SKIP>
-__device__ __forceinline__ void path_product(const uint32_t *__restrict__ base, int rst, int adx,
-                                             int n, int m, uint32_t (&A)[R], uint32_t (&O)[R],
-                                             const uint32_t (&mk)[R], unsigned phase_mask) {
-  int err = n, q = 0;
-  auto advance = [&]() {
-    err += 2 * m;
-    if (err >= 2 * n) {
-      err -= 2 * n;
-      ++q;
-    }
-  };
-  auto pixel = [&](int k, int &off, int &sh) {
-    const int X = XM ? k : q;
-    const int Y = XM ? q : k;
-    const int px = Q2 ? adx - X : X;
-    off = Y * rst + (px >> 5);
-    sh = px & 31;
-  };
-  int k = 0;
-  for (; k + 1 <= n; k += 2) {
-    int off0, sh0, off1, sh1;
-    pixel(k, off0, sh0);
-    advance();
-    pixel(k + 1, off1, sh1);
-    advance();
-    const uint32_t *p0 = base + off0;
-    uint32_t t0[R], t1[R];
-    if (off0 == off1) {
-      uint32_t d[R + 1];
-#pragma unroll
-      for (int c = 0; c <= R; ++c) d[c] = p0[c];
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        t0[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh0);
-        t1[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh1);
-      }
-    } else {
-      const uint32_t *p1 = base + off1;
-      uint32_t d0[R + 1], d1[R + 1];
-#pragma unroll
-      for (int c = 0; c <= R; ++c) {
-        d0[c] = p0[c];
-        d1[c] = p1[c];
-      }
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        t0[i] = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
-        t1[i] = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0[i], t1[i], 0x80);
-      O[i] = O[i] | t0[i] | t1[i];
-    }
-    if constexpr (SKIP) {
-      if ((k & 15) == 14) {
-        uint32_t live = 0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          if (phase_mask & 2u) live |= A[i] & mk[i];
-          if (phase_mask & 1u) live |= ~O[i] & mk[i];
-        }
-        if (!__any(live != 0u)) return;
-      }
-    }
-  }
-  if (k == n) {  // odd pixel count: the last pixel alone
-    int off, sh;
-    pixel(k, off, sh);
-    const uint32_t *p = base + off;
-    uint32_t d[R + 1];
-#pragma unroll
-    for (int c = 0; c <= R; ++c) d[c] = p[c];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const uint32_t t = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);
-      A[i] &= t;
-      O[i] |= t;
-    }
-  }
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Count of vector `idx` = (dx, dy) for phase slot p, in the image's output layout (the GRID
-// layout also fills -v, eq. (symmetry)).
-__device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int dx, int dy,
-                                          uint32_t c) {
-  if (I.layout == 0) {
-    I.out[(size_t)p * I.nv + idx] = c;
-  } else {
-    const int gw = 2 * I.cx + 1;
-    const size_t g = (size_t)gw * (2 * I.cy + 1);
-    I.out[(size_t)p * g + (size_t)(dy + I.cy) * gw + (dx + I.cx)] = c;
-    I.out[(size_t)p * g + (size_t)(I.cy - dy) * gw + (I.cx - dx)] = c;
-  }
-}
+// Chains.  Every segment path is taken from (0,0) in the order of its major axis, and the first
+// l + 1 pixels of the path of a vector v are, up to a translation, often the whole path of a
+// shorter vector u of the domain: u is one of the "shorter overlapping segments" of v that the
+// paper's enhanced evaluation builds on (Sec. 3.2).  The counts are translation invariant on a
+// periodic image, so one walk of v's path gives the count of u as well, read off the running
+// product after pixel l.  The host cuts the domain into chains (a walked vector and the vectors
+// whose paths are its prefixes, in increasing l; every vector in exactly one chain), which
+// removes more than half of the pixel work of the per-vector walk (at cutoff 128: 1 272 832
+// instead of 2 862 081 pixels per 32 start pixels).
+//
+// A workgroup owns one bin of chains and counts them over every row tile of the image; its
+// waves split the work as (chain group, band group): wave w walks the chains j = cw, cw + nwc,
+// ... of the bin over the bands bw, bw + nwb, ... of the tile (cw = w / nwb, bw = w % nwb).  At a
+// member's end the wave sums its popcounts (both phases packed in one word) across lanes and one
+// lane adds them into the member's count slot in LDS; after the last tile the workgroup writes
+// each member's count once.
 
 // Vector i of the canonical half domain: [0,cx] x [0,cy] row by row, then [-cx,-1] x [1,cy].
 __device__ __forceinline__ VecDesc canonical_vec(int i, int cx, int cy) {
@@ -207,16 +111,172 @@ __device__ __forceinline__ VecDesc canonical_vec(int i, int cx, int cy) {
   return v;
 }
 
-// One work item: waves w = 0..wpg-1 of the workgroup take bins bin0 + w of image I and count
-// their vectors over every row tile of the image.  lds: staged rows; cnt: per-wave count slots
-// (used only when the image has several row tiles).  Each count is written once, by lane 0 of
-// the wave owning the vector.
-// CANON: no vector table; the wave with global index g of the I.nbins waves takes the canonical
-// vectors g, g + nbins, g + 2 nbins, ... (interleaving spreads long and short vectors evenly).
-template <int R, bool SKIP, bool CANON = false>
-__device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg,
+// Sum over the wave of v, valid in lane 63 (DPP: within quads, half rows and rows, then row
+// broadcasts 15 and 31).  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_sum63(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
+// Count of vector `idx` = (dx, dy) for phase slot p, in the image's output layout (the GRID
+// layout also fills -v, eq. (symmetry)).
+__device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int dx, int dy,
+                                          uint32_t c) {
+  if (I.layout == 0) {
+    I.out[(size_t)p * I.nv + idx] = c;
+  } else {
+    const int gw = 2 * I.cx + 1;
+    const size_t g = (size_t)gw * (2 * I.cy + 1);
+    I.out[(size_t)p * g + (size_t)(dy + I.cy) * gw + (dx + I.cx)] = c;
+    I.out[(size_t)p * g + (size_t)(I.cy - dy) * gw + (I.cx - dx)] = c;
+  }
+}
+
+// Walk of one chain for the lane's R words of one row: A &= t, O |= t over the walked vector's
+// pixels; after pixel l of each member the wave's counts go to the member's slot.
+// XM: x is the major axis.  Q2: dx < 0 (mirrored in x and shifted by |dx|, a translation).
+// Pixels are taken in pairs: two funnel shifts, one 3-input AND (v_bitop3_b32) and one 3-input
+// OR (v_or3_b32) per word; when both pixels of a pair read the same dwords (same row, same word
+// column) the dwords are loaded once.  A pair never straddles a member's end.
+//
+// SKIP (the paper's "enhanced" evaluation, Sec. 3.2): a member whose count over the wave's rows
+// is zero for every requested phase has no occurrence there, so neither has any longer member of
+// the chain; the walk stops at that member.  Between members the wave also tests, after 16, 32,
+// 64, ... pixels, whether any start pixel can still count (phase 1 needs a set bit of A, phase 0
+// a clear bit of O, under the valid mask mk).  Later pixels only clear A and set O, so the
+// counts are those of the full walk.
+template <int R, bool XM, bool Q2, bool SKIP, bool CANON>
+__device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, int rst, int adx,
+                                           int n, int m, const MemDesc *__restrict__ mems,
+                                           int m0, int nm, int lw, uint32_t (&A)[R],
+                                           uint32_t (&O)[R], const uint32_t (&mk)[R],
+                                           unsigned phase_mask, uint32_t *__restrict__ slots,
+                                           int lane) {
+  int err = n, q = 0;
+  auto advance = [&]() {
+    err += 2 * m;
+    if (err >= 2 * n) {
+      err -= 2 * n;
+      ++q;
+    }
+  };
+  auto pixel = [&](int k, int &off, int &sh) {
+    const int X = XM ? k : q;
+    const int Y = XM ? q : k;
+    const int px = Q2 ? adx - X : X;
+    off = Y * rst + (px >> 5);
+    sh = px & 31;
+  };
+  int mi = 0;
+  int next_l = CANON ? lw : __builtin_amdgcn_readfirstlane(mems[m0].l);
+  int next_test = 16;
+  int k = 0;
+  for (;;) {
+    if (k + 1 <= next_l) {
+      int off0, sh0, off1, sh1;
+      pixel(k, off0, sh0);
+      advance();
+      pixel(k + 1, off1, sh1);
+      advance();
+      const uint32_t *p0 = base + off0;
+      uint32_t t0[R], t1[R];
+      if (off0 == off1) {
+        uint32_t d[R + 1];
+#pragma unroll
+        for (int c = 0; c <= R; ++c) d[c] = p0[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          t0[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh0);
+          t1[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh1);
+        }
+      } else {
+        const uint32_t *p1 = base + off1;
+        uint32_t d0[R + 1], d1[R + 1];
+#pragma unroll
+        for (int c = 0; c <= R; ++c) {
+          d0[c] = p0[c];
+          d1[c] = p1[c];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          t0[i] = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
+          t1[i] = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0[i], t1[i], 0x80);
+        O[i] = O[i] | t0[i] | t1[i];
+      }
+      k += 2;
+    } else {
+      int off, sh;
+      pixel(k, off, sh);
+      advance();
+      const uint32_t *p = base + off;
+      uint32_t d[R + 1];
+#pragma unroll
+      for (int c = 0; c <= R; ++c) d[c] = p[c];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const uint32_t t = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);
+        A[i] &= t;
+        O[i] |= t;
+      }
+      k += 1;
+    }
+    if (k - 1 == next_l) {
+      // member mi ends at pixel next_l: phase 0 in the low half-word, phase 1 in the high one
+      // (a lane counts at most 32 R <= 512 start pixels, a wave at most 32 768)
+      uint32_t p0 = 0, p1 = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        p1 += __popc(A[i] & mk[i]);
+        p0 += __popc(~O[i] & mk[i]);
+      }
+      if (!(phase_mask & 2u)) p1 = 0;
+      if (!(phase_mask & 1u)) p0 = 0;
+      const uint32_t s = wave_sum63(p0 | (p1 << 16));
+      if (lane == 63 && s) {
+        atomicAdd(slots + 2 * mi, s & 0xffffu);
+        atomicAdd(slots + 2 * mi + 1, s >> 16);
+      }
+      if (++mi == nm) return;
+      if constexpr (SKIP) {
+        if (__builtin_amdgcn_readlane(s, 63) == 0u) return;
+      }
+      next_l = __builtin_amdgcn_readfirstlane(mems[m0 + mi].l);
+    } else if constexpr (SKIP) {
+      if (k >= next_test) {
+        next_test *= 2;
+        uint32_t live = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (phase_mask & 2u) live |= A[i] & mk[i];
+          if (phase_mask & 1u) live |= ~O[i] & mk[i];
+        }
+        if (!__any(live != 0u)) return;
+      }
+    }
+  }
+}
+
+// One work item: bin `bin` of image I (one workgroup).  lds: staged rows; slots: two count
+// words per member of the bin, zeroed here and added into by the waves over every band and row
+// tile; each count is then written once.
+// CANON: no chain tables; bin b takes the canonical vectors b, b + nbins, b + 2 nbins, ... as
+// chains of one member each (interleaving spreads long and short vectors evenly).
+// GLOB: rows are read from the extended image in device memory (one tile, I.lds_rows rows of
+// E with a periodic halo), for halos too large for LDS; only the count slots live in LDS.
+template <int R, bool SKIP, bool CANON = false, bool GLOB = false>
+__device__ __forceinline__ void process_item(const FullImg &I, int bin, int wpg,
                                              unsigned phase_mask, uint32_t *__restrict__ lds,
-                                             uint32_t *__restrict__ cnt) {
+                                             uint32_t *__restrict__ slots) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rpw = 64 / I.S;
@@ -224,44 +284,63 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
   const int r_in = lane - strip * rpw;
   const int swd = (I.W + 31) >> 5;
   const uint32_t lastmask = (I.W & 31) ? ((1u << (I.W & 31)) - 1u) : 0xffffffffu;
-  const int bin = bin0 + wave;
-  int vb, ve;
+  int cb, ce, mb, nmb;
   if constexpr (CANON) {
-    vb = 0;
-    ve = bin < I.nbins && bin < I.nv ? (I.nv - 1 - bin) / I.nbins + 1 : 0;
+    cb = 0;
+    ce = bin < I.nv ? (I.nv - 1 - bin) / I.nbins + 1 : 0;
+    mb = 0;
+    nmb = ce;
   } else {
-    vb = bin < I.nbins ? I.bin_off[bin] : 0;
-    ve = bin < I.nbins ? I.bin_off[bin + 1] : 0;
+    cb = I.bin_off[bin];
+    ce = I.bin_off[bin + 1];
+    mb = cb < ce ? I.chains[cb].m0 : 0;
+    nmb = cb < ce ? I.chains[ce - 1].m0 + I.chains[ce - 1].nm - mb : 0;
   }
-  auto vec_at = [&](int j) -> VecDesc {
-    if constexpr (CANON) return canonical_vec(bin + j * I.nbins, I.cx, I.cy);
-    else return I.vecs[j];
-  };
-  const bool tiled = I.ntiles > 1;
+  for (int t = threadIdx.x; t < 2 * nmb; t += blockDim.x) slots[t] = 0u;
+  const int nwb = I.nwb;
+  const int nwc = wpg / nwb;
+  const int cw = wave / nwb, bw = wave - cw * nwb;
   for (int t_id = 0; t_id < I.ntiles; ++t_id) {
     const int Y0 = t_id * I.tile;
     const int rows_here = min(I.tile, I.H - Y0);
-    if (t_id) __syncthreads();  // every wave is done with the previous tile
-    // Stage rows Y0 .. Y0 + lds_rows - 1 (mod H) of E.
-    for (int i = threadIdx.x; i < I.lds_rows * I.we; i += blockDim.x) {
-      const int r = i / I.we;
-      const int e = i - r * I.we;
-      const int y = (Y0 + r) % I.H;
-      lds[r * I.rst + e] = I.E[(size_t)y * I.we + e];
+    __syncthreads();  // slots zeroed; every wave is done with the previous tile
+    if constexpr (!GLOB) {
+      // Stage rows Y0 .. Y0 + lds_rows - 1 (mod H) of E.
+      for (int i = threadIdx.x; i < I.lds_rows * I.we; i += blockDim.x) {
+        const int r = i / I.we;
+        const int e = i - r * I.we;
+        const int y = (Y0 + r) % I.H;
+        lds[r * I.rst + e] = I.E[(size_t)y * I.we + e];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     const int nbands = (rows_here + rpw - 1) / rpw;
-    for (int j = vb; j < ve; ++j) {
-      const VecDesc v = vec_at(j);
-      const int dx = v.dx, dy = v.dy;
+    for (int j = cb + cw; j < ce; j += nwc) {
+      int dx, dy, m0, nm, lw;
+      if constexpr (CANON) {
+        const VecDesc v = canonical_vec(bin + j * I.nbins, I.cx, I.cy);
+        dx = v.dx;
+        dy = v.dy;
+        m0 = j;
+        nm = 1;
+        lw = max(dx < 0 ? -dx : dx, dy);
+      } else {
+        const ChainDesc c = I.chains[j];
+        dx = c.dx;
+        dy = c.dy;
+        m0 = c.m0;
+        nm = c.nm;
+        lw = c.lw;
+      }
       const int adx = dx < 0 ? -dx : dx;
       const int n = adx > dy ? adx : dy;
       const bool xm = adx >= dy;
       const int m = xm ? dy : adx;
-      uint32_t c0 = 0, c1 = 0;
-      for (int band = 0; band < nbands; ++band) {
+      uint32_t *cs = slots + 2 * (m0 - mb);
+      for (int band = bw; band < nbands; band += nwb) {
         const int row = band * rpw + r_in;
-        const uint32_t *base = lds + row * I.rst + strip * R;
+        const uint32_t *base =
+            (GLOB ? I.E + (size_t)(Y0 + row) * I.rst : lds + row * I.rst) + strip * R;
         const bool row_ok = row < rows_here;
         uint32_t A[R], O[R], mk[R];
 #pragma unroll
@@ -274,76 +353,73 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin0, int wpg
         }
         if (I.sample && row_ok) {
           // Monte-Carlo approximation: only start pixels of the position set count.  Lane bit b
-          // of word w stands for the placement whose first pixel is 32w + b (+ |dx| for a
-          // mirrored vector), so the set's extended row is read at that shift.
+          // of word w stands for the placement whose first pixel is 32w + b (+ |dx| of the
+          // walked vector when it is mirrored: the members share its frame), so the set's
+          // extended row is read at that shift.
           const uint32_t *srow = I.sample + (size_t)(Y0 + row) * I.sample_stride + strip * R;
           const int so = dx < 0 ? (adx >> 5) : 0, ssh = dx < 0 ? (adx & 31) : 0;
 #pragma unroll
           for (int i = 0; i < R; ++i)
             mk[i] &= __builtin_amdgcn_alignbit(srow[so + i + 1], srow[so + i], ssh);
         }
+        const MemDesc *md = I.mems;
         if (xm) {
-          if (dx < 0) path_product<R, true, true, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
-          else path_product<R, true, false, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
+          if (dx < 0) walk_chain<R, true, true, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
+          else walk_chain<R, true, false, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
         } else {
-          if (dx < 0) path_product<R, false, true, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
-          else path_product<R, false, false, SKIP>(base, I.rst, adx, n, m, A, O, mk, phase_mask);
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          c1 += __popc(A[i] & mk[i]);
-          c0 += __popc(~O[i] & mk[i]);
-        }
-      }
-      c0 = wave_sum(c0);
-      c1 = wave_sum(c1);
-      if (lane == 0) {
-        if (!tiled) {
-          int p = 0;
-          if (phase_mask & 1) put_count(I, p++, v.idx, dx, dy, c0);
-          if (phase_mask & 2) put_count(I, p, v.idx, dx, dy, c1);
-        } else {
-          uint32_t *slot = cnt + 2 * (wave * kMaxBin + (j - vb));
-          slot[0] = t_id ? slot[0] + c0 : c0;
-          slot[1] = t_id ? slot[1] + c1 : c1;
+          if (dx < 0) walk_chain<R, false, true, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
+          else walk_chain<R, false, false, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
         }
       }
     }
   }
-  if (tiled && lane == 0) {
-    for (int j = vb; j < ve; ++j) {
-      const VecDesc v = vec_at(j);
-      const uint32_t *slot = cnt + 2 * (wave * kMaxBin + (j - vb));
-      int p = 0;
-      if (phase_mask & 1) put_count(I, p++, v.idx, v.dx, v.dy, slot[0]);
-      if (phase_mask & 2) put_count(I, p, v.idx, v.dx, v.dy, slot[1]);
+  __syncthreads();  // every wave's additions are in the slots
+  for (int t = threadIdx.x; t < nmb; t += blockDim.x) {
+    int idx, dx, dy;
+    if constexpr (CANON) {
+      const VecDesc v = canonical_vec(bin + t * I.nbins, I.cx, I.cy);
+      idx = v.idx;
+      dx = v.dx;
+      dy = v.dy;
+    } else {
+      const MemDesc md = I.mems[mb + t];
+      idx = md.idx;
+      dx = md.dx;
+      dy = md.dy;
     }
+    int p = 0;
+    if (phase_mask & 1) put_count(I, p++, idx, dx, dy, slots[2 * t]);
+    if (phase_mask & 2) put_count(I, p, idx, dx, dy, slots[2 * t + 1]);
   }
 }
 
-// One image, one workgroup per work item (item = blockIdx.x).
-template <int R, bool SKIP>
+// One image, one workgroup per bin.
+template <int R, bool SKIP, bool GLOB = false>
 __global__ void __launch_bounds__(1024)
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
-  process_item<R, SKIP>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
+  process_item<R, SKIP, false, GLOB>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
 }
 
-// One image without a vector table (canonical vectors interleaved over the waves).
+// One image without chain tables (canonical vectors interleaved over the bins).
 template <int R>
 __global__ void __launch_bounds__(1024)
 k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
-  process_item<R, false, true>(I, blockIdx.x * wpg, wpg, phase_mask, lds, lds + cnt_off);
+  process_item<R, false, true>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
 }
 
-// Many images, persistent workgroups drawing work items from a device counter in descending
-// cost order until the list is exhausted (every wave reaches the exit test).
+// Many images, persistent workgroups drawing work items (image, bin) from a device counter in
+// descending cost order until the list is exhausted (every wave reaches the exit test).  The
+// counts pool is read from `args` (written before each replay of the captured launch); image i's
+// counts start at counts_off[i].
 __global__ void __launch_bounds__(1024)
-k_lpf_batch(const FullImg *__restrict__ imgs, const int2 *__restrict__ items, int n_items,
+k_lpf_batch(const FullImg *__restrict__ imgs, const BatchArgs *__restrict__ args,
+            const int64_t *__restrict__ counts_off, const int2 *__restrict__ items, int n_items,
             int *__restrict__ counter, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_item;
+  uint32_t *const counts = args->counts;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
@@ -351,15 +427,26 @@ k_lpf_batch(const FullImg *__restrict__ imgs, const int2 *__restrict__ items, in
     __syncthreads();
     if (it >= n_items) break;
     const int2 w = items[it];
-    const FullImg I = imgs[w.x];
-    switch (I.R) {
-      case 1: process_item<1, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 2: process_item<2, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 4: process_item<4, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      case 8: process_item<8, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
-      default: process_item<16, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+    FullImg I = imgs[w.x];
+    I.out = counts + counts_off[w.x];
+    if (!I.glob) {
+      switch (I.R) {
+        case 1: process_item<1, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 2: process_item<2, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 4: process_item<4, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 8: process_item<8, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        default: process_item<16, false>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      }
+    } else {
+      switch (I.R) {
+        case 1: process_item<1, false, false, true>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 2: process_item<2, false, false, true>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 4: process_item<4, false, false, true>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        case 8: process_item<8, false, false, true>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+        default: process_item<16, false, false, true>(I, w.y, wpg, phase_mask, lds, lds + cnt_off); break;
+      }
     }
-    __syncthreads();  // the item's last tile is no longer read before the next staging
+    __syncthreads();  // the item's counts are written and its rows no longer read
   }
 }
 
@@ -368,19 +455,29 @@ __global__ void k_reset_counter(int *counter) {
 }
 
 size_t full_lds_bytes(const FullShape &sh, int wpg) {
-  size_t b = (size_t)sh.lds_rows * sh.rst * sizeof(uint32_t);
-  if (sh.ntiles > 1) b += (size_t)wpg * kMaxBin * 2 * sizeof(uint32_t);
-  return b;
+  (void)wpg;
+  const size_t stage = sh.glob ? 0 : (size_t)sh.lds_rows * sh.rst * sizeof(uint32_t);
+  return stage + (size_t)kSlotWords * sizeof(uint32_t);
+}
+
+// The launch shape the kernel assumes: nwb waves per chain dividing the workgroup's waves.
+static bool shape_ok(const FullImg &I, const FullShape &sh) {
+  return sh.wpg >= 1 && sh.wpg <= 16 && I.nwb >= 1 && sh.wpg % I.nwb == 0 && sh.nbins >= 1 &&
+         I.nbins == sh.nbins && I.R == sh.R && 64 % I.S == 0;
 }
 
 template <int R, bool SKIP>
 static hipError_t launch_full_r(const FullImg &I, const FullShape &sh, unsigned phase_mask,
                                 hipStream_t stream) {
-  const int nwg = sh.nbins / sh.wpg;
+  if (!shape_ok(I, sh) || I.glob != sh.glob) return hipErrorInvalidValue;
   const size_t lds = full_lds_bytes(sh, sh.wpg);
-  const int cnt_off = sh.lds_rows * sh.rst;
-  hipLaunchKernelGGL((k_lpf_full<R, SKIP>), dim3(nwg), dim3(64 * sh.wpg), lds, stream, I, sh.wpg,
-                     phase_mask, cnt_off);
+  const int cnt_off = sh.glob ? 0 : sh.lds_rows * sh.rst;
+  if (sh.glob)
+    hipLaunchKernelGGL((k_lpf_full<R, SKIP, true>), dim3(sh.nbins), dim3(64 * sh.wpg), lds,
+                       stream, I, sh.wpg, phase_mask, cnt_off);
+  else
+    hipLaunchKernelGGL((k_lpf_full<R, SKIP>), dim3(sh.nbins), dim3(64 * sh.wpg), lds, stream, I,
+                       sh.wpg, phase_mask, cnt_off);
   return hipGetLastError();
 }
 
@@ -400,10 +497,10 @@ static hipError_t launch_full_s(const FullImg &I, const FullShape &sh, unsigned 
 template <int R>
 static hipError_t launch_canon_r(const FullImg &I, const FullShape &sh, unsigned phase_mask,
                                  hipStream_t stream) {
-  const int nwg = sh.nbins / sh.wpg;
+  if (!shape_ok(I, sh) || sh.glob) return hipErrorInvalidValue;
   const size_t lds = full_lds_bytes(sh, sh.wpg);
   const int cnt_off = sh.lds_rows * sh.rst;
-  hipLaunchKernelGGL((k_lpf_full_canon<R>), dim3(nwg), dim3(64 * sh.wpg), lds, stream, I,
+  hipLaunchKernelGGL((k_lpf_full_canon<R>), dim3(sh.nbins), dim3(64 * sh.wpg), lds, stream, I,
                      sh.wpg, phase_mask, cnt_off);
   return hipGetLastError();
 }
@@ -426,28 +523,61 @@ hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mas
               : launch_full_s<false>(I, sh, phase_mask, stream);
 }
 
-hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
-                        int wpg, unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
+// Workgroups of one full-evaluation kernel resident per CU (registers and LDS of the launch).
+int full_wgs_per_cu(int R, bool skip, int wpg, size_t lds_bytes) {
+  const void *f = nullptr;
+  switch (R) {
+    case 1: f = skip ? (const void *)k_lpf_full<1, true> : (const void *)k_lpf_full<1, false>; break;
+    case 2: f = skip ? (const void *)k_lpf_full<2, true> : (const void *)k_lpf_full<2, false>; break;
+    case 4: f = skip ? (const void *)k_lpf_full<4, true> : (const void *)k_lpf_full<4, false>; break;
+    case 8: f = skip ? (const void *)k_lpf_full<8, true> : (const void *)k_lpf_full<8, false>; break;
+    default: f = skip ? (const void *)k_lpf_full<16, true> : (const void *)k_lpf_full<16, false>; break;
+  }
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpg, lds_bytes) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_batch(const FullImg *imgs, const BatchArgs *args, const int64_t *counts_off,
+                        const int2 *items, int n_items, int *counter, int wpg,
+                        unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
                         hipStream_t stream) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, stream, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lpf_batch, dim3(n_wg), dim3(64 * wpg), lds_bytes, stream, imgs, items,
-                     n_items, counter, wpg, phase_mask, cnt_off);
+  hipLaunchKernelGGL(k_lpf_batch, dim3(n_wg), dim3(64 * wpg), lds_bytes, stream, imgs, args,
+                     counts_off, items, n_items, counter, wpg, phase_mask, cnt_off);
   return hipGetLastError();
 }
 
-// E for many images in one launch: image b's rows at ext_off[b], we[b] dwords per row.
-__global__ void k_ext_batch(const FullImg *__restrict__ imgs, const uint64_t *__restrict__ pool,
+// The buffers of one lpf_batch call, written on the call's stream before the captured launch.
+__global__ void k_batch_args(BatchArgs *args, const uint64_t *pool, uint32_t *counts) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    args->pool = pool;
+    args->counts = counts;
+  }
+}
+
+hipError_t launch_batch_args(BatchArgs *args, const uint64_t *pool, uint32_t *counts,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_batch_args, dim3(1), dim3(64), 0, stream, args, pool, counts);
+  return hipGetLastError();
+}
+
+// E for many images in one launch: image b's rows at ext_off[b], we[b] dwords per row; the
+// packed images at args->pool + bits_off[b].
+__global__ void k_ext_batch(const FullImg *__restrict__ imgs, const BatchArgs *__restrict__ args,
                             const int64_t *__restrict__ bits_off, uint32_t *__restrict__ ext,
                             const int64_t *__restrict__ ext_off) {
   const int b = blockIdx.z;
   const FullImg I = imgs[b];
+  const uint64_t *const pool = args->pool;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (e >= I.we || y >= I.H) return;
+  if (e >= I.we || y >= (I.glob ? I.lds_rows : I.H)) return;
   const uint32_t *row = reinterpret_cast<const uint32_t *>(pool + bits_off[b]) +
-                        (size_t)y * 2 * ((I.W + 63) / 64);
+                        (size_t)(y % I.H) * 2 * ((I.W + 63) / 64);
   const int W = I.W;
   const int s = (int)(((int64_t)32 * e) % W);
   uint32_t v;
@@ -466,10 +596,10 @@ __global__ void k_ext_batch(const FullImg *__restrict__ imgs, const uint64_t *__
 }
 
 hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int max_h,
-                            const uint64_t *pool, const int64_t *bits_off, uint32_t *ext,
+                            const BatchArgs *args, const int64_t *bits_off, uint32_t *ext,
                             const int64_t *ext_off, hipStream_t stream) {
   dim3 grid((max_we + 63) / 64, max_h, n_images);
-  hipLaunchKernelGGL(k_ext_batch, grid, dim3(64), 0, stream, imgs, pool, bits_off, ext, ext_off);
+  hipLaunchKernelGGL(k_ext_batch, grid, dim3(64), 0, stream, imgs, args, bits_off, ext, ext_off);
   return hipGetLastError();
 }
 
@@ -480,6 +610,11 @@ hipError_t prepare_full_kernels(int max_lds_bytes) {
                        (const void *)k_lpf_full<16, false>, (const void *)k_lpf_full<1, true>,
                        (const void *)k_lpf_full<2, true>, (const void *)k_lpf_full<4, true>,
                        (const void *)k_lpf_full<8, true>, (const void *)k_lpf_full<16, true>,
+                       (const void *)k_lpf_full<1, false, true>, (const void *)k_lpf_full<2, false, true>,
+                       (const void *)k_lpf_full<4, false, true>, (const void *)k_lpf_full<8, false, true>,
+                       (const void *)k_lpf_full<16, false, true>, (const void *)k_lpf_full<1, true, true>,
+                       (const void *)k_lpf_full<2, true, true>, (const void *)k_lpf_full<4, true, true>,
+                       (const void *)k_lpf_full<8, true, true>, (const void *)k_lpf_full<16, true, true>,
                        (const void *)k_lpf_full_canon<1>, (const void *)k_lpf_full_canon<2>,
                        (const void *)k_lpf_full_canon<4>, (const void *)k_lpf_full_canon<8>,
                        (const void *)k_lpf_full_canon<16>};

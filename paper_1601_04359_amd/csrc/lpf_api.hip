@@ -85,10 +85,12 @@ hipError_t ensure_zeroed(DevBuf &b, size_t n, hipStream_t s) {
 
 struct FullPlan {
   FullShape sh{};
-  VecDesc *vecs = nullptr;   // device, bin order
-  int32_t *bin_off = nullptr;  // device, nbins + 1
+  ChainDesc *chains = nullptr;  // device, bin order
+  MemDesc *mems = nullptr;      // device, chain order
+  int32_t *bin_off = nullptr;   // device, nbins + 1
   int64_t nv = 0;
-  std::vector<int64_t> bin_cost;  // host: cost of each bin (pixels + overhead per vector)
+  int64_t walk = 0, path_pixels = 0;  // pixels walked per start word; M_c
+  std::vector<int64_t> bin_cost;  // host: cost of each bin (pixels + overhead per member)
 };
 
 struct TunedShape {
@@ -172,6 +174,7 @@ struct lpf_ctx_s {
   int dev = 0;
   uint32_t *noalloc_scratch = nullptr;  // this device's address of `scratch`
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
+  std::map<std::pair<int, int>, ChainSet> chain_sets;  // chains per cutoff (host)
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
@@ -182,6 +185,7 @@ struct lpf_ctx_s {
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
+  uint64_t batch_clock = 0;  // use counter of the cached batch graphs
   DevBuf ext, ext3, s2ext, s2acc, sext, rank_buf;
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
@@ -228,16 +232,22 @@ struct lpf_anneal_s {
 constexpr int64_t kRecBudget = (int64_t)16 << 30;
 
 // A captured lpf_batch launch (extended images, counter reset, persistent kernel).
+// Keyed by the descriptors, phase mask, layout and shape overrides, not by the caller's
+// buffers: those go through `args`, written before each replay.  At most kMaxBatchGraphs are
+// kept; the least recently used is released first.
 struct BatchGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   FullImg *imgs = nullptr;
+  BatchArgs *args = nullptr;
   int2 *items = nullptr;
-  int64_t *bits_off = nullptr, *ext_off = nullptr;
+  int64_t *bits_off = nullptr, *ext_off = nullptr, *counts_off = nullptr;
   int *counter = nullptr;
   uint32_t *ext = nullptr;
   int n_items = 0, n_wg = 0;
+  uint64_t last_use = 0;
 };
+constexpr size_t kMaxBatchGraphs = 16;
 
 struct lpf_cnn_s {
   lpf_ctx ctx = nullptr;
@@ -253,9 +263,11 @@ void free_batch_graph(BatchGraph *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   (void)hipFree(b->imgs);
+  (void)hipFree(b->args);
   (void)hipFree(b->items);
   (void)hipFree(b->bits_off);
   (void)hipFree(b->ext_off);
+  (void)hipFree(b->counts_off);
   (void)hipFree(b->counter);
   (void)hipFree(b->ext);
   delete b;
@@ -298,29 +310,37 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   }
   sh.rst = best;
   int budget = fL ? fL : 64 * 1024;
+  sh.glob = 0;
   for (;;) {
     int tile;
-    const int slots = sh.wpg * kMaxBin * 2 * 4;  // count slots when the image needs row tiles
-    const int rows_all = budget / (sh.rst * 4);
-    if (rows_all - cy - rpw >= H) {
+    const int slots = kSlotWords * 4;  // count slots of the bin's members
+    const int rows_max = (budget - slots) / (sh.rst * 4);
+    if (rows_max - cy - rpw >= H) {
       tile = H;
     } else {
-      const int rows_max = (budget - slots) / (sh.rst * 4);
       tile = ((rows_max - cy - rpw) / rpw) * rpw;
     }
     if (tile >= 1) {
       sh.tile = tile;
       break;
     }
-    if (budget >= kBigLds) {
-      why = "cutoff cy too large for on-chip staging of the halo rows";
-      return false;
+    if (budget >= kBigLds || fL) {
+      // the halo rows do not fit in the staging budget: read the rows of the periodically
+      // extended image from device memory (L2) instead, one tile of all H rows
+      sh.glob = 1;
+      sh.tile = H;
+      sh.rst = sh.we;
+      break;
     }
     budget = kBigLds;
     if (!fW) sh.wpg = 16;  // one group per CU: use all of its waves
   }
   sh.ntiles = (H + sh.tile - 1) / sh.tile;
   sh.lds_rows = sh.tile + cy + rpw;
+  // waves sharing a chain: as many as the tile has bands (a power of two dividing wpg)
+  const int bands = (sh.tile + rpw - 1) / rpw;
+  sh.nwb = 1;
+  while (sh.nwb * 2 <= std::min(sh.wpg, bands) && sh.wpg % (sh.nwb * 2) == 0) sh.nwb *= 2;
   return true;
 }
 
@@ -330,66 +350,58 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
   if (!choose_shape(c, W, H, cx, cy, sh, why)) return fail(LPF_E_UNSUPPORTED, "lpf_full: " + why);
   if (full_lds_bytes(sh, sh.wpg) > (size_t)kMaxLds)
     return fail(LPF_E_UNSUPPORTED, "lpf_full: tile shape needs more than 160 KiB of LDS");
-  auto key = std::make_tuple(W, H, cx, cy, sh.R * 1000 + sh.S, sh.wpg, sh.tile);
+  auto key = std::make_tuple(W, H, cx, cy, sh.R * 1000 + sh.S, sh.wpg, 2 * sh.tile + sh.glob);
   auto it = c->full_plans.find(key);
   if (it != c->full_plans.end()) {
     plan = &it->second;
     return LPF_OK;
   }
-  std::vector<int16_t> can;
-  canonical_vectors(cx, cy, can);
-  const int64_t nv = (int64_t)can.size() / 2;
+  const int64_t nv = lpf_num_vectors(cx, cy);
   if (nv > (int64_t)1 << 30) return fail(LPF_E_UNSUPPORTED, "lpf_full: too many vectors");
-
-  // Wave-level bins, longest-processing-time-first on cost = pixels + per-band overhead, at most
-  // kMaxBin vectors per bin.
-  int64_t nb = std::min<int64_t>(nv, 8192);
-  nb = std::max<int64_t>(nb, (2 * nv + kMaxBin - 1) / kMaxBin);
-  nb = (nb + sh.wpg - 1) / sh.wpg * sh.wpg;
-  sh.nbins = (int)nb;
-  std::vector<int> order(nv);
-  std::vector<int> cost(nv);
-  for (int64_t i = 0; i < nv; ++i) {
-    order[i] = (int)i;
-    const int adx = std::abs((int)can[2 * i]), ady = std::abs((int)can[2 * i + 1]);
-    cost[i] = std::max(adx, ady) + 1 + 2;
+  auto chs = c->chain_sets.find(std::make_pair(cx, cy));
+  if (chs == c->chain_sets.end()) {
+    build_chains(cx, cy, c->chain_sets[std::make_pair(cx, cy)]);
+    chs = c->chain_sets.find(std::make_pair(cx, cy));
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  using Item = std::pair<int64_t, int>;  // (load, bin)
-  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-  for (int b = 0; b < sh.nbins; ++b) heap.push({0, b});
-  std::vector<std::vector<int>> bins(sh.nbins);
-  for (int i : order) {
-    Item t = heap.top();
-    heap.pop();
-    bins[t.second].push_back(i);
-    if ((int)bins[t.second].size() < kMaxBin) heap.push({t.first + cost[i], t.second});
-  }
-  std::vector<VecDesc> vecs;
-  vecs.reserve(nv);
-  std::vector<int32_t> off(sh.nbins + 1, 0);
-  for (int b = 0; b < sh.nbins; ++b) {
-    off[b] = (int32_t)vecs.size();
-    for (int i : bins[b]) vecs.push_back(VecDesc{can[2 * i], can[2 * i + 1], i});
-  }
-  off[sh.nbins] = (int32_t)vecs.size();
+  const ChainSet &all = chs->second;
+  // Workgroup-level bins of chain pieces (pack_bins): as many bins as the device holds
+  // workgroups at once (every workgroup then walks about the same number of pixels), fewer when
+  // there are too few chains to keep each wave of a workgroup busy.
+  const int nwc = sh.wpg / sh.nwb;
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
+  const int resident = cus * full_wgs_per_cu(sh.R, false, sh.wpg, full_lds_bytes(sh, sh.wpg));
+  const int64_t nb_want =
+      std::min<int64_t>(resident, std::max<int64_t>(1, (int64_t)all.chains.size() / (4 * nwc)));
+  BinPlan bp;
+  pack_bins(all, nb_want, bp);
+  sh.nbins = bp.nbins;
+  const std::vector<ChainDesc> &chains = bp.chains;
+  const std::vector<MemDesc> &mems = bp.mems;
+  const std::vector<int32_t> &off = bp.off;
 
   FullPlan p;
   p.sh = sh;
   p.nv = nv;
+  p.walk = all.walk;
+  p.path_pixels = all.path_pixels;
   hipError_t e;
-  if ((e = hipMalloc(&p.vecs, sizeof(VecDesc) * std::max<int64_t>(nv, 1))) != hipSuccess)
+  if ((e = hipMalloc(&p.chains, sizeof(ChainDesc) * std::max<size_t>(chains.size(), 1))) != hipSuccess ||
+      (e = hipMalloc(&p.mems, sizeof(MemDesc) * std::max<size_t>(mems.size(), 1))) != hipSuccess ||
+      (e = hipMalloc(&p.bin_off, sizeof(int32_t) * off.size())) != hipSuccess) {
+    (void)hipFree(p.chains);
+    (void)hipFree(p.mems);
     return hip_fail(e, "lpf_full: plan allocation");
-  if ((e = hipMalloc(&p.bin_off, sizeof(int32_t) * off.size())) != hipSuccess)
-    return hip_fail(e, "lpf_full: plan allocation");
-  if ((e = hipMemcpy(p.vecs, vecs.data(), sizeof(VecDesc) * nv, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p.bin_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess)
-    return hip_fail(e, "lpf_full: plan upload");
-  for (int b = 0; b < sh.nbins; ++b) {
-    int64_t c = 0;
-    for (int i : bins[b]) c += cost[i];
-    p.bin_cost.push_back(c);
   }
+  if ((e = hipMemcpy(p.chains, chains.data(), sizeof(ChainDesc) * chains.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.mems, mems.data(), sizeof(MemDesc) * mems.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p.bin_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(p.chains);
+    (void)hipFree(p.mems);
+    (void)hipFree(p.bin_off);
+    return hip_fail(e, "lpf_full: plan upload");
+  }
+  p.bin_cost = bp.cost;
   auto res = c->full_plans.emplace(key, p);
   plan = &res.first->second;
   return LPF_OK;
@@ -509,8 +521,11 @@ FullImg make_img(const FullPlan &p, const uint32_t *ext, uint32_t *out, int W, i
   FullImg I{};
   I.E = ext;
   I.out = out;
-  I.vecs = p.vecs;
+  I.chains = p.chains;
+  I.mems = p.mems;
   I.bin_off = p.bin_off;
+  I.nwb = p.sh.nwb;
+  I.glob = p.sh.glob;
   I.W = W;
   I.H = H;
   I.cx = cx;
@@ -972,7 +987,8 @@ void lpf_ctx_destroy(lpf_ctx c) {
     DeviceGuard g(c->dev);
     (void)hipDeviceSynchronize();
     for (auto &kv : c->full_plans) {
-      (void)hipFree(kv.second.vecs);
+      (void)hipFree(kv.second.chains);
+      (void)hipFree(kv.second.mems);
       (void)hipFree(kv.second.bin_off);
     }
     release_batch_graphs(c);
@@ -1030,10 +1046,12 @@ lpf_status full_impl(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int 
   const FullShape &sh = plan->sh;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  if ((e = c->ext.ensure((size_t)H * sh.we * sizeof(uint32_t))) != hipSuccess)
+  const int ext_rows = sh.glob ? sh.lds_rows : H;
+  if ((e = c->ext.ensure((size_t)ext_rows * sh.we * sizeof(uint32_t))) != hipSuccess)
     return hip_fail(e, "lpf_full: scratch");
   uint32_t *ext = (uint32_t *)c->ext.p;
-  if ((e = launch_ext(bits, W, H, sh.we, ext, s)) != hipSuccess) return hip_fail(e, "lpf_full: ext");
+  if ((e = launch_ext(bits, W, H, sh.we, ext, s, ext_rows)) != hipSuccess)
+    return hip_fail(e, "lpf_full: ext");
   FullImg I = make_img(*plan, ext, counts, W, H, cx, cy, out_layout);
   if (sample) {
     if ((e = c->sext.ensure((size_t)H * sh.we * sizeof(uint32_t))) != hipSuccess)
@@ -1077,16 +1095,20 @@ lpf_status lpf_full_noalloc(lpf_ctx c, const uint64_t *bits, int W, int H, int c
     return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: " + why);
   if (full_lds_bytes(sh, sh.wpg) > (size_t)kMaxLds)
     return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: tile shape needs more than 160 KiB of LDS");
+  if (sh.glob)
+    return fail(LPF_E_UNSUPPORTED,
+                "lpf_full_noalloc: halo rows exceed on-chip staging (use lpf_full)");
   if ((size_t)H * sh.we > kNoAllocWords)
     return fail(LPF_E_UNSUPPORTED,
                 "lpf_full_noalloc: extended image of " + std::to_string((size_t)H * sh.we * 4) +
                     " bytes exceeds the fixed scratch of " + std::to_string(kNoAllocWords * 4) +
                     " bytes (H * (words per row + cx/32 + 1) * 4)");
   const int64_t nv = (int64_t)(cx + 1) * (cy + 1) + (int64_t)cx * cy;
-  // waves: as many as lpf_full's bins (at most kMaxBin vectors each when rows are tiled)
-  int64_t nb = std::min<int64_t>(nv, 8192);
-  nb = std::max<int64_t>(nb, (nv + kMaxBin - 1) / kMaxBin);
-  nb = (nb + sh.wpg - 1) / sh.wpg * sh.wpg;
+  // bins (one workgroup each): two per CU, at most kSlotWords / 2 vectors each
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
+  int64_t nb = std::min<int64_t>(nv, 2 * (int64_t)cus);
+  nb = std::max<int64_t>(nb, (2 * nv + kSlotWords - 1) / kSlotWords);
   if (nv > (int64_t)1 << 30 || nb > (int64_t)1 << 24)
     return fail(LPF_E_UNSUPPORTED, "lpf_full_noalloc: too many vectors");
   sh.nbins = (int)nb;
@@ -1112,8 +1134,24 @@ lpf_status lpf_full_noalloc(lpf_ctx c, const uint64_t *bits, int W, int H, int c
   I.nv = (int)nv;
   I.layout = out_layout;
   I.nbins = sh.nbins;
+  I.nwb = sh.nwb;
   if ((e = launch_full_canon(I, sh, phase_mask, s)) != hipSuccess)
     return hip_fail(e, "lpf_full_noalloc: kernel");
+  return LPF_OK;
+}
+
+lpf_status lpf_peak_probe(lpf_ctx c, int kind, int64_t iters, int nwg, uint32_t *sink,
+                          double *work, void *stream) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_peak_probe: ctx is NULL");
+  if (kind < 0 || kind > 4) return fail(LPF_E_INVAL, "lpf_peak_probe: kind must be 0..4");
+  if (iters < 1 || iters > ((int64_t)1 << 40)) return fail(LPF_E_INVAL, "lpf_peak_probe: iters");
+  if (nwg < 1 || nwg > 65536) return fail(LPF_E_INVAL, "lpf_peak_probe: nwg must be 1..65536");
+  if (!sink) return fail(LPF_E_INVAL, "lpf_peak_probe: sink is NULL");
+  DeviceGuard g(c->dev);
+  if (!g.ok) return fail(LPF_E_DEVICE, "lpf_peak_probe: cannot select the context's device");
+  hipError_t e = launch_probe(kind, iters, nwg, sink, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lpf_peak_probe");
+  if (work) *work = probe_work(kind, iters, nwg);
   return LPF_OK;
 }
 
@@ -1831,17 +1869,24 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
   DeviceGuard g(c->dev);
   if (!g.ok) return fail(LPF_E_DEVICE, "lpf_batch: cannot select the context's device");
   hipStream_t s = (hipStream_t)stream;
-  // cache key: buffers, layout and every descriptor
+  // cache key: layout, shape overrides and every descriptor (the buffers are set per call)
   std::string key;
   {
     char buf[96];
-    snprintf(buf, sizeof buf, "%p|%p|%u|%d|%d|%d%d%d%d|", (const void *)bits_pool,
-             (void *)counts_pool, phase_mask, out_layout, n_images, c->force_R, c->force_S,
-             c->force_wpg, c->force_lds);
+    snprintf(buf, sizeof buf, "%u|%d|%d|%d|%d|%d|%d|", phase_mask, out_layout, n_images,
+             c->force_R, c->force_S, c->force_wpg, c->force_lds);
     key = buf;
     key.append(reinterpret_cast<const char *>(descs), sizeof(lpf_image_desc) * (size_t)n_images);
   }
   auto it = c->batch_graphs.find(key);
+  if (it == c->batch_graphs.end() && c->batch_graphs.size() >= kMaxBatchGraphs) {
+    auto lru = c->batch_graphs.begin();
+    for (auto j = c->batch_graphs.begin(); j != c->batch_graphs.end(); ++j)
+      if (j->second->last_use < lru->second->last_use) lru = j;
+    (void)hipDeviceSynchronize();  // its last replay may still run on any stream
+    free_batch_graph(lru->second);
+    c->batch_graphs.erase(lru);
+  }
   if (it == c->batch_graphs.end()) {
     // 16 waves per group when some image needs the large staging budget (one group per CU)
     int wpg = 8;
@@ -1856,7 +1901,7 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
       if (full_lds_bytes(probe, 8) > 80 * 1024) wpg = 16;
     }
     std::vector<FullImg> imgs(n_images);
-    std::vector<int64_t> bits_off(n_images), ext_off(n_images);
+    std::vector<int64_t> bits_off(n_images), ext_off(n_images), counts_off(n_images);
     std::vector<std::pair<int64_t, int2>> items;
     int64_t ext_total = 0;
     size_t stage_max = 0;
@@ -1873,18 +1918,17 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
       const FullShape &sh = plan->sh;
       ext_off[i] = ext_total;
       bits_off[i] = d.bits_off;
-      ext_total += (int64_t)d.H * sh.we;
-      imgs[i] = make_img(*plan, nullptr, counts_pool + d.counts_off, d.W, d.H, d.cx, d.cy, out_layout);
-      stage_max = std::max(stage_max, (size_t)sh.lds_rows * sh.rst);
+      ext_total += (int64_t)(sh.glob ? sh.lds_rows : d.H) * sh.we;
+      imgs[i] = make_img(*plan, nullptr, nullptr, d.W, d.H, d.cx, d.cy, out_layout);
+      counts_off[i] = d.counts_off;
+      if (!sh.glob) stage_max = std::max(stage_max, (size_t)sh.lds_rows * sh.rst);
       any_tiled = any_tiled || sh.ntiles > 1;
       max_we = std::max(max_we, sh.we);
-      max_h = std::max(max_h, d.H);
+      max_h = std::max(max_h, sh.glob ? sh.lds_rows : d.H);
       const int64_t rows_work = (int64_t)d.H * sh.S;
-      for (int b0 = 0; b0 < sh.nbins; b0 += wpg) {
-        int64_t cst = 0;
-        for (int b = b0; b < std::min(b0 + wpg, sh.nbins); ++b) cst = std::max(cst, plan->bin_cost[b]);
-        items.push_back({cst * rows_work * sh.R + (int64_t)sh.lds_rows * sh.we, make_int2(i, b0)});
-      }
+      for (int b = 0; b < sh.nbins; ++b)
+        items.push_back({plan->bin_cost[b] * rows_work * sh.R + (int64_t)sh.lds_rows * sh.we * sh.ntiles,
+                         make_int2(i, b)});
     }
     std::stable_sort(items.begin(), items.end(),
                      [](const std::pair<int64_t, int2> &a, const std::pair<int64_t, int2> &b) {
@@ -1892,7 +1936,8 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
                      });
     std::vector<int2> item_list(items.size());
     for (size_t k = 0; k < items.size(); ++k) item_list[k] = items[k].second;
-    const size_t lds_bytes = stage_max * 4 + (any_tiled ? (size_t)wpg * kMaxBin * 2 * 4 : 0);
+    const size_t lds_bytes = stage_max * 4 + (size_t)kSlotWords * 4;
+    (void)any_tiled;
     if (lds_bytes > (size_t)(kMaxLds - kBatchStaticLds))
       return fail(LPF_E_UNSUPPORTED, "lpf_batch: staging exceeds LDS");
     BatchGraph *b = new (std::nothrow) BatchGraph();
@@ -1900,6 +1945,8 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     hipError_t e;
     if ((e = hipMalloc(&b->ext, sizeof(uint32_t) * (size_t)std::max<int64_t>(ext_total, 1))) != hipSuccess ||
         (e = hipMalloc(&b->imgs, sizeof(FullImg) * n_images)) != hipSuccess ||
+        (e = hipMalloc(&b->args, sizeof(BatchArgs))) != hipSuccess ||
+        (e = hipMalloc(&b->counts_off, sizeof(int64_t) * n_images)) != hipSuccess ||
         (e = hipMalloc(&b->items, sizeof(int2) * item_list.size())) != hipSuccess ||
         (e = hipMalloc(&b->bits_off, sizeof(int64_t) * n_images)) != hipSuccess ||
         (e = hipMalloc(&b->ext_off, sizeof(int64_t) * n_images)) != hipSuccess ||
@@ -1911,7 +1958,8 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     if ((e = hipMemcpy(b->imgs, imgs.data(), sizeof(FullImg) * n_images, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(b->items, item_list.data(), sizeof(int2) * item_list.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(b->bits_off, bits_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(b->ext_off, ext_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(b->ext_off, ext_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->counts_off, counts_off.data(), sizeof(int64_t) * n_images, hipMemcpyHostToDevice)) != hipSuccess) {
       free_batch_graph(b);
       return hip_fail(e, "lpf_batch: upload");
     }
@@ -1928,10 +1976,11 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     }
     hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-      hipError_t e1 = launch_ext_batch(b->imgs, n_images, max_we, max_h, bits_pool, b->bits_off,
+      hipError_t e1 = launch_ext_batch(b->imgs, n_images, max_we, max_h, b->args, b->bits_off,
                                        b->ext, b->ext_off, cap);
-      hipError_t e2 = launch_batch(b->imgs, b->items, b->n_items, b->counter, wpg, phase_mask,
-                                   lds_bytes, (int)stage_max, b->n_wg, cap);
+      hipError_t e2 = launch_batch(b->imgs, b->args, b->counts_off, b->items, b->n_items,
+                                   b->counter, wpg, phase_mask, lds_bytes, (int)stage_max,
+                                   b->n_wg, cap);
       ce = hipStreamEndCapture(cap, &b->graph);
       if (ce == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) ce = e1 != hipSuccess ? e1 : e2;
     }
@@ -1943,7 +1992,10 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     }
     it = c->batch_graphs.emplace(key, b).first;
   }
-  hipError_t e = hipGraphLaunch(it->second->exec, s);
+  it->second->last_use = ++c->batch_clock;
+  hipError_t e = launch_batch_args(it->second->args, bits_pool, counts_pool, s);
+  if (e != hipSuccess) return hip_fail(e, "lpf_batch: buffers");
+  e = hipGraphLaunch(it->second->exec, s);
   if (e != hipSuccess) return hip_fail(e, "lpf_batch: graph launch");
   return LPF_OK;
 }

@@ -9,10 +9,24 @@
 
 namespace lpf {
 
-// One entry of a launch plan's vector list: the vector and its canonical index in D_c.
+// A vector of D_c and its canonical index.
 struct VecDesc {
   int16_t dx, dy;
   int32_t idx;
+};
+
+// A chain of the full-evaluation plan: the walked vector (dx, dy), its members
+// mems[m0 .. m0 + nm) in increasing l, and lw = the last member's l (the walked vector itself).
+struct ChainDesc {
+  int16_t dx, dy;
+  int32_t m0, nm, lw;
+};
+// A member of a chain: vector (dx, dy) with canonical index idx, whose path is (up to a
+// translation) pixels 0..l of the chain's walked path.
+struct MemDesc {
+  int32_t idx;
+  int16_t dx, dy;
+  int32_t l;
 };
 
 // Tile shape of the full-evaluation kernel.
@@ -23,28 +37,55 @@ struct VecDesc {
 //   rst     LDS row stride in dwords (>= we), chosen against bank conflicts
 //   we      dwords per row of the extended image: S*R + (cx >> 5) + 1
 //   lds_rows rows staged in LDS per workgroup: tile + cy + 64/S
+//   nwb     waves sharing a chain (each takes every nwb-th band of a tile); wpg / nwb chain groups
+//   nbins   workgroup-level bins of chains (one workgroup each)
+//   glob    1: the halo rows do not fit in LDS; rows are read from the extended image in device
+//           memory (lds_rows rows of E, periodic), one tile of H rows, only count slots in LDS
 struct FullShape {
   int R, S, wpg, tile, ntiles, rst, we, lds_rows;
-  int nbins;  // wave-level vector bins (a multiple of wpg), at most kMaxBin vectors each
+  int nwb;
+  int nbins;
+  int glob;
 };
 
-// Most vectors in one wave-level bin (count slots in LDS when an image has several row tiles).
-constexpr int kMaxBin = 64;
+// Count slots of one bin in LDS (two words per member): at most kSlotWords / 2 members per bin.
+constexpr int kSlotWords = 512;
 // LDS the persistent batch kernel keeps for itself (the claimed work item), below the 160 KiB.
 constexpr int kBatchStaticLds = 256;
 
 // One image as seen by the full-evaluation kernels.
 struct FullImg {
-  const uint32_t *E;        // extended image, H x we dwords
-  uint32_t *out;            // counts in the output layout
-  const VecDesc *vecs;      // vectors in bin order
-  const int32_t *bin_off;   // nbins + 1
-  int W, H, cx, cy, R, S, we, rst, tile, ntiles, lds_rows, nv, layout, nbins;
+  const uint32_t *E;          // extended image, H x we dwords
+  uint32_t *out;              // counts in the output layout
+  const ChainDesc *chains;    // chains in bin order
+  const MemDesc *mems;        // members in chain order
+  const int32_t *bin_off;     // nbins + 1 (chain offsets)
+  int W, H, cx, cy, R, S, we, rst, tile, ntiles, lds_rows, nv, layout, nbins, nwb, glob;
   // Monte-Carlo position set: extended rows of its mask like E (bit j of row y = position
   // (j mod W, y) is counted), sample_stride = we dwords per row; nullptr = every pixel
   const uint32_t *sample;
   int sample_stride;
 };
+
+// Chains of the canonical half domain D_c (plan_full.hip): every vector in exactly one chain.
+struct ChainSet {
+  std::vector<ChainDesc> chains;  // m0 indexes mems
+  std::vector<MemDesc> mems;
+  int64_t walk = 0;               // sum over chains of (lw + 1): pixels walked per start word
+  int64_t path_pixels = 0;        // M_c = sum over D_c of (n + 1)
+};
+void build_chains(int cx, int cy, ChainSet &out);
+// Chains cut into pieces of at most kSlotWords / 4 members and packed into bins (one workgroup
+// each), longest processing time first: chains in bin order with their members (m0 indexes
+// mems), off[nbins + 1] chain offsets, cost = pixels walked + 3 per member of each bin.
+struct BinPlan {
+  std::vector<ChainDesc> chains;
+  std::vector<MemDesc> mems;
+  std::vector<int32_t> off;
+  std::vector<int64_t> cost;
+  int nbins = 0;
+};
+void pack_bins(const ChainSet &all, int64_t nb_want, BinPlan &out);
 
 // Geometry of one extended image used by the delta kernel (see k_delta.hip): width, height,
 // dwords per row, dword offset in the concatenated buffer, and the 64-bit pattern of columns
@@ -304,8 +345,9 @@ int cnn_conv_blocks(int64_t npix);
 
 // Kernel launchers (defined in k_full.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_pack(const uint8_t *img, int W, int H, uint64_t *bits, hipStream_t stream);
+// rows >= H rows of the extended image (row r holds pixel row r mod H); 0 = H.
 hipError_t launch_ext(const uint64_t *bits, int W, int H, int we, uint32_t *ext,
-                      hipStream_t stream);
+                      hipStream_t stream, int rows = 0);
 // skip: the enhanced evaluation (waves stop a segment once no start pixel can still count).
 hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mask, bool skip,
                        hipStream_t stream);
@@ -313,13 +355,27 @@ hipError_t launch_full(const FullImg &I, const FullShape &sh, unsigned phase_mas
 hipError_t launch_full_canon(const FullImg &I, const FullShape &sh, unsigned phase_mask,
                              hipStream_t stream);
 size_t full_lds_bytes(const FullShape &sh, int wpg);
-hipError_t launch_batch(const FullImg *imgs, const int2 *items, int n_items, int *counter,
-                        int wpg, unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
+int full_wgs_per_cu(int R, bool skip, int wpg, size_t lds_bytes);
+// The caller's buffers of one lpf_batch call (device struct, set before each replay).
+struct BatchArgs {
+  const uint64_t *pool;
+  uint32_t *counts;
+};
+hipError_t launch_batch(const FullImg *imgs, const BatchArgs *args, const int64_t *counts_off,
+                        const int2 *items, int n_items, int *counter, int wpg,
+                        unsigned phase_mask, size_t lds_bytes, int cnt_off, int n_wg,
                         hipStream_t stream);
+hipError_t launch_batch_args(BatchArgs *args, const uint64_t *pool, uint32_t *counts,
+                             hipStream_t stream);
 hipError_t launch_ext_batch(const FullImg *imgs, int n_images, int max_we, int max_h,
-                            const uint64_t *pool, const int64_t *bits_off, uint32_t *ext,
+                            const BatchArgs *args, const int64_t *bits_off, uint32_t *ext,
                             const int64_t *ext_off, hipStream_t stream);
 hipError_t prepare_full_kernels(int max_lds_bytes);
+
+// Throughput probes (k_peak.hip): kind 0-3 int32 VALU mixes, 4 LDS reads; nwg workgroups of 256
+// threads, sink[nwg * 256].  probe_work = lane-operations (or LDS bytes) of one launch.
+hipError_t launch_probe(int kind, int64_t iters, int nwg, uint32_t *sink, hipStream_t stream);
+double probe_work(int kind, int64_t iters, int nwg);
 
 // ---- 3-D volumes (k_lpf3.hip) ----
 // E: extended rows of the volume (row z*H + y, we >= S*R + (cx >> 5) + 1 dwords), vec: the

@@ -4,8 +4,10 @@ Samples are (cell state, interchange (a, b), exact energy change de) triples tak
 annealing runs: the chain is advanced with uniform proposals, its state is copied every few
 steps, random phase-preserving interchanges of that state are labelled with their exact de by
 lpf_anneal_delta_energy, and the network is fitted so that S[a] + S[b] predicts -de / sigma.
-All arithmetic (annealing, labels, forward, backward, Adam) runs in liblpf's kernels; this
-module only moves tensors and indices around.
+The annealing, the exact labels, the network's forward and backward passes and Adam run in
+liblpf's kernels.  This module does the data bookkeeping on the host with numpy: it draws the
+labelled interchanges from an unpacked copy of each snapshot, takes sigma as the standard
+deviation of the collected labels, scales them, and picks the mini-batches.
 """
 from __future__ import annotations
 

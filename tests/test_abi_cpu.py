@@ -137,3 +137,49 @@ def test_3d_entry_points_on_the_host():
         assert np.array_equal(_abi.lpf_vectors3(*c), oracle.vectors3(*c))
     assert lib.lpf_full3d(None, None, 8, 8, 8, 1, 1, 1, 3, None, None) == _abi.LPF_E_INVAL
     assert b"ctx" in lib.lpf_last_error()
+
+
+def _chain_stats_reference(cx, cy):
+    """Chains from the definition: a vector is walked when its digitised path (oracle
+    digitisation) is not, up to a translation, a proper prefix of another vector's path; the
+    walk is the sum of the walked paths' pixel counts."""
+    def norm(pix):
+        x0 = min(int(x) for x, y in pix if y == 0)
+        return frozenset((int(x) - x0, int(y)) for x, y in pix)
+    vecs = oracle.vectors(cx, cy)
+    paths = [oracle.bresenham(int(dx), int(dy)) for dx, dy in vecs]
+    prefixes = set()
+    for p in paths:
+        for l in range(len(p) - 1):
+            prefixes.add(norm(p[:l + 1]))
+    walked = [p for p in paths if norm(p) not in prefixes]
+    return {"vectors": len(vecs), "chains": len(walked), "walk": sum(len(p) for p in walked),
+            "path_pixels": sum(len(p) for p in paths)}
+
+
+@pytest.mark.parametrize("cx,cy", [(0, 0), (1, 1), (0, 7), (7, 0), (5, 9), (16, 16), (40, 3),
+                                   (32, 32)])
+def test_chain_stats_match_definition(cx, cy):
+    from paper_1601_04359_amd import _abi
+    assert _abi.lpf_chain_stats(cx, cy) == _chain_stats_reference(cx, cy)
+
+
+def test_chain_stats_headline_cutoff():
+    # cutoff 128: the walk of the chains is 1 272 832 pixels per start word against
+    # M_c = 2 862 081 for one walk per vector (M_c pinned by the closed form of the memory count)
+    from paper_1601_04359_amd import _abi
+    s = _abi.lpf_chain_stats(128, 128)
+    assert s["vectors"] == 33025 and s["path_pixels"] == 2862081
+    assert s["chains"] == 11200 and s["walk"] == 1272832
+
+
+@pytest.mark.parametrize("cx,cy,nb", [(0, 0, 1), (1, 1, 4), (5, 9, 8), (16, 16, 64),
+                                      (40, 300, 512), (128, 128, 512), (255, 255, 1),
+                                      (512, 512, 256)])
+def test_full_plan_checks(cx, cy, nb):
+    # the launch plan of lpf_full (host logic): every vector exactly once, each one the walked
+    # path's pixel l with that path's first l + 1 pixels as its own path, bins within their slots
+    from paper_1601_04359_amd import _abi
+    r = _abi.lpf_plan_check(cx, cy, nb)
+    assert r["bins"] >= 1 and r["max_members"] <= 256
+    assert r["walk"] >= _abi.lpf_chain_stats(cx, cy)["walk"]

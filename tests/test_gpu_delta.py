@@ -119,12 +119,11 @@ def test_delta_cell_256_c48(ctx):
 
 
 def test_delta_many_candidates(ctx):
-    # a 4096-candidate batch (one annealing step's worth): sampled rows against the oracle,
-    # and the sum rule that holds for every row: sum over vectors of dL(0,0) = 0 (phase counts
-    # are preserved by an interchange)
+    # a 4096-candidate batch (one annealing step's worth) at 128 x 128, cutoff 32, both phases:
+    # every row against the oracle, and dL(0,0) = 0 (an interchange keeps the phase counts)
+    print("[gpu] delta 128x128 c=32, 4096 candidates, all rows", flush=True)
     img = wl.random_cell(128, 128, 5734, 6)
     sw = _swaps(img, 4096, 9)
     got = _gpu_delta(ctx, img, 32, 32, sw, 3)
     assert not got[:, :, 0].any()
-    idx = np.random.default_rng(0).choice(4096, 24, replace=False)
-    assert np.array_equal(got[idx], oracle.delta_swap(img, 32, 32, sw[idx], 3))
+    assert np.array_equal(got, oracle.delta_swap(img, 32, 32, sw, 3))

@@ -150,21 +150,18 @@ def _property_checks(img, got, cx, cy):
 
 def test_rsa_512_cutoff_128(ctx):
     # the 512 x 512, cutoff 128 workload at full size, in the benchmark's launch configuration:
-    # sampled vectors against the oracle, properties on all vectors
-    _announce("512x512 rsa disks, cutoff 128")
+    # every one of the 33 025 x 2 counts against the oracle (about a minute on 16 host threads)
+    _announce("512x512 rsa disks, cutoff 128, all vectors against the oracle")
     img = wl.rsa_512()
     got = _gpu_counts(ctx, img, 128, 128)
-    v = oracle.vectors(128, 128)
-    g = np.random.default_rng(4)
-    idx = np.unique(np.concatenate([g.choice(len(v), 120, replace=False), [0, 1, 128, 129, len(v) - 1],
-                                    np.flatnonzero((np.abs(v[:, 0]) == 128) | (v[:, 1] == 128))[:20]]))
-    ref = oracle.lpf_vectors(img, v[idx], 3)
-    assert np.array_equal(got[:, idx], ref)
+    ref = oracle.lpf(img, 128, 128, 3)
+    assert np.array_equal(got, ref), int((got != ref).sum())
     _property_checks(img, got, 128, 128)
 
 
 def test_tiled_large_image(ctx):
-    # a 1024 x 1024 image with cutoff 512 (several row tiles): tiling property + sampled oracle
+    # 1024 x 1024 images with cutoff 255 and 512 (several row tiles): tiling pins of every vector
+    # and sampled oracle vectors of a disk image
     _announce("1024x1024 cutoff 512 (row tiles)")
     small = wl.boolean_disks(256, 256, 9.0, 0.4, 17)
     img = np.tile(small, (4, 4))
@@ -174,6 +171,12 @@ def test_tiled_large_image(ctx):
     idx = np.unique(np.concatenate([g.choice(len(v), 60, replace=False), [0, len(v) - 1]]))
     sub = oracle.lpf_vectors(small, v[idx], 3).astype(np.int64)
     assert np.array_equal(got[:, idx].astype(np.int64), 16 * sub)
+    # 1024 x 1024 at cutoff 512 = a 256 (wide) x 64 (tall) tile repeated 4 x 16 times: every one
+    # of the 525 313 x 2 counts is 64 times the tile's (periodicity), the tile's from the oracle
+    tile = wl.boolean_disks(256, 64, 6.0, 0.4, 29)
+    got = _gpu_counts(ctx, np.tile(tile, (16, 4)), 512, 512)
+    sub = oracle.lpf_vectors(tile, oracle.vectors(512, 512), 3).astype(np.int64)
+    assert np.array_equal(got.astype(np.int64), 64 * sub)
     big = wl.boolean_disks(1024, 1024, 7.0, 0.35, 23)
     got = _gpu_counts(ctx, big, 512, 512)
     v = oracle.vectors(512, 512)
@@ -231,6 +234,55 @@ def test_enhanced_tiled(ctx):
     finally:
         ctx.set_full_shape(0, 0, 0, 0)
     assert np.array_equal(std, enh)
+
+
+def test_rows_from_device_memory_forced(ctx):
+    # a staging budget that cannot hold a row tile and its halo makes the kernel read rows of the
+    # extended image from device memory: same counts, standard, enhanced and sampled
+    _announce("rows from device memory (forced), 200x150 cutoff (40, 37)")
+    import torch
+    img = wl.boolean_disks(200, 150, 6.0, 0.45, 99)
+    ref = oracle.lpf(img, 40, 37, 3)
+    sample = wl.sample_positions(200, 150, 3000, 8)
+    bits = ctx.pack(torch.from_numpy(img).cuda())
+    sbits = ctx.pack(torch.from_numpy(sample).cuda())
+    try:
+        ctx.set_full_shape(0, 0, 0, 1)
+        std, enh = _both(ctx, img, 40, 37)
+        smp = ctx.full_sampled(bits, 200, 150, 40, 37, sbits, 3)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_full_shape(0, 0, 0, 0)
+    assert np.array_equal(std.astype(np.uint32), ref)
+    assert np.array_equal(enh.astype(np.uint32), ref)
+    assert np.array_equal(smp.cpu().numpy().astype(np.uint32),
+                          oracle.lpf_sampled(img, 40, 37, sample, 3))
+
+
+def test_full_domain_1024(ctx):
+    # the paper's whole domain (cutoff W - 1) at 1024 x 1024: the halo rows exceed LDS, so rows
+    # come from device memory.  The image is a 512 x 512 disk image tiled 2 x 2: every vector
+    # within the 512 image's own domain has 4 times that image's count (the 512 run stages its
+    # rows in LDS); longer vectors are checked on samples against the oracle, all by properties
+    _announce("1024x1024 full domain (cutoff 1023), rows from device memory")
+    small = wl.boolean_disks(512, 512, 8.0, 0.4, 41)
+    img = np.tile(small, (2, 2))
+    got = _gpu_counts(ctx, img, 1023, 1023)
+    sub = _gpu_counts(ctx, small, 511, 511)
+    v = oracle.vectors(1023, 1023)
+    inner = (np.abs(v[:, 0]) <= 511) & (v[:, 1] <= 511)
+    vi = v[inner].astype(np.int64)
+    pos = np.where(vi[:, 0] >= 0, vi[:, 1] * 512 + vi[:, 0],
+                   512 * 512 + (vi[:, 1] - 1) * 511 + vi[:, 0] + 511)
+    assert np.array_equal(got[:, inner].astype(np.int64), 4 * sub[:, pos].astype(np.int64))
+    g = np.random.default_rng(12)
+    far = np.flatnonzero(~inner)
+    idx = np.unique(np.concatenate([g.choice(far, 40, replace=False), [len(v) - 1], far[:3]]))
+    assert np.array_equal(got[:, idx], oracle.lpf_vectors(img, v[idx], 3))
+    sv = oracle.vectors(511, 511)
+    sidx = g.choice(len(sv), 30, replace=False)
+    assert np.array_equal(sub[:, sidx], oracle.lpf_vectors(small, sv[sidx], 3))
+    _property_checks(img, got, 1023, 1023)
 
 
 def test_cutoff_beyond_int16_is_refused(ctx):
