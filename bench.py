@@ -5,10 +5,14 @@ U[5, 20] px, volume fraction 0.3, seed 1602), all vectors with |dx|, |dy| <= 128
 bit-packed input already resident in device memory.  One step = one lpf_full call.
 
 Prints ONE JSON line.  `value` = path placements per second (|D_c| * W * H * phases / t).
-`roofline` reports the dominant kernel (k_lpf_full) against the integer-VALU peak, with its
-algorithmic op count (N/32)(3 M_c + 2 |D_c|): one funnel shift, one AND and one OR per segment
-pixel per 32 start pixels, and one popcount per vector per 32 start pixels per phase.
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+`roofline` reports the dominant kernel (k_lpf_full) against the integer-VALU peak (theoretical,
+and measured on the box by lpf_peak_probe), with the op count the kernel issues per launch:
+(N/32)(2 walk + 4 |D_c|), walk = pixels of the chains it walks (lpf_chain_stats): per walked pixel
+and 32 start pixels one funnel shift and half of a 3-input AND and of a 3-input OR, per vector
+two masks and two popcounts.  `cpu_baseline` times the CPU oracle on a bounded sample of the same
+workload (median of 5, all host threads and one), and `parity` compares those oracle counts with
+the GPU's.  `anneal` and `learned` are the metric's second half: time to a fixed LPF error of the
+128^2 reconstruction, and learned against uniform proposals on the 256^2 cell.
 """
 from __future__ import annotations
 
@@ -59,6 +63,67 @@ def path_pixels(cx: int, cy: int) -> int:
     return int(n[keep].sum())
 
 
+def host_threads() -> int:
+    """Host threads the oracle may use: the process's CPU affinity, capped by OMP_NUM_THREADS."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "threads_usable": host_threads()}
+
+
+def measure_peaks(ctx, stream, nwg=4096, iters=20000, reps=3) -> dict:
+    """Sustained int32 VALU rate (the path product's instruction mix: two funnel shifts, a
+    3-input AND and a 3-input OR) and LDS read bandwidth, from lpf_peak_probe launches timed with
+    events on `stream` (median of `reps`)."""
+    import numpy as np
+    import torch
+    from paper_1601_04359_amd import _abi
+    sink = torch.empty(nwg * 256, dtype=torch.int32, device=stream.device)
+    out = {}
+    with torch.cuda.stream(stream):
+        for kind, name in ((0, "valu_mix_tops"), (1, "valu_bitop3_tops"), (2, "valu_alignbit_tops"),
+                           (3, "valu_bcnt_tops"), (4, "lds_read_tbps")):
+            _abi.lpf_peak_probe(ctx.handle, kind, 100, nwg, sink, stream)
+            ts, work = [], 0.0
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                work = _abi.lpf_peak_probe(ctx.handle, kind, iters, nwg, sink, stream)
+                b.record(stream)
+                stream.synchronize()
+                ts.append(a.elapsed_time(b) / 1e3)
+            out[name] = round(work / float(np.median(ts)) / 1e12, 3)
+    return out
+
+
+def chain_ops(W: int, H: int, cx: int, cy: int) -> dict:
+    """Ops k_lpf_full issues per launch, (N/32)(2 walk + 4 |D_c|), and the per-vector walk's
+    count (N/32)(3 M_c + 2 |D_c|) of the same counts, for comparison."""
+    from paper_1601_04359_amd import _abi
+    st = _abi.lpf_chain_stats(cx, cy)
+    words = W * H / 32.0
+    return {"chains": st["chains"], "walk": st["walk"], "path_pixels": st["path_pixels"],
+            "ops_model": words * (2 * st["walk"] + 4 * st["vectors"]),
+            "ops_per_vector_walk": words * (3 * st["path_pixels"] + 2 * st["vectors"])}
+
+
 def ops_alg(W: int, H: int, cx: int, cy: int, nph: int) -> float:
     nv = (cx + 1) * (cy + 1) + cx * cy
     M = path_pixels(cx, cy)
@@ -73,21 +138,128 @@ def s2_ops_alg(W: int, H: int, cx: int, cy: int) -> float:
     return float(2 * nv * H * ((W + 31) // 32))
 
 
-def cpu_baseline(img, cx, cy, stride=16):
-    """The CPU oracle on every `stride`-th vector of the same workload (all host threads)."""
+def cpu_baseline(img, cx, cy, gpu_counts=None, stride_all=32, stride_one=256, reps=5):
+    """The CPU oracle on every `stride_all`-th vector of the same workload with all host threads
+    and on every `stride_one`-th vector with one thread, median of `reps` runs each; when the GPU
+    counts are given, the oracle counts of both samples are compared with them."""
     import numpy as np
     import oracle
-    v = oracle.vectors(cx, cy)[::stride]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    oracle.lpf_vectors(img, v, 3, nthreads=threads)
-    dt = time.perf_counter() - t0
+    v = oracle.vectors(cx, cy)
     H, W = img.shape
-    placements = len(v) * W * H * 2
-    return {"value": placements / dt / 1e9, "unit": "Gplacements/s", "cores": threads,
+    threads = host_threads()
+
+    def med(idx, nth):
+        ts, res = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = oracle.lpf_vectors(img, v[idx], 3, nthreads=nth)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), res
+
+    ia = np.arange(0, len(v), stride_all)
+    io = np.arange(0, len(v), stride_one)
+    ta, ra = med(ia, threads)
+    to, ro = med(io, 1)
+    parity = None
+    if gpu_counts is not None:
+        g = np.asarray(gpu_counts).astype(np.uint32)
+        parity = {"vectors_compared": int(len(np.union1d(ia, io))), "phases": 2,
+                  "equal": bool(np.array_equal(g[:, ia], ra) and np.array_equal(g[:, io], ro))}
+    base = {"value": len(ia) * W * H * 2 / ta / 1e9, "unit": "Gplacements/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{len(v)} of {len(oracle.vectors(cx, cy))} vectors (every {stride}th in "
-                      f"canonical order), both phases, {W}x{H}, {dt:.1f} s"}
+            "sample": f"{len(ia)} of {len(v)} vectors (every {stride_all}th in canonical order), "
+                      f"both phases, {W}x{H}; median of {reps} runs of {ta:.2f} s",
+            "one_core": {"value": len(io) * W * H * 2 / to / 1e9, "unit": "Gplacements/s",
+                         "cores": 1,
+                         "sample": f"{len(io)} vectors (every {stride_one}th), median of {reps} "
+                                   f"runs of {to:.2f} s"},
+            "cpu": host_cpu()}
+    return base, parity
+
+
+def chess_500(ctx, stream, reps: int = 5) -> dict:
+    """The paper's largest timing shape: chess with 10-pixel squares, 500 x 500, the whole domain
+    (cutoff 499), both phases; standard and enhanced evaluations (median of `reps`), next to the
+    paper's times for the same shape on its hardware (Table "comptime")."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    W = 500
+    img = wl.checkerboard(W, W, 10)
+    with torch.cuda.stream(stream):
+        bits = ctx.pack(torch.from_numpy(img).to(stream.device), stream=stream)
+        a = ctx.full(bits, W, W, W - 1, W - 1, 3, stream=stream)
+        b = ctx.full_enhanced(bits, W, W, W - 1, W - 1, 3, stream=stream)
+        stream.synchronize()
+
+        def med(fn):
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                stream.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts))
+        t_std = med(lambda: ctx.full(bits, W, W, W - 1, W - 1, 3, out=a, stream=stream))
+        t_enh = med(lambda: ctx.full_enhanced(bits, W, W, W - 1, W - 1, 3, out=b, stream=stream))
+    ref = PAPER_CHESS[500]
+    return {"standard_ms": round(t_std, 3), "enhanced_ms": round(t_enh, 3),
+            "counts_equal": bool(torch.equal(a, b)),
+            "paper_gpu_standard_s": ref["gpu_std"], "paper_gpu_enhanced_s": ref["gpu_enh"],
+            "paper_cpu_standard_s": ref["cpu_std"],
+            "paper_hardware": "one Quadro 4000 (Fermi), CUDA 6.5; CPU: one Xeon E5-2620 core"}
+
+
+def delta_bench(ctx, stream, steps: int) -> dict:
+    """Stateless lpf_delta_swap: 4096 uniform phase-preserving interchanges of the 128 x 128
+    reconstruction cell (seed 1), cutoff 32, phase 1, in one call.  Its algorithmic work is
+    4 sum_v (n_v + 1)^2 pixel tests per candidate and phase (old and new image on the placements
+    through a and through b); a bitwise kernel tests at most 32 start pixels per lane-op, so its
+    peak is 32 x the int32 VALU peak."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1601_04359_amd import _abi
+    W = H = 128
+    c, K, mask = 32, 4096, 2
+    cell = wl.random_cell(W, H, int(round(0.35 * W * H)), 1)
+    g = np.random.default_rng(1)
+    ones, zeros = np.flatnonzero(cell.ravel() == 1), np.flatnonzero(cell.ravel() == 0)
+    sw = np.stack([g.choice(ones, K), g.choice(zeros, K)], 1).astype(np.int32)
+    dev = torch.device("cuda:0")
+    with torch.cuda.stream(stream):
+        bits = ctx.pack(torch.from_numpy(cell).to(dev), stream=stream)
+        swaps = torch.from_numpy(sw).to(dev)
+        nv = (c + 1) * (c + 1) + c * c
+        delta = torch.empty((K, 1, nv), dtype=torch.int32, device=dev)
+        for _ in range(3):
+            _abi.lpf_delta_swap(ctx.handle, bits, W, H, c, c, mask, swaps, K, delta, stream)
+        ts = []
+        for _ in range(max(5, steps)):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            _abi.lpf_delta_swap(ctx.handle, bits, W, H, c, c, mask, swaps, K, delta, stream)
+            b.record(stream)
+            stream.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+    t = float(np.median(ts))
+    dx = np.arange(-c, c + 1)[None, :]
+    dy = np.arange(0, c + 1)[:, None]
+    n = np.maximum(np.abs(dx), dy) + 1
+    keep = ~((dy == 0) & (dx < 0))
+    tests = 4.0 * float((n[keep].astype(np.float64) ** 2).sum()) * K
+    rate = tests / t
+    return {"ms_median": round(t * 1e3, 4), "candidates_per_s": round(K / t, 1),
+            "pixel_tests_per_s_T": round(rate / 1e12, 3),
+            "roofline": {"bound": "alu", "achieved": round(rate / 32 / 1e12, 3),
+                         "peak": round(P_INT_TOPS, 3), "unit": "Tops/s (32 pixel tests per op)",
+                         "frac": round(rate / 32 / 1e12 / P_INT_TOPS, 4),
+                         "kernel": "k_delta (+k_ext3 in the event window)"},
+            "config": "128x128 cell, cutoff 32, phase 1, 4096 interchanges, one call"}
 
 
 def anneal_bench(args) -> dict:
@@ -118,6 +290,7 @@ def anneal_bench(args) -> dict:
     torch.cuda.synchronize()
     warm.close()
     walls, finals, accepted, e0, drift_ok, method = [], [], [], None, True, None
+    recs1 = None
     T_dev = torch.from_numpy(Ts).to(dev)
     for seed in range(1, args.chains + 1):
         ch = chain(seed)
@@ -130,6 +303,8 @@ def anneal_bench(args) -> dict:
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         r = step_records(recs)
+        if seed == 1:
+            recs1 = recs
         finals.append(float(r["e"][-1]))
         accepted.append(int((r["k"] >= 0).sum()))
         drift_ok &= bool(torch.equal(ctx.full(ch.bits, 128, 128, 32, 32, 2), ch.counts))
@@ -148,6 +323,33 @@ def anneal_bench(args) -> dict:
     ch.close()
     ctx.close()
     wall = float(np.median(walls))
+    eager_equal = bool(torch.equal(recs_e, recs1))
+    baseline = None
+    if getattr(args, "oracle_steps", 0):
+        # the oracle's chain 1 on the host cores: its target counts computed by the oracle, its
+        # first steps timed and compared with the GPU chain's records
+        import oracle
+        threads = host_threads()
+        t0 = time.perf_counter()
+        T_or = oracle.lpf(wl.anneal_target(), 32, 32, 2, nthreads=threads)
+        t_target = time.perf_counter() - t0
+        ref = oracle.AnnealState(cell, 32, 32, 2, T_or, 1024 * 1024, 1, nthreads=threads)
+        ns = min(args.oracle_steps, nsteps)
+        t0 = time.perf_counter()
+        res = ref.run(ns, 4096, Ts[:ns])
+        t_or = time.perf_counter() - t0
+        g = step_records(recs1[:ns])
+        same = (bool(np.array_equal(g["k"], res["k"])) and bool(np.array_equal(g["a"], res["a"]))
+                and bool(np.array_equal(g["b"], res["b"]))
+                and bool(np.array_equal(g["e"], res["e"])))
+        baseline = {"value": round(ns / t_or, 2), "unit": "steps/s", "cores": threads,
+                    "kind": "oracle",
+                    "sample": f"first {ns} steps of chain 1 (K = 4096, first-accept), after the "
+                              f"oracle's own target counts ({t_target:.1f} s)",
+                    "gpu_steps_per_s_same_chain": round(nsteps / walls[0], 1),
+                    "records_equal_gpu": same}
+        print(f"  oracle chain: {ns} steps in {t_or:.2f} s, equal to the GPU records: {same}",
+              file=sys.stderr, flush=True)
     return {
         "metric": "anneal time to fixed LPF error",
         "value": round(wall, 4),
@@ -173,6 +375,8 @@ def anneal_bench(args) -> dict:
         "wall_s_per_chain": [round(w, 4) for w in walls],
         "accepted_per_chain": accepted,
         "counts_equal_full_recount": drift_ok,
+        "eager_records_equal_graph": eager_equal,
+        "cpu_baseline": baseline,
         "eager_s_chain1": round(wall_eager, 4),
         "note": "each chain is one lpf_anneal_run call (hipGraph replays of 32 captured steps); "
                 "eager_s_chain1 is the first chain stepped by one anneal_step call per step",
@@ -744,9 +948,12 @@ def main() -> int:
                     help="timed steps (default 20; 20000 annealing steps for anneal/learned)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--no-anneal", action="store_true",
+                    help="default workload: leave out the annealing and learned-proposal keys")
+    ap.add_argument("--oracle-steps", type=int, default=200,
+                    help="anneal workload: oracle chain steps timed and compared with the GPU")
     ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper",
-                                           "mutual", "mc", "volume"],
+                                           "mutual", "mc", "volume", "peak"],
                     default="full")
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
@@ -772,6 +979,16 @@ def main() -> int:
 
     if args.workload == "anneal":
         print(json.dumps(anneal_bench(args)), flush=True)
+        return 0
+    if args.workload == "peak":
+        import torch
+        from paper_1601_04359_amd import Context
+        ctx = Context(0)
+        pk = measure_peaks(ctx, torch.cuda.Stream(device=torch.device("cuda:0")), reps=5)
+        ctx.close()
+        print(json.dumps({"metric": "sustained on-chip throughput", "value": pk["valu_mix_tops"],
+                          "unit": "Tops/s", "peaks": pk,
+                          "peak_theoretical_valu_tops": round(P_INT_TOPS, 3)}), flush=True)
         return 0
     if args.workload == "batch":
         print(json.dumps(batch_bench(args)), flush=True)
@@ -811,6 +1028,11 @@ def main() -> int:
         del src, dst
     ctx = Context(0)
     stream = torch.cuda.Stream(device=dev)
+    peaks = measure_peaks(ctx, stream)
+
+    def event_pair():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
     with torch.cuda.stream(stream):
         bits = ctx.pack(torch.from_numpy(img).to(dev), stream=stream)
         out = torch.empty((nph, (cx + 1) * (cy + 1) + cx * cy), dtype=torch.int32, device=dev)
@@ -818,8 +1040,7 @@ def main() -> int:
             ctx.full(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=out, stream=stream)
         stream.synchronize()
         # events on the launch stream, one pair per step
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+        evs = [event_pair() for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
@@ -829,14 +1050,26 @@ def main() -> int:
         stream.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # the same evaluation with the packed image copied from pinned host memory first (the
+        # paper's host-to-device copy of the image)
+        host_bits = bits.cpu().pin_memory()
+        bits_h = torch.empty_like(bits)
+        h2d = []
+        for _ in range(5):
+            a, b = event_pair()
+            a.record(stream)
+            bits_h.copy_(host_bits, non_blocking=True)
+            ctx.full(bits_h, W, H, cx, cy, 3, LPF_OUT_HALF, out=out, stream=stream)
+            b.record(stream)
+            stream.synchronize()
+            h2d.append(a.elapsed_time(b))
         # the paper's "enhanced" evaluation on the same image (same counts, reported separately)
         ref = out.clone()
         enh = torch.empty_like(out)
         ctx.full_enhanced(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=enh, stream=stream)
         stream.synchronize()
         enh_equal = bool(torch.equal(enh, ref))
-        eevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(args.steps)]
+        eevs = [event_pair() for _ in range(args.steps)]
         for i in range(args.steps):
             eevs[i][0].record(stream)
             ctx.full_enhanced(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=enh, stream=stream)
@@ -849,23 +1082,22 @@ def main() -> int:
         s2u = ctx.s2(bits, W, H, 1, 1, 3, LPF_OUT_HALF, stream=stream)
         stream.synchronize()
         s2_unit_ok = bool(torch.equal(unit, s2u))
-        sevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(args.steps)]
+        sevs = [event_pair() for _ in range(args.steps)]
         for i in range(args.steps):
             sevs[i][0].record(stream)
             ctx.s2(bits, W, H, cx, cy, 3, LPF_OUT_HALF, out=s2o, stream=stream)
             sevs[i][1].record(stream)
         stream.synchronize()
-    s2_ms = float(np.mean([a.elapsed_time(b) for a, b in sevs]))
+    s2_ms = float(np.median([a.elapsed_time(b) for a, b in sevs]))
     step_ms = [a.elapsed_time(b) for a, b in evs]
-    enh_ms = float(np.mean([a.elapsed_time(b) for a, b in eevs]))
+    enh_ms = float(np.median([a.elapsed_time(b) for a, b in eevs]))
     ms = wall * 1e3 / args.steps
     nv = (cx + 1) * (cy + 1) + cx * cy
     placements = nv * W * H * nph
     value = placements / (wall / args.steps) / 1e9
-    kern_s = float(np.mean(step_ms)) / 1e3
-    ops = ops_alg(W, H, cx, cy, nph)
-    achieved = ops / kern_s / 1e12
+    kern_s = float(np.median(step_ms)) / 1e3
+    co = chain_ops(W, H, cx, cy)
+    achieved = co["ops_model"] / kern_s / 1e12
     line = {
         "metric": "LPF path-placements/s",
         "value": round(value, 3),
@@ -886,31 +1118,67 @@ def main() -> int:
                      "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4),
                      "traffic": measured_traffic(),
                      "kernel": "k_lpf_full (+k_ext inside the event window)",
-                     "event_ms_mean": round(kern_s * 1e3, 4),
-                     "ops_alg_per_launch": ops},
-        "enhanced": {"ms_per_step": round(enh_ms, 4),
+                     "model": "int32 lane-ops issued per launch = (N/32)(2 walk + 4 |D_c|), "
+                              f"walk = {co['walk']} pixels over {co['chains']} chains",
+                     "ops_per_launch": co["ops_model"],
+                     "peak_theoretical": round(P_INT_TOPS, 3),
+                     "peak_measured": peaks["valu_mix_tops"],
+                     "frac_of_measured": round(achieved / peaks["valu_mix_tops"], 4),
+                     "event_ms_median": round(kern_s * 1e3, 4),
+                     "event_ms_mean": round(float(np.mean(step_ms)), 4),
+                     "ops_per_vector_walk": co["ops_per_vector_walk"],
+                     "per_vector_walk_equivalent_tops": round(
+                         co["ops_per_vector_walk"] / kern_s / 1e12, 3)},
+        "h2d_inclusive_ms_median": round(float(np.median(h2d)), 4),
+        "peaks_measured": peaks,
+        "enhanced": {"ms_median": round(enh_ms, 4),
                      "placements_per_s_G": round(placements / (enh_ms / 1e3) / 1e9, 3),
                      "speedup_vs_standard": round(kern_s * 1e3 / enh_ms, 3),
                      "counts_equal_standard": enh_equal,
-                     "note": "segments abandoned per wave once no start pixel can still count "
-                             "(Sec. 3.3 enhanced evaluation); not used for the roofline"},
+                     "note": "a chain's walk stops for a band once a member has no occurrence "
+                             "there (Sec. 3.2 enhanced evaluation); not used for the roofline"},
     }
     s2_ops = s2_ops_alg(W, H, cx, cy)
     s2_ach = s2_ops / (s2_ms / 1e3) / 1e12
-    line["s2"] = {"ms_per_step": round(s2_ms, 4),
+    line["s2"] = {"ms_median": round(s2_ms, 4),
                   "pair_placements_per_s_G": round(placements / (s2_ms / 1e3) / 1e9, 3),
                   "roofline": {"bound": "alu", "achieved": round(s2_ach, 3),
                                "peak": round(P_INT_TOPS, 3), "unit": "Tops/s",
                                "frac": round(s2_ach / P_INT_TOPS, 4),
                                "kernel": "k_s2_full (+k_s2_zero, k_s2_finish inside the event "
                                          "window)",
-                               "ops_alg_per_launch": s2_ops},
+                               "ops_per_launch": s2_ops},
                   "unit_steps_equal_lpf": s2_unit_ok,
                   "note": "two-point counts W*H*S2 of the same image and cutoff (Sec. 2.1), "
                           "both phases (phase 0 by eq. (S2add))"}
+    line["delta"] = delta_bench(ctx, stream, args.steps)
+    line["paper_chess_500"] = chess_500(ctx, stream)
+    gpu_counts = out.cpu().numpy()
     ctx.close()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(img, cx, cy, args.cpu_stride)
+        base, parity = cpu_baseline(img, cx, cy, gpu_counts)
+        line["cpu_baseline"] = base
+        line["parity"] = parity
+    if not args.no_anneal:
+        print("  anneal (128^2 cell, cutoff 32, 5 chains of 20000 steps)", file=sys.stderr,
+              flush=True)
+        an = anneal_bench(argparse.Namespace(steps=20000, warmup=3, chains=5,
+                                             oracle_steps=0 if args.no_cpu_baseline else 200))
+        line["anneal"] = {k: an[k] for k in ("metric", "value", "unit", "higher_is_better",
+                                             "ms_per_step", "e_start", "e_star",
+                                             "wall_s_per_chain", "counts_equal_full_recount",
+                                             "eager_records_equal_graph", "cpu_baseline")}
+        line["anneal"]["config"] = an["config"]
+        print("  learned (256^2 cell, cutoff 48, 5 chains)", file=sys.stderr, flush=True)
+        le = learned_bench(argparse.Namespace(steps=20000, warmup=3, chains=5, snapshots=256,
+                                              per_snapshot=4096, train_steps=400, beta=0.0,
+                                              refresh=4, rank=1))
+        line["learned"] = {k: le[k] for k in ("metric", "value", "unit", "higher_is_better",
+                                              "e_start", "e_star", "plain_s_median",
+                                              "plain_s_per_chain", "learned_s_per_chain",
+                                              "learned_steps_to_e_star", "speedup_vs_plain",
+                                              "train_s", "data_s")}
+        line["learned"]["config"] = le["config"]
     print(json.dumps(line), flush=True)
     return 0
 
