@@ -32,20 +32,23 @@ P_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 # HBM bytes per k_lpf_full launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled by the
 # same counters on a 256 MiB copy), profiles/k_lpf_full_512_c128.md.  Valid only for the kernel
 # source and tile-shape choice the counters were taken on; reported as null once either changes.
-MEASURED_TRAFFIC = {"src_sha256_16": "7431cbc5c17c54d1", "bytes": int(2057.78125 * 1024)}
+MEASURED_TRAFFIC = {"src_sha256_16": "ddf86ed3a84ecbf2", "bytes": int((2 * 833.938 + 1351.59) * 1024)}
 
 
 def source_hash() -> str:
-    """Hash of the kernel source and of the host function that picks its tile shape."""
+    """Hash of the kernel source, the plan builder, and the host functions that pick the tile
+    shape and the bins."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1601_04359_amd", "csrc")
     h = hashlib.sha256()
-    with open(os.path.join(csrc, "k_full.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("k_full.hip", "plan_full.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     with open(os.path.join(csrc, "lpf_api.hip"), "rb") as f:
         api = f.read()
-    i = api.index(b"bool choose_shape(")
-    h.update(api[i:api.index(b"\n}\n", i)])
+    for fn in (b"bool choose_shape(", b"lpf_status get_full_plan("):
+        i = api.index(fn)
+        h.update(api[i:api.index(b"\n}\n", i)])
     return h.hexdigest()[:16]
 
 

@@ -137,6 +137,29 @@ __device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int 
   }
 }
 
+// Valid start pixels of a lane's words, computed when a member's count is taken (not kept in
+// registers during the walk): word w = w0 + i of the row is full below the last word, the last
+// word keeps the bits below W mod 32, rows past the tile have none; with a Monte-Carlo position
+// set only its members count (its extended row read at the walked vector's shift).
+struct LaneMask {
+  int w0, swd;
+  uint32_t lastmask;
+  bool row_ok;
+  const uint32_t *srow;  // the position set's extended row at this lane's first word, or null
+  int so, ssh;
+};
+
+template <bool SAMPLE>
+__device__ __forceinline__ uint32_t lane_mask(const LaneMask &L, int i) {
+  const int w = L.w0 + i;
+  uint32_t mw = (w < L.swd - 1) ? 0xffffffffu : (w == L.swd - 1 ? L.lastmask : 0u);
+  if (!L.row_ok) mw = 0u;
+  if constexpr (SAMPLE) {
+    if (L.row_ok) mw &= __builtin_amdgcn_alignbit(L.srow[L.so + i + 1], L.srow[L.so + i], L.ssh);
+  }
+  return mw;
+}
+
 // Walk of one chain for the lane's R words of one row: A &= t, O |= t over the walked vector's
 // pixels; after pixel l of each member the wave's counts go to the member's slot.
 // XM: x is the major axis.  Q2: dx < 0 (mirrored in x and shifted by |dx|, a translation).
@@ -146,15 +169,16 @@ __device__ __forceinline__ void put_count(const FullImg &I, int p, int idx, int 
 //
 // SKIP (the paper's "enhanced" evaluation, Sec. 3.2): a member whose count over the wave's rows
 // is zero for every requested phase has no occurrence there, so neither has any longer member of
-// the chain; the walk stops at that member.  Between members the wave also tests, after 16, 32,
-// 64, ... pixels, whether any start pixel can still count (phase 1 needs a set bit of A, phase 0
-// a clear bit of O, under the valid mask mk).  Later pixels only clear A and set O, so the
-// counts are those of the full walk.
-template <int R, bool XM, bool Q2, bool SKIP, bool CANON>
+// the chain (later pixels only clear A and set O); the walk stops at that member.  The test reads
+// the count the member's emission has just summed.  Far from the next member the wave also
+// tests, after 32, 64, 128, ... pixels, whether any start pixel can still count.
+// FULL (wave-uniform): every bit of the lane's words is a start pixel (mk all ones), so the
+// popcounts need no mask.
+template <int R, bool XM, bool Q2, bool SKIP, bool CANON, bool SAMPLE>
 __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, int rst, int adx,
                                            int n, int m, const MemDesc *__restrict__ mems,
                                            int m0, int nm, int lw, uint32_t (&A)[R],
-                                           uint32_t (&O)[R], const uint32_t (&mk)[R],
+                                           uint32_t (&O)[R], const LaneMask &lm, bool full,
                                            unsigned phase_mask, uint32_t *__restrict__ slots,
                                            int lane) {
   int err = n, q = 0;
@@ -174,73 +198,60 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
   };
   int mi = 0;
   int next_l = CANON ? lw : __builtin_amdgcn_readfirstlane(mems[m0].l);
-  int next_test = 16;
+  int next_test = 32;
   int k = 0;
   for (;;) {
+    // the next two pixels, or one when a second would pass the member's end; one pixel is taken
+    // as a pair of equal pixels (A & t & t = A & t), so that the vector code has a single path
+    // and the accumulators stay in place
+    int off0, sh0, off1, sh1;
+    pixel(k, off0, sh0);
+    advance();
     if (k + 1 <= next_l) {
-      int off0, sh0, off1, sh1;
-      pixel(k, off0, sh0);
-      advance();
       pixel(k + 1, off1, sh1);
       advance();
-      const uint32_t *p0 = base + off0;
-      uint32_t t0[R], t1[R];
-      if (off0 == off1) {
-        uint32_t d[R + 1];
-#pragma unroll
-        for (int c = 0; c <= R; ++c) d[c] = p0[c];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          t0[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh0);
-          t1[i] = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh1);
-        }
-      } else {
-        const uint32_t *p1 = base + off1;
-        uint32_t d0[R + 1], d1[R + 1];
-#pragma unroll
-        for (int c = 0; c <= R; ++c) {
-          d0[c] = p0[c];
-          d1[c] = p1[c];
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          t0[i] = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
-          t1[i] = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0[i], t1[i], 0x80);
-        O[i] = O[i] | t0[i] | t1[i];
-      }
       k += 2;
     } else {
-      int off, sh;
-      pixel(k, off, sh);
-      advance();
-      const uint32_t *p = base + off;
-      uint32_t d[R + 1];
-#pragma unroll
-      for (int c = 0; c <= R; ++c) d[c] = p[c];
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const uint32_t t = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);
-        A[i] &= t;
-        O[i] |= t;
-      }
+      off1 = off0;
+      sh1 = sh0;
       k += 1;
+    }
+    const uint32_t *p0 = base + off0;
+    const uint32_t *p1 = base + off1;
+    uint32_t d0[R + 1], d1[R + 1];
+#pragma unroll
+    for (int c = 0; c <= R; ++c) {
+      d0[c] = p0[c];
+      d1[c] = p1[c];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const uint32_t t0 = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
+      const uint32_t t1 = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
+      A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0, t1, 0x80);
+      O[i] = O[i] | t0 | t1;
     }
     if (k - 1 == next_l) {
       // member mi ends at pixel next_l: phase 0 in the low half-word, phase 1 in the high one
       // (a lane counts at most 32 R <= 512 start pixels, a wave at most 32 768)
       uint32_t p0 = 0, p1 = 0;
+      if (full) {
+        if (phase_mask & 2u) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        p1 += __popc(A[i] & mk[i]);
-        p0 += __popc(~O[i] & mk[i]);
+          for (int i = 0; i < R; ++i) p1 += __popc(A[i]);
+        }
+        if (phase_mask & 1u) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) p0 += __popc(~O[i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const uint32_t mk = lane_mask<SAMPLE>(lm, i);
+          if (phase_mask & 2u) p1 += __popc(A[i] & mk);
+          if (phase_mask & 1u) p0 += __popc(~O[i] & mk);
+        }
       }
-      if (!(phase_mask & 2u)) p1 = 0;
-      if (!(phase_mask & 1u)) p0 = 0;
       const uint32_t s = wave_sum63(p0 | (p1 << 16));
       if (lane == 63 && s) {
         atomicAdd(slots + 2 * mi, s & 0xffffu);
@@ -252,13 +263,16 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
       }
       next_l = __builtin_amdgcn_readfirstlane(mems[m0 + mi].l);
     } else if constexpr (SKIP) {
-      if (k >= next_test) {
-        next_test *= 2;
+      // far from the next member: test after 32, 64, 128, ... pixels whether any start pixel
+      // can still count for a requested phase (a set bit of A, a clear bit of O, if valid)
+      if (k >= next_test && next_l - k >= 16) {
+        next_test = 2 * k;
         uint32_t live = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-          if (phase_mask & 2u) live |= A[i] & mk[i];
-          if (phase_mask & 1u) live |= ~O[i] & mk[i];
+          const uint32_t mk = full ? 0xffffffffu : lane_mask<SAMPLE>(lm, i);
+          if (phase_mask & 2u) live |= A[i] & mk;
+          if (phase_mask & 1u) live |= ~O[i] & mk;
         }
         if (!__any(live != 0u)) return;
       }
@@ -273,7 +287,8 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
 // chains of one member each (interleaving spreads long and short vectors evenly).
 // GLOB: rows are read from the extended image in device memory (one tile, I.lds_rows rows of
 // E with a periodic halo), for halos too large for LDS; only the count slots live in LDS.
-template <int R, bool SKIP, bool CANON = false, bool GLOB = false>
+// SAMPLE: I.sample holds a Monte-Carlo position set (the approximation's instance).
+template <int R, bool SKIP, bool CANON = false, bool GLOB = false, bool SAMPLE = false>
 __device__ __forceinline__ void process_item(const FullImg &I, int bin, int wpg,
                                              unsigned phase_mask, uint32_t *__restrict__ lds,
                                              uint32_t *__restrict__ slots) {
@@ -342,33 +357,37 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin, int wpg,
         const uint32_t *base =
             (GLOB ? I.E + (size_t)(Y0 + row) * I.rst : lds + row * I.rst) + strip * R;
         const bool row_ok = row < rows_here;
-        uint32_t A[R], O[R], mk[R];
+        uint32_t A[R], O[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           A[i] = 0xffffffffu;
           O[i] = 0u;
-          const int w = strip * R + i;
-          const uint32_t mw = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
-          mk[i] = row_ok ? mw : 0u;
         }
-        if (I.sample && row_ok) {
-          // Monte-Carlo approximation: only start pixels of the position set count.  Lane bit b
-          // of word w stands for the placement whose first pixel is 32w + b (+ |dx| of the
-          // walked vector when it is mirrored: the members share its frame), so the set's
-          // extended row is read at that shift.
-          const uint32_t *srow = I.sample + (size_t)(Y0 + row) * I.sample_stride + strip * R;
-          const int so = dx < 0 ? (adx >> 5) : 0, ssh = dx < 0 ? (adx & 31) : 0;
-#pragma unroll
-          for (int i = 0; i < R; ++i)
-            mk[i] &= __builtin_amdgcn_alignbit(srow[so + i + 1], srow[so + i], ssh);
-        }
+        // Monte-Carlo approximation: only start pixels of the position set count.  Lane bit b of
+        // word w stands for the placement whose first pixel is 32w + b (+ |dx| of the walked
+        // vector when it is mirrored: the members share its frame), so the set's extended row is
+        // read at that shift.
+        LaneMask lmk;
+        lmk.w0 = strip * R;
+        lmk.swd = swd;
+        lmk.lastmask = lastmask;
+        lmk.row_ok = row_ok;
+        lmk.srow = SAMPLE ? I.sample + (size_t)(Y0 + (row_ok ? row : 0)) * I.sample_stride + strip * R
+                          : nullptr;
+        lmk.so = dx < 0 ? (adx >> 5) : 0;
+        lmk.ssh = dx < 0 ? (adx & 31) : 0;
+        // every bit of every lane's words a start pixel: no masks at the members' counts
+        const bool lane_full = row_ok && !SAMPLE &&
+                               (strip * R + R - 1 < swd - 1 ||
+                                (strip * R + R - 1 == swd - 1 && lastmask == 0xffffffffu));
+        const bool full = __all(lane_full);
         const MemDesc *md = I.mems;
         if (xm) {
-          if (dx < 0) walk_chain<R, true, true, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
-          else walk_chain<R, true, false, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
+          if (dx < 0) walk_chain<R, true, true, SKIP, CANON, SAMPLE>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, lmk, full, phase_mask, cs, lane);
+          else walk_chain<R, true, false, SKIP, CANON, SAMPLE>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, lmk, full, phase_mask, cs, lane);
         } else {
-          if (dx < 0) walk_chain<R, false, true, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
-          else walk_chain<R, false, false, SKIP, CANON>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, mk, phase_mask, cs, lane);
+          if (dx < 0) walk_chain<R, false, true, SKIP, CANON, SAMPLE>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, lmk, full, phase_mask, cs, lane);
+          else walk_chain<R, false, false, SKIP, CANON, SAMPLE>(base, I.rst, adx, n, m, md, m0, nm, lw, A, O, lmk, full, phase_mask, cs, lane);
         }
       }
     }
@@ -393,17 +412,18 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin, int wpg,
   }
 }
 
-// One image, one workgroup per bin.
-template <int R, bool SKIP, bool GLOB = false>
-__global__ void __launch_bounds__(1024)
+// One image, one workgroup per bin.  At most 128 registers per lane (four waves per SIMD): at
+// the usual staging sizes LDS already limits a CU to two workgroups of eight waves.
+template <int R, bool SKIP, bool GLOB = false, bool SAMPLE = false>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
-  process_item<R, SKIP, false, GLOB>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
+  process_item<R, SKIP, false, GLOB, SAMPLE>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
 }
 
 // One image without chain tables (canonical vectors interleaved over the bins).
 template <int R>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   process_item<R, false, true>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
@@ -413,7 +433,7 @@ k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
 // descending cost order until the list is exhausted (every wave reaches the exit test).  The
 // counts pool is read from `args` (written before each replay of the captured launch); image i's
 // counts start at counts_off[i].
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_batch(const FullImg *__restrict__ imgs, const BatchArgs *__restrict__ args,
             const int64_t *__restrict__ counts_off, const int2 *__restrict__ items, int n_items,
             int *__restrict__ counter, int wpg, unsigned phase_mask, int cnt_off) {
@@ -462,7 +482,7 @@ size_t full_lds_bytes(const FullShape &sh, int wpg) {
 
 // The launch shape the kernel assumes: nwb waves per chain dividing the workgroup's waves.
 static bool shape_ok(const FullImg &I, const FullShape &sh) {
-  return sh.wpg >= 1 && sh.wpg <= 16 && I.nwb >= 1 && sh.wpg % I.nwb == 0 && sh.nbins >= 1 &&
+  return sh.wpg >= 1 && sh.wpg <= 8 && I.nwb >= 1 && sh.wpg % I.nwb == 0 && sh.nbins >= 1 &&
          I.nbins == sh.nbins && I.R == sh.R && 64 % I.S == 0;
 }
 
@@ -472,12 +492,24 @@ static hipError_t launch_full_r(const FullImg &I, const FullShape &sh, unsigned 
   if (!shape_ok(I, sh) || I.glob != sh.glob) return hipErrorInvalidValue;
   const size_t lds = full_lds_bytes(sh, sh.wpg);
   const int cnt_off = sh.glob ? 0 : sh.lds_rows * sh.rst;
-  if (sh.glob)
-    hipLaunchKernelGGL((k_lpf_full<R, SKIP, true>), dim3(sh.nbins), dim3(64 * sh.wpg), lds,
-                       stream, I, sh.wpg, phase_mask, cnt_off);
-  else
-    hipLaunchKernelGGL((k_lpf_full<R, SKIP>), dim3(sh.nbins), dim3(64 * sh.wpg), lds, stream, I,
-                       sh.wpg, phase_mask, cnt_off);
+  const dim3 g(sh.nbins), b(64 * sh.wpg);
+  if constexpr (SKIP) {  // the enhanced evaluation has no Monte-Carlo variant
+    if (I.sample) return hipErrorInvalidValue;
+    if (sh.glob)
+      hipLaunchKernelGGL((k_lpf_full<R, true, true>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+    else
+      hipLaunchKernelGGL((k_lpf_full<R, true>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+  } else if (I.sample) {
+    if (sh.glob)
+      hipLaunchKernelGGL((k_lpf_full<R, false, true, true>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+    else
+      hipLaunchKernelGGL((k_lpf_full<R, false, false, true>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+  } else {
+    if (sh.glob)
+      hipLaunchKernelGGL((k_lpf_full<R, false, true>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+    else
+      hipLaunchKernelGGL((k_lpf_full<R, false>), g, b, lds, stream, I, sh.wpg, phase_mask, cnt_off);
+  }
   return hipGetLastError();
 }
 
@@ -615,6 +647,11 @@ hipError_t prepare_full_kernels(int max_lds_bytes) {
                        (const void *)k_lpf_full<16, false, true>, (const void *)k_lpf_full<1, true, true>,
                        (const void *)k_lpf_full<2, true, true>, (const void *)k_lpf_full<4, true, true>,
                        (const void *)k_lpf_full<8, true, true>, (const void *)k_lpf_full<16, true, true>,
+                       (const void *)k_lpf_full<1, false, false, true>, (const void *)k_lpf_full<2, false, false, true>,
+                       (const void *)k_lpf_full<4, false, false, true>, (const void *)k_lpf_full<8, false, false, true>,
+                       (const void *)k_lpf_full<16, false, false, true>, (const void *)k_lpf_full<1, false, true, true>,
+                       (const void *)k_lpf_full<2, false, true, true>, (const void *)k_lpf_full<4, false, true, true>,
+                       (const void *)k_lpf_full<8, false, true, true>, (const void *)k_lpf_full<16, false, true, true>,
                        (const void *)k_lpf_full_canon<1>, (const void *)k_lpf_full_canon<2>,
                        (const void *)k_lpf_full_canon<4>, (const void *)k_lpf_full_canon<8>,
                        (const void *)k_lpf_full_canon<16>};

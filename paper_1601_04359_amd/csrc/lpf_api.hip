@@ -333,7 +333,6 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
       break;
     }
     budget = kBigLds;
-    if (!fW) sh.wpg = 16;  // one group per CU: use all of its waves
   }
   sh.ntiles = (H + sh.tile - 1) / sh.tile;
   sh.lds_rows = sh.tile + cy + rpw;
@@ -364,15 +363,16 @@ lpf_status get_full_plan(lpf_ctx c, int W, int H, int cx, int cy, FullPlan *&pla
     chs = c->chain_sets.find(std::make_pair(cx, cy));
   }
   const ChainSet &all = chs->second;
-  // Workgroup-level bins of chain pieces (pack_bins): as many bins as the device holds
-  // workgroups at once (every workgroup then walks about the same number of pixels), fewer when
-  // there are too few chains to keep each wave of a workgroup busy.
+  // Workgroup-level bins of chain pieces (pack_bins): twice as many bins as the device holds
+  // workgroups at once (each walks about the same number of pixels; the second wave of
+  // workgroups evens out what the cost model misses), fewer when there are too few chains to
+  // keep each wave of a workgroup busy.
   const int nwc = sh.wpg / sh.nwb;
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
   const int resident = cus * full_wgs_per_cu(sh.R, false, sh.wpg, full_lds_bytes(sh, sh.wpg));
   const int64_t nb_want =
-      std::min<int64_t>(resident, std::max<int64_t>(1, (int64_t)all.chains.size() / (4 * nwc)));
+      std::min<int64_t>(2 * resident, std::max<int64_t>(1, (int64_t)all.chains.size() / (4 * nwc)));
   BinPlan bp;
   pack_bins(all, nb_want, bp);
   sh.nbins = bp.nbins;
@@ -1172,10 +1172,10 @@ lpf_status lpf_full_sampled(lpf_ctx c, const uint64_t *bits, int W, int H, int c
 lpf_status lpf_set_full_shape(lpf_ctx c, int R, int S, int waves_per_group, int lds_bytes) {
   if (!c) return fail(LPF_E_INVAL, "lpf_set_full_shape: ctx is NULL");
   auto pow2ok = [](int v, int hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
-  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 16 ||
+  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 8 ||
       lds_bytes < 0 || lds_bytes > kMaxLds)
     return fail(LPF_E_INVAL, "lpf_set_full_shape: R in {1..16}, S in {1..64} powers of two, "
-                             "waves 1..16, lds <= 160 KiB (0 = automatic)");
+                             "waves 1..8, lds <= 160 KiB (0 = automatic)");
   std::lock_guard<std::mutex> lk(c->mu);
   c->force_R = R;
   c->force_S = S;
@@ -1888,18 +1888,9 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     c->batch_graphs.erase(lru);
   }
   if (it == c->batch_graphs.end()) {
-    // 16 waves per group when some image needs the large staging budget (one group per CU)
-    int wpg = 8;
-    for (int i = 0; i < n_images && wpg == 8; ++i) {
-      FullShape probe{};
-      std::string why;
-      const int saved_wpg = c->force_wpg;
-      c->force_wpg = 8;
-      const bool okp = choose_shape(c, descs[i].W, descs[i].H, descs[i].cx, descs[i].cy, probe, why);
-      c->force_wpg = saved_wpg;
-      if (!okp) return fail(LPF_E_UNSUPPORTED, "lpf_batch: " + why + " (image " + std::to_string(i) + ")");
-      if (full_lds_bytes(probe, 8) > 80 * 1024) wpg = 16;
-    }
+    // 8 waves per group (the kernels' register budget allows at most 8); every image's shape is
+    // checked while its plan is built
+    const int wpg = 8;
     std::vector<FullImg> imgs(n_images);
     std::vector<int64_t> bits_off(n_images), ext_off(n_images), counts_off(n_images);
     std::vector<std::pair<int64_t, int2>> items;
@@ -2032,7 +2023,7 @@ lpf_status lpf_autotune_full(lpf_ctx c, const uint64_t *bits, int W, int H, int 
   }
   for (int R : {2, 4, 8, 16}) {
     if (R > 2 * next_pow2(swd) && R > 2) continue;
-    for (int wpg : {4, 8, 16}) {
+    for (int wpg : {4, 8}) {
       for (int lds : {64 * 1024, kBigLds}) {
         c->force_R = R;
         c->force_S = 0;
