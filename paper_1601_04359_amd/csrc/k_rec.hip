@@ -613,17 +613,20 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
 // (step_apply).  Each workgroup takes the step's decision itself (ctl->ks, or the same scan of the
 // last round), so one launch replaces the upkeep kernel followed by the update kernel: the upkeep
 // touches counts, image bits, pixel lists and energy, none of which the update reads.
+// The update waves stride over the 2 nv (vector, side) pairs, so that the launch stays within
+// what the device holds at once (a second round of workgroups would repeat the whole latency
+// chain of decision, load and flips).
 template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __shared__ int s_ks0, s_first;
   __shared__ int32_t path[4][64];
-  // the wave's vector and path pixel do not depend on the decision: load them first, at clamped
-  // indices (no branch), so that they overlap the decision's reads
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wid = (int)blockIdx.x * 4 + wave;
-  const int v = wid >> 1;
-  const int4 m = g.meta[min(v, g.nv - 1)];
-  const int32_t pk = g.pix[m.x + min(lane, m.y)];
+  // the wave's first vector and path pixel do not depend on the decision: load them first, at
+  // clamped indices (no branch), so that they overlap the decision's reads
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wid0 = (int)blockIdx.x * 4 + wave;
+  const int v0 = wid0 >> 1;
+  int4 m = g.meta[min(v0, g.nv - 1)];
+  int32_t pk = g.pix[m.x + min(lane, m.y)];
   if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
   __syncthreads();
   const int ks0 = s_ks0;
@@ -632,9 +635,17 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
     step_apply(f, ks, ks0 < 0 && ks >= 0);
     return;
   }
-  if (ks < 0 || v >= g.nv) return;
+  if (ks < 0) return;
   const int2 ab = f.cand[ks];
-  rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk, path[wave]);
+  for (int wid = wid0; wid < 2 * g.nv; wid += 4 * nupd) {
+    const int v = wid >> 1;
+    if (wid != wid0) {
+      __builtin_amdgcn_wave_barrier();  // path[] of the previous pair is no longer read
+      m = g.meta[v];
+      pk = g.pix[m.x + min(lane, m.y)];
+    }
+    rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk, path[wave]);
+  }
 }
 
 #define LPF_REC_MASK_SWITCH(mask, CALL) \
@@ -658,7 +669,8 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
 }
 
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
-  const int nupd = (2 * g.nv + 3) / 4;  // one wave per (vector, side)
+  // one wave per (vector, side), at most 1024 update workgroups (the waves then stride)
+  const int nupd = std::min((2 * g.nv + 3) / 4, 1024);
 #define LPF_END(M) \
   hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
