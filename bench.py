@@ -217,52 +217,70 @@ def chess_500(ctx, stream, reps: int = 5) -> dict:
 
 
 def delta_bench(ctx, stream, steps: int) -> dict:
-    """Stateless lpf_delta_swap: 4096 uniform phase-preserving interchanges of the 128 x 128
-    reconstruction cell (seed 1), cutoff 32, phase 1, in one call.  Its algorithmic work is
-    4 sum_v (n_v + 1)^2 pixel tests per candidate and phase (old and new image on the placements
-    through a and through b); a bitwise kernel tests at most 32 start pixels per lane-op, so its
-    peak is 32 x the int32 VALU peak."""
+    """Stateless lpf_delta_swap: 4096 uniform phase-preserving interchanges in one call, on the
+    128 x 128 reconstruction cell with cutoff 32, phase 1 (headline) and on the 256 x 256 cell
+    with cutoff 48, both phases (the learned workload's shape).  Algorithmic work: 4 sum_v
+    (n_v + 1)^2 pixel tests per candidate and phase (old and new image on the placements through
+    a and through b); a bitwise kernel tests at most 32 placements per lane-op, so its peak is
+    32 x the int32 VALU peak.  Both recount methods are timed on the same call (offset rows, the
+    default, and runs of start columns) and their outputs compared."""
     import numpy as np
     import torch
     import workloads as wl
     from paper_1601_04359_amd import _abi
-    W = H = 128
-    c, K, mask = 32, 4096, 2
-    cell = wl.random_cell(W, H, int(round(0.35 * W * H)), 1)
-    g = np.random.default_rng(1)
-    ones, zeros = np.flatnonzero(cell.ravel() == 1), np.flatnonzero(cell.ravel() == 0)
-    sw = np.stack([g.choice(ones, K), g.choice(zeros, K)], 1).astype(np.int32)
     dev = torch.device("cuda:0")
-    with torch.cuda.stream(stream):
-        bits = ctx.pack(torch.from_numpy(cell).to(dev), stream=stream)
-        swaps = torch.from_numpy(sw).to(dev)
-        nv = (c + 1) * (c + 1) + c * c
-        delta = torch.empty((K, 1, nv), dtype=torch.int32, device=dev)
-        for _ in range(3):
-            _abi.lpf_delta_swap(ctx.handle, bits, W, H, c, c, mask, swaps, K, delta, stream)
-        ts = []
-        for _ in range(max(5, steps)):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            _abi.lpf_delta_swap(ctx.handle, bits, W, H, c, c, mask, swaps, K, delta, stream)
-            b.record(stream)
-            stream.synchronize()
-            ts.append(a.elapsed_time(b) / 1e3)
-    t = float(np.median(ts))
-    dx = np.arange(-c, c + 1)[None, :]
-    dy = np.arange(0, c + 1)[:, None]
-    n = np.maximum(np.abs(dx), dy) + 1
-    keep = ~((dy == 0) & (dx < 0))
-    tests = 4.0 * float((n[keep].astype(np.float64) ** 2).sum()) * K
-    rate = tests / t
-    return {"ms_median": round(t * 1e3, 4), "candidates_per_s": round(K / t, 1),
-            "pixel_tests_per_s_T": round(rate / 1e12, 3),
-            "roofline": {"bound": "alu", "achieved": round(rate / 32 / 1e12, 3),
-                         "peak": round(P_INT_TOPS, 3), "unit": "Tops/s (32 pixel tests per op)",
-                         "frac": round(rate / 32 / 1e12 / P_INT_TOPS, 4),
-                         "kernel": "k_delta (+k_ext3 in the event window)"},
-            "config": "128x128 cell, cutoff 32, phase 1, 4096 interchanges, one call"}
+
+    def one(W, c, mask, seed):
+        K = 4096
+        cell = wl.random_cell(W, W, int(round(0.35 * W * W)), seed)
+        g = np.random.default_rng(seed)
+        ones, zeros = np.flatnonzero(cell.ravel() == 1), np.flatnonzero(cell.ravel() == 0)
+        sw = np.stack([g.choice(ones, K), g.choice(zeros, K)], 1).astype(np.int32)
+        nph = (mask & 1) + (mask >> 1)
+        res = {}
+        with torch.cuda.stream(stream):
+            bits = ctx.pack(torch.from_numpy(cell).to(dev), stream=stream)
+            swaps = torch.from_numpy(sw).to(dev)
+            nv = (c + 1) * (c + 1) + c * c
+            outs = {}
+            for name, method in (("rows", _abi.LPF_SWAP_AUTO), ("runs", _abi.LPF_SWAP_RUNS)):
+                _abi.lpf_set_delta_method(ctx.handle, method)
+                delta = torch.empty((K, nph, nv), dtype=torch.int32, device=dev)
+                for _ in range(3):
+                    _abi.lpf_delta_swap(ctx.handle, bits, W, W, c, c, mask, swaps, K, delta, stream)
+                ts = []
+                for _ in range(max(5, steps) if name == "rows" else 5):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    _abi.lpf_delta_swap(ctx.handle, bits, W, W, c, c, mask, swaps, K, delta, stream)
+                    b.record(stream)
+                    stream.synchronize()
+                    ts.append(a.elapsed_time(b) / 1e3)
+                res[name] = float(np.median(ts))
+                outs[name] = delta
+            _abi.lpf_set_delta_method(ctx.handle, _abi.LPF_SWAP_AUTO)
+        dx = np.arange(-c, c + 1)[None, :]
+        dy = np.arange(0, c + 1)[:, None]
+        n = np.maximum(np.abs(dx), dy) + 1
+        keep = ~((dy == 0) & (dx < 0))
+        tests = 4.0 * float((n[keep].astype(np.float64) ** 2).sum()) * K * nph
+        t = res["rows"]
+        rate = tests / t
+        return {"ms_median": round(t * 1e3, 4), "runs_ms_median": round(res["runs"] * 1e3, 4),
+                "speedup_vs_runs": round(res["runs"] / t, 2),
+                "candidates_per_s": round(K / t, 1),
+                "pixel_tests_per_s_T": round(rate / 1e12, 3),
+                "roofline": {"bound": "alu", "achieved": round(rate / 32 / 1e12, 3),
+                             "peak": round(P_INT_TOPS, 3), "unit": "Tops/s (32 pixel tests per op)",
+                             "frac": round(rate / 32 / 1e12 / P_INT_TOPS, 4),
+                             "kernel": "k_delta_diag (+k_dframe in the event window)"},
+                "outputs_equal_runs": bool(torch.equal(outs["rows"], outs["runs"])),
+                "config": f"{W}x{W} cell, cutoff {c}, phase mask {mask}, 4096 interchanges, one call"}
+
+    out = one(128, 32, 2, 1)
+    out["cell_256_c48_both"] = one(256, 48, 3, 2)
+    return out
 
 
 def anneal_bench(args) -> dict:
@@ -956,7 +974,7 @@ def main() -> int:
     ap.add_argument("--oracle-steps", type=int, default=200,
                     help="anneal workload: oracle chain steps timed and compared with the GPU")
     ap.add_argument("--workload", choices=["full", "anneal", "batch", "learned", "paper",
-                                           "mutual", "mc", "volume", "peak"],
+                                           "mutual", "mc", "volume", "peak", "delta"],
                     default="full")
     ap.add_argument("--snapshots", type=int, default=256)
     ap.add_argument("--per-snapshot", type=int, default=4096)
@@ -995,6 +1013,15 @@ def main() -> int:
         return 0
     if args.workload == "batch":
         print(json.dumps(batch_bench(args)), flush=True)
+        return 0
+    if args.workload == "delta":
+        import torch
+        from paper_1601_04359_amd import Context
+        ctx = Context(0)
+        d = delta_bench(ctx, torch.cuda.Stream(device=torch.device("cuda:0")), args.steps)
+        ctx.close()
+        print(json.dumps({"metric": "interchange deltas", "value": d["candidates_per_s"],
+                          "unit": "candidates/s", "delta": d}), flush=True)
         return 0
     if args.workload == "learned":
         print(json.dumps(learned_bench(args)), flush=True)

@@ -171,11 +171,23 @@ lpf_status lpf_peak_probe(lpf_ctx ctx, int kind, int64_t iters, int nwg, uint32_
  * written in full) with delta[s][p][i] = L_p(I')(v_i) - L_p(I)(v_i), canonical vector order.
  * An interchange of two pixels of the same phase, a == b, or an index outside [0, W*H) gives an
  * all-zero row (indices live on the device and are not checked on the host).  Only the
- * translations whose segment covers a or b are recounted.  Same requirements on W, H, cx, cy,
- * phase_mask as lpf_full; 0 <= n <= 2^24.  Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
+ * translations whose segment covers a or b are recounted: by offset rows (for cutoffs up to 255,
+ * a per-cutoff table of at most 256 MB built on the first call) or by runs of start columns
+ * (any cutoff; see lpf_set_delta_method).  Same requirements on W, H, cx, cy, phase_mask as
+ * lpf_full; 0 <= n <= 2^24.  Errors: LPF_E_INVAL, LPF_E_NOMEM, LPF_E_DEVICE. */
 lpf_status lpf_delta_swap(lpf_ctx ctx, const uint64_t *bits, int W, int H, int cx, int cy,
                           unsigned phase_mask, const int32_t *swaps, int n, int32_t *delta,
                           void *stream);
+
+/* How later lpf_delta_swap calls on ctx recount (the results are identical):
+ * LPF_SWAP_AUTO: offset rows -- for a fixed difference d between a path index and a placement
+ *   index, the pixels of all placements of a vector lie on one image row (column) at two
+ *   neighbouring offsets, so one 32-bit window gives the pixel word of up to 32 placements --
+ *   when the cutoff's table fits, else runs;
+ * LPF_SWAP_RUNS: runs of contiguous start columns, one path product per start row.
+ * Errors: LPF_E_INVAL (NULL ctx, other method). */
+enum { LPF_SWAP_AUTO = 0, LPF_SWAP_RUNS = 1 };
+lpf_status lpf_set_delta_method(lpf_ctx ctx, int method);
 
 /* ---- 3-D volumes (the extension of Sec. 2; the ensemble of cuts of Sec. 6.3) ---------------- */
 

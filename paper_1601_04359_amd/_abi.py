@@ -27,6 +27,7 @@ LPF_E_UNSUPPORTED = -95
 LPF_PHASE0, LPF_PHASE1, LPF_BOTH = 1, 2, 3
 LPF_OUT_HALF, LPF_OUT_GRID = 0, 1
 LPF_DELTA_AUTO, LPF_DELTA_RECOUNT, LPF_DELTA_RECORDS, LPF_DELTA_S2 = 0, 1, 2, 3
+LPF_SWAP_AUTO, LPF_SWAP_RUNS = 0, 1
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _u64 = ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_uint64
@@ -59,6 +60,7 @@ _sig("lpf_plan_check", _i32, _i32, _i32, _i64, _P)
 _sig("lpf_peak_probe", _i32, _P, _i32, _i64, _i32, _P, ctypes.POINTER(ctypes.c_double), _P)
 _sig("lpf_set_full_shape", _i32, _P, _i32, _i32, _i32, _i32)
 _sig("lpf_delta_swap", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _i32, _P, _P)
+_sig("lpf_set_delta_method", _i32, _P, _i32)
 _sig("lpf_anneal_create", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
      _P, _i32, _P, ctypes.POINTER(_P), _P)
 _sig("lpf_anneal_create_s2", _i32, _P, _P, _i32, _i32, _i32, _i32, _u32, _P, _P, _i64, _u64, _u64,
@@ -253,6 +255,10 @@ def lpf_delta_swap(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: in
     _check(_lib.lpf_delta_swap(ctx, _dev(bits, torch.int64, "bits"), W, H, cx, cy, phase_mask,
                                _dev(swaps, torch.int32, "swaps") if n else None, n,
                                _dev(delta, torch.int32, "delta") if n else None, _stream(stream)))
+
+
+def lpf_set_delta_method(ctx: int, method: int) -> None:
+    _check(_lib.lpf_set_delta_method(ctx, method))
 
 
 def lpf_s2(ctx: int, bits: torch.Tensor, W: int, H: int, cx: int, cy: int, phase_mask: int,

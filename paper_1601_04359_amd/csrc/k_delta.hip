@@ -133,9 +133,261 @@ hipError_t launch_delta(const DeltaLaunch &L, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// ---- offset rows ----
+// Frames of the offset-row delta: frame 0 row r = y + cy holds x along its bits, frame 1 row
+// r = x + cx holds y; bit B + u is minor coordinate u, both coordinates periodic.
+__global__ void k_dframe(const uint64_t *__restrict__ bits, int W, int H, DiagGeo g,
+                         uint32_t *__restrict__ F) {
+  const int f = blockIdx.z;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= g.we[f] || r >= g.rows[f]) return;
+  const int wpr = (W + 63) >> 6;
+  const int Pr = f == 0 ? H : W, Pm = f == 0 ? W : H;
+  int maj = (r - g.rowoff[f]) % Pr;
+  maj += maj < 0 ? Pr : 0;
+  int u = (32 * e - g.B[f]) % Pm;
+  u += u < 0 ? Pm : 0;
+  uint32_t v = 0;
+  for (int t = 0; t < 32; ++t) {
+    const int x = f == 0 ? u : maj, y = f == 0 ? maj : u;
+    v |= (uint32_t)((bits[(size_t)y * wpr + (x >> 6)] >> (x & 63)) & 1ull) << t;
+    u = u + 1 == Pm ? 0 : u + 1;
+  }
+  F[(size_t)g.off[f] + (size_t)r * g.we[f] + e] = v;
+}
+
+hipError_t launch_dframe(const uint64_t *bits, int W, int H, const DiagGeo &g, uint32_t *F,
+                         hipStream_t stream) {
+  const int we = std::max(g.we[0], g.we[1]), rows = std::max(g.rows[0], g.rows[1]);
+  hipLaunchKernelGGL(k_dframe, dim3((we + 63) / 64, rows, 2), dim3(64), 0, stream, bits, W, H, g,
+                     F);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Lane state of one side (the pixel s whose placements are evaluated) in one frame: dword of
+// its row, its minor bit, and the other pixel q of the interchange relative to it (row
+// difference s - q, minor difference q - s), for the one-pixel change of the other side.
+struct SideFrame {
+  int row, minb, dr, dq;
+};
+
+__device__ __forceinline__ SideFrame side_frame(const DiagGeo &g, int f, int sx, int sy, int qx,
+                                                int qy) {
+  const int sr = f == 0 ? sy : sx, sm = f == 0 ? sx : sy;
+  const int qr = f == 0 ? qy : qx, qm = f == 0 ? qx : qy;
+  return SideFrame{g.off[f] + (sr + g.rowoff[f]) * g.we[f], sm + g.B[f], sr - qr, qm - sm};
+}
+
+// Bits of the window (origin o, frame row of offset du = sr * d) that hold the other pixel q.
+__device__ __forceinline__ uint32_t other_bits(const SideFrame &s, int du, int o, int Pr, int Pm,
+                                               uint32_t pat) {
+  const int x = s.dr + du;
+  const bool on_row = x == 0 || x == Pr || x == -Pr;
+  int t = s.dq - o;  // in (-2 Pm, 2 Pm)
+  t += t < 0 ? Pm : 0;
+  t += t < 0 ? Pm : 0;
+  t -= t >= Pm ? Pm : 0;
+  return (on_row && t < 32) ? pat << t : 0u;
+}
+
+__device__ __forceinline__ uint32_t window(const uint32_t *__restrict__ F, const SideFrame &s,
+                                           int du_dw, int o) {
+  const int pos = s.minb + o;
+  const uint32_t *p = F + s.row + du_dw + (pos >> 5);
+  return __builtin_amdgcn_alignbit(p[1], p[0], (uint32_t)pos);
+}
+
+}  // namespace
+
+// dL of candidate interchanges (lanes: 256 per workgroup) for the vector groups of chunk
+// blockIdx.y.  With J1 = I with b set to 1 and J0 = I with a cleared (a the phase-1 pixel):
+//   dL1 = sum_{P_b} lambda1(J1) - sum_{P_a} lambda1(J1),  dL0 = sum_{P_a} lambda0(J0) - sum_{P_b} lambda0(J0)
+// (a placement in both sets counts the same on both sides and cancels).  The pixel s itself
+// (d = 0) is 1 in J1 and 0 in J0 on either side, so it never decides a product and is skipped;
+// the only other changed pixel is b in side a's J1 and a in side b's J0.
+template <unsigned MASK, bool LDS>
+__global__ void __launch_bounds__(256)
+k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__restrict__ bits,
+             int W, int H, const int2 *__restrict__ cand, int K,
+             const DiagGroup *__restrict__ groups, const int32_t *__restrict__ chunk_off,
+             const DiagRow *__restrict__ rows, int nv, int32_t *__restrict__ out) {
+  extern __shared__ uint32_t lds[];
+  constexpr bool P0 = (MASK & 1u) != 0, P1 = (MASK & 2u) != 0;
+  constexpr int nph = (P0 ? 1 : 0) + (P1 ? 1 : 0);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = k < K;
+  int a = 0, b = 0;
+  if (ok) {
+    const int2 ab = cand[k];
+    a = ab.x;
+    b = ab.y;
+  }
+  const int64_t NN = (int64_t)W * H;
+  ok = ok && a >= 0 && b >= 0 && a < NN && b < NN && a != b;
+  if (ok) {
+    const int va = pixel_value(bits, W, a), vb = pixel_value(bits, W, b);
+    ok = va != vb;
+    if (va == 0) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+  }
+  if (!ok) {
+    a = 0;
+    b = 0;
+  }
+  const int ay = a / W, ax = a - ay * W, by = b / W, bx = b - by * W;
+  const uint32_t *F;
+  if constexpr (LDS) {
+    for (int i = threadIdx.x; i < geo.total; i += blockDim.x) lds[i] = Fg[i];
+    __syncthreads();
+    F = lds;
+  } else {
+    F = Fg;
+  }
+  // side 0: placements through a (other pixel b), side 1: through b (other pixel a)
+  const SideFrame sf[2][2] = {{side_frame(geo, 0, ax, ay, bx, by), side_frame(geo, 0, bx, by, ax, ay)},
+                              {side_frame(geo, 1, ax, ay, bx, by), side_frame(geo, 1, bx, by, ax, ay)}};
+  const int c0 = chunk_off[blockIdx.y], c1 = chunk_off[blockIdx.y + 1];
+  for (int gi = c0; gi < c1; ++gi) {
+    const DiagGroup &gr = groups[gi];
+    const int G = gr.G, n = gr.n, f = gr.frame, sr = gr.sr, nb = gr.nb, row0 = gr.row0;
+    const SideFrame s0 = f == 0 ? sf[0][0] : sf[1][0];
+    const SideFrame s1 = f == 0 ? sf[0][1] : sf[1][1];
+    const int we = f == 0 ? geo.we[0] : geo.we[1];
+    const int Pr = f == 0 ? H : W, Pm = f == 0 ? W : H;
+    const uint32_t pat = f == 0 ? geo.pat[0] : geo.pat[1];
+    int dl0[kDiagG], dl1[kDiagG];
+#pragma unroll
+    for (int g = 0; g < kDiagG; ++g) {
+      dl0[g] = 0;
+      dl1[g] = 0;
+    }
+    for (int bl = 0; bl < nb; ++bl) {
+      uint32_t A[2][kDiagG], O[2][kDiagG];
+#pragma unroll
+      for (int g = 0; g < kDiagG; ++g) {
+        A[0][g] = A[1][g] = 0xffffffffu;
+        O[0][g] = O[1][g] = 0u;
+      }
+      const int r1 = row0 + gr.boff[bl + 1];
+      for (int r = row0 + gr.boff[bl]; r < r1; ++r) {
+        const DiagRow &R = rows[r];
+        const int du = sr * (int)R.d, o = R.o;
+        const uint32_t valid = R.valid;
+        const uint32_t w0 = window(F, s0, du * we, o), w1 = window(F, s1, du * we, o);
+        // J1 on side 0 sets b; J0 on side 1 clears a
+        const uint32_t q0 = P1 ? other_bits(s0, du, o, Pr, Pm, pat) : 0u;
+        const uint32_t q1 = P0 ? other_bits(s1, du, o, Pr, Pm, pat) : 0u;
+        const uint32_t wa0 = w0 | q0, wo1 = w1 & ~q1;
+        // one word serves both products of a side unless its other pixel is in the window
+        const bool split = P0 && P1 && __builtin_amdgcn_ballot_w64((q0 | q1) != 0u) != 0;
+        auto step = [&](int g, uint32_t wA0, uint32_t wO0, uint32_t wA1, uint32_t wO1) {
+          const uint32_t j = R.j[g], hs = R.hs[g];
+          if constexpr (P1) {
+            const uint32_t t0 = __builtin_amdgcn_bitop3_b32(
+                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wA0, j + 1, 1),
+                (uint32_t)__builtin_amdgcn_sbfe((int)wA0, j, 1), 0xCA);
+            const uint32_t t1 = __builtin_amdgcn_bitop3_b32(
+                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wA1, j + 1, 1),
+                (uint32_t)__builtin_amdgcn_sbfe((int)wA1, j, 1), 0xCA);
+            A[0][g] = __builtin_amdgcn_bitop3_b32(A[0][g], t0, valid, 0xD0);  // A & (t | ~valid)
+            A[1][g] = __builtin_amdgcn_bitop3_b32(A[1][g], t1, valid, 0xD0);
+          }
+          if constexpr (P0) {
+            const uint32_t t0 = __builtin_amdgcn_bitop3_b32(
+                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wO0, j + 1, 1),
+                (uint32_t)__builtin_amdgcn_sbfe((int)wO0, j, 1), 0xCA);
+            const uint32_t t1 = __builtin_amdgcn_bitop3_b32(
+                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wO1, j + 1, 1),
+                (uint32_t)__builtin_amdgcn_sbfe((int)wO1, j, 1), 0xCA);
+            O[0][g] = __builtin_amdgcn_bitop3_b32(O[0][g], t0, valid, 0xF8);  // O | (t & valid)
+            O[1][g] = __builtin_amdgcn_bitop3_b32(O[1][g], t1, valid, 0xF8);
+          }
+        };
+        if (!split) {
+          // fast path: side 0's A word and side 1's O word carry their (absent) changes
+          const uint32_t x0 = P1 ? wa0 : w0, x1 = P0 ? wo1 : w1;
+#pragma unroll
+          for (int g4 = 0; g4 < kDiagG; g4 += 4) {
+            if (g4 >= G) break;
+#pragma unroll
+            for (int g = g4; g < g4 + 4; ++g) step(g, x0, x0, x1, x1);
+          }
+        } else {
+#pragma unroll
+          for (int g4 = 0; g4 < kDiagG; g4 += 4) {
+            if (g4 >= G) break;
+#pragma unroll
+            for (int g = g4; g < g4 + 4; ++g) step(g, wa0, w0, w1, wo1);
+          }
+        }
+      }
+      // placements of the block
+      const int nk = min(31, n - 32 * bl);
+      const uint32_t V = nk == 31 ? 0xffffffffu : ((1u << (nk + 1)) - 1u);
+#pragma unroll
+      for (int g = 0; g < kDiagG; ++g) {
+        if (P1) dl1[g] += __popc(A[1][g] & V) - __popc(A[0][g] & V);
+        if (P0) dl0[g] += __popc(~O[0][g] & V) - __popc(~O[1][g] & V);
+      }
+    }
+    if (k < K) {
+      int32_t *ok_out = out + (size_t)k * nph * nv;
+#pragma unroll
+      for (int g4 = 0; g4 < kDiagG; g4 += 4) {
+        if (g4 >= G) break;
+#pragma unroll
+        for (int g = g4; g < g4 + 4; ++g) {
+          if (g < G) {
+            const int idx = gr.idx[g];
+            int p = 0;
+            if (P0) ok_out[(size_t)(p++) * nv + idx] = ok ? dl0[g] : 0;
+            if (P1) ok_out[(size_t)p * nv + idx] = ok ? dl1[g] : 0;
+          }
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_delta_diag(const DiagLaunch &L, hipStream_t stream) {
+  const dim3 grid((unsigned)((L.K + 255) / 256), (unsigned)L.nchunks), block(256);
+  const size_t lds = L.use_lds ? (size_t)L.geo.total * sizeof(uint32_t) : 0;
+#define LPF_DIAG(M)                                                                             \
+  if (L.use_lds)                                                                                \
+    hipLaunchKernelGGL((k_delta_diag<M, true>), grid, block, lds, stream, L.F, L.geo, L.bits,   \
+                       L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv, L.delta_out); \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_delta_diag<M, false>), grid, block, 0, stream, L.F, L.geo, L.bits,    \
+                       L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv, L.delta_out);
+  switch (L.phase_mask) {
+    case 1: LPF_DIAG(1u); break;
+    case 2: LPF_DIAG(2u); break;
+    case 3: LPF_DIAG(3u); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LPF_DIAG
+  return hipGetLastError();
+}
+
 hipError_t prepare_delta_kernels(int max_lds_bytes) {
-  return hipFuncSetAttribute((const void *)k_delta<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             max_lds_bytes);
+  hipError_t e = hipFuncSetAttribute((const void *)k_delta<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_delta_diag<1u, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_delta_diag<2u, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_delta_diag<3u, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+  return e;
 }
 
 }  // namespace lpf

@@ -108,6 +108,16 @@ struct DeltaPlan {
   bool use_lds = false;
 };
 
+// Launch plan of the offset-row delta (plan_delta.hip): vector groups, rows, chunks (device).
+// ok = false: the table would exceed kDiagTableMax (the run-based kernel is used instead).
+struct DiagPlan {
+  DiagGroup *groups = nullptr;
+  DiagRow *rows = nullptr;
+  int32_t *chunk_off = nullptr;
+  int nchunks = 0;
+  bool ok = false;
+};
+
 // Launch plan of the two-point counts (k_s2.hip).
 struct S2Plan {
   int4 *fams = nullptr;      // device: vector families {dx0, dy, members}, sorted by dy
@@ -176,6 +186,7 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int, int, int, int, int>, FullPlan> full_plans;
   std::map<std::pair<int, int>, ChainSet> chain_sets;  // chains per cutoff (host)
   std::map<std::tuple<int, int, int, int, int>, DeltaPlan> delta_plans;
+  std::map<std::tuple<int, int, int>, DiagPlan> diag_plans;  // (cx, cy, chunks)
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
   // 3-D vectors per cutoff: sorted by major axis, longest first within each; the axis ranges
@@ -190,6 +201,7 @@ struct lpf_ctx_s {
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
+  bool force_run_delta = false;  // lpf_delta_swap through the run-based kernel (comparisons)
 };
 
 
@@ -653,6 +665,49 @@ lpf_status get_delta_plan(lpf_ctx c, int W, int H, int cx, int cy, int nchunks_r
   return LPF_OK;
 }
 
+constexpr size_t kDiagTableMax = (size_t)256 << 20;  // bytes of offset rows per plan
+
+lpf_status get_diag_plan(lpf_ctx c, int cx, int cy, int nchunks_req, DiagPlan *&plan) {
+  auto key = std::make_tuple(cx, cy, nchunks_req);
+  auto it = c->diag_plans.find(key);
+  if (it != c->diag_plans.end()) {
+    plan = &it->second;
+    return LPF_OK;
+  }
+  DiagPlan p;
+  DiagTable t;
+  bool built = false;
+  try {
+    built = std::max(cx, cy) <= 255 && build_diag_table(cx, cy, nchunks_req, kDiagTableMax, t);
+  } catch (const std::exception &ex) {
+    return fail(LPF_E_UNSUPPORTED, std::string("delta table: ") + ex.what());
+  }
+  if (built) {
+    hipError_t e;
+    if ((e = hipMalloc(&p.groups, sizeof(DiagGroup) * t.groups.size())) != hipSuccess ||
+        (e = hipMalloc(&p.rows, sizeof(DiagRow) * std::max<size_t>(1, t.rows.size()))) != hipSuccess ||
+        (e = hipMalloc(&p.chunk_off, sizeof(int32_t) * t.chunk_off.size())) != hipSuccess) {
+      (void)hipFree(p.groups);
+      (void)hipFree(p.rows);
+      (void)hipFree(p.chunk_off);
+      return hip_fail(e, "delta table allocation");
+    }
+    if ((e = hipMemcpy(p.groups, t.groups.data(), sizeof(DiagGroup) * t.groups.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (!t.rows.empty() && (e = hipMemcpy(p.rows, t.rows.data(), sizeof(DiagRow) * t.rows.size(), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(p.chunk_off, t.chunk_off.data(), sizeof(int32_t) * t.chunk_off.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipFree(p.groups);
+      (void)hipFree(p.rows);
+      (void)hipFree(p.chunk_off);
+      return hip_fail(e, "delta table upload");
+    }
+    p.nchunks = (int)t.chunk_off.size() - 1;
+    p.ok = true;
+  }
+  auto res = c->diag_plans.emplace(key, p);
+  plan = &res.first->second;
+  return LPF_OK;
+}
+
 // Number of vector chunks for K candidates: enough workgroups to fill the device.
 int delta_chunks(int K) {
   const int groups = (K + 255) / 256;
@@ -997,6 +1052,11 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.chunk_off);
       (void)hipFree(kv.second.runs);
     }
+    for (auto &kv : c->diag_plans) {
+      (void)hipFree(kv.second.groups);
+      (void)hipFree(kv.second.rows);
+      (void)hipFree(kv.second.chunk_off);
+    }
     for (auto &kv : c->vec3) (void)hipFree(kv.second.vec);
     for (auto &kv : c->s2_plans) {
       (void)hipFree(kv.second.fams);
@@ -1196,10 +1256,40 @@ lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx,
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->dev);
   if (!g.ok) return fail(LPF_E_DEVICE, "lpf_delta_swap: cannot select the context's device");
-  DeltaPlan *plan = nullptr;
-  if ((st = get_delta_plan(c, W, H, cx, cy, delta_chunks(n), plan)) != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
+  // offset rows where their table fits (cutoffs up to 255), else the run-based kernel
+  DiagPlan *dp = nullptr;
+  if (!c->force_run_delta) {
+    if ((st = get_diag_plan(c, cx, cy, delta_chunks(n), dp)) != LPF_OK) return st;
+  }
+  if (dp && dp->ok) {
+    const DiagGeo geo = diag_geometry(W, H, cx, cy);
+    if ((e = c->ext3.ensure((size_t)geo.total * 4)) != hipSuccess)
+      return hip_fail(e, "lpf_delta_swap: scratch");
+    if ((e = launch_dframe(bits, W, H, geo, (uint32_t *)c->ext3.p, s)) != hipSuccess)
+      return hip_fail(e, "lpf_delta_swap: frames");
+    DiagLaunch L{};
+    L.F = (const uint32_t *)c->ext3.p;
+    L.geo = geo;
+    L.bits = bits;
+    L.W = W;
+    L.H = H;
+    L.cand = reinterpret_cast<const int2 *>(swaps);
+    L.K = n;
+    L.groups = dp->groups;
+    L.chunk_off = dp->chunk_off;
+    L.rows = dp->rows;
+    L.nchunks = dp->nchunks;
+    L.phase_mask = phase_mask;
+    L.nv = (int)lpf_num_vectors(cx, cy);
+    L.delta_out = delta;
+    L.use_lds = (int64_t)geo.total * 4 <= kDeltaLdsMax;
+    if ((e = launch_delta_diag(L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
+    return LPF_OK;
+  }
+  DeltaPlan *plan = nullptr;
+  if ((st = get_delta_plan(c, W, H, cx, cy, delta_chunks(n), plan)) != LPF_OK) return st;
   if ((e = c->ext3.ensure((size_t)plan->geo.total * 4)) != hipSuccess)
     return hip_fail(e, "lpf_delta_swap: scratch");
   if ((e = launch_ext3(bits, W, H, plan->geo, (uint32_t *)c->ext3.p, s)) != hipSuccess)
@@ -1221,6 +1311,15 @@ lpf_status lpf_delta_swap(lpf_ctx c, const uint64_t *bits, int W, int H, int cx,
   L.nchunks = plan->nchunks;
   L.use_lds = plan->use_lds;
   if ((e = launch_delta(L, s)) != hipSuccess) return hip_fail(e, "lpf_delta_swap: kernel");
+  return LPF_OK;
+}
+
+lpf_status lpf_set_delta_method(lpf_ctx c, int method) {
+  if (!c) return fail(LPF_E_INVAL, "lpf_set_delta_method: ctx is NULL");
+  if (method != LPF_SWAP_AUTO && method != LPF_SWAP_RUNS)
+    return fail(LPF_E_INVAL, "lpf_set_delta_method: method must be LPF_SWAP_AUTO or LPF_SWAP_RUNS");
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->force_run_delta = method == LPF_SWAP_RUNS;
   return LPF_OK;
 }
 
@@ -1314,12 +1413,12 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
   // slabs in LDS when at least cz + 1 planes fit the 64 KiB budget (two workgroups per CU) or
   // the full LDS; otherwise rows from global memory
   const int rst = we | 1;
-  const size_t plane = (size_t)H * rst * sizeof(uint32_t);
+  const size_t plane = (size_t)(H + 2 * cy) * rst * sizeof(uint32_t);
   size_t budget = 64 * 1024;
   if ((size_t)(cz + 1) * plane > budget) budget = kMaxLds;
   if ((size_t)(cz + 1) * plane <= budget) {
     const int zb = (int)std::min<int64_t>(D, (int64_t)(budget / plane) - cz);
-    e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, zb, cz, vec,
+    e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, zb, cz, cy, vec,
                          v3p->maj_off, (int)nv, phase_mask, counts, s);
   } else {
     e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,

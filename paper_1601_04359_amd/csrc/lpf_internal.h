@@ -121,6 +121,67 @@ struct DeltaLaunch {
   bool use_lds;
 };
 
+// ---- stateless interchange deltas by offset rows (k_delta.hip, plan_delta.hip) ----
+// For placement s - p_k of a vector with major extent n and minor extent m, its pixel with path
+// index i = k + d is s + (p_{k+d} - p_k): the major coordinate moves by d (times the row step sr)
+// and the minor one by y_{k+d} - y_k, which is floor(d m / n) or one more for every k (y_k the
+// digitised minor coordinate of eq. (segments)).  So for a fixed d the pixels of all placements
+// k lie on one frame row at two neighbouring minor offsets, and one 32-bit window of that row,
+// two single-bit extracts and a select give the pixel word of all (up to 32) placements at once.
+// Vectors of one class (frame, row step, minor sign, n) with consecutive m share the d loop and
+// the window.
+constexpr int kDiagG = 16;
+struct DiagGroup {
+  int32_t row0;         // first row of block 0
+  int32_t boff[9];      // rows of placement block b: row0 + boff[b] .. row0 + boff[b + 1] - 1
+  int32_t idx[kDiagG];  // canonical vector indices
+  int16_t n;            // major extent
+  int8_t G;             // vectors
+  int8_t frame;         // 0: frame rows are y (steep vectors), 1: rows are x (flat vectors)
+  int8_t sr;            // frame row step per unit of d (+1 or -1)
+  int8_t nb;            // placement blocks of 32 (n + 1 placements)
+  int8_t pad[2];
+};
+struct DiagRow {
+  int16_t d;             // path index minus placement index (never 0)
+  int16_t o;             // window origin: minor offset (from the lane's pixel) of window bit 0
+  uint32_t valid;        // placements t of the block whose pixel index k + d lies in [0, n]
+  uint32_t hs[kDiagG];   // bit t set: placement t's pixel is window bit j + 1, else bit j
+  uint8_t j[kDiagG];     // window bit of the lower of the vector's two offsets (<= 30)
+};
+// Two extended frames with periodic halos: frame 0 rows r = y + cy (bits along x), frame 1 rows
+// r = x + cx (bits along y); bit B[f] + u of a row is minor coordinate u (mod the period).
+struct DiagGeo {
+  int we[2];        // dwords per row
+  int rows[2];      // rows per frame
+  int off[2];       // first dword of each frame
+  int total;        // dwords of both frames
+  int B[2];         // bit of minor coordinate 0
+  int rowoff[2];    // row of major coordinate 0 (cy, cx)
+  uint32_t pat[2];  // bits 0, P, 2P, ... below 32 for the minor period P (W, H)
+};
+struct DiagTable {
+  std::vector<DiagGroup> groups;  // chunk order
+  std::vector<DiagRow> rows;
+  std::vector<int32_t> chunk_off;  // nchunks + 1
+};
+struct DiagLaunch {
+  const uint32_t *F;
+  DiagGeo geo;
+  const uint64_t *bits;
+  int W, H;
+  const int2 *cand;
+  int K;
+  const DiagGroup *groups;
+  const int32_t *chunk_off;
+  const DiagRow *rows;
+  int nchunks;
+  unsigned phase_mask;
+  int nv;
+  int32_t *delta_out;
+  bool use_lds;
+};
+
 // Per-step control block of the round-wise evaluation (k_step.hip).
 struct StepCtl {
   int32_t done;      // a round has accepted
@@ -312,6 +373,13 @@ hipError_t launch_lse(const uint32_t *counts, const uint32_t *target, int64_t nt
                       int64_t Nt, double *e, hipStream_t stream);
 hipError_t launch_delta(const DeltaLaunch &L, hipStream_t stream);
 hipError_t prepare_delta_kernels(int max_lds_bytes);
+// Offset-row deltas (plan_delta.hip, k_delta.hip).  build_diag_table: false when the table
+// would exceed max_bytes.
+bool build_diag_table(int cx, int cy, int nchunks, size_t max_bytes, DiagTable &t);
+DiagGeo diag_geometry(int W, int H, int cx, int cy);
+hipError_t launch_dframe(const uint64_t *bits, int W, int H, const DiagGeo &g, uint32_t *F,
+                         hipStream_t stream);
+hipError_t launch_delta_diag(const DiagLaunch &L, hipStream_t stream);
 hipError_t launch_step(const StepLaunch &L, hipStream_t stream);
 hipError_t prepare_step_kernels(int max_lds_bytes);
 
@@ -383,12 +451,12 @@ double probe_work(int kind, int64_t iters, int nwg);
 hipError_t launch_lpf3(const uint32_t *E, int W, int H, int D, int we, int R, int S,
                        const int4 *vec, int nv, unsigned phase_mask, uint32_t *counts,
                        hipStream_t stream);
-// Slabs of zb start planes staged with their cz-plane halo in LDS ((zb + cz) * H * rst dwords),
-// counts accumulated with atomics (zeroed here first).
-// vec sorted by major axis (x, then y, then z; maj_off[0..3] the ranges, host array), longest
-// first within each.
+// Slabs of zb start planes staged with their cz-plane halo in LDS, each plane with cy periodic
+// halo rows above and below ((zb + cz) * (H + 2 cy) * rst dwords), counts accumulated with
+// atomics (zeroed here first).  vec sorted by major axis (x, then y, then z; maj_off[0..3] the
+// ranges, host array), longest first within each.
 hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst,
-                            int zb, int cz, const int4 *vec, const int *maj_off, int nv,
+                            int zb, int cz, int cy, const int4 *vec, const int *maj_off, int nv,
                             unsigned phase_mask, uint32_t *counts, hipStream_t stream);
 hipError_t prepare_lpf3_kernels(int max_lds_bytes);
 

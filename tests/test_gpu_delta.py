@@ -127,3 +127,34 @@ def test_delta_many_candidates(ctx):
     got = _gpu_delta(ctx, img, 32, 32, sw, 3)
     assert not got[:, :, 0].any()
     assert np.array_equal(got, oracle.delta_swap(img, 32, 32, sw, 3))
+
+
+@pytest.mark.parametrize("H,W,cx,cy,mask,n", [
+    (9, 7, 6, 8, 3, 40), (65, 64, 63, 64, 3, 40), (128, 128, 32, 32, 2, 256), (20, 300, 260, 3, 3, 12),
+])
+def test_delta_runs_method_equal(ctx, H, W, cx, cy, mask, n):
+    # the run-based recount (the only one for cutoffs above 255) against the offset rows and the
+    # oracle on the same interchanges
+    from paper_1601_04359_amd import _abi
+    print(f"[gpu] delta runs vs offset rows {H}x{W} c=({cx},{cy}) mask={mask}", flush=True)
+    img = wl.random_binary(W, H, 0.5, 3 * H + W)
+    sw = _swaps(img, n, W + 5, near=n // 3)
+    rows = _gpu_delta(ctx, img, cx, cy, sw, mask)
+    _abi.lpf_set_delta_method(ctx.handle, _abi.LPF_SWAP_RUNS)
+    try:
+        runs = _gpu_delta(ctx, img, cx, cy, sw, mask)
+    finally:
+        _abi.lpf_set_delta_method(ctx.handle, _abi.LPF_SWAP_AUTO)
+    ref = oracle.delta_swap(img, cx, cy, sw, mask)
+    assert np.array_equal(runs, ref)
+    assert np.array_equal(rows, ref)
+
+
+def test_delta_frames_in_device_memory(ctx):
+    # 512 x 512, cutoff 40: the two extended frames (about 95 KB) exceed the LDS budget and are
+    # read from device memory
+    print("[gpu] delta 512x512 c=40, frames in device memory", flush=True)
+    img = wl.boolean_disks(512, 512, 6.0, 0.35, 12)
+    sw = _swaps(img, 24, 4, near=8)
+    got = _gpu_delta(ctx, img, 40, 40, sw, 3)
+    assert np.array_equal(got, oracle.delta_swap(img, 40, 40, sw, 3))
