@@ -122,25 +122,30 @@ k_lpf3(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S,
 }
 
 // Slab variant: workgroup (blockIdx.x, blockIdx.y) stages planes Z0 .. Z0 + zb + cz - 1 (mod D),
-// Z0 = blockIdx.y * zb, of the extended volume in LDS (rst dwords per row, H rows per plane) and
-// its waves count vectors of vec[v0 .. v1) (vpw per wave; dz >= 0 for canonical vectors, so a
-// segment stays in the slab) over the start rows of planes Z0 .. Z0 + zb - 1; the slab's counts
-// are added into counts (zeroed before the launch) with integer atomics.  MAJ: the major axis of
-// every vector of the range (0 = x, 1 = y, 2 = z), so the voxel walk has no axis branches.
+// Z0 = blockIdx.y * zb, of the extended volume in LDS, each plane with cy periodic halo rows
+// above and below (HH = H + 2 cy rows of rst dwords, LDS row cy + y = volume row y), and its
+// waves count vectors of vec[v0 .. v1) (vpw per wave; dz >= 0 for canonical vectors, so a segment
+// stays in the slab, and |dy| <= cy, so it stays in the halo) over the start rows of planes
+// Z0 .. Z0 + zb - 1; the slab's counts are added into counts (zeroed before the launch) with
+// integer atomics.  MAJ: the major axis of every vector of the range (0 = x, 1 = y, 2 = z), so
+// the voxel walk has no axis branches.
 template <int R, int MAJ>
 __global__ void __launch_bounds__(512)
 k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, int rst, int zb,
-            int cz, const int4 *__restrict__ vec, int v0, int v1, int vpw, int nv,
+            int cz, int cy, const int4 *__restrict__ vec, int v0, int v1, int vpw, int nv,
             unsigned phase_mask, uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t lds[];
   const int Z0 = blockIdx.y * zb;
   const int planes = min(zb, D - Z0);  // start planes of this slab
   const int staged = planes + cz;
-  for (int i = threadIdx.x; i < staged * H * we; i += blockDim.x) {
-    const int pr = i / we, e = i - pr * we;  // pr = plane * H + row
-    const int pl = pr / H, y = pr - pl * H;
+  const int HH = H + 2 * cy;
+  for (int i = threadIdx.x; i < staged * HH * we; i += blockDim.x) {
+    const int pr = i / we, e = i - pr * we;  // pr = plane * HH + halo row
+    const int pl = pr / HH, yh = pr - pl * HH;
     int z = Z0 + pl;
     z = z >= D ? z - D : z;  // cz <= D - 1
+    int y = yh - cy;  // in [-cy, H + cy), cy <= H - 1
+    y = y < 0 ? y + H : (y >= H ? y - H : y);
     lds[pr * rst + e] = E[((size_t)z * H + y) * we + e];
   }
   __syncthreads();
@@ -169,15 +174,11 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
     const int ma = MAJ == 0 ? a1 : a0;  // minor a: y for MAJ 0, else x
     const int mb = MAJ == 2 ? a1 : a2;  // minor b: y for MAJ 2, else z
     uint32_t c0 = 0, c1 = 0;
-    // RPL start rows per lane per band: the scalar voxel walk is shared by their vector work
-    // a voxel's dword offset is the lane's row start (Pq) plus a wave-uniform part, plus or minus
-    // one period of rows when the lane's row wraps in y (from the voxel with qy >= Tq on: the
-    // minor coordinate only grows along the path and stays below H)
-    // offsets in bytes, so that they are LDS addresses as they stand
-    const int HR = H * rst * 4;
-    const int wadj = s1 > 0 ? -HR : HR;
+    // RPL start rows per lane per band: the scalar voxel walk is shared by their vector work.
+    // A voxel's byte offset is the lane's row start (Pq) plus a wave-uniform part; the halo rows
+    // make the y wrap unnecessary.  Offsets in bytes, so that they are LDS addresses as they stand.
     for (int r0 = 0; r0 < rows; r0 += rpw * RPL) {
-      int Pq[RPL], Tq[RPL];
+      int Pq[RPL];
       uint32_t A[RPL][R], O[RPL][R], mk[RPL][R];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
@@ -185,8 +186,7 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         const bool row_ok = r < rows;
         const int zr = row_ok ? r / H : 0;
         const int yr = row_ok ? r - zr * H : 0;
-        Pq[q] = (zr * H + yr) * rst * 4;
-        Tq[q] = s1 > 0 ? H - yr : yr + 1;
+        Pq[q] = (zr * HH + yr + cy) * rst * 4;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           A[q][i] = 0xffffffffu;
@@ -214,9 +214,9 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
         const int qy = MAJ == 1 ? k : (MAJ == 0 ? qa : qb);
         const int qz = MAJ == 2 ? k : qb;
         const int px = dx < 0 ? a0 - qx : qx;  // mirrored and shifted by |dx| when dx < 0
-        const int su = ((qz * H + s1 * qy) * rst + (px >> 5)) * 4;  // wave-uniform
+        const int su = ((qz * HH + s1 * qy) * rst + (px >> 5)) * 4;  // wave-uniform
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) off[q] = Pq[q] + su + (qy >= Tq[q] ? wadj : 0);
+        for (int q = 0; q < RPL; ++q) off[q] = Pq[q] + su;
         sh = px & 31;
       };
       int k = 0;
@@ -286,7 +286,7 @@ __global__ void k_lpf3_zero(uint32_t *__restrict__ counts, int64_t n) {
 }
 
 hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst,
-                            int zb, int cz, const int4 *vec, const int *maj_off, int nv,
+                            int zb, int cz, int cy, const int4 *vec, const int *maj_off, int nv,
                             unsigned phase_mask, uint32_t *counts, hipStream_t stream) {
   const int nph = (int)(phase_mask & 1u) + (int)((phase_mask >> 1) & 1u);
   const int64_t nc = (int64_t)nph * nv;
@@ -296,7 +296,7 @@ hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int 
   if (e != hipSuccess) return e;
   constexpr int kWaves = 8;
   const int nslab = (D + zb - 1) / zb;
-  const size_t lds = (size_t)(zb + cz) * H * rst * sizeof(uint32_t);
+  const size_t lds = (size_t)(zb + cz) * (H + 2 * cy) * rst * sizeof(uint32_t);
   for (int maj = 0; maj < 3; ++maj) {
     const int v0 = maj_off[maj], v1 = maj_off[maj + 1];
     const int cnt = v1 - v0;
@@ -308,7 +308,7 @@ hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int 
     const dim3 grid((unsigned)((cnt + kWaves * vpw - 1) / (kWaves * vpw)), (unsigned)nslab);
 #define LPF3S(RR, MM)                                                                           \
   hipLaunchKernelGGL((k_lpf3_slab<RR, MM>), grid, dim3(64 * kWaves), lds, stream, E, W, H, D,   \
-                     we, S, rst, zb, cz, vec, v0, v1, vpw, nv, phase_mask, counts)
+                     we, S, rst, zb, cz, cy, vec, v0, v1, vpw, nv, phase_mask, counts)
 #define LPF3M(RR)                               \
   switch (maj) {                                \
     case 0: LPF3S(RR, 0); break;                \

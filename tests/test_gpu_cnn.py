@@ -41,14 +41,20 @@ def _bits(ctx, imgs):
     return torch.cat([ctx.pack(torch.from_numpy(im).cuda()).reshape(-1) for im in imgs])
 
 
-# Tolerance: activations and weights are bf16 (8 significant bits, relative spacing 2^-8).  The
-# GPU accumulates in fp32 and the oracle in fp64, so a pre-activation within a rounding error of
-# a bf16 rounding boundary can round to the neighbouring bf16 value (one ulp, 2^-8 relative) on
-# one side only; through three layers such flips stay well below 2^-5 of the score scale.
-def _close(got, ref, frac=2.0 ** -5):
+# Tolerance: activations and weights are bf16 (8 significant bits, relative spacing 2^-8), and
+# the oracle rounds the same values to bf16 at the same places, so the two differ only by the
+# order and precision of the accumulation (fp32 against fp64): about 2^-24 relative per score.
+# The exception is a pre-activation within that distance of a bf16 rounding boundary, which
+# rounds to the neighbouring bf16 value (one ulp, 2^-8 relative) on one side only; such flips are
+# rare, and a flipped activation is diluted by the layers after it.  Hence two bounds: the 99th
+# percentile of the error stays at fp32 accumulation level (2^-20 of the score scale; measured
+# at most 8e-8), and the largest error stays below one bf16 ulp of the scale times two (2^-7;
+# measured at most 2.9e-3, on 6 of 16 384 scores of a 128 x 128 image).
+def _close(got, ref, typical=2.0 ** -20, worst=2.0 ** -7):
     scale = np.sqrt(np.mean(ref ** 2)) + 1e-12
     err = np.abs(got - ref)
-    assert np.max(err) <= frac * scale, (np.max(err), scale)
+    assert np.quantile(err, 0.99) <= typical * scale, (np.quantile(err, 0.99), scale)
+    assert np.max(err) <= worst * scale, (np.max(err), scale)
 
 
 @pytest.mark.parametrize("W,H,batch", [(16, 16, 1), (24, 40, 2), (128, 128, 2), (37, 29, 3),
@@ -97,15 +103,18 @@ def test_grad_matches_oracle(ctx):
     grad, loss = net.grad(_bits(ctx, imgs), 2, cnn_samples(idx, a, b, y, "cuda"))
     torch.cuda.synchronize()
     ref_loss, ref_grad = cnn.loss_and_grad(prm, imgs, np.stack([idx, a, b, y], 1))
-    assert abs(float(loss.cpu()[0]) - ref_loss) <= 2.0 ** -5 * ref_loss
+    # same rounding model on both sides (bf16 values, fp32 against fp64 sums): the loss agrees to
+    # fp32 accumulation level (measured 5e-9 relative), each gradient group to 2^-14 of its scale
+    # (measured at most 1.8e-6) and in direction to 1e-7
+    assert abs(float(loss.cpu()[0]) - ref_loss) <= 2.0 ** -20 * ref_loss
     got = grad.cpu().numpy().astype(np.float64)
     for k, off, size in _groups():
         gk, rk = got[off:off + size], ref_grad[off:off + size]
         scale = np.sqrt(np.mean(rk ** 2)) + 1e-12
-        assert np.max(np.abs(gk - rk)) <= 2.0 ** -4 * scale + 1e-7, (k, np.max(np.abs(gk - rk)), scale)
+        assert np.max(np.abs(gk - rk)) <= 2.0 ** -14 * scale, (k, np.max(np.abs(gk - rk)), scale)
         # direction: cosine similarity of each group
         cos = np.dot(gk, rk) / (np.linalg.norm(gk) * np.linalg.norm(rk) + 1e-30)
-        assert cos > 0.999, (k, cos)
+        assert cos > 1.0 - 1e-7, (k, cos)
     net.close()
 
 
