@@ -168,26 +168,30 @@ hipError_t launch_dframe(const uint64_t *bits, int W, int H, const DiagGeo &g, u
 namespace {
 
 // Lane state of one side (the pixel s whose placements are evaluated) in one frame: dword of
-// its row, its minor bit, and the other pixel q of the interchange relative to it (row
-// difference s - q, minor difference q - s), for the one-pixel change of the other side.
+// its row and its minor bit; for the other pixel q of the interchange, the two row offsets du
+// (from s) that can hold it, and its minor offset from s reduced to [0, P).
 struct SideFrame {
-  int row, minb, dr, dq;
+  int row, minb, du1, du2, dqn;
 };
 
 __device__ __forceinline__ SideFrame side_frame(const DiagGeo &g, int f, int sx, int sy, int qx,
-                                                int qy) {
+                                                int qy, int W, int H) {
+  const int Pr = f == 0 ? H : W, Pm = f == 0 ? W : H;
   const int sr = f == 0 ? sy : sx, sm = f == 0 ? sx : sy;
   const int qr = f == 0 ? qy : qx, qm = f == 0 ? qx : qy;
-  return SideFrame{g.off[f] + (sr + g.rowoff[f]) * g.we[f], sm + g.B[f], sr - qr, qm - sm};
+  // row s + du holds q iff du = q - s modulo Pr; |du| <= cutoff < Pr leaves two candidates
+  const int dr = qr - sr;  // in (-Pr, Pr)
+  const int du2 = dr > 0 ? dr - Pr : dr + Pr;
+  int dq = qm - sm;
+  dq += dq < 0 ? Pm : 0;
+  return SideFrame{g.off[f] + (sr + g.rowoff[f]) * g.we[f], sm + g.B[f], dr, du2, dq};
 }
 
-// Bits of the window (origin o, frame row of offset du = sr * d) that hold the other pixel q.
-__device__ __forceinline__ uint32_t other_bits(const SideFrame &s, int du, int o, int Pr, int Pm,
+// Bits of the window (origin o, frame row offset du) that hold the other pixel q.
+__device__ __forceinline__ uint32_t other_bits(const SideFrame &s, int du, int o, int Pm,
                                                uint32_t pat) {
-  const int x = s.dr + du;
-  const bool on_row = x == 0 || x == Pr || x == -Pr;
-  int t = s.dq - o;  // in (-2 Pm, 2 Pm)
-  t += t < 0 ? Pm : 0;
+  const bool on_row = du == s.du1 || du == s.du2;
+  int t = s.dqn - o;  // in (-Pm, 2 Pm)
   t += t < 0 ? Pm : 0;
   t -= t >= Pm ? Pm : 0;
   return (on_row && t < 32) ? pat << t : 0u;
@@ -202,6 +206,75 @@ __device__ __forceinline__ uint32_t window(const uint32_t *__restrict__ F, const
 
 }  // namespace
 
+// Rows r0 .. r1 - 1 of one placement block of a group of NG (a multiple of 4, >= G) vectors on
+// one side (0: placements through a, 1: through b), added into dl0 / dl1 with the side's sign.
+// The product that sees the other pixel's change is A on side 0 (b set in J1) and O on side 1
+// (a cleared in J0).
+template <unsigned MASK, int NG>
+__device__ __forceinline__ void side_rows(const uint32_t *__restrict__ F,
+                                          const DiagRow *__restrict__ rows, int r0, int r1,
+                                          const SideFrame &sx, int side, int sr, int we, int Pm,
+                                          uint32_t pat, uint32_t V, int (&dl0)[kDiagG],
+                                          int (&dl1)[kDiagG]) {
+  constexpr bool P0 = (MASK & 1u) != 0, P1 = (MASK & 2u) != 0;
+  const bool patch = side == 0 ? P1 : P0;
+  uint32_t A[NG], O[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    A[g] = 0xffffffffu;
+    O[g] = 0u;
+  }
+  for (int r = r0; r < r1; ++r) {
+    const DiagRow &R = rows[r];
+    const int du = sr * R.d, o = R.o;
+    const uint32_t valid = R.valid;
+    uint32_t hs[NG], jp[NG / 4];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) hs[g] = R.hs[g];
+#pragma unroll
+    for (int g = 0; g < NG / 4; ++g) jp[g] = R.jp[g];
+    const uint32_t w = window(F, sx, du * we, o);
+    const uint32_t q = patch ? other_bits(sx, du, o, Pm, pat) : 0u;
+    const uint32_t wA = side == 0 ? (w | q) : w, wO = side == 0 ? w : (w & ~q);
+    auto step = [&](int g, uint32_t xA, uint32_t xO) {
+      const uint32_t j = (jp[g >> 2] >> (8 * (g & 3))) & 0xffu;
+      if constexpr (P1) {
+        const uint32_t t = __builtin_amdgcn_bitop3_b32(
+            hs[g], (uint32_t)__builtin_amdgcn_sbfe((int)xA, j + 1, 1),
+            (uint32_t)__builtin_amdgcn_sbfe((int)xA, j, 1), 0xCA);
+        A[g] = __builtin_amdgcn_bitop3_b32(A[g], t, valid, 0xD0);  // A & (t | ~valid)
+      }
+      if constexpr (P0) {
+        const uint32_t t = __builtin_amdgcn_bitop3_b32(
+            hs[g], (uint32_t)__builtin_amdgcn_sbfe((int)xO, j + 1, 1),
+            (uint32_t)__builtin_amdgcn_sbfe((int)xO, j, 1), 0xCA);
+        O[g] = __builtin_amdgcn_bitop3_b32(O[g], t, valid, 0xF8);  // O | (t & valid)
+      }
+    };
+    // with both products, one word serves both unless the other pixel is in the window
+    if (P0 && P1 && __builtin_amdgcn_ballot_w64(q != 0u) != 0) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) step(g, wA, wO);
+    } else {
+      const uint32_t x = P1 ? wA : wO;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) step(g, x, x);
+    }
+  }
+  // dL1 = (through b) - (through a) for phase 1, the reverse for phase 0
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (P1) {
+      const int c = __popc(A[g] & V);
+      dl1[g] += side == 0 ? -c : c;
+    }
+    if (P0) {
+      const int c = __popc(~O[g] & V);
+      dl0[g] += side == 0 ? c : -c;
+    }
+  }
+}
+
 // dL of candidate interchanges (lanes: 256 per workgroup) for the vector groups of chunk
 // blockIdx.y.  With J1 = I with b set to 1 and J0 = I with a cleared (a the phase-1 pixel):
 //   dL1 = sum_{P_b} lambda1(J1) - sum_{P_a} lambda1(J1),  dL0 = sum_{P_a} lambda0(J0) - sum_{P_b} lambda0(J0)
@@ -209,7 +282,7 @@ __device__ __forceinline__ uint32_t window(const uint32_t *__restrict__ F, const
 // (d = 0) is 1 in J1 and 0 in J0 on either side, so it never decides a product and is skipped;
 // the only other changed pixel is b in side a's J1 and a in side b's J0.
 template <unsigned MASK, bool LDS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__restrict__ bits,
              int W, int H, const int2 *__restrict__ cand, int K,
              const DiagGroup *__restrict__ groups, const int32_t *__restrict__ chunk_off,
@@ -249,17 +322,16 @@ k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__res
   } else {
     F = Fg;
   }
-  // side 0: placements through a (other pixel b), side 1: through b (other pixel a)
-  const SideFrame sf[2][2] = {{side_frame(geo, 0, ax, ay, bx, by), side_frame(geo, 0, bx, by, ax, ay)},
-                              {side_frame(geo, 1, ax, ay, bx, by), side_frame(geo, 1, bx, by, ax, ay)}};
   const int c0 = chunk_off[blockIdx.y], c1 = chunk_off[blockIdx.y + 1];
   for (int gi = c0; gi < c1; ++gi) {
     const DiagGroup &gr = groups[gi];
     const int G = gr.G, n = gr.n, f = gr.frame, sr = gr.sr, nb = gr.nb, row0 = gr.row0;
-    const SideFrame s0 = f == 0 ? sf[0][0] : sf[1][0];
-    const SideFrame s1 = f == 0 ? sf[0][1] : sf[1][1];
+    // lane state in the group's frame (recomputed per group: fewer live registers); side 0:
+    // placements through a (other pixel b), side 1: through b (other pixel a)
+    const SideFrame s0 = side_frame(geo, f, ax, ay, bx, by, W, H);
+    const SideFrame s1 = side_frame(geo, f, bx, by, ax, ay, W, H);
     const int we = f == 0 ? geo.we[0] : geo.we[1];
-    const int Pr = f == 0 ? H : W, Pm = f == 0 ? W : H;
+    const int Pm = f == 0 ? W : H;
     const uint32_t pat = f == 0 ? geo.pat[0] : geo.pat[1];
     int dl0[kDiagG], dl1[kDiagG];
 #pragma unroll
@@ -267,73 +339,22 @@ k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__res
       dl0[g] = 0;
       dl1[g] = 0;
     }
+    const int ng4 = (G + 3) >> 2;
     for (int bl = 0; bl < nb; ++bl) {
-      uint32_t A[2][kDiagG], O[2][kDiagG];
-#pragma unroll
-      for (int g = 0; g < kDiagG; ++g) {
-        A[0][g] = A[1][g] = 0xffffffffu;
-        O[0][g] = O[1][g] = 0u;
-      }
-      const int r1 = row0 + gr.boff[bl + 1];
-      for (int r = row0 + gr.boff[bl]; r < r1; ++r) {
-        const DiagRow &R = rows[r];
-        const int du = sr * (int)R.d, o = R.o;
-        const uint32_t valid = R.valid;
-        const uint32_t w0 = window(F, s0, du * we, o), w1 = window(F, s1, du * we, o);
-        // J1 on side 0 sets b; J0 on side 1 clears a
-        const uint32_t q0 = P1 ? other_bits(s0, du, o, Pr, Pm, pat) : 0u;
-        const uint32_t q1 = P0 ? other_bits(s1, du, o, Pr, Pm, pat) : 0u;
-        const uint32_t wa0 = w0 | q0, wo1 = w1 & ~q1;
-        // one word serves both products of a side unless its other pixel is in the window
-        const bool split = P0 && P1 && __builtin_amdgcn_ballot_w64((q0 | q1) != 0u) != 0;
-        auto step = [&](int g, uint32_t wA0, uint32_t wO0, uint32_t wA1, uint32_t wO1) {
-          const uint32_t j = R.j[g], hs = R.hs[g];
-          if constexpr (P1) {
-            const uint32_t t0 = __builtin_amdgcn_bitop3_b32(
-                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wA0, j + 1, 1),
-                (uint32_t)__builtin_amdgcn_sbfe((int)wA0, j, 1), 0xCA);
-            const uint32_t t1 = __builtin_amdgcn_bitop3_b32(
-                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wA1, j + 1, 1),
-                (uint32_t)__builtin_amdgcn_sbfe((int)wA1, j, 1), 0xCA);
-            A[0][g] = __builtin_amdgcn_bitop3_b32(A[0][g], t0, valid, 0xD0);  // A & (t | ~valid)
-            A[1][g] = __builtin_amdgcn_bitop3_b32(A[1][g], t1, valid, 0xD0);
-          }
-          if constexpr (P0) {
-            const uint32_t t0 = __builtin_amdgcn_bitop3_b32(
-                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wO0, j + 1, 1),
-                (uint32_t)__builtin_amdgcn_sbfe((int)wO0, j, 1), 0xCA);
-            const uint32_t t1 = __builtin_amdgcn_bitop3_b32(
-                hs, (uint32_t)__builtin_amdgcn_sbfe((int)wO1, j + 1, 1),
-                (uint32_t)__builtin_amdgcn_sbfe((int)wO1, j, 1), 0xCA);
-            O[0][g] = __builtin_amdgcn_bitop3_b32(O[0][g], t0, valid, 0xF8);  // O | (t & valid)
-            O[1][g] = __builtin_amdgcn_bitop3_b32(O[1][g], t1, valid, 0xF8);
-          }
-        };
-        if (!split) {
-          // fast path: side 0's A word and side 1's O word carry their (absent) changes
-          const uint32_t x0 = P1 ? wa0 : w0, x1 = P0 ? wo1 : w1;
-#pragma unroll
-          for (int g4 = 0; g4 < kDiagG; g4 += 4) {
-            if (g4 >= G) break;
-#pragma unroll
-            for (int g = g4; g < g4 + 4; ++g) step(g, x0, x0, x1, x1);
-          }
-        } else {
-#pragma unroll
-          for (int g4 = 0; g4 < kDiagG; g4 += 4) {
-            if (g4 >= G) break;
-#pragma unroll
-            for (int g = g4; g < g4 + 4; ++g) step(g, wa0, w0, w1, wo1);
-          }
-        }
-      }
+      const int r0 = row0 + gr.boff[bl], r1 = row0 + gr.boff[bl + 1];
       // placements of the block
       const int nk = min(31, n - 32 * bl);
       const uint32_t V = nk == 31 ? 0xffffffffu : ((1u << (nk + 1)) - 1u);
-#pragma unroll
-      for (int g = 0; g < kDiagG; ++g) {
-        if (P1) dl1[g] += __popc(A[1][g] & V) - __popc(A[0][g] & V);
-        if (P0) dl0[g] += __popc(~O[0][g] & V) - __popc(~O[1][g] & V);
+      // side 0 (placements through a) and side 1 (through b) in turn: the accumulators of one
+      // side only are live; the vector count is a compile-time multiple of 4
+      for (int side = 0; side < 2; ++side) {
+        const SideFrame &sx = side == 0 ? s0 : s1;
+        switch (ng4) {
+          case 1: side_rows<MASK, 4>(F, rows, r0, r1, sx, side, sr, we, Pm, pat, V, dl0, dl1); break;
+          case 2: side_rows<MASK, 8>(F, rows, r0, r1, sx, side, sr, we, Pm, pat, V, dl0, dl1); break;
+          case 3: side_rows<MASK, 12>(F, rows, r0, r1, sx, side, sr, we, Pm, pat, V, dl0, dl1); break;
+          default: side_rows<MASK, 16>(F, rows, r0, r1, sx, side, sr, we, Pm, pat, V, dl0, dl1); break;
+        }
       }
     }
     if (k < K) {

@@ -198,7 +198,10 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
   };
   int mi = 0;
   int next_l = CANON ? lw : __builtin_amdgcn_readfirstlane(mems[m0].l);
+  // the next pixel index with work beside the path product: a member's end, or (SKIP) a
+  // liveness test; one compare per pixel pair either way
   int next_test = 32;
+  int next_ev = SKIP ? min(next_l, next_test) : next_l;
   int k = 0;
   for (;;) {
     // the next two pixels, or one when a second would pass the member's end; one pixel is taken
@@ -231,6 +234,7 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
       A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0, t1, 0x80);
       O[i] = O[i] | t0 | t1;
     }
+    if (k - 1 < next_ev) continue;
     if (k - 1 == next_l) {
       // member mi ends at pixel next_l: phase 0 in the low half-word, phase 1 in the high one
       // (a lane counts at most 32 R <= 512 start pixels, a wave at most 32 768)
@@ -263,10 +267,10 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
       }
       next_l = __builtin_amdgcn_readfirstlane(mems[m0 + mi].l);
     } else if constexpr (SKIP) {
-      // far from the next member: test after 32, 64, 128, ... pixels whether any start pixel
-      // can still count for a requested phase (a set bit of A, a clear bit of O, if valid)
-      if (k >= next_test && next_l - k >= 16) {
-        next_test = 2 * k;
+      // test after 32, 64, 128, ... pixels, when the next member is still far, whether any start
+      // pixel can still count for a requested phase (a set bit of A, a clear bit of O, if valid)
+      next_test = 2 * k;
+      if (next_l - k >= 16) {
         uint32_t live = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -277,6 +281,7 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
         if (!__any(live != 0u)) return;
       }
     }
+    next_ev = SKIP ? min(next_l, next_test) : next_l;
   }
 }
 

@@ -131,23 +131,27 @@ struct DeltaLaunch {
 // Vectors of one class (frame, row step, minor sign, n) with consecutive m share the d loop and
 // the window.
 constexpr int kDiagG = 16;
+// Every field is a 32-bit word: the kernel reads them with scalar loads (sub-dword fields would
+// be read per lane).
 struct DiagGroup {
   int32_t row0;         // first row of block 0
   int32_t boff[9];      // rows of placement block b: row0 + boff[b] .. row0 + boff[b + 1] - 1
   int32_t idx[kDiagG];  // canonical vector indices
-  int16_t n;            // major extent
-  int8_t G;             // vectors
-  int8_t frame;         // 0: frame rows are y (steep vectors), 1: rows are x (flat vectors)
-  int8_t sr;            // frame row step per unit of d (+1 or -1)
-  int8_t nb;            // placement blocks of 32 (n + 1 placements)
-  int8_t pad[2];
+  int32_t n;            // major extent
+  int32_t G;            // vectors
+  int32_t frame;        // 0: frame rows are y (steep vectors), 1: rows are x (flat vectors)
+  int32_t sr;           // frame row step per unit of d (+1 or -1)
+  int32_t nb;           // placement blocks of 32 (n + 1 placements)
+  int32_t pad;
 };
 struct DiagRow {
-  int16_t d;             // path index minus placement index (never 0)
-  int16_t o;             // window origin: minor offset (from the lane's pixel) of window bit 0
-  uint32_t valid;        // placements t of the block whose pixel index k + d lies in [0, n]
-  uint32_t hs[kDiagG];   // bit t set: placement t's pixel is window bit j + 1, else bit j
-  uint8_t j[kDiagG];     // window bit of the lower of the vector's two offsets (<= 30)
+  int32_t d;                  // path index minus placement index (never 0)
+  int32_t o;                  // window origin: minor offset (from the lane's pixel) of window bit 0
+  uint32_t valid;             // placements t of the block whose pixel index k + d lies in [0, n]
+  uint32_t hs[kDiagG];        // bit t set: placement t's pixel is window bit j + 1, else bit j
+  uint32_t jp[kDiagG / 4];    // byte g % 4 of word g / 4: window bit j of the lower of vector
+                              // g's two offsets (<= 30)
+  uint32_t pad;
 };
 // Two extended frames with periodic halos: frame 0 rows r = y + cy (bits along x), frame 1 rows
 // r = x + cx (bits along y); bit B[f] + u of a row is minor coordinate u (mod the period).

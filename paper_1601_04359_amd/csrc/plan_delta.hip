@@ -108,11 +108,11 @@ bool build_diag_table(int cx, int cy, int nchunks, size_t max_bytes, DiagTable &
     for (size_t g0 = 0; g0 < c.m.size(); g0 += kDiagG) {
       const int G = (int)std::min<size_t>(kDiagG, c.m.size() - g0);
       DiagGroup gr{};
-      gr.n = (int16_t)n;
-      gr.G = (int8_t)G;
-      gr.frame = (int8_t)c.frame;
-      gr.sr = (int8_t)c.sr;
-      gr.nb = (int8_t)((n + 32) / 32);
+      gr.n = n;
+      gr.G = G;
+      gr.frame = c.frame;
+      gr.sr = c.sr;
+      gr.nb = (n + 32) / 32;
       if (gr.nb > 8) throw std::runtime_error("diag table: more than 8 placement blocks");
       for (int g = 0; g < kDiagG; ++g) gr.idx[g] = g < G ? index.at(c.v[g0 + g]) : 0;
       // digitised minor coordinate y_k of each vector (eq. (segments))
@@ -129,7 +129,7 @@ bool build_diag_table(int cx, int cy, int nchunks, size_t max_bytes, DiagTable &
           const int lo = std::max(0, -d - kb0), hi = std::min(kb1 - kb0, n - d - kb0);
           if (lo > hi) continue;
           DiagRow r{};
-          r.d = (int16_t)d;
+          r.d = d;
           r.valid = (hi - lo == 31 ? 0xffffffffu : ((1u << (hi - lo + 1)) - 1u)) << lo;
           int lower[kDiagG];
           int omin = 1 << 30;
@@ -149,11 +149,11 @@ bool build_diag_table(int cx, int cy, int nchunks, size_t max_bytes, DiagTable &
             r.hs[g] = c.ms > 0 ? hib : ~hib;
             omin = std::min(omin, lower[g]);
           }
-          r.o = (int16_t)omin;
+          r.o = omin;
           for (int g = 0; g < G; ++g) {
             const int j = lower[g] - omin;
             if (j < 0 || j > 30) throw std::runtime_error("diag table: window span");
-            r.j[g] = (uint8_t)j;
+            r.jp[g / 4] |= (uint32_t)j << (8 * (g % 4));
           }
           rows.push_back(r);
         }
