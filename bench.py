@@ -180,6 +180,58 @@ def cpu_baseline(img, cx, cy, gpu_counts=None, stride_all=32, stride_one=256, re
     return base, parity
 
 
+def s2_full_domain(ctx, stream, bits, W, reps: int = 5) -> dict:
+    """Two-point counts over every shift of a W x W image (cutoff W - 1: the domain the paper
+    evaluates S2 on through the FFT, Sec. 2.1): the direct count, and for comparison the
+    autocorrelation of the phase-1 indicator by a float64 FFT (torch.fft on the same device,
+    rounded to integers and compared with the direct phase-1 counts)."""
+    import numpy as np
+    import torch
+    from paper_1601_04359_amd import LPF_OUT_HALF
+    c = W - 1
+    dev = stream.device
+
+    def med(fn):
+        fn()
+        stream.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            stream.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    with torch.cuda.stream(stream):
+        out = ctx.s2(bits, W, W, c, c, 3, LPF_OUT_HALF, stream=stream)
+        t_direct = med(lambda: ctx.s2(bits, W, W, c, c, 3, LPF_OUT_HALF, out=out, stream=stream))
+        # the phase-1 indicator, unpacked from the packed rows
+        words = bits.view(torch.int64).reshape(W, -1)
+        cols = torch.arange(W, device=dev)
+        ind = ((words[:, cols // 64] >> (cols % 64)) & 1).to(torch.float64)
+        holder = {}
+
+        def fft_s2():
+            F = torch.fft.rfft2(ind)
+            holder["S"] = torch.fft.irfft2(F * F.conj(), s=(W, W))
+        t_fft = med(fft_s2)
+        S = torch.round(holder["S"]).to(torch.int64)
+        dx = torch.cat([torch.arange(0, c + 1, device=dev).repeat(c + 1),
+                        torch.arange(-c, 0, device=dev).repeat(c)])
+        dy = torch.cat([torch.arange(0, c + 1, device=dev).repeat_interleave(c + 1),
+                        torch.arange(1, c + 1, device=dev).repeat_interleave(c)])
+        fft_counts = S[dy % W, dx % W]
+        equal = bool(torch.equal(fft_counts, out[1].to(torch.int64)))
+    return {"cutoff": c, "vectors": int(out.shape[1]), "direct_ms_median": round(t_direct, 4),
+            "fft_float64_torch_ms_median": round(t_fft, 4),
+            "fft_phase1_equal_direct": equal,
+            "note": "direct count of both phases' exact integers against one float64 FFT "
+                    "autocorrelation of phase 1 (rounded), both on this GPU"}
+
+
 def chess_500(ctx, stream, reps: int = 5) -> dict:
     """The paper's largest timing shape: chess with 10-pixel squares, 500 x 500, the whole domain
     (cutoff 499), both phases; standard and enhanced evaluations (median of `reps`), next to the
@@ -932,11 +984,16 @@ def batch_bench(args) -> dict:
     kern_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
     placements = 0
     ops = 0.0
+    ops_vec = 0.0
+    cops = {}
     for b in spec:
         c = b.side // 2
         nv = (c + 1) * (c + 1) + c * c
         placements += nv * b.side * b.side * 2
-        ops += ops_alg(b.side, b.side, c, c, 2)
+        if c not in cops:
+            cops[c] = chain_ops(b.side, b.side, c, c)
+        ops += cops[c]["ops_model"]
+        ops_vec += ops_alg(b.side, b.side, c, c, 2)
     achieved = ops / kern_s / 1e12
     sides = [b.side for b in spec]
     line = {
@@ -956,7 +1013,11 @@ def batch_bench(args) -> dict:
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(P_INT_TOPS, 3),
                      "unit": "Tops/s", "frac": round(achieved / P_INT_TOPS, 4), "traffic": None,
                      "kernel": "k_lpf_batch (+k_ext_batch in the event window)",
-                     "event_ms_mean": round(kern_s * 1e3, 3), "ops_alg_per_launch": ops},
+                     "model": "int32 lane-ops issued per launch = sum over images of "
+                              "(N/32)(2 walk + 4 |D_c|), walk = pixels over the cutoff's chains",
+                     "event_ms_mean": round(kern_s * 1e3, 3), "ops_per_launch": ops,
+                     "ops_per_vector_walk": ops_vec,
+                     "per_vector_walk_equivalent_tops": round(ops_vec / kern_s / 1e12, 3)},
     }
     ctx.close()
     return line
@@ -1181,6 +1242,7 @@ def main() -> int:
                   "unit_steps_equal_lpf": s2_unit_ok,
                   "note": "two-point counts W*H*S2 of the same image and cutoff (Sec. 2.1), "
                           "both phases (phase 0 by eq. (S2add))"}
+    line["s2"]["full_domain_512"] = s2_full_domain(ctx, stream, bits, W)
     line["delta"] = delta_bench(ctx, stream, args.steps)
     line["paper_chess_500"] = chess_500(ctx, stream)
     gpu_counts = out.cpu().numpy()

@@ -255,8 +255,9 @@ lpf_status lpf_batch(lpf_ctx ctx, const uint64_t *bits_pool, const lpf_image_des
                      int n_images, unsigned phase_mask, int out_layout, uint32_t *counts_pool,
                      void *stream);
 
-/* Autotuner for lpf_full: times the tile shapes R in {2,4,8,16}, waves per group in {4,8} and
- * staging budgets {64 KiB, 160 KiB} on the given image (several runs each, stream-ordered and
+/* Autotuner for lpf_full: times the tile shapes R in {2,4,8,16}, waves per group in {4,8} (and
+ * 16 with the 160 KiB budget, one group per CU) and staging budgets {64 KiB, 160 KiB} on the
+ * given image (several runs each, stream-ordered and
  * synchronised here) and records the fastest for images of this W, H, cx, cy in the context;
  * lpf_full and lpf_batch then use it.  *best_ms (host, may be NULL) receives its time.  This
  * replaces the paper's fixed occupancy rule, eq. (block).  Errors: as lpf_full. */
@@ -469,7 +470,8 @@ void lpf_cnn_destroy(lpf_cnn net);
 
 /* Tile-shape override for lpf_full (and the kernels that share its launch plans); used by the
  * autotuner.  R = 32-pixel words per lane (1,2,4,8,16), S = lanes per image row (power of two,
- * <= 64), waves_per_group (1..8), lds_bytes = staging budget per workgroup (<= 160 KiB; a
+ * <= 64), waves_per_group (1..16; automatic: 8, or 16 when the rows need the 160 KiB budget),
+ * lds_bytes = staging budget per workgroup (<= 160 KiB; a
  * budget too small for one row tile and its halo selects rows read from device memory).
  * 0 in any field restores the automatic choice for that field.  This replaces the paper's
  * occupancy rule for the block size, eq. (block).  Errors: LPF_E_INVAL for values out of range.

@@ -234,7 +234,9 @@ __device__ __forceinline__ void walk_chain(const uint32_t *__restrict__ base, in
       A[i] = __builtin_amdgcn_bitop3_b32(A[i], t0, t1, 0x80);
       O[i] = O[i] | t0 | t1;
     }
-    if (k - 1 < next_ev) continue;
+    if constexpr (SKIP) {
+      if (k - 1 < next_ev) continue;
+    }
     if (k - 1 == next_l) {
       // member mi ends at pixel next_l: phase 0 in the low half-word, phase 1 in the high one
       // (a lane counts at most 32 R <= 512 start pixels, a wave at most 32 768)
@@ -420,7 +422,7 @@ __device__ __forceinline__ void process_item(const FullImg &I, int bin, int wpg,
 // One image, one workgroup per bin.  At most 128 registers per lane (four waves per SIMD): at
 // the usual staging sizes LDS already limits a CU to two workgroups of eight waves.
 template <int R, bool SKIP, bool GLOB = false, bool SAMPLE = false>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   process_item<R, SKIP, false, GLOB, SAMPLE>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
@@ -428,7 +430,7 @@ k_lpf_full(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
 
 // One image without chain tables (canonical vectors interleaved over the bins).
 template <int R>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
   extern __shared__ uint32_t lds[];
   process_item<R, false, true>(I, blockIdx.x, wpg, phase_mask, lds, lds + cnt_off);
@@ -438,7 +440,7 @@ k_lpf_full_canon(FullImg I, int wpg, unsigned phase_mask, int cnt_off) {
 // descending cost order until the list is exhausted (every wave reaches the exit test).  The
 // counts pool is read from `args` (written before each replay of the captured launch); image i's
 // counts start at counts_off[i].
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 k_lpf_batch(const FullImg *__restrict__ imgs, const BatchArgs *__restrict__ args,
             const int64_t *__restrict__ counts_off, const int2 *__restrict__ items, int n_items,
             int *__restrict__ counter, int wpg, unsigned phase_mask, int cnt_off) {
@@ -487,7 +489,7 @@ size_t full_lds_bytes(const FullShape &sh, int wpg) {
 
 // The launch shape the kernel assumes: nwb waves per chain dividing the workgroup's waves.
 static bool shape_ok(const FullImg &I, const FullShape &sh) {
-  return sh.wpg >= 1 && sh.wpg <= 8 && I.nwb >= 1 && sh.wpg % I.nwb == 0 && sh.nbins >= 1 &&
+  return sh.wpg >= 1 && sh.wpg <= 16 && I.nwb >= 1 && sh.wpg % I.nwb == 0 && sh.nbins >= 1 &&
          I.nbins == sh.nbins && I.R == sh.R && 64 % I.S == 0;
 }
 

@@ -668,33 +668,9 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
   return hipGetLastError();
 }
 
-// Workgroups of k_rec_step_end<MASK> the device holds at once (registers and LDS), less one for
-// the upkeep workgroup.
-template <unsigned MASK>
-int rec_end_resident() {
-  static int cached = 0;
-  if (cached) return cached;
-  int dev = 0, cus = 256, per = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_rec_step_end<MASK>, 256,
-                                                   0) != hipSuccess || per < 1)
-    per = 1;
-  cached = std::max(64, cus * per - 1);
-  return cached;
-}
-
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
-  // one wave per (vector, side), at most as many update workgroups as stay resident beside the
-  // upkeep workgroup (the waves then stride: a second round of workgroups would queue behind
-  // the first)
-  int cap = 1024;
-  switch (g.mask) {
-    case 1: cap = rec_end_resident<1>(); break;
-    case 2: cap = rec_end_resident<2>(); break;
-    default: cap = rec_end_resident<3>(); break;
-  }
-  const int nupd = std::min((2 * g.nv + 3) / 4, cap);
+  // one wave per (vector, side), at most 1024 update workgroups (the waves then stride)
+  const int nupd = std::min((2 * g.nv + 3) / 4, 1024);
 #define LPF_END(M) \
   hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
@@ -704,10 +680,11 @@ hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t 
 
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream) {
-  // about 2048 workgroups (what the device holds at once at this kernel's register use): more
-  // only queue behind them, and a round after an accepting round is all early exits
+  // about 512 workgroups: a round after an accepting round is all early exits, whose cost grows
+  // with the grid (2 048 workgroups took 0.8 us longer per step); a round that does evaluate
+  // strides its candidates over them
   const int nvb = (L.rg.nv + 255) / 256;
-  const int gy = std::max(1, std::min(std::min(r.C, 512), (2048 + nvb - 1) / nvb));
+  const int gy = std::max(1, std::min(std::min(r.C, 512), (512 + nvb - 1) / nvb));
   const dim3 grid((unsigned)nvb, (unsigned)gy);
   int16_t *dl = decide ? L.dl : nullptr;
   // round 1 after a round 0 evaluated with the draws: round 0's sums are in S0

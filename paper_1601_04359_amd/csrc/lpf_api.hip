@@ -309,7 +309,7 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
   const int rpw = 64 / S;
   sh.R = R;
   sh.S = S;
-  // 8 waves per group when one tile fits the default budget (two groups per CU), else 16
+  // 8 waves per group when one tile fits the default budget (two groups per CU), else 16 (below)
   sh.wpg = fW ? fW : 8;
   sh.we = S * R + (cx >> 5) + 1;
   int best = sh.we, best_score = 1 << 30;
@@ -345,6 +345,9 @@ bool choose_shape(lpf_ctx c, int W, int H, int cx, int cy, FullShape &sh, std::s
       break;
     }
     budget = kBigLds;
+    // one workgroup per CU at this budget: 16 waves keep four per SIMD (1 024² at cutoff 512:
+    // 199 ms against 244 ms with 8)
+    if (!fW) sh.wpg = 16;
   }
   sh.ntiles = (H + sh.tile - 1) / sh.tile;
   sh.lds_rows = sh.tile + cy + rpw;
@@ -1232,10 +1235,10 @@ lpf_status lpf_full_sampled(lpf_ctx c, const uint64_t *bits, int W, int H, int c
 lpf_status lpf_set_full_shape(lpf_ctx c, int R, int S, int waves_per_group, int lds_bytes) {
   if (!c) return fail(LPF_E_INVAL, "lpf_set_full_shape: ctx is NULL");
   auto pow2ok = [](int v, int hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
-  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 8 ||
+  if (!pow2ok(R, 16) || !pow2ok(S, 64) || waves_per_group < 0 || waves_per_group > 16 ||
       lds_bytes < 0 || lds_bytes > kMaxLds)
     return fail(LPF_E_INVAL, "lpf_set_full_shape: R in {1..16}, S in {1..64} powers of two, "
-                             "waves 1..8, lds <= 160 KiB (0 = automatic)");
+                             "waves 1..16, lds <= 160 KiB (0 = automatic)");
   std::lock_guard<std::mutex> lk(c->mu);
   c->force_R = R;
   c->force_S = S;
@@ -1987,9 +1990,10 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     c->batch_graphs.erase(lru);
   }
   if (it == c->batch_graphs.end()) {
-    // 8 waves per group (the kernels' register budget allows at most 8); every image's shape is
-    // checked while its plan is built
-    const int wpg = 8;
+    // 8 waves per group, or 16 when some image's rows need so much LDS that only one group fits
+    // a CU (four waves per SIMD either way; one launch has one group size); every image's shape
+    // is checked while its plan is built
+    int wpg = 8;
     std::vector<FullImg> imgs(n_images);
     std::vector<int64_t> bits_off(n_images), ext_off(n_images), counts_off(n_images);
     std::vector<std::pair<int64_t, int2>> items;
@@ -1997,6 +2001,13 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
     size_t stage_max = 0;
     bool any_tiled = false;
     int max_we = 1, max_h = 1;
+    for (int pass = 0; pass < 2; ++pass) {
+    items.clear();
+    ext_total = 0;
+    stage_max = 0;
+    any_tiled = false;
+    max_we = 1;
+    max_h = 1;
     for (int i = 0; i < n_images; ++i) {
       const lpf_image_desc &d = descs[i];
       FullPlan *plan = nullptr;
@@ -2019,6 +2030,12 @@ lpf_status lpf_batch(lpf_ctx c, const uint64_t *bits_pool, const lpf_image_desc 
       for (int b = 0; b < sh.nbins; ++b)
         items.push_back({plan->bin_cost[b] * rows_work * sh.R + (int64_t)sh.lds_rows * sh.we * sh.ntiles,
                          make_int2(i, b)});
+    }
+    if (pass == 0 && (stage_max * 4 + (size_t)kSlotWords * 4) * 2 > (size_t)kMaxLds) {
+      wpg = 16;
+      continue;
+    }
+    break;
     }
     std::stable_sort(items.begin(), items.end(),
                      [](const std::pair<int64_t, int2> &a, const std::pair<int64_t, int2> &b) {
@@ -2122,8 +2139,9 @@ lpf_status lpf_autotune_full(lpf_ctx c, const uint64_t *bits, int W, int H, int 
   }
   for (int R : {2, 4, 8, 16}) {
     if (R > 2 * next_pow2(swd) && R > 2) continue;
-    for (int wpg : {4, 8}) {
+    for (int wpg : {4, 8, 16}) {
       for (int lds : {64 * 1024, kBigLds}) {
+        if (wpg == 16 && lds != kBigLds) continue;  // 16 waves only at one group per CU
         c->force_R = R;
         c->force_S = 0;
         c->force_wpg = wpg;
