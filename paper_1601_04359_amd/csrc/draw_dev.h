@@ -54,6 +54,14 @@ __device__ __forceinline__ int upper_index(const double *__restrict__ cw, int n,
   return lo;
 }
 
+// A list slot uniform in [0, n) from the high half of a 64-bit draw.
+__device__ __forceinline__ int uniform_slot(uint64_t r, int n) {
+  return (int)(((r >> 32) * (uint64_t)n) >> 32);
+}
+
+// Tag of step `step` in ProposeArgs::pre (never 0, the value of a cleared entry).
+__device__ __forceinline__ int pre_tag(uint64_t step) { return (int)(step & 0x3fffffffull) + 1; }
+
 // Candidate k of the current step: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
 // proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void (a = b = -1) unless
 // both pixels are interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn
@@ -72,8 +80,8 @@ __device__ __forceinline__ void draw_candidate(const ProposeArgs &p, int k, int 
     ia = upper_index(p.cw1, n1, ua);
     ib = upper_index(p.cw0, n0, ub);
   } else {
-    ia = (int)(((c[0] >> 32) * (uint64_t)n1) >> 32);
-    ib = (int)(((c[1] >> 32) * (uint64_t)n0) >> 32);
+    ia = uniform_slot(c[0], n1);
+    ib = uniform_slot(c[1], n0);
   }
   a = st->pos1[ia];
   b = st->pos0[ib];
@@ -105,6 +113,36 @@ __device__ __forceinline__ void propose_draw(const ProposeArgs &p, int k, int &a
   p.cand[k] = make_int2(a, b);
   p.slot[k] = make_int2(ia, ib);
   p.U[k] = u;
+  if (p.pre && p.proposal == 0 && k < 64) {
+    // the next step's slots of candidate k: the same draw with the step counter advanced (a
+    // phase-preserving interchange keeps n1 and n0)
+    const AnnealDev *st = p.st;
+    const uint64_t next = st->step + 1;
+    uint64_t c[4] = {next, (uint64_t)k, 0ull, 0ull};
+    philox4x64_10(c, p.seed, 0x6c7066ull);
+    p.pre[(int)(next & 1ull) * 64 + k] =
+        make_int4(uniform_slot(c[0], st->n1), uniform_slot(c[1], st->n0), pre_tag(next), 0);
+  }
+}
+
+// Candidate k (< 64) of the current step for round 0: its slots from the previous step's draw
+// when they were written for this step, else drawn here.  Only a and b are produced.
+__device__ __forceinline__ void round0_candidate(const ProposeArgs &p, int k, int &a, int &b) {
+  if (p.pre && p.proposal == 0) {
+    // both parities are read at once, beside the state, so that no load waits on the step
+    const int4 q0 = p.pre[k], q1 = p.pre[64 + k];
+    const AnnealDev *st = p.st;
+    const int tag = pre_tag(st->step);
+    const int4 q = q0.z == tag ? q0 : q1;
+    if (q.z == tag) {
+      a = st->pos1[q.x];
+      b = st->pos0[q.y];
+      return;
+    }
+  }
+  int ia, ib;
+  double u;
+  draw_candidate(p, k, a, b, ia, ib, u);
 }
 
 }  // namespace lpf

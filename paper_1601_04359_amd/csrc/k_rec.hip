@@ -373,9 +373,8 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
     Lc[q] = counts[(size_t)q * g.nv + vc];
     Tc[q] = target[(size_t)q * g.nv + vc];
   }
-  int a, b, ia, ib;
-  double u;
-  draw_candidate(p, kr, a, b, ia, ib, u);
+  int a, b;
+  round0_candidate(p, kr, a, b);
   int d[2];
   rec_delta<MASK, true>(g, p.bits, a, b, v, m, d);
   int64_t S = 0;

@@ -235,6 +235,7 @@ struct lpf_anneal_s {
   int refresh = 1, learn_age = 0;  // learned draws between re-scorings, draws since the last
   bool rank = false;               // evaluate learned draws by descending predicted gain
   DevBuf scores, cw1, cw0, cwb, eS, eCtl, order, rank_buf, S0;
+  DevBuf pre;              // uniform draws: the next step's round-0 list slots (ProposeArgs::pre)
   DevBuf Tcur;             // the current step's temperature (device scalar)
   uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
   hipStream_t cap = nullptr;  // private stream for capturing runs of steps
@@ -795,6 +796,8 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   p.rank_score = rank_score;
   p.rank_keys = rank_keys;
   p.rank_lists = rank_keys ? rank_keys + kRankMax : nullptr;
+  // a round 0 drawn in its own launch reads the slots the previous step's draw wrote
+  p.pre = defer && draw == LPF_PROP_UNIFORM && a->pre.p ? (int4 *)a->pre.p : nullptr;
   if (defer) {
     *defer = p;
     return LPF_OK;
@@ -1716,7 +1719,8 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
       (e = a->Tcur.ensure(sizeof(double))) != hipSuccess ||
       (e = a->order.ensure(sizeof(int32_t) * (size_t)K)) != hipSuccess ||
       (e = a->rank_buf.ensure(kRankScratch)) != hipSuccess ||
-      (e = ensure_zeroed(a->S0, sizeof(int64_t) * 64, s)) != hipSuccess)
+      (e = ensure_zeroed(a->S0, sizeof(int64_t) * 64, s)) != hipSuccess ||
+      (e = ensure_zeroed(a->pre, sizeof(int4) * 128, s)) != hipSuccess)
     return hip_fail(e, "anneal: scratch");
   if (proposal == LPF_PROP_LEARNED) {  // the draw's buffers, so that it allocates nothing
     const int64_t N = (int64_t)a->W * a->H;
@@ -1936,6 +1940,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->dl.release();
     a->ctl.release();
     a->scores.release();
+    a->pre.release();
     a->cw1.release();
     a->cw0.release();
     a->cwb.release();

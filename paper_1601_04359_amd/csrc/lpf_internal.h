@@ -249,6 +249,10 @@ struct ProposeArgs {
   double *T_cur;
   const float *rank_score;
   uint64_t *rank_keys, *rank_lists;
+  // uniform draws: the list slots of the next step's first 64 candidates, written by this step's
+  // draw (int4 {slot1, slot0, tag, 0} at (step & 1) * 64 + k, tag = (step & 0x3fffffff) + 1), so
+  // that the next round 0 skips the counter-based generator; null: none
+  int4 *pre;
 };
 struct StepLaunch {
   bool s2;                   // descriptor: two-point probability (k_s2.hip), else lineal path
