@@ -630,8 +630,10 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __syncthreads();
   const int ks0 = s_ks0;
   const int ks = step_choice(f, ks0, &s_first);
+  // counts += dL shared by all nupd + 1 workgroups (one term per thread at most sizes)
+  step_counts(f, ks, (int)blockIdx.x, nupd + 1);
   if ((int)blockIdx.x == nupd) {
-    step_apply(f, ks, ks0 < 0 && ks >= 0);
+    step_apply(f, ks, ks0 < 0 && ks >= 0, false);
     return;
   }
   if (ks < 0) return;

@@ -102,14 +102,22 @@ __device__ __forceinline__ int step_choice(const FinalArgs &f, int ks0, int *s_f
   return fst == INT_MAX ? -1 : (f.order ? f.order[f.li0 + fst] : f.li0 + fst);
 }
 
+// counts += dL of the accepted candidate ks for terms part, part + parts, ... (called by `parts`
+// workgroups, part = 0 .. parts - 1, each over its threads).
+__device__ __forceinline__ void step_counts(const FinalArgs &f, int ks, int part, int parts) {
+  if (ks < 0) return;
+  for (int t = part * (int)blockDim.x + (int)threadIdx.x; t < f.nterms; t += parts * (int)blockDim.x)
+    f.counts[t] = (uint32_t)((int32_t)f.counts[t] + (int32_t)f.dl[t * f.dl_t + ks * f.dl_k]);
+}
+
 // The step's upkeep by one workgroup, given its accepted candidate ks (or -1): the control block
-// when this step's decision was taken here (decided), counts += dL, image bits, pixel lists,
-// energy, the step's record and the step counter; S0 (when given) is cleared.
-__device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool decided) {
+// when this step's decision was taken here (decided), counts += dL (unless with_counts is false:
+// then the caller's workgroups share it through step_counts), image bits, pixel lists, energy,
+// the step's record and the step counter; S0 (when given) is cleared.
+__device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool decided,
+                                           bool with_counts = true) {
   if (f.S0 && threadIdx.x < 64) f.S0[threadIdx.x] = 0;  // clear for the next step's round 0
-  if (ks >= 0)
-    for (int t = threadIdx.x; t < f.nterms; t += blockDim.x)
-      f.counts[t] = (uint32_t)((int32_t)f.counts[t] + (int32_t)f.dl[t * f.dl_t + ks * f.dl_k]);
+  if (with_counts) step_counts(f, ks, 0, 1);
   if (threadIdx.x != 0) return;
   AnnealDev *st = f.st;
   StepResult *out = f.out_base >= 0 ? f.out + ((int64_t)st->step - f.out_base) : f.out;
