@@ -99,6 +99,8 @@ __device__ __forceinline__ void propose_draw(const ProposeArgs &p, int k, int &a
   if (p.ctl && k == 0) {
     p.ctl->done = 0;
     p.ctl->ks = -1;
+    p.ctl->a = -1;
+    p.ctl->b = -1;
     p.ctl->S = 0;
   }
   if (p.T_cur && k == 0)

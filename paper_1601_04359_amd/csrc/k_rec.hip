@@ -183,6 +183,63 @@ k_rec_build(RecGeo g) {
   }
 }
 
+// within() for |d| < M, without a division.
+__device__ __forceinline__ bool within_small(int d, int M, int r) {
+  const int m = d < 0 ? d + M : d;
+  return m <= r || M - m <= r;
+}
+
+// Calls hit(k) for every path index k of vector v (m = meta[v], n = m.y > 0) whose placement
+// x = a - p_k also lies in P_b, i.e. b - a = p_j - p_k for some j; (DX, DY) = b - a.  Along the
+// major axis p_j - p_k has the index difference t = j - k, so t is fixed modulo the period by
+// b - a: t = t0 for k <= n - t0 and t = t0 - P for k >= P - t0.  The minor coordinate of point k
+// is floor((2 k e + n) / 2n) (e the minor extent), so with the error term r_k = (2 k e + n) mod 2n
+// and 2 t e = q 2n + r (0 <= r < 2n) the minor difference of points k + t and k is q when
+// r_k < 2n - r and q + 1 otherwise: only when one of the two equals the minor part of b - a
+// (modulo its period) are the error terms walked, with no division in the loop.
+template <class F>
+__device__ __forceinline__ void both_placements(const RecGeo &g, int4 m, int DX, int DY, F &&hit) {
+  const int n = m.y, dxv = m.z, dyv = m.w;
+  const int adx = dxv < 0 ? -dxv : dxv;
+  const bool xm = adx >= dyv;
+  const int sx = dxv < 0 ? -1 : 1;
+  const int Pm = xm ? g.W : g.H, Qm = xm ? g.H : g.W;
+  int t0 = xm ? sx * DX : DY;  // in (-Pm, Pm)
+  t0 += t0 < 0 ? Pm : 0;
+  int mm = xm ? DY : sx * DX;  // in (-Qm, Qm)
+  mm += mm < 0 ? Qm : 0;
+  const int mext = xm ? dyv : adx, n2 = 2 * n;
+  for (int ps = 0; ps < 2; ++ps) {
+    const int t = ps == 0 ? t0 : t0 - Pm;
+    const int k0 = ps == 0 ? 0 : Pm - t0;
+    const int k1 = ps == 0 ? n - t0 : n;
+    if (k0 > k1) continue;
+    const int T2 = 2 * t * mext;
+    int q = T2 / n2, r = T2 - q * n2;
+    if (r < 0) {  // floor division
+      r += n2;
+      --q;
+    }
+    const bool lo_ok = q == mm || q == mm - Qm, hi_ok = q + 1 == mm || q + 1 == mm - Qm;
+    if (!lo_ok && !hi_ok) continue;
+    const int th = n2 - r;
+    int e = ps == 0 ? n : (n + 2 * k0 * mext) % n2;
+    for (int kk = k0; kk <= k1; ++kk) {
+      if (kk > k0) {
+        e += 2 * mext;
+        e -= e >= n2 ? n2 : 0;
+      }
+      if (e >= th ? hi_ok : lo_ok) hit(kk);
+    }
+  }
+}
+
+// Bits sh .. sh + 63 of three consecutive words.
+__device__ __forceinline__ uint64_t window64(const uint32_t (&x)[3], uint32_t sh) {
+  return ((uint64_t)__builtin_amdgcn_alignbit(x[2], x[1], sh) << 32) |
+         __builtin_amdgcn_alignbit(x[1], x[0], sh);
+}
+
 // Exact dL of interchange (a, b) for vector v, one entry per kept phase.  Invalid or same-phase
 // pairs change nothing.
 // ORDERED: the pair is known to be (phase-1 pixel, phase-0 pixel), as the annealer's draws are,
@@ -207,14 +264,22 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
     }
   }
   const int off = m.x, n = m.y, len = n + 1;
-  const uint32_t *RA = g.rec + (size_t)a * g.rstride;                // planes A of a
+  const uint32_t *RA = g.rec + (size_t)a * g.rstride;                 // planes A of a
   const uint32_t *RB = g.rec + (size_t)b * g.rstride + P::nph * g.Rw;  // planes B of b
+  const uint32_t *RBa = g.rec + (size_t)a * g.rstride + P::nph * g.Rw;  // planes B of a
+  // placements in P_a ∩ P_b keep their count (a leaves phase 1, b enters it); they exist only
+  // when b - a lies within the vector's box.  Such a placement holds b (phase 0), so for phase 1
+  // only the sum over P_b can count it, by [ones = n], which plane B of a records for it too;
+  // it holds a (phase 1), so for phase 0 only the sum over P_a can, by [ones = 1] of plane A
+  // of a.  Both are taken out of dL.
+  const int DX = bx - ax, DY = by - ay;
   if (len <= 64) {
     // a range of up to 64 bits spans three words (planes carry two padding words): every
-    // plane's words are requested before any is used, so the record reads overlap
+    // plane's words are requested before any is used, so the record reads overlap; the words
+    // of planes B of a that a placement in both sets needs are requested with them
     const int w = off >> 5;
     const uint32_t sh = (uint32_t)(off & 31);
-    uint32_t xa[P::nph][3], xb[P::nph][3];
+    uint32_t xa[P::nph][3], xb[P::nph][3], xc[P::nph][3];
 #pragma unroll
     for (int p = 0; p < P::nph; ++p)
 #pragma unroll
@@ -222,61 +287,46 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
         xa[p][i] = RA[(size_t)p * g.Rw + w + i];
         xb[p][i] = RB[(size_t)p * g.Rw + w + i];
       }
+    const bool near = n > 0 && within_small(DX, g.W, m.z < 0 ? -m.z : m.z) &&
+                      within_small(DY, g.H, m.w);
+#pragma unroll
+    for (int p = 0; p < P::nph; ++p)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) xc[p][i] = 0u;
+    if (near) {
+#pragma unroll
+      for (int p = 0; p < P::nph; ++p)
+        if (P::phase(p))
+#pragma unroll
+          for (int i = 0; i < 3; ++i) xc[p][i] = RBa[(size_t)p * g.Rw + w + i];
+    }
 #pragma unroll
     for (int p = 0; p < P::nph; ++p) {
       const int cA = popcount_window(xa[p], sh, len), cB = popcount_window(xb[p], sh, len);
       d[p] = P::phase(p) ? cB - cA : cA - cB;
     }
-  } else {
+    if (near) {
+      uint64_t both = 0;  // bit k: placement a - p_k lies in P_b too
+      both_placements(g, m, DX, DY, [&](int k) { both |= 1ull << k; });
 #pragma unroll
-    for (int p = 0; p < P::nph; ++p) {
-      const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
-      const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
-      d[p] = P::phase(p) ? cB - cA : cA - cB;
+      for (int p = 0; p < P::nph; ++p)
+        d[p] -= __popcll(both & window64(P::phase(p) ? xc[p] : xa[p], sh));
     }
+    return;
   }
-  // placements in P_a ∩ P_b: x = a - p_k with b - x = (b - a) + p_k = p_j on the path
-  const int DX = bx - ax, DY = by - ay;
-  if (n > 0 && within(DX, g.W, m.z < 0 ? -m.z : m.z) && within(DY, g.H, m.w)) {
-    const uint32_t *RBa = g.rec + (size_t)a * g.rstride + P::nph * g.Rw;  // planes B of a
-    // Along the major axis p_j - p_k has the index difference t = j - k, so t is fixed modulo
-    // the period by b - a: t = t0 for k <= n - t0 and t = t0 - P for k >= P - t0.  For those k
-    // the minor coordinates of k and k + t (kept as error terms, no division in the loop) must
-    // differ by the minor part of b - a modulo its period.
-    const int dxv = m.z, dyv = m.w;
-    const int adx = dxv < 0 ? -dxv : dxv;
-    const bool xm = adx >= dyv;
-    const int sx = dxv < 0 ? -1 : 1;
-    const int Pm = xm ? g.W : g.H, Qm = xm ? g.H : g.W;
-    int t0 = xm ? sx * DX : DY;  // in (-Pm, Pm)
-    t0 += t0 < 0 ? Pm : 0;
-    int mm = xm ? DY : sx * DX;  // in (-Qm, Qm)
-    mm += mm < 0 ? Qm : 0;
-    const int mext = xm ? dyv : adx;
-    for (int ps = 0; ps < 2; ++ps) {
-      const int t = ps == 0 ? t0 : t0 - Pm;
-      const int k0 = ps == 0 ? 0 : Pm - t0;
-      const int k1 = ps == 0 ? n - t0 : n;
-      if (k0 > k1) continue;
-      const int va = n + 2 * k0 * mext, vb = n + 2 * (k0 + t) * mext;
-      int fa = va / (2 * n), ea = va - 2 * n * fa;
-      int fb = vb / (2 * n), eb = vb - 2 * n * fb;
-      for (int kk = k0; kk <= k1; ++kk) {
-        if (kk > k0) {
-          ea += 2 * mext;
-          if (ea >= 2 * n) { ea -= 2 * n; ++fa; }
-          eb += 2 * mext;
-          if (eb >= 2 * n) { eb -= 2 * n; ++fb; }
-        }
-        const int diff = fb - fa;
-        if (diff != mm && diff != mm - Qm) continue;
 #pragma unroll
-        for (int s = 0; s < P::nph; ++s)
-          d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + kk)
-                              : plane_bit(RA + (size_t)s * g.Rw, off + kk);
-      }
-    }
+  for (int p = 0; p < P::nph; ++p) {
+    const int cA = popcount_range(RA + (size_t)p * g.Rw, off, len);
+    const int cB = popcount_range(RB + (size_t)p * g.Rw, off, len);
+    d[p] = P::phase(p) ? cB - cA : cA - cB;
   }
+  if (within_small(DX, g.W, m.z < 0 ? -m.z : m.z) && within_small(DY, g.H, m.w))
+    both_placements(g, m, DX, DY, [&](int k) {
+#pragma unroll
+      for (int s = 0; s < P::nph; ++s)
+        d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + k)
+                            : plane_bit(RA + (size_t)s * g.Rw, off + k);
+    });
 }
 
 // One round: block (vector block, candidate slot); the slots stride over the round's evaluation
@@ -295,7 +345,6 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
   using P = Planes<MASK>;
   __shared__ long long s_part[4];
   __shared__ int s_prev;
-  if (ctl->done) return;  // an earlier round accepted
   if (prev_round_accepted(S_acc, S0, cand, U, order, pi0, pC, Tp,
                           (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;
@@ -618,7 +667,7 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
 template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
-  __shared__ int s_ks0, s_first;
+  __shared__ int s_first;
   __shared__ int32_t path[4][64];
   // the wave's first vector and path pixel do not depend on the decision: load them first, at
   // clamped indices (no branch), so that they overlap the decision's reads
@@ -626,18 +675,19 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   const int v0 = wid0 >> 1;
   int4 m = g.meta[min(v0, g.nv - 1)];
   int32_t pk = g.pix[m.x + min(lane, m.y)];
-  if (threadIdx.x == 0) s_ks0 = f.ctl->ks;
-  __syncthreads();
-  const int ks0 = s_ks0;
+  // done, ks, a, b of an earlier round's decision in one load (nothing in this launch writes
+  // the control block: the upkeep is told not to)
+  const int4 c4 = *reinterpret_cast<const int4 *>(f.ctl);
+  const int ks0 = c4.y;
   const int ks = step_choice(f, ks0, &s_first);
   // counts += dL shared by all nupd + 1 workgroups (one term per thread at most sizes)
   step_counts(f, ks, (int)blockIdx.x, nupd + 1);
   if ((int)blockIdx.x == nupd) {
-    step_apply(f, ks, ks0 < 0 && ks >= 0, false);
+    step_apply(f, ks, false, false);
     return;
   }
   if (ks < 0) return;
-  const int2 ab = f.cand[ks];
+  const int2 ab = ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
   for (int wid = wid0; wid < 2 * g.nv; wid += 4 * nupd) {
     const int v = wid >> 1;
     if (wid != wid0) {
@@ -669,9 +719,26 @@ hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t s
   return hipGetLastError();
 }
 
+// One wave per (vector, side) pair when that many workgroups are resident at once; otherwise
+// 1024 workgroups whose waves stride over the pairs.  A grid beyond what the device holds queues
+// a second wave of workgroups, which repeats the launch's whole latency chain (decision, loads,
+// flips); and when the pairs need more than one pass anyway, 1024 workgroups measured faster
+// than the resident maximum (fewer workgroups to dispatch, each taking the decision).
+int rec_end_workgroups(const RecGeo &g, int cus) {
+  const int need = (2 * g.nv + 3) / 4;
+  int per_cu = 0;
+  hipError_t e = hipSuccess;
+#define LPF_OCC(M) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M>, 256, 0)
+  LPF_REC_MASK_SWITCH(g.mask, LPF_OCC)
+#undef LPF_OCC
+  // the step's upkeep workgroup runs beside the update workgroups
+  if (e == hipSuccess && need + 1 <= per_cu * cus) return need;
+  return std::min(need, 1024);
+}
+
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
-  // one wave per (vector, side), at most 1024 update workgroups (the waves then stride)
-  const int nupd = std::min((2 * g.nv + 3) / 4, 1024);
+  const int nupd = g.end_wgs > 0 ? g.end_wgs : std::min((2 * g.nv + 3) / 4, 1024);
 #define LPF_END(M) \
   hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)

@@ -302,7 +302,6 @@ k_s2_round(const uint64_t *__restrict__ bits, int W, int H, const int2 *__restri
            const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
-  if (ctl->done) return;  // an earlier round accepted
   if (prev_round_accepted(S_acc, nullptr, cand, U, order, pi0, pC, Tp,
                           (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;

@@ -27,6 +27,8 @@ __global__ void k_step_reset(StepCtl *__restrict__ ctl, int64_t *__restrict__ S_
   if (i == 0) {
     ctl->done = 0;
     ctl->ks = -1;
+    ctl->a = -1;
+    ctl->b = -1;
     ctl->S = 0;
   }
 }
@@ -43,7 +45,6 @@ k_round_delta(const uint32_t *__restrict__ Eg, DeltaGeo geo, const uint64_t *__r
               const double *__restrict__ U, const double *__restrict__ Tp, int pi0, int pC) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_prev;
-  if (ctl->done) return;  // an earlier round accepted
   if (prev_round_accepted(S_acc, nullptr, cand, U, order, pi0, pC, Tp,
                           (double)N * (double)N * (double)Nt, ctl, &s_prev))
     return;
@@ -121,7 +122,10 @@ k_round_decide(const int64_t *__restrict__ S_acc, const int2 *__restrict__ cand,
   }
   if (threadIdx.x == 0 && s_first != INT_MAX) {
     const int ks = order ? order[k0 + s_first] : k0 + s_first;
+    const int2 ab = cand[ks];
     ctl->ks = ks;
+    ctl->a = ab.x;
+    ctl->b = ab.y;
     ctl->S = S_acc[ks];
     ctl->done = 1;
   }

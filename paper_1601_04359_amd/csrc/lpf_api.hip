@@ -910,6 +910,9 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     g.oplane = (int64_t)((a->W + 7) / 8) * ((a->H + 7) / 8) * 64;
     g.mask = a->mask;
     g.sample = a->sample;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, a->ctx->dev);
+    g.end_wgs = rec_end_workgroups(g, cus);
     const int64_t N = (int64_t)a->W * a->H;
     if ((e = a->rmeta.ensure(sizeof(int4) * meta.size())) != hipSuccess ||
         (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||

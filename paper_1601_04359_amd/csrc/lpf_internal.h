@@ -187,9 +187,10 @@ struct DiagLaunch {
 };
 
 // Per-step control block of the round-wise evaluation (k_step.hip).
-struct StepCtl {
+struct alignas(16) StepCtl {
   int32_t done;      // a round has accepted
   int32_t ks;        // accepted candidate, -1 when none
+  int32_t a, b;      // its interchange (cand[ks]), set with ks, so that one load gives all three
   long long S;       // its integer energy sum
 };
 
@@ -222,6 +223,7 @@ struct RecGeo {
   // outside it keeps ones + 128 (n <= 126), which meets no plane condition before or after any
   // interchange, so it never counts.
   const uint64_t *sample;
+  int end_wgs;          // update workgroups of the step's end (rec_end_workgroups)
 };
 
 struct AnnealDev;
@@ -369,6 +371,8 @@ hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 // decision and upkeep, and the accepted interchange applied to ones and records) in one launch.
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream);
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream);
+// Update workgroups of the records method's step end on a device of `cus` compute units.
+int rec_end_workgroups(const RecGeo &g, int cus);
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
                             hipStream_t stream);
 // Round 0 (r.C <= 64 candidates) together with the step's draws L.draw (L.fuse_draw).

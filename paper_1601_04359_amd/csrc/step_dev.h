@@ -24,30 +24,37 @@ __device__ __forceinline__ int64_t round_sum(const int64_t *__restrict__ S_acc,
 
 // First accepted evaluation position among i0 .. i0 + C - 1 (C <= 64), tested by the calling
 // wave, one candidate per lane (accept iff de <= 0 or U < exp(-de / T)); every lane gets the
-// answer, -1 when none.
+// answer, -1 when none, and in ab the accepted candidate's pixels.
 __device__ __forceinline__ int wave_first_accepted(const int64_t *__restrict__ S_acc,
                                                    const int64_t *__restrict__ S0,
                                                    const int2 *__restrict__ cand,
                                                    const double *__restrict__ U,
                                                    const int32_t *__restrict__ order, int i0, int C,
-                                                   double T, double scale) {
+                                                   const double *__restrict__ Tp, double scale,
+                                                   int2 &ab) {
   const int lane = threadIdx.x & 63;
   bool acc = false;
+  int2 c = make_int2(-1, -1);
   if (lane < C) {
     const int k = order ? order[i0 + lane] : i0 + lane;
-    if (cand[k].x >= 0) {
+    c = cand[k];
+    if (c.x >= 0) {
       const double de = (double)round_sum(S_acc, S0, lane, k) / scale;
-      acc = de <= 0.0 || U[k] < exp(-de / T);
+      acc = de <= 0.0 || U[k] < exp(-de / *Tp);
     }
   }
   const unsigned long long m = __ballot(acc);
-  return m ? i0 + (__ffsll(m) - 1) : -1;
+  if (!m) return -1;
+  const int f = __ffsll(m) - 1;
+  ab = make_int2(__shfl(c.x, f), __shfl(c.y, f));
+  return i0 + f;
 }
 
-// Start of a round that also decides the previous round (pC > 0 candidates at positions pi0..):
-// every workgroup evaluates that decision; when it accepted, workgroup (0, 0) records it (and
-// copies its energy sum from S0 to S_acc when given) and all workgroups return true (skip the
-// round).
+// Start of a round: true (skip the round) when an earlier round accepted (ctl->done) or when the
+// previous round (pC > 0 candidates at positions pi0.., decided here by every workgroup)
+// accepted; then workgroup (0, 0) records that decision (and copies its energy sum from S0 to
+// S_acc when given).  The control block and the previous round's operands are loaded together,
+// so the test costs one memory latency.
 __device__ __forceinline__ bool prev_round_accepted(int64_t *__restrict__ S_acc,
                                                    const int64_t *__restrict__ S0,
                                                    const int2 *__restrict__ cand,
@@ -56,19 +63,23 @@ __device__ __forceinline__ bool prev_round_accepted(int64_t *__restrict__ S_acc,
                                                    int pC, const double *__restrict__ Tp,
                                                    double scale, StepCtl *__restrict__ ctl,
                                                    int *s_prev) {
-  if (pC <= 0) return false;
+  if (pC <= 0) return ctl->done != 0;
+  int2 ab = make_int2(-1, -1);
   if (threadIdx.x < 64) {
-    const int f = wave_first_accepted(S_acc, S0, cand, U, order, pi0, pC, *Tp, scale);
-    if (threadIdx.x == 0) *s_prev = f;
+    const int done = ctl->done;
+    const int f = wave_first_accepted(S_acc, S0, cand, U, order, pi0, pC, Tp, scale, ab);
+    if (threadIdx.x == 0) *s_prev = done ? -2 : f;
   }
   __syncthreads();
   const int f = *s_prev;
-  if (f < 0) return false;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+  if (f == -1) return false;
+  if (f >= 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     const int ks = order ? order[f] : f;
     const int64_t S = round_sum(S_acc, S0, f - pi0, ks);
     if (S0) S_acc[ks] = S;
     ctl->ks = ks;
+    ctl->a = ab.x;
+    ctl->b = ab.y;
     ctl->S = S;
     ctl->done = 1;
   }
@@ -125,15 +136,17 @@ __device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool deci
   r.step = st->step;
   r.pad = 0;
   if (ks >= 0) {
+    const int a = f.cand[ks].x, b = f.cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
     if (decided) {
       f.ctl->ks = ks;
+      f.ctl->a = a;
+      f.ctl->b = b;
       f.ctl->S = f.S_acc[ks];
       f.ctl->done = 1;
     }
     const double de = (double)f.S_acc[ks] / ((double)f.N * (double)f.N * (double)f.Nt);
     const double e = *f.e_io + de;
     *f.e_io = e;
-    const int a = f.cand[ks].x, b = f.cand[ks].y;  // a: phase 1 -> 0, b: phase 0 -> 1
     const int W = f.W, wpr = (W + 63) >> 6;
     const int ay = a / W, ax = a - ay * W, by = b / W, bx = b - by * W;
     f.bits[(size_t)ay * wpr + (ax >> 6)] &= ~(1ull << (ax & 63));
