@@ -539,15 +539,17 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
 // vector v on one side (side 0: the placements through a, 1: through b), by one wave.  Lane k
 // takes placement x_k = s - p_k (s = a or b), updates ones(v, x_k) and finds which plane bits of
 // x_k change; those bits live in the records of the pixels x_k + p_j at bit off + j, j = 0..n.
-// For n + 1 <= 64 the flips are merged before they are issued: with j = k + d, the record pixel
-// is s + (p_{k+d} - p_k), and for a fixed d that difference takes at most two values along a
-// digitised straight line, so lane d gathers, per value, the changed k into one mask and flips
-// mask << (off + d) with at most three atomic XORs per plane, instead of one per (k, j).  (A
-// third value, not expected, is flipped bit by bit.)  Longer paths flip bit by bit.
+// For n + 1 <= 64 the flips are merged before they are issued: with j = k + d the record pixel
+// is s + (p_{k+d} - p_k), whose major part is d and whose minor part is q_d or q_d + 1: with the
+// minor extent e, 2 d e = q_d 2n + rho_d (0 <= rho_d < 2n) and the error term
+// r_k = (2 k e + n) mod 2n of point k, it is q_d + 1 exactly when r_k >= 2n - rho_d.  So lane d
+// splits the changed k into those two classes (one compare per changed k against the error term
+// that lane k holds) and flips each class's mask << (off + d) with at most three atomic XORs per
+// plane, instead of one per (k, j).  Longer paths flip bit by bit.
 // m = meta[v]; pk = p_lane (lane <= n, n + 1 <= 64), loaded by the caller ahead of the decision.
 template <unsigned MASK>
 __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, int v, int side,
-                                                int4 m, int32_t pk_lane, int32_t *path) {
+                                                int4 m, int32_t pk_lane) {
   using P = Planes<MASK>;
   const int lane = threadIdx.x & 63;
   const int off = m.x, n = m.y;
@@ -590,11 +592,7 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
     }
     return;
   }
-  unsigned chg = 0;
-  if (lane <= n) {
-    path[lane] = pk_lane;
-    chg = update(lane, pk_lane);
-  }
+  const unsigned chg = lane <= n ? update(lane, pk_lane) : 0u;
   uint64_t M[P::n], any = 0;
 #pragma unroll
   for (int pl = 0; pl < P::n; ++pl) {
@@ -602,51 +600,59 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
     any |= M[pl];
   }
   if (!any) return;
-  __builtin_amdgcn_wave_barrier();  // path[] written by this wave's lanes, read below
-  for (int dd = lane; dd <= 2 * n; dd += 64) {
+  const int adx = m.z < 0 ? -m.z : m.z;
+  const bool xm = adx >= m.w;
+  const int sgn = m.z < 0 ? -1 : 1, mext = xm ? m.w : adx, n2 = 2 * n;
+  const int ek = n > 0 && lane <= n ? (2 * lane * mext + n) % n2 : 0;  // error term of point lane
+  // this lane's offsets d = dd - n, dd = lane and lane + 64 (when dd <= 2n): q_d and the
+  // threshold 2n - rho_d of class q_d + 1 (none for d = 0)
+  int q[2], th[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int d = lane + 64 * h - n;
+    q[h] = 0;
+    th[h] = INT_MAX;
+    if (d != 0 && d <= n) {  // then n > 0
+      const int T2 = 2 * d * mext;
+      int qq = T2 / n2, rho = T2 - qq * n2;
+      if (rho < 0) {  // floor division
+        rho += n2;
+        --qq;
+      }
+      q[h] = qq;
+      th[h] = n2 - rho;
+    }
+  }
+  uint64_t c1[2] = {0ull, 0ull};  // changed k of class q_d + 1
+  for (uint64_t t = any; t; t &= t - 1) {
+    const int k = __ffsll((unsigned long long)t) - 1;  // uniform
+    const int e = __builtin_amdgcn_readlane(ek, k);
+    c1[0] |= (uint64_t)(e >= th[0]) << k;
+    c1[1] |= (uint64_t)(e >= th[1]) << k;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int dd = lane + 64 * h;
+    if (dd > 2 * n) continue;
     const int d = dd - n;
     const int k0 = d < 0 ? -d : 0, k1 = d > 0 ? n - d : n;
     const uint64_t range = ((~0ull) >> (63 - k1)) & ((~0ull) << k0);
-    uint64_t todo = any & range;
-    int ncls = 0;
-    int cdx[2] = {0, 0}, cdy[2] = {0, 0};
-    uint64_t cm[2][P::n];
+    const int base = off + d, sh = base & 31;
 #pragma unroll
-    for (int pl = 0; pl < P::n; ++pl) cm[0][pl] = cm[1][pl] = 0ull;
-    while (todo) {
-      const int k = __ffsll((unsigned long long)todo) - 1;
-      todo &= todo - 1;
-      const int32_t p0 = path[k], p1 = path[k + d];
-      const int ddx = pix_dx(p1) - pix_dx(p0), ddy = pix_dy(p1) - pix_dy(p0);
-      int c = -1;
-      for (int q = 0; q < ncls; ++q)
-        if (cdx[q] == ddx && cdy[q] == ddy) c = q;
-      if (c < 0 && ncls < 2) {
-        c = ncls++;
-        cdx[c] = ddx;
-        cdy[c] = ddy;
-      }
-      if (c < 0) {  // a third difference: flip this placement's bits one by one
-        unsigned ck = 0;
-#pragma unroll
-        for (int pl = 0; pl < P::n; ++pl) ck |= (unsigned)((M[pl] >> k) & 1ull) << pl;
-        flip_bit(wrapi(sx + ddx % g.W, g.W), wrapi(sy + ddy % g.H, g.H), ck, off + k + d);
-        continue;
-      }
-#pragma unroll
-      for (int pl = 0; pl < P::n; ++pl) cm[c][pl] |= M[pl] & (1ull << k);
-    }
-    const int base = off + d;
-    for (int c = 0; c < ncls; ++c) {
-      const int qx = wrapi(sx + cdx[c] % g.W, g.W), qy = wrapi(sy + cdy[c] % g.H, g.H);
+    for (int c = 0; c < 2; ++c) {
+      const uint64_t cls = range & (c ? c1[h] : ~c1[h]);
+      if (!(cls & any)) continue;
+      const int mn = q[h] + c;
+      const int qx = wrapi(sx + (xm ? sgn * d : sgn * mn), g.W);
+      const int qy = wrapi(sy + (xm ? mn : d), g.H);
       uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride + (base >> 5);
 #pragma unroll
       for (int pl = 0; pl < P::n; ++pl) {
-        if (!cm[c][pl]) continue;
-        const int sh = base & 31;
-        const uint32_t w0 = (uint32_t)(cm[c][pl] << sh);
-        const uint32_t w1 = (uint32_t)((cm[c][pl] << sh) >> 32);
-        const uint32_t w2 = sh ? (uint32_t)(cm[c][pl] >> (64 - sh)) : 0u;
+        const uint64_t cm = M[pl] & cls;
+        if (!cm) continue;
+        const uint32_t w0 = (uint32_t)(cm << sh);
+        const uint32_t w1 = (uint32_t)((cm << sh) >> 32);
+        const uint32_t w2 = sh ? (uint32_t)(cm >> (64 - sh)) : 0u;
         uint32_t *Rp = R + (size_t)pl * g.Rw;
         if (w0) atomicXor(Rp, w0);
         if (w1) atomicXor(Rp + 1, w1);
@@ -668,7 +674,6 @@ template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __shared__ int s_first;
-  __shared__ int32_t path[4][64];
   // the wave's first vector and path pixel do not depend on the decision: load them first, at
   // clamped indices (no branch), so that they overlap the decision's reads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wid0 = (int)blockIdx.x * 4 + wave;
@@ -691,11 +696,10 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   for (int wid = wid0; wid < 2 * g.nv; wid += 4 * nupd) {
     const int v = wid >> 1;
     if (wid != wid0) {
-      __builtin_amdgcn_wave_barrier();  // path[] of the previous pair is no longer read
       m = g.meta[v];
       pk = g.pix[m.x + min(lane, m.y)];
     }
-    rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk, path[wave]);
+    rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk);
   }
 }
 
