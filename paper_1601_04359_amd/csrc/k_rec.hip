@@ -92,13 +92,6 @@ __device__ __forceinline__ bool on_path(int rx, int ry, int dx, int dy, int n, i
   return rxm == gx;
 }
 
-// Is some residue of d modulo M within [-r, r]?
-__device__ __forceinline__ bool within(int d, int M, int r) {
-  int m = d % M;
-  m += m < 0 ? M : 0;
-  return m <= r || M - m <= r;
-}
-
 // The plane conditions: side 0 (A) / 1 (B), phase 0 / 1.
 __device__ __forceinline__ bool plane_cond(int side, int phase, int o, int n) {
   return side == 0 ? (phase ? o == n + 1 : o == 1) : (phase ? o == n : o == 0);
@@ -183,22 +176,27 @@ k_rec_build(RecGeo g) {
   }
 }
 
-// within() for |d| < M, without a division.
+// Is d (|d| < M) within [-r, r] modulo M?
 __device__ __forceinline__ bool within_small(int d, int M, int r) {
   const int m = d < 0 ? d + M : d;
   return m <= r || M - m <= r;
 }
 
-// Calls hit(k) for every path index k of vector v (m = meta[v], n = m.y > 0) whose placement
-// x = a - p_k also lies in P_b, i.e. b - a = p_j - p_k for some j; (DX, DY) = b - a.  Along the
-// major axis p_j - p_k has the index difference t = j - k, so t is fixed modulo the period by
-// b - a: t = t0 for k <= n - t0 and t = t0 - P for k >= P - t0.  The minor coordinate of point k
-// is floor((2 k e + n) / 2n) (e the minor extent), so with the error term r_k = (2 k e + n) mod 2n
-// and 2 t e = q 2n + r (0 <= r < 2n) the minor difference of points k + t and k is q when
-// r_k < 2n - r and q + 1 otherwise: only when one of the two equals the minor part of b - a
-// (modulo its period) are the error terms walked, with no division in the loop.
-template <class F>
-__device__ __forceinline__ void both_placements(const RecGeo &g, int4 m, int DX, int DY, F &&hit) {
+// Placements of vector v (m = meta[v], n = m.y > 0) through s whose other end s + (DX, DY) is on
+// their path as well: x = s - p_k with x + p_j = s + (DX, DY) for some j.  Along the major axis
+// p_j - p_k has the index difference t = j - k, so t is fixed modulo the period by (DX, DY):
+// t = t0 for k <= n - t0 and t = t0 - P for k >= P - t0 (range 0 and 1).  The minor coordinate
+// of point k is floor((2 k e + n) / 2n) (e the minor extent), so with the error term
+// r_k = (2 k e + n) mod 2n and 2 t e = q 2n + rho (0 <= rho < 2n) the minor difference of
+// points k + t and k is q when r_k < 2n - rho and q + 1 otherwise; a range holds placements
+// only when one of the two equals the minor part of (DX, DY) modulo its period: those k with
+// r_k < th (lo) or r_k >= th (hi).
+struct BothRange {
+  int k0, k1, th;
+  bool lo, hi;
+};
+__device__ __forceinline__ void both_ranges(const RecGeo &g, int4 m, int DX, int DY,
+                                            BothRange (&r)[2], int &mext) {
   const int n = m.y, dxv = m.z, dyv = m.w;
   const int adx = dxv < 0 ? -dxv : dxv;
   const bool xm = adx >= dyv;
@@ -208,28 +206,60 @@ __device__ __forceinline__ void both_placements(const RecGeo &g, int4 m, int DX,
   t0 += t0 < 0 ? Pm : 0;
   int mm = xm ? DY : sx * DX;  // in (-Qm, Qm)
   mm += mm < 0 ? Qm : 0;
-  const int mext = xm ? dyv : adx, n2 = 2 * n;
+  mext = xm ? dyv : adx;
+  const int n2 = 2 * n;
+#pragma unroll
   for (int ps = 0; ps < 2; ++ps) {
     const int t = ps == 0 ? t0 : t0 - Pm;
-    const int k0 = ps == 0 ? 0 : Pm - t0;
-    const int k1 = ps == 0 ? n - t0 : n;
-    if (k0 > k1) continue;
+    r[ps].k0 = ps == 0 ? 0 : Pm - t0;
+    r[ps].k1 = ps == 0 ? n - t0 : n;
     const int T2 = 2 * t * mext;
-    int q = T2 / n2, r = T2 - q * n2;
-    if (r < 0) {  // floor division
-      r += n2;
+    int q = T2 / n2, rho = T2 - q * n2;
+    if (rho < 0) {  // floor division
+      rho += n2;
       --q;
     }
-    const bool lo_ok = q == mm || q == mm - Qm, hi_ok = q + 1 == mm || q + 1 == mm - Qm;
-    if (!lo_ok && !hi_ok) continue;
-    const int th = n2 - r;
-    int e = ps == 0 ? n : (n + 2 * k0 * mext) % n2;
-    for (int kk = k0; kk <= k1; ++kk) {
-      if (kk > k0) {
+    const bool any = r[ps].k0 <= r[ps].k1;
+    r[ps].lo = any && (q == mm || q == mm - Qm);
+    r[ps].hi = any && (q + 1 == mm || q + 1 == mm - Qm);
+    r[ps].th = n2 - rho;
+  }
+}
+
+// Bit k set for each such placement, for n + 1 <= 64, from the error-term masks (one load per
+// range that can hold any).
+__device__ __forceinline__ uint64_t both_mask(const RecGeo &g, int4 m, int v, int DX, int DY) {
+  BothRange r[2];
+  int mext;
+  both_ranges(g, m, DX, DY, r, mext);
+  const uint64_t *E = g.emask + (2 * (int64_t)m.x - v);
+  uint64_t both = 0;
+#pragma unroll
+  for (int ps = 0; ps < 2; ++ps) {
+    if (!r[ps].lo && !r[ps].hi) continue;
+    const uint64_t ge = E[r[ps].th];
+    const uint64_t range = ((~0ull) >> (63 - r[ps].k1)) & ((~0ull) << r[ps].k0);
+    both |= range & ((r[ps].hi ? ge : 0ull) | (r[ps].lo ? ~ge : 0ull));
+  }
+  return both;
+}
+
+// hit(k) for each such placement, walking the error terms (paths of any length).
+template <class F>
+__device__ __forceinline__ void both_walk(const RecGeo &g, int4 m, int DX, int DY, F &&hit) {
+  BothRange r[2];
+  int mext;
+  both_ranges(g, m, DX, DY, r, mext);
+  const int n = m.y, n2 = 2 * n;
+  for (int ps = 0; ps < 2; ++ps) {
+    if (!r[ps].lo && !r[ps].hi) continue;
+    int e = (n + 2 * r[ps].k0 * mext) % n2;
+    for (int kk = r[ps].k0; kk <= r[ps].k1; ++kk) {
+      if (kk > r[ps].k0) {
         e += 2 * mext;
         e -= e >= n2 ? n2 : 0;
       }
-      if (e >= th ? hi_ok : lo_ok) hit(kk);
+      if (e >= r[ps].th ? r[ps].hi : r[ps].lo) hit(kk);
     }
   }
 }
@@ -306,8 +336,7 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
       d[p] = P::phase(p) ? cB - cA : cA - cB;
     }
     if (near) {
-      uint64_t both = 0;  // bit k: placement a - p_k lies in P_b too
-      both_placements(g, m, DX, DY, [&](int k) { both |= 1ull << k; });
+      const uint64_t both = both_mask(g, m, v, DX, DY);  // bit k: a - p_k lies in P_b too
 #pragma unroll
       for (int p = 0; p < P::nph; ++p)
         d[p] -= __popcll(both & window64(P::phase(p) ? xc[p] : xa[p], sh));
@@ -321,7 +350,7 @@ __device__ __forceinline__ void rec_delta(const RecGeo &g, const uint64_t *__res
     d[p] = P::phase(p) ? cB - cA : cA - cB;
   }
   if (within_small(DX, g.W, m.z < 0 ? -m.z : m.z) && within_small(DY, g.H, m.w))
-    both_placements(g, m, DX, DY, [&](int k) {
+    both_walk(g, m, DX, DY, [&](int k) {
 #pragma unroll
       for (int s = 0; s < P::nph; ++s)
         d[s] -= P::phase(s) ? plane_bit(RBa + (size_t)s * g.Rw, off + k)
@@ -376,8 +405,8 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
       }
     }
     // block sum (int64: exact), one accumulation per block
-    for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+    S = wave_sum63_i64(S);
+    if ((threadIdx.x & 63) == 63) s_part[threadIdx.x >> 6] = S;
     __syncthreads();
     if (threadIdx.x == 0) {
       long long tot = 0;
@@ -434,8 +463,8 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
       dl[(int64_t)((size_t)q * g.nv + v) * dl_t + (int64_t)kr * dl_k] = (int16_t)d[q];
     }
   }
-  for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
-  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+  S = wave_sum63_i64(S);
+  if ((threadIdx.x & 63) == 63) s_part[threadIdx.x >> 6] = S;
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot = 0;
@@ -525,8 +554,8 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
       dl[(int64_t)((size_t)q * g.nv + v) * dl_t + (int64_t)k * dl_k] = (int16_t)d[q];
     }
   }
-  for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
-  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = S;
+  S = wave_sum63_i64(S);
+  if ((threadIdx.x & 63) == 63) s_part[threadIdx.x >> 6] = S;
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot = 0;
@@ -557,10 +586,14 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
   const int sx = side ? bx : ax, sy = side ? by : ay;
   // placements in both P_a and P_b keep their count (possible only when b - a is within reach)
   const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
-  const bool near = within(ox, g.W, m.z < 0 ? -m.z : m.z) && within(oy, g.H, m.w);
+  const bool near = within_small(ox, g.W, m.z < 0 ? -m.z : m.z) && within_small(oy, g.H, m.w);
+  // paths of fewer than 64 pixels: those placements as a mask over k
+  const uint64_t keep = near && n > 0 && n + 1 <= 64 ? both_mask(g, m, v, ox, oy) : 0ull;
   auto update = [&](int k, int32_t pk) -> unsigned {
     const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
-    if (near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H)) return 0u;
+    if (n + 1 <= 64 ? ((keep >> k) & 1ull) != 0
+                    : near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H))
+      return 0u;
     uint8_t *op = g.ones + (size_t)v * g.oplane + ones_at(g, x, y);
     const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
     *op = (uint8_t)o1;

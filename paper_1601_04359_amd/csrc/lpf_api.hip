@@ -227,7 +227,7 @@ struct lpf_anneal_s {
   int rec_choice = -1;  // resolved method (1 records, 0 recount), -1 until first needed
   bool rec_ready = false, rec_valid = false;
   RecGeo rg{};
-  DevBuf rmeta, rpix, rvbit, rec, ones;
+  DevBuf rmeta, rpix, rvbit, remask, rec, ones;
   // learned proposals: a network scoring the current cell, or a caller's score field
   lpf_cnn net = nullptr;
   const float *scores_ext = nullptr;
@@ -899,6 +899,18 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
         vbit.push_back((int32_t)((i << 8) | n));
       }
     }
+    // error-term masks of the paths of fewer than 64 pixels (RecGeo::emask): per threshold t
+    // from 2n down to 0, the indices whose error term is at least t
+    std::vector<uint64_t> emask(2 * pix.size() - (size_t)nv, 0ull);
+    for (int64_t i = 0; i < nv; ++i) {
+      const int off = meta[i].x, n = meta[i].y, adx = std::abs(meta[i].z), dy = meta[i].w;
+      if (n == 0 || n + 1 > 64) continue;
+      const int ext = adx >= dy ? dy : adx, n2 = 2 * n;
+      std::vector<uint64_t> eq((size_t)n2, 0ull);
+      for (int k = 0; k <= n; ++k) eq[(size_t)((2LL * k * ext + n) % n2)] |= 1ull << k;
+      const size_t b0 = (size_t)(2 * (int64_t)off - i);
+      for (int t = n2 - 1; t >= 0; --t) emask[b0 + t] = emask[b0 + t + 1] | eq[(size_t)t];
+    }
     RecGeo g{};
     g.nv = (int)nv;
     g.Mc = (int)pix.size();
@@ -917,17 +929,20 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     if ((e = a->rmeta.ensure(sizeof(int4) * meta.size())) != hipSuccess ||
         (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||
         (e = a->rvbit.ensure(sizeof(int32_t) * vbit.size())) != hipSuccess ||
+        (e = a->remask.ensure(sizeof(uint64_t) * emask.size())) != hipSuccess ||
         (e = a->rec.ensure(sizeof(uint32_t) * (size_t)(N * g.rstride))) != hipSuccess ||
         (e = a->ones.ensure((size_t)(nv * g.oplane))) != hipSuccess)
       return hip_fail(e, "anneal: records allocation");
     if ((e = hipMemcpyAsync(a->rmeta.p, meta.data(), sizeof(int4) * meta.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(a->rpix.p, pix.data(), sizeof(int32_t) * pix.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(a->rvbit.p, vbit.data(), sizeof(int32_t) * vbit.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(a->remask.p, emask.data(), sizeof(uint64_t) * emask.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return hip_fail(e, "anneal: records tables");
     g.meta = (const int4 *)a->rmeta.p;
     g.pix = (const int32_t *)a->rpix.p;
     g.vbit = (const int32_t *)a->rvbit.p;
+    g.emask = (const uint64_t *)a->remask.p;
     g.rec = (uint32_t *)a->rec.p;
     g.ones = (uint8_t *)a->ones.p;
     a->rg = g;
@@ -1937,6 +1952,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->ksel.release();
     a->rmeta.release();
     a->rpix.release();
+    a->remask.release();
     a->rvbit.release();
     a->rec.release();
     a->ones.release();

@@ -224,6 +224,9 @@ struct RecGeo {
   // interchange, so it never counts.
   const uint64_t *sample;
   int end_wgs;          // update workgroups of the step's end (rec_end_workgroups)
+  // per vector v with 0 < n < 64, at 2 off(v) - v + t (t = 0 .. 2n): the path indices k whose
+  // minor error term (2 k e + n) mod 2n is at least t (e the minor extent), bit k
+  const uint64_t *emask;
 };
 
 struct AnnealDev;

@@ -11,6 +11,28 @@
 
 namespace lpf {
 
+// v plus the value of the lane that DPP control CTRL selects (0 where ROW_MASK leaves a row out),
+// on both 32-bit halves with the carry.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int64_t dpp_add64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+  return (int64_t)(u + (((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the wave of a 64-bit value, valid in lane 63: DPP within quads, half rows and rows,
+// then row broadcasts 15 and 31.  Every lane must be active.
+__device__ __forceinline__ int64_t wave_sum63_i64(int64_t v) {
+  v = dpp_add64<0xB1, 0xF>(v);   // quad_perm 1,0,3,2
+  v = dpp_add64<0x4E, 0xF>(v);   // quad_perm 2,3,0,1
+  v = dpp_add64<0x141, 0xF>(v);  // row_half_mirror
+  v = dpp_add64<0x140, 0xF>(v);  // row_mirror
+  v = dpp_add64<0x142, 0xA>(v);  // row_bcast:15
+  v = dpp_add64<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
+
 __device__ __forceinline__ void add_acc(int64_t *p, int64_t v) {
   if (v != 0) atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
