@@ -568,64 +568,55 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
 // vector v on one side (side 0: the placements through a, 1: through b), by one wave.  Lane k
 // takes placement x_k = s - p_k (s = a or b), updates ones(v, x_k) and finds which plane bits of
 // x_k change; those bits live in the records of the pixels x_k + p_j at bit off + j, j = 0..n.
-// For n + 1 <= 64 the flips are merged before they are issued: with j = k + d the record pixel
-// is s + (p_{k+d} - p_k), whose major part is d and whose minor part is q_d or q_d + 1: with the
-// minor extent e, 2 d e = q_d 2n + rho_d (0 <= rho_d < 2n) and the error term
+// Placements in both P_a and P_b keep their count and are left alone.
+//
+// For n + 1 <= 64 (upd_load, then upd_apply, so that a wave can issue the loads of several
+// pairs before it applies any) the flips are merged before they are issued: with j = k + d the
+// record pixel is s + (p_{k+d} - p_k), whose major part is d and whose minor part is q_d or
+// q_d + 1: with the minor extent e, 2 d e = q_d 2n + rho_d (0 <= rho_d < 2n) and the error term
 // r_k = (2 k e + n) mod 2n of point k, it is q_d + 1 exactly when r_k >= 2n - rho_d.  So lane d
 // splits the changed k into those two classes (one compare per changed k against the error term
 // that lane k holds) and flips each class's mask << (off + d) with at most three atomic XORs per
-// plane, instead of one per (k, j).  Longer paths flip bit by bit.
-// m = meta[v]; pk = p_lane (lane <= n, n + 1 <= 64), loaded by the caller ahead of the decision.
+// plane, instead of one per (k, j).  Longer paths flip bit by bit (upd_long).
+struct UpdPair {
+  int v, side;
+  int4 m;         // meta[v]
+  int32_t pk;     // p_lane (lane <= n)
+  uint8_t *op;    // ones byte of the lane's placement
+  int o0;         // its value before the interchange
+  uint64_t keep;  // placements in both P_a and P_b (bit k)
+};
+
 template <unsigned MASK>
-__device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, int v, int side,
-                                                int4 m, int32_t pk_lane) {
+__device__ __forceinline__ void upd_load(const RecGeo &g, int a, int b, UpdPair &u) {
+  const int lane = threadIdx.x & 63;
+  const int n = u.m.y;
+  const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
+  const int sx = u.side ? bx : ax, sy = u.side ? by : ay;
+  const int ox = u.side ? ax - bx : bx - ax, oy = u.side ? ay - by : by - ay;
+  const bool near = within_small(ox, g.W, u.m.z < 0 ? -u.m.z : u.m.z) && within_small(oy, g.H, u.m.w);
+  u.keep = near && n > 0 ? both_mask(g, u.m, u.v, ox, oy) : 0ull;
+  const int x = wrapi(sx - pix_dx(u.pk), g.W), y = wrapi(sy - pix_dy(u.pk), g.H);
+  u.op = g.ones + (size_t)u.v * g.oplane + ones_at(g, x, y);
+  u.o0 = lane <= n ? (int)*u.op : 0;
+}
+
+template <unsigned MASK>
+__device__ __forceinline__ void upd_apply(const RecGeo &g, int a, int b, const UpdPair &u) {
   using P = Planes<MASK>;
   const int lane = threadIdx.x & 63;
-  const int off = m.x, n = m.y;
+  const int off = u.m.x, n = u.m.y;
   const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
-  const int sx = side ? bx : ax, sy = side ? by : ay;
-  // placements in both P_a and P_b keep their count (possible only when b - a is within reach)
-  const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
-  const bool near = within_small(ox, g.W, m.z < 0 ? -m.z : m.z) && within_small(oy, g.H, m.w);
-  // paths of fewer than 64 pixels: those placements as a mask over k
-  const uint64_t keep = near && n > 0 && n + 1 <= 64 ? both_mask(g, m, v, ox, oy) : 0ull;
-  auto update = [&](int k, int32_t pk) -> unsigned {
-    const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
-    if (n + 1 <= 64 ? ((keep >> k) & 1ull) != 0
-                    : near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H))
-      return 0u;
-    uint8_t *op = g.ones + (size_t)v * g.oplane + ones_at(g, x, y);
-    const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
-    *op = (uint8_t)o1;
-    unsigned chg = 0;
+  const int sx = u.side ? bx : ax, sy = u.side ? by : ay;
+  unsigned chg = 0;
+  if (lane <= n && !((u.keep >> lane) & 1ull)) {
+    const int o0 = u.o0, o1 = u.side ? o0 + 1 : o0 - 1;
+    *u.op = (uint8_t)o1;
 #pragma unroll
     for (int pl = 0; pl < P::n; ++pl)
       if (plane_cond(P::side(pl), P::phase(pl), o0, n) != plane_cond(P::side(pl), P::phase(pl), o1, n))
         chg |= 1u << pl;
-    return chg;
-  };
-  auto flip_bit = [&](int qx, int qy, unsigned chg, int bit) {
-    uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
-#pragma unroll
-    for (int pl = 0; pl < P::n; ++pl)
-      if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (bit >> 5), 1u << (bit & 31));
-  };
-  if (n + 1 > 64) {
-    for (int kc = 0; kc <= n; kc += 64) {
-      const int k = kc + lane;
-      if (k > n) continue;
-      const int32_t pk = g.pix[off + k];
-      const unsigned chg = update(k, pk);
-      if (!chg) continue;
-      const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
-      for (int j = 0; j <= n; ++j) {
-        const int32_t pj = g.pix[off + j];
-        flip_bit(wrapi(x + pix_dx(pj), g.W), wrapi(y + pix_dy(pj), g.H), chg, off + j);
-      }
-    }
-    return;
   }
-  const unsigned chg = lane <= n ? update(lane, pk_lane) : 0u;
   uint64_t M[P::n], any = 0;
 #pragma unroll
   for (int pl = 0; pl < P::n; ++pl) {
@@ -633,9 +624,9 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
     any |= M[pl];
   }
   if (!any) return;
-  const int adx = m.z < 0 ? -m.z : m.z;
-  const bool xm = adx >= m.w;
-  const int sgn = m.z < 0 ? -1 : 1, mext = xm ? m.w : adx, n2 = 2 * n;
+  const int adx = u.m.z < 0 ? -u.m.z : u.m.z;
+  const bool xm = adx >= u.m.w;
+  const int sgn = u.m.z < 0 ? -1 : 1, mext = xm ? u.m.w : adx, n2 = 2 * n;
   const int ek = n > 0 && lane <= n ? (2 * lane * mext + n) % n2 : 0;  // error term of point lane
   // this lane's offsets d = dd - n, dd = lane and lane + 64 (when dd <= 2n): q_d and the
   // threshold 2n - rho_d of class q_d + 1 (none for d = 0)
@@ -695,24 +686,73 @@ __device__ __forceinline__ void rec_update_wave(const RecGeo &g, int a, int b, i
   }
 }
 
+// The same for a path of more than 64 pixels, bit by bit.
+template <unsigned MASK>
+__device__ __forceinline__ void upd_long(const RecGeo &g, int a, int b, int v, int side, int4 m) {
+  using P = Planes<MASK>;
+  const int lane = threadIdx.x & 63;
+  const int off = m.x, n = m.y;
+  const int ay = a / g.W, ax = a - ay * g.W, by = b / g.W, bx = b - by * g.W;
+  const int sx = side ? bx : ax, sy = side ? by : ay;
+  const int ox = side ? ax - bx : bx - ax, oy = side ? ay - by : by - ay;
+  const bool near = within_small(ox, g.W, m.z < 0 ? -m.z : m.z) && within_small(oy, g.H, m.w);
+  for (int kc = 0; kc <= n; kc += 64) {
+    const int k = kc + lane;
+    if (k > n) continue;
+    const int32_t pk = g.pix[off + k];
+    if (near && on_path(ox + pix_dx(pk), oy + pix_dy(pk), m.z, m.w, n, g.W, g.H)) continue;
+    const int x = wrapi(sx - pix_dx(pk), g.W), y = wrapi(sy - pix_dy(pk), g.H);
+    uint8_t *op = g.ones + (size_t)v * g.oplane + ones_at(g, x, y);
+    const int o0 = (int)*op, o1 = side ? o0 + 1 : o0 - 1;
+    *op = (uint8_t)o1;
+    unsigned chg = 0;
+#pragma unroll
+    for (int pl = 0; pl < P::n; ++pl)
+      if (plane_cond(P::side(pl), P::phase(pl), o0, n) != plane_cond(P::side(pl), P::phase(pl), o1, n))
+        chg |= 1u << pl;
+    if (!chg) continue;
+    for (int j = 0; j <= n; ++j) {
+      const int32_t pj = g.pix[off + j];
+      const int qx = wrapi(x + pix_dx(pj), g.W), qy = wrapi(y + pix_dy(pj), g.H);
+      uint32_t *R = g.rec + ((size_t)qy * g.W + qx) * g.rstride;
+      const int bit = off + j;
+#pragma unroll
+      for (int pl = 0; pl < P::n; ++pl)
+        if (chg & (1u << pl)) atomicXor(R + (size_t)pl * g.Rw + (bit >> 5), 1u << (bit & 31));
+    }
+  }
+}
+
 // End of a step under the records method: workgroups 0 .. nupd - 1 apply the accepted
-// interchange to ones and records (rec_update_wave), workgroup nupd does the step's upkeep
+// interchange to ones and records (upd_load and upd_apply, upd_long for paths of 64 pixels or
+// more), workgroup nupd does the step's upkeep
 // (step_apply).  Each workgroup takes the step's decision itself (ctl->ks, or the same scan of the
 // last round), so one launch replaces the upkeep kernel followed by the update kernel: the upkeep
 // touches counts, image bits, pixel lists and energy, none of which the update reads.
 // The update waves stride over the 2 nv (vector, side) pairs, so that the launch stays within
 // what the device holds at once (a second round of workgroups would repeat the whole latency
 // chain of decision, load and flips).
-template <unsigned MASK>
+// PRE: the wave's first PRE (vector, side) pairs are prefetched (1 when every pair has its own
+// wave).
+template <unsigned MASK, int PRE>
 __global__ void __launch_bounds__(256)
 k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   __shared__ int s_first;
-  // the wave's first vector and path pixel do not depend on the decision: load them first, at
-  // clamped indices (no branch), so that they overlap the decision's reads
+  // the wave's first PRE (vector, side) pairs: vectors and path pixels do not depend on the
+  // decision, so they are loaded first, at clamped indices (no branch), to overlap its reads
+  constexpr int kPre = PRE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wid0 = (int)blockIdx.x * 4 + wave;
-  const int v0 = wid0 >> 1;
-  int4 m = g.meta[min(v0, g.nv - 1)];
-  int32_t pk = g.pix[m.x + min(lane, m.y)];
+  const int stride = 4 * nupd, npairs = 2 * g.nv;
+  UpdPair u[kPre];
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) {
+    const int wid = min(wid0 + i * stride, npairs - 1);
+    u[i].v = wid >> 1;
+    u[i].side = wid & 1;
+    u[i].m = g.meta[u[i].v];
+  }
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) u[i].pk = g.pix[u[i].m.x + min(lane, u[i].m.y)];
   // done, ks, a, b of an earlier round's decision in one load (nothing in this launch writes
   // the control block: the upkeep is told not to)
   const int4 c4 = *reinterpret_cast<const int4 *>(f.ctl);
@@ -726,13 +766,30 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   }
   if (ks < 0) return;
   const int2 ab = ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
-  for (int wid = wid0; wid < 2 * g.nv; wid += 4 * nupd) {
-    const int v = wid >> 1;
-    if (wid != wid0) {
-      m = g.meta[v];
-      pk = g.pix[m.x + min(lane, m.y)];
+  // the loads of every prefetched pair are issued before any pair is applied
+#pragma unroll
+  for (int i = 0; i < kPre; ++i)
+    if (wid0 + i * stride < npairs && u[i].m.y < 64) upd_load<MASK>(g, ab.x, ab.y, u[i]);
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) {
+    if (wid0 + i * stride >= npairs) break;
+    if (u[i].m.y < 64)
+      upd_apply<MASK>(g, ab.x, ab.y, u[i]);
+    else
+      upd_long<MASK>(g, ab.x, ab.y, u[i].v, u[i].side, u[i].m);
+  }
+  for (int wid = wid0 + kPre * stride; wid < npairs; wid += stride) {
+    UpdPair w;
+    w.v = wid >> 1;
+    w.side = wid & 1;
+    w.m = g.meta[w.v];
+    if (w.m.y < 64) {
+      w.pk = g.pix[w.m.x + min(lane, w.m.y)];
+      upd_load<MASK>(g, ab.x, ab.y, w);
+      upd_apply<MASK>(g, ab.x, ab.y, w);
+    } else {
+      upd_long<MASK>(g, ab.x, ab.y, w.v, w.side, w.m);
     }
-    rec_update_wave<MASK>(g, ab.x, ab.y, v, wid & 1, m, pk);
   }
 }
 
@@ -766,7 +823,7 @@ int rec_end_workgroups(const RecGeo &g, int cus) {
   int per_cu = 0;
   hipError_t e = hipSuccess;
 #define LPF_OCC(M) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M>, 256, 0)
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M, 1>, 256, 0)
   LPF_REC_MASK_SWITCH(g.mask, LPF_OCC)
 #undef LPF_OCC
   // the step's upkeep workgroup runs beside the update workgroups
@@ -776,8 +833,15 @@ int rec_end_workgroups(const RecGeo &g, int cus) {
 
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
   const int nupd = g.end_wgs > 0 ? g.end_wgs : std::min((2 * g.nv + 3) / 4, 1024);
-#define LPF_END(M) \
-  hipLaunchKernelGGL(k_rec_step_end<M>, dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, f, nupd)
+  // pairs per wave: with more than one, the first three are prefetched together
+  const bool one = 2 * g.nv <= 4 * nupd;
+#define LPF_END(M)                                                                             \
+  if (one)                                                                                     \
+    hipLaunchKernelGGL((k_rec_step_end<M, 1>), dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, \
+                       f, nupd);                                                               \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_rec_step_end<M, 3>), dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, \
+                       f, nupd);
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
 #undef LPF_END
   return hipGetLastError();
