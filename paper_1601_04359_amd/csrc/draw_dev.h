@@ -115,20 +115,23 @@ __device__ __forceinline__ void propose_draw(const ProposeArgs &p, int k, int &a
   p.cand[k] = make_int2(a, b);
   p.slot[k] = make_int2(ia, ib);
   p.U[k] = u;
-  if (p.pre && p.proposal == 0 && k < 64) {
-    // the next step's slots of candidate k: the same draw with the step counter advanced (a
-    // phase-preserving interchange keeps n1 and n0)
-    const AnnealDev *st = p.st;
-    const uint64_t next = st->step + 1;
-    uint64_t c[4] = {next, (uint64_t)k, 0ull, 0ull};
-    philox4x64_10(c, p.seed, 0x6c7066ull);
-    p.pre[(int)(next & 1ull) * 64 + k] =
-        make_int4(uniform_slot(c[0], st->n1), uniform_slot(c[1], st->n0), pre_tag(next), 0);
-  }
 }
 
-// Candidate k (< 64) of the current step for round 0: its slots from the previous step's draw
-// when they were written for this step, else drawn here.  Only a and b are produced.
+// The next step's uniform candidate k (< 64) for its round 0, drawn during this step: the same
+// draw with the step counter advanced (a phase-preserving interchange keeps n1 and n0), its
+// pixels read from the lists as they are before this step's interchange (round0_candidate
+// corrects the one that the interchange moves).
+__device__ __forceinline__ void pre_draw(const ProposeArgs &p, int k) {
+  const AnnealDev *st = p.st;
+  const uint64_t next = st->step + 1;
+  uint64_t c[4] = {next, (uint64_t)k, 0ull, 0ull};
+  philox4x64_10(c, p.seed, 0x6c7066ull);
+  const int a = st->pos1[uniform_slot(c[0], st->n1)], b = st->pos0[uniform_slot(c[1], st->n0)];
+  p.pre[(int)(next & 1ull) * 64 + k] = make_int4(a, b, pre_tag(next), 0);
+}
+
+// Candidate k (< 64) of the current step for round 0: from the previous step's pre_draw when
+// it was written for this step, else drawn here.  Only a and b are produced.
 __device__ __forceinline__ void round0_candidate(const ProposeArgs &p, int k, int &a, int &b) {
   if (p.pre && p.proposal == 0) {
     // both parities are read at once, beside the state, so that no load waits on the step
@@ -137,8 +140,11 @@ __device__ __forceinline__ void round0_candidate(const ProposeArgs &p, int k, in
     const int tag = pre_tag(st->step);
     const int4 q = q0.z == tag ? q0 : q1;
     if (q.z == tag) {
-      a = st->pos1[q.x];
-      b = st->pos0[q.y];
+      // the previous step's interchange put its b at its a's slot of the phase-1 list and its a
+      // at its b's slot of the phase-0 list (the lists hold distinct pixels, so a pixel read
+      // before it equals that a exactly when it was read at that slot)
+      a = q.x == st->last_a ? st->last_b : q.x;
+      b = q.y == st->last_b ? st->last_a : q.y;
       return;
     }
   }

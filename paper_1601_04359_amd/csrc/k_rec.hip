@@ -418,11 +418,13 @@ k_rec_round(RecGeo g, const uint64_t *__restrict__ bits, const int2 *__restrict_
 }
 
 // Round 0 of a step in the launch of the step's draws (unranked draws, K > 64): workgroups
-// [0, nprop) are the draws of k_propose (propose_draw); workgroup nprop + kr * nvb + vb takes
-// vector block vb of draw kr < C0, which it draws again itself (the same counter gives the same
-// draw, so it does not wait for the draw blocks), and adds its block sum into S0[kr] instead of
-// S_acc, which the draw blocks are zeroing.  S0 is zero at the start of every step (cleared at
-// allocation and by the end of each step); round 1 reads it when it decides round 0.
+// [0, nprop) are the draws of k_propose (propose_draw); workgroup nprop draws the next step's
+// first 64 uniform candidates (pre_draw); workgroup nprop + 1 + kr * nvb + vb takes vector block
+// vb of draw kr < C0, which it takes from the previous step's pre_draw or draws again itself (the
+// same counter gives the same draw, so it does not wait for the draw blocks), and adds its block
+// sum into S0[kr] instead of S_acc, which the draw blocks are zeroing.  S0 is zero at the start
+// of every step (cleared at allocation and by the end of each step); round 1 reads it when it
+// decides round 0.
 template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__restrict__ counts,
@@ -436,8 +438,12 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
     propose_draw(p, (int)(blockIdx.x * blockDim.x + threadIdx.x), a, b);
     return;
   }
+  if ((int)blockIdx.x == nprop) {  // the next step's round-0 candidates
+    if (p.pre && p.proposal == 0 && threadIdx.x < 64) pre_draw(p, (int)threadIdx.x);
+    return;
+  }
   const int nvb = (g.nv + 255) >> 8;
-  const int bi = (int)blockIdx.x - nprop, kr = bi / nvb, vb = bi - kr * nvb;
+  const int bi = (int)blockIdx.x - nprop - 1, kr = bi / nvb, vb = bi - kr * nvb;
   if (kr >= C0) return;
   const int v = vb * 256 + (int)threadIdx.x;
   const bool vin = v < g.nv;
@@ -876,7 +882,7 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
 hipError_t launch_rec_draw_round0(const StepLaunch &L, const RoundPlan &r, hipStream_t stream) {
   const int nprop = (L.draw.K + 255) / 256;
   const int nvb = (L.rg.nv + 255) / 256;
-  const unsigned grid = (unsigned)(nprop + nvb * r.C);
+  const unsigned grid = (unsigned)(nprop + 1 + nvb * r.C);
 #define LPF_R0(M)                                                                            \
   hipLaunchKernelGGL(k_rec_draw_round0<M>, dim3(grid), dim3(256), 0, stream, L.rg, L.draw, nprop, \
                      r.C, L.counts, L.target, L.N, L.Nt, L.S0, L.dl, L.dl_t, L.dl_k)

@@ -1591,6 +1591,8 @@ lpf_status anneal_create(lpf_ctx c, uint64_t *bits, int W, int H, int cx, int cy
   hipError_t e;
   AnnealDev host{};
   host.step = step0;
+  host.last_a = -1;
+  host.last_b = -1;
   a->host_step = step0;
   if ((e = hipMalloc(&a->dev, sizeof(AnnealDev))) != hipSuccess ||
       (e = hipMalloc(&a->pos, sizeof(int32_t) * (size_t)N)) != hipSuccess) {

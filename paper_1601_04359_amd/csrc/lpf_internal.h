@@ -254,9 +254,10 @@ struct ProposeArgs {
   double *T_cur;
   const float *rank_score;
   uint64_t *rank_keys, *rank_lists;
-  // uniform draws: the list slots of the next step's first 64 candidates, written by this step's
-  // draw (int4 {slot1, slot0, tag, 0} at (step & 1) * 64 + k, tag = (step & 0x3fffffff) + 1), so
-  // that the next round 0 skips the counter-based generator; null: none
+  // uniform draws: the next step's first 64 candidates, drawn during this step (int4 {a, b, tag,
+  // 0} at (step & 1) * 64 + k, tag = (step & 0x3fffffff) + 1, pixels as the lists hold them
+  // before this step's interchange), so that the next round 0 neither runs the counter-based
+  // generator nor reads the lists; null: none
   int4 *pre;
 };
 struct StepLaunch {
@@ -318,6 +319,7 @@ struct AnnealDev {
   uint64_t step;
   int32_t n1, n0;
   int32_t *pos1, *pos0;  // phase-1 / phase-0 pixel lists (n1 and n0 entries)
+  int32_t last_a, last_b;  // the last step's accepted interchange, -1 when none
 };
 // Same layout as lpf_step_result in include/lpf.h.
 struct StepResult {

@@ -175,12 +175,16 @@ __device__ __forceinline__ void step_apply(const FinalArgs &f, int ks, bool deci
     f.bits[(size_t)by * wpr + (bx >> 6)] |= 1ull << (bx & 63);
     st->pos1[f.slot[ks].x] = b;
     st->pos0[f.slot[ks].y] = a;
+    st->last_a = a;
+    st->last_b = b;
     r.k = ks;
     r.a = a;
     r.b = b;
     r.de = de;
     r.e = e;
   } else {
+    st->last_a = -1;
+    st->last_b = -1;
     r.k = -1;
     r.a = -1;
     r.b = -1;
