@@ -494,43 +494,58 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
                   int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t,
                   int64_t dl_k) {
   using P = Planes<MASK>;
+  constexpr int kPer = kRankMax / 256;  // draws of [0, R) per thread in the compaction
   __shared__ uint64_t sl[2][64];
   __shared__ uint64_t s_key;
-  __shared__ int s_cnt[4];
+  __shared__ int s_cnt[kPer][4];
   __shared__ long long s_part[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int R = min(K, kRankMax), T = min(R, kRankTop), nl = (R + 255) >> 8;
-  const uint64_t m = merge_lists16(lists, nl, sl);
   if (blockIdx.x == 0) {
+    // this thread's keys are requested before the merge, so that their latency overlaps it
+    uint64_t kk[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int i = j * 256 + (int)threadIdx.x;
+      kk[j] = i < R ? keys[i] : 0ull;
+    }
+    const uint64_t m = merge_lists16(lists, nl, sl);
     if (w == 0) {
       if (lane < T) order[lane] = (int32_t)~(uint32_t)m;
       if (lane == T - 1) s_key = m;  // the T-th best key: every other draw is below it
     }
     __syncthreads();
     const uint64_t thr = s_key;
+    // the other draws of [0, R) in draw order: every wave's count per slice j first, then the
+    // positions from their prefix sums (one barrier for all slices)
+    uint64_t bal[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int i = j * 256 + (int)threadIdx.x;
+      bal[j] = __ballot(i < R && kk[j] < thr);
+      if (lane == 0) s_cnt[j][w] = __popcll(bal[j]);
+    }
+    __syncthreads();
     int base = T;
-    for (int c0 = 0; c0 < R; c0 += 256) {
-      const int i = c0 + (int)threadIdx.x;
-      const bool rest = i < R && keys[i] < thr;
-      const uint64_t bal = __ballot(rest);
-      if (lane == 0) s_cnt[w] = __popcll(bal);
-      __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
       int before = 0, total = 0;
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
-        before += v < w ? s_cnt[v] : 0;
-        total += s_cnt[v];
+        before += v < w ? s_cnt[j][v] : 0;
+        total += s_cnt[j][v];
       }
-      if (rest) {
-        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        order[base + before + below] = i;
+      if ((bal[j] >> lane) & 1ull) {
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+        order[base + before + below] = j * 256 + (int)threadIdx.x;
       }
       base += total;
-      __syncthreads();
     }
     for (int i = R + (int)threadIdx.x; i < K; i += 256) order[i] = i;
     return;
   }
+  const uint64_t m = merge_lists16(lists, nl, sl);
   const int nvb = (g.nv + 255) >> 8;
   const int bi = (int)blockIdx.x - 1, kr = bi / nvb, vb = bi - kr * nvb;
   if (w == 0 && lane == kr) s_key = m;
