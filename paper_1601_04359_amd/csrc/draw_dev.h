@@ -62,15 +62,21 @@ __device__ __forceinline__ int uniform_slot(uint64_t r, int n) {
 // Tag of step `step` in ProposeArgs::pre (never 0, the value of a cleared entry).
 __device__ __forceinline__ int pre_tag(uint64_t step) { return (int)(step & 0x3fffffffull) + 1; }
 
-// Candidate k of the current step: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
+// Candidate k of step `step`: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
 // proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void (a = b = -1) unless
 // both pixels are interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn
 // with probability proportional to the weights whose inclusive prefix sums are cw1 (over pos1)
 // and b likewise with cw0 (over pos0), by inversion of r0, r1.  ia, ib: the list slots; u = r2.
-__device__ __forceinline__ void draw_candidate(const ProposeArgs &p, int k, int &a, int &b,
-                                               int &ia, int &ib, double &u) {
+// (sa, sb), sa >= 0: an interchange being applied in the same launch (the draws of the next step
+// in the launch that ends this one), whose two list writes may or may not be visible: a's slot
+// of the phase-1 list holds sa before and sb after it, b's slot of the phase-0 list sb before and
+// sa after, and no other slot holds either pixel, so a read of either value there is taken as
+// the value after it.  Not with proposal 1, which reads the image.
+__device__ __forceinline__ void draw_candidate_at(const ProposeArgs &p, uint64_t step, int k,
+                                                  int sa, int sb, int &a, int &b, int &ia,
+                                                  int &ib, double &u) {
   const AnnealDev *st = p.st;
-  uint64_t c[4] = {st->step, (uint64_t)k, 0ull, 0ull};
+  uint64_t c[4] = {step, (uint64_t)k, 0ull, 0ull};
   philox4x64_10(c, p.seed, 0x6c7066ull);
   const int n1 = st->n1, n0 = st->n0;
   const double u3 = (double)(c[3] >> 11) * (1.0 / 9007199254740992.0);
@@ -85,11 +91,37 @@ __device__ __forceinline__ void draw_candidate(const ProposeArgs &p, int k, int 
   }
   a = st->pos1[ia];
   b = st->pos0[ib];
+  if (sa >= 0) {
+    a = a == sa || a == sb ? sb : a;
+    b = b == sb || b == sa ? sa : b;
+  }
   if (p.proposal == 1 && !(interfacial(p.bits, p.W, p.H, a) && interfacial(p.bits, p.W, p.H, b))) {
     a = -1;
     b = -1;
   }
   u = (double)(c[2] >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Candidate k of the current step.
+__device__ __forceinline__ void draw_candidate(const ProposeArgs &p, int k, int &a, int &b,
+                                               int &ia, int &ib, double &u) {
+  draw_candidate_at(p, p.st->step, k, -1, -1, a, b, ia, ib, u);
+}
+
+// Draw k (< K) of step `step` into cand / slot / U, without the resets of propose_draw: the
+// next step's draws made in the launch that ends this step (sa, sb: this step's interchange, -1
+// when none; see draw_candidate_at).  a, b: the draw (-1 when k >= K).
+__device__ __forceinline__ void next_draw(const ProposeArgs &p, uint64_t step, int k, int sa,
+                                          int sb, int &a, int &b) {
+  a = -1;
+  b = -1;
+  if (k >= p.K) return;
+  int ia, ib;
+  double u;
+  draw_candidate_at(p, step, k, sa, sb, a, b, ia, ib, u);
+  p.cand[k] = make_int2(a, b);
+  p.slot[k] = make_int2(ia, ib);
+  p.U[k] = u;
 }
 
 // Draw k (< K) into cand / slot / U; also zeroes its energy sum (S_acc) and, for k = 0, the

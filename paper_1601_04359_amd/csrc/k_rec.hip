@@ -480,21 +480,40 @@ k_rec_draw_round0(RecGeo g, ProposeArgs p, int nprop, int C0, const uint32_t *__
 }
 
 // Round 0 of a ranked step together with the merge of the ranking (records method, K > 64,
-// after k_propose wrote the rank keys and workgroup lists): every workgroup merges the lists
-// itself (merge_lists16).  Workgroup 0 writes the evaluation order for the later rounds (the best
-// 64, then the other draws of [0, R) in draw order, then R .. K - 1); workgroup
-// 1 + kr * nvb + vb evaluates vector block vb of the kr-th best draw and adds its block sum into
-// S_acc, which k_propose zeroed.
+// after k_propose or the previous step's end wrote the rank keys and workgroup lists): every
+// workgroup merges the lists itself (merge_lists16).  Workgroup 0 writes the evaluation order for
+// the later rounds (the best 64, then the other draws of [0, R) in draw order, then R .. K - 1);
+// workgroup 1 + kr * nvb + vb evaluates vector block vb of the kr-th best draw and adds its block
+// sum into S0[kr] (zero at the start of every step; round 1 reads it when it decides round 0).
+// The launch also does the step's resets, which a draw made by the previous step's end does not.
 template <unsigned MASK>
 __global__ void __launch_bounds__(256)
 k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *__restrict__ keys,
                   int K, int32_t *__restrict__ order, const uint64_t *__restrict__ bits,
                   const int2 *__restrict__ cand, int C0, const uint32_t *__restrict__ counts,
                   const uint32_t *__restrict__ target, int64_t N, int64_t Nt,
-                  int64_t *__restrict__ S_acc, int16_t *__restrict__ dl, int64_t dl_t,
-                  int64_t dl_k) {
+                  int64_t *__restrict__ S_acc, int64_t *__restrict__ S0,
+                  int16_t *__restrict__ dl, int64_t dl_t, int64_t dl_k,
+                  StepCtl *__restrict__ ctl, const AnnealDev *__restrict__ st,
+                  double *__restrict__ T_cur, const double *__restrict__ T_sched, int64_t T_base,
+                  double T_value) {
   using P = Planes<MASK>;
   constexpr int kPer = kRankMax / 256;  // draws of [0, R) per thread in the compaction
+  // the step's resets: energy sums of the later rounds (spread over all workgroups; round 0
+  // adds into S0), and in workgroup 0 the control block, the next step's number and the step's
+  // temperature
+  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < K; i += (int)(gridDim.x * blockDim.x))
+    S_acc[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint64_t step = st->step;
+    ctl->done = 0;
+    ctl->ks = -1;
+    ctl->a = -1;
+    ctl->b = -1;
+    ctl->S = 0;
+    ctl->next_step = step + 1;
+    *T_cur = T_sched ? T_sched[(int64_t)step - T_base] : T_value;
+  }
   __shared__ uint64_t sl[2][64];
   __shared__ uint64_t s_key;
   __shared__ int s_cnt[kPer][4];
@@ -581,7 +600,7 @@ k_rec_rank_round0(RecGeo g, const uint64_t *__restrict__ lists, const uint64_t *
   if (threadIdx.x == 0) {
     long long tot = 0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += s_part[q];
-    add_acc(&S_acc[k], tot);
+    add_acc(&S0[kr], tot);
   }
 }
 
@@ -754,11 +773,15 @@ __device__ __forceinline__ void upd_long(const RecGeo &g, int a, int b, int v, i
 // what the device holds at once (a second round of workgroups would repeat the whole latency
 // chain of decision, load and flips).
 // PRE: the wave's first PRE (vector, side) pairs are prefetched (1 when every pair has its own
-// wave).
+// wave).  Workgroups past nupd (ranked chains) draw the next step with the arguments nx:
+// candidates, rank keys and each 256-draw workgroup's best 64, from the pixel lists as this
+// step's interchange leaves them (draw_candidate_at), so that the next step needs no launch of
+// its draws.
 template <unsigned MASK, int PRE>
 __global__ void __launch_bounds__(256)
-k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
+k_rec_step_end(RecGeo g, FinalArgs f, int nupd, ProposeArgs nx) {
   __shared__ int s_first;
+  __shared__ uint64_t sl[2][64];
   // the wave's first PRE (vector, side) pairs: vectors and path pixels do not depend on the
   // decision, so they are loaded first, at clamped indices (no branch), to overlap its reads
   constexpr int kPre = PRE;
@@ -779,6 +802,19 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd) {
   const int4 c4 = *reinterpret_cast<const int4 *>(f.ctl);
   const int ks0 = c4.y;
   const int ks = step_choice(f, ks0, &s_first);
+  if ((int)blockIdx.x > nupd) {
+    const int2 sab = ks < 0 ? make_int2(-1, -1) : ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
+    const int db = (int)blockIdx.x - nupd - 1, k = db * 256 + (int)threadIdx.x;
+    int a, b;
+    next_draw(nx, f.ctl->next_step, k, sab.x, sab.y, a, b);
+    if (nx.rank_score && db * 256 < min(nx.K, kRankMax)) {
+      const bool ranked = k < min(nx.K, kRankMax);
+      const uint64_t key = ranked ? rank_key(a, b, k, nx.rank_score) : 0ull;
+      if (ranked) nx.rank_keys[k] = key;
+      block_top64(key, sl, nx.rank_lists + (size_t)db * kRankTop);
+    }
+    return;
+  }
   // counts += dL shared by all nupd + 1 workgroups (one term per thread at most sizes)
   step_counts(f, ks, (int)blockIdx.x, nupd + 1);
   if ((int)blockIdx.x == nupd) {
@@ -847,22 +883,29 @@ int rec_end_workgroups(const RecGeo &g, int cus) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M, 1>, 256, 0)
   LPF_REC_MASK_SWITCH(g.mask, LPF_OCC)
 #undef LPF_OCC
-  // the step's upkeep workgroup runs beside the update workgroups
-  if (e == hipSuccess && need + 1 <= per_cu * cus) return need;
+  // the step's upkeep workgroup runs beside the update workgroups, and up to 64 workgroups of
+  // the next step's draws in ranked chains
+  if (e == hipSuccess && need + 1 + 64 <= per_cu * cus) return need;
   return std::min(need, 1024);
 }
 
-hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream) {
+hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, const ProposeArgs *next,
+                               hipStream_t stream) {
   const int nupd = g.end_wgs > 0 ? g.end_wgs : std::min((2 * g.nv + 3) / 4, 1024);
   // pairs per wave: with more than one, the first three are prefetched together
   const bool one = 2 * g.nv <= 4 * nupd;
+  ProposeArgs nx{};
+  int ndraw = 0;
+  if (next) {
+    nx = *next;
+    ndraw = (nx.K + 255) / 256;
+  }
+  const dim3 grid((unsigned)(nupd + 1 + ndraw));
 #define LPF_END(M)                                                                             \
   if (one)                                                                                     \
-    hipLaunchKernelGGL((k_rec_step_end<M, 1>), dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, \
-                       f, nupd);                                                               \
+    hipLaunchKernelGGL((k_rec_step_end<M, 1>), grid, dim3(256), 0, stream, g, f, nupd, nx);  \
   else                                                                                         \
-    hipLaunchKernelGGL((k_rec_step_end<M, 3>), dim3((unsigned)nupd + 1), dim3(256), 0, stream, g, \
-                       f, nupd);
+    hipLaunchKernelGGL((k_rec_step_end<M, 3>), grid, dim3(256), 0, stream, g, f, nupd, nx);
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
 #undef LPF_END
   return hipGetLastError();
@@ -877,8 +920,8 @@ hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide
   const int gy = std::max(1, std::min(std::min(r.C, 512), (512 + nvb - 1) / nvb));
   const dim3 grid((unsigned)nvb, (unsigned)gy);
   int16_t *dl = decide ? L.dl : nullptr;
-  // round 1 after a round 0 evaluated with the draws: round 0's sums are in S0
-  const int64_t *S0 = decide && L.fuse_draw && r.pC > 0 ? L.S0 : nullptr;
+  // round 1 after a round 0 evaluated with the draws or the ranking's merge: its sums are in S0
+  const int64_t *S0 = decide && (L.fuse_draw || L.fuse_rank) && r.pC > 0 ? L.S0 : nullptr;
 #define LPF_ROUND_O(M, O)                                                                      \
   hipLaunchKernelGGL((k_rec_round<M, O>), grid, dim3(256), 0, stream, L.rg, L.bits, L.cand, L.K, \
                      r.k0, r.C, L.counts, L.target, L.N, L.Nt, L.S_acc, dl, L.dl_t, L.dl_k,   \
@@ -912,7 +955,8 @@ hipError_t launch_rec_rank_round0(const StepLaunch &L, const RoundPlan &r, hipSt
 #define LPF_RR0(M)                                                                             \
   hipLaunchKernelGGL(k_rec_rank_round0<M>, dim3(grid), dim3(256), 0, stream, L.rg,               \
                      L.rank_keys + kRankMax, L.rank_keys, L.K, L.order_rw, L.bits, L.cand, r.C, \
-                     L.counts, L.target, L.N, L.Nt, L.S_acc, L.dl, L.dl_t, L.dl_k)
+                     L.counts, L.target, L.N, L.Nt, L.S_acc, L.S0, L.dl, L.dl_t, L.dl_k, L.ctl, \
+                     L.st, L.T_cur, L.T_sched, L.T_base, L.T_value)
   LPF_REC_MASK_SWITCH(L.rg.mask, LPF_RR0)
 #undef LPF_RR0
   return hipGetLastError();

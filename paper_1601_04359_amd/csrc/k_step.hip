@@ -222,9 +222,10 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
   f.li0 = nr ? L.rounds[nr - 1].k0 : 0;
   f.lC = nr ? L.rounds[nr - 1].C : 0;
   f.out_base = L.out_base;
-  f.S0 = L.fuse_draw ? L.S0 : nullptr;
-  // records: the upkeep and the update of ones and records share one launch
-  if (L.records && !L.s2) return launch_rec_step_end(L.rg, f, stream);
+  f.S0 = L.fuse_draw || L.fuse_rank ? L.S0 : nullptr;
+  // records: the upkeep and the update of ones and records share one launch (with the next
+  // step's draws in ranked chains)
+  if (L.records && !L.s2) return launch_rec_step_end(L.rg, f, L.draw_next ? &L.next : nullptr, stream);
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, f);
   return hipGetLastError();
 }

@@ -238,6 +238,8 @@ struct lpf_anneal_s {
   DevBuf pre;              // uniform draws: the next step's round-0 list slots (ProposeArgs::pre)
   DevBuf Tcur;             // the current step's temperature (device scalar)
   uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
+  bool predrawn = false;   // ranked chain: the next step's draws are made by the last step's end
+  int predrawn_K = 0;      // ... for that many candidates
   hipStream_t cap = nullptr;  // private stream for capturing runs of steps
 };
 
@@ -718,21 +720,26 @@ int delta_chunks(int K) {
   return std::max(1, 2048 / groups);
 }
 
-// Candidates of the chain's current step into a->cand / U / slot (learned weights first); with
-// rank, learned draws also leave their rank keys and workgroup lists in a->rank_buf.  With defer,
-// the draws' arguments go to *defer for a launch that also evaluates round 0, and nothing but the
-// learned weights is launched here.
+// Candidates of the chain's current step into a->cand / U / slot (learned weights first), in the
+// half of those double-buffered arrays that the step's parity selects; with rank, learned draws
+// also leave their rank keys and workgroup lists in a->rank_buf.  With defer, the draws'
+// arguments go to *defer for a launch that also evaluates round 0 (or for none: the previous
+// step's end made them), and nothing but the learned weights is launched here.  args: when
+// given, also receives the arguments.  upkeep false: the learned proposal's re-scoring and draw
+// count are left alone (a draw made ahead of its step).
 lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
                            int64_t *S_acc = nullptr, StepCtl *ctl = nullptr,
                            const double *T_sched = nullptr, int64_t T_base = 0, double T = 0.0,
                            double *T_cur = nullptr, bool rank = false,
-                           ProposeArgs *defer = nullptr) {
+                           ProposeArgs *defer = nullptr, ProposeArgs *args = nullptr,
+                           bool upkeep = true) {
   hipError_t e;
   const int64_t N = (int64_t)a->W * a->H;
-  if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
-      (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
-      (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess)
+  if ((e = a->cand.ensure(sizeof(int2) * 2 * (size_t)K)) != hipSuccess ||
+      (e = a->U.ensure(sizeof(double) * 2 * (size_t)K)) != hipSuccess ||
+      (e = a->slot.ensure(sizeof(int2) * 2 * (size_t)K)) != hipSuccess)
     return hip_fail(e, "anneal: candidate scratch");
+  const size_t half = (size_t)(a->host_step & 1) * (size_t)K;
   const double *cw1 = nullptr, *cw0 = nullptr;
   const float *rank_score = nullptr;
   uint64_t *rank_keys = nullptr;
@@ -744,7 +751,7 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
                      (e = a->cw0.ensure(sizeof(double) * (size_t)N)) != hipSuccess ||
                      (e = a->cwb.ensure(sizeof(double) * 4 * (size_t)((N + 1023) / 1024))) != hipSuccess))
       return hip_fail(e, "anneal: proposal scratch");
-    if (a->learn_age == 0 || a->learn_age >= a->refresh) {
+    if (upkeep && (a->learn_age == 0 || a->learn_age >= a->refresh)) {
       const float *sc = a->scores_ext;
       if (a->net) {
         if ((e = a->scores.ensure(sizeof(float) * (size_t)N)) != hipSuccess)
@@ -759,7 +766,7 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
         return hip_fail(e, "anneal: proposal weights");
       a->learn_age = 0;
     }
-    ++a->learn_age;
+    if (upkeep) ++a->learn_age;
     if (weighted) {
       cw1 = (const double *)a->cw1.p;
       cw0 = (const double *)a->cw0.p;
@@ -784,9 +791,9 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   p.cw1 = cw1;
   p.cw0 = cw0;
   p.eps = a->eps;
-  p.cand = (int2 *)a->cand.p;
-  p.U = (double *)a->U.p;
-  p.slot = (int2 *)a->slot.p;
+  p.cand = (int2 *)a->cand.p + half;
+  p.U = (double *)a->U.p + half;
+  p.slot = (int2 *)a->slot.p + half;
   p.S_acc = S_acc;
   p.ctl = ctl;
   p.T_sched = T_sched;
@@ -797,7 +804,8 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   p.rank_keys = rank_keys;
   p.rank_lists = rank_keys ? rank_keys + kRankMax : nullptr;
   // a round 0 drawn in its own launch reads the slots the previous step's draw wrote
-  p.pre = defer && draw == LPF_PROP_UNIFORM && a->pre.p ? (int4 *)a->pre.p : nullptr;
+  p.pre = defer && !rank && draw == LPF_PROP_UNIFORM && a->pre.p ? (int4 *)a->pre.p : nullptr;
+  if (args) *args = p;
   if (defer) {
     *defer = p;
     return LPF_OK;
@@ -1729,9 +1737,9 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
   const int nph = nph_of(a->mask);
   const int64_t nv = lpf_num_vectors(a->cx, a->cy);
   const size_t nterms = (size_t)nph * nv;
-  if ((e = a->cand.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
-      (e = a->U.ensure(sizeof(double) * (size_t)K)) != hipSuccess ||
-      (e = a->slot.ensure(sizeof(int2) * (size_t)K)) != hipSuccess ||
+  if ((e = a->cand.ensure(sizeof(int2) * 2 * (size_t)K)) != hipSuccess ||
+      (e = a->U.ensure(sizeof(double) * 2 * (size_t)K)) != hipSuccess ||
+      (e = a->slot.ensure(sizeof(int2) * 2 * (size_t)K)) != hipSuccess ||
       (e = a->S_acc.ensure(sizeof(int64_t) * (size_t)K)) != hipSuccess ||
       (e = a->dl.ensure(sizeof(int16_t) * nterms * (size_t)K)) != hipSuccess ||
       (e = a->ctl.ensure(sizeof(StepCtl))) != hipSuccess ||
@@ -1792,30 +1800,59 @@ lpf_status step_setup(lpf_anneal a, int K, int proposal, hipStream_t s, StepLaun
 // learned proposals, whose re-scoring cadence is kept on the host).
 lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaPlan *plan,
                         bool rec, const double *T_sched, int64_t T_base, double T,
-                        lpf_step_result *out, int64_t out_base, hipStream_t s) {
+                        lpf_step_result *out, int64_t out_base, hipStream_t s,
+                        bool allow_next = false) {
   hipError_t e;
   lpf_status st;
   const bool rank = proposal == LPF_PROP_LEARNED && a->rank;
-  // records method, unranked: the draws and round 0 share one launch
+  // the step's half of the double-buffered candidates (the end of a ranked step draws the next
+  // step into the other half while it still reads this one)
+  const size_t half = (size_t)(a->host_step & 1) * (size_t)K;
+  L.cand = (const int2 *)a->cand.p + half;
+  L.slot = (const int2 *)a->slot.p + half;
+  L.U = (const double *)a->U.p + half;
+  // records method, unranked: the draws and round 0 share one launch; ranked: round 0 merges the
+  // ranking and does the step's resets
   L.fuse_draw = rec && !rank && L.rounds.size() >= 2 && L.rounds[0].C == 64;
+  L.fuse_rank = rec && rank && L.rounds.size() >= 2 && L.rounds[0].C == 64;
   L.S0 = (int64_t *)a->S0.p;
+  const bool drawn = L.fuse_rank && a->predrawn;  // made by the previous step's end
+  ProposeArgs none{}, args{};
   if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p,
                             T_sched, T_base, T, (double *)a->Tcur.p, rank,
-                            L.fuse_draw ? &L.draw : nullptr)) != LPF_OK)
+                            L.fuse_draw ? &L.draw : drawn ? &none : nullptr, &args)) != LPF_OK)
     return st;
   L.order = nullptr;
-  L.fuse_rank = false;
+  L.draw_next = false;
   if (rank) {
     const uint64_t *keys = (const uint64_t *)a->rank_buf.p;
     int32_t *ord = (int32_t *)a->order.p;
     // records method: round 0 merges the ranking itself and writes the order for later rounds
-    L.fuse_rank = rec && L.rounds.size() >= 2 && L.rounds[0].C == 64;
     L.rank_keys = keys;
     L.order_rw = ord;
+    L.T_cur = (double *)a->Tcur.p;
+    L.T_sched = T_sched;
+    L.T_base = T_base;
+    L.T_value = T;
     if (!L.fuse_rank && (e = launch_rank_merge(keys + kRankMax, keys, K, ord, s)) != hipSuccess)
       return hip_fail(e, "anneal: ranking");
     L.order = ord;
+    // the end of this step draws the next one, unless that one re-scores the cell first
+    L.draw_next = allow_next && L.fuse_rank && !(a->learn_age == 0 || a->learn_age >= a->refresh);
+    if (L.draw_next) {
+      const size_t nhalf = (size_t)((a->host_step + 1) & 1) * (size_t)K;
+      L.next = args;
+      L.next.cand = (int2 *)a->cand.p + nhalf;
+      L.next.slot = (int2 *)a->slot.p + nhalf;
+      L.next.U = (double *)a->U.p + nhalf;
+      L.next.S_acc = nullptr;
+      L.next.ctl = nullptr;
+      L.next.T_cur = nullptr;
+      L.next.pre = nullptr;
+    }
   }
+  a->predrawn = L.draw_next;
+  a->predrawn_K = K;
   L.out = reinterpret_cast<StepResult *>(out);
   L.out_base = out_base;
   if ((e = launch_step(L, s)) != hipSuccess) return hip_fail(e, "anneal: evaluation");
@@ -1848,7 +1885,9 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   DeltaPlan *plan = nullptr;
   bool rec = false;
   if ((st = step_setup(a, K, proposal, s, L, plan, rec)) != LPF_OK) return st;
-  return step_enqueue(a, K, proposal, L, plan, rec, nullptr, 0, T, out, -1, s);
+  // the previous call's end drew this step when it was a ranked step with as many candidates
+  if (a->predrawn_K != K || proposal != LPF_PROP_LEARNED) a->predrawn = false;
+  return step_enqueue(a, K, proposal, L, plan, rec, nullptr, 0, T, out, -1, s, true);
 }
 
 lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sched, int nsteps,
@@ -1880,32 +1919,50 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     }
     return age;
   };
+  a->predrawn = false;
   if (graphable && nsteps >= kGraphSteps) {
     if (!a->cap && (e = hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "lpf_anneal_run: capture stream");
+    // a ranked chain's steps are drawn by the previous step's end (except those that re-score
+    // the cell): the graph's first step is, in every replay after the first, so its draws for
+    // the first replay are made here
+    if (proposal == LPF_PROP_LEARNED && a->rank && rec && L.rounds.size() >= 2 &&
+        L.rounds[0].C == 64 && !(a->learn_age == 0 || a->learn_age >= a->refresh)) {
+      if ((st = draw_candidates(a, K, proposal, s, (int64_t *)a->S_acc.p, (StepCtl *)a->ctl.p,
+                                T_sched, base, 0.0, (double *)a->Tcur.p, true, nullptr, nullptr,
+                                false)) != LPF_OK)
+        return st;
+      a->predrawn = true;
+    }
     // the capture enqueues nothing; the replays run on the caller's stream s
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const uint64_t step_before = a->host_step;
-    const bool e3_before = a->e3_valid, rec_before = a->rec_valid;
+    const bool e3_before = a->e3_valid, rec_before = a->rec_valid, drawn_before = a->predrawn;
     const int age_before = a->learn_age;
     if ((e = hipStreamBeginCapture(a->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(e, "lpf_anneal_run: capture");
     lpf_status cst = LPF_OK;
     for (int i = 0; i < kGraphSteps && cst == LPF_OK; ++i)
-      cst = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, a->cap);
+      cst = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, a->cap, true);
     hipError_t ce = hipStreamEndCapture(a->cap, &graph);
-    // the capture enqueued nothing: restore the host counters it advanced
+    // the capture enqueued nothing: restore the host counters it advanced (every replay leaves
+    // the next step drawn as the capture found its first: the re-scoring pattern repeats)
+    const bool drawn_after = a->predrawn;
     a->host_step = step_before;
     a->e3_valid = e3_before;
     a->rec_valid = rec_before;
     a->learn_age = age_before;
+    a->predrawn = drawn_before;
+    // (with 32 a multiple of the re-scoring interval they agree; should they not, the steps are
+    // enqueued one by one instead)
+    const bool replayable = drawn_after == drawn_before;
     if (cst != LPF_OK || ce != hipSuccess ||
         (ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return cst != LPF_OK ? cst : hip_fail(ce, "lpf_anneal_run: graph");
     }
-    for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+    for (; replayable && done + kGraphSteps <= nsteps; done += kGraphSteps) {
       if ((e = hipGraphLaunch(exec, s)) != hipSuccess) break;
       a->host_step += kGraphSteps;
       if (proposal == LPF_PROP_LEARNED) a->learn_age = age_after(a->learn_age, kGraphSteps);
@@ -1917,8 +1974,11 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     if (e != hipSuccess) return hip_fail(e, "lpf_anneal_run: graph launch");
   }
   for (; done < nsteps; ++done)
-    if ((st = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, s)) != LPF_OK)
+    if ((st = step_enqueue(a, K, proposal, L, plan, rec, T_sched, base, 0.0, out, base, s,
+                           done + 1 < nsteps)) != LPF_OK)
       return st;
+  // a draw made past the run's last step is not used: the next call draws its first step
+  a->predrawn = false;
   return LPF_OK;
 }
 
@@ -2363,6 +2423,7 @@ lpf_status lpf_anneal_set_proposal(lpf_anneal a, lpf_cnn net, const float *score
   a->refresh = refresh;
   a->rank = rank != 0;
   a->learn_age = 0;
+  a->predrawn = false;
   a->net = net;
   a->scores_ext = net ? nullptr : scores;
   a->beta = beta;
@@ -2396,9 +2457,11 @@ lpf_status lpf_anneal_propose(lpf_anneal a, int K, int proposal, int32_t *cand_o
   std::lock_guard<std::mutex> lk(a->ctx->mu);
   DeviceGuard g(a->ctx->dev);
   hipStream_t s = (hipStream_t)stream;
+  a->predrawn = false;  // this draw overwrites the half a draw made ahead would be in
   lpf_status st = draw_candidates(a, K, proposal, s);
   if (st != LPF_OK) return st;
-  hipError_t e = launch_copy_cand((const int2 *)a->cand.p, K, cand_out, s);
+  const size_t half = (size_t)(a->host_step & 1) * (size_t)K;
+  hipError_t e = launch_copy_cand((const int2 *)a->cand.p + half, K, cand_out, s);
   return e == hipSuccess ? LPF_OK : hip_fail(e, "lpf_anneal_propose");
 }
 
@@ -2470,6 +2533,7 @@ lpf_status lpf_anneal_set_method(lpf_anneal a, int method) {
     return fail(LPF_E_UNSUPPORTED, "lpf_anneal_set_method: records: " + why);
   std::lock_guard<std::mutex> lk(a->ctx->mu);
   a->method = method;
+  a->predrawn = false;
   a->rec_choice = a->sample ? 1 : -1;
   return LPF_OK;
 }

@@ -192,6 +192,7 @@ struct alignas(16) StepCtl {
   int32_t ks;        // accepted candidate, -1 when none
   int32_t a, b;      // its interchange (cand[ks]), set with ks, so that one load gives all three
   long long S;       // its integer energy sum
+  uint64_t next_step;  // ranked records steps: the step after this one (set by the step's round 0)
 };
 
 // One round of candidates k0 .. k0 + C - 1.  Recount method: `block` candidates per workgroup
@@ -302,10 +303,21 @@ struct StepLaunch {
   ProposeArgs draw;
   int64_t *S0;
   // records method, ranked draws, K > 64: every round-0 workgroup merges the ranking's workgroup
-  // lists (rank_keys + kRankMax) itself, and one writes the order (order_rw) for the later rounds
+  // lists (rank_keys + kRankMax) itself, and one writes the order (order_rw) for the later rounds;
+  // round 0 adds its sums into S0 and also does the step's resets (ctl, S_acc, the temperature
+  // T_cur from T_sched[step - T_base] or T_value), so that its draws may come from the previous
+  // step's end
   bool fuse_rank;
   const uint64_t *rank_keys;
   int32_t *order_rw;
+  double *T_cur;
+  const double *T_sched;
+  int64_t T_base;
+  double T_value;
+  // ranked records chains: the end of this step also draws the next step (next: its arguments,
+  // into the other half of the double-buffered cand / slot / U)
+  bool draw_next;
+  ProposeArgs next;
 };
 
 hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
@@ -375,7 +387,9 @@ hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 // Placement-state records: build ones and records from the packed image; end a step (its
 // decision and upkeep, and the accepted interchange applied to ones and records) in one launch.
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream);
-hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, hipStream_t stream);
+// next (ranked chains): the next step's draws, made in the same launch; nullptr: none.
+hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, const ProposeArgs *next,
+                               hipStream_t stream);
 // Update workgroups of the records method's step end on a device of `cus` compute units.
 int rec_end_workgroups(const RecGeo &g, int cus);
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
