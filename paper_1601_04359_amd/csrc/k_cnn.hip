@@ -140,7 +140,8 @@ __global__ void k_cnn_head_fwd(const uint16_t *__restrict__ A3, const float *__r
 constexpr int kScoreTile = 16;
 
 // One 3x3 layer on LDS regions: `in` is a (wout + 2)^2 region with cin (4 or 16) channels per
-// pixel, `out` the wout^2 region inside it with 16; 4 waves take 16-pixel tiles in turn.
+// pixel, `out` the wout^2 region inside it with 16; the workgroup's waves take 16-pixel tiles in
+// turn.
 __device__ __forceinline__ void conv_region(const uint16_t *in, int cin, uint16_t *out, int wout,
                                             const uint16_t *__restrict__ Wf,
                                             const float *__restrict__ bias) {
@@ -152,7 +153,8 @@ __device__ __forceinline__ void conv_region(const uint16_t *in, int cin, uint16_
   for (int t = 0; t < 9; ++t)
     Bw[t] = *reinterpret_cast<const s4v *>(Wf + (t * 16 + m) * 16 + 4 * g);
   const float bco = bias[m];
-  for (int tile = wave; tile * 16 < nout; tile += 4) {
+  const int nwaves = (int)(blockDim.x >> 6);
+  for (int tile = wave; tile * 16 < nout; tile += nwaves) {
     const int i = tile * 16 + m;
     const bool pin = i < nout;
     const int ry = pin ? i / wout : 0, rx = pin ? i - ry * wout : 0;
@@ -172,7 +174,9 @@ __device__ __forceinline__ void conv_region(const uint16_t *in, int cin, uint16_
   }
 }
 
-__global__ void __launch_bounds__(256)
+// 1024 threads: each layer's tiles spread over 16 waves (four per SIMD), so that the chains of
+// MFMA and LDS latency of one wave overlap those of the others.
+__global__ void __launch_bounds__(1024)
 k_cnn_score(const uint64_t *__restrict__ bits, int W, int H, const uint16_t *__restrict__ Wf,
             const float *__restrict__ prm, const float *__restrict__ W4bf,
             float *__restrict__ S) {
@@ -486,7 +490,7 @@ hipError_t cnn_score(const CnnBufs &B, const uint64_t *bits, int W, int H, float
                      hipStream_t s) {
   const dim3 grid((unsigned)((W + kScoreTile - 1) / kScoreTile),
                   (unsigned)((H + kScoreTile - 1) / kScoreTile));
-  hipLaunchKernelGGL(k_cnn_score, grid, dim3(256), 0, s, bits, W, H, B.Wf, B.prm, B.W4bf, S);
+  hipLaunchKernelGGL(k_cnn_score, grid, dim3(1024), 0, s, bits, W, H, B.Wf, B.prm, B.W4bf, S);
   return hipGetLastError();
 }
 

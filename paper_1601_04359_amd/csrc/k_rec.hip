@@ -110,66 +110,160 @@ struct Planes {
 
 }  // namespace
 
-// ones(v, x) for every vector and placement: lanes over placements, one vector per block row.
+// Records build, in three launches.  (1) k_rec_ext: the packed image (and the position set)
+// as rows of 32-bit words extended periodically (bit x = pixel x mod W, ew words per row).
+// (2) k_rec_cond: per vector and 32 consecutive placements x of a row, the count ones(v, x) in
+// bit slices (one 32-bit word per count bit, a ripple add per path pixel), from which the ones
+// bytes and the plane conditions follow (ones = 0, 1, n, n + 1); the conditions are stored as
+// rows of cw words extended periodically past W, so that any 64 placements starting below W
+// are three consecutive words.  (3) k_rec_fill: the record bit j = off(v) + k of pixel q is the
+// condition of placement q - p_k, so for 64 consecutive pixels of a row lane t (bit j0 + t) reads
+// the 64-bit window of its vector's condition row that starts at q0 - p_t; a bit transpose
+// across the wave (lanes t x bits over q into lanes q x bits over t) then gives each pixel's 64
+// record bits, which are staged in LDS and written per pixel as contiguous dwords.
 __global__ void __launch_bounds__(256)
-k_rec_ones(RecGeo g, const uint64_t *__restrict__ bits) {
-  const int v = blockIdx.x;
-  const int64_t N = (int64_t)g.W * g.H;
-  const int64_t x = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  if (x >= N) return;
-  const int4 m = g.meta[v];
+k_rec_ext(RecGeo g, const uint64_t *__restrict__ bits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsrc = g.sample ? 2 : 1;
+  if (i >= g.H * g.ew * nsrc) return;
+  const int src = i / (g.H * g.ew), r = i - src * g.H * g.ew;
+  const int y = r / g.ew, w = r - y * g.ew;
+  const uint64_t *img = src ? g.sample : bits;
   const int wpr = (g.W + 63) >> 6;
-  const int py = (int)(x / g.W), px = (int)(x - (int64_t)py * g.W);
-  int o = 0;
-  for (int k = 0; k <= m.y; ++k) {
-    const int32_t p = g.pix[m.x + k];
-    o += image_bit(bits, wpr, wrapi(px + pix_dx(p), g.W), wrapi(py + pix_dy(p), g.H));
+  uint32_t o = 0;
+  for (int b = 0; b < 32; ++b) {
+    int x = 32 * w + b;
+    while (x >= g.W) x -= g.W;
+    o |= (uint32_t)image_bit(img, wpr, x, y) << b;
   }
-  if (g.sample && !image_bit(g.sample, wpr, px, py)) o += 128;  // outside the position set
-  g.ones[(size_t)v * g.oplane + ones_at(g, px, py)] = (uint8_t)o;
+  g.ext[(size_t)src * g.H * g.ew + (size_t)y * g.ew + w] = o;
 }
 
-// Records of 64 pixels over one 32-dword tile of the record per workgroup (the waves of the
-// workgroup take the tile's dwords in turn), staged in LDS so that each pixel's record is written with contiguous stores.  Per record
-// bit j the tables give vbit[j] = (v << 8) | n and pix[j] = p_k, independent scalar loads.
+// The 32 bits starting at bit s (0 <= s < W) of an extended row.
+__device__ __forceinline__ uint32_t ext_window32(const uint32_t *row, int s) {
+  return __builtin_amdgcn_alignbit(row[(s >> 5) + 1], row[s >> 5], (uint32_t)(s & 31));
+}
+
+// Bit-sliced count c (nb slices) equal to K, per bit position.
+__device__ __forceinline__ uint32_t count_eq(const uint32_t (&c)[8], int nb, int K) {
+  uint32_t e = ~0u;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+    if (b < nb) e &= ((K >> b) & 1) ? c[b] : ~c[b];
+  return ((K >> nb) == 0) ? e : 0u;
+}
+
+// Lanes over (row y, word xw) of vector blockIdx.x: placements x = 32 xw + i (taken mod W).
 template <unsigned MASK>
 __global__ void __launch_bounds__(256)
-k_rec_build(RecGeo g) {
+k_rec_cond(RecGeo g) {
   using P = Planes<MASK>;
-  const int32_t *__restrict__ vbit = g.vbit;
+  const int v = blockIdx.x;
+  const int t = blockIdx.y * blockDim.x + threadIdx.x;
+  if (t >= g.H * g.cw) return;
+  const int y = t / g.cw, xw = t - y * g.cw;
+  const int4 m = g.meta[v];
+  const int n = m.y, nb = 32 - __clz(n + 1);  // count bits for 0 .. n + 1 (n <= 254)
+  uint32_t c[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) c[b] = 0u;
+  for (int j = 0; j <= n; ++j) {
+    const int32_t p = g.pix[m.x + j];
+    const int yy = wrapi(y + pix_dy(p), g.H);
+    int s = 32 * xw + pix_dx(p);
+    while (s < 0) s += g.W;
+    while (s >= g.W) s -= g.W;
+    uint32_t carry = ext_window32(g.ext + (size_t)yy * g.ew, s);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b < nb) {
+        const uint32_t t2 = c[b] & carry;
+        c[b] ^= carry;
+        carry = t2;
+      }
+    }
+  }
+  int s0 = 32 * xw;
+  while (s0 >= g.W) s0 -= g.W;
+  const uint32_t in = g.sample ? ext_window32(g.ext + (size_t)(g.H + y) * g.ew, s0) : ~0u;
+#pragma unroll
+  for (int pl = 0; pl < P::n; ++pl) {
+    const int K = P::side(pl) == 0 ? (P::phase(pl) ? n + 1 : 1) : (P::phase(pl) ? n : 0);
+    g.cond[((size_t)(v * P::n + pl) * g.H + y) * g.cw + xw] = count_eq(c, nb, K) & in;
+  }
+  // ones bytes of the placements below W (outside the position set: + 128, n <= 126)
+  for (int i = 0; i < 32; ++i) {
+    const int x = 32 * xw + i;
+    if (x >= g.W) break;
+    int o = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if (b < nb) o |= (int)((c[b] >> i) & 1u) << b;
+    if (!((in >> i) & 1u)) o += 128;
+    g.ones[(size_t)v * g.oplane + ones_at(g, x, y)] = (uint8_t)o;
+  }
+}
+
+// x's 64 bits transposed across the wave (lane i gets bit i of every lane, lane t in bit t).
+// Every lane must be active.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
+  auto step = [&](uint64_t y, int S, uint64_t msk) {
+    return (lane & S) ? ((x & ~msk) | ((y & ~msk) >> S)) : ((x & msk) | ((y & msk) << S));
+  };
+  x = step(xor_lane64<32>(x), 32, 0x00000000FFFFFFFFull);
+  x = step(xor_lane64<16>(x), 16, 0x0000FFFF0000FFFFull);
+  x = step(xor_lane64<8>(x), 8, 0x00FF00FF00FF00FFull);
+  x = step(xor_lane64<4>(x), 4, 0x0F0F0F0F0F0F0F0Full);
+  x = step(xor_lane64<2>(x), 2, 0x3333333333333333ull);
+  x = step(xor_lane64<1>(x), 1, 0x5555555555555555ull);
+  return x;
+}
+
+// Workgroup (row segment of 64 pixels, 32-dword tile of the record): each wave takes 64-bit
+// chunks of the tile in turn.
+template <unsigned MASK>
+__global__ void __launch_bounds__(256)
+k_rec_fill(RecGeo g) {
+  using P = Planes<MASK>;
   __shared__ uint32_t tile[P::n][64][33];
-  const int64_t N = (int64_t)g.W * g.H;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t q0 = (int64_t)blockIdx.x * 64;
-  const int64_t q = q0 + lane;
-  const bool valid = q < N;
-  const int qy = valid ? (int)(q / g.W) : 0, qx = valid ? (int)(q - (int64_t)qy * g.W) : 0;
+  const int nseg = (g.W + 63) >> 6;
+  const int qy = (int)blockIdx.x / nseg, qx0 = ((int)blockIdx.x - qy * nseg) * 64;
   const int w0 = blockIdx.y * 32;
   const int nw = min(32, g.Rw - w0);
   const int nwaves = (int)(blockDim.x >> 6);
-  for (int wd = wv; wd < nw; wd += nwaves) {
-    uint32_t acc[P::n];
+  for (int ch = wv; 2 * ch < nw; ch += nwaves) {
+    const int j = (w0 + 2 * ch) * 32 + lane;  // this lane's record bit
+    uint64_t seg[P::n];
 #pragma unroll
-    for (int pl = 0; pl < P::n; ++pl) acc[pl] = 0u;
-    const int jb = (w0 + wd) * 32;
-    const int tn = min(32, g.Mc - jb);
-    for (int t = 0; t < tn; ++t) {
-      const int vn = vbit[jb + t];
-      const int32_t p = g.pix[jb + t];
-      const int v = vn >> 8, n = vn & 255;
-      const int xx = wrapi(qx - pix_dx(p), g.W), yy = wrapi(qy - pix_dy(p), g.H);
-      const int o = valid ? (int)g.ones[(size_t)v * g.oplane + ones_at(g, xx, yy)] : -1;
+    for (int pl = 0; pl < P::n; ++pl) seg[pl] = 0ull;
+    if (j < g.Mc) {
+      const int v = g.vbit[j] >> 8;
+      const int32_t p = g.pix[j];
+      const int yy = wrapi(qy - pix_dy(p), g.H);
+      int x0 = qx0 - pix_dx(p);
+      while (x0 < 0) x0 += g.W;
+      while (x0 >= g.W) x0 -= g.W;
+      const int sh = x0 & 31;
 #pragma unroll
-      for (int pl = 0; pl < P::n; ++pl)
-        acc[pl] |= (plane_cond(P::side(pl), P::phase(pl), o, n) ? 1u : 0u) << t;
+      for (int pl = 0; pl < P::n; ++pl) {
+        const uint32_t *r = g.cond + ((size_t)(v * P::n + pl) * g.H + yy) * g.cw + (x0 >> 5);
+        const uint32_t r0 = r[0], r1 = r[1], r2 = r[2];
+        seg[pl] = ((uint64_t)__builtin_amdgcn_alignbit(r2, r1, (uint32_t)sh) << 32) |
+                  __builtin_amdgcn_alignbit(r1, r0, (uint32_t)sh);
+      }
     }
 #pragma unroll
-    for (int pl = 0; pl < P::n; ++pl) tile[pl][lane][wd] = acc[pl];
+    for (int pl = 0; pl < P::n; ++pl) {
+      const uint64_t tr = wave_transpose64(seg[pl], lane);  // lane = pixel qx0 + lane
+      tile[pl][lane][2 * ch] = (uint32_t)tr;
+      tile[pl][lane][2 * ch + 1] = (uint32_t)(tr >> 32);
+    }
   }
   __syncthreads();
   // write out: wave wv writes pixels wv, wv + nwaves, ...; lanes over the tile's dwords
-  for (int pq = wv; pq < 64 && q0 + pq < N; pq += nwaves) {
-    uint32_t *R = g.rec + (size_t)(q0 + pq) * g.rstride + w0;
+  for (int pq = wv; pq < 64 && qx0 + pq < g.W; pq += nwaves) {
+    uint32_t *R = g.rec + ((size_t)qy * g.W + qx0 + pq) * g.rstride + w0;
     if (lane < nw)
 #pragma unroll
       for (int pl = 0; pl < P::n; ++pl) R[(size_t)pl * g.Rw + lane] = tile[pl][pq][lane];
@@ -858,16 +952,19 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd, ProposeArgs nx) {
   }
 
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream) {
-  const int64_t N = (int64_t)g.W * g.H;
-  hipLaunchKernelGGL(k_rec_ones, dim3((unsigned)g.nv, (unsigned)((N + 255) / 256)), dim3(256), 0,
-                     stream, g, bits);
+  const int next = g.H * g.ew * (g.sample ? 2 : 1);
+  hipLaunchKernelGGL(k_rec_ext, dim3((unsigned)((next + 255) / 256)), dim3(256), 0, stream, g, bits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((g.Rw + 31) / 32));
-#define LPF_BUILD(M) hipLaunchKernelGGL(k_rec_build<M>, grid, dim3(256), 0, stream, g)
+  const dim3 gc((unsigned)g.nv, (unsigned)((g.H * g.cw + 255) / 256));
+  const dim3 gf((unsigned)(g.H * ((g.W + 63) / 64)), (unsigned)((g.Rw + 31) / 32));
+#define LPF_BUILD(M)                                                              \
+  hipLaunchKernelGGL(k_rec_cond<M>, gc, dim3(256), 0, stream, g);                 \
+  if ((e = hipGetLastError()) == hipSuccess)                                      \
+    hipLaunchKernelGGL(k_rec_fill<M>, gf, dim3(256), 0, stream, g);
   LPF_REC_MASK_SWITCH(g.mask, LPF_BUILD)
 #undef LPF_BUILD
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 // One wave per (vector, side) pair when that many workgroups are resident at once; otherwise

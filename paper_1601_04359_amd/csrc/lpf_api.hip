@@ -227,7 +227,7 @@ struct lpf_anneal_s {
   int rec_choice = -1;  // resolved method (1 records, 0 recount), -1 until first needed
   bool rec_ready = false, rec_valid = false;
   RecGeo rg{};
-  DevBuf rmeta, rpix, rvbit, remask, rec, ones;
+  DevBuf rmeta, rpix, rvbit, remask, rec, ones, rext, rcond;
   // learned proposals: a network scoring the current cell, or a caller's score field
   lpf_cnn net = nullptr;
   const float *scores_ext = nullptr;
@@ -844,7 +844,9 @@ bool records_fit(lpf_anneal a, int64_t *bytes, std::string *why) {
     for (int64_t i = 0; i < nv; ++i) Mc += std::max(std::abs((int)can[2 * i]), (int)can[2 * i + 1]) + 1;
   }
   const int64_t Rw = (Mc + 31) / 32 + 2;  // two padding words per plane
-  const int64_t b = N * 2 * nph * Rw * 4 + nv * ((int64_t)((a->W + 7) / 8) * ((a->H + 7) / 8) * 64);
+  // records, ones, and the build's condition rows
+  const int64_t b = N * 2 * nph * Rw * 4 + nv * ((int64_t)((a->W + 7) / 8) * ((a->H + 7) / 8) * 64) +
+                    nv * 2 * nph * (int64_t)a->H * ((a->W - 1) / 32 + 3) * 4;
   if (bytes) *bytes = b;
   if (std::max(a->cx, a->cy) > 254) {
     if (why) *why = "cutoff above 254 (path counts are bytes)";
@@ -933,11 +935,15 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, a->ctx->dev);
     g.end_wgs = rec_end_workgroups(g, cus);
+    g.ew = (a->W + 31) / 32 + 2;
+    g.cw = (a->W - 1) / 32 + 3;
     const int64_t N = (int64_t)a->W * a->H;
     if ((e = a->rmeta.ensure(sizeof(int4) * meta.size())) != hipSuccess ||
         (e = a->rpix.ensure(sizeof(int32_t) * pix.size())) != hipSuccess ||
         (e = a->rvbit.ensure(sizeof(int32_t) * vbit.size())) != hipSuccess ||
         (e = a->remask.ensure(sizeof(uint64_t) * emask.size())) != hipSuccess ||
+        (e = a->rext.ensure(sizeof(uint32_t) * (size_t)g.H * g.ew * (a->sample ? 2 : 1))) != hipSuccess ||
+        (e = a->rcond.ensure(sizeof(uint32_t) * (size_t)nv * 2 * g.nph * g.H * g.cw)) != hipSuccess ||
         (e = a->rec.ensure(sizeof(uint32_t) * (size_t)(N * g.rstride))) != hipSuccess ||
         (e = a->ones.ensure((size_t)(nv * g.oplane))) != hipSuccess)
       return hip_fail(e, "anneal: records allocation");
@@ -951,6 +957,8 @@ lpf_status setup_records(lpf_anneal a, hipStream_t s) {
     g.pix = (const int32_t *)a->rpix.p;
     g.vbit = (const int32_t *)a->rvbit.p;
     g.emask = (const uint64_t *)a->remask.p;
+    g.ext = (uint32_t *)a->rext.p;
+    g.cond = (uint32_t *)a->rcond.p;
     g.rec = (uint32_t *)a->rec.p;
     g.ones = (uint8_t *)a->ones.p;
     a->rg = g;
@@ -2015,6 +2023,8 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->rmeta.release();
     a->rpix.release();
     a->remask.release();
+    a->rext.release();
+    a->rcond.release();
     a->rvbit.release();
     a->rec.release();
     a->ones.release();

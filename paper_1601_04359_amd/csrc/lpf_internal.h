@@ -225,6 +225,11 @@ struct RecGeo {
   // interchange, so it never counts.
   const uint64_t *sample;
   int end_wgs;          // update workgroups of the step's end (rec_end_workgroups)
+  // build scratch: the image (and position set) as periodically extended rows of ew 32-bit
+  // words (ew = ceil(W / 32) + 2), and per vector and plane the placement conditions as rows of
+  // cw words extended periodically past W (cw = ceil(W / 32) + 2 rounded as (W - 1) / 32 + 3)
+  uint32_t *ext, *cond;
+  int ew, cw;
   // per vector v with 0 < n < 64, at 2 off(v) - v + t (t = 0 .. 2n): the path indices k whose
   // minor error term (2 k e + n) mod 2n is at least t (e the minor extent), bit k
   const uint64_t *emask;
