@@ -867,13 +867,13 @@ __device__ __forceinline__ void upd_long(const RecGeo &g, int a, int b, int v, i
 // what the device holds at once (a second round of workgroups would repeat the whole latency
 // chain of decision, load and flips).
 // PRE: the wave's first PRE (vector, side) pairs are prefetched (1 when every pair has its own
-// wave).  Workgroups past nupd (ranked chains) draw the next step with the arguments nx:
+// wave).  DRAW: workgroups past nupd (ranked chains) draw the next step with the arguments *nxp:
 // candidates, rank keys and each 256-draw workgroup's best 64, from the pixel lists as this
 // step's interchange leaves them (draw_candidate_at), so that the next step needs no launch of
 // its draws.
-template <unsigned MASK, int PRE>
+template <unsigned MASK, int PRE, bool DRAW>
 __global__ void __launch_bounds__(256)
-k_rec_step_end(RecGeo g, FinalArgs f, int nupd, ProposeArgs nx) {
+k_rec_step_end(RecGeo g, FinalArgs f, int nupd, const ProposeArgs *__restrict__ nxp) {
   __shared__ int s_first;
   __shared__ uint64_t sl[2][64];
   // the wave's first PRE (vector, side) pairs: vectors and path pixels do not depend on the
@@ -896,9 +896,10 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd, ProposeArgs nx) {
   const int4 c4 = *reinterpret_cast<const int4 *>(f.ctl);
   const int ks0 = c4.y;
   const int ks = step_choice(f, ks0, &s_first);
-  if ((int)blockIdx.x > nupd) {
+  if (DRAW && (int)blockIdx.x > nupd) {
     const int2 sab = ks < 0 ? make_int2(-1, -1) : ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
     const int db = (int)blockIdx.x - nupd - 1, k = db * 256 + (int)threadIdx.x;
+    const ProposeArgs &nx = *nxp;
     int a, b;
     next_draw(nx, f.ctl->next_step, k, sab.x, sab.y, a, b);
     if (nx.rank_score && db * 256 < min(nx.K, kRankMax)) {
@@ -951,6 +952,21 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd, ProposeArgs nx) {
     default: CALL(3u); break;                 \
   }
 
+// The two parities' arguments of the next-step draws into device memory (kernel arguments are
+// copied at the launch, so the host structs need not outlive it).
+__global__ void k_rec_set_next(ProposeArgs *__restrict__ dst, ProposeArgs a0, ProposeArgs a1) {
+  if (threadIdx.x == 0) {
+    dst[0] = a0;
+    dst[1] = a1;
+  }
+}
+
+hipError_t launch_rec_set_next(ProposeArgs *dst, const ProposeArgs &a0, const ProposeArgs &a1,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_rec_set_next, dim3(1), dim3(64), 0, stream, dst, a0, a1);
+  return hipGetLastError();
+}
+
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream) {
   const int next = g.H * g.ew * (g.sample ? 2 : 1);
   hipLaunchKernelGGL(k_rec_ext, dim3((unsigned)((next + 255) / 256)), dim3(256), 0, stream, g, bits);
@@ -977,7 +993,7 @@ int rec_end_workgroups(const RecGeo &g, int cus) {
   int per_cu = 0;
   hipError_t e = hipSuccess;
 #define LPF_OCC(M) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M, 1>, 256, 0)
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rec_step_end<M, 1, true>, 256, 0)
   LPF_REC_MASK_SWITCH(g.mask, LPF_OCC)
 #undef LPF_OCC
   // the step's upkeep workgroup runs beside the update workgroups, and up to 64 workgroups of
@@ -987,23 +1003,26 @@ int rec_end_workgroups(const RecGeo &g, int cus) {
 }
 
 hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, const ProposeArgs *next,
-                               hipStream_t stream) {
+                               int ndraw, hipStream_t stream) {
   const int nupd = g.end_wgs > 0 ? g.end_wgs : std::min((2 * g.nv + 3) / 4, 1024);
   // pairs per wave: with more than one, the first three are prefetched together
   const bool one = 2 * g.nv <= 4 * nupd;
-  ProposeArgs nx{};
-  int ndraw = 0;
-  if (next) {
-    nx = *next;
-    ndraw = (nx.K + 255) / 256;
-  }
+  const ProposeArgs *nx = next;
+  if (!next) ndraw = 0;
   const dim3 grid((unsigned)(nupd + 1 + ndraw));
-#define LPF_END(M)                                                                             \
+#define LPF_END_D(M, D)                                                                       \
   if (one)                                                                                     \
-    hipLaunchKernelGGL((k_rec_step_end<M, 1>), grid, dim3(256), 0, stream, g, f, nupd, nx);  \
+    hipLaunchKernelGGL((k_rec_step_end<M, 1, D>), grid, dim3(256), 0, stream, g, f, nupd, nx); \
   else                                                                                         \
-    hipLaunchKernelGGL((k_rec_step_end<M, 3>), grid, dim3(256), 0, stream, g, f, nupd, nx);
+    hipLaunchKernelGGL((k_rec_step_end<M, 3, D>), grid, dim3(256), 0, stream, g, f, nupd, nx);
+#define LPF_END(M)       \
+  if (nx) {              \
+    LPF_END_D(M, true)   \
+  } else {               \
+    LPF_END_D(M, false)  \
+  }
   LPF_REC_MASK_SWITCH(g.mask, LPF_END)
+#undef LPF_END_D
 #undef LPF_END
   return hipGetLastError();
 }

@@ -225,7 +225,9 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t stream) {
   f.S0 = L.fuse_draw || L.fuse_rank ? L.S0 : nullptr;
   // records: the upkeep and the update of ones and records share one launch (with the next
   // step's draws in ranked chains)
-  if (L.records && !L.s2) return launch_rec_step_end(L.rg, f, L.draw_next ? &L.next : nullptr, stream);
+  if (L.records && !L.s2)
+    return launch_rec_step_end(L.rg, f, L.draw_next ? L.next : nullptr,
+                               L.draw_next ? (L.K + 255) / 256 : 0, stream);
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(1024), 0, stream, f);
   return hipGetLastError();
 }

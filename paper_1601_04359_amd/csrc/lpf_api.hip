@@ -240,6 +240,11 @@ struct lpf_anneal_s {
   uint64_t host_step = 0;  // host copy of the step counter (steps enqueued so far)
   bool predrawn = false;   // ranked chain: the next step's draws are made by the last step's end
   int predrawn_K = 0;      // ... for that many candidates
+  // arguments of those draws per parity of the drawn step, in device memory (nxargs), and the
+  // host copies they were made from (nx_ok: uploaded)
+  DevBuf nxargs;
+  ProposeArgs nx_host[2];
+  bool nx_ok[2] = {false, false};
   hipStream_t cap = nullptr;  // private stream for capturing runs of steps
 };
 
@@ -813,6 +818,31 @@ lpf_status draw_candidates(lpf_anneal a, int K, int proposal, hipStream_t s,
   if ((e = launch_propose(p, s)) != hipSuccess)
     return hip_fail(e, "anneal: propose");
   return LPF_OK;
+}
+
+// The arguments of a ranked step's draws made by the previous step's end, drawing into half h
+// of the candidate buffers (from the step's own arguments; no resets).
+ProposeArgs next_args_of(const ProposeArgs &p, lpf_anneal a, int K, int h) {
+  ProposeArgs q = p;
+  q.cand = (int2 *)a->cand.p + (size_t)h * K;
+  q.slot = (int2 *)a->slot.p + (size_t)h * K;
+  q.U = (double *)a->U.p + (size_t)h * K;
+  q.S_acc = nullptr;
+  q.ctl = nullptr;
+  q.T_cur = nullptr;
+  q.pre = nullptr;
+  q.T_sched = nullptr;
+  q.T_base = 0;
+  q.T = 0.0;
+  return q;
+}
+
+bool same_next_args(const ProposeArgs &x, const ProposeArgs &y) {
+  return x.st == y.st && x.bits == y.bits && x.W == y.W && x.H == y.H && x.seed == y.seed &&
+         x.K == y.K && x.proposal == y.proposal && x.cw1 == y.cw1 && x.cw0 == y.cw0 &&
+         x.eps == y.eps && x.cand == y.cand && x.U == y.U && x.slot == y.slot &&
+         x.rank_score == y.rank_score && x.rank_keys == y.rank_keys &&
+         x.rank_lists == y.rank_lists;
 }
 
 // Candidate rounds of a step: 64, then the rest in rounds of at most 8192.  A step whose first
@@ -1847,16 +1877,12 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
     L.order = ord;
     // the end of this step draws the next one, unless that one re-scores the cell first
     L.draw_next = allow_next && L.fuse_rank && !(a->learn_age == 0 || a->learn_age >= a->refresh);
-    if (L.draw_next) {
-      const size_t nhalf = (size_t)((a->host_step + 1) & 1) * (size_t)K;
-      L.next = args;
-      L.next.cand = (int2 *)a->cand.p + nhalf;
-      L.next.slot = (int2 *)a->slot.p + nhalf;
-      L.next.U = (double *)a->U.p + nhalf;
-      L.next.S_acc = nullptr;
-      L.next.ctl = nullptr;
-      L.next.T_cur = nullptr;
-      L.next.pre = nullptr;
+    if (L.draw_next) {  // with the arguments prepare_next_args uploaded for this configuration
+      const int nh = (int)((a->host_step + 1) & 1);
+      if (a->nx_ok[nh] && same_next_args(next_args_of(args, a, K, nh), a->nx_host[nh]))
+        L.next = (const ProposeArgs *)a->nxargs.p + nh;
+      else
+        L.draw_next = false;
     }
   }
   a->predrawn = L.draw_next;
@@ -1878,6 +1904,34 @@ lpf_status step_enqueue(lpf_anneal a, int K, int proposal, StepLaunch &L, DeltaP
   return LPF_OK;
 }
 
+// Uploads (when they changed) the arguments of the next-step draws of a ranked records chain, so
+// that a step's end can draw the next step; outside any capture.
+lpf_status prepare_next_args(lpf_anneal a, int K, int proposal, const StepLaunch &L, bool rec,
+                             hipStream_t s) {
+  if (!(proposal == LPF_PROP_LEARNED && a->rank && rec && L.rounds.size() >= 2 &&
+        L.rounds[0].C == 64))
+    return LPF_OK;
+  ProposeArgs none{}, p{};
+  lpf_status st = draw_candidates(a, K, proposal, s, nullptr, nullptr, nullptr, 0, 0.0, nullptr,
+                                  true, &none, &p, false);
+  if (st != LPF_OK) return st;
+  bool dirty = false;
+  for (int h = 0; h < 2; ++h) {
+    const ProposeArgs q = next_args_of(p, a, K, h);
+    if (!a->nx_ok[h] || !same_next_args(q, a->nx_host[h])) {
+      a->nx_host[h] = q;
+      dirty = true;
+    }
+  }
+  if (!dirty) return LPF_OK;
+  hipError_t e;
+  if ((e = a->nxargs.ensure(2 * sizeof(ProposeArgs))) != hipSuccess ||
+      (e = launch_rec_set_next((ProposeArgs *)a->nxargs.p, a->nx_host[0], a->nx_host[1], s)) != hipSuccess)
+    return hip_fail(e, "anneal: next-step draw arguments");
+  a->nx_ok[0] = a->nx_ok[1] = true;
+  return LPF_OK;
+}
+
 }  // namespace
 
 lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_result *out,
@@ -1895,6 +1949,7 @@ lpf_status anneal_step(lpf_anneal a, int K, int proposal, double T, lpf_step_res
   if ((st = step_setup(a, K, proposal, s, L, plan, rec)) != LPF_OK) return st;
   // the previous call's end drew this step when it was a ranked step with as many candidates
   if (a->predrawn_K != K || proposal != LPF_PROP_LEARNED) a->predrawn = false;
+  if ((st = prepare_next_args(a, K, proposal, L, rec, s)) != LPF_OK) return st;
   return step_enqueue(a, K, proposal, L, plan, rec, nullptr, 0, T, out, -1, s, true);
 }
 
@@ -1928,6 +1983,7 @@ lpf_status lpf_anneal_run(lpf_anneal a, int K, int proposal, const double *T_sch
     return age;
   };
   a->predrawn = false;
+  if ((st = prepare_next_args(a, K, proposal, L, rec, s)) != LPF_OK) return st;
   if (graphable && nsteps >= kGraphSteps) {
     if (!a->cap && (e = hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "lpf_anneal_run: capture stream");
@@ -2024,6 +2080,7 @@ void lpf_anneal_destroy(lpf_anneal a) {
     a->rpix.release();
     a->remask.release();
     a->rext.release();
+    a->nxargs.release();
     a->rcond.release();
     a->rvbit.release();
     a->rec.release();

@@ -319,10 +319,10 @@ struct StepLaunch {
   const double *T_sched;
   int64_t T_base;
   double T_value;
-  // ranked records chains: the end of this step also draws the next step (next: its arguments,
-  // into the other half of the double-buffered cand / slot / U)
+  // ranked records chains: the end of this step also draws the next step (next: its arguments in
+  // device memory, drawing into the other half of the double-buffered cand / slot / U)
   bool draw_next;
-  ProposeArgs next;
+  const ProposeArgs *next;
 };
 
 hipError_t launch_ext3(const uint64_t *bits, int W, int H, const DeltaGeo &geo, uint32_t *E,
@@ -392,9 +392,12 @@ hipError_t launch_energy(const StepLaunch &L, double *de, hipStream_t stream);
 // Placement-state records: build ones and records from the packed image; end a step (its
 // decision and upkeep, and the accepted interchange applied to ones and records) in one launch.
 hipError_t launch_rec_build(const RecGeo &g, const uint64_t *bits, hipStream_t stream);
-// next (ranked chains): the next step's draws, made in the same launch; nullptr: none.
-hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, const ProposeArgs *next,
+hipError_t launch_rec_set_next(ProposeArgs *dst, const ProposeArgs &a0, const ProposeArgs &a1,
                                hipStream_t stream);
+// next (ranked chains, device memory): the arguments of the next step's draws, made in the same
+// launch by ndraw extra workgroups; nullptr: none.
+hipError_t launch_rec_step_end(const RecGeo &g, const FinalArgs &f, const ProposeArgs *next,
+                               int ndraw, hipStream_t stream);
 // Update workgroups of the records method's step end on a device of `cus` compute units.
 int rec_end_workgroups(const RecGeo &g, int cus);
 hipError_t launch_rec_round(const StepLaunch &L, const RoundPlan &r, bool decide,
