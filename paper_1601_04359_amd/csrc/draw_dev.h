@@ -62,6 +62,16 @@ __device__ __forceinline__ int uniform_slot(uint64_t r, int n) {
 // Tag of step `step` in ProposeArgs::pre (never 0, the value of a cleared entry).
 __device__ __forceinline__ int pre_tag(uint64_t step) { return (int)(step & 0x3fffffffull) + 1; }
 
+// Pixels a (read from the phase-1 list) and b (from the phase-0 list) as the lists hold them
+// after the interchange (sa, sb) whose writes a read may or may not have seen (sa < 0: none):
+// see draw_candidate_at.
+__device__ __forceinline__ void after_interchange(int &a, int &b, int sa, int sb) {
+  if (sa >= 0) {
+    a = a == sa || a == sb ? sb : a;
+    b = b == sb || b == sa ? sa : b;
+  }
+}
+
 // Candidate k of step `step`: ctr = {step, k, 0, 0}, key = {seed, 0x6c7066}.
 // proposal 0: a, b uniform in the phase-1 / phase-0 lists; 1: as 0, void (a = b = -1) unless
 // both pixels are interfacial; 2 (learned): with probability eps (r3) as 0, otherwise a drawn
@@ -91,10 +101,7 @@ __device__ __forceinline__ void draw_candidate_at(const ProposeArgs &p, uint64_t
   }
   a = st->pos1[ia];
   b = st->pos0[ib];
-  if (sa >= 0) {
-    a = a == sa || a == sb ? sb : a;
-    b = b == sb || b == sa ? sa : b;
-  }
+  after_interchange(a, b, sa, sb);
   if (p.proposal == 1 && !(interfacial(p.bits, p.W, p.H, a) && interfacial(p.bits, p.W, p.H, b))) {
     a = -1;
     b = -1;
@@ -106,22 +113,6 @@ __device__ __forceinline__ void draw_candidate_at(const ProposeArgs &p, uint64_t
 __device__ __forceinline__ void draw_candidate(const ProposeArgs &p, int k, int &a, int &b,
                                                int &ia, int &ib, double &u) {
   draw_candidate_at(p, p.st->step, k, -1, -1, a, b, ia, ib, u);
-}
-
-// Draw k (< K) of step `step` into cand / slot / U, without the resets of propose_draw: the
-// next step's draws made in the launch that ends this step (sa, sb: this step's interchange, -1
-// when none; see draw_candidate_at).  a, b: the draw (-1 when k >= K).
-__device__ __forceinline__ void next_draw(const ProposeArgs &p, uint64_t step, int k, int sa,
-                                          int sb, int &a, int &b) {
-  a = -1;
-  b = -1;
-  if (k >= p.K) return;
-  int ia, ib;
-  double u;
-  draw_candidate_at(p, step, k, sa, sb, a, b, ia, ib, u);
-  p.cand[k] = make_int2(a, b);
-  p.slot[k] = make_int2(ia, ib);
-  p.U[k] = u;
 }
 
 // Draw k (< K) into cand / slot / U; also zeroes its energy sum (S_acc) and, for k = 0, the

@@ -895,13 +895,23 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd, const ProposeArgs *__restrict__ 
   // the control block: the upkeep is told not to)
   const int4 c4 = *reinterpret_cast<const int4 *>(f.ctl);
   const int ks0 = c4.y;
-  const int ks = step_choice(f, ks0, &s_first);
   if (DRAW && (int)blockIdx.x > nupd) {
-    const int2 sab = ks < 0 ? make_int2(-1, -1) : ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
-    const int db = (int)blockIdx.x - nupd - 1, k = db * 256 + (int)threadIdx.x;
+    // the draw does not depend on this step's decision, only its correction for the step's
+    // interchange does: the counter-based draw and its list reads go first
     const ProposeArgs &nx = *nxp;
-    int a, b;
-    next_draw(nx, f.ctl->next_step, k, sab.x, sab.y, a, b);
+    const int db = (int)blockIdx.x - nupd - 1, k = db * 256 + (int)threadIdx.x;
+    const bool in = k < nx.K;
+    int a = -1, b = -1, ia = 0, ib = 0;
+    double u = 0.0;
+    if (in) draw_candidate_at(nx, f.ctl->next_step, k, -1, -1, a, b, ia, ib, u);
+    const int ks = step_choice(f, ks0, &s_first);
+    const int2 sab = ks < 0 ? make_int2(-1, -1) : ks0 >= 0 ? make_int2(c4.z, c4.w) : f.cand[ks];
+    if (in) {
+      after_interchange(a, b, sab.x, sab.y);
+      nx.cand[k] = make_int2(a, b);
+      nx.slot[k] = make_int2(ia, ib);
+      nx.U[k] = u;
+    }
     if (nx.rank_score && db * 256 < min(nx.K, kRankMax)) {
       const bool ranked = k < min(nx.K, kRankMax);
       const uint64_t key = ranked ? rank_key(a, b, k, nx.rank_score) : 0ull;
@@ -910,6 +920,7 @@ k_rec_step_end(RecGeo g, FinalArgs f, int nupd, const ProposeArgs *__restrict__ 
     }
     return;
   }
+  const int ks = step_choice(f, ks0, &s_first);
   // counts += dL shared by all nupd + 1 workgroups (one term per thread at most sizes)
   step_counts(f, ks, (int)blockIdx.x, nupd + 1);
   if ((int)blockIdx.x == nupd) {
