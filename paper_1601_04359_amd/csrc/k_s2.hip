@@ -27,11 +27,6 @@ namespace lpf {
 
 // ------------------------------------------------------------------------ full evaluation
 
-__global__ void k_s2_zero(uint32_t *__restrict__ acc, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) acc[i] = 0;
-}
-
 // Phase-1 counts over start rows [y0, y0 + rb), y0 = blockIdx.y * rb, for the vector families of
 // group blockIdx.x (at most 64: one per lane), added into acc (integer atomics: the sum does not
 // depend on the order).  The workgroup's waves share the families and split the rows (wave w
@@ -153,11 +148,14 @@ __device__ __forceinline__ void canonical_vector(int64_t i, int cx, int cy, int 
 }
 
 // Output layout from the phase-1 sums: HALF counts[p][i]; GRID counts[p][dy+cy][dx+cx] with the
-// entry of -v equal to that of v (C(-v) = C(v) on a periodic image).
+// entry of -v equal to that of v (C(-v) = C(v) on a periodic image).  Also clears the other
+// accumulator (ncap entries) for the next call, so that no launch zeroes acc before the counts.
 __global__ void k_s2_finish(const uint32_t *__restrict__ acc, int64_t nv, int cx, int cy,
                             int64_t N, unsigned phase_mask, int layout,
-                            uint32_t *__restrict__ out) {
+                            uint32_t *__restrict__ out, uint32_t *__restrict__ clear,
+                            int64_t ncap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncap) clear[i] = 0;
   if (i >= nv) return;
   const uint32_t c1 = acc[i];
   const uint32_t c0 = (uint32_t)(N - 2 * (int64_t)acc[0] + (int64_t)c1);
@@ -180,10 +178,7 @@ __global__ void k_s2_finish(const uint32_t *__restrict__ acc, int64_t nv, int cx
 }
 
 hipError_t launch_s2_full(const S2Launch &L, hipStream_t stream) {
-  hipLaunchKernelGGL(k_s2_zero, dim3((unsigned)((L.nv + 255) / 256)), dim3(256), 0, stream, L.acc,
-                     L.nv);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
   const dim3 grid((unsigned)L.ngroups, (unsigned)L.nrb);
   const int q1 = (L.cx + 1) * (L.cy + 1);
 #define LPF_S2_FULL(JJ)                                                                        \
@@ -199,8 +194,10 @@ hipError_t launch_s2_full(const S2Launch &L, hipStream_t stream) {
   }
 #undef LPF_S2_FULL
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_s2_finish, dim3((unsigned)((L.nv + 255) / 256)), dim3(256), 0, stream,
-                     L.acc, L.nv, L.cx, L.cy, (int64_t)L.W * L.H, L.phase_mask, L.layout, L.out);
+  const int64_t nf = std::max(L.nv, L.ncap);
+  hipLaunchKernelGGL(k_s2_finish, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, stream,
+                     L.acc, L.nv, L.cx, L.cy, (int64_t)L.W * L.H, L.phase_mask, L.layout, L.out,
+                     L.clear, L.ncap);
   return hipGetLastError();
 }
 

@@ -198,6 +198,7 @@ struct lpf_ctx_s {
   std::map<std::string, struct BatchGraph *> batch_graphs;
   uint64_t batch_clock = 0;  // use counter of the cached batch graphs
   DevBuf ext, ext3, s2ext, s2acc, sext, rank_buf;
+  int s2half = 0;  // lpf_s2: which half of s2acc the next call accumulates into
   std::mutex mu;
   // shape override (autotuner): R, S, wpg, lds budget; 0 = automatic
   int force_R = 0, force_S = 0, force_wpg = 0, force_lds = 0;
@@ -1513,8 +1514,11 @@ lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
   if ((st = get_s2_plan(c, W, H, cx, cy, plan)) != LPF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  if ((e = c->s2acc.ensure((size_t)plan->nv * sizeof(uint32_t))) != hipSuccess)
+  // two accumulators of ncap entries, zero on (re)allocation; each call clears the one it does
+  // not use for the next
+  if ((e = ensure_zeroed(c->s2acc, 2 * (size_t)plan->nv * sizeof(uint32_t), s)) != hipSuccess)
     return hip_fail(e, "lpf_s2: scratch");
+  const int64_t ncap = (int64_t)(c->s2acc.bytes / (2 * sizeof(uint32_t)));
   S2Launch L{};
   L.E = reinterpret_cast<const uint32_t *>(bits);  // the kernel extends the rows as it stages them
   L.W = W;
@@ -1533,11 +1537,14 @@ lpf_status lpf_s2(lpf_ctx c, const uint64_t *bits, int W, int H, int cx, int cy,
   L.fams = plan->fams;
   L.groups = plan->groups;
   L.lds_bytes = plan->lds;
-  L.acc = (uint32_t *)c->s2acc.p;
+  L.acc = (uint32_t *)c->s2acc.p + (size_t)c->s2half * ncap;
+  L.clear = (uint32_t *)c->s2acc.p + (size_t)(c->s2half ^ 1) * ncap;
+  L.ncap = ncap;
   L.nv = plan->nv;
   L.phase_mask = phase_mask;
   L.out = counts;
   if ((e = launch_s2_full(L, s)) != hipSuccess) return hip_fail(e, "lpf_s2: kernel");
+  c->s2half ^= 1;
   return LPF_OK;
 }
 

@@ -509,7 +509,10 @@ struct S2Launch {
   const int4 *fams;         // dy-sorted families
   const int4 *groups;       // {first, end, dy of first, dy of last}
   size_t lds_bytes;
-  uint32_t *acc;
+  // acc: zero on entry; clear: the other of two accumulators (ncap entries each), which the
+  // previous call has finished reading and this call's last launch clears for the next call
+  uint32_t *acc, *clear;
+  int64_t ncap;
   int64_t nv;
   unsigned phase_mask;
   uint32_t *out;
