@@ -121,36 +121,86 @@ k_lpf3(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S,
   }
 }
 
+// Voxel table of the segments for the slab kernel: vector j (launch order) owns the int2 entries
+// walk[woff[j] ...], one per voxel k = 0..n of its segment and one repeat of the last voxel when
+// n + 1 is odd (AND and OR are idempotent, so the repeat leaves the product unchanged):
+// {byte offset of the voxel's row word in a slab relative to the start row, bit shift px & 31}.
+// The slab geometry (ps dwords per plane, rst dwords per row) fixes the offsets.  The 3-D
+// digitisation: n = max(|dx|, |dy|, |dz|), the major axis is the first of x, y, z with extent n and
+// each minor coordinate follows its own error term (the 2-D rounding per minor axis).
+__global__ void k_lpf3_walk(const int4 *__restrict__ vec, int nv, const int *__restrict__ woff,
+                            int ps, int rst, int2 *__restrict__ walk) {
+  // one wave per vector, one lane per voxel: after k steps an error term started at n and
+  // advanced by 2a (less 2n per carry) has carried floor((2ka + n) / 2n) times
+  const int j = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+  if (j >= nv) return;
+  const int lane = threadIdx.x & 63;
+  const int4 v = vec[j];
+  const int dx = v.x, dy = v.y, dz = v.z;
+  const int a0 = dx < 0 ? -dx : dx, a1 = dy < 0 ? -dy : dy, a2 = dz < 0 ? -dz : dz;
+  const int s1 = dy < 0 ? -1 : 1, s2 = dz < 0 ? -1 : 1;
+  const int n = max(a0, max(a1, a2));
+  const int maj = a0 == n ? 0 : (a1 == n ? 1 : 2);
+  const int ma = maj == 0 ? a1 : a0;  // minor a: y for an x-major vector, else x
+  const int mb = maj == 2 ? a1 : a2;  // minor b: y for a z-major vector, else z
+  int2 *w = walk + woff[j];
+  const int cnt = (n + 2) & ~1;  // n + 1 voxels, the last repeated when n + 1 is odd
+  for (int i = lane; i < cnt; i += 64) {
+    const int k = min(i, n);
+    // 2kn + n < 2^32 for n <= 32767
+    const int qa = n ? (int)((2u * k * ma + n) / (2u * n)) : 0;
+    const int qb = n ? (int)((2u * k * mb + n) / (2u * n)) : 0;
+    const int qx = maj == 0 ? k : qa;
+    const int qy = maj == 1 ? k : (maj == 0 ? qa : qb);
+    const int qz = maj == 2 ? k : qb;
+    const int px = dx < 0 ? a0 - qx : qx;  // mirrored and shifted by |dx| when dx < 0
+    w[i] = make_int2((s2 * qz * ps + s1 * qy * rst + (px >> 5)) * 4, px & 31);
+  }
+}
+
 // Slab variant: workgroup (blockIdx.x, blockIdx.y) stages planes Z0 .. Z0 + zb + cz - 1 (mod D),
 // Z0 = blockIdx.y * zb, of the extended volume in LDS, each plane with cy periodic halo rows
-// above and below (HH = H + 2 cy rows of rst dwords, LDS row cy + y = volume row y), and its
-// waves count vectors of vec[v0 .. v1) (vpw per wave; dz >= 0 for canonical vectors, so a segment
+// above and below (HH = H + 2 cy rows of rst dwords, LDS row cy + y = volume row y; planes ps
+// dwords apart, ps >= HH rst, the gap chosen so that start rows on both sides of a plane
+// boundary keep the bank pattern of consecutive rows), and its
+// waves count vectors of vec[0 .. nv) (vpw per wave; dz >= 0 for canonical vectors, so a segment
 // stays in the slab, and |dy| <= cy, so it stays in the halo) over the start rows of planes
 // Z0 .. Z0 + zb - 1; the slab's counts are added into counts (zeroed before the launch) with
-// integer atomics.  MAJ: the major axis of every vector of the range (0 = x, 1 = y, 2 = z), so
-// the voxel walk has no axis branches.
-template <int R, int MAJ>
+// integer atomics.  The voxels come from the table of k_lpf3_walk, two per scalar load.
+template <int R>
 __global__ void __launch_bounds__(512)
-k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, int rst, int zb,
-            int cz, int cy, const int4 *__restrict__ vec, int v0, int v1, int vpw, int nv,
-            unsigned phase_mask, uint32_t *__restrict__ counts) {
+k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, int rst, int ps, int zb,
+            int cz, int cy, const int4 *__restrict__ vec, const int *__restrict__ woff,
+            const int2 *__restrict__ walk, int vpw, int nv, unsigned phase_mask,
+            uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t lds[];
   const int Z0 = blockIdx.y * zb;
   const int planes = min(zb, D - Z0);  // start planes of this slab
   const int staged = planes + cz;
   const int HH = H + 2 * cy;
-  for (int i = threadIdx.x; i < staged * HH * we; i += blockDim.x) {
-    const int pr = i / we, e = i - pr * we;  // pr = plane * HH + halo row
-    const int pl = pr / HH, yh = pr - pl * HH;
-    int z = Z0 + pl;
-    z = z >= D ? z - D : z;  // cz <= D - 1
-    int y = yh - cy;  // in [-cy, H + cy), cy <= H - 1
-    y = y < 0 ? y + H : (y >= H ? y - H : y);
-    lds[pr * rst + e] = E[((size_t)z * H + y) * we + e];
+  {
+    // element i = row pr (plane pl, halo row yh) and dword e; the thread's elements advance by
+    // blockDim.x, so the row and plane are carried forward instead of divided out each time
+    const int step = blockDim.x, dq = step / we, dr = step - dq * we;
+    int e = threadIdx.x % we, pr = threadIdx.x / we;
+    int pl = pr / HH, yh = pr - pl * HH;
+    const int total_rows = staged * HH;
+    while (pr < total_rows) {
+      int z = Z0 + pl;
+      z = z >= D ? z - D : z;  // cz <= D - 1
+      int y = yh - cy;  // in [-cy, H + cy), cy <= H - 1
+      y = y < 0 ? y + H : (y >= H ? y - H : y);
+      lds[pl * ps + yh * rst + e] = E[((size_t)z * H + y) * we + e];
+      e += dr;
+      int adv = dq;
+      if (e >= we) { e -= we; ++adv; }
+      pr += adv;
+      yh += adv;
+      while (yh >= HH) { yh -= HH; ++pl; }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  // wave-uniform vector indices: the Bresenham state lives in scalar registers
   const int waves = blockDim.x >> 6, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rpw = 64 / S;
   const int strip = lane / rpw;
@@ -159,103 +209,90 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
   const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
   const int rows = planes * H;
   constexpr int RPL = R <= 4 ? 2 : 1;
+  // the lane's words: all-ones, the last word's valid bits, or none past the row
+  uint32_t mw[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int w = strip * R + i;
+    mw[i] = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
+  }
+  // start row r0 + q * rpw + r_in of each band: its (plane, row) advance by a fixed step per
+  // band, so the LDS row start (Pb, in bytes) is carried forward; a lane past the slab's rows
+  // reads the first start row (P0) and counts nothing
+  const int bstep = rpw * RPL, dzb = bstep / H, dyb = bstep - dzb * H;
+  const int dPb = (dzb * ps + dyb * rst) * 4, wrapP = (ps - H * rst) * 4, P0 = cy * rst * 4;
+  int Pf[RPL], yf[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = q * rpw + r_in;
+    const int zr = r / H;
+    yf[q] = r - zr * H;
+    Pf[q] = (zr * ps + (yf[q] + cy) * rst) * 4;
+  }
   // vpw vectors per wave, interleaved across the waves (neighbours in the length order)
   for (int jj = 0; jj < vpw; ++jj) {
-    const int j = __builtin_amdgcn_readfirstlane(v0 + (blockIdx.x * vpw + jj) * waves + wave);
-    if (j >= v1) break;  // after the only barrier
+    const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * vpw + jj) * waves + wave);
+    if (j >= nv) break;  // after the only barrier
     const int dx = __builtin_amdgcn_readfirstlane(vec[j].x);
     const int dy = __builtin_amdgcn_readfirstlane(vec[j].y);
     const int dz = __builtin_amdgcn_readfirstlane(vec[j].z);
     const int idx = __builtin_amdgcn_readfirstlane(vec[j].w);
-    const int a0 = dx < 0 ? -dx : dx, a1 = dy < 0 ? -dy : dy, a2 = dz;
-    const int s1 = dy < 0 ? -1 : 1;
-    const int n = MAJ == 0 ? a0 : (MAJ == 1 ? a1 : a2);
-    // the two minor axes: magnitudes (the major one gets coordinate k)
-    const int ma = MAJ == 0 ? a1 : a0;  // minor a: y for MAJ 0, else x
-    const int mb = MAJ == 2 ? a1 : a2;  // minor b: y for MAJ 2, else z
+    const int n = max(dx < 0 ? -dx : dx, max(dy < 0 ? -dy : dy, dz < 0 ? -dz : dz));
+    const int npair = (n + 2) >> 1;
+    // two voxels per entry pair: {offset0, shift0, offset1, shift1}
+    const int4 *wp = reinterpret_cast<const int4 *>(walk + __builtin_amdgcn_readfirstlane(woff[j]));
     uint32_t c0 = 0, c1 = 0;
-    // RPL start rows per lane per band: the scalar voxel walk is shared by their vector work.
-    // A voxel's byte offset is the lane's row start (Pq) plus a wave-uniform part; the halo rows
-    // make the y wrap unnecessary.  Offsets in bytes, so that they are LDS addresses as they stand.
-    for (int r0 = 0; r0 < rows; r0 += rpw * RPL) {
+    int Pb[RPL], yb[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      Pb[q] = Pf[q];
+      yb[q] = yf[q];
+    }
+    // RPL start rows per lane per band share each scalar table load.  A voxel's byte offset is
+    // the lane's row start plus the table's wave-uniform part; the halo rows make the y wrap
+    // unnecessary.  A (phase 1: AND of the voxels) and N (phase 0: AND of their complements)
+    // start as the lane's valid bits, so the counts need no mask.
+    for (int r0 = 0; r0 < rows; r0 += bstep) {
       int Pq[RPL];
-      uint32_t A[RPL][R], O[RPL][R], mk[RPL][R];
+      uint32_t A[RPL][R], N[RPL][R];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        const int r = r0 + q * rpw + r_in;
-        const bool row_ok = r < rows;
-        const int zr = row_ok ? r / H : 0;
-        const int yr = row_ok ? r - zr * H : 0;
-        Pq[q] = (zr * HH + yr + cy) * rst * 4;
+        const bool row_ok = r0 + q * rpw + r_in < rows;
+        Pq[q] = row_ok ? Pb[q] : P0;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-          A[q][i] = 0xffffffffu;
-          O[q][i] = 0u;
-          const int w = strip * R + i;
-          const uint32_t mw = (w < swd - 1) ? 0xffffffffu : (w == swd - 1 ? lastmask : 0u);
-          mk[q][i] = row_ok ? mw : 0u;
+          A[q][i] = row_ok ? mw[i] : 0u;
+          N[q][i] = A[q][i];
+        }
+        Pb[q] += dPb;
+        yb[q] += dyb;
+        if (yb[q] >= H) {
+          yb[q] -= H;
+          Pb[q] += wrapP;
         }
       }
       const char *base = reinterpret_cast<const char *>(lds + strip * R);
       auto word = [&](int off, int c) -> uint32_t {
         return *reinterpret_cast<const uint32_t *>(base + off + 4 * c);
       };
-      // Bresenham state of voxel k: minor coordinates qa, qb with error terms ea, eb; voxels in
-      // pairs (two funnel shifts, one 3-input AND, one 3-input OR)
-      int ea = n, eb = n, qa = 0, qb = 0;
-      auto advance = [&]() {
-        ea += 2 * ma;
-        if (ea >= 2 * n) { ea -= 2 * n; ++qa; }
-        eb += 2 * mb;
-        if (eb >= 2 * n) { eb -= 2 * n; ++qb; }
-      };
-      auto voxel = [&](int k, int (&off)[RPL], int &sh) {
-        const int qx = MAJ == 0 ? k : qa;
-        const int qy = MAJ == 1 ? k : (MAJ == 0 ? qa : qb);
-        const int qz = MAJ == 2 ? k : qb;
-        const int px = dx < 0 ? a0 - qx : qx;  // mirrored and shifted by |dx| when dx < 0
-        const int su = ((qz * HH + s1 * qy) * rst + (px >> 5)) * 4;  // wave-uniform
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) off[q] = Pq[q] + su;
-        sh = px & 31;
-      };
-      int k = 0;
-      for (; k + 1 <= n; k += 2) {
-        int off0[RPL], off1[RPL], sh0, sh1;
-        voxel(k, off0, sh0);
-        advance();
-        voxel(k + 1, off1, sh1);
-        advance();
+      for (int p = 0; p < npair; ++p) {
+        const int4 t = wp[p];
+        const int su0 = __builtin_amdgcn_readfirstlane(t.x), sh0 = __builtin_amdgcn_readfirstlane(t.y);
+        const int su1 = __builtin_amdgcn_readfirstlane(t.z), sh1 = __builtin_amdgcn_readfirstlane(t.w);
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
           uint32_t d0[R + 1], d1[R + 1];
 #pragma unroll
           for (int c = 0; c <= R; ++c) {
-            d0[c] = word(off0[q], c);
-            d1[c] = word(off1[q], c);
+            d0[c] = word(Pq[q] + su0, c);
+            d1[c] = word(Pq[q] + su1, c);
           }
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const uint32_t t0 = __builtin_amdgcn_alignbit(d0[i + 1], d0[i], sh0);
             const uint32_t t1 = __builtin_amdgcn_alignbit(d1[i + 1], d1[i], sh1);
-            A[q][i] = __builtin_amdgcn_bitop3_b32(A[q][i], t0, t1, 0x80);
-            O[q][i] = O[q][i] | t0 | t1;
-          }
-        }
-      }
-      if (k == n) {  // odd voxel count: the last voxel alone
-        int off[RPL], sh;
-        voxel(k, off, sh);
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-          uint32_t d[R + 1];
-#pragma unroll
-          for (int c = 0; c <= R; ++c) d[c] = word(off[q], c);
-#pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const uint32_t t = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);
-            A[q][i] &= t;
-            O[q][i] |= t;
+            A[q][i] = __builtin_amdgcn_bitop3_b32(A[q][i], t0, t1, 0x80);  // A & t0 & t1
+            N[q][i] = __builtin_amdgcn_bitop3_b32(N[q][i], t0, t1, 0x10);  // N & ~t0 & ~t1
           }
         }
       }
@@ -263,8 +300,8 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
       for (int q = 0; q < RPL; ++q)
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-          c1 += __popc(A[q][i] & mk[q][i]);
-          c0 += __popc(~O[q][i] & mk[q][i]);
+          c1 += __popc(A[q][i]);
+          c0 += __popc(N[q][i]);
         }
     }
     c0 = wave_sum3(c0);
@@ -285,61 +322,49 @@ __global__ void k_lpf3_zero(uint32_t *__restrict__ counts, int64_t n) {
   if (i < n) counts[i] = 0;
 }
 
-hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst,
-                            int zb, int cz, int cy, const int4 *vec, const int *maj_off, int nv,
-                            unsigned phase_mask, uint32_t *counts, hipStream_t stream) {
+hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst, int ps,
+                            int zb, int cz, int cy, const int4 *vec, const int *woff, int2 *walk,
+                            bool build, int nv, unsigned phase_mask, uint32_t *counts,
+                            hipStream_t stream) {
   const int nph = (int)(phase_mask & 1u) + (int)((phase_mask >> 1) & 1u);
   const int64_t nc = (int64_t)nph * nv;
+  if (nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lpf3_zero, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream,
                      counts, nc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  constexpr int kWaves = 8;
-  const int nslab = (D + zb - 1) / zb;
-  const size_t lds = (size_t)(zb + cz) * (H + 2 * cy) * rst * sizeof(uint32_t);
-  for (int maj = 0; maj < 3; ++maj) {
-    const int v0 = maj_off[maj], v1 = maj_off[maj + 1];
-    const int cnt = v1 - v0;
-    if (cnt <= 0) continue;
-    // enough vectors per wave that staging a slab is amortised, while keeping about 2048
-    // workgroups
-    const int64_t groups_at_1 = ((int64_t)cnt + kWaves - 1) / kWaves;
-    const int vpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, groups_at_1 * nslab / 2048));
-    const dim3 grid((unsigned)((cnt + kWaves * vpw - 1) / (kWaves * vpw)), (unsigned)nslab);
-#define LPF3S(RR, MM)                                                                           \
-  hipLaunchKernelGGL((k_lpf3_slab<RR, MM>), grid, dim3(64 * kWaves), lds, stream, E, W, H, D,   \
-                     we, S, rst, zb, cz, cy, vec, v0, v1, vpw, nv, phase_mask, counts)
-#define LPF3M(RR)                               \
-  switch (maj) {                                \
-    case 0: LPF3S(RR, 0); break;                \
-    case 1: LPF3S(RR, 1); break;                \
-    default: LPF3S(RR, 2); break;               \
-  }
-    switch (R) {
-      case 1: LPF3M(1); break;
-      case 2: LPF3M(2); break;
-      case 4: LPF3M(4); break;
-      case 8: LPF3M(8); break;
-      case 16: LPF3M(16); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef LPF3M
-#undef LPF3S
+  if (build) {
+    hipLaunchKernelGGL(k_lpf3_walk, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, stream, vec,
+                       nv, woff, ps, rst, walk);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return hipSuccess;
+  constexpr int kWaves = 8;
+  const int nslab = (D + zb - 1) / zb;
+  const size_t lds = (size_t)(zb + cz) * ps * sizeof(uint32_t);
+  // enough vectors per wave that staging a slab is amortised, while keeping about 2048
+  // workgroups
+  const int64_t groups_at_1 = ((int64_t)nv + kWaves - 1) / kWaves;
+  const int vpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, groups_at_1 * nslab / 2048));
+  const dim3 grid((unsigned)((nv + kWaves * vpw - 1) / (kWaves * vpw)), (unsigned)nslab);
+#define LPF3S(RR)                                                                              \
+  hipLaunchKernelGGL((k_lpf3_slab<RR>), grid, dim3(64 * kWaves), lds, stream, E, W, H, D, we,  \
+                     S, rst, ps, zb, cz, cy, vec, woff, walk, vpw, nv, phase_mask, counts)
+  switch (R) {
+    case 1: LPF3S(1); break;
+    case 2: LPF3S(2); break;
+    case 4: LPF3S(4); break;
+    case 8: LPF3S(8); break;
+    case 16: LPF3S(16); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LPF3S
+  return hipGetLastError();
 }
 
 hipError_t prepare_lpf3_kernels(int max_lds_bytes) {
-  const void *fns[] = {
-      (const void *)k_lpf3_slab<1, 0>,  (const void *)k_lpf3_slab<1, 1>,
-      (const void *)k_lpf3_slab<1, 2>,  (const void *)k_lpf3_slab<2, 0>,
-      (const void *)k_lpf3_slab<2, 1>,  (const void *)k_lpf3_slab<2, 2>,
-      (const void *)k_lpf3_slab<4, 0>,  (const void *)k_lpf3_slab<4, 1>,
-      (const void *)k_lpf3_slab<4, 2>,  (const void *)k_lpf3_slab<8, 0>,
-      (const void *)k_lpf3_slab<8, 1>,  (const void *)k_lpf3_slab<8, 2>,
-      (const void *)k_lpf3_slab<16, 0>, (const void *)k_lpf3_slab<16, 1>,
-      (const void *)k_lpf3_slab<16, 2>};
+  const void *fns[] = {(const void *)k_lpf3_slab<1>, (const void *)k_lpf3_slab<2>,
+                       (const void *)k_lpf3_slab<4>, (const void *)k_lpf3_slab<8>,
+                       (const void *)k_lpf3_slab<16>};
   hipError_t e = hipSuccess;
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

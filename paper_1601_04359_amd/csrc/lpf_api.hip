@@ -189,10 +189,13 @@ struct lpf_ctx_s {
   std::map<std::tuple<int, int, int>, DiagPlan> diag_plans;  // (cx, cy, chunks)
   std::map<std::tuple<int, int, int, int>, TunedShape> tuned;   // autotuner results
   std::map<std::tuple<int, int, int, int>, S2Plan> s2_plans;
-  // 3-D vectors per cutoff: sorted by major axis, longest first within each; the axis ranges
+  // 3-D vectors per cutoff, longest first, and the start of each one's voxel-table entries
   struct Vec3 {
     int4 *vec = nullptr;
-    int maj_off[4] = {0, 0, 0, 0};
+    int *woff = nullptr;
+    int64_t nwalk = 0;  // table entries (int2), a multiple of 2
+    int2 *walk = nullptr;          // the voxel table, built for the slab geometry below
+    int walk_ps = -1, walk_rst = -1;
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
@@ -1128,7 +1131,11 @@ void lpf_ctx_destroy(lpf_ctx c) {
       (void)hipFree(kv.second.rows);
       (void)hipFree(kv.second.chunk_off);
     }
-    for (auto &kv : c->vec3) (void)hipFree(kv.second.vec);
+    for (auto &kv : c->vec3) {
+      (void)hipFree(kv.second.vec);
+      (void)hipFree(kv.second.woff);
+      (void)hipFree(kv.second.walk);
+    }
     for (auto &kv : c->s2_plans) {
       (void)hipFree(kv.second.fams);
       (void)hipFree(kv.second.groups);
@@ -1450,26 +1457,28 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
   if (it != c->vec3.end()) {
     v3p = &it->second;
   } else {
-    // launch order: by major axis (one kernel instance each), longest segments first, so that
-    // the waves of a workgroup walk segments of equal length and the long ones start early
+    // launch order: longest segments first, so that the waves of a workgroup walk segments of
+    // equal length and the long ones start early; each vector's voxel-table entries: n + 1
+    // rounded up to even
     std::vector<int16_t> v3((size_t)nv * 3);
     lpf_vectors3(cx, cy, cz, v3.data());
     std::vector<int4> hv(nv);
     for (int64_t i = 0; i < nv; ++i) hv[i] = make_int4(v3[3 * i], v3[3 * i + 1], v3[3 * i + 2], (int)i);
     auto len = [](const int4 &a) { return std::max(std::abs(a.x), std::max(std::abs(a.y), std::abs(a.z))); };
-    auto maj = [&](const int4 &a) { const int n = len(a); return std::abs(a.x) == n ? 0 : (std::abs(a.y) == n ? 1 : 2); };
-    std::stable_sort(hv.begin(), hv.end(), [&](const int4 &a, const int4 &b) {
-      return maj(a) != maj(b) ? maj(a) < maj(b) : len(a) > len(b);
-    });
+    std::stable_sort(hv.begin(), hv.end(), [&](const int4 &a, const int4 &b) { return len(a) > len(b); });
+    std::vector<int> woff(nv);
     lpf_ctx_s::Vec3 rec;
-    for (int m = 0; m < 3; ++m) {
-      int64_t k = 0;
-      while (k < nv && maj(hv[k]) <= m) ++k;
-      rec.maj_off[m + 1] = (int)k;
+    for (int64_t i = 0; i < nv; ++i) {
+      woff[i] = (int)rec.nwalk;
+      rec.nwalk += (len(hv[i]) + 2) & ~1;
     }
+    if (rec.nwalk > ((int64_t)1 << 30)) return fail(LPF_E_UNSUPPORTED, "lpf_full3d: voxel table too large");
     if ((e = hipMalloc(&rec.vec, sizeof(int4) * nv)) != hipSuccess) return hip_fail(e, "lpf_full3d: vectors");
-    if ((e = hipMemcpy(rec.vec, hv.data(), sizeof(int4) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
+    if ((e = hipMalloc(&rec.woff, sizeof(int) * nv)) != hipSuccess ||
+        (e = hipMemcpy(rec.vec, hv.data(), sizeof(int4) * nv, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(rec.woff, woff.data(), sizeof(int) * nv, hipMemcpyHostToDevice)) != hipSuccess) {
       (void)hipFree(rec.vec);
+      (void)hipFree(rec.woff);
       return hip_fail(e, "lpf_full3d: vectors");
     }
     v3p = &(c->vec3[key] = rec);
@@ -1481,16 +1490,34 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
     return hip_fail(e, "lpf_full3d: scratch");
   if ((e = launch_ext(bits, W, rows, we, (uint32_t *)c->ext.p, s)) != hipSuccess)
     return hip_fail(e, "lpf_full3d: ext");
-  // slabs in LDS when at least cz + 1 planes fit the 64 KiB budget (two workgroups per CU) or
-  // the full LDS; otherwise rows from global memory
+  // slabs in LDS when at least cz + 1 planes fit half the LDS (two workgroups per CU) or all
+  // of it; otherwise rows from global memory
+  // rows rst (odd) dwords apart, so that a wave's consecutive start rows fall in distinct banks;
+  // planes ps dwords apart, with a gap that makes the jump over the 2 cy halo rows between two
+  // planes a multiple of 32 dwords (the banks one half-wave's reads spread over), so that rows
+  // on both sides of a plane boundary do too
   const int rst = we | 1;
-  const size_t plane = (size_t)(H + 2 * cy) * rst * sizeof(uint32_t);
-  size_t budget = 64 * 1024;
+  const int64_t ps64 = (int64_t)(H + 2 * cy) * rst + ((32 - (2LL * cy * rst) % 32) % 32);
+  const size_t plane = (size_t)ps64 * sizeof(uint32_t);
+  size_t budget = kMaxLds / 2;
   if ((size_t)(cz + 1) * plane > budget) budget = kMaxLds;
   if ((size_t)(cz + 1) * plane <= budget) {
     const int zb = (int)std::min<int64_t>(D, (int64_t)(budget / plane) - cz);
-    e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, zb, cz, cy, vec,
-                         v3p->maj_off, (int)nv, phase_mask, counts, s);
+    // the voxel table is rebuilt when the slab geometry changes (calls on one context do not
+    // overlap) and in every captured call, so that a replayed graph carries its own build
+    if (!v3p->walk && (e = hipMalloc(&v3p->walk, (size_t)v3p->nwalk * sizeof(int2))) != hipSuccess)
+      return hip_fail(e, "lpf_full3d: voxel table");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "lpf_full3d: stream");
+    const int ps = (int)ps64;
+    const bool build = cap != hipStreamCaptureStatusNone || v3p->walk_ps != ps || v3p->walk_rst != rst;
+    if (build) v3p->walk_ps = v3p->walk_rst = -1;
+    e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, ps, zb, cz, cy, vec,
+                         v3p->woff, v3p->walk, build, (int)nv, phase_mask, counts, s);
+    if (e == hipSuccess && build) {
+      v3p->walk_ps = ps;
+      v3p->walk_rst = rst;
+    }
   } else {
     e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,
                     counts, s);

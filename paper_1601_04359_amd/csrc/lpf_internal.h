@@ -491,12 +491,15 @@ hipError_t launch_lpf3(const uint32_t *E, int W, int H, int D, int we, int R, in
                        const int4 *vec, int nv, unsigned phase_mask, uint32_t *counts,
                        hipStream_t stream);
 // Slabs of zb start planes staged with their cz-plane halo in LDS, each plane with cy periodic
-// halo rows above and below ((zb + cz) * (H + 2 cy) * rst dwords), counts accumulated with
-// atomics (zeroed here first).  vec sorted by major axis (x, then y, then z; maj_off[0..3] the
-// ranges, host array), longest first within each.
-hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst,
-                            int zb, int cz, int cy, const int4 *vec, const int *maj_off, int nv,
-                            unsigned phase_mask, uint32_t *counts, hipStream_t stream);
+// halo rows above and below ((H + 2 cy) rows of rst dwords in a plane of ps >= (H + 2 cy) rst
+// dwords; (zb + cz) * ps dwords in all), counts accumulated with
+// atomics (zeroed here first).  vec in launch order (longest first); woff[j] the first of vector
+// j's voxel-table entries (n + 1 rounded up to even); walk: the table (woff[nv - 1] + its
+// entries int2), written here first when build is set (it depends on ps and rst only).
+hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst, int ps,
+                            int zb, int cz, int cy, const int4 *vec, const int *woff, int2 *walk,
+                            bool build, int nv, unsigned phase_mask, uint32_t *counts,
+                            hipStream_t stream);
 hipError_t prepare_lpf3_kernels(int max_lds_bytes);
 
 // ---- two-point probability (k_s2.hip) ----

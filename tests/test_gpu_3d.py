@@ -28,7 +28,8 @@ def _dev(a):
 
 
 CASES = [(1, 1, 1, 0, 0, 0), (5, 4, 3, 4, 3, 2), (12, 10, 8, 11, 9, 7), (37, 5, 3, 20, 4, 2),
-         (70, 6, 5, 40, 5, 4), (100, 4, 4, 99, 3, 3), (33, 33, 7, 6, 6, 6), (1, 9, 8, 0, 8, 7)]
+         (70, 6, 5, 40, 5, 4), (100, 4, 4, 99, 3, 3), (33, 33, 7, 6, 6, 6), (1, 9, 8, 0, 8, 7),
+         (20, 3, 100, 4, 2, 10)]  # the last: many bands of start rows over short planes
 
 
 @pytest.mark.parametrize("W,H,D,cx,cy,cz", CASES)
@@ -47,6 +48,18 @@ def test_full3d_matches_oracle(ctx, W, H, D, cx, cy, cz):
             continue
         sel = {1: [0], 2: [1], 3: [0, 1]}[mask]
         assert np.array_equal(got.cpu().numpy().astype(np.uint32), want[sel]), mask
+
+
+def test_full3d_same_cutoff_other_shapes(ctx):
+    # one cutoff, volumes whose plane geometry differs (halo rows, row words) in turn: the cached
+    # voxel table follows the shape of each call
+    import torch
+    for W, H, D in ((20, 6, 5), (70, 9, 5), (20, 6, 5), (40, 6, 4)):
+        print(f"[gpu] lpf3 {W}x{H}x{D} c=(3,2,2) after other shapes", flush=True)
+        vol = wl.gaussian_field_3d(W, H, D, 1.2, 0.5, W + H + D)
+        got = ctx.full3d(ctx.pack3d(_dev(vol)), W, H, D, 3, 2, 2, 3)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy().astype(np.uint32), oracle.lpf3(vol, 3, 2, 2, 3))
 
 
 def test_vectors3_match_oracle():
