@@ -206,7 +206,10 @@ lpf_status lpf_vectors3(int cx, int cy, int cz, int16_t *dxdydz);
  * (row z*H + y, lpf_pack of the (D*H) x W byte array), read only.  With cz = 0 the counts are the
  * sums over the D xy-cuts of their 2-D functions (lpf_full), the ensemble average of Sec. 6.3 times
  * D*W*H.  Requires 1 <= W, H, D <= 65535, W*H*D < 2^32, 0 <= cx <= W-1, 0 <= cy <= H-1,
- * 0 <= cz <= D-1, cutoffs <= 32767, phase_mask in {1,2,3}.
+ * 0 <= cz <= D-1, cutoffs <= 32767, phase_mask in {1,2,3}.  The first call for a cutoff and a
+ * volume shape allocates the vector list and the segments' voxel table in the context (device
+ * memory kept until lpf_destroy; later calls only read them), so a call to be captured in a
+ * graph follows one made outside the capture.
  * Errors: LPF_E_INVAL, LPF_E_UNSUPPORTED (W > 32768, too many vectors), LPF_E_NOMEM,
  * LPF_E_DEVICE. */
 lpf_status lpf_full3d(lpf_ctx ctx, const uint64_t *bits, int W, int H, int D, int cx, int cy,

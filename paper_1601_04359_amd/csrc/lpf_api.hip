@@ -194,8 +194,8 @@ struct lpf_ctx_s {
     int4 *vec = nullptr;
     int *woff = nullptr;
     int64_t nwalk = 0;  // table entries (int2), a multiple of 2
-    int2 *walk = nullptr;          // the voxel table, built for the slab geometry below
-    int walk_ps = -1, walk_rst = -1;
+    // voxel tables per slab geometry (plane stride ps, row stride rst): built once, then only read
+    std::map<std::pair<int, int>, int2 *> walk;
   };
   std::map<std::tuple<int, int, int>, Vec3> vec3;
   std::map<std::string, struct BatchGraph *> batch_graphs;
@@ -1134,7 +1134,7 @@ void lpf_ctx_destroy(lpf_ctx c) {
     for (auto &kv : c->vec3) {
       (void)hipFree(kv.second.vec);
       (void)hipFree(kv.second.woff);
-      (void)hipFree(kv.second.walk);
+      for (auto &w : kv.second.walk) (void)hipFree(w.second);
     }
     for (auto &kv : c->s2_plans) {
       (void)hipFree(kv.second.fams);
@@ -1503,20 +1503,21 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
   if ((size_t)(cz + 1) * plane > budget) budget = kMaxLds;
   if ((size_t)(cz + 1) * plane <= budget) {
     const int zb = (int)std::min<int64_t>(D, (int64_t)(budget / plane) - cz);
-    // the voxel table is rebuilt when the slab geometry changes (calls on one context do not
-    // overlap) and in every captured call, so that a replayed graph carries its own build
-    if (!v3p->walk && (e = hipMalloc(&v3p->walk, (size_t)v3p->nwalk * sizeof(int2))) != hipSuccess)
-      return hip_fail(e, "lpf_full3d: voxel table");
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "lpf_full3d: stream");
+    // the voxel table of this geometry: built by the first call that needs it (enqueued before
+    // that call's kernel), never written again
     const int ps = (int)ps64;
-    const bool build = cap != hipStreamCaptureStatusNone || v3p->walk_ps != ps || v3p->walk_rst != rst;
-    if (build) v3p->walk_ps = v3p->walk_rst = -1;
+    int2 *&walk = v3p->walk[std::make_pair(ps, rst)];
+    const bool build = walk == nullptr;
+    if (build && (e = hipMalloc(&walk, (size_t)v3p->nwalk * sizeof(int2))) != hipSuccess) {
+      walk = nullptr;
+      v3p->walk.erase(std::make_pair(ps, rst));
+      return hip_fail(e, "lpf_full3d: voxel table");
+    }
     e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, ps, zb, cz, cy, vec,
-                         v3p->woff, v3p->walk, build, (int)nv, phase_mask, counts, s);
-    if (e == hipSuccess && build) {
-      v3p->walk_ps = ps;
-      v3p->walk_rst = rst;
+                         v3p->woff, walk, build, (int)nv, phase_mask, counts, s);
+    if (e != hipSuccess && build) {  // the table may not have been written: drop it
+      (void)hipFree(walk);
+      v3p->walk.erase(std::make_pair(ps, rst));
     }
   } else {
     e = launch_lpf3((const uint32_t *)c->ext.p, W, H, D, we, R, S, vec, (int)nv, phase_mask,
