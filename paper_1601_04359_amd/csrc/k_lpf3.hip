@@ -166,8 +166,10 @@ __global__ void k_lpf3_walk(const int4 *__restrict__ vec, int nv, const int *__r
 // waves count vectors of vec[0 .. nv) (vpw per wave; dz >= 0 for canonical vectors, so a segment
 // stays in the slab, and |dy| <= cy, so it stays in the halo) over the start rows of planes
 // Z0 .. Z0 + zb - 1; the slab's counts are added into counts (zeroed before the launch) with
-// integer atomics.  The voxels come from the table of k_lpf3_walk, two per scalar load.
-template <int R>
+// integer atomics.  The voxels come from the table of k_lpf3_walk, two per scalar load.  RPL
+// start rows per lane share each table load (R <= 4: 2 for short segments, where the per-band
+// work weighs more, 1 for long ones).
+template <int R, int RPL>
 __global__ void __launch_bounds__(512)
 k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, int rst, int ps, int zb,
             int cz, int cy, const int4 *__restrict__ vec, const int *__restrict__ woff,
@@ -208,7 +210,6 @@ k_lpf3_slab(const uint32_t *__restrict__ E, int W, int H, int D, int we, int S, 
   const int swd = (W + 31) >> 5;
   const uint32_t lastmask = (W & 31) ? ((1u << (W & 31)) - 1u) : 0xffffffffu;
   const int rows = planes * H;
-  constexpr int RPL = R <= 4 ? 2 : 1;
   // the lane's words: all-ones, the last word's valid bits, or none past the row
   uint32_t mw[R];
 #pragma unroll
@@ -324,7 +325,7 @@ __global__ void k_lpf3_zero(uint32_t *__restrict__ counts, int64_t n) {
 
 hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst, int ps,
                             int zb, int cz, int cy, const int4 *vec, const int *woff, int2 *walk,
-                            bool build, int nv, unsigned phase_mask, uint32_t *counts,
+                            bool build, int rpl, int nv, unsigned phase_mask, uint32_t *counts,
                             hipStream_t stream) {
   const int nph = (int)(phase_mask & 1u) + (int)((phase_mask >> 1) & 1u);
   const int64_t nc = (int64_t)nph * nv;
@@ -346,15 +347,16 @@ hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int 
   const int64_t groups_at_1 = ((int64_t)nv + kWaves - 1) / kWaves;
   const int vpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, groups_at_1 * nslab / 2048));
   const dim3 grid((unsigned)((nv + kWaves * vpw - 1) / (kWaves * vpw)), (unsigned)nslab);
-#define LPF3S(RR)                                                                              \
-  hipLaunchKernelGGL((k_lpf3_slab<RR>), grid, dim3(64 * kWaves), lds, stream, E, W, H, D, we,  \
-                     S, rst, ps, zb, cz, cy, vec, woff, walk, vpw, nv, phase_mask, counts)
+#define LPF3S(RR, QQ)                                                                          \
+  hipLaunchKernelGGL((k_lpf3_slab<RR, QQ>), grid, dim3(64 * kWaves), lds, stream, E, W, H, D,  \
+                     we, S, rst, ps, zb, cz, cy, vec, woff, walk, vpw, nv, phase_mask, counts)
+  const bool two = rpl == 2;
   switch (R) {
-    case 1: LPF3S(1); break;
-    case 2: LPF3S(2); break;
-    case 4: LPF3S(4); break;
-    case 8: LPF3S(8); break;
-    case 16: LPF3S(16); break;
+    case 1: if (two) LPF3S(1, 2); else LPF3S(1, 1); break;
+    case 2: if (two) LPF3S(2, 2); else LPF3S(2, 1); break;
+    case 4: if (two) LPF3S(4, 2); else LPF3S(4, 1); break;
+    case 8: LPF3S(8, 1); break;
+    case 16: LPF3S(16, 1); break;
     default: return hipErrorInvalidValue;
   }
 #undef LPF3S
@@ -362,9 +364,10 @@ hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int 
 }
 
 hipError_t prepare_lpf3_kernels(int max_lds_bytes) {
-  const void *fns[] = {(const void *)k_lpf3_slab<1>, (const void *)k_lpf3_slab<2>,
-                       (const void *)k_lpf3_slab<4>, (const void *)k_lpf3_slab<8>,
-                       (const void *)k_lpf3_slab<16>};
+  const void *fns[] = {(const void *)k_lpf3_slab<1, 1>, (const void *)k_lpf3_slab<1, 2>,
+                       (const void *)k_lpf3_slab<2, 1>, (const void *)k_lpf3_slab<2, 2>,
+                       (const void *)k_lpf3_slab<4, 1>, (const void *)k_lpf3_slab<4, 2>,
+                       (const void *)k_lpf3_slab<8, 1>, (const void *)k_lpf3_slab<16, 1>};
   hipError_t e = hipSuccess;
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

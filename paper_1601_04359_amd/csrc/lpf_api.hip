@@ -1513,8 +1513,12 @@ lpf_status lpf_full3d(lpf_ctx c, const uint64_t *bits, int W, int H, int D, int 
       v3p->walk.erase(std::make_pair(ps, rst));
       return hip_fail(e, "lpf_full3d: voxel table");
     }
+    // two start rows per lane for short segments (measured at 100^3: cutoff 16, about 14 voxels
+    // per segment, 0.98 ms against 1.02 with one; the full in-plane domain of the cuts, about 67,
+    // 4.74 ms with one against 4.96 with two)
+    const int rpl = v3p->nwalk < 32 * nv ? 2 : 1;
     e = launch_lpf3_slab((const uint32_t *)c->ext.p, W, H, D, we, R, S, rst, ps, zb, cz, cy, vec,
-                         v3p->woff, walk, build, (int)nv, phase_mask, counts, s);
+                         v3p->woff, walk, build, rpl, (int)nv, phase_mask, counts, s);
     if (e != hipSuccess && build) {  // the table may not have been written: drop it
       (void)hipFree(walk);
       v3p->walk.erase(std::make_pair(ps, rst));

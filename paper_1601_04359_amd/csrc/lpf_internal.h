@@ -495,10 +495,11 @@ hipError_t launch_lpf3(const uint32_t *E, int W, int H, int D, int we, int R, in
 // dwords; (zb + cz) * ps dwords in all), counts accumulated with
 // atomics (zeroed here first).  vec in launch order (longest first); woff[j] the first of vector
 // j's voxel-table entries (n + 1 rounded up to even); walk: the table (woff[nv - 1] + its
-// entries int2), written here first when build is set (it depends on ps and rst only).
+// entries int2), written here first when build is set (it depends on ps and rst only); rpl:
+// start rows per lane (2 is used only for R <= 4).
 hipError_t launch_lpf3_slab(const uint32_t *E, int W, int H, int D, int we, int R, int S, int rst, int ps,
                             int zb, int cz, int cy, const int4 *vec, const int *woff, int2 *walk,
-                            bool build, int nv, unsigned phase_mask, uint32_t *counts,
+                            bool build, int rpl, int nv, unsigned phase_mask, uint32_t *counts,
                             hipStream_t stream);
 hipError_t prepare_lpf3_kernels(int max_lds_bytes);
 
