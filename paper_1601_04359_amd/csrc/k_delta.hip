@@ -305,14 +305,16 @@ __device__ __forceinline__ void side_rows(const uint32_t *__restrict__ F,
   }
 }
 
-// dL of candidate interchanges (lanes: 256 per workgroup) for the vector groups of chunk
-// blockIdx.y.  With J1 = I with b set to 1 and J0 = I with a cleared (a the phase-1 pixel):
+// dL of candidate interchanges (lanes: BS per workgroup) for the vector groups of chunk
+// blockIdx.y.  All waves of a workgroup read the same table rows through the scalar cache; with
+// one product, 16 waves per workgroup (fewer chunks per CU) measured 7 % faster than 4 at
+// 128^2 / cutoff 32, with both (122 registers) 10 % slower at 256^2 / cutoff 48.  With J1 = I with b set to 1 and J0 = I with a cleared (a the phase-1 pixel):
 //   dL1 = sum_{P_b} lambda1(J1) - sum_{P_a} lambda1(J1),  dL0 = sum_{P_a} lambda0(J0) - sum_{P_b} lambda0(J0)
 // (a placement in both sets counts the same on both sides and cancels).  The pixel s itself
 // (d = 0) is 1 in J1 and 0 in J0 on either side, so it never decides a product and is skipped;
 // the only other changed pixel is b in side a's J1 and a in side b's J0.
-template <unsigned MASK, bool LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+template <unsigned MASK, bool LDS, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__restrict__ bits,
              int W, int H, const int2 *__restrict__ cand, int K,
              const DiagGroup *__restrict__ groups, const int32_t *__restrict__ chunk_off,
@@ -407,19 +409,23 @@ k_delta_diag(const uint32_t *__restrict__ Fg, DiagGeo geo, const uint64_t *__res
 }
 
 hipError_t launch_delta_diag(const DiagLaunch &L, hipStream_t stream) {
-  const dim3 grid((unsigned)((L.K + 255) / 256), (unsigned)L.nchunks), block(256);
   const size_t lds = L.use_lds ? (size_t)L.geo.total * sizeof(uint32_t) : 0;
-#define LPF_DIAG(M)                                                                             \
-  if (L.use_lds)                                                                                \
-    hipLaunchKernelGGL((k_delta_diag<M, true>), grid, block, lds, stream, L.F, L.geo, L.bits,   \
-                       L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv, L.delta_out); \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_delta_diag<M, false>), grid, block, 0, stream, L.F, L.geo, L.bits,    \
-                       L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv, L.delta_out);
+#define LPF_DIAG(M, BS)                                                                         \
+  {                                                                                             \
+    const dim3 grid((unsigned)((L.K + BS - 1) / BS), (unsigned)L.nchunks), block(BS);           \
+    if (L.use_lds)                                                                              \
+      hipLaunchKernelGGL((k_delta_diag<M, true, BS>), grid, block, lds, stream, L.F, L.geo,     \
+                         L.bits, L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv,    \
+                         L.delta_out);                                                          \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_delta_diag<M, false, BS>), grid, block, 0, stream, L.F, L.geo,      \
+                         L.bits, L.W, L.H, L.cand, L.K, L.groups, L.chunk_off, L.rows, L.nv,    \
+                         L.delta_out);                                                          \
+  }
   switch (L.phase_mask) {
-    case 1: LPF_DIAG(1u); break;
-    case 2: LPF_DIAG(2u); break;
-    case 3: LPF_DIAG(3u); break;
+    case 1: LPF_DIAG(1u, 1024); break;
+    case 2: LPF_DIAG(2u, 1024); break;
+    case 3: LPF_DIAG(3u, 256); break;
     default: return hipErrorInvalidValue;
   }
 #undef LPF_DIAG
@@ -430,13 +436,13 @@ hipError_t prepare_delta_kernels(int max_lds_bytes) {
   hipError_t e = hipFuncSetAttribute((const void *)k_delta<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_delta_diag<1u, true>,
+    e = hipFuncSetAttribute((const void *)k_delta_diag<1u, true, 1024>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_delta_diag<2u, true>,
+    e = hipFuncSetAttribute((const void *)k_delta_diag<2u, true, 1024>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_delta_diag<3u, true>,
+    e = hipFuncSetAttribute((const void *)k_delta_diag<3u, true, 256>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
   return e;
 }
