@@ -29,7 +29,8 @@ def _dev(a):
 
 CASES = [(1, 1, 1, 0, 0, 0), (5, 4, 3, 4, 3, 2), (12, 10, 8, 11, 9, 7), (37, 5, 3, 20, 4, 2),
          (70, 6, 5, 40, 5, 4), (100, 4, 4, 99, 3, 3), (33, 33, 7, 6, 6, 6), (1, 9, 8, 0, 8, 7),
-         (20, 3, 100, 4, 2, 10)]  # the last: many bands of start rows over short planes
+         (20, 3, 100, 4, 2, 10),  # many bands of start rows over short planes
+         (200, 6, 5, 10, 2, 3), (300, 4, 4, 40, 2, 2)]  # 8 and 16 words per lane
 
 
 @pytest.mark.parametrize("W,H,D,cx,cy,cz", CASES)
