@@ -6,11 +6,11 @@
 // (y + py, z + pz) of the extended volume (one v_alignbit_b32) and folds it into A (AND) and O
 // (OR); popcount(A & valid) counts phase 1, popcount(~O & valid) phase 0.  Vectors with dx < 0
 // are mirrored in x and shifted by |dx| (a translation, which leaves a periodic count unchanged).
-// The segment's voxels are generated on the scalar unit (Bresenham with two error terms), one
-// wave per vector; lanes own R words of one start row (S lanes per row) and walk all H*D start
-// rows in bands.  Rows are read from the extended volume in global memory (it stays in L2 for the
-// volume sizes of the paper) by k_lpf3, or, when a slab of planes with its cz-plane halo fits,
-// from LDS by k_lpf3_slab.
+// One wave per vector; lanes own R words of one start row (S lanes per row) and walk all H*D
+// start rows in bands.  When a slab of planes with its cz-plane halo fits in LDS, k_lpf3_slab
+// reads rows from LDS and the segment's voxels from a table (k_lpf3_walk); otherwise k_lpf3 reads
+// rows from the extended volume in global memory (it stays in L2 for the volume sizes of the
+// paper) and generates the voxels on the scalar unit (Bresenham with two error terms).
 #include "lpf_internal.h"
 
 namespace lpf {
